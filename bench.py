@@ -1,0 +1,204 @@
+"""Benchmark of the periodic GMG homogenization path on one MI355X.
+
+Workload (one "step"): a batch of 64 elasticity cells at 128^3 from the mixed
+lattice families (gyroid / Schwarz-P / diamond sheets, periodic truss,
+spinodal; family = seed mod 5, VF ~ U(0.15, 0.5), seeds 1000..1063).  Every
+cell goes through the whole path: sparse hierarchy + Galerkin operators +
+coarse factor, load vector, mixed-precision GMG-PCG (FP32 bulk, FP64
+refinement) to relative residual 1e-5, and the FP64 C_H reduction.
+
+Prints one JSON line (see the design doc for the field definitions).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ms to 1e-5 rel. residual per cell + DOF/s: learned-init+1 V-cycle vs plain GMG"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per active node of one fine-level Chebyshev sweep, FP32 elastic:
+# read u 72 + f 72 + D^-1 12 + d 72, write u' 72 + d 72
+CHEB_BYTES_PER_NODE = 372
+
+
+def _gen(seed_n):
+    seed, N = seed_n
+    from gmt_inputs.lattices import workload_cell
+    fam, vf, vox = workload_cell(N, seed)
+    return seed, fam, vf, vox
+
+
+def make_cells(N, seeds):
+    procs = max(1, min(16, os.cpu_count() or 1))
+    with mp.get_context("fork").Pool(procs) as pool:
+        return pool.map(_gen, [(s, N) for s in seeds])
+
+
+def cpu_baseline(tol):
+    """The CPU FP64 oracle on a bounded sample: one 64^3 workload cell, GMG-PCG to tol + C_H."""
+    from gmt_inputs.lattices import workload_cell
+    from oracle import solve as osolve
+
+    fam, vf, vox = workload_cell(64, 1000)
+    w0, c0 = time.perf_counter(), time.process_time()
+    P = osolve.Problem(vox, 5)
+    u, its = osolve.pcg(P, tol=tol)
+    osolve.homogenize(P, u)
+    wall = time.perf_counter() - w0
+    cpu = time.process_time() - c0
+    return {"wall_s": wall, "threads": max(1, round(cpu / wall)), "n_e": int(P.levels[0].n_e),
+            "n_n": int(P.levels[0].n_n), "family": fam, "vf": vf, "iterations": its}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cells", type=int, default=64)
+    ap.add_argument("--N", type=int, default=128)
+    ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding is a design note in DESIGN.md, not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2604_26518_amd import binding as B
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.perf_counter()
+    cells = make_cells(args.N, list(range(1000, 1000 + args.cells)))
+    gen_s = time.perf_counter() - t0
+    vox_dev = [torch.from_numpy(v).to(dev) for (_, _, _, v) in cells]
+    torch.cuda.synchronize()
+    levels = B.default_levels(args.N)
+    print(f"# generated {len(cells)} cells at {args.N}^3 in {gen_s:.1f} s; levels={levels}",
+          file=sys.stderr, flush=True)
+
+    def step(record=None):
+        solve_s = 0.0
+        dofs = 0
+        its = []
+        for k, vox in enumerate(vox_dev):
+            H = B.Hierarchy(vox, levels, "elastic")
+            f = H.load_vector()
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            u, rep = H.solve(f, tol=args.tol, precision="f32")
+            solve_s += time.perf_counter() - ts
+            CH = H.homogenize(u)
+            if not rep["converged"]:
+                raise RuntimeError(f"cell {k} did not converge: {rep}")
+            dofs += H.n_n(1) * 3 * 6
+            its.append(rep["iterations"])
+            if record is not None:
+                record.append({"seed": cells[k][0], "family": cells[k][1], "n_n": H.n_n(1),
+                               "its": rep["iterations"], "outer": rep["outer"],
+                               "res": max(rep["rel_res"]), "C11": float(CH[0, 0])})
+            H.close()
+        return solve_s, dofs, its
+
+    for w in range(args.warmup):
+        step()
+        print(f"# warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solve_total = 0.0
+    dofs = 0
+    its_all = []
+    record = []
+    for k in range(args.steps):
+        s, d, its = step(record if k == 0 else None)
+        solve_total += s
+        dofs += d
+        its_all += its
+        print(f"# step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ncell = args.steps * len(vox_dev)
+    ms_cell = wall / ncell * 1e3
+    ms_cell_solve = solve_total / ncell * 1e3
+
+    # --- dominant kernel: fine-level Chebyshev sweep (FP32), HIP events on the launch stream
+    vox = vox_dev[0]
+    H = B.Hierarchy(vox, levels, "elastic")
+    f32 = H.load_vector(torch.float32)
+    u32 = torch.zeros_like(f32)
+    lam = H.level_info(1)["lambda_max"]
+    lo, hi = lam / 30.0, 1.1 * lam
+    for _ in range(3):
+        H.smooth(f32, u32, 2, "chebyshev", lo, hi)
+    reps = 50
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        H.smooth(f32, u32, 2, "chebyshev", lo, hi)  # exactly two sweep launches
+    e1.record(stream)
+    torch.cuda.synchronize()
+    per_launch_s = e0.elapsed_time(e1) / 1e3 / (2 * reps)
+    nbytes = CHEB_BYTES_PER_NODE * H.n_n(1)
+    achieved = nbytes / per_launch_s / 1e9
+    kernel_info = {"n_n": H.n_n(1), "us_per_launch": per_launch_s * 1e6}
+    H.close()
+
+    out = {
+        "metric": METRIC,
+        "value": round(ms_cell, 3),
+        "unit": "ms/cell",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{len(vox_dev)} elasticity cells at {args.N}^3, mixed TPMS-sheet/truss/"
+                               f"spinodal families, VF U(0.15,0.5), plain GMG-PCG (FP32 bulk, FP64 "
+                               f"refinement) to {args.tol:g}, whole path incl. hierarchy build",
+                   "cells": len(vox_dev), "N": args.N, "levels": levels, "tol": args.tol},
+        "ms_per_cell_solve_only": round(ms_cell_solve, 3),
+        "dof_solves_per_s": round(dofs / wall, 1),
+        "iterations_mean": float(np.mean(its_all)),
+        "iterations_max": int(np.max(its_all)),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_apply_shared<float,3,EPI_CHEB> (fine-level Chebyshev sweep)", **kernel_info},
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(args.tol)
+        n_n_128 = float(np.mean([r["n_n"] for r in record]))
+        scale = n_n_128 / cb["n_n"]
+        out["cpu_baseline"] = {"value": round(cb["wall_s"] * 1e3 * scale, 1), "unit": "ms/cell", "cores": cb["threads"],
+                               "kind": "oracle",
+                               "sample": f"one 64^3 {cb['family']} cell (VF {cb['vf']:.2f}, seed 1000), oracle "
+                                         f"GMG-PCG to {args.tol:g} + C_H in {cb['wall_s']:.1f} s, scaled by the "
+                                         f"node ratio {scale:.2f} to a mean 128^3 cell"}
+    print(json.dumps(out), flush=True)
+    if os.environ.get("GMT_BENCH_CELLS"):
+        with open(os.environ["GMT_BENCH_CELLS"], "w") as fh:
+            json.dump(record, fh, indent=1)
+
+
+if __name__ == "__main__":
+    main()

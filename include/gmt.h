@@ -1,0 +1,208 @@
+/*
+ * gmt.h -- C ABI of the MI355X periodic geometric-multigrid homogenization library.
+ *
+ * The library computes the effective stiffness C_H (6x6) of a periodic binary
+ * voxel cell under linear elasticity, or the effective conductivity kappa_H
+ * (3x3) under steady heat conduction, by solving the periodic cell problems
+ * K u = f (paper Sec. 3.1, eq. linear_system; App. F) with a matrix-free,
+ * element-by-element geometric multigrid on the sparse active-voxel hierarchy
+ * (Sec. 4.1, Sec. 4.6, Alg. 1 / Alg. 2, App. E).
+ *
+ * Conventions (fixed by this library where the paper is silent):
+ *   - a voxel cell is N^3 uint8 (0 = void, nonzero = solid), linear index
+ *     x + N*(y + N*z), x fastest; voxel size 1, |Omega| = N^3;
+ *   - levels are numbered as in the paper, l = 1 (finest) .. L (coarsest);
+ *     level l has N_l = N / 2^(l-1) voxels per axis;
+ *   - active elements / nodes of a level are sorted by linear index and
+ *     identified by their rank (0-based id);
+ *   - hex8 local corner a + 2b + 4c sits at offset (a, b, c) of its voxel;
+ *   - a vector holds c load cases of d DOFs per node in the layout
+ *     [n_n][c][d] row-major (elastic c = 6, d = 3, Voigt order
+ *     11, 22, 33, 23, 13, 12 with engineering shear; thermal c = 3, d = 1);
+ *   - gauge: the solution returned by gmt_solve has every DOF of node id 0
+ *     of level 1 equal to zero (a translation of any solution).
+ *
+ * Memory and streams: every pointer named d_* is device memory owned by the
+ * caller; h_* is host memory owned by the caller.  The hierarchy owns its
+ * internal buffers (obtained through gmt_params.alloc when given, else
+ * hipMalloc) and frees them in gmt_destroy.  Calls enqueue work on the given
+ * hipStream_t (NULL = the null stream); calls that return host values
+ * synchronize that stream before returning.  A hierarchy may be used from one
+ * host thread at a time.
+ *
+ * Errors: every call returns a gmt_status; GMT_OK = 0.  Nothing aborts.
+ * gmt_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef GMT_H
+#define GMT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GMT_OK = 0,
+  GMT_E_INVAL = 1,    /* bad argument: size, level, dtype, null pointer, empty cell */
+  GMT_E_NOMEM = 2,    /* an allocation failed */
+  GMT_E_HIP = 3,      /* a HIP runtime call failed (message names it) */
+  GMT_E_NOCONV = 4,   /* the iteration budget ran out or the residual went non-finite */
+  GMT_E_SINGULAR = 5, /* coarsest-level Cholesky met a non-positive pivot */
+  GMT_E_STATE = 6     /* call not valid for this hierarchy (e.g. wrong physics) */
+} gmt_status;
+
+typedef enum { GMT_ELASTIC = 0, GMT_THERMAL = 1 } gmt_physics;
+typedef enum { GMT_F64 = 0, GMT_F32 = 1 } gmt_dtype;
+typedef enum { GMT_SMOOTH_CHEBYSHEV = 0, GMT_SMOOTH_JACOBI = 1 } gmt_smoother;
+
+typedef struct gmt_hier* gmt_hier_t;
+
+/* Parameters of one cell.  Zero-initialise and set what you need; zero
+ * fields take the defaults named below. */
+typedef struct {
+  int32_t physics;      /* gmt_physics */
+  double E, nu;         /* isotropic solid (elastic); default E = 1, nu = 0.3 */
+  double kappa;         /* conductivity (thermal); default 1 */
+  int32_t levels;       /* L >= 1; N must be divisible by 2^(L-1) and N_L >= 2 */
+  int32_t power_iters;  /* power iterations for lambda_max(D^-1 K); default 20 */
+  uint64_t seed;        /* seed of the power-iteration start vector */
+  /* optional allocator for the hierarchy's internal device buffers */
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*release)(void* ptr, void* ctx);
+  void* alloc_ctx;
+} gmt_params;
+
+typedef struct {
+  int32_t N;   /* voxels per axis on this level */
+  int32_t n_e; /* active elements */
+  int32_t n_n; /* active nodes */
+  int32_t c;   /* load cases (6 elastic, 3 thermal) */
+  int32_t d;   /* DOFs per node (3 elastic, 1 thermal) */
+  double lambda_max; /* power-iteration estimate of the largest eigenvalue of D^-1 K */
+} gmt_level_desc;
+
+/* Smoothing of one V-cycle.  For every level l (1..L-1) the smoother is either
+ * weighted Jacobi u += omega D^-1 (f - K u) (nu sweeps) or the degree-nu
+ * Chebyshev iteration for D^-1 K on [lo, hi].  Host arrays of length L
+ * indexed by level-1; NULL arrays take the defaults omega = 4/(3 lambda_max),
+ * lo = lambda_max / 30, hi = 1.1 lambda_max. */
+typedef struct {
+  int32_t nu1, nu2;   /* pre / post smoothing degree; default 2 / 2 when both 0 */
+  int32_t smoother;   /* gmt_smoother */
+  const double* omega;
+  const double* lo;
+  const double* hi;
+} gmt_cycle_opts;
+
+typedef struct {
+  double tol;         /* stop when max_m ||f_m - K u_m|| / ||f_m|| <= tol (FP64); default 1e-5 */
+  int32_t max_iter;   /* total inner PCG iterations; default 500 */
+  int32_t precision;  /* GMT_F64: all-FP64; GMT_F32: FP32 inner PCG + FP64 refinement */
+  int32_t max_outer;  /* FP64 refinement steps; default 8 */
+  int32_t check_every;/* inner convergence check period (host sync); default 1 */
+  gmt_cycle_opts cycle;
+} gmt_solve_opts;
+
+typedef struct {
+  int32_t iterations;      /* inner PCG iterations (V-cycles) spent */
+  int32_t outer;           /* FP64 residual evaluations / refinement steps */
+  int32_t converged;       /* 1 when max_m rel_res[m] <= tol */
+  int32_t c;               /* load cases reported */
+  double rel_res[6];       /* final FP64 relative residual per case */
+  double rel_res_init[6];  /* FP64 relative residual of the initial guess */
+} gmt_solve_report;
+
+/* Sec. 4.1 (active set, occupancy, eq. gmgcoarsenode) and App. E.1 (transfer
+ * stencils), plus the Galerkin operators of Sec. 4.6, the Jacobi diagonal, a
+ * lambda_max estimate per level and the factor of the pinned coarsest matrix.
+ * d_voxels: N^3 uint8 on the device.  Fails with GMT_E_INVAL for an empty
+ * cell or bad N / levels, GMT_E_SINGULAR if the coarsest factorisation fails. */
+gmt_status gmt_build_hierarchy(const uint8_t* d_voxels, int32_t N, const gmt_params* params,
+                               void* stream, gmt_hier_t* out);
+
+void gmt_destroy(gmt_hier_t h);
+
+gmt_status gmt_level_info(gmt_hier_t h, int32_t level, gmt_level_desc* out);
+
+/* Exports the integer maps of one level (Sec. 4.1.1, eq. gmgcoarsenode; App. E.2
+ * stencil tuple).  Any pointer may be NULL to skip it.  Sizes: elem_lin[n_e],
+ * node_lin[n_n], occ8[n_n] (bit a+2b+4c set iff the element at offset
+ * (a-1, b-1, c-1) from the node is active), elem_nodes[n_e][8],
+ * prol_idx[n_n][8] and prol_w[n_n][8] (level < L only: id of coarse corner
+ * o_k = (k&1, k>>1&1, k>>2&1) of the parent cell, -1 / 0.0 where w_k = 0). */
+gmt_status gmt_export_maps(gmt_hier_t h, int32_t level, int32_t* d_elem_lin, int32_t* d_node_lin,
+                           uint8_t* d_occ8, int32_t* d_elem_nodes, int32_t* d_prol_idx,
+                           double* d_prol_w, void* stream);
+
+/* Galerkin element matrices of level l >= 2 (Sec. 4.6, K_c = R_loc K_patch P_loc):
+ * d_K[n_e][8d][8d] FP64.  Level 1 returns the voxel K_e for every element. */
+gmt_status gmt_export_element_matrices(gmt_hier_t h, int32_t level, double* d_K, void* stream);
+
+/* diag(K^l) as d_D[n_n][d] FP64. */
+gmt_status gmt_export_diagonal(gmt_hier_t h, int32_t level, double* d_D, void* stream);
+
+/* f = sum_e A_e^T K_e X0 (App. F.1 f_e = K_e X0, X0 the affine unit-strain field),
+ * d_f[n_n][c][d] of level 1 in dtype. */
+gmt_status gmt_load_vector(gmt_hier_t h, void* d_f, int32_t dtype, void* stream);
+
+/* y = K^l u = sum_e A_e^T K_e A_e u, matrix-free (Sec. 4.6). */
+gmt_status gmt_apply_K(gmt_hier_t h, int32_t level, const void* d_u, void* d_y, int32_t dtype,
+                       void* stream);
+
+/* r = f - K^l u. */
+gmt_status gmt_residual(gmt_hier_t h, int32_t level, const void* d_f, const void* d_u, void* d_r,
+                        int32_t dtype, void* stream);
+
+/* nu smoothing steps on level l in place on d_u (weighted Jacobi with omega = p1,
+ * or Chebyshev on [lo, hi] = [p1, p2]); the smoother of Alg. 1 lines 3 and 12. */
+gmt_status gmt_smooth(gmt_hier_t h, int32_t level, const void* d_f, void* d_u, int32_t nu,
+                      int32_t smoother, double p1, double p2, int32_t dtype, void* stream);
+
+/* f_{l+1} = R r_l with R = P^T, unscaled, in gather form (App. E.2). */
+gmt_status gmt_restrict(gmt_hier_t h, int32_t level, const void* d_rf, void* d_fc, int32_t dtype,
+                        void* stream);
+
+/* u_l += P u_{l+1} (App. E.2 weighted gather). */
+gmt_status gmt_prolong_add(gmt_hier_t h, int32_t level, const void* d_uc, void* d_uf, int32_t dtype,
+                           void* stream);
+
+/* Exact solve of the coarsest level: node 0's DOFs pinned to zero, RHS there
+ * ignored, u = K_L,pinned^-1 f (replaces the coarsest GS of Alg. 1/2). */
+gmt_status gmt_coarse_solve(gmt_hier_t h, const void* d_f, void* d_u, int32_t dtype, void* stream);
+
+/* One V-cycle (Alg. 2) in place on d_u (level-1 vector, its initial guess u^1).
+ * d_e_init: NULL, or an array of L pointers indexed by level-1 whose entries
+ * 2..L-1 (indices 1..L-2) may be NULL or point to injected corrections
+ * e^l[n_n^l][c][d] (Alg. 2 line 6); entry L is unused (exact coarsest solve). */
+gmt_status gmt_vcycle(gmt_hier_t h, const void* d_f, void* d_u, const void* const* d_e_init,
+                      const gmt_cycle_opts* opts, int32_t dtype, void* stream);
+
+/* Solve K u = f to opts->tol (relative residual, Sec. 5.2, evaluated in FP64)
+ * by conjugate gradients preconditioned with one V-cycle per iteration,
+ * starting from the guess in d_u (zeros = the plain solver).  d_f and d_u are
+ * FP64 level-1 vectors; on return d_u holds the solution in the gauge
+ * u(node 0) = 0.  Returns GMT_E_NOCONV (with the report filled) when the
+ * budget is spent.  Synchronizes the stream. */
+gmt_status gmt_solve(gmt_hier_t h, const void* d_f, void* d_u, const gmt_solve_opts* opts,
+                     gmt_solve_report* report, void* stream);
+
+/* h_rel[c] = ||f_m - K u_m||_2 / ||f_m||_2 per case in FP64 (a case whose load
+ * is below 1e-12 of the largest case is normalised by the largest ||f||). */
+gmt_status gmt_relative_residual(gmt_hier_t h, const void* d_f, const void* d_u, int32_t dtype,
+                                 double* h_rel, void* stream);
+
+/* Effective tensor (App. F.1 / F.2):
+ * C_H = 1/N^3 sum_e (X0 - u_e)^T K_e (X0 - u_e), evaluated in FP64 through the
+ * equivalent assembled form (n_e C0 - F^T U - U^T F + U^T K U) / N^3.
+ * h_CH: c x c row-major host array.  Synchronizes the stream. */
+gmt_status gmt_homogenize(gmt_hier_t h, const void* d_u, int32_t dtype, double* h_CH, void* stream);
+
+const char* gmt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMT_H */

@@ -162,3 +162,25 @@ def load_vector(level, Ke: np.ndarray, X0: np.ndarray) -> np.ndarray:
     for a in range(8):
         np.add.at(f, level.elem_nodes[:, a], np.broadcast_to(fe[a], (level.n_e, c, d)))
     return f
+
+
+def apply_K_rows(level, mats, u: np.ndarray, rows) -> np.ndarray:
+    """Rows ``rows`` of K u only: the element sum of Sec. 4.6 restricted to the
+    elements that touch those nodes (for spot checks of very large cells)."""
+    rows = np.asarray(rows, dtype=np.int64)
+    touch = np.isin(level.elem_nodes, rows)
+    elems = np.nonzero(touch.any(axis=1))[0]
+    n, c, d = u.shape
+    en = level.elem_nodes[elems]
+    Ue = u[en].transpose(0, 1, 3, 2).reshape(len(elems), -1, c)
+    M = mats if np.ndim(mats) == 2 else mats[elems]
+    Ye = (np.einsum("ij,ejc->eic", M, Ue) if np.ndim(M) == 2 else np.einsum("eij,ejc->eic", M, Ue))
+    Ye = Ye.reshape(-1, 8, d, c).transpose(0, 1, 3, 2)
+    pos = {int(r): k for k, r in enumerate(rows)}
+    out = np.zeros((len(rows), c, d))
+    for e_loc in range(len(elems)):
+        for a in range(8):
+            k = pos.get(int(en[e_loc, a]))
+            if k is not None:
+                out[k] += Ye[e_loc, a]
+    return out

@@ -1,0 +1,392 @@
+"""ctypes binding of libgmt (include/gmt.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Torch tensors supply device memory and the current HIP stream.  Each
+method validates device, dtype, contiguity and element counts on the host
+before a pointer crosses the ABI, so a wrong shape raises here instead of
+reaching a kernel.
+"""
+
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgmt.so")
+
+GMT_OK, GMT_E_INVAL, GMT_E_NOMEM, GMT_E_HIP, GMT_E_NOCONV, GMT_E_SINGULAR, GMT_E_STATE = range(7)
+GMT_ELASTIC, GMT_THERMAL = 0, 1
+GMT_F64, GMT_F32 = 0, 1
+GMT_SMOOTH_CHEBYSHEV, GMT_SMOOTH_JACOBI = 0, 1
+
+_STATUS = {1: "GMT_E_INVAL", 2: "GMT_E_NOMEM", 3: "GMT_E_HIP", 4: "GMT_E_NOCONV",
+           5: "GMT_E_SINGULAR", 6: "GMT_E_STATE"}
+
+ALLOC_FN = ct.CFUNCTYPE(ct.c_void_p, ct.c_size_t, ct.c_void_p)
+RELEASE_FN = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_void_p)
+
+
+class GmtParams(ct.Structure):
+    _fields_ = [("physics", ct.c_int32), ("E", ct.c_double), ("nu", ct.c_double),
+                ("kappa", ct.c_double), ("levels", ct.c_int32), ("power_iters", ct.c_int32),
+                ("seed", ct.c_uint64), ("alloc", ALLOC_FN), ("release", RELEASE_FN),
+                ("alloc_ctx", ct.c_void_p)]
+
+
+class GmtLevelDesc(ct.Structure):
+    _fields_ = [("N", ct.c_int32), ("n_e", ct.c_int32), ("n_n", ct.c_int32),
+                ("c", ct.c_int32), ("d", ct.c_int32), ("lambda_max", ct.c_double)]
+
+
+class GmtCycleOpts(ct.Structure):
+    _fields_ = [("nu1", ct.c_int32), ("nu2", ct.c_int32), ("smoother", ct.c_int32),
+                ("omega", ct.POINTER(ct.c_double)), ("lo", ct.POINTER(ct.c_double)),
+                ("hi", ct.POINTER(ct.c_double))]
+
+
+class GmtSolveOpts(ct.Structure):
+    _fields_ = [("tol", ct.c_double), ("max_iter", ct.c_int32), ("precision", ct.c_int32),
+                ("max_outer", ct.c_int32), ("check_every", ct.c_int32), ("cycle", GmtCycleOpts)]
+
+
+class GmtSolveReport(ct.Structure):
+    _fields_ = [("iterations", ct.c_int32), ("outer", ct.c_int32), ("converged", ct.c_int32),
+                ("c", ct.c_int32), ("rel_res", ct.c_double * 6), ("rel_res_init", ct.c_double * 6)]
+
+
+class GmtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+# exported symbols and their argument types (must match include/gmt.h)
+_P = ct.c_void_p
+_I = ct.c_int32
+SIGNATURES = {
+    "gmt_build_hierarchy": (_P, _I, ct.POINTER(GmtParams), _P, ct.POINTER(_P)),
+    "gmt_destroy": (_P,),
+    "gmt_level_info": (_P, _I, ct.POINTER(GmtLevelDesc)),
+    "gmt_export_maps": (_P, _I, _P, _P, _P, _P, _P, _P, _P),
+    "gmt_export_element_matrices": (_P, _I, _P, _P),
+    "gmt_export_diagonal": (_P, _I, _P, _P),
+    "gmt_load_vector": (_P, _P, _I, _P),
+    "gmt_apply_K": (_P, _I, _P, _P, _I, _P),
+    "gmt_residual": (_P, _I, _P, _P, _P, _I, _P),
+    "gmt_smooth": (_P, _I, _P, _P, _I, _I, ct.c_double, ct.c_double, _I, _P),
+    "gmt_restrict": (_P, _I, _P, _P, _I, _P),
+    "gmt_prolong_add": (_P, _I, _P, _P, _I, _P),
+    "gmt_coarse_solve": (_P, _P, _P, _I, _P),
+    "gmt_vcycle": (_P, _P, _P, _P, ct.POINTER(GmtCycleOpts), _I, _P),
+    "gmt_solve": (_P, _P, _P, ct.POINTER(GmtSolveOpts), ct.POINTER(GmtSolveReport), _P),
+    "gmt_relative_residual": (_P, _P, _P, _I, ct.POINTER(ct.c_double), _P),
+    "gmt_homogenize": (_P, _P, _I, ct.POINTER(ct.c_double), _P),
+    "gmt_last_error": (),
+}
+
+
+def lib():
+    """Load libgmt.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2604_26518_amd.build`")
+        L = ct.CDLL(LIB_PATH)
+        for name, args in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = list(args)
+            fn.restype = ct.c_char_p if name == "gmt_last_error" else (None if name == "gmt_destroy" else ct.c_int)
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != GMT_OK:
+        raise GmtError(status, lib().gmt_last_error().decode())
+
+
+def _stream():
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ct.c_void_p(t.data_ptr()) if t is not None else None
+
+
+_DT = {torch.float64: GMT_F64, torch.float32: GMT_F32}
+
+
+def _dbl_array(vals):
+    if vals is None:
+        return None
+    arr = (ct.c_double * len(vals))(*[float(v) for v in vals])
+    return ct.cast(arr, ct.POINTER(ct.c_double)), arr
+
+
+class _TorchArena:
+    """Device memory for the library's internal buffers from torch's caching allocator."""
+
+    def __init__(self, device):
+        self.device = torch.device(device)
+        self.live = {}
+        self.alloc_cb = ALLOC_FN(self._alloc)
+        self.release_cb = RELEASE_FN(self._release)
+
+    def _alloc(self, nbytes, ctx):
+        try:
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        except RuntimeError:
+            return None
+        ptr = t.data_ptr()
+        self.live[ptr] = t
+        return ptr
+
+    def _release(self, ptr, ctx):
+        self.live.pop(ptr, None)
+
+
+class Hierarchy:
+    """One periodic cell: its sparse GMG hierarchy and operators on the GPU."""
+
+    def __init__(self, voxels, levels: int, physics: str = "elastic", E: float = 1.0,
+                 nu: float = 0.3, kappa: float = 1.0, power_iters: int = 20, seed: int = 0,
+                 device="cuda", torch_memory: bool = True):
+        if physics not in ("elastic", "thermal"):
+            raise ValueError(physics)
+        if isinstance(voxels, np.ndarray):
+            voxels = torch.from_numpy(np.ascontiguousarray(voxels, dtype=np.uint8))
+        N = int(voxels.shape[0])
+        if tuple(voxels.shape) != (N, N, N):
+            raise ValueError("voxels must be N^3")
+        self._vox = voxels.to(device=device, dtype=torch.uint8).contiguous()
+        self.N = N
+        self.physics = physics
+        self.c, self.d = (6, 3) if physics == "elastic" else (3, 1)
+        p = GmtParams()
+        p.physics = GMT_ELASTIC if physics == "elastic" else GMT_THERMAL
+        p.E, p.nu, p.kappa = E, nu, kappa
+        p.levels = levels
+        p.power_iters = power_iters
+        p.seed = seed
+        self._arena = None
+        if torch_memory:
+            self._arena = _TorchArena(self._vox.device)
+            p.alloc = self._arena.alloc_cb
+            p.release = self._arena.release_cb
+        h = ct.c_void_p()
+        _check(lib().gmt_build_hierarchy(_ptr(self._vox), N, ct.byref(p), _stream(), ct.byref(h)))
+        self._h = h
+        self.L = levels
+        self.levels = [self.level_info(l) for l in range(1, levels + 1)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gmt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- shapes
+    def level_info(self, level: int) -> dict:
+        d = GmtLevelDesc()
+        _check(lib().gmt_level_info(self._h, level, ct.byref(d)))
+        return {"N": d.N, "n_e": d.n_e, "n_n": d.n_n, "c": d.c, "d": d.d, "lambda_max": d.lambda_max}
+
+    def n_n(self, level: int = 1) -> int:
+        return self.levels[level - 1]["n_n"]
+
+    def n_e(self, level: int = 1) -> int:
+        return self.levels[level - 1]["n_e"]
+
+    def vec(self, level: int = 1, dtype=torch.float64, fill=0.0):
+        return torch.full((self.n_n(level), self.c, self.d), fill, dtype=dtype, device=self._vox.device)
+
+    def _v(self, t, level, dtype=None, name="vector"):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA tensor")
+        if dtype is not None and t.dtype != dtype:
+            raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+        if t.dtype not in _DT:
+            raise TypeError(f"{name} must be float32 or float64")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        want = self.n_n(level) * self.c * self.d
+        if t.numel() != want:
+            raise ValueError(f"{name} has {t.numel()} elements, level {level} needs {want}")
+        return t
+
+    def _level(self, level):
+        if not 1 <= level <= self.L:
+            raise ValueError(f"level {level} outside 1..{self.L}")
+
+    # -- maps and operators (exports)
+    def export_maps(self, level: int):
+        self._level(level)
+        info = self.levels[level - 1]
+        dev = self._vox.device
+        out = {
+            "elem_lin": torch.empty(info["n_e"], dtype=torch.int32, device=dev),
+            "node_lin": torch.empty(info["n_n"], dtype=torch.int32, device=dev),
+            "occ8": torch.empty(info["n_n"], dtype=torch.uint8, device=dev),
+            "elem_nodes": torch.empty(info["n_e"], 8, dtype=torch.int32, device=dev),
+        }
+        if level < self.L:
+            out["prol_idx"] = torch.empty(info["n_n"], 8, dtype=torch.int32, device=dev)
+            out["prol_w"] = torch.empty(info["n_n"], 8, dtype=torch.float64, device=dev)
+        _check(lib().gmt_export_maps(self._h, level, _ptr(out["elem_lin"]), _ptr(out["node_lin"]),
+                                     _ptr(out["occ8"]), _ptr(out["elem_nodes"]),
+                                     _ptr(out.get("prol_idx")), _ptr(out.get("prol_w")), _stream()))
+        return out
+
+    def export_element_matrices(self, level: int):
+        self._level(level)
+        M = 8 * self.d
+        K = torch.empty(self.n_e(level), M, M, dtype=torch.float64, device=self._vox.device)
+        _check(lib().gmt_export_element_matrices(self._h, level, _ptr(K), _stream()))
+        return K
+
+    def export_diagonal(self, level: int):
+        self._level(level)
+        D = torch.empty(self.n_n(level), self.d, dtype=torch.float64, device=self._vox.device)
+        _check(lib().gmt_export_diagonal(self._h, level, _ptr(D), _stream()))
+        return D
+
+    def load_vector(self, dtype=torch.float64):
+        f = self.vec(1, dtype)
+        _check(lib().gmt_load_vector(self._h, _ptr(f), _DT[dtype], _stream()))
+        return f
+
+    def apply_K(self, u, level: int = 1, out=None):
+        self._level(level)
+        self._v(u, level, name="u")
+        y = torch.empty_like(u) if out is None else self._v(out, level, u.dtype, "out")
+        _check(lib().gmt_apply_K(self._h, level, _ptr(u), _ptr(y), _DT[u.dtype], _stream()))
+        return y
+
+    def residual(self, f, u, level: int = 1):
+        self._level(level)
+        self._v(u, level, name="u")
+        self._v(f, level, u.dtype, "f")
+        r = torch.empty_like(u)
+        _check(lib().gmt_residual(self._h, level, _ptr(f), _ptr(u), _ptr(r), _DT[u.dtype], _stream()))
+        return r
+
+    def smooth(self, f, u, nu: int, smoother: str = "chebyshev", p1: float = 0.0, p2: float = 0.0,
+               level: int = 1):
+        """nu smoothing steps in place on u: Jacobi (omega = p1) or Chebyshev on [p1, p2]."""
+        self._level(level)
+        self._v(u, level, name="u")
+        self._v(f, level, u.dtype, "f")
+        sm = GMT_SMOOTH_JACOBI if smoother == "jacobi" else GMT_SMOOTH_CHEBYSHEV
+        _check(lib().gmt_smooth(self._h, level, _ptr(f), _ptr(u), nu, sm, p1, p2, _DT[u.dtype], _stream()))
+        return u
+
+    def restrict(self, rf, level: int = 1):
+        self._level(level)
+        if level == self.L:
+            raise ValueError("no level below the coarsest")
+        self._v(rf, level, name="rf")
+        fc = self.vec(level + 1, rf.dtype)
+        _check(lib().gmt_restrict(self._h, level, _ptr(rf), _ptr(fc), _DT[rf.dtype], _stream()))
+        return fc
+
+    def prolong_add(self, uc, uf, level: int = 1):
+        self._level(level)
+        if level == self.L:
+            raise ValueError("no level below the coarsest")
+        self._v(uf, level, name="uf")
+        self._v(uc, level + 1, uf.dtype, "uc")
+        _check(lib().gmt_prolong_add(self._h, level, _ptr(uc), _ptr(uf), _DT[uf.dtype], _stream()))
+        return uf
+
+    def coarse_solve(self, f):
+        self._v(f, self.L, name="f")
+        u = torch.empty_like(f)
+        _check(lib().gmt_coarse_solve(self._h, _ptr(f), _ptr(u), _DT[f.dtype], _stream()))
+        return u
+
+    def _cycle(self, nu1=2, nu2=2, smoother="chebyshev", omega=None, lo=None, hi=None):
+        o = GmtCycleOpts()
+        o.nu1, o.nu2 = nu1, nu2
+        o.smoother = GMT_SMOOTH_JACOBI if smoother == "jacobi" else GMT_SMOOTH_CHEBYSHEV
+        keep = []
+        for name, vals in (("omega", omega), ("lo", lo), ("hi", hi)):
+            if vals is not None:
+                if len(vals) != self.L:
+                    raise ValueError(f"{name} needs {self.L} entries")
+                p, arr = _dbl_array(vals)
+                setattr(o, name, p)
+                keep.append(arr)
+        return o, keep
+
+    def vcycle(self, f, u, e_init=None, nu1=2, nu2=2, smoother="chebyshev", omega=None, lo=None, hi=None):
+        """One V-cycle (Alg. 2) in place on u; e_init: list indexed by level-1 of corrections or None."""
+        self._v(u, 1, name="u")
+        self._v(f, 1, u.dtype, "f")
+        o, keep = self._cycle(nu1, nu2, smoother, omega, lo, hi)
+        arr = None
+        if e_init is not None:
+            if len(e_init) != self.L:
+                raise ValueError(f"e_init needs {self.L} entries")
+            ptrs = []
+            for l, e in enumerate(e_init, start=1):
+                if e is None or l == 1 or l == self.L:
+                    ptrs.append(None)
+                else:
+                    self._v(e, l, u.dtype, f"e_init[{l}]")
+                    ptrs.append(e.data_ptr())
+            arr = (ct.c_void_p * self.L)(*ptrs)
+        _check(lib().gmt_vcycle(self._h, _ptr(f), _ptr(u), arr, ct.byref(o), _DT[u.dtype], _stream()))
+        return u
+
+    def solve(self, f, u=None, tol=1e-5, max_iter=500, precision="f64", max_outer=8, check_every=1,
+              nu1=2, nu2=2, smoother="chebyshev", omega=None, lo=None, hi=None, raise_on_noconv=True):
+        self._v(f, 1, torch.float64, "f")
+        if u is None:
+            u = torch.zeros_like(f)
+        self._v(u, 1, torch.float64, "u")
+        o = GmtSolveOpts()
+        o.tol, o.max_iter, o.max_outer, o.check_every = tol, max_iter, max_outer, check_every
+        o.precision = GMT_F64 if precision == "f64" else GMT_F32
+        o.cycle, keep = self._cycle(nu1, nu2, smoother, omega, lo, hi)
+        rep = GmtSolveReport()
+        st = lib().gmt_solve(self._h, _ptr(f), _ptr(u), ct.byref(o), ct.byref(rep), _stream())
+        report = {"iterations": rep.iterations, "outer": rep.outer, "converged": bool(rep.converged),
+                  "rel_res": list(rep.rel_res)[:self.c], "rel_res_init": list(rep.rel_res_init)[:self.c],
+                  "status": st}
+        if st != GMT_OK and (st != GMT_E_NOCONV or raise_on_noconv):
+            _check(st)
+        return u, report
+
+    def relative_residual(self, f, u):
+        self._v(u, 1, name="u")
+        self._v(f, 1, u.dtype, "f")
+        out = (ct.c_double * 6)()
+        _check(lib().gmt_relative_residual(self._h, _ptr(f), _ptr(u), _DT[u.dtype], out, _stream()))
+        return np.array(out[:self.c])
+
+    def homogenize(self, u):
+        self._v(u, 1, name="u")
+        out = (ct.c_double * 36)()
+        _check(lib().gmt_homogenize(self._h, _ptr(u), _DT[u.dtype], out, _stream()))
+        return np.array(out[:self.c * self.c]).reshape(self.c, self.c)
+
+
+def default_levels(N: int, coarsest: int = 4) -> int:
+    """Levels so that the coarsest grid has ``coarsest`` (or the nearest feasible) voxels per axis."""
+    L = 1
+    n = N
+    while n % 2 == 0 and n // 2 >= coarsest:
+        n //= 2
+        L += 1
+    return L

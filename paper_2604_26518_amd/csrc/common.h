@@ -1,0 +1,218 @@
+// Internal declarations shared by the kernels and the host runtime of libgmt.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "gmt.h"
+
+namespace gmt {
+
+// ---------------------------------------------------------------- errors
+
+struct Failure {
+  gmt_status status;
+  std::string msg;
+};
+
+[[noreturn]] void fail(gmt_status st, const char* fmt, ...);
+
+#define GMT_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      ::gmt::fail(GMT_E_HIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),     \
+                  __FILE__, __LINE__);                                                  \
+  } while (0)
+
+#define GMT_LAUNCH_CHECK() GMT_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------- kinds of element operator
+
+// How the element matrices of a level are stored (Sec. 4.6 EBE form):
+//   SHARED : level 1, every active voxel carries the same K_e;
+//   TABLE  : level 2, K_E depends only on which of its 8 children are active,
+//            so it is one of 256 precomputed Galerkin sums (index = child mask);
+//   PERELEM: level >= 3, one Galerkin matrix per coarse element.
+enum Kind { KIND_SHARED = 0, KIND_TABLE = 1, KIND_PERELEM = 2 };
+
+template <typename T>
+struct LevelView {
+  int N;
+  int n_n;
+  const int* node_lin;
+  const int* node_map;  // dense N^3 -> node id or -1
+  const int* elem_map;  // dense N^3 -> element id or -1
+  const uint8_t* occ8;  // per node: bit k set iff octant element k is active
+  const uint8_t* cmask; // per element: bit c set iff child c is active (level >= 2)
+  const T* K;           // SHARED: K_e; TABLE: 256 matrices; PERELEM: n_e matrices
+};
+
+// Epilogue of a node-centric operator sweep.
+enum Epi { EPI_KU = 0, EPI_RESID = 1, EPI_JACOBI = 2, EPI_CHEB = 3 };
+
+template <typename T>
+struct EpiArgs {
+  const T* f;
+  const T* dinv;  // [n_n][d]
+  T* dvec;        // Chebyshev direction, updated in place
+  T* out;
+  T omega;        // Jacobi weight
+  T rho1, rho2;   // Chebyshev: d = rho1 d + rho2 D^-1 (f - K u); rho1 == 0 skips reading d
+};
+
+// ---------------------------------------------------------------- kernel launchers (kernels.hip)
+
+template <typename T>
+void launch_apply(const LevelView<T>& L, int kind, int D, int C, int epi, const T* u,
+                  const EpiArgs<T>& e, hipStream_t s);
+template <typename T>
+void launch_smooth_zero(int n, int D, int C, const T* f, const T* dinv, T scale, T* out, T* dvec,
+                        hipStream_t s);
+template <typename T>
+void launch_restrict(const LevelView<T>& fine, const LevelView<T>& coarse, int Q, const T* rf, T* fc,
+                     hipStream_t s);
+template <typename T>
+void launch_prolong_add(const LevelView<T>& fine, const LevelView<T>& coarse, int Q, const T* uc, T* uf,
+                        hipStream_t s);
+template <typename T>
+void launch_coarse_solve(const T* cinv, int cn, int D, int C, const T* f, T* u, hipStream_t s);
+template <typename T>
+void launch_fill(T* p, size_t n, T v, hipStream_t s);
+template <typename Tin, typename Tout>
+void launch_convert(const Tin* a, Tout* b, size_t n, hipStream_t s);
+template <typename T>
+void launch_copy(const T* a, T* b, size_t n, hipStream_t s);
+// per-case dot products sum_{i,d} a[i][c][d] b[i][c][d] accumulated in FP64 -> out[c]
+template <typename T>
+void launch_dot(const T* a, const T* b, int n, int C, int D, double* partial, double* out,
+                hipStream_t s);
+// Gram matrix out[c1*C + c2] = sum_{i,d} a[i][c1][d] b[i][c2][d] in FP64
+template <typename Ta, typename Tb>
+void launch_gram(const Ta* a, const Tb* b, int n, int C, int D, double* partial, double* out,
+                 hipStream_t s);
+// u += alpha[c] p ; r -= alpha[c] q
+template <typename T>
+void launch_pcg_update(T* u, T* r, const T* p, const T* q, const double* alpha, size_t n, int C,
+                       int D, hipStream_t s);
+// p = z + beta[c] p
+template <typename T>
+void launch_pcg_direction(T* p, const T* z, const double* beta, size_t n, int C, int D, hipStream_t s);
+void launch_pcg_alpha(const double* rz, const double* pq, double* alpha, int C, hipStream_t s);
+void launch_pcg_beta(const double* rz_new, double* rz, double* beta, int C, hipStream_t s);
+template <typename T>
+void launch_gauge_shift(T* u, int n, int Q, T* tmp, hipStream_t s);
+// v -= column mean over nodes (projection off the rigid translations)
+template <typename T>
+void launch_project(T* v, int n, int Q, double* partial, double* sums, hipStream_t s);
+// u64 += (double) d
+template <typename T>
+void launch_accumulate(double* u, const T* d, size_t n, hipStream_t s);
+
+// hierarchy construction kernels
+void launch_voxel_elem_flags(const uint8_t* vox, size_t n, int* flags, hipStream_t s);
+void launch_node_flags(const int* elem_map_or_flags, int N, int* node_flags, hipStream_t s);
+void launch_coarsen_flags(const int* fine_elem_map, int Nf, int* coarse_flags, uint8_t* dense_cmask,
+                          hipStream_t s);
+int64_t scan_compact(const int* flags, size_t n, int* map_out, int* lin_out, int* scratch_blocks,
+                     int* d_total, hipStream_t s);
+size_t scan_scratch_ints(size_t n);
+void launch_occ8(const int* node_lin, int n_n, const int* elem_map, int N, uint8_t* occ8,
+                 hipStream_t s);
+void launch_gather_cmask(const int* elem_lin, int n_e, const uint8_t* dense_cmask, uint8_t* cmask,
+                         hipStream_t s);
+void launch_elem_nodes(const int* elem_lin, int n_e, const int* node_map, int N, int* out,
+                       hipStream_t s);
+void launch_prol_maps(const int* node_lin, int n_n, int Nf, const int* coarse_node_map, int Nc,
+                      int* idx, double* w, hipStream_t s);
+void launch_galerkin(const int* elem_lin_c, int n_e_c, int Nc, const int* elem_map_f,
+                     const uint8_t* cmask_f, const double* Ksrc, int src_kind, int D,
+                     const double* Ps, double* out64, float* out32, hipStream_t s);
+template <typename T>
+void launch_diagonal(const LevelView<T>& L, int kind, int D, T* diag, hipStream_t s);
+void launch_load_vector(const int* node_lin, const uint8_t* occ8, int n_n, int D, int C,
+                        const double* fe, double* f, hipStream_t s);
+void launch_random(double* x, size_t n, uint64_t seed, hipStream_t s);
+void launch_expand_elem_matrices(const LevelView<double>& L, int kind, int n_e, int D,
+                                 const int* elem_lin, double* out, hipStream_t s);
+template <typename T>
+void launch_inv(const T* a, T* b, size_t n, hipStream_t s);
+
+// ---------------------------------------------------------------- hierarchy
+
+struct LevelData {
+  int N = 0, n_e = 0, n_n = 0;
+  int kind = KIND_SHARED;
+  int* node_lin = nullptr;
+  int* elem_lin = nullptr;
+  int* node_map = nullptr;
+  int* elem_map = nullptr;
+  uint8_t* occ8 = nullptr;
+  uint8_t* cmask = nullptr;   // per element, levels >= 2
+  double* Kel64 = nullptr;    // per element, levels >= 3
+  float* Kel32 = nullptr;
+  double* diag64 = nullptr;   // [n_n][d]
+  double* dinv64 = nullptr;
+  float* dinv32 = nullptr;
+  double lam = 0.0;           // lambda_max(D^-1 K) estimate
+};
+
+template <typename T>
+struct Work {
+  bool ready = false;
+  std::vector<T*> f, u, ualt, dvec, r;  // per level (f[0], u[0] unused: caller owns them)
+  T *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr, *px = nullptr;  // PCG vectors
+};
+
+struct Hier {
+  gmt_params p{};
+  int N = 0, L = 0, C = 0, D = 0, Q = 0;
+  std::vector<LevelData> lv;
+  double Ke[576] = {0};
+  double fe[576] = {0};  // K_e X0, (8d) x c row-major
+  double C0[36] = {0};   // X0^T K_e X0 (= base tensor)
+  double fe_norm = 0;    // ||f_e||_F, the scale of a nonzero load
+  double* Ke64 = nullptr;
+  float* Ke32 = nullptr;
+  double* fe64 = nullptr;
+  double* table64 = nullptr;
+  float* table32 = nullptr;
+  double* Ps = nullptr;  // 8 children x 8 x 8 local prolongation weights
+  double* cinv64 = nullptr;
+  float* cinv32 = nullptr;
+  int cn = 0;
+  double* f64 = nullptr;      // load vector (level 1)
+  double* red_partial = nullptr;
+  double* red_out = nullptr;  // small device scratch for reductions / PCG scalars
+  double* gauge_tmp64 = nullptr;
+  float* gauge_tmp32 = nullptr;
+  Work<float> w32;
+  Work<double> w64;
+  // FP64 / FP32 level-1 scratch vectors of the solve and query entry points
+  double *s_r64 = nullptr, *s_t64 = nullptr, *s_x64 = nullptr;
+  float *s_b32 = nullptr, *s_x32 = nullptr;
+  std::vector<void*> owned;
+
+  void* raw_alloc(size_t bytes);
+  void release(void* ptr);  // frees one buffer obtained from raw_alloc
+  template <typename T>
+  T* alloc(size_t n) {
+    return static_cast<T*>(raw_alloc(n * sizeof(T) + 16));
+  }
+  void release_all();
+
+  template <typename T>
+  LevelView<T> view(int l) const;
+  template <typename T>
+  Work<T>& work();
+  template <typename T>
+  void ensure_work();
+};
+
+constexpr int kRedBlocks = 1024;  // fixed grid of the two-stage reductions (deterministic order)
+
+}  // namespace gmt

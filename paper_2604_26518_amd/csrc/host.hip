@@ -1,0 +1,1165 @@
+// Host runtime of libgmt: hierarchy construction, element constants, the
+// pinned coarsest factorisation, V-cycle / PCG orchestration and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <memory>
+
+#include "common.h"
+
+namespace gmt {
+
+// ================================================================ errors
+
+static thread_local std::string g_last_error;
+
+void fail(gmt_status st, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  throw Failure{st, std::string(buf)};
+}
+
+template <typename F>
+static gmt_status guarded(F&& fn) {
+  try {
+    fn();
+    return GMT_OK;
+  } catch (const Failure& f) {
+    g_last_error = f.msg;
+    return f.status;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return GMT_E_NOMEM;
+  } catch (...) {
+    g_last_error = "unknown internal error";
+    return GMT_E_STATE;
+  }
+}
+
+// ================================================================ allocation
+
+void* Hier::raw_alloc(size_t bytes) {
+  void* ptr = nullptr;
+  if (p.alloc) {
+    ptr = p.alloc(bytes, p.alloc_ctx);
+    if (!ptr) fail(GMT_E_NOMEM, "allocator callback returned NULL for %zu bytes", bytes);
+  } else {
+    hipError_t e = hipMalloc(&ptr, bytes);
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      fail(GMT_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+  }
+  owned.push_back(ptr);
+  return ptr;
+}
+
+void Hier::release(void* q) {
+  auto it = std::find(owned.begin(), owned.end(), q);
+  if (it == owned.end()) return;
+  owned.erase(it);
+  if (p.release)
+    p.release(q, p.alloc_ctx);
+  else
+    (void)hipFree(q);
+}
+
+void Hier::release_all() {
+  for (void* q : owned) {
+    if (p.release)
+      p.release(q, p.alloc_ctx);
+    else if (!p.alloc)
+      (void)hipFree(q);
+  }
+  owned.clear();
+}
+
+template <typename T>
+LevelView<T> Hier::view(int l) const {
+  const LevelData& d = lv[l];
+  LevelView<T> v{};
+  v.N = d.N;
+  v.n_n = d.n_n;
+  v.node_lin = d.node_lin;
+  v.node_map = d.node_map;
+  v.elem_map = d.elem_map;
+  v.occ8 = d.occ8;
+  v.cmask = d.cmask;
+  if constexpr (std::is_same<T, double>::value)
+    v.K = d.kind == KIND_SHARED ? Ke64 : (d.kind == KIND_TABLE ? table64 : d.Kel64);
+  else
+    v.K = d.kind == KIND_SHARED ? Ke32 : (d.kind == KIND_TABLE ? table32 : d.Kel32);
+  return v;
+}
+
+template <>
+Work<float>& Hier::work<float>() {
+  return w32;
+}
+template <>
+Work<double>& Hier::work<double>() {
+  return w64;
+}
+
+template <typename T>
+void Hier::ensure_work() {
+  Work<T>& W = work<T>();
+  if (W.ready) return;
+  W.f.assign(L, nullptr);
+  W.u.assign(L, nullptr);
+  W.ualt.assign(L, nullptr);
+  W.dvec.assign(L, nullptr);
+  W.r.assign(L, nullptr);
+  for (int l = 0; l < L; ++l) {
+    const size_t n = (size_t)lv[l].n_n * Q;
+    if (l > 0) {
+      W.f[l] = alloc<T>(n);
+      W.u[l] = alloc<T>(n);
+    }
+    W.ualt[l] = alloc<T>(n);
+    W.dvec[l] = alloc<T>(n);
+    W.r[l] = alloc<T>(n);
+  }
+  const size_t n0 = (size_t)lv[0].n_n * Q;
+  W.pr = alloc<T>(n0);
+  W.pz = alloc<T>(n0);
+  W.pp = alloc<T>(n0);
+  W.pq = alloc<T>(n0);
+  W.px = alloc<T>(n0);
+  W.ready = true;
+}
+
+template LevelView<float> Hier::view<float>(int) const;
+template LevelView<double> Hier::view<double>(int) const;
+
+// ================================================================ element constants (App. F)
+
+// Trilinear shape-function gradients on the unit cube at point (px,py,pz);
+// corner a = ax + 2 ay + 4 az.
+static void shape_gradients(double px, double py, double pz, double g[8][3]) {
+  for (int a = 0; a < 8; ++a) {
+    const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+    const double fx = ax ? px : 1.0 - px, fy = ay ? py : 1.0 - py, fz = az ? pz : 1.0 - pz;
+    const double sx = ax ? 1.0 : -1.0, sy = ay ? 1.0 : -1.0, sz = az ? 1.0 : -1.0;
+    g[a][0] = sx * fy * fz;
+    g[a][1] = fx * sy * fz;
+    g[a][2] = fx * fy * sz;
+  }
+}
+
+// K_e and X0 of the unit voxel (2x2x2 Gauss quadrature, exact for hex8),
+// f_e = K_e X0 and C0 = X0^T K_e X0.
+static void element_constants(Hier& h) {
+  const int D = h.D, M = 8 * D, C = h.C;
+  std::vector<double> K(M * M, 0.0), X(M * C, 0.0);
+  const double gp[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+  if (D == 3) {
+    const double E = h.p.E, nu = h.p.nu;
+    const double lam = E * nu / ((1 + nu) * (1 - 2 * nu)), G = E / (2 * (1 + nu));
+    double Cm[6][6] = {{0}};
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Cm[i][j] = lam + (i == j ? 2 * G : 0.0);
+    Cm[3][3] = Cm[4][4] = Cm[5][5] = G;
+    for (int qz = 0; qz < 2; ++qz)
+      for (int qy = 0; qy < 2; ++qy)
+        for (int qx = 0; qx < 2; ++qx) {
+          double g[8][3];
+          shape_gradients(gp[qx], gp[qy], gp[qz], g);
+          // strain rows (11,22,33,23,13,12), engineering shear
+          double B[6][24] = {{0}};
+          for (int a = 0; a < 8; ++a) {
+            B[0][3 * a + 0] = g[a][0];
+            B[1][3 * a + 1] = g[a][1];
+            B[2][3 * a + 2] = g[a][2];
+            B[3][3 * a + 1] = g[a][2];
+            B[3][3 * a + 2] = g[a][1];
+            B[4][3 * a + 0] = g[a][2];
+            B[4][3 * a + 2] = g[a][0];
+            B[5][3 * a + 0] = g[a][1];
+            B[5][3 * a + 1] = g[a][0];
+          }
+          double CB[6][24];
+          for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 24; ++j) {
+              double s = 0;
+              for (int k = 0; k < 6; ++k) s += Cm[i][k] * B[k][j];
+              CB[i][j] = s;
+            }
+          for (int i = 0; i < 24; ++i)
+            for (int j = 0; j < 24; ++j) {
+              double s = 0;
+              for (int k = 0; k < 6; ++k) s += B[k][i] * CB[k][j];
+              K[i * M + j] += 0.125 * s;
+            }
+        }
+    for (int a = 0; a < 8; ++a) {
+      const double x = a & 1, y = (a >> 1) & 1, z = (a >> 2) & 1;
+      X[(3 * a + 0) * C + 0] = x;
+      X[(3 * a + 1) * C + 1] = y;
+      X[(3 * a + 2) * C + 2] = z;
+      X[(3 * a + 1) * C + 3] = 0.5 * z;
+      X[(3 * a + 2) * C + 3] = 0.5 * y;
+      X[(3 * a + 0) * C + 4] = 0.5 * z;
+      X[(3 * a + 2) * C + 4] = 0.5 * x;
+      X[(3 * a + 0) * C + 5] = 0.5 * y;
+      X[(3 * a + 1) * C + 5] = 0.5 * x;
+    }
+  } else {
+    for (int qz = 0; qz < 2; ++qz)
+      for (int qy = 0; qy < 2; ++qy)
+        for (int qx = 0; qx < 2; ++qx) {
+          double g[8][3];
+          shape_gradients(gp[qx], gp[qy], gp[qz], g);
+          for (int a = 0; a < 8; ++a)
+            for (int b = 0; b < 8; ++b)
+              K[a * 8 + b] += 0.125 * h.p.kappa * (g[a][0] * g[b][0] + g[a][1] * g[b][1] + g[a][2] * g[b][2]);
+        }
+    for (int a = 0; a < 8; ++a) {
+      X[a * C + 0] = a & 1;
+      X[a * C + 1] = (a >> 1) & 1;
+      X[a * C + 2] = (a >> 2) & 1;
+    }
+  }
+  for (int i = 0; i < M * M; ++i) h.Ke[i] = K[i];
+  for (int i = 0; i < M; ++i)
+    for (int c = 0; c < C; ++c) {
+      double s = 0;
+      for (int j = 0; j < M; ++j) s += K[i * M + j] * X[j * C + c];
+      h.fe[i * C + c] = s;
+    }
+  for (int c1 = 0; c1 < C; ++c1)
+    for (int c2 = 0; c2 < C; ++c2) {
+      double s = 0;
+      for (int i = 0; i < M; ++i) s += X[i * C + c1] * h.fe[i * C + c2];
+      h.C0[c1 * C + c2] = s;
+    }
+  double fn = 0;
+  for (int i = 0; i < M * C; ++i) fn += h.fe[i] * h.fe[i];
+  h.fe_norm = std::sqrt(fn);
+}
+
+// Ps[c][m][o]: weight of coarse-element corner o at corner m of child c
+// (trilinear, App. E.1 restricted to one coarse cell).
+static void local_prolongation(double Ps[8][8][8]) {
+  for (int c = 0; c < 8; ++c)
+    for (int m = 0; m < 8; ++m)
+      for (int o = 0; o < 8; ++o) {
+        double w = 1.0;
+        for (int d = 0; d < 3; ++d) {
+          const double pos = 0.5 * (((c >> d) & 1) + ((m >> d) & 1));
+          w *= 1.0 - std::fabs(pos - ((o >> d) & 1));
+        }
+        Ps[c][m][o] = w;
+      }
+}
+
+// 256-entry table of level-2 element matrices: entry mask = sum over children
+// c in mask (ascending) of P_c^T K_e P_c.
+static void mask_table(const Hier& h, const double Ps[8][8][8], std::vector<double>& tab) {
+  const int D = h.D, M = 8 * D;
+  std::vector<double> G(8 * M * M, 0.0);
+  for (int c = 0; c < 8; ++c) {
+    std::vector<double> T1(M * M, 0.0);
+    for (int r = 0; r < M; ++r)
+      for (int col = 0; col < M; ++col) {
+        const int p = col / D, j = col % D;
+        double s = 0;
+        for (int n = 0; n < 8; ++n) s += h.Ke[r * M + n * D + j] * Ps[c][n][p];
+        T1[r * M + col] = s;
+      }
+    for (int r = 0; r < M; ++r)
+      for (int col = 0; col < M; ++col) {
+        const int o = r / D, i = r % D;
+        double s = 0;
+        for (int m = 0; m < 8; ++m) s += Ps[c][m][o] * T1[(m * D + i) * M + col];
+        G[(size_t)c * M * M + r * M + col] = s;
+      }
+  }
+  tab.assign((size_t)256 * M * M, 0.0);
+  for (int mask = 0; mask < 256; ++mask)
+    for (int c = 0; c < 8; ++c)
+      if (mask & (1 << c))
+        for (int t = 0; t < M * M; ++t) tab[(size_t)mask * M * M + t] += G[(size_t)c * M * M + t];
+}
+
+// ================================================================ coarsest level
+
+// Dense FP64 Cholesky of the pinned coarsest matrix and its explicit inverse.
+static void coarse_factor(Hier& h, hipStream_t s) {
+  const int l = h.L - 1;
+  LevelData& d = h.lv[l];
+  const int D = h.D, M = 8 * D;
+  const int n = d.n_n * D;
+  if (n > 2048) fail(GMT_E_INVAL, "coarsest level has %d DOFs (> 2048): use more levels", n);
+  h.cn = n;
+  // element matrices and connectivity of the coarsest level
+  double* dK = h.alloc<double>((size_t)d.n_e * M * M);
+  int* dEN = h.alloc<int>((size_t)d.n_e * 8);
+  launch_expand_elem_matrices(h.view<double>(l), d.kind, d.n_e, D, d.elem_lin, dK, s);
+  launch_elem_nodes(d.elem_lin, d.n_e, d.node_map, d.N, dEN, s);
+  std::vector<double> Ke((size_t)d.n_e * M * M);
+  std::vector<int> en((size_t)d.n_e * 8);
+  GMT_HIP(hipMemcpyAsync(Ke.data(), dK, Ke.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  GMT_HIP(hipMemcpyAsync(en.data(), dEN, en.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+  GMT_HIP(hipStreamSynchronize(s));
+  std::vector<double> A((size_t)n * n, 0.0);
+  for (int e = 0; e < d.n_e; ++e)
+    for (int a = 0; a < 8; ++a)
+      for (int i = 0; i < D; ++i)
+        for (int b = 0; b < 8; ++b)
+          for (int j = 0; j < D; ++j)
+            A[(size_t)(en[e * 8 + a] * D + i) * n + en[e * 8 + b] * D + j] +=
+                Ke[(size_t)e * M * M + (a * D + i) * M + b * D + j];
+  // pin node 0: identity rows / columns
+  for (int i = 0; i < D; ++i) {
+    for (int j = 0; j < n; ++j) A[(size_t)i * n + j] = A[(size_t)j * n + i] = 0.0;
+    A[(size_t)i * n + i] = 1.0;
+  }
+  double dmax = 0;
+  for (int i = 0; i < n; ++i) dmax = std::max(dmax, A[(size_t)i * n + i]);
+  // in-place lower Cholesky
+  for (int j = 0; j < n; ++j) {
+    double sjj = A[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) sjj -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
+    if (!(sjj > 1e-13 * dmax)) fail(GMT_E_SINGULAR, "coarsest Cholesky: pivot %d is %g", j, sjj);
+    const double ljj = std::sqrt(sjj);
+    A[(size_t)j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      double sij = A[(size_t)i * n + j];
+      const double* ri = &A[(size_t)i * n];
+      const double* rj = &A[(size_t)j * n];
+      for (int k = 0; k < j; ++k) sij -= ri[k] * rj[k];
+      A[(size_t)i * n + j] = sij / ljj;
+    }
+  }
+  // W = L^-1 (lower), then inv = W^T W
+  std::vector<double> W((size_t)n * n, 0.0);
+  for (int c = 0; c < n; ++c) {
+    W[(size_t)c * n + c] = 1.0 / A[(size_t)c * n + c];
+    for (int i = c + 1; i < n; ++i) {
+      double sacc = 0;
+      for (int k = c; k < i; ++k) sacc += A[(size_t)i * n + k] * W[(size_t)k * n + c];
+      W[(size_t)i * n + c] = -sacc / A[(size_t)i * n + i];
+    }
+  }
+  std::vector<double> inv((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double sacc = 0;
+      for (int k = i; k < n; ++k) sacc += W[(size_t)k * n + i] * W[(size_t)k * n + j];
+      inv[(size_t)i * n + j] = inv[(size_t)j * n + i] = sacc;
+    }
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < n; ++j) inv[(size_t)i * n + j] = inv[(size_t)j * n + i] = 0.0;
+  h.cinv64 = h.alloc<double>((size_t)n * n);
+  h.cinv32 = h.alloc<float>((size_t)n * n);
+  GMT_HIP(hipMemcpyAsync(h.cinv64, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  launch_convert<double, float>(h.cinv64, h.cinv32, inv.size(), s);
+  GMT_HIP(hipStreamSynchronize(s));
+  h.release(dK);
+  h.release(dEN);
+}
+
+// ================================================================ building blocks
+
+template <typename T>
+static const T* dinv_of(const Hier& h, int l) {
+  if constexpr (std::is_same<T, double>::value)
+    return h.lv[l].dinv64;
+  else
+    return h.lv[l].dinv32;
+}
+
+template <typename T>
+static void apply(Hier& h, int l, int epi, const T* u, const T* f, T* out, int C, hipStream_t s,
+                  T omega = 0, T rho1 = 0, T rho2 = 0, T* dvec = nullptr) {
+  EpiArgs<T> e{};
+  e.f = f;
+  e.dinv = dinv_of<T>(h, l);
+  e.dvec = dvec;
+  e.out = out;
+  e.omega = omega;
+  e.rho1 = rho1;
+  e.rho2 = rho2;
+  launch_apply<T>(h.view<T>(l), h.lv[l].kind, h.D, C, epi, u, e, s);
+}
+
+struct CycleCfg {
+  int nu1 = 2, nu2 = 2, smoother = GMT_SMOOTH_CHEBYSHEV;
+  std::vector<double> omega, lo, hi;
+};
+
+static CycleCfg make_cycle(const Hier& h, const gmt_cycle_opts* o) {
+  CycleCfg c;
+  if (o) {
+    c.nu1 = o->nu1;
+    c.nu2 = o->nu2;
+    if (c.nu1 == 0 && c.nu2 == 0) c.nu1 = c.nu2 = 2;
+    c.smoother = o->smoother;
+  }
+  if (c.nu1 < 0 || c.nu2 < 0 || c.nu1 > 64 || c.nu2 > 64) fail(GMT_E_INVAL, "smoothing degree out of range");
+  if (c.smoother != GMT_SMOOTH_CHEBYSHEV && c.smoother != GMT_SMOOTH_JACOBI) fail(GMT_E_INVAL, "bad smoother");
+  for (int l = 0; l < h.L; ++l) {
+    const double lam = h.lv[l].lam;
+    c.omega.push_back(o && o->omega ? o->omega[l] : 4.0 / (3.0 * lam));
+    c.lo.push_back(o && o->lo ? o->lo[l] : lam / 30.0);
+    c.hi.push_back(o && o->hi ? o->hi[l] : 1.1 * lam);
+    if (c.smoother == GMT_SMOOTH_CHEBYSHEV && !(c.hi[l] > c.lo[l] && c.lo[l] > 0))
+      fail(GMT_E_INVAL, "Chebyshev interval of level %d is not 0 < lo < hi", l + 1);
+  }
+  return c;
+}
+
+// nu smoothing steps on level l; u / ualt are swapped so that u holds the result.
+template <typename T>
+static void smooth(Hier& h, int l, const T* f, T*& u, T*& ualt, T* dvec, int nu, bool zero_start,
+                   int smoother, double p1, double p2, hipStream_t s) {
+  const int n = h.lv[l].n_n;
+  if (nu <= 0) {
+    if (zero_start) launch_fill<T>(u, (size_t)n * h.Q, T(0), s);
+    return;
+  }
+  const T* dinv = dinv_of<T>(h, l);
+  if (smoother == GMT_SMOOTH_JACOBI) {
+    const T omega = (T)p1;
+    for (int it = 0; it < nu; ++it) {
+      if (it == 0 && zero_start) {
+        launch_smooth_zero<T>(n, h.D, h.C, f, dinv, omega, u, nullptr, s);
+      } else {
+        apply<T>(h, l, EPI_JACOBI, u, f, ualt, h.C, s, omega);
+        std::swap(u, ualt);
+      }
+    }
+    return;
+  }
+  const double lo = p1, hi = p2;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  if (zero_start) {
+    launch_smooth_zero<T>(n, h.D, h.C, f, dinv, (T)(1.0 / theta), u, dvec, s);
+  } else {
+    apply<T>(h, l, EPI_CHEB, u, f, ualt, h.C, s, T(0), T(0), (T)(1.0 / theta), dvec);
+    std::swap(u, ualt);
+  }
+  for (int k = 1; k < nu; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    apply<T>(h, l, EPI_CHEB, u, f, ualt, h.C, s, T(0), (T)(rn * rho), (T)(2.0 * rn / delta), dvec);
+    std::swap(u, ualt);
+    rho = rn;
+  }
+}
+
+template <typename T>
+static const T* cinv_of(const Hier& h) {
+  if constexpr (std::is_same<T, double>::value)
+    return h.cinv64;
+  else
+    return h.cinv32;
+}
+
+// One V-cycle (Alg. 2) in precision T on caller buffers f0 / u0 (level 1).
+template <typename T>
+static void vcycle(Hier& h, const T* f0, T* u0, bool u0_zero, const T* const* e_init, const CycleCfg& cfg,
+                   hipStream_t s) {
+  h.ensure_work<T>();
+  Work<T>& W = h.work<T>();
+  const int L = h.L;
+  std::vector<T*> cur(L), alt(L);
+  std::vector<const T*> fl(L);
+  cur[0] = u0;
+  alt[0] = W.ualt[0];
+  fl[0] = f0;
+  auto p1 = [&](int l) { return cfg.smoother == GMT_SMOOTH_JACOBI ? cfg.omega[l] : cfg.lo[l]; };
+  auto p2 = [&](int l) { return cfg.hi[l]; };
+  for (int l = 0; l < L - 1; ++l) {
+    const bool zs = l == 0 ? u0_zero : !(e_init && e_init[l]);
+    smooth<T>(h, l, fl[l], cur[l], alt[l], W.dvec[l], cfg.nu1, zs, cfg.smoother, p1(l), p2(l), s);
+    apply<T>(h, l, EPI_RESID, cur[l], fl[l], W.r[l], h.C, s);
+    launch_restrict<T>(h.view<T>(l), h.view<T>(l + 1), h.Q, W.r[l], W.f[l + 1], s);
+    fl[l + 1] = W.f[l + 1];
+    cur[l + 1] = W.u[l + 1];
+    alt[l + 1] = W.ualt[l + 1];
+    if (e_init && e_init[l + 1] && l + 1 < L - 1)
+      launch_copy<T>(e_init[l + 1], cur[l + 1], (size_t)h.lv[l + 1].n_n * h.Q, s);
+  }
+  launch_coarse_solve<T>(cinv_of<T>(h), h.cn, h.D, h.C, fl[L - 1], cur[L - 1], s);
+  for (int l = L - 2; l >= 0; --l) {
+    launch_prolong_add<T>(h.view<T>(l), h.view<T>(l + 1), h.Q, cur[l + 1], cur[l], s);
+    smooth<T>(h, l, fl[l], cur[l], alt[l], W.dvec[l], cfg.nu2, false, cfg.smoother, p1(l), p2(l), s);
+  }
+  if (cur[0] != u0) launch_copy<T>(cur[0], u0, (size_t)h.lv[0].n_n * h.Q, s);
+}
+
+static void host_dot(Hier& h, const double* dev, int n, double* out, hipStream_t s) {
+  GMT_HIP(hipMemcpyAsync(out, dev, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  GMT_HIP(hipStreamSynchronize(s));
+}
+
+// Inner PCG on K x = b from x = 0, V-cycle preconditioned.  The periodic
+// system is singular (rigid translations, constant per DOF component, span the
+// null space) and consistent in exact arithmetic.  Rounding re-introduces a
+// translation component into r every iteration; the pinned coarsest solve would
+// turn it into a large spurious correction, so CG runs on the range of K: the
+// preconditioner is M^-1 = Pi V Pi with Pi the projection that removes the
+// column means (symmetric, so CG stays valid).
+// Stops when ||r_m|| <= tol[m] * ||b_m|| for every case, after maxit
+// iterations, or when the residual stagnates.
+template <typename T>
+static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int check_every, const CycleCfg& cfg,
+               hipStream_t s) {
+  h.ensure_work<T>();
+  Work<T>& W = h.work<T>();
+  const int n = h.lv[0].n_n, C = h.C, D = h.D, Q = h.Q;
+  const size_t tot = (size_t)n * Q;
+  double* sc = h.red_out;
+  double *rz = sc, *pq = sc + 8, *alpha = sc + 16, *beta = sc + 24, *rzn = sc + 32, *rr = sc + 40;
+  double* sums = sc + 200;
+  double bn2[8], rr_h[8];
+  launch_fill<T>(x, tot, T(0), s);
+  launch_copy<T>(b, W.pr, tot, s);
+  launch_project<T>(W.pr, n, Q, h.red_partial, sums, s);
+  launch_dot<T>(W.pr, W.pr, n, C, D, h.red_partial, rr, s);
+  host_dot(h, rr, C, bn2, s);
+  auto precond = [&]() {
+    vcycle<T>(h, W.pr, W.pz, true, nullptr, cfg, s);
+    launch_project<T>(W.pz, n, Q, h.red_partial, sums, s);
+  };
+  precond();
+  launch_copy<T>(W.pz, W.pp, tot, s);
+  launch_dot<T>(W.pr, W.pz, n, C, D, h.red_partial, rz, s);
+  int it = 0;
+  double best = INFINITY;
+  int since_best = 0;
+  while (it < maxit) {
+    ++it;
+    apply<T>(h, 0, EPI_KU, W.pp, nullptr, W.pq, C, s);
+    launch_dot<T>(W.pp, W.pq, n, C, D, h.red_partial, pq, s);
+    launch_pcg_alpha(rz, pq, alpha, C, s);
+    launch_pcg_update<T>(x, W.pr, W.pp, W.pq, alpha, tot, C, D, s);
+    launch_project<T>(W.pr, n, Q, h.red_partial, sums, s);
+    if (it % check_every == 0 || it == maxit) {
+      launch_dot<T>(W.pr, W.pr, n, C, D, h.red_partial, rr, s);
+      host_dot(h, rr, C, rr_h, s);
+      bool done = true;
+      double worst = 0;  // progress measure: max_m ||r_m|| / (tol_m ||b_m||)
+      for (int c = 0; c < C; ++c) {
+        if (!std::isfinite(rr_h[c])) fail(GMT_E_NOCONV, "PCG residual of case %d is not finite", c);
+        const double target = tol[c] * std::sqrt(bn2[c]);
+        if (std::sqrt(rr_h[c]) > target) done = false;
+        if (target > 0) worst = std::max(worst, std::sqrt(rr_h[c]) / target);
+      }
+      if (done) break;
+      if (worst < 0.98 * best) {
+        best = worst;
+        since_best = 0;
+      } else if ((since_best += check_every) >= 20) {
+        break;  // stagnation: hand back to the FP64 refinement loop
+      }
+    }
+    precond();
+    launch_dot<T>(W.pr, W.pz, n, C, D, h.red_partial, rzn, s);
+    launch_pcg_beta(rzn, rz, beta, C, s);
+    launch_pcg_direction<T>(W.pp, W.pz, beta, tot, C, D, s);
+  }
+  return it;
+}
+
+// FP64 relative residual per case of u64 against f64 (both level-1 FP64).
+// True when every case's load is rounding noise (e.g. the uniform solid):
+// max_m ||f_m|| <= 1e-12 ||f_e||_F sqrt(n_e).
+static bool zero_load(const Hier& h, const double* fnorm) {
+  double fmax = 0;
+  for (int c = 0; c < h.C; ++c) fmax = std::max(fmax, fnorm[c]);
+  return fmax <= 1e-12 * h.fe_norm * std::sqrt((double)h.lv[0].n_e);
+}
+
+static void rel_residual64(Hier& h, const double* f, const double* u, double* r, double* rel,
+                           double* fnorm_out, hipStream_t s) {
+  const int n = h.lv[0].n_n, C = h.C, D = h.D;
+  apply<double>(h, 0, EPI_RESID, u, f, r, C, s);
+  double* rr = h.red_out + 48;
+  double* ff = h.red_out + 56;
+  launch_dot<double>(r, r, n, C, D, h.red_partial, rr, s);
+  launch_dot<double>(f, f, n, C, D, h.red_partial, ff, s);
+  double rh[8], fh[8];
+  host_dot(h, rr, C, rh, s);
+  host_dot(h, ff, C, fh, s);
+  double fmax = 0;
+  for (int c = 0; c < C; ++c) fmax = std::max(fmax, std::sqrt(fh[c]));
+  for (int c = 0; c < C; ++c) {
+    double den = std::sqrt(fh[c]);
+    if (den <= 1e-12 * fmax) den = fmax;
+    rel[c] = den > 0 ? std::sqrt(rh[c]) / den : 0.0;
+    if (fnorm_out) fnorm_out[c] = den;
+  }
+}
+
+static double* scratch64(Hier& h, double** slot) {
+  if (!*slot) *slot = h.alloc<double>((size_t)h.lv[0].n_n * h.Q);
+  return *slot;
+}
+
+// ================================================================ build
+
+static int ilog2_exact(int v) {
+  int k = 0;
+  while ((1 << k) < v) ++k;
+  return (1 << k) == v ? k : -1;
+}
+
+// Phase timer for the build (GMT_TIMING=1 prints phase wall times to stderr).
+struct PhaseTimer {
+  bool on;
+  hipStream_t s;
+  std::chrono::steady_clock::time_point t0;
+  explicit PhaseTimer(hipStream_t st) : on(std::getenv("GMT_TIMING") != nullptr), s(st), t0(std::chrono::steady_clock::now()) {}
+  void mark(const char* what) {
+    if (!on) return;
+    (void)hipStreamSynchronize(s);
+    auto t1 = std::chrono::steady_clock::now();
+    fprintf(stderr, "[gmt build] %-12s %8.3f ms\n", what, std::chrono::duration<double, std::milli>(t1 - t0).count());
+    t0 = t1;
+  }
+};
+
+static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
+  PhaseTimer timer(s);
+  const int N = h.N;
+  const size_t n3 = (size_t)N * N * N;
+  element_constants(h);
+  const int D = h.D, M = 8 * D;
+  h.Ke64 = h.alloc<double>(M * M);
+  h.Ke32 = h.alloc<float>(M * M);
+  h.fe64 = h.alloc<double>(M * h.C);
+  GMT_HIP(hipMemcpyAsync(h.Ke64, h.Ke, M * M * sizeof(double), hipMemcpyHostToDevice, s));
+  launch_convert<double, float>(h.Ke64, h.Ke32, M * M, s);
+  GMT_HIP(hipMemcpyAsync(h.fe64, h.fe, M * h.C * sizeof(double), hipMemcpyHostToDevice, s));
+  double Ps[8][8][8];
+  local_prolongation(Ps);
+  h.Ps = h.alloc<double>(512);
+  GMT_HIP(hipMemcpyAsync(h.Ps, Ps, 512 * sizeof(double), hipMemcpyHostToDevice, s));
+  h.red_partial = h.alloc<double>((size_t)kRedBlocks * 64);
+  h.red_out = h.alloc<double>(256);
+  h.gauge_tmp64 = h.alloc<double>(32);
+  h.gauge_tmp32 = h.alloc<float>(32);
+
+  // temporary buffers (released with the hierarchy; small relative to the maps)
+  int* flags = h.alloc<int>(n3);
+  int* scr = h.alloc<int>(scan_scratch_ints(n3));
+  int* d_total = h.alloc<int>(1);
+  uint8_t* dmask = h.alloc<uint8_t>(n3 / 8 + 1);
+
+  h.lv.resize(h.L);
+  for (int l = 0; l < h.L; ++l) {
+    LevelData& d = h.lv[l];
+    d.N = N >> l;
+    const size_t nl3 = (size_t)d.N * d.N * d.N;
+    d.elem_map = h.alloc<int>(nl3);
+    d.node_map = h.alloc<int>(nl3);
+    if (l == 0) {
+      launch_voxel_elem_flags(vox, n3, flags, s);
+    } else {
+      launch_coarsen_flags(h.lv[l - 1].elem_map, h.lv[l - 1].N, flags, dmask, s);
+    }
+    const int64_t ne = scan_compact(flags, nl3, nullptr, nullptr, scr, d_total, s);
+    if (ne == 0) fail(GMT_E_INVAL, "empty active set");
+    d.n_e = (int)ne;
+    d.elem_lin = h.alloc<int>(ne);
+    scan_compact(flags, nl3, d.elem_map, d.elem_lin, scr, d_total, s);
+    launch_node_flags(d.elem_map, d.N, flags, s);
+    const int64_t nn = scan_compact(flags, nl3, nullptr, nullptr, scr, d_total, s);
+    d.n_n = (int)nn;
+    d.node_lin = h.alloc<int>(nn);
+    scan_compact(flags, nl3, d.node_map, d.node_lin, scr, d_total, s);
+    d.occ8 = h.alloc<uint8_t>(nn);
+    launch_occ8(d.node_lin, d.n_n, d.elem_map, d.N, d.occ8, s);
+    if (l >= 1) {
+      d.cmask = h.alloc<uint8_t>(ne);
+      launch_gather_cmask(d.elem_lin, d.n_e, dmask, d.cmask, s);
+    }
+    d.kind = l == 0 ? KIND_SHARED : (l == 1 ? KIND_TABLE : KIND_PERELEM);
+  }
+
+  timer.mark("maps");
+  // Galerkin operators
+  if (h.L >= 2) {
+    std::vector<double> tab;
+    mask_table(h, Ps, tab);
+    h.table64 = h.alloc<double>(tab.size());
+    h.table32 = h.alloc<float>(tab.size());
+    GMT_HIP(hipMemcpyAsync(h.table64, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_convert<double, float>(h.table64, h.table32, tab.size(), s);
+    GMT_HIP(hipStreamSynchronize(s));
+  }
+  for (int l = 2; l < h.L; ++l) {
+    LevelData& d = h.lv[l];
+    const LevelData& f = h.lv[l - 1];
+    d.Kel64 = h.alloc<double>((size_t)d.n_e * M * M);
+    d.Kel32 = h.alloc<float>((size_t)d.n_e * M * M);
+    const double* src = f.kind == KIND_TABLE ? h.table64 : f.Kel64;
+    launch_galerkin(d.elem_lin, d.n_e, d.N, f.elem_map, f.cmask, src, f.kind, D, h.Ps, d.Kel64, d.Kel32, s);
+  }
+  timer.mark("galerkin");
+  // Jacobi diagonals
+  for (int l = 0; l < h.L; ++l) {
+    LevelData& d = h.lv[l];
+    const size_t nd = (size_t)d.n_n * D;
+    d.diag64 = h.alloc<double>(nd);
+    d.dinv64 = h.alloc<double>(nd);
+    d.dinv32 = h.alloc<float>(nd);
+    launch_diagonal<double>(h.view<double>(l), d.kind, D, d.diag64, s);
+    launch_inv<double>(d.diag64, d.dinv64, nd, s);
+    launch_convert<double, float>(d.dinv64, d.dinv32, nd, s);
+  }
+  // load vector
+  h.f64 = h.alloc<double>((size_t)h.lv[0].n_n * h.Q);
+  launch_load_vector(h.lv[0].node_lin, h.lv[0].occ8, h.lv[0].n_n, D, h.C, h.fe64, h.f64, s);
+
+  timer.mark("diag+load");
+  // lambda_max(D^-1 K) per level by power iteration (FP64, one vector)
+  {
+    const int iters = h.p.power_iters > 0 ? h.p.power_iters : 20;
+    size_t nmax = 0;
+    for (auto& d : h.lv) nmax = std::max(nmax, (size_t)d.n_n * D);
+    double* x = h.alloc<double>(nmax);
+    double* y = h.alloc<double>(nmax);
+    double* t = h.alloc<double>(nmax);
+    for (int l = 0; l < h.L; ++l) {
+      LevelData& d = h.lv[l];
+      const int n = d.n_n;
+      launch_random(x, (size_t)n * D, h.p.seed + 0x1000193ull * (l + 1), s);
+      double lam = 0;
+      for (int it = 0; it < iters; ++it) {
+        apply<double>(h, l, EPI_KU, x, nullptr, y, 1, s);
+        launch_smooth_zero<double>(n, D, 1, x, d.diag64, 1.0, t, nullptr, s);  // t = D x
+        double* o = h.red_out + 64;
+        launch_dot<double>(x, y, n, 1, D, h.red_partial, o, s);
+        launch_dot<double>(x, t, n, 1, D, h.red_partial, o + 1, s);
+        launch_smooth_zero<double>(n, D, 1, y, d.dinv64, 1.0, t, nullptr, s);  // t = D^-1 K x
+        launch_dot<double>(t, t, n, 1, D, h.red_partial, o + 2, s);
+        double hv[3];
+        host_dot(h, o, 3, hv, s);
+        lam = hv[1] > 0 ? hv[0] / hv[1] : 0.0;
+        const double nrm = std::sqrt(hv[2]);
+        if (!(nrm > 0) || !std::isfinite(nrm)) break;
+        launch_smooth_zero<double>(n, D, 1, y, d.dinv64, 1.0 / nrm, x, nullptr, s);
+      }
+      if (!(lam > 0) || !std::isfinite(lam)) fail(GMT_E_SINGULAR, "lambda_max estimate failed on level %d", l + 1);
+      d.lam = lam;
+    }
+  }
+  timer.mark("lambda");
+  GMT_HIP(hipStreamSynchronize(s));
+  h.release(flags);
+  h.release(scr);
+  h.release(d_total);
+  h.release(dmask);
+  coarse_factor(h, s);
+  timer.mark("coarse");
+}
+
+// ================================================================ solve
+
+static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, gmt_solve_report* rep,
+                  hipStream_t s, gmt_status* st) {
+  const double tol = o && o->tol > 0 ? o->tol : 1e-5;
+  const int max_iter = o && o->max_iter > 0 ? o->max_iter : 500;
+  const int max_outer = o && o->max_outer > 0 ? o->max_outer : 8;
+  const int prec = o ? o->precision : GMT_F64;
+  const int check = o && o->check_every > 0 ? o->check_every : 1;
+  if (prec != GMT_F64 && prec != GMT_F32) fail(GMT_E_INVAL, "bad precision");
+  const CycleCfg cfg = make_cycle(h, o ? &o->cycle : nullptr);
+  double* r64 = scratch64(h, &h.s_r64);
+  const int C = h.C;
+  const size_t tot = (size_t)h.lv[0].n_n * h.Q;
+  gmt_solve_report R{};
+  R.c = C;
+  double rel[8], den[8];
+  int its = 0;
+  for (int outer = 0;; ++outer) {
+    rel_residual64(h, f, u, r64, rel, den, s);
+    if (outer == 0 && zero_load(h, den)) {
+      // zero load: the solution in the pinned gauge is u = 0
+      launch_fill<double>(u, tot, 0.0, s);
+      for (int c = 0; c < C; ++c) rel[c] = 0.0;
+    }
+    double worst = 0;
+    for (int c = 0; c < C; ++c) {
+      if (!std::isfinite(rel[c])) worst = INFINITY;
+      else worst = std::max(worst, rel[c]);
+      R.rel_res[c] = rel[c];
+      if (outer == 0) R.rel_res_init[c] = rel[c];
+    }
+    R.outer = outer + 1;
+    if (worst <= tol) {
+      R.converged = 1;
+      break;
+    }
+    if (!std::isfinite(worst) || outer >= max_outer || its >= max_iter) break;
+    double itol[8];
+    // an FP32 inner solve is asked for at most four orders of reduction; the
+    // FP64 refinement step recovers the rest
+    const double floor = prec == GMT_F32 ? 1e-4 : 1e-14;
+    for (int c = 0; c < C; ++c) {
+      // target ||r_m|| <= tol/2 * den_m after this step; relative to the current ||r_m||
+      const double rn = rel[c] * den[c];
+      double t = rn > 0 ? 0.5 * tol * den[c] / rn : 1.0;
+      itol[c] = std::min(0.9, std::max(floor, t));
+    }
+    if (prec == GMT_F32) {
+      if (!h.s_b32) h.s_b32 = h.alloc<float>(tot);
+      if (!h.s_x32) h.s_x32 = h.alloc<float>(tot);
+      launch_convert<double, float>(r64, h.s_b32, tot, s);
+      its += pcg<float>(h, h.s_b32, h.s_x32, itol, max_iter - its, check, cfg, s);
+      launch_accumulate<float>(u, h.s_x32, tot, s);
+    } else {
+      double* x64 = scratch64(h, &h.s_x64);
+      its += pcg<double>(h, r64, x64, itol, max_iter - its, check, cfg, s);
+      launch_accumulate<double>(u, x64, tot, s);
+    }
+  }
+  launch_gauge_shift<double>(u, h.lv[0].n_n, h.Q, h.gauge_tmp64, s);
+  GMT_HIP(hipStreamSynchronize(s));
+  R.iterations = its;
+  if (rep) *rep = R;
+  *st = R.converged ? GMT_OK : GMT_E_NOCONV;
+  if (!R.converged) {
+    double worst = 0;
+    for (int c = 0; c < C; ++c) worst = std::max(worst, R.rel_res[c]);
+    g_last_error = "gmt_solve: tolerance not reached (residual " + std::to_string(worst) + " after " +
+                   std::to_string(its) + " iterations)";
+  }
+}
+
+}  // namespace gmt
+
+// ================================================================ C ABI
+
+using namespace gmt;
+
+struct gmt_hier {
+  Hier h;
+};
+
+static hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+static void check_level(const gmt_hier* H, int level) {
+  if (!H) fail(GMT_E_INVAL, "null hierarchy");
+  if (level < 1 || level > H->h.L) fail(GMT_E_INVAL, "level %d outside 1..%d", level, H->h.L);
+}
+
+static void check_dtype(int dtype) {
+  if (dtype != GMT_F64 && dtype != GMT_F32) fail(GMT_E_INVAL, "dtype must be GMT_F64 or GMT_F32");
+}
+
+template <typename T>
+static void smooth_api(Hier& h, int l, const T* f, T* u, int nu, int sm, double p1, double p2, hipStream_t s) {
+  h.ensure_work<T>();
+  Work<T>& W = h.work<T>();
+  T* cur = u;
+  T* alt = W.ualt[l];
+  smooth<T>(h, l, f, cur, alt, W.dvec[l], nu, false, sm, p1, p2, s);
+  if (cur != u) launch_copy<T>(cur, u, (size_t)h.lv[l].n_n * h.Q, s);
+}
+
+extern "C" {
+
+const char* gmt_last_error(void) { return g_last_error.c_str(); }
+
+gmt_status gmt_build_hierarchy(const uint8_t* d_voxels, int32_t N, const gmt_params* params, void* stream,
+                               gmt_hier_t* out) {
+  gmt_hier* H = nullptr;
+  gmt_status st = guarded([&] {
+    if (!out) fail(GMT_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!d_voxels) fail(GMT_E_INVAL, "voxels is NULL");
+    if (!params) fail(GMT_E_INVAL, "params is NULL");
+    if (N < 2 || N > 1024) fail(GMT_E_INVAL, "N = %d outside 2..1024", N);
+    const int L = params->levels;
+    if (L < 1 || L > 12) fail(GMT_E_INVAL, "levels = %d outside 1..12", L);
+    if (N % (1 << (L - 1)) != 0 || (N >> (L - 1)) < 2)
+      fail(GMT_E_INVAL, "N = %d must be divisible by 2^(L-1) = %d with N_L >= 2", N, 1 << (L - 1));
+    if (params->physics != GMT_ELASTIC && params->physics != GMT_THERMAL) fail(GMT_E_INVAL, "bad physics");
+    if ((params->alloc == nullptr) != (params->release == nullptr))
+      fail(GMT_E_INVAL, "alloc and release must be given together");
+    H = new gmt_hier();
+    Hier& h = H->h;
+    h.p = *params;
+    if (h.p.E == 0) h.p.E = 1.0;
+    if (h.p.nu == 0 && params->physics == GMT_ELASTIC) h.p.nu = 0.3;
+    if (h.p.kappa == 0) h.p.kappa = 1.0;
+    if (h.p.physics == GMT_ELASTIC && !(h.p.E > 0 && h.p.nu > -1.0 && h.p.nu < 0.5))
+      fail(GMT_E_INVAL, "need E > 0 and -1 < nu < 0.5");
+    if (h.p.physics == GMT_THERMAL && !(h.p.kappa > 0)) fail(GMT_E_INVAL, "need kappa > 0");
+    h.N = N;
+    h.L = L;
+    h.D = params->physics == GMT_ELASTIC ? 3 : 1;
+    h.C = params->physics == GMT_ELASTIC ? 6 : 3;
+    h.Q = h.C * h.D;
+    (void)ilog2_exact;
+    build(h, d_voxels, S(stream));
+    GMT_HIP(hipStreamSynchronize(S(stream)));
+    *out = H;
+  });
+  if (st != GMT_OK && H) {
+    (void)hipDeviceSynchronize();
+    H->h.release_all();
+    delete H;
+  }
+  return st;
+}
+
+void gmt_destroy(gmt_hier_t H) {
+  if (!H) return;
+  (void)hipDeviceSynchronize();
+  H->h.release_all();
+  delete H;
+}
+
+gmt_status gmt_level_info(gmt_hier_t H, int32_t level, gmt_level_desc* out) {
+  return guarded([&] {
+    check_level(H, level);
+    if (!out) fail(GMT_E_INVAL, "out is NULL");
+    const LevelData& d = H->h.lv[level - 1];
+    out->N = d.N;
+    out->n_e = d.n_e;
+    out->n_n = d.n_n;
+    out->c = H->h.C;
+    out->d = H->h.D;
+    out->lambda_max = d.lam;
+  });
+}
+
+gmt_status gmt_export_maps(gmt_hier_t H, int32_t level, int32_t* d_elem_lin, int32_t* d_node_lin, uint8_t* d_occ8,
+                           int32_t* d_elem_nodes, int32_t* d_prol_idx, double* d_prol_w, void* stream) {
+  return guarded([&] {
+    check_level(H, level);
+    Hier& h = H->h;
+    const LevelData& d = h.lv[level - 1];
+    hipStream_t s = S(stream);
+    if (d_elem_lin) GMT_HIP(hipMemcpyAsync(d_elem_lin, d.elem_lin, d.n_e * sizeof(int), hipMemcpyDeviceToDevice, s));
+    if (d_node_lin) GMT_HIP(hipMemcpyAsync(d_node_lin, d.node_lin, d.n_n * sizeof(int), hipMemcpyDeviceToDevice, s));
+    if (d_occ8) GMT_HIP(hipMemcpyAsync(d_occ8, d.occ8, d.n_n, hipMemcpyDeviceToDevice, s));
+    if (d_elem_nodes) launch_elem_nodes(d.elem_lin, d.n_e, d.node_map, d.N, d_elem_nodes, s);
+    if (d_prol_idx || d_prol_w) {
+      if (level == h.L) fail(GMT_E_INVAL, "no transfer stencil below the coarsest level");
+      const LevelData& c = h.lv[level];
+      launch_prol_maps(d.node_lin, d.n_n, d.N, c.node_map, c.N, d_prol_idx, d_prol_w, s);
+    }
+  });
+}
+
+gmt_status gmt_export_element_matrices(gmt_hier_t H, int32_t level, double* d_K, void* stream) {
+  return guarded([&] {
+    check_level(H, level);
+    if (!d_K) fail(GMT_E_INVAL, "d_K is NULL");
+    Hier& h = H->h;
+    const LevelData& d = h.lv[level - 1];
+    launch_expand_elem_matrices(h.view<double>(level - 1), d.kind, d.n_e, h.D, d.elem_lin, d_K, S(stream));
+  });
+}
+
+gmt_status gmt_export_diagonal(gmt_hier_t H, int32_t level, double* d_D, void* stream) {
+  return guarded([&] {
+    check_level(H, level);
+    if (!d_D) fail(GMT_E_INVAL, "d_D is NULL");
+    const LevelData& d = H->h.lv[level - 1];
+    GMT_HIP(hipMemcpyAsync(d_D, d.diag64, (size_t)d.n_n * H->h.D * sizeof(double), hipMemcpyDeviceToDevice,
+                           S(stream)));
+  });
+}
+
+gmt_status gmt_load_vector(gmt_hier_t H, void* d_f, int32_t dtype, void* stream) {
+  return guarded([&] {
+    check_level(H, 1);
+    check_dtype(dtype);
+    if (!d_f) fail(GMT_E_INVAL, "d_f is NULL");
+    Hier& h = H->h;
+    const size_t n = (size_t)h.lv[0].n_n * h.Q;
+    if (dtype == GMT_F64)
+      GMT_HIP(hipMemcpyAsync(d_f, h.f64, n * sizeof(double), hipMemcpyDeviceToDevice, S(stream)));
+    else
+      launch_convert<double, float>(h.f64, (float*)d_f, n, S(stream));
+  });
+}
+
+gmt_status gmt_apply_K(gmt_hier_t H, int32_t level, const void* d_u, void* d_y, int32_t dtype, void* stream) {
+  return guarded([&] {
+    check_level(H, level);
+    check_dtype(dtype);
+    if (!d_u || !d_y) fail(GMT_E_INVAL, "null vector");
+    if (d_u == d_y) fail(GMT_E_INVAL, "u and y must not alias");
+    Hier& h = H->h;
+    if (dtype == GMT_F64)
+      apply<double>(h, level - 1, EPI_KU, (const double*)d_u, nullptr, (double*)d_y, h.C, S(stream));
+    else
+      apply<float>(h, level - 1, EPI_KU, (const float*)d_u, nullptr, (float*)d_y, h.C, S(stream));
+  });
+}
+
+gmt_status gmt_residual(gmt_hier_t H, int32_t level, const void* d_f, const void* d_u, void* d_r, int32_t dtype,
+                        void* stream) {
+  return guarded([&] {
+    check_level(H, level);
+    check_dtype(dtype);
+    if (!d_f || !d_u || !d_r) fail(GMT_E_INVAL, "null vector");
+    if (d_r == d_u) fail(GMT_E_INVAL, "r and u must not alias");
+    Hier& h = H->h;
+    if (dtype == GMT_F64)
+      apply<double>(h, level - 1, EPI_RESID, (const double*)d_u, (const double*)d_f, (double*)d_r, h.C, S(stream));
+    else
+      apply<float>(h, level - 1, EPI_RESID, (const float*)d_u, (const float*)d_f, (float*)d_r, h.C, S(stream));
+  });
+}
+
+gmt_status gmt_smooth(gmt_hier_t H, int32_t level, const void* d_f, void* d_u, int32_t nu, int32_t smoother,
+                      double p1, double p2, int32_t dtype, void* stream) {
+  return guarded([&] {
+    check_level(H, level);
+    check_dtype(dtype);
+    if (!d_f || !d_u) fail(GMT_E_INVAL, "null vector");
+    if (nu < 0 || nu > 64) fail(GMT_E_INVAL, "nu out of range");
+    if (smoother == GMT_SMOOTH_CHEBYSHEV && !(p2 > p1 && p1 > 0)) fail(GMT_E_INVAL, "need 0 < lo < hi");
+    if (smoother != GMT_SMOOTH_CHEBYSHEV && smoother != GMT_SMOOTH_JACOBI) fail(GMT_E_INVAL, "bad smoother");
+    Hier& h = H->h;
+    if (dtype == GMT_F64)
+      smooth_api<double>(h, level - 1, (const double*)d_f, (double*)d_u, nu, smoother, p1, p2, S(stream));
+    else
+      smooth_api<float>(h, level - 1, (const float*)d_f, (float*)d_u, nu, smoother, p1, p2, S(stream));
+  });
+}
+
+gmt_status gmt_restrict(gmt_hier_t H, int32_t level, const void* d_rf, void* d_fc, int32_t dtype, void* stream) {
+  return guarded([&] {
+    check_level(H, level);
+    check_dtype(dtype);
+    if (level == H->h.L) fail(GMT_E_INVAL, "no level below the coarsest");
+    if (!d_rf || !d_fc) fail(GMT_E_INVAL, "null vector");
+    Hier& h = H->h;
+    if (dtype == GMT_F64)
+      launch_restrict<double>(h.view<double>(level - 1), h.view<double>(level), h.Q, (const double*)d_rf,
+                              (double*)d_fc, S(stream));
+    else
+      launch_restrict<float>(h.view<float>(level - 1), h.view<float>(level), h.Q, (const float*)d_rf,
+                             (float*)d_fc, S(stream));
+  });
+}
+
+gmt_status gmt_prolong_add(gmt_hier_t H, int32_t level, const void* d_uc, void* d_uf, int32_t dtype, void* stream) {
+  return guarded([&] {
+    check_level(H, level);
+    check_dtype(dtype);
+    if (level == H->h.L) fail(GMT_E_INVAL, "no level below the coarsest");
+    if (!d_uc || !d_uf) fail(GMT_E_INVAL, "null vector");
+    Hier& h = H->h;
+    if (dtype == GMT_F64)
+      launch_prolong_add<double>(h.view<double>(level - 1), h.view<double>(level), h.Q, (const double*)d_uc,
+                                 (double*)d_uf, S(stream));
+    else
+      launch_prolong_add<float>(h.view<float>(level - 1), h.view<float>(level), h.Q, (const float*)d_uc,
+                                (float*)d_uf, S(stream));
+  });
+}
+
+gmt_status gmt_coarse_solve(gmt_hier_t H, const void* d_f, void* d_u, int32_t dtype, void* stream) {
+  return guarded([&] {
+    check_level(H, 1);
+    check_dtype(dtype);
+    if (!d_f || !d_u || d_f == d_u) fail(GMT_E_INVAL, "null or aliased vector");
+    Hier& h = H->h;
+    if (dtype == GMT_F64)
+      launch_coarse_solve<double>(h.cinv64, h.cn, h.D, h.C, (const double*)d_f, (double*)d_u, S(stream));
+    else
+      launch_coarse_solve<float>(h.cinv32, h.cn, h.D, h.C, (const float*)d_f, (float*)d_u, S(stream));
+  });
+}
+
+gmt_status gmt_vcycle(gmt_hier_t H, const void* d_f, void* d_u, const void* const* d_e_init,
+                      const gmt_cycle_opts* opts, int32_t dtype, void* stream) {
+  return guarded([&] {
+    check_level(H, 1);
+    check_dtype(dtype);
+    if (!d_f || !d_u || d_f == d_u) fail(GMT_E_INVAL, "null or aliased vector");
+    Hier& h = H->h;
+    const CycleCfg cfg = make_cycle(h, opts);
+    if (dtype == GMT_F64)
+      vcycle<double>(h, (const double*)d_f, (double*)d_u, false, (const double* const*)d_e_init, cfg, S(stream));
+    else
+      vcycle<float>(h, (const float*)d_f, (float*)d_u, false, (const float* const*)d_e_init, cfg, S(stream));
+  });
+}
+
+gmt_status gmt_solve(gmt_hier_t H, const void* d_f, void* d_u, const gmt_solve_opts* opts, gmt_solve_report* report,
+                     void* stream) {
+  gmt_status st = GMT_OK;
+  gmt_status g = guarded([&] {
+    check_level(H, 1);
+    if (!d_f || !d_u || d_f == d_u) fail(GMT_E_INVAL, "null or aliased vector");
+    solve(H->h, (const double*)d_f, (double*)d_u, opts, report, S(stream), &st);
+  });
+  return g != GMT_OK ? g : st;
+}
+
+gmt_status gmt_relative_residual(gmt_hier_t H, const void* d_f, const void* d_u, int32_t dtype, double* h_rel,
+                                 void* stream) {
+  return guarded([&] {
+    check_level(H, 1);
+    check_dtype(dtype);
+    if (!d_f || !d_u || !h_rel) fail(GMT_E_INVAL, "null pointer");
+    Hier& h = H->h;
+    const size_t tot = (size_t)h.lv[0].n_n * h.Q;
+    const double *f = (const double*)d_f, *u = (const double*)d_u;
+    hipStream_t s = S(stream);
+    if (dtype == GMT_F32) {
+      double* tf = scratch64(h, &h.s_x64);
+      double* tu = scratch64(h, &h.s_t64);
+      launch_convert<float, double>((const float*)d_f, tf, tot, s);
+      launch_convert<float, double>((const float*)d_u, tu, tot, s);
+      f = tf;
+      u = tu;
+    }
+    rel_residual64(h, f, u, scratch64(h, &h.s_r64), h_rel, nullptr, s);
+  });
+}
+
+gmt_status gmt_homogenize(gmt_hier_t H, const void* d_u, int32_t dtype, double* h_CH, void* stream) {
+  return guarded([&] {
+    check_level(H, 1);
+    check_dtype(dtype);
+    if (!d_u || !h_CH) fail(GMT_E_INVAL, "null pointer");
+    Hier& h = H->h;
+    hipStream_t s = S(stream);
+    const int n = h.lv[0].n_n, C = h.C;
+    const size_t tot = (size_t)n * h.Q;
+    const double* u = (const double*)d_u;
+    if (dtype == GMT_F32) {
+      double* tu = scratch64(h, &h.s_t64);
+      launch_convert<float, double>((const float*)d_u, tu, tot, s);
+      u = tu;
+    }
+    double* y = scratch64(h, &h.s_r64);
+    apply<double>(h, 0, EPI_KU, u, nullptr, y, C, s);
+    double* A = h.red_out + 96;
+    double* B = h.red_out + 160;
+    launch_gram<double, double>(h.f64, u, n, C, h.D, h.red_partial, A, s);  // A[i][j] = f_i . u_j
+    launch_gram<double, double>(u, y, n, C, h.D, h.red_partial, B, s);      // B[i][j] = u_i . (K u)_j
+    double Ah[36], Bh[36];
+    host_dot(h, A, C * C, Ah, s);
+    host_dot(h, B, C * C, Bh, s);
+    const double vol = (double)h.N * h.N * h.N;
+    const double ne = h.lv[0].n_e;
+    for (int i = 0; i < C; ++i)
+      for (int j = 0; j < C; ++j)
+        h_CH[i * C + j] = (ne * h.C0[i * C + j] - Ah[i * C + j] - Ah[j * C + i] + Bh[i * C + j]) / vol;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,1128 @@
+// gfx950 kernels of libgmt: node-centric EBE operator sweeps, transfers,
+// reductions and the hierarchy-construction passes.
+//
+// Node-centric EBE (Sec. 4.6): y_i = sum over the (up to) 8 active elements e
+// around node i of the 3 (elastic) / 1 (thermal) rows of K_e belonging to
+// i's local corner, times the element vector u_e.  Summed over all nodes this
+// performs exactly the element products of sum_e A_e^T K_e A_e u, without
+// atomics, so every result is deterministic.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace gmt {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ int wrapm(int v, int N) { return v < 0 ? v + N : (v >= N ? v - N : v); }
+
+// ---------------------------------------------------------------- operator sweeps
+
+// Epilogue for one (case, dof) value.
+template <typename T, int EPI>
+__device__ __forceinline__ void epilogue(const EpiArgs<T>& e, size_t idx, T acc, T uself, T dinv) {
+  if constexpr (EPI == EPI_KU) {
+    e.out[idx] = acc;
+  } else if constexpr (EPI == EPI_RESID) {
+    e.out[idx] = e.f[idx] - acc;
+  } else if constexpr (EPI == EPI_JACOBI) {
+    e.out[idx] = uself + e.omega * dinv * (e.f[idx] - acc);
+  } else {
+    T dn = e.rho2 * dinv * (e.f[idx] - acc);
+    if (e.rho1 != T(0)) dn += e.rho1 * e.dvec[idx];
+    e.dvec[idx] = dn;
+    e.out[idx] = uself + dn;
+  }
+}
+
+// Level 1: the shared voxel K_e, element activity from the node's occupancy byte.
+// One thread per node; for each case the 27 neighbour values live in registers
+// and the K_e coefficients are wave-uniform (scalar loads).
+template <typename T, int D, int EPI>
+__global__ __launch_bounds__(kBlock) void k_apply_shared(LevelView<T> L, int C,
+                                                         const T* __restrict__ u, EpiArgs<T> e) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.n_n) return;
+  const int N = L.N;
+  const int lin = L.node_lin[i];
+  const int x = lin % N;
+  const int t = lin / N;
+  const int y = t % N;
+  const int z = t / N;
+  const int xs[3] = {wrapm(x - 1, N), x, wrapm(x + 1, N)};
+  const int ys[3] = {wrapm(y - 1, N), y, wrapm(y + 1, N)};
+  const int zs[3] = {wrapm(z - 1, N), z, wrapm(z + 1, N)};
+  int nb[27];
+#pragma unroll
+  for (int j = 0; j < 27; ++j) nb[j] = L.node_map[xs[j % 3] + N * (ys[(j / 3) % 3] + N * zs[j / 9])];
+  const unsigned occ = L.occ8[i];
+  const T* __restrict__ K = L.K;
+  for (int c = 0; c < C; ++c) {
+    T uv[27][D];
+#pragma unroll
+    for (int j = 0; j < 27; ++j) {
+#pragma unroll
+      for (int q = 0; q < D; ++q) uv[j][q] = nb[j] >= 0 ? u[((size_t)nb[j] * C + c) * D + q] : T(0);
+    }
+    T acc[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) acc[q] = T(0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (occ & (1u << k)) {
+        const int a = 7 - k;
+        const int ak = k & 1, bk = (k >> 1) & 1, ck = (k >> 2) & 1;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const int j = (ak + (m & 1)) + 3 * (bk + ((m >> 1) & 1)) + 9 * (ck + ((m >> 2) & 1));
+#pragma unroll
+          for (int q = 0; q < D; ++q) {
+#pragma unroll
+            for (int q2 = 0; q2 < D; ++q2)
+              acc[q] = fma(K[(a * D + q) * (8 * D) + m * D + q2], uv[j][q2], acc[q]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      T dv = T(0);
+      if constexpr (EPI == EPI_JACOBI || EPI == EPI_CHEB) dv = e.dinv[(size_t)i * D + q];
+      epilogue<T, EPI>(e, ((size_t)i * C + c) * D + q, acc[q], uv[13][q], dv);
+    }
+  }
+}
+
+// Levels >= 2: per-element matrices (mask table or stored), element ids from
+// the dense element map.  Element-outer loop: the 3 coefficient rows of an
+// element are loaded once and used for all C cases.
+template <typename T, int D, int C, int KIND, int EPI>
+__global__ __launch_bounds__(kBlock) void k_apply_coarse(LevelView<T> L, const T* __restrict__ u,
+                                                         EpiArgs<T> e) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.n_n) return;
+  const int N = L.N;
+  const int lin = L.node_lin[i];
+  const int x = lin % N;
+  const int t = lin / N;
+  const int y = t % N;
+  const int z = t / N;
+  const int xs[3] = {wrapm(x - 1, N), x, wrapm(x + 1, N)};
+  const int ys[3] = {wrapm(y - 1, N), y, wrapm(y + 1, N)};
+  const int zs[3] = {wrapm(z - 1, N), z, wrapm(z + 1, N)};
+  T acc[C][D];
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int q = 0; q < D; ++q) acc[c][q] = T(0);
+  constexpr int M = 8 * D;
+#pragma unroll 1
+  for (int k = 0; k < 8; ++k) {
+    const int ak = k & 1, bk = (k >> 1) & 1, ck = (k >> 2) & 1;
+    const int eid = L.elem_map[xs[ak] + N * (ys[bk] + N * zs[ck])];
+    if (eid < 0) continue;
+    const T* __restrict__ Km;
+    if constexpr (KIND == KIND_TABLE)
+      Km = L.K + (size_t)L.cmask[eid] * M * M;
+    else
+      Km = L.K + (size_t)eid * M * M;
+    Km += (7 - k) * D * M;
+#pragma unroll 1
+    for (int m = 0; m < 8; ++m) {
+      const int nx = xs[ak + (m & 1)], ny = ys[bk + ((m >> 1) & 1)], nz = zs[ck + ((m >> 2) & 1)];
+      const int id = L.node_map[nx + N * (ny + N * nz)];
+      if (id < 0) continue;  // cannot happen: corners of active elements are active
+      T coef[D][D];
+#pragma unroll
+      for (int q = 0; q < D; ++q)
+#pragma unroll
+        for (int q2 = 0; q2 < D; ++q2) coef[q][q2] = Km[q * M + m * D + q2];
+      const T* __restrict__ un = u + (size_t)id * C * D;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+#pragma unroll
+        for (int q2 = 0; q2 < D; ++q2) {
+          const T v = un[c * D + q2];
+#pragma unroll
+          for (int q = 0; q < D; ++q) acc[c][q] = fma(coef[q][q2], v, acc[c][q]);
+        }
+      }
+    }
+  }
+  const T* __restrict__ us = u + (size_t)i * C * D;
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      T dv = T(0);
+      if constexpr (EPI == EPI_JACOBI || EPI == EPI_CHEB) dv = e.dinv[(size_t)i * D + q];
+      T uself = T(0);
+      if constexpr (EPI == EPI_JACOBI || EPI == EPI_CHEB) uself = us[c * D + q];
+      epilogue<T, EPI>(e, ((size_t)i * C + c) * D + q, acc[c][q], uself, dv);
+    }
+}
+
+// First smoothing step from a zero iterate: u = scale * D^-1 f (K 0 = 0).
+template <typename T>
+__global__ void k_smooth_zero(int n, int D, int C, const T* __restrict__ f, const T* __restrict__ dinv,
+                              T scale, T* __restrict__ out, T* __restrict__ dvec) {
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  const size_t total = (size_t)n * C * D;
+  if (idx >= total) return;
+  const size_t node = idx / ((size_t)C * D);
+  const int q = (int)(idx % D);
+  const T v = scale * dinv[node * D + q] * f[idx];
+  out[idx] = v;
+  if (dvec) dvec[idx] = v;
+}
+
+// ---------------------------------------------------------------- transfers (App. E.2)
+
+// Restriction in gather form: coarse node X collects the fine nodes 2X + delta,
+// delta in {-1,0,1}^3, with weight prod_d (1 - |delta_d|/2): exactly R = P^T.
+template <typename T, int Q>
+__global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> F, LevelView<T> Cv, const T* __restrict__ rf,
+                                                     T* __restrict__ fc) {
+  const int J = blockIdx.x * kBlock + threadIdx.x;
+  if (J >= Cv.n_n) return;
+  const int Nc = Cv.N, Nf = F.N;
+  const int lin = Cv.node_lin[J];
+  const int X = lin % Nc;
+  const int t = lin / Nc;
+  const int Y = t % Nc;
+  const int Z = t / Nc;
+  T acc[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) acc[q] = T(0);
+#pragma unroll 1
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int fz = wrapm(2 * Z + dz, Nf);
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int fy = wrapm(2 * Y + dy, Nf);
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int fx = wrapm(2 * X + dx, Nf);
+        const int id = F.node_map[fx + Nf * (fy + Nf * fz)];
+        if (id < 0) continue;
+        const T w = T((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
+        const T* __restrict__ r = rf + (size_t)id * Q;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) acc[q] = fma(w, r[q], acc[q]);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) fc[(size_t)J * Q + q] = acc[q];
+}
+
+// Prolongation + correction: u_f(i) += sum_k W_ik u_c(I_ik) (App. E.1 weights).
+template <typename T, int Q>
+__global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView<T> F, LevelView<T> Cv, const T* __restrict__ uc,
+                                                        T* __restrict__ uf) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= F.n_n) return;
+  const int Nc = Cv.N, Nf = F.N;
+  const int lin = F.node_lin[i];
+  const int x = lin % Nf;
+  const int t = lin / Nf;
+  const int y = t % Nf;
+  const int z = t / Nf;
+  // per axis: even coordinate -> one parent (weight 1); odd -> two (1/2 each)
+  const int cx0 = x >> 1, cy0 = y >> 1, cz0 = z >> 1;
+  const int nx = (x & 1) ? 2 : 1, ny = (y & 1) ? 2 : 1, nz = (z & 1) ? 2 : 1;
+  T acc[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) acc[q] = uf[(size_t)i * Q + q];
+  const T w = T(1.0 / (nx * ny * nz));
+#pragma unroll 1
+  for (int oz = 0; oz < nz; ++oz)
+    for (int oy = 0; oy < ny; ++oy)
+      for (int ox = 0; ox < nx; ++ox) {
+        const int X = wrapm(cx0 + ox, Nc), Y = wrapm(cy0 + oy, Nc), Z = wrapm(cz0 + oz, Nc);
+        const int id = Cv.node_map[X + Nc * (Y + Nc * Z)];
+        if (id < 0) continue;  // cannot happen for a consistent hierarchy
+        const T* __restrict__ v = uc + (size_t)id * Q;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) acc[q] = fma(w, v[q], acc[q]);
+      }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) uf[(size_t)i * Q + q] = acc[q];
+}
+
+// ---------------------------------------------------------------- coarsest solve
+
+// u = Kinv f with Kinv the pinned inverse (symmetric, pinned rows/cols zero).
+// One thread per DOF row; reads Kinv column-wise (= row-wise by symmetry).
+template <typename T, int C>
+__global__ void k_coarse_solve(const T* __restrict__ Kinv, int cn, int D, const T* __restrict__ f,
+                               T* __restrict__ u) {
+  const int row = blockIdx.x * kBlock + threadIdx.x;
+  if (row >= cn) return;
+  double acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = 0.0;
+  for (int j = 0; j < cn; ++j) {
+    const double kv = (double)Kinv[(size_t)j * cn + row];
+    const int node = j / D, q = j % D;
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] += kv * (double)f[((size_t)node * C + c) * D + q];
+  }
+  const int node = row / D, q = row % D;
+#pragma unroll
+  for (int c = 0; c < C; ++c) u[((size_t)node * C + c) * D + q] = (T)acc[c];
+}
+
+// ---------------------------------------------------------------- vector kernels
+
+template <typename T>
+__global__ void k_fill(T* p, size_t n, T v) {
+  size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_convert(const Tin* __restrict__ a, Tout* __restrict__ b, size_t n) {
+  size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) b[i] = (Tout)a[i];
+}
+
+template <typename T>
+__global__ void k_inv(const T* __restrict__ a, T* __restrict__ b, size_t n) {
+  size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) b[i] = a[i] != T(0) ? T(1) / a[i] : T(0);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Block reduction of NV values per thread -> partial[block][NV]; fixed order.
+template <int NV>
+__device__ void block_reduce_store(double (&v)[NV], double* __restrict__ partial) {
+  __shared__ double sh[kBlock / 64][NV];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = wave_sum(v[k]);
+    if (lane == 0) sh[wid][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) s += sh[w][threadIdx.x];
+    partial[(size_t)blockIdx.x * NV + threadIdx.x] = s;
+  }
+}
+
+template <typename T, int C, int D>
+__global__ __launch_bounds__(kBlock) void k_dot(const T* __restrict__ a, const T* __restrict__ b, int n,
+                                                double* __restrict__ partial) {
+  double v[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) v[c] = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        const size_t idx = ((size_t)i * C + c) * D + q;
+        v[c] += (double)a[idx] * (double)b[idx];
+      }
+  }
+  block_reduce_store<C>(v, partial);
+}
+
+template <typename Ta, typename Tb, int C, int D>
+__global__ __launch_bounds__(kBlock) void k_gram(const Ta* __restrict__ a, const Tb* __restrict__ b, int n,
+                                                 double* __restrict__ partial) {
+  double v[C * C];
+#pragma unroll
+  for (int c = 0; c < C * C; ++c) v[c] = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    double av[C][D], bv[C][D];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        av[c][q] = (double)a[((size_t)i * C + c) * D + q];
+        bv[c][q] = (double)b[((size_t)i * C + c) * D + q];
+      }
+#pragma unroll
+    for (int c1 = 0; c1 < C; ++c1)
+#pragma unroll
+      for (int c2 = 0; c2 < C; ++c2)
+#pragma unroll
+        for (int q = 0; q < D; ++q) v[c1 * C + c2] += av[c1][q] * bv[c2][q];
+  }
+  block_reduce_store<C * C>(v, partial);
+}
+
+// Column sums over nodes: partial[block][q] = sum_i v[i][q] (FP64 accumulation).
+template <typename T, int Q>
+__global__ __launch_bounds__(kBlock) void k_colsum(const T* __restrict__ v, int n, double* __restrict__ partial) {
+  double acc[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) acc[q] = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q] += (double)v[(size_t)i * Q + q];
+  }
+  block_reduce_store<Q>(acc, partial);
+}
+
+// v[i][q] -= sums[q] / n : removes the rigid-translation (constant) component.
+template <typename T>
+__global__ void k_sub_mean(T* __restrict__ v, size_t total, int Q, const double* __restrict__ sums, double inv_n) {
+  size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < total) v[i] -= (T)(sums[i % Q] * inv_n);
+}
+
+// Second stage: out[k] = sum over blocks of partial[b][k], fixed order.
+__global__ void k_reduce_final(const double* __restrict__ partial, int nblocks, int nv, double* __restrict__ out) {
+  __shared__ double sh[kBlock];
+  for (int k = 0; k < nv; ++k) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) s += partial[(size_t)b * nv + k];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = sh[0];
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ void k_pcg_update(T* __restrict__ u, T* __restrict__ r, const T* __restrict__ p,
+                             const T* __restrict__ q, const double* __restrict__ alpha, size_t n, int C,
+                             int D) {
+  size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const T a = (T)alpha[(i / D) % C];
+  u[i] = fma(a, p[i], u[i]);
+  r[i] = fma(-a, q[i], r[i]);
+}
+
+template <typename T>
+__global__ void k_pcg_direction(T* __restrict__ p, const T* __restrict__ z, const double* __restrict__ beta,
+                                size_t n, int C, int D) {
+  size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const T b = (T)beta[(i / D) % C];
+  p[i] = fma(b, p[i], z[i]);
+}
+
+__global__ void k_pcg_alpha(const double* rz, const double* pq, double* alpha, int C) {
+  int c = threadIdx.x;
+  if (c < C) alpha[c] = (pq[c] > 0.0 && isfinite(rz[c] / pq[c])) ? rz[c] / pq[c] : 0.0;
+}
+
+__global__ void k_pcg_beta(const double* rz_new, double* rz, double* beta, int C) {
+  int c = threadIdx.x;
+  if (c < C) {
+    beta[c] = (rz[c] != 0.0 && isfinite(rz_new[c] / rz[c])) ? rz_new[c] / rz[c] : 0.0;
+    rz[c] = rz_new[c];
+  }
+}
+
+template <typename T>
+__global__ void k_copy_node(const T* __restrict__ u, int Q, T* __restrict__ tmp) {
+  if ((int)threadIdx.x < Q) tmp[threadIdx.x] = u[threadIdx.x];
+}
+
+template <typename T>
+__global__ void k_sub_node(T* __restrict__ u, size_t n, int Q, const T* __restrict__ tmp) {
+  size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) u[i] -= tmp[i % Q];
+}
+
+template <typename T>
+__global__ void k_accumulate(double* __restrict__ u, const T* __restrict__ d, size_t n) {
+  size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) u[i] += (double)d[i];
+}
+
+// ---------------------------------------------------------------- hierarchy construction
+
+__global__ void k_voxel_flags(const uint8_t* __restrict__ vox, size_t n, int* __restrict__ flags) {
+  size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) flags[i] = vox[i] != 0;
+}
+
+// node (x,y,z) active iff element (x-a, y-b, z-c) is active for some corner (a,b,c)
+// (vertex union of eq. gmgcoarsenode); input: dense element map (>= 0 active)
+__global__ void k_node_flags(const int* __restrict__ emap, int N, int* __restrict__ nflags) {
+  size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  const size_t n = (size_t)N * N * N;
+  if (i >= n) return;
+  const int x = (int)(i % N), y = (int)((i / N) % N), z = (int)(i / ((size_t)N * N));
+  int f = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int ex = wrapm(x - (k & 1), N), ey = wrapm(y - ((k >> 1) & 1), N), ez = wrapm(z - ((k >> 2) & 1), N);
+    f |= emap[ex + N * (ey + N * ez)] >= 0;
+  }
+  nflags[i] = f;
+}
+
+// coarse voxel (I,J,K) active iff any child (2I+a, 2J+b, 2K+c) is active; the
+// child pattern is kept as a mask byte (bit a+2b+4c)
+__global__ void k_coarsen(const int* __restrict__ femap, int Nf, int* __restrict__ cflags,
+                          uint8_t* __restrict__ dcmask) {
+  const int Nc = Nf / 2;
+  size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  const size_t n = (size_t)Nc * Nc * Nc;
+  if (i >= n) return;
+  const int X = (int)(i % Nc), Y = (int)((i / Nc) % Nc), Z = (int)(i / ((size_t)Nc * Nc));
+  unsigned m = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int fx = 2 * X + (c & 1), fy = 2 * Y + ((c >> 1) & 1), fz = 2 * Z + ((c >> 2) & 1);
+    if (femap[fx + Nf * (fy + Nf * fz)] >= 0) m |= 1u << c;
+  }
+  cflags[i] = m != 0;
+  dcmask[i] = (uint8_t)m;
+}
+
+// --- scan: 256 threads x 16 items per block
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ int block_exclusive_scan(int v, int* total) {
+  __shared__ int wsum[kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int tt = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += tt;
+  }
+  if (lane == 63) wsum[wid] = incl;
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) {
+    if (w < wid) off += wsum[w];
+    tot += wsum[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + incl - v;
+}
+
+__global__ void k_scan_reduce(const int* __restrict__ flags, size_t n, int* __restrict__ bsum) {
+  const size_t base = (size_t)blockIdx.x * kScanTile;
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    size_t i = base + (size_t)k * kBlock + threadIdx.x;
+    if (i < n) s += flags[i];
+  }
+  int tot;
+  block_exclusive_scan(s, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// exclusive scan of nb block sums by one block; total -> *d_total
+__global__ void k_scan_top(int* __restrict__ bsum, int nb, int* __restrict__ d_total) {
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < nb; base += kBlock) {
+    const int i = base + threadIdx.x;
+    const int v = i < nb ? bsum[i] : 0;
+    int tot;
+    const int ex = block_exclusive_scan(v, &tot);
+    const int c0 = carry;
+    if (i < nb) bsum[i] = c0 + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) carry = c0 + tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *d_total = carry;
+}
+
+// per block: ids of the flagged items in linear order; map (id or -1), lin (id -> index)
+__global__ void k_scan_compact(const int* __restrict__ flags, size_t n, const int* __restrict__ boff,
+                               int* __restrict__ map, int* __restrict__ lin) {
+  const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    size_t i = base + k;
+    v[k] = i < n ? flags[i] : 0;
+    s += v[k];
+  }
+  int tot;
+  int off = block_exclusive_scan(s, &tot) + boff[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    size_t i = base + k;
+    if (i < n) {
+      if (v[k]) {
+        map[i] = off;
+        if (lin) lin[off] = (int)i;
+        ++off;
+      } else {
+        map[i] = -1;
+      }
+    }
+  }
+}
+
+__global__ void k_occ8(const int* __restrict__ node_lin, int n_n, const int* __restrict__ emap, int N,
+                       uint8_t* __restrict__ occ8) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n_n) return;
+  const int lin = node_lin[i];
+  const int x = lin % N, y = (lin / N) % N, z = lin / (N * N);
+  unsigned m = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int ex = wrapm(x - 1 + (k & 1), N), ey = wrapm(y - 1 + ((k >> 1) & 1), N),
+              ez = wrapm(z - 1 + ((k >> 2) & 1), N);
+    if (emap[ex + N * (ey + N * ez)] >= 0) m |= 1u << k;
+  }
+  occ8[i] = (uint8_t)m;
+}
+
+__global__ void k_gather_cmask(const int* __restrict__ elem_lin, int n_e, const uint8_t* __restrict__ dense,
+                               uint8_t* __restrict__ cmask) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e < n_e) cmask[e] = dense[elem_lin[e]];
+}
+
+__global__ void k_elem_nodes(const int* __restrict__ elem_lin, int n_e, const int* __restrict__ node_map, int N,
+                             int* __restrict__ out) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n_e) return;
+  const int lin = elem_lin[e];
+  const int x = lin % N, y = (lin / N) % N, z = lin / (N * N);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int nx = wrapm(x + (k & 1), N), ny = wrapm(y + ((k >> 1) & 1), N), nz = wrapm(z + ((k >> 2) & 1), N);
+    out[(size_t)e * 8 + k] = node_map[nx + N * (ny + N * nz)];
+  }
+}
+
+// App. E.1: x_c = floor(x_f/2), corners (x_c + o_k) mod N_c, w_k = prod (1 - |xi - o|)
+__global__ void k_prol_maps(const int* __restrict__ node_lin, int n_n, int Nf, const int* __restrict__ cmap,
+                            int Nc, int* __restrict__ idx, double* __restrict__ w) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n_n) return;
+  const int lin = node_lin[i];
+  const int x = lin % Nf, y = (lin / Nf) % Nf, z = lin / (Nf * Nf);
+  const double xi[3] = {(x & 1) * 0.5, (y & 1) * 0.5, (z & 1) * 0.5};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int o[3] = {k & 1, (k >> 1) & 1, (k >> 2) & 1};
+    double wk = 1.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) wk *= 1.0 - fabs(xi[d] - (double)o[d]);
+    int id = -1;
+    if (wk != 0.0) {
+      const int X = wrapm((x >> 1) + o[0], Nc), Y = wrapm((y >> 1) + o[1], Nc), Z = wrapm((z >> 1) + o[2], Nc);
+      id = cmap[X + Nc * (Y + Nc * Z)];
+    }
+    if (idx) idx[(size_t)i * 8 + k] = id;
+    if (w) w[(size_t)i * 8 + k] = wk;
+  }
+}
+
+// Local Galerkin projection (Sec. 4.6): K_E = sum_{active children c} P_c^T K_c P_c,
+// P_c = Ps_c (8x8 trilinear weights) (x) I_D.  One block per coarse element.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_galerkin(const int* __restrict__ elem_lin_c, int Nc,
+                                                     const int* __restrict__ emap_f,
+                                                     const uint8_t* __restrict__ cmask_f,
+                                                     const double* __restrict__ Ksrc, int src_kind,
+                                                     const double* __restrict__ Ps, double* __restrict__ out64,
+                                                     float* __restrict__ out32) {
+  constexpr int M = 8 * D;
+  __shared__ double Kc[M * M];
+  __shared__ double T1[M * M];
+  __shared__ double acc[M * M];
+  __shared__ double P[64];
+  const int e = blockIdx.x;
+  const int Nf = 2 * Nc;
+  const int lin = elem_lin_c[e];
+  const int X = lin % Nc, Y = (lin / Nc) % Nc, Z = lin / (Nc * Nc);
+  for (int t = threadIdx.x; t < M * M; t += kBlock) acc[t] = 0.0;
+  for (int c = 0; c < 8; ++c) {
+    const int fx = 2 * X + (c & 1), fy = 2 * Y + ((c >> 1) & 1), fz = 2 * Z + ((c >> 2) & 1);
+    const int fid = emap_f[fx + Nf * (fy + Nf * fz)];
+    if (fid < 0) continue;  // uniform across the block
+    const double* src = src_kind == KIND_SHARED ? Ksrc
+                        : src_kind == KIND_TABLE ? Ksrc + (size_t)cmask_f[fid] * M * M
+                                                 : Ksrc + (size_t)fid * M * M;
+    __syncthreads();
+    for (int t = threadIdx.x; t < M * M; t += kBlock) Kc[t] = src[t];
+    if (threadIdx.x < 64) P[threadIdx.x] = Ps[c * 64 + threadIdx.x];
+    __syncthreads();
+    // T1[(m,i),(p,j)] = sum_n Kc[(m,i),(n,j)] P[n][p]
+    for (int t = threadIdx.x; t < M * M; t += kBlock) {
+      const int row = t / M, col = t % M;
+      const int p = col / D, j = col % D;
+      double s = 0.0;
+#pragma unroll
+      for (int n = 0; n < 8; ++n) s += Kc[row * M + n * D + j] * P[n * 8 + p];
+      T1[t] = s;
+    }
+    __syncthreads();
+    // acc[(o,i),(p,j)] += sum_m P[m][o] T1[(m,i),(p,j)]
+    for (int t = threadIdx.x; t < M * M; t += kBlock) {
+      const int row = t / M, col = t % M;
+      const int o = row / D, i = row % D;
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) s += P[m * 8 + o] * T1[(m * D + i) * M + col];
+      acc[t] += s;
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < M * M; t += kBlock) {
+    out64[(size_t)e * M * M + t] = acc[t];
+    out32[(size_t)e * M * M + t] = (float)acc[t];
+  }
+}
+
+template <typename T, int D, int KIND>
+__global__ void k_diagonal(LevelView<T> L, T* __restrict__ diag) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.n_n) return;
+  constexpr int M = 8 * D;
+  const int N = L.N;
+  const int lin = L.node_lin[i];
+  const int x = lin % N, y = (lin / N) % N, z = lin / (N * N);
+  T acc[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) acc[q] = T(0);
+  for (int k = 0; k < 8; ++k) {
+    const T* Km;
+    if constexpr (KIND == KIND_SHARED) {
+      if (!(L.occ8[i] & (1u << k))) continue;
+      Km = L.K;
+    } else {
+      const int ex = wrapm(x - 1 + (k & 1), N), ey = wrapm(y - 1 + ((k >> 1) & 1), N),
+                ez = wrapm(z - 1 + ((k >> 2) & 1), N);
+      const int eid = L.elem_map[ex + N * (ey + N * ez)];
+      if (eid < 0) continue;
+      Km = KIND == KIND_TABLE ? L.K + (size_t)L.cmask[eid] * M * M : L.K + (size_t)eid * M * M;
+    }
+    const int a = 7 - k;
+#pragma unroll
+    for (int q = 0; q < D; ++q) acc[q] += Km[(a * D + q) * M + a * D + q];
+  }
+#pragma unroll
+  for (int q = 0; q < D; ++q) diag[(size_t)i * D + q] = acc[q];
+}
+
+// Every element matrix of a level as an explicit [n_e][M][M] array (export / coarsest assembly).
+template <int D, int KIND>
+__global__ void k_expand_elem(LevelView<double> L, int n_e, const int* __restrict__ elem_lin,
+                              double* __restrict__ out) {
+  constexpr int M = 8 * D;
+  const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= (size_t)n_e * M * M) return;
+  const int e = (int)(t / (M * M));
+  const int r = (int)(t % (M * M));
+  double v;
+  if constexpr (KIND == KIND_SHARED)
+    v = L.K[r];
+  else if constexpr (KIND == KIND_TABLE)
+    v = L.K[(size_t)L.cmask[e] * M * M + r];
+  else
+    v = L.K[(size_t)e * M * M + r];
+  out[t] = v;
+}
+
+// f_i = sum over active octant elements of the rows of f_e = K_e X0 at i's corner
+__global__ void k_load_vector(const int* __restrict__ node_lin, const uint8_t* __restrict__ occ8, int n_n,
+                              int D, int C, const double* __restrict__ fe, double* __restrict__ f) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n_n) return;
+  const unsigned occ = occ8[i];
+  for (int c = 0; c < C; ++c)
+    for (int q = 0; q < D; ++q) {
+      double s = 0.0;
+      for (int k = 0; k < 8; ++k)
+        if (occ & (1u << k)) s += fe[((7 - k) * D + q) * C + c];
+      f[((size_t)i * C + c) * D + q] = s;
+    }
+}
+
+// counter-based uniform(-1,1) values (splitmix64 finaliser of seed + index)
+__global__ void k_random(double* __restrict__ x, size_t n, uint64_t seed) {
+  size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  uint64_t z = seed + 0x9E3779B97F4A7C15ull * (i + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  x[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+inline unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+// ================================================================ launchers
+
+template <typename T, int D, int C, int EPI>
+static void apply_dispatch_kind(const LevelView<T>& L, int kind, const T* u, const EpiArgs<T>& e, hipStream_t s) {
+  const unsigned g = blocks_for(L.n_n);
+  if (g == 0) return;
+  if (kind == KIND_SHARED)
+    hipLaunchKernelGGL((k_apply_shared<T, D, EPI>), dim3(g), dim3(kBlock), 0, s, L, C, u, e);
+  else if (kind == KIND_TABLE)
+    hipLaunchKernelGGL((k_apply_coarse<T, D, C, KIND_TABLE, EPI>), dim3(g), dim3(kBlock), 0, s, L, u, e);
+  else
+    hipLaunchKernelGGL((k_apply_coarse<T, D, C, KIND_PERELEM, EPI>), dim3(g), dim3(kBlock), 0, s, L, u, e);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename T, int D, int C>
+static void apply_dispatch_epi(const LevelView<T>& L, int kind, int epi, const T* u, const EpiArgs<T>& e,
+                               hipStream_t s) {
+  switch (epi) {
+    case EPI_KU: apply_dispatch_kind<T, D, C, EPI_KU>(L, kind, u, e, s); break;
+    case EPI_RESID: apply_dispatch_kind<T, D, C, EPI_RESID>(L, kind, u, e, s); break;
+    case EPI_JACOBI: apply_dispatch_kind<T, D, C, EPI_JACOBI>(L, kind, u, e, s); break;
+    default: apply_dispatch_kind<T, D, C, EPI_CHEB>(L, kind, u, e, s); break;
+  }
+}
+
+template <typename T>
+void launch_apply(const LevelView<T>& L, int kind, int D, int C, int epi, const T* u, const EpiArgs<T>& e,
+                  hipStream_t s) {
+  if (D == 3 && C == 6) apply_dispatch_epi<T, 3, 6>(L, kind, epi, u, e, s);
+  else if (D == 3 && C == 1) apply_dispatch_epi<T, 3, 1>(L, kind, epi, u, e, s);
+  else if (D == 1 && C == 3) apply_dispatch_epi<T, 1, 3>(L, kind, epi, u, e, s);
+  else if (D == 1 && C == 1) apply_dispatch_epi<T, 1, 1>(L, kind, epi, u, e, s);
+  else fail(GMT_E_INVAL, "unsupported (d, c) = (%d, %d)", D, C);
+}
+
+template <typename T>
+void launch_smooth_zero(int n, int D, int C, const T* f, const T* dinv, T scale, T* out, T* dvec,
+                        hipStream_t s) {
+  const size_t tot = (size_t)n * C * D;
+  if (!tot) return;
+  hipLaunchKernelGGL(k_smooth_zero<T>, dim3(blocks_for(tot)), dim3(kBlock), 0, s, n, D, C, f, dinv, scale, out,
+                     dvec);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_restrict(const LevelView<T>& F, const LevelView<T>& Cv, int Q, const T* rf, T* fc, hipStream_t s) {
+  const unsigned g = blocks_for(Cv.n_n);
+  if (!g) return;
+  switch (Q) {
+    case 18: hipLaunchKernelGGL((k_restrict<T, 18>), dim3(g), dim3(kBlock), 0, s, F, Cv, rf, fc); break;
+    case 3: hipLaunchKernelGGL((k_restrict<T, 3>), dim3(g), dim3(kBlock), 0, s, F, Cv, rf, fc); break;
+    case 1: hipLaunchKernelGGL((k_restrict<T, 1>), dim3(g), dim3(kBlock), 0, s, F, Cv, rf, fc); break;
+    default: fail(GMT_E_INVAL, "unsupported Q=%d", Q);
+  }
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_prolong_add(const LevelView<T>& F, const LevelView<T>& Cv, int Q, const T* uc, T* uf, hipStream_t s) {
+  const unsigned g = blocks_for(F.n_n);
+  if (!g) return;
+  switch (Q) {
+    case 18: hipLaunchKernelGGL((k_prolong_add<T, 18>), dim3(g), dim3(kBlock), 0, s, F, Cv, uc, uf); break;
+    case 3: hipLaunchKernelGGL((k_prolong_add<T, 3>), dim3(g), dim3(kBlock), 0, s, F, Cv, uc, uf); break;
+    case 1: hipLaunchKernelGGL((k_prolong_add<T, 1>), dim3(g), dim3(kBlock), 0, s, F, Cv, uc, uf); break;
+    default: fail(GMT_E_INVAL, "unsupported Q=%d", Q);
+  }
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_coarse_solve(const T* cinv, int cn, int D, int C, const T* f, T* u, hipStream_t s) {
+  const unsigned g = blocks_for(cn);
+  if (C == 6) hipLaunchKernelGGL((k_coarse_solve<T, 6>), dim3(g), dim3(kBlock), 0, s, cinv, cn, D, f, u);
+  else if (C == 3) hipLaunchKernelGGL((k_coarse_solve<T, 3>), dim3(g), dim3(kBlock), 0, s, cinv, cn, D, f, u);
+  else if (C == 1) hipLaunchKernelGGL((k_coarse_solve<T, 1>), dim3(g), dim3(kBlock), 0, s, cinv, cn, D, f, u);
+  else fail(GMT_E_INVAL, "unsupported C=%d", C);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_fill(T* p, size_t n, T v, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_fill<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, p, n, v);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename Tin, typename Tout>
+void launch_convert(const Tin* a, Tout* b, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3(blocks_for(n)), dim3(kBlock), 0, s, a, b, n);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_copy(const T* a, T* b, size_t n, hipStream_t s) {
+  launch_convert<T, T>(a, b, n, s);
+}
+
+template <typename T>
+void launch_inv(const T* a, T* b, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_inv<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, b, n);
+  GMT_LAUNCH_CHECK();
+}
+
+static unsigned red_grid(int n) {
+  unsigned g = blocks_for((size_t)n);
+  if (g > (unsigned)kRedBlocks) g = kRedBlocks;
+  return g == 0 ? 1 : g;
+}
+
+template <typename T>
+void launch_dot(const T* a, const T* b, int n, int C, int D, double* partial, double* out, hipStream_t s) {
+  const unsigned g = red_grid(n);
+  if (C == 6 && D == 3) hipLaunchKernelGGL((k_dot<T, 6, 3>), dim3(g), dim3(kBlock), 0, s, a, b, n, partial);
+  else if (C == 1 && D == 3) hipLaunchKernelGGL((k_dot<T, 1, 3>), dim3(g), dim3(kBlock), 0, s, a, b, n, partial);
+  else if (C == 3 && D == 1) hipLaunchKernelGGL((k_dot<T, 3, 1>), dim3(g), dim3(kBlock), 0, s, a, b, n, partial);
+  else if (C == 1 && D == 1) hipLaunchKernelGGL((k_dot<T, 1, 1>), dim3(g), dim3(kBlock), 0, s, a, b, n, partial);
+  else fail(GMT_E_INVAL, "unsupported (c, d)");
+  GMT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, partial, (int)g, C, out);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename Ta, typename Tb>
+void launch_gram(const Ta* a, const Tb* b, int n, int C, int D, double* partial, double* out, hipStream_t s) {
+  const unsigned g = red_grid(n);
+  if (C == 6 && D == 3) hipLaunchKernelGGL((k_gram<Ta, Tb, 6, 3>), dim3(g), dim3(kBlock), 0, s, a, b, n, partial);
+  else if (C == 3 && D == 1) hipLaunchKernelGGL((k_gram<Ta, Tb, 3, 1>), dim3(g), dim3(kBlock), 0, s, a, b, n, partial);
+  else fail(GMT_E_INVAL, "unsupported (c, d)");
+  GMT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, partial, (int)g, C * C, out);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_project(T* v, int n, int Q, double* partial, double* sums, hipStream_t s) {
+  const unsigned g = red_grid(n);
+  switch (Q) {
+    case 18: hipLaunchKernelGGL((k_colsum<T, 18>), dim3(g), dim3(kBlock), 0, s, v, n, partial); break;
+    case 3: hipLaunchKernelGGL((k_colsum<T, 3>), dim3(g), dim3(kBlock), 0, s, v, n, partial); break;
+    case 1: hipLaunchKernelGGL((k_colsum<T, 1>), dim3(g), dim3(kBlock), 0, s, v, n, partial); break;
+    default: fail(GMT_E_INVAL, "unsupported Q=%d", Q);
+  }
+  GMT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, partial, (int)g, Q, sums);
+  GMT_LAUNCH_CHECK();
+  const size_t tot = (size_t)n * Q;
+  hipLaunchKernelGGL(k_sub_mean<T>, dim3(blocks_for(tot)), dim3(kBlock), 0, s, v, tot, Q, sums, 1.0 / n);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_pcg_update(T* u, T* r, const T* p, const T* q, const double* alpha, size_t n, int C, int D,
+                       hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_pcg_update<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, u, r, p, q, alpha, n, C, D);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_pcg_direction(T* p, const T* z, const double* beta, size_t n, int C, int D, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_pcg_direction<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, p, z, beta, n, C, D);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_pcg_alpha(const double* rz, const double* pq, double* alpha, int C, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(64), 0, s, rz, pq, alpha, C);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_pcg_beta(const double* rz_new, double* rz, double* beta, int C, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(64), 0, s, rz_new, rz, beta, C);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_gauge_shift(T* u, int n, int Q, T* tmp, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_node<T>, dim3(1), dim3(64), 0, s, u, Q, tmp);
+  GMT_LAUNCH_CHECK();
+  const size_t tot = (size_t)n * Q;
+  hipLaunchKernelGGL(k_sub_node<T>, dim3(blocks_for(tot)), dim3(kBlock), 0, s, u, tot, Q, tmp);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_accumulate(double* u, const T* d, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_accumulate<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, u, d, n);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_voxel_elem_flags(const uint8_t* vox, size_t n, int* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_voxel_flags, dim3(blocks_for(n)), dim3(kBlock), 0, s, vox, n, flags);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_node_flags(const int* emap, int N, int* nflags, hipStream_t s) {
+  const size_t n = (size_t)N * N * N;
+  hipLaunchKernelGGL(k_node_flags, dim3(blocks_for(n)), dim3(kBlock), 0, s, emap, N, nflags);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_coarsen_flags(const int* femap, int Nf, int* cflags, uint8_t* dcmask, hipStream_t s) {
+  const size_t Nc = Nf / 2;
+  const size_t n = Nc * Nc * Nc;
+  hipLaunchKernelGGL(k_coarsen, dim3(blocks_for(n)), dim3(kBlock), 0, s, femap, Nf, cflags, dcmask);
+  GMT_LAUNCH_CHECK();
+}
+
+size_t scan_scratch_ints(size_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+int64_t scan_compact(const int* flags, size_t n, int* map_out, int* lin_out, int* scratch, int* d_total,
+                     hipStream_t s) {
+  const unsigned nb = (unsigned)((n + kScanTile - 1) / kScanTile);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, flags, n, scratch);
+  GMT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, scratch, (int)nb, d_total);
+  GMT_LAUNCH_CHECK();
+  int total = 0;
+  GMT_HIP(hipMemcpyAsync(&total, d_total, sizeof(int), hipMemcpyDeviceToHost, s));
+  GMT_HIP(hipStreamSynchronize(s));
+  if (map_out) {
+    hipLaunchKernelGGL(k_scan_compact, dim3(nb), dim3(kBlock), 0, s, flags, n, scratch, map_out, lin_out);
+    GMT_LAUNCH_CHECK();
+  }
+  return total;
+}
+
+void launch_occ8(const int* node_lin, int n_n, const int* emap, int N, uint8_t* occ8, hipStream_t s) {
+  if (!n_n) return;
+  hipLaunchKernelGGL(k_occ8, dim3(blocks_for(n_n)), dim3(kBlock), 0, s, node_lin, n_n, emap, N, occ8);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_gather_cmask(const int* elem_lin, int n_e, const uint8_t* dense, uint8_t* cmask, hipStream_t s) {
+  if (!n_e) return;
+  hipLaunchKernelGGL(k_gather_cmask, dim3(blocks_for(n_e)), dim3(kBlock), 0, s, elem_lin, n_e, dense, cmask);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_elem_nodes(const int* elem_lin, int n_e, const int* node_map, int N, int* out, hipStream_t s) {
+  if (!n_e) return;
+  hipLaunchKernelGGL(k_elem_nodes, dim3(blocks_for(n_e)), dim3(kBlock), 0, s, elem_lin, n_e, node_map, N, out);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_prol_maps(const int* node_lin, int n_n, int Nf, const int* cmap, int Nc, int* idx, double* w,
+                      hipStream_t s) {
+  if (!n_n) return;
+  hipLaunchKernelGGL(k_prol_maps, dim3(blocks_for(n_n)), dim3(kBlock), 0, s, node_lin, n_n, Nf, cmap, Nc, idx, w);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_galerkin(const int* elem_lin_c, int n_e_c, int Nc, const int* emap_f, const uint8_t* cmask_f,
+                     const double* Ksrc, int src_kind, int D, const double* Ps, double* out64, float* out32,
+                     hipStream_t s) {
+  if (!n_e_c) return;
+  if (D == 3)
+    hipLaunchKernelGGL(k_galerkin<3>, dim3(n_e_c), dim3(kBlock), 0, s, elem_lin_c, Nc, emap_f, cmask_f, Ksrc,
+                       src_kind, Ps, out64, out32);
+  else
+    hipLaunchKernelGGL(k_galerkin<1>, dim3(n_e_c), dim3(kBlock), 0, s, elem_lin_c, Nc, emap_f, cmask_f, Ksrc,
+                       src_kind, Ps, out64, out32);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_diagonal(const LevelView<T>& L, int kind, int D, T* diag, hipStream_t s) {
+  const unsigned g = blocks_for(L.n_n);
+  if (!g) return;
+#define GMT_DIAG(DD, KK) hipLaunchKernelGGL((k_diagonal<T, DD, KK>), dim3(g), dim3(kBlock), 0, s, L, diag)
+  if (D == 3) {
+    if (kind == KIND_SHARED) GMT_DIAG(3, KIND_SHARED);
+    else if (kind == KIND_TABLE) GMT_DIAG(3, KIND_TABLE);
+    else GMT_DIAG(3, KIND_PERELEM);
+  } else {
+    if (kind == KIND_SHARED) GMT_DIAG(1, KIND_SHARED);
+    else if (kind == KIND_TABLE) GMT_DIAG(1, KIND_TABLE);
+    else GMT_DIAG(1, KIND_PERELEM);
+  }
+#undef GMT_DIAG
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_expand_elem_matrices(const LevelView<double>& L, int kind, int n_e, int D, const int* elem_lin,
+                                 double* out, hipStream_t s) {
+  const size_t tot = (size_t)n_e * 64 * D * D;
+  if (!tot) return;
+  const unsigned g = blocks_for(tot);
+#define GMT_EXP(DD, KK) hipLaunchKernelGGL((k_expand_elem<DD, KK>), dim3(g), dim3(kBlock), 0, s, L, n_e, elem_lin, out)
+  if (D == 3) {
+    if (kind == KIND_SHARED) GMT_EXP(3, KIND_SHARED);
+    else if (kind == KIND_TABLE) GMT_EXP(3, KIND_TABLE);
+    else GMT_EXP(3, KIND_PERELEM);
+  } else {
+    if (kind == KIND_SHARED) GMT_EXP(1, KIND_SHARED);
+    else if (kind == KIND_TABLE) GMT_EXP(1, KIND_TABLE);
+    else GMT_EXP(1, KIND_PERELEM);
+  }
+#undef GMT_EXP
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_load_vector(const int* node_lin, const uint8_t* occ8, int n_n, int D, int C, const double* fe,
+                        double* f, hipStream_t s) {
+  if (!n_n) return;
+  hipLaunchKernelGGL(k_load_vector, dim3(blocks_for(n_n)), dim3(kBlock), 0, s, node_lin, occ8, n_n, D, C, fe, f);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_random(double* x, size_t n, uint64_t seed, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_random, dim3(blocks_for(n)), dim3(kBlock), 0, s, x, n, seed);
+  GMT_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- explicit instantiations
+
+#define GMT_INST_T(T)                                                                                          \
+  template void launch_apply<T>(const LevelView<T>&, int, int, int, int, const T*, const EpiArgs<T>&,         \
+                                hipStream_t);                                                                \
+  template void launch_smooth_zero<T>(int, int, int, const T*, const T*, T, T*, T*, hipStream_t);            \
+  template void launch_restrict<T>(const LevelView<T>&, const LevelView<T>&, int, const T*, T*, hipStream_t); \
+  template void launch_prolong_add<T>(const LevelView<T>&, const LevelView<T>&, int, const T*, T*,           \
+                                      hipStream_t);                                                          \
+  template void launch_coarse_solve<T>(const T*, int, int, int, const T*, T*, hipStream_t);                  \
+  template void launch_fill<T>(T*, size_t, T, hipStream_t);                                                  \
+  template void launch_copy<T>(const T*, T*, size_t, hipStream_t);                                           \
+  template void launch_inv<T>(const T*, T*, size_t, hipStream_t);                                            \
+  template void launch_dot<T>(const T*, const T*, int, int, int, double*, double*, hipStream_t);             \
+  template void launch_pcg_update<T>(T*, T*, const T*, const T*, const double*, size_t, int, int,            \
+                                     hipStream_t);                                                           \
+  template void launch_pcg_direction<T>(T*, const T*, const double*, size_t, int, int, hipStream_t);         \
+  template void launch_gauge_shift<T>(T*, int, int, T*, hipStream_t);                                        \
+  template void launch_project<T>(T*, int, int, double*, double*, hipStream_t);                               \
+  template void launch_accumulate<T>(double*, const T*, size_t, hipStream_t);                                \
+  template void launch_diagonal<T>(const LevelView<T>&, int, int, T*, hipStream_t);
+
+GMT_INST_T(float)
+GMT_INST_T(double)
+template void launch_convert<double, float>(const double*, float*, size_t, hipStream_t);
+template void launch_convert<float, double>(const float*, double*, size_t, hipStream_t);
+template void launch_gram<double, double>(const double*, const double*, int, int, int, double*, double*,
+                                          hipStream_t);
+template void launch_gram<float, double>(const float*, const double*, int, int, int, double*, double*,
+                                         hipStream_t);
+
+}  // namespace gmt

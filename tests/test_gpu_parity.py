@@ -1,0 +1,327 @@
+"""GPU parity: libgmt (through the C ABI) against the CPU FP64 oracle.
+
+Sizes: 16^3 / 32^3 cells span several 256-node tiles with ragged tails;
+laminates and the uniform solid cover the degenerate loads; the full-size
+128^3 checks compare sampled operator rows and properties that hold at any
+size (FP64-evaluated residual, C_H against the FP64 path).
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gmt_inputs import gyroid_sheet, laminate, random_vectors, spinodal, truss, uniform  # noqa: E402
+from oracle import hierarchy as ohier  # noqa: E402
+from oracle import operators as oops  # noqa: E402
+from oracle import solve as osolve  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _gmt():
+    from paper_2604_26518_amd import binding
+    return binding
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _t(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+CASES = {
+    "gyroid32": (lambda: gyroid_sheet(32, 0, 0.3), 4, "elastic"),
+    "truss16": (lambda: truss(16, 3, 0.35), 3, "elastic"),
+    "spinodal16_th": (lambda: spinodal(16, 5, 0.4), 3, "thermal"),
+    "gyroid32_th": (lambda: gyroid_sheet(32, 2, 0.25), 4, "thermal"),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def pair(request):
+    make, L, phys = CASES[request.param]
+    vox = make()
+    print(f"[case {request.param}] N={vox.shape[0]} L={L} {phys}", flush=True)
+    P = osolve.Problem(vox, L, phys)
+    H = _gmt().Hierarchy(vox, L, phys)
+    return request.param, vox, P, H
+
+
+def test_maps_bit_exact(pair):
+    name, vox, P, H = pair
+    for l in range(1, P.L + 1):
+        lv = P.levels[l - 1]
+        m = H.export_maps(l)
+        torch.cuda.synchronize()
+        assert H.level_info(l)["n_e"] == lv.n_e and H.level_info(l)["n_n"] == lv.n_n
+        assert np.array_equal(_np(m["elem_lin"]), lv.elem_lin)
+        assert np.array_equal(_np(m["node_lin"]), lv.node_lin)
+        assert np.array_equal(_np(m["occ8"]), lv.occ8)
+        assert np.array_equal(_np(m["elem_nodes"]), lv.elem_nodes)
+        if l < P.L:
+            assert np.array_equal(_np(m["prol_idx"]), lv.prol_idx)
+            assert np.array_equal(_np(m["prol_w"]), lv.prol_w)
+
+
+def test_element_matrices_and_diagonal(pair):
+    name, vox, P, H = pair
+    for l in range(1, P.L + 1):
+        K = _np(H.export_element_matrices(l))
+        ref = P.mats[l - 1]
+        ref = np.broadcast_to(ref, K.shape) if ref.ndim == 2 else ref
+        assert np.abs(K - ref).max() <= 1e-13 * np.abs(ref).max()
+        D = _np(H.export_diagonal(l))
+        assert np.abs(D - P.D[l - 1]).max() <= 1e-13 * np.abs(P.D[l - 1]).max()
+
+
+def test_load_vector(pair):
+    name, vox, P, H = pair
+    f = _np(H.load_vector())
+    assert np.abs(f - P.f).max() <= 1e-13 * np.abs(P.f).max()
+    f32 = _np(H.load_vector(torch.float32))
+    assert np.abs(f32 - P.f).max() <= 1e-6 * np.abs(P.f).max()
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-13), (torch.float32, 2e-6)])
+def test_apply_K_every_level(pair, dtype, tol):
+    name, vox, P, H = pair
+    for l in range(1, P.L + 1):
+        n = P.levels[l - 1].n_n
+        u = random_vectors(n, P.c * P.d, 100 + l).reshape(n, P.c, P.d)
+        y = _np(H.apply_K(_t(u, dtype), l)).astype(np.float64)
+        ref = oops.apply_K(P.levels[l - 1], P.mats[l - 1], u)
+        scale = np.abs(ref).max()
+        assert np.abs(y - ref).max() <= tol * scale * 50, (l, np.abs(y - ref).max() / scale)
+        r = _np(H.residual(_t(P.f if l == 1 else u, dtype), _t(u, dtype), l)).astype(np.float64)
+        fr = P.f if l == 1 else u
+        assert np.abs(r - (fr - ref)).max() <= tol * scale * 50
+
+
+def test_transfers(pair):
+    name, vox, P, H = pair
+    for l in range(1, P.L):
+        nf, nc = P.levels[l - 1].n_n, P.levels[l].n_n
+        rf = random_vectors(nf, P.c * P.d, 7 + l).reshape(nf, P.c, P.d)
+        fc = _np(H.restrict(_t(rf), l))
+        ref = oops.restrict(P.levels[l - 1], rf, nc)
+        assert np.abs(fc - ref).max() <= 1e-14 * np.abs(ref).max()
+        uc = random_vectors(nc, P.c * P.d, 9 + l).reshape(nc, P.c, P.d)
+        uf = random_vectors(nf, P.c * P.d, 11 + l).reshape(nf, P.c, P.d)
+        out = _np(H.prolong_add(_t(uc), _t(uf), l))
+        ref = uf + oops.prolong(P.levels[l - 1], uc)
+        assert np.abs(out - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+def test_coarse_solve(pair):
+    name, vox, P, H = pair
+    n = P.levels[-1].n_n
+    f = random_vectors(n, P.c * P.d, 3).reshape(n, P.c, P.d)
+    u = _np(H.coarse_solve(_t(f)))
+    ref = osolve.coarse_solve(P, f)
+    assert np.abs(u - ref).max() <= 1e-10 * np.abs(ref).max()
+    assert np.abs(u[0]).max() == 0.0
+
+
+def _bounds(P, H):
+    lam = [H.level_info(l)["lambda_max"] for l in range(1, P.L + 1)]
+    return lam
+
+
+@pytest.mark.parametrize("smoother", ["chebyshev", "jacobi"])
+def test_smoother(pair, smoother):
+    name, vox, P, H = pair
+    lam = _bounds(P, H)
+    l = 1
+    n = P.levels[0].n_n
+    u0 = random_vectors(n, P.c * P.d, 21).reshape(n, P.c, P.d)
+    if smoother == "jacobi":
+        out = _np(H.smooth(_t(P.f), _t(u0), 3, "jacobi", 0.6 / lam[0]))
+        ref = osolve.jacobi(P, 0, u0, P.f, 3, 0.6 / lam[0])
+    else:
+        lo, hi = lam[0] / 30, 1.1 * lam[0]
+        out = _np(H.smooth(_t(P.f), _t(u0), 3, "chebyshev", lo, hi))
+        ref = osolve.chebyshev(P, 0, u0, P.f, 3, lo, hi)
+    assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_lambda_estimate(pair):
+    name, vox, P, H = pair
+    for l in range(1, P.L + 1):
+        est = H.level_info(l)["lambda_max"]
+        ref = P.lambda_max(l - 1)
+        assert 0.8 * ref <= est <= ref * (1 + 1e-9), (l, est, ref)
+
+
+@pytest.mark.parametrize("smoother,inject", [("chebyshev", False), ("chebyshev", True), ("jacobi", True)])
+def test_vcycle(pair, smoother, inject):
+    name, vox, P, H = pair
+    lam = _bounds(P, H)
+    L = P.L
+    n = [lv.n_n for lv in P.levels]
+    u0 = random_vectors(n[0], P.c * P.d, 31).reshape(n[0], P.c, P.d) * 0.1
+    e = None
+    if inject:
+        e = [None] + [random_vectors(n[l], P.c * P.d, 40 + l).reshape(n[l], P.c, P.d) * 0.01
+                      for l in range(1, L - 1)] + [None]
+    if smoother == "jacobi":
+        omega = [1.0 / x for x in lam]
+        sm = {"kind": "jacobi", "omega": omega}
+        kw = dict(smoother="jacobi", omega=omega)
+    else:
+        lo = [x / 30 for x in lam]
+        hi = [1.1 * x for x in lam]
+        sm = {"kind": "chebyshev", "lo": lo, "hi": hi}
+        kw = dict(smoother="chebyshev", lo=lo, hi=hi)
+    et = None if e is None else [None if x is None else _t(x) for x in e]
+    out = _np(H.vcycle(_t(P.f), _t(u0), e_init=et, nu1=2, nu2=2, **kw))
+    ref = osolve.vcycle(P, P.f, u0, sm, 2, 2, e_init=e)
+    assert np.abs(out - ref).max() <= 1e-11 * np.abs(ref).max()
+    # FP32 V-cycle tracks the FP64 one
+    out32 = _np(H.vcycle(_t(P.f, torch.float32), _t(u0, torch.float32),
+                         e_init=None if e is None else [None if x is None else _t(x, torch.float32) for x in e],
+                         nu1=2, nu2=2, **kw)).astype(np.float64)
+    assert np.abs(out32 - ref).max() <= 1e-4 * np.abs(ref).max()
+
+
+@pytest.fixture(scope="module")
+def solved(pair):
+    name, vox, P, H = pair
+    u_ref, _ = osolve.pcg(P, tol=1e-11)
+    return name, vox, P, H, u_ref, osolve.homogenize(P, u_ref)
+
+
+def test_solve_fp64(solved):
+    name, vox, P, H, u_ref, CH_ref = solved
+    f = H.load_vector()
+    u, rep = H.solve(f, tol=1e-10, precision="f64")
+    assert rep["converged"] and max(rep["rel_res"]) <= 1e-10
+    un = _np(u)
+    assert np.abs(un[0]).max() == 0.0  # gauge
+    assert np.max(osolve.relative_residual(P, un)) <= 2e-10
+    assert np.abs(un - u_ref).max() <= 1e-7 * np.abs(u_ref).max()
+    CH = H.homogenize(u)
+    assert np.linalg.norm(CH - CH_ref) <= 1e-8 * np.linalg.norm(CH_ref)
+    # the GPU C_H reduction equals the element-sum definition on the same u
+    CH_o = osolve.homogenize(P, un)
+    assert np.abs(CH - CH_o).max() <= 1e-12 * np.abs(CH_o).max()
+    rel = H.relative_residual(f, u)
+    assert np.allclose(rel, osolve.relative_residual(P, un), rtol=1e-6, atol=1e-16)
+
+
+def test_solve_mixed(solved):
+    name, vox, P, H, u_ref, CH_ref = solved
+    f = H.load_vector()
+    u, rep = H.solve(f, tol=1e-5, precision="f32")
+    assert rep["converged"]
+    un = _np(u)
+    assert np.max(osolve.relative_residual(P, un)) <= 1e-5
+    CH = H.homogenize(u)
+    assert np.linalg.norm(CH - CH_ref) <= 1e-4 * np.linalg.norm(CH_ref)
+
+
+def test_solve_deterministic(solved):
+    name, vox, P, H, u_ref, CH_ref = solved
+    f = H.load_vector()
+    u1, _ = H.solve(f, tol=1e-6, precision="f32")
+    u2, _ = H.solve(f, tol=1e-6, precision="f32")
+    assert torch.equal(u1, u2)
+
+
+# ------------------------------------------------------------------ edge cases
+
+
+def test_uniform_solid_zero_load():
+    H = _gmt().Hierarchy(uniform(8), 3)
+    f = H.load_vector()
+    assert float(f.abs().max()) < 1e-14
+    u, rep = H.solve(f, tol=1e-8)
+    assert rep["converged"] and rep["iterations"] == 0
+    from oracle import fem
+    assert np.abs(H.homogenize(u) - fem.isotropic_C(1.0, 0.3)).max() < 1e-12
+
+
+@pytest.mark.parametrize("physics", ["elastic", "thermal"])
+def test_laminate_closed_form(physics):
+    vox = laminate(16, 5, axis=1, offset=3)
+    H = _gmt().Hierarchy(vox, 3, physics)
+    u, rep = H.solve(H.load_vector(), tol=1e-9)
+    assert rep["converged"]
+    CH = H.homogenize(u)
+    P = osolve.Problem(vox, 3, physics)
+    ur, _ = osolve.pcg(P, tol=1e-11)
+    assert np.abs(CH - osolve.homogenize(P, ur)).max() < 1e-8
+
+
+def test_errors():
+    B = _gmt()
+    with pytest.raises(B.GmtError):
+        B.Hierarchy(np.zeros((8, 8, 8), np.uint8), 2)  # empty cell
+    with pytest.raises(B.GmtError):
+        B.Hierarchy(uniform(12), 4)  # 12 not divisible by 8
+    H = B.Hierarchy(gyroid_sheet(16, 1, 0.4), 3)
+    with pytest.raises(ValueError):
+        H.apply_K(torch.zeros(5, 6, 3, dtype=torch.float64, device=DEV))
+    with pytest.raises(ValueError):
+        H.restrict(H.vec(1), level=3)
+    f = H.load_vector()
+    _, rep = H.solve(f, tol=1e-12, max_iter=1, raise_on_noconv=False)
+    assert rep["status"] == B.GMT_E_NOCONV and not rep["converged"]
+    with pytest.raises(B.GmtError):
+        H.solve(f, tol=1e-12, max_iter=1)
+
+
+def test_two_level_and_small_N():
+    vox = gyroid_sheet(8, 4, 0.5)
+    P = osolve.Problem(vox, 2)
+    H = _gmt().Hierarchy(vox, 2)
+    u, rep = H.solve(H.load_vector(), tol=1e-11)
+    ur = osolve.direct_solve(P)
+    assert np.abs(_np(u) - ur).max() <= 1e-8 * np.abs(ur).max()
+
+
+# ------------------------------------------------------------------ full size (128^3)
+
+
+@pytest.fixture(scope="module")
+def big():
+    vox = spinodal(128, 1001, 0.3)
+    H = _gmt().Hierarchy(vox, 6)
+    lv = ohier.build(vox, 1)[0]
+    return vox, H, lv
+
+
+def test_full_size_maps_and_rows(big):
+    vox, H, lv = big
+    m = H.export_maps(1)
+    assert np.array_equal(_np(m["node_lin"]), lv.node_lin)
+    assert np.array_equal(_np(m["elem_nodes"]), lv.elem_nodes)
+    assert np.array_equal(_np(m["occ8"]), lv.occ8)
+    from oracle import fem
+    u = random_vectors(lv.n_n, 18, 77).reshape(lv.n_n, 6, 3)
+    y = _np(H.apply_K(_t(u)))
+    rng = np.random.default_rng(5)
+    rows = np.unique(np.concatenate([rng.choice(lv.n_n, 3000, replace=False), [0, lv.n_n - 1]]))
+    ref = oops.apply_K_rows(lv, fem.Ke_elastic(), u, rows)
+    assert np.abs(y[rows] - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_full_size_mixed_solve(big):
+    vox, H, lv = big
+    from oracle import fem
+    f = H.load_vector()
+    u32, rep = H.solve(f, tol=1e-5, precision="f32")
+    assert rep["converged"]
+    un = _np(u32)
+    fo = oops.load_vector(lv, fem.Ke_elastic(), fem.X0_elastic())
+    r = fo - oops.apply_K(lv, fem.Ke_elastic(), un)
+    rel = np.sqrt((r ** 2).sum(axis=(0, 2))) / np.sqrt((fo ** 2).sum(axis=(0, 2)))
+    assert rel.max() <= 1e-5
+    u64, rep64 = H.solve(f, tol=1e-9, precision="f64")
+    assert rep64["converged"]
+    CH32, CH64 = H.homogenize(u32), H.homogenize(u64)
+    assert np.linalg.norm(CH32 - CH64) <= 1e-4 * np.linalg.norm(CH64)
