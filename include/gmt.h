@@ -199,6 +199,73 @@ gmt_status gmt_relative_residual(gmt_hier_t h, const void* d_f, const void* d_u,
  * h_CH: c x c row-major host array.  Synchronizes the stream. */
 gmt_status gmt_homogenize(gmt_hier_t h, const void* d_u, int32_t dtype, double* h_CH, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned initializer (Sec. 4.2-4.5 with a sparse-convolution backbone): a
+ * U-Net on the same active node sets P_1..P_L, periodic neighbour maps, the
+ * 8-bit occupancy embedded by a 256-entry table, learned 27-tap pooling from
+ * the fine nodes 2x + k and unpooling along the same connectivity, and a
+ * three-layer head per level l < L that predicts u_hat^1 (l = 1) and the
+ * corrections e_hat^l (1 < l < L).  BF16 weights and activations, FP32 sums.
+ *
+ * Flat FP32 parameter layout (caller-owned), in this order:
+ *   E [256][C1];  for l = 1..L: We_l [27][C_l][C_l], be_l [C_l];
+ *   for l = 1..L-1: Wp_l [27][C_l][C_{l+1}], bp_l [C_{l+1}], Wu_l [27][C_{l+1}][C_l],
+ *   bu_l [C_l], Wd_l [27][C_l][C_l], bd_l [C_l], W1_l [C_l][H], b1_l [H], W2_l [H][H],
+ *   b2_l [H], W3_l [H][q], b3_l [q]      (q = c*d; tap t <-> offset (t%3-1, t/3%3-1, t/9-1)).
+ * ------------------------------------------------------------------------ */
+#define GMT_NN_MAX_LEVELS 8
+typedef struct {
+  int32_t levels;                       /* = the hierarchy's L */
+  int32_t channels[GMT_NN_MAX_LEVELS];  /* C_l in {16, 32, 64} */
+  int32_t head;                         /* H = 32 */
+} gmt_nn_config;
+
+/* Number of FP32 parameters of the network for a physics (q = 18 or 3). */
+gmt_status gmt_nn_param_count(const gmt_nn_config* cfg, int32_t physics, size_t* n_params);
+
+/* Builds the network's neighbour tables and activation buffers for a hierarchy. */
+gmt_status gmt_nn_setup(gmt_hier_t h, const gmt_nn_config* cfg, void* stream);
+
+/* Forward pass.  d_out: array of L pointers indexed by level-1; entry l-1
+ * (l = 1..L-1) receives the level-l prediction [n_l][c][d] FP32 (u_hat^1 for
+ * l = 1, e_hat^l otherwise) or is NULL to skip it; entry L-1 is unused. */
+gmt_status gmt_nn_forward(gmt_hier_t h, const float* d_params, float* const* d_out, void* stream);
+
+/* Backward pass of the last forward: d_grad += d/dparams sum_l <d_gout[l], out[l]>
+ * (same indexing as gmt_nn_forward; NULL entries contribute nothing). */
+gmt_status gmt_nn_backward(gmt_hier_t h, const float* const* d_gout, float* d_grad, void* stream);
+
+/* AdamW step on FP32 master weights (bias-corrected moments, step >= 1,
+ * decoupled weight decay wd, gradient multiplied by grad_scale first). */
+gmt_status gmt_nn_adamw(float* d_params, const float* d_grad, float* d_m, float* d_v, size_t n, double lr,
+                        double beta1, double beta2, double eps, double wd, int32_t step, double grad_scale,
+                        void* stream);
+
+/* Training helpers on flat FP32 vectors: h_out = ||d_x||_2^2 (FP64 sum), and
+ * the exponential moving average d_ema = decay * d_ema + (1 - decay) * d_x. */
+gmt_status gmt_nn_norm2(const float* d_x, size_t n, double* h_out, void* stream);
+gmt_status gmt_nn_ema(float* d_ema, const float* d_x, size_t n, double decay, void* stream);
+
+/* One V-cycle of Alg. 2 started from network outputs, in FP32, and the
+ * physics loss of Sec. 4.5:  L = log10(||f - K u^1||_2 + 1e-12)
+ * + lambda * sum_{case,dof} (sum_i u^1_i)^2  (norm over all cases and DOFs).
+ * d_pred: L pointers by level-1 (entry 0 = u_hat^1 [n_1][c][d], required;
+ * entries 1..L-2 = e_hat^l or NULL) FP32.  Outputs (each optional): d_u1, the
+ * V-cycle result [n_1][c][d] FP32; h_out[0] = loss, h_out[1] = ||r||, and
+ * h_out[2..2+c) the per-case relative residuals; d_gpred (same indexing as
+ * d_pred, NULL entries skipped) receives dL/d(pred) through the exact adjoint
+ * of the V-cycle.  Synchronizes the stream. */
+gmt_status gmt_vcycle_loss(gmt_hier_t h, const float* const* d_pred, const gmt_cycle_opts* opts,
+                           double lambda, float* d_u1, double* h_out, float* const* d_gpred, void* stream);
+
+/* Instrumentation (tracing/profiling): times `reps` Chebyshev sweeps of
+ * level l (the fused K.u + smoother update, on internal FP32 or FP64 work
+ * vectors, no layout staging) with HIP events recorded on the given stream and
+ * returns the mean duration of one sweep in h_ms.  Level 1 sweeps launch two
+ * kernels (all-solid interior nodes, boundary nodes).  Synchronizes the stream. */
+gmt_status gmt_time_sweep(gmt_hier_t h, int32_t level, int32_t reps, int32_t dtype, double* h_ms,
+                          void* stream);
+
 const char* gmt_last_error(void);
 
 #ifdef __cplusplus

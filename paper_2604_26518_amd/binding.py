@@ -58,6 +58,22 @@ class GmtSolveReport(ct.Structure):
                 ("c", ct.c_int32), ("rel_res", ct.c_double * 6), ("rel_res_init", ct.c_double * 6)]
 
 
+NN_MAX_LEVELS = 8
+
+
+class GmtNNConfig(ct.Structure):
+    _fields_ = [("levels", ct.c_int32), ("channels", ct.c_int32 * NN_MAX_LEVELS), ("head", ct.c_int32)]
+
+
+def nn_config(levels, channels, head=32):
+    cfg = GmtNNConfig()
+    cfg.levels = levels
+    for l, c in enumerate(channels):
+        cfg.channels[l] = c
+    cfg.head = head
+    return cfg
+
+
 class GmtError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{_STATUS.get(status, status)}: {msg}")
@@ -87,6 +103,16 @@ SIGNATURES = {
     "gmt_solve": (_P, _P, _P, ct.POINTER(GmtSolveOpts), ct.POINTER(GmtSolveReport), _P),
     "gmt_relative_residual": (_P, _P, _P, _I, ct.POINTER(ct.c_double), _P),
     "gmt_homogenize": (_P, _P, _I, ct.POINTER(ct.c_double), _P),
+    "gmt_time_sweep": (_P, _I, _I, _I, ct.POINTER(ct.c_double), _P),
+    "gmt_nn_param_count": (ct.POINTER(GmtNNConfig), _I, ct.POINTER(ct.c_size_t)),
+    "gmt_nn_setup": (_P, ct.POINTER(GmtNNConfig), _P),
+    "gmt_nn_forward": (_P, _P, _P, _P),
+    "gmt_nn_backward": (_P, _P, _P, _P),
+    "gmt_nn_adamw": (_P, _P, _P, _P, ct.c_size_t, ct.c_double, ct.c_double, ct.c_double, ct.c_double,
+                     ct.c_double, _I, ct.c_double, _P),
+    "gmt_nn_norm2": (_P, ct.c_size_t, ct.POINTER(ct.c_double), _P),
+    "gmt_nn_ema": (_P, _P, ct.c_size_t, ct.c_double, _P),
+    "gmt_vcycle_loss": (_P, _P, ct.POINTER(GmtCycleOpts), ct.c_double, _P, ct.POINTER(ct.c_double), _P, _P),
     "gmt_last_error": (),
 }
 
@@ -375,11 +401,109 @@ class Hierarchy:
         _check(lib().gmt_relative_residual(self._h, _ptr(f), _ptr(u), _DT[u.dtype], out, _stream()))
         return np.array(out[:self.c])
 
+    # -- learned initializer
+    def nn_setup(self, channels, head=32):
+        if len(channels) != self.L:
+            raise ValueError(f"need {self.L} channel counts")
+        self._nn_cfg = nn_config(self.L, channels, head)
+        self.n_params = nn_param_count(self.L, channels, head, self.physics)
+        _check(lib().gmt_nn_setup(self._h, ct.byref(self._nn_cfg), _stream()))
+
+    def _check_params(self, params):
+        if not (isinstance(params, torch.Tensor) and params.is_cuda and params.dtype == torch.float32
+                and params.is_contiguous() and params.numel() == self.n_params):
+            raise ValueError(f"params must be a contiguous float32 CUDA tensor of {self.n_params} values")
+
+    def nn_forward(self, params):
+        """Predictions [u_hat^1, e_hat^2, ..., e_hat^{L-1}] as float32 [n_l][c][d] tensors."""
+        self._check_params(params)
+        outs = [self.vec(l, torch.float32) for l in range(1, self.L)] + [None]
+        _check(lib().gmt_nn_forward(self._h, _ptr(params), _ptr_array(outs), _stream()))
+        return outs[:-1]
+
+    def nn_backward(self, gouts, grad):
+        """grad += d/dparams sum_l <gouts[l], outs[l]> for the last forward."""
+        self._check_params(grad)
+        gl = list(gouts) + [None] * (self.L - len(gouts))
+        for l, g in enumerate(gl[:self.L - 1], start=1):
+            if g is not None:
+                self._v(g, l, torch.float32, f"gout[{l}]")
+        _check(lib().gmt_nn_backward(self._h, _ptr_array(gl), _ptr(grad), _stream()))
+
+    def vcycle_loss(self, preds, lam=0.0, want_grad=True, want_u1=False, nu1=2, nu2=2, smoother="chebyshev",
+                    omega=None, lo=None, hi=None):
+        """Alg. 2 V-cycle from network outputs + the physics loss and its gradient.
+
+        preds: [u_hat^1, e_hat^2 or None, ...] float32.  Returns (loss, ||r||, rel[c], u1, grads).
+        """
+        pl = list(preds) + [None] * (self.L - len(preds))
+        self._v(pl[0], 1, torch.float32, "u_hat")
+        for l in range(2, self.L):
+            if pl[l - 1] is not None:
+                self._v(pl[l - 1], l, torch.float32, f"e_hat[{l}]")
+        pl[self.L - 1] = None
+        o, keep = self._cycle(nu1, nu2, smoother, omega, lo, hi)
+        u1 = self.vec(1, torch.float32) if want_u1 else None
+        grads = None
+        if want_grad:
+            grads = [torch.empty_like(p) if p is not None else None for p in pl[:self.L - 1]] + [None]
+        out = (ct.c_double * (2 + self.c))()
+        _check(lib().gmt_vcycle_loss(self._h, _ptr_array(pl), ct.byref(o), lam,
+                                     _ptr(u1) if u1 is not None else None, out,
+                                     _ptr_array(grads) if grads is not None else None, _stream()))
+        return out[0], out[1], np.array(out[2:2 + self.c]), u1, (grads[:-1] if grads is not None else None)
+
+    def time_sweep(self, level: int = 1, reps: int = 50, dtype=torch.float32) -> float:
+        """Mean milliseconds of one fused Chebyshev sweep of a level (HIP events)."""
+        self._level(level)
+        out = ct.c_double()
+        _check(lib().gmt_time_sweep(self._h, level, reps, _DT[dtype], ct.byref(out), _stream()))
+        return out.value
+
     def homogenize(self, u):
         self._v(u, 1, name="u")
         out = (ct.c_double * 36)()
         _check(lib().gmt_homogenize(self._h, _ptr(u), _DT[u.dtype], out, _stream()))
         return np.array(out[:self.c * self.c]).reshape(self.c, self.c)
+
+
+def nn_param_count(levels, channels, head=32, physics="elastic") -> int:
+    out = ct.c_size_t()
+    cfg = nn_config(levels, channels, head)
+    _check(lib().gmt_nn_param_count(ct.byref(cfg), GMT_ELASTIC if physics == "elastic" else GMT_THERMAL,
+                                    ct.byref(out)))
+    return int(out.value)
+
+
+def adamw(params, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, wd=1e-2, grad_scale=1.0):
+    for t in (params, grad, m, v):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise TypeError("AdamW buffers must be contiguous float32 CUDA tensors")
+        if t.numel() != params.numel():
+            raise ValueError("AdamW buffers must have the same size")
+    _check(lib().gmt_nn_adamw(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), lr, beta1, beta2,
+                              eps, wd, step, grad_scale, _stream()))
+
+
+def norm2(x) -> float:
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
+        raise TypeError("norm2 needs a contiguous float32 CUDA tensor")
+    out = ct.c_double()
+    _check(lib().gmt_nn_norm2(_ptr(x), x.numel(), ct.byref(out), _stream()))
+    return out.value
+
+
+def ema(e, x, decay):
+    for t in (e, x):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise TypeError("ema needs contiguous float32 CUDA tensors")
+    if e.numel() != x.numel():
+        raise ValueError("size mismatch")
+    _check(lib().gmt_nn_ema(_ptr(e), _ptr(x), x.numel(), decay, _stream()))
+
+
+def _ptr_array(tensors):
+    return (ct.c_void_p * len(tensors))(*[None if t is None else t.data_ptr() for t in tensors])
 
 
 def default_levels(N: int, coarsest: int = 4) -> int:

@@ -50,10 +50,18 @@ struct LevelView {
   const uint8_t* occ8;  // per node: bit k set iff octant element k is active
   const uint8_t* cmask; // per element: bit c set iff child c is active (level >= 2)
   const T* K;           // SHARED: K_e; TABLE: 256 matrices; PERELEM: n_e matrices
+  // level 1 only: nodes whose 8 voxels are all solid (assembled stencil S,
+  // 27 x D x D) and the remaining boundary nodes (masked EBE)
+  int n_int, n_bnd;
+  int zero;  // always 0 (defeats loop-invariant hoisting of coefficient loads)
+  const int* interior;
+  const int* boundary;
+  const T* S;
 };
 
 // Epilogue of a node-centric operator sweep.
-enum Epi { EPI_KU = 0, EPI_RESID = 1, EPI_JACOBI = 2, EPI_CHEB = 3 };
+// EPI_CHEB0 is the first Chebyshev step (d = rho2 D^-1 r, the previous d is not read).
+enum Epi { EPI_KU = 0, EPI_RESID = 1, EPI_JACOBI = 2, EPI_CHEB = 3, EPI_CHEB0 = 4 };
 
 template <typename T>
 struct EpiArgs {
@@ -62,7 +70,7 @@ struct EpiArgs {
   T* dvec;        // Chebyshev direction, updated in place
   T* out;
   T omega;        // Jacobi weight
-  T rho1, rho2;   // Chebyshev: d = rho1 d + rho2 D^-1 (f - K u); rho1 == 0 skips reading d
+  T rho1, rho2;   // Chebyshev: d = rho1 d + rho2 D^-1 (f - K u)
 };
 
 // ---------------------------------------------------------------- kernel launchers (kernels.hip)
@@ -74,10 +82,10 @@ template <typename T>
 void launch_smooth_zero(int n, int D, int C, const T* f, const T* dinv, T scale, T* out, T* dvec,
                         hipStream_t s);
 template <typename T>
-void launch_restrict(const LevelView<T>& fine, const LevelView<T>& coarse, int Q, const T* rf, T* fc,
+void launch_restrict(const LevelView<T>& fine, const LevelView<T>& coarse, int Q, int D, const T* rf, T* fc,
                      hipStream_t s);
 template <typename T>
-void launch_prolong_add(const LevelView<T>& fine, const LevelView<T>& coarse, int Q, const T* uc, T* uf,
+void launch_prolong_add(const LevelView<T>& fine, const LevelView<T>& coarse, int Q, int D, const T* uc, T* uf,
                         hipStream_t s);
 template <typename T>
 void launch_coarse_solve(const T* cinv, int cn, int D, int C, const T* f, T* u, hipStream_t s);
@@ -95,20 +103,25 @@ void launch_dot(const T* a, const T* b, int n, int C, int D, double* partial, do
 template <typename Ta, typename Tb>
 void launch_gram(const Ta* a, const Tb* b, int n, int C, int D, double* partial, double* out,
                  hipStream_t s);
-// u += alpha[c] p ; r -= alpha[c] q
+// u += alpha[c] p ; r -= alpha[c] q  (vectors [C][n][D])
 template <typename T>
-void launch_pcg_update(T* u, T* r, const T* p, const T* q, const double* alpha, size_t n, int C,
-                       int D, hipStream_t s);
+void launch_pcg_update(T* u, T* r, const T* p, const T* q, const double* alpha, int n, int Q, int D,
+                       hipStream_t s);
 // p = z + beta[c] p
 template <typename T>
-void launch_pcg_direction(T* p, const T* z, const double* beta, size_t n, int C, int D, hipStream_t s);
+void launch_pcg_direction(T* p, const T* z, const double* beta, int n, int Q, int D, hipStream_t s);
+// layout changes between the ABI's [n][C][D] and the solver's [C][n][D] (with type conversion)
+template <typename Tin, typename Tout>
+void launch_aos_to_soa(const Tin* a, Tout* b, int n, int C, int D, hipStream_t s);
+template <typename Tin, typename Tout>
+void launch_soa_to_aos(const Tin* a, Tout* b, int n, int C, int D, hipStream_t s);
 void launch_pcg_alpha(const double* rz, const double* pq, double* alpha, int C, hipStream_t s);
 void launch_pcg_beta(const double* rz_new, double* rz, double* beta, int C, hipStream_t s);
 template <typename T>
-void launch_gauge_shift(T* u, int n, int Q, T* tmp, hipStream_t s);
+void launch_gauge_shift(T* u, int n, int Q, int D, T* tmp, hipStream_t s);
 // v -= column mean over nodes (projection off the rigid translations)
 template <typename T>
-void launch_project(T* v, int n, int Q, double* partial, double* sums, hipStream_t s);
+void launch_project(T* v, int n, int Q, int D, double* partial, double* sums, hipStream_t s);
 // u64 += (double) d
 template <typename T>
 void launch_accumulate(double* u, const T* d, size_t n, hipStream_t s);
@@ -123,6 +136,7 @@ int64_t scan_compact(const int* flags, size_t n, int* map_out, int* lin_out, int
 size_t scan_scratch_ints(size_t n);
 void launch_occ8(const int* node_lin, int n_n, const int* elem_map, int N, uint8_t* occ8,
                  hipStream_t s);
+void launch_occ_flags(const uint8_t* occ8, int n, int want_full, int* flags, hipStream_t s);
 void launch_gather_cmask(const int* elem_lin, int n_e, const uint8_t* dense_cmask, uint8_t* cmask,
                          hipStream_t s);
 void launch_elem_nodes(const int* elem_lin, int n_e, const int* node_map, int N, int* out,
@@ -153,6 +167,9 @@ struct LevelData {
   int* elem_map = nullptr;
   uint8_t* occ8 = nullptr;
   uint8_t* cmask = nullptr;   // per element, levels >= 2
+  int* interior = nullptr;    // level 1: nodes with occupancy 255
+  int* boundary = nullptr;    // level 1: the other nodes
+  int n_int = 0, n_bnd = 0;
   double* Kel64 = nullptr;    // per element, levels >= 3
   float* Kel32 = nullptr;
   double* diag64 = nullptr;   // [n_n][d]
@@ -165,6 +182,7 @@ template <typename T>
 struct Work {
   bool ready = false;
   std::vector<T*> f, u, ualt, dvec, r;  // per level (f[0], u[0] unused: caller owns them)
+  std::vector<T*> io1, io2, io3;        // per level staging for the ABI layout changes
   T *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr, *px = nullptr;  // PCG vectors
 };
 
@@ -178,6 +196,8 @@ struct Hier {
   double fe_norm = 0;    // ||f_e||_F, the scale of a nonzero load
   double* Ke64 = nullptr;
   float* Ke32 = nullptr;
+  double* S64 = nullptr;  // assembled interior stencil, 27 x D x D
+  float* S32 = nullptr;
   double* fe64 = nullptr;
   double* table64 = nullptr;
   float* table32 = nullptr;
@@ -193,9 +213,10 @@ struct Hier {
   Work<float> w32;
   Work<double> w64;
   // FP64 / FP32 level-1 scratch vectors of the solve and query entry points
-  double *s_r64 = nullptr, *s_t64 = nullptr, *s_x64 = nullptr;
+  double *s_r64 = nullptr, *s_t64 = nullptr, *s_x64 = nullptr, *s_f64s = nullptr, *s_u64s = nullptr;
   float *s_b32 = nullptr, *s_x32 = nullptr;
   std::vector<void*> owned;
+  void* nn = nullptr;  // learned-initializer state (nn.hip)
 
   void* raw_alloc(size_t bytes);
   void release(void* ptr);  // frees one buffer obtained from raw_alloc
@@ -211,8 +232,33 @@ struct Hier {
   Work<T>& work();
   template <typename T>
   void ensure_work();
+  template <typename T>
+  void ensure_io(int l);  // staging buffers io1/io2/io3 of level l
 };
 
-constexpr int kRedBlocks = 1024;  // fixed grid of the two-stage reductions (deterministic order)
+constexpr int kRedBlocks = 1024;
+
+// learned initializer (nn.hip)
+void nn_setup(Hier& h, const gmt_nn_config& cfg, hipStream_t s);
+void nn_release(Hier& h);
+size_t nn_param_count(const gmt_nn_config& cfg, int q);
+void nn_forward(Hier& h, const float* params, float* const* out, hipStream_t s);
+void nn_backward(Hier& h, const float* const* gout, float* grad, hipStream_t s);
+void nn_adamw(float* p, const float* g, float* m, float* v, size_t n, double lr, double b1, double b2, double eps,
+              double wd, int step, double gscale, hipStream_t s);
+double nn_norm2(Hier* h, const float* x, size_t n, hipStream_t s);
+void nn_ema(float* e, const float* x, size_t n, double decay, hipStream_t s);
+// column sums over nodes of a [C][n][D] vector -> sums[Q] (FP64)
+template <typename T>
+void launch_colsum(const T* v, int n, int Q, int D, double* partial, double* sums, hipStream_t s);
+// y = alpha * x + beta * y  (elementwise)
+template <typename T>
+void launch_axpby(T* y, const T* x, T alpha, T beta, size_t n, hipStream_t s);
+// y[(c*n+i)*D+d] = alpha * x[...] + add[c*D+d]   (per-component constant, FP64 add)
+template <typename T>
+void launch_scale_add_comp(T* y, const T* x, T alpha, const double* add, int n, int C, int D, hipStream_t s);
+// v[(c*n+i)*D+d] *= w[i*D+d] (mode 0) or /= w[i*D+d] (mode 1)
+template <typename T>
+void launch_mul_nodewise(T* v, const T* w, int n, int C, int D, int divide, hipStream_t s);  // fixed grid of the two-stage reductions (deterministic order)
 
 }  // namespace gmt

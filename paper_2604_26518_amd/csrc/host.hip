@@ -93,10 +93,17 @@ LevelView<T> Hier::view(int l) const {
   v.elem_map = d.elem_map;
   v.occ8 = d.occ8;
   v.cmask = d.cmask;
-  if constexpr (std::is_same<T, double>::value)
+  v.n_int = d.n_int;
+  v.n_bnd = d.n_bnd;
+  v.interior = d.interior;
+  v.boundary = d.boundary;
+  if constexpr (std::is_same<T, double>::value) {
     v.K = d.kind == KIND_SHARED ? Ke64 : (d.kind == KIND_TABLE ? table64 : d.Kel64);
-  else
+    v.S = S64;
+  } else {
     v.K = d.kind == KIND_SHARED ? Ke32 : (d.kind == KIND_TABLE ? table32 : d.Kel32);
+    v.S = S32;
+  }
   return v;
 }
 
@@ -115,6 +122,9 @@ void Hier::ensure_work() {
   if (W.ready) return;
   W.f.assign(L, nullptr);
   W.u.assign(L, nullptr);
+  W.io1.assign(L, nullptr);
+  W.io2.assign(L, nullptr);
+  W.io3.assign(L, nullptr);
   W.ualt.assign(L, nullptr);
   W.dvec.assign(L, nullptr);
   W.r.assign(L, nullptr);
@@ -135,6 +145,17 @@ void Hier::ensure_work() {
   W.pq = alloc<T>(n0);
   W.px = alloc<T>(n0);
   W.ready = true;
+}
+
+template <typename T>
+void Hier::ensure_io(int l) {
+  ensure_work<T>();
+  Work<T>& W = work<T>();
+  if (W.io1[l]) return;
+  const size_t n = (size_t)lv[l].n_n * Q;
+  W.io1[l] = alloc<T>(n);
+  W.io2[l] = alloc<T>(n);
+  W.io3[l] = alloc<T>(n);
 }
 
 template LevelView<float> Hier::view<float>(int) const;
@@ -446,7 +467,7 @@ static void smooth(Hier& h, int l, const T* f, T*& u, T*& ualt, T* dvec, int nu,
   if (zero_start) {
     launch_smooth_zero<T>(n, h.D, h.C, f, dinv, (T)(1.0 / theta), u, dvec, s);
   } else {
-    apply<T>(h, l, EPI_CHEB, u, f, ualt, h.C, s, T(0), T(0), (T)(1.0 / theta), dvec);
+    apply<T>(h, l, EPI_CHEB0, u, f, ualt, h.C, s, T(0), T(0), (T)(1.0 / theta), dvec);
     std::swap(u, ualt);
   }
   for (int k = 1; k < nu; ++k) {
@@ -465,25 +486,27 @@ static const T* cinv_of(const Hier& h) {
     return h.cinv32;
 }
 
-// One V-cycle (Alg. 2) in precision T on caller buffers f0 / u0 (level 1).
+// One V-cycle (Alg. 2) in precision T on caller buffers f0 / u0 of level l0
+// (the finest level for the solver; l0 > 0 runs the sub-cycle of the coarser
+// levels, used by the adjoint of the learned path).
 template <typename T>
 static void vcycle(Hier& h, const T* f0, T* u0, bool u0_zero, const T* const* e_init, const CycleCfg& cfg,
-                   hipStream_t s) {
+                   hipStream_t s, int l0 = 0) {
   h.ensure_work<T>();
   Work<T>& W = h.work<T>();
   const int L = h.L;
   std::vector<T*> cur(L), alt(L);
   std::vector<const T*> fl(L);
-  cur[0] = u0;
-  alt[0] = W.ualt[0];
-  fl[0] = f0;
+  cur[l0] = u0;
+  alt[l0] = W.ualt[l0];
+  fl[l0] = f0;
   auto p1 = [&](int l) { return cfg.smoother == GMT_SMOOTH_JACOBI ? cfg.omega[l] : cfg.lo[l]; };
   auto p2 = [&](int l) { return cfg.hi[l]; };
-  for (int l = 0; l < L - 1; ++l) {
-    const bool zs = l == 0 ? u0_zero : !(e_init && e_init[l]);
+  for (int l = l0; l < L - 1; ++l) {
+    const bool zs = l == l0 ? u0_zero : !(e_init && e_init[l]);
     smooth<T>(h, l, fl[l], cur[l], alt[l], W.dvec[l], cfg.nu1, zs, cfg.smoother, p1(l), p2(l), s);
     apply<T>(h, l, EPI_RESID, cur[l], fl[l], W.r[l], h.C, s);
-    launch_restrict<T>(h.view<T>(l), h.view<T>(l + 1), h.Q, W.r[l], W.f[l + 1], s);
+    launch_restrict<T>(h.view<T>(l), h.view<T>(l + 1), h.Q, h.D, W.r[l], W.f[l + 1], s);
     fl[l + 1] = W.f[l + 1];
     cur[l + 1] = W.u[l + 1];
     alt[l + 1] = W.ualt[l + 1];
@@ -491,11 +514,11 @@ static void vcycle(Hier& h, const T* f0, T* u0, bool u0_zero, const T* const* e_
       launch_copy<T>(e_init[l + 1], cur[l + 1], (size_t)h.lv[l + 1].n_n * h.Q, s);
   }
   launch_coarse_solve<T>(cinv_of<T>(h), h.cn, h.D, h.C, fl[L - 1], cur[L - 1], s);
-  for (int l = L - 2; l >= 0; --l) {
-    launch_prolong_add<T>(h.view<T>(l), h.view<T>(l + 1), h.Q, cur[l + 1], cur[l], s);
+  for (int l = L - 2; l >= l0; --l) {
+    launch_prolong_add<T>(h.view<T>(l), h.view<T>(l + 1), h.Q, h.D, cur[l + 1], cur[l], s);
     smooth<T>(h, l, fl[l], cur[l], alt[l], W.dvec[l], cfg.nu2, false, cfg.smoother, p1(l), p2(l), s);
   }
-  if (cur[0] != u0) launch_copy<T>(cur[0], u0, (size_t)h.lv[0].n_n * h.Q, s);
+  if (cur[l0] != u0) launch_copy<T>(cur[l0], u0, (size_t)h.lv[l0].n_n * h.Q, s);
 }
 
 static void host_dot(Hier& h, const double* dev, int n, double* out, hipStream_t s) {
@@ -525,12 +548,12 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
   double bn2[8], rr_h[8];
   launch_fill<T>(x, tot, T(0), s);
   launch_copy<T>(b, W.pr, tot, s);
-  launch_project<T>(W.pr, n, Q, h.red_partial, sums, s);
+  launch_project<T>(W.pr, n, Q, D, h.red_partial, sums, s);
   launch_dot<T>(W.pr, W.pr, n, C, D, h.red_partial, rr, s);
   host_dot(h, rr, C, bn2, s);
   auto precond = [&]() {
     vcycle<T>(h, W.pr, W.pz, true, nullptr, cfg, s);
-    launch_project<T>(W.pz, n, Q, h.red_partial, sums, s);
+    launch_project<T>(W.pz, n, Q, D, h.red_partial, sums, s);
   };
   precond();
   launch_copy<T>(W.pz, W.pp, tot, s);
@@ -543,8 +566,8 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
     apply<T>(h, 0, EPI_KU, W.pp, nullptr, W.pq, C, s);
     launch_dot<T>(W.pp, W.pq, n, C, D, h.red_partial, pq, s);
     launch_pcg_alpha(rz, pq, alpha, C, s);
-    launch_pcg_update<T>(x, W.pr, W.pp, W.pq, alpha, tot, C, D, s);
-    launch_project<T>(W.pr, n, Q, h.red_partial, sums, s);
+    launch_pcg_update<T>(x, W.pr, W.pp, W.pq, alpha, n, Q, D, s);
+    launch_project<T>(W.pr, n, Q, D, h.red_partial, sums, s);
     if (it % check_every == 0 || it == maxit) {
       launch_dot<T>(W.pr, W.pr, n, C, D, h.red_partial, rr, s);
       host_dot(h, rr, C, rr_h, s);
@@ -560,14 +583,14 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
       if (worst < 0.98 * best) {
         best = worst;
         since_best = 0;
-      } else if ((since_best += check_every) >= 20) {
+      } else if ((since_best += check_every) >= 100) {
         break;  // stagnation: hand back to the FP64 refinement loop
       }
     }
     precond();
     launch_dot<T>(W.pr, W.pz, n, C, D, h.red_partial, rzn, s);
     launch_pcg_beta(rzn, rz, beta, C, s);
-    launch_pcg_direction<T>(W.pp, W.pz, beta, tot, C, D, s);
+    launch_pcg_direction<T>(W.pp, W.pz, beta, n, Q, D, s);
   }
   return it;
 }
@@ -688,6 +711,56 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
     d.kind = l == 0 ? KIND_SHARED : (l == 1 ? KIND_TABLE : KIND_PERELEM);
   }
 
+  // level 1: interior (occupancy 255) and boundary node lists
+  {
+    LevelData& d = h.lv[0];
+    int* tmpmap = h.alloc<int>(d.n_n);
+    for (int full = 1; full >= 0; --full) {
+      launch_occ_flags(d.occ8, d.n_n, full, flags, s);
+      const int64_t cnt = scan_compact(flags, d.n_n, nullptr, nullptr, scr, d_total, s);
+      int* list = cnt > 0 ? h.alloc<int>(cnt) : nullptr;
+      if (cnt > 0) scan_compact(flags, d.n_n, tmpmap, list, scr, d_total, s);
+      if (full) {
+        d.interior = list;
+        d.n_int = (int)cnt;
+      } else {
+        d.boundary = list;
+        d.n_bnd = (int)cnt;
+      }
+    }
+    GMT_HIP(hipStreamSynchronize(s));
+    h.release(tmpmap);
+  }
+  // assembled interior stencil of the shared K_e: S[j][d][d2] over the 27 offsets
+  {
+    std::vector<double> S((size_t)27 * D * D, 0.0);
+    for (int k = 0; k < 8; ++k) {
+      const int a = 7 - k;
+      for (int m = 0; m < 8; ++m) {
+        const int j = ((k & 1) + (m & 1)) + 3 * (((k >> 1) & 1) + ((m >> 1) & 1)) +
+                      9 * (((k >> 2) & 1) + ((m >> 2) & 1));
+        for (int d = 0; d < D; ++d)
+          for (int d2 = 0; d2 < D; ++d2) S[(j * D + d) * D + d2] += h.Ke[(a * D + d) * M + m * D + d2];
+      }
+    }
+    double smax = 0;
+    for (double v : S) smax = std::max(smax, std::fabs(v));
+    for (int j = 0; j < 27; ++j) {
+      const int o[3] = {j % 3 - 1, (j / 3) % 3 - 1, j / 9 - 1};
+      for (int d = 0; d < D; ++d)
+        for (int d2 = 0; d2 < D; ++d2) {
+          const bool nz = D == 1 ? ((o[0] != 0) + (o[1] != 0) + (o[2] != 0)) != 1
+                                 : (d == d2 || (o[d] != 0 && o[d2] != 0));
+          if (!nz && std::fabs(S[(j * D + d) * D + d2]) > 1e-12 * smax)
+            fail(GMT_E_STATE, "interior stencil entry (%d,%d,%d) expected zero", j, d, d2);
+        }
+    }
+    h.S64 = h.alloc<double>(S.size());
+    h.S32 = h.alloc<float>(S.size());
+    GMT_HIP(hipMemcpyAsync(h.S64, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_convert<double, float>(h.S64, h.S32, S.size(), s);
+    GMT_HIP(hipStreamSynchronize(s));
+  }
   timer.mark("maps");
   // Galerkin operators
   if (h.L >= 2) {
@@ -826,7 +899,7 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
       launch_accumulate<double>(u, x64, tot, s);
     }
   }
-  launch_gauge_shift<double>(u, h.lv[0].n_n, h.Q, h.gauge_tmp64, s);
+  launch_gauge_shift<double>(u, h.lv[0].n_n, h.Q, h.D, h.gauge_tmp64, s);
   GMT_HIP(hipStreamSynchronize(s));
   R.iterations = its;
   if (rep) *rep = R;
@@ -860,19 +933,54 @@ static void check_dtype(int dtype) {
   if (dtype != GMT_F64 && dtype != GMT_F32) fail(GMT_E_INVAL, "dtype must be GMT_F64 or GMT_F32");
 }
 
-template <typename T>
-static void smooth_api(Hier& h, int l, const T* f, T* u, int nu, int sm, double p1, double p2, hipStream_t s) {
-  h.ensure_work<T>();
-  Work<T>& W = h.work<T>();
-  T* cur = u;
-  T* alt = W.ualt[l];
-  smooth<T>(h, l, f, cur, alt, W.dvec[l], nu, false, sm, p1, p2, s);
-  if (cur != u) launch_copy<T>(cur, u, (size_t)h.lv[l].n_n * h.Q, s);
-}
-
-extern "C" {
+// Every gmt_* definition below has C linkage through its declaration in gmt.h.
 
 const char* gmt_last_error(void) { return g_last_error.c_str(); }
+
+template <typename T>
+static double time_sweep(Hier& h, int l, int reps, hipStream_t s) {
+  h.ensure_io<T>(l);
+  Work<T>& W = h.work<T>();
+  const size_t n = (size_t)h.lv[l].n_n * h.Q;
+  T* f = W.io1[l];
+  T* u = W.io2[l];
+  T* alt = W.io3[l];
+  launch_fill<T>(f, n, T(1), s);
+  launch_fill<T>(u, n, T(0), s);
+  launch_fill<T>(W.dvec[l], n, T(0), s);
+  const double lam = h.lv[l].lam;
+  const double lo = lam / 30.0, hi = 1.1 * lam;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  const double rn = 1.0 / (2.0 * sigma - 1.0 / sigma);
+  auto sweep = [&]() {
+    apply<T>(h, l, EPI_CHEB, u, f, alt, h.C, s, T(0), (T)(rn / sigma), (T)(2.0 * rn / delta), W.dvec[l]);
+    std::swap(u, alt);
+  };
+  for (int k = 0; k < 2; ++k) sweep();
+  hipEvent_t e0, e1;
+  GMT_HIP(hipEventCreate(&e0));
+  GMT_HIP(hipEventCreate(&e1));
+  GMT_HIP(hipEventRecord(e0, s));
+  for (int k = 0; k < reps; ++k) sweep();
+  GMT_HIP(hipEventRecord(e1, s));
+  GMT_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  GMT_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / reps;
+}
+
+gmt_status gmt_time_sweep(gmt_hier_t H, int32_t level, int32_t reps, int32_t dtype, double* h_ms, void* stream) {
+  return guarded([&] {
+    check_level(H, level);
+    check_dtype(dtype);
+    if (!h_ms) fail(GMT_E_INVAL, "h_ms is NULL");
+    if (reps < 1 || reps > 100000) fail(GMT_E_INVAL, "reps out of range");
+    *h_ms = dtype == GMT_F64 ? time_sweep<double>(H->h, level - 1, reps, S(stream))
+                             : time_sweep<float>(H->h, level - 1, reps, S(stream));
+  });
+}
 
 gmt_status gmt_build_hierarchy(const uint8_t* d_voxels, int32_t N, const gmt_params* params, void* stream,
                                gmt_hier_t* out) {
@@ -920,6 +1028,7 @@ gmt_status gmt_build_hierarchy(const uint8_t* d_voxels, int32_t N, const gmt_par
 void gmt_destroy(gmt_hier_t H) {
   if (!H) return;
   (void)hipDeviceSynchronize();
+  nn_release(H->h);
   H->h.release_all();
   delete H;
 }
@@ -983,12 +1092,34 @@ gmt_status gmt_load_vector(gmt_hier_t H, void* d_f, int32_t dtype, void* stream)
     check_dtype(dtype);
     if (!d_f) fail(GMT_E_INVAL, "d_f is NULL");
     Hier& h = H->h;
-    const size_t n = (size_t)h.lv[0].n_n * h.Q;
+    const int n = h.lv[0].n_n;
     if (dtype == GMT_F64)
-      GMT_HIP(hipMemcpyAsync(d_f, h.f64, n * sizeof(double), hipMemcpyDeviceToDevice, S(stream)));
+      launch_soa_to_aos<double, double>(h.f64, (double*)d_f, n, h.C, h.D, S(stream));
     else
-      launch_convert<double, float>(h.f64, (float*)d_f, n, S(stream));
+      launch_soa_to_aos<double, float>(h.f64, (float*)d_f, n, h.C, h.D, S(stream));
   });
+}
+
+// ABI vectors are [n][c][d]; the solver's are [c*d + d][n].  The staging helpers
+// below move one caller vector of level l into / out of a level-l work buffer.
+template <typename T>
+static T* stage_in(Hier& h, int l, const void* src, T* dst, hipStream_t s) {
+  launch_aos_to_soa<T, T>((const T*)src, dst, h.lv[l].n_n, h.C, h.D, s);
+  return dst;
+}
+template <typename T>
+static void stage_out(Hier& h, int l, const T* src, void* dst, hipStream_t s) {
+  launch_soa_to_aos<T, T>(src, (T*)dst, h.lv[l].n_n, h.C, h.D, s);
+}
+
+template <typename T>
+static void apply_api(Hier& h, int l, int epi, const void* d_u, const void* d_f, void* d_out, hipStream_t s) {
+  h.ensure_io<T>(l);
+  Work<T>& W = h.work<T>();
+  const T* u = stage_in<T>(h, l, d_u, W.io1[l], s);
+  const T* f = d_f ? stage_in<T>(h, l, d_f, W.io2[l], s) : nullptr;
+  apply<T>(h, l, epi, u, f, W.io3[l], h.C, s);
+  stage_out<T>(h, l, W.io3[l], d_out, s);
 }
 
 gmt_status gmt_apply_K(gmt_hier_t H, int32_t level, const void* d_u, void* d_y, int32_t dtype, void* stream) {
@@ -997,11 +1128,10 @@ gmt_status gmt_apply_K(gmt_hier_t H, int32_t level, const void* d_u, void* d_y, 
     check_dtype(dtype);
     if (!d_u || !d_y) fail(GMT_E_INVAL, "null vector");
     if (d_u == d_y) fail(GMT_E_INVAL, "u and y must not alias");
-    Hier& h = H->h;
     if (dtype == GMT_F64)
-      apply<double>(h, level - 1, EPI_KU, (const double*)d_u, nullptr, (double*)d_y, h.C, S(stream));
+      apply_api<double>(H->h, level - 1, EPI_KU, d_u, nullptr, d_y, S(stream));
     else
-      apply<float>(h, level - 1, EPI_KU, (const float*)d_u, nullptr, (float*)d_y, h.C, S(stream));
+      apply_api<float>(H->h, level - 1, EPI_KU, d_u, nullptr, d_y, S(stream));
   });
 }
 
@@ -1012,12 +1142,23 @@ gmt_status gmt_residual(gmt_hier_t H, int32_t level, const void* d_f, const void
     check_dtype(dtype);
     if (!d_f || !d_u || !d_r) fail(GMT_E_INVAL, "null vector");
     if (d_r == d_u) fail(GMT_E_INVAL, "r and u must not alias");
-    Hier& h = H->h;
     if (dtype == GMT_F64)
-      apply<double>(h, level - 1, EPI_RESID, (const double*)d_u, (const double*)d_f, (double*)d_r, h.C, S(stream));
+      apply_api<double>(H->h, level - 1, EPI_RESID, d_u, d_f, d_r, S(stream));
     else
-      apply<float>(h, level - 1, EPI_RESID, (const float*)d_u, (const float*)d_f, (float*)d_r, h.C, S(stream));
+      apply_api<float>(H->h, level - 1, EPI_RESID, d_u, d_f, d_r, S(stream));
   });
+}
+
+template <typename T>
+static void smooth_abi(Hier& h, int l, const void* d_f, void* d_u, int nu, int sm, double p1, double p2,
+                       hipStream_t s) {
+  h.ensure_io<T>(l);
+  Work<T>& W = h.work<T>();
+  const T* f = stage_in<T>(h, l, d_f, W.io1[l], s);
+  T* u = stage_in<T>(h, l, d_u, W.io2[l], s);
+  T* alt = W.io3[l];
+  smooth<T>(h, l, f, u, alt, W.dvec[l], nu, false, sm, p1, p2, s);
+  stage_out<T>(h, l, u, d_u, s);
 }
 
 gmt_status gmt_smooth(gmt_hier_t H, int32_t level, const void* d_f, void* d_u, int32_t nu, int32_t smoother,
@@ -1029,12 +1170,21 @@ gmt_status gmt_smooth(gmt_hier_t H, int32_t level, const void* d_f, void* d_u, i
     if (nu < 0 || nu > 64) fail(GMT_E_INVAL, "nu out of range");
     if (smoother == GMT_SMOOTH_CHEBYSHEV && !(p2 > p1 && p1 > 0)) fail(GMT_E_INVAL, "need 0 < lo < hi");
     if (smoother != GMT_SMOOTH_CHEBYSHEV && smoother != GMT_SMOOTH_JACOBI) fail(GMT_E_INVAL, "bad smoother");
-    Hier& h = H->h;
     if (dtype == GMT_F64)
-      smooth_api<double>(h, level - 1, (const double*)d_f, (double*)d_u, nu, smoother, p1, p2, S(stream));
+      smooth_abi<double>(H->h, level - 1, d_f, d_u, nu, smoother, p1, p2, S(stream));
     else
-      smooth_api<float>(h, level - 1, (const float*)d_f, (float*)d_u, nu, smoother, p1, p2, S(stream));
+      smooth_abi<float>(H->h, level - 1, d_f, d_u, nu, smoother, p1, p2, S(stream));
   });
+}
+
+template <typename T>
+static void restrict_abi(Hier& h, int l, const void* d_rf, void* d_fc, hipStream_t s) {
+  h.ensure_io<T>(l);
+  h.ensure_io<T>(l + 1);
+  Work<T>& W = h.work<T>();
+  const T* rf = stage_in<T>(h, l, d_rf, W.io1[l], s);
+  launch_restrict<T>(h.view<T>(l), h.view<T>(l + 1), h.Q, h.D, rf, W.io2[l + 1], s);
+  stage_out<T>(h, l + 1, W.io2[l + 1], d_fc, s);
 }
 
 gmt_status gmt_restrict(gmt_hier_t H, int32_t level, const void* d_rf, void* d_fc, int32_t dtype, void* stream) {
@@ -1043,14 +1193,22 @@ gmt_status gmt_restrict(gmt_hier_t H, int32_t level, const void* d_rf, void* d_f
     check_dtype(dtype);
     if (level == H->h.L) fail(GMT_E_INVAL, "no level below the coarsest");
     if (!d_rf || !d_fc) fail(GMT_E_INVAL, "null vector");
-    Hier& h = H->h;
     if (dtype == GMT_F64)
-      launch_restrict<double>(h.view<double>(level - 1), h.view<double>(level), h.Q, (const double*)d_rf,
-                              (double*)d_fc, S(stream));
+      restrict_abi<double>(H->h, level - 1, d_rf, d_fc, S(stream));
     else
-      launch_restrict<float>(h.view<float>(level - 1), h.view<float>(level), h.Q, (const float*)d_rf,
-                             (float*)d_fc, S(stream));
+      restrict_abi<float>(H->h, level - 1, d_rf, d_fc, S(stream));
   });
+}
+
+template <typename T>
+static void prolong_abi(Hier& h, int l, const void* d_uc, void* d_uf, hipStream_t s) {
+  h.ensure_io<T>(l);
+  h.ensure_io<T>(l + 1);
+  Work<T>& W = h.work<T>();
+  const T* uc = stage_in<T>(h, l + 1, d_uc, W.io1[l + 1], s);
+  T* uf = stage_in<T>(h, l, d_uf, W.io2[l], s);
+  launch_prolong_add<T>(h.view<T>(l), h.view<T>(l + 1), h.Q, h.D, uc, uf, s);
+  stage_out<T>(h, l, uf, d_uf, s);
 }
 
 gmt_status gmt_prolong_add(gmt_hier_t H, int32_t level, const void* d_uc, void* d_uf, int32_t dtype, void* stream) {
@@ -1059,14 +1217,21 @@ gmt_status gmt_prolong_add(gmt_hier_t H, int32_t level, const void* d_uc, void* 
     check_dtype(dtype);
     if (level == H->h.L) fail(GMT_E_INVAL, "no level below the coarsest");
     if (!d_uc || !d_uf) fail(GMT_E_INVAL, "null vector");
-    Hier& h = H->h;
     if (dtype == GMT_F64)
-      launch_prolong_add<double>(h.view<double>(level - 1), h.view<double>(level), h.Q, (const double*)d_uc,
-                                 (double*)d_uf, S(stream));
+      prolong_abi<double>(H->h, level - 1, d_uc, d_uf, S(stream));
     else
-      launch_prolong_add<float>(h.view<float>(level - 1), h.view<float>(level), h.Q, (const float*)d_uc,
-                                (float*)d_uf, S(stream));
+      prolong_abi<float>(H->h, level - 1, d_uc, d_uf, S(stream));
   });
+}
+
+template <typename T>
+static void coarse_abi(Hier& h, const void* d_f, void* d_u, hipStream_t s) {
+  const int l = h.L - 1;
+  h.ensure_io<T>(l);
+  Work<T>& W = h.work<T>();
+  const T* f = stage_in<T>(h, l, d_f, W.io1[l], s);
+  launch_coarse_solve<T>(cinv_of<T>(h), h.cn, h.D, h.C, f, W.io2[l], s);
+  stage_out<T>(h, l, W.io2[l], d_u, s);
 }
 
 gmt_status gmt_coarse_solve(gmt_hier_t H, const void* d_f, void* d_u, int32_t dtype, void* stream) {
@@ -1074,12 +1239,32 @@ gmt_status gmt_coarse_solve(gmt_hier_t H, const void* d_f, void* d_u, int32_t dt
     check_level(H, 1);
     check_dtype(dtype);
     if (!d_f || !d_u || d_f == d_u) fail(GMT_E_INVAL, "null or aliased vector");
-    Hier& h = H->h;
     if (dtype == GMT_F64)
-      launch_coarse_solve<double>(h.cinv64, h.cn, h.D, h.C, (const double*)d_f, (double*)d_u, S(stream));
+      coarse_abi<double>(H->h, d_f, d_u, S(stream));
     else
-      launch_coarse_solve<float>(h.cinv32, h.cn, h.D, h.C, (const float*)d_f, (float*)d_u, S(stream));
+      coarse_abi<float>(H->h, d_f, d_u, S(stream));
   });
+}
+
+template <typename T>
+static void vcycle_abi(Hier& h, const void* d_f, void* d_u, const void* const* d_e_init, const CycleCfg& cfg,
+                       hipStream_t s) {
+  h.ensure_io<T>(0);
+  Work<T>& W = h.work<T>();
+  const T* f = stage_in<T>(h, 0, d_f, W.io1[0], s);
+  T* u = stage_in<T>(h, 0, d_u, W.io2[0], s);
+  std::vector<const T*> e(h.L, nullptr);
+  bool any = false;
+  if (d_e_init) {
+    for (int l = 1; l < h.L - 1; ++l)
+      if (d_e_init[l]) {
+        h.ensure_io<T>(l);
+        e[l] = stage_in<T>(h, l, d_e_init[l], W.io3[l], s);
+        any = true;
+      }
+  }
+  vcycle<T>(h, f, u, false, any ? e.data() : nullptr, cfg, s);
+  stage_out<T>(h, 0, u, d_u, s);
 }
 
 gmt_status gmt_vcycle(gmt_hier_t H, const void* d_f, void* d_u, const void* const* d_e_init,
@@ -1091,9 +1276,9 @@ gmt_status gmt_vcycle(gmt_hier_t H, const void* d_f, void* d_u, const void* cons
     Hier& h = H->h;
     const CycleCfg cfg = make_cycle(h, opts);
     if (dtype == GMT_F64)
-      vcycle<double>(h, (const double*)d_f, (double*)d_u, false, (const double* const*)d_e_init, cfg, S(stream));
+      vcycle_abi<double>(h, d_f, d_u, d_e_init, cfg, S(stream));
     else
-      vcycle<float>(h, (const float*)d_f, (float*)d_u, false, (const float* const*)d_e_init, cfg, S(stream));
+      vcycle_abi<float>(h, d_f, d_u, d_e_init, cfg, S(stream));
   });
 }
 
@@ -1103,9 +1288,28 @@ gmt_status gmt_solve(gmt_hier_t H, const void* d_f, void* d_u, const gmt_solve_o
   gmt_status g = guarded([&] {
     check_level(H, 1);
     if (!d_f || !d_u || d_f == d_u) fail(GMT_E_INVAL, "null or aliased vector");
-    solve(H->h, (const double*)d_f, (double*)d_u, opts, report, S(stream), &st);
+    Hier& h = H->h;
+    hipStream_t s = S(stream);
+    const int n = h.lv[0].n_n;
+    double* f = scratch64(h, &h.s_f64s);
+    double* u = scratch64(h, &h.s_u64s);
+    launch_aos_to_soa<double, double>((const double*)d_f, f, n, h.C, h.D, s);
+    launch_aos_to_soa<double, double>((const double*)d_u, u, n, h.C, h.D, s);
+    solve(h, f, u, opts, report, s, &st);
+    launch_soa_to_aos<double, double>(u, (double*)d_u, n, h.C, h.D, s);
+    GMT_HIP(hipStreamSynchronize(s));
   });
   return g != GMT_OK ? g : st;
+}
+
+// caller vector (level 1, dtype) -> FP64 [Q][n] scratch
+static const double* to_soa64(Hier& h, const void* src, int dtype, double** slot, hipStream_t s) {
+  double* dst = scratch64(h, slot);
+  if (dtype == GMT_F64)
+    launch_aos_to_soa<double, double>((const double*)src, dst, h.lv[0].n_n, h.C, h.D, s);
+  else
+    launch_aos_to_soa<float, double>((const float*)src, dst, h.lv[0].n_n, h.C, h.D, s);
+  return dst;
 }
 
 gmt_status gmt_relative_residual(gmt_hier_t H, const void* d_f, const void* d_u, int32_t dtype, double* h_rel,
@@ -1115,17 +1319,9 @@ gmt_status gmt_relative_residual(gmt_hier_t H, const void* d_f, const void* d_u,
     check_dtype(dtype);
     if (!d_f || !d_u || !h_rel) fail(GMT_E_INVAL, "null pointer");
     Hier& h = H->h;
-    const size_t tot = (size_t)h.lv[0].n_n * h.Q;
-    const double *f = (const double*)d_f, *u = (const double*)d_u;
     hipStream_t s = S(stream);
-    if (dtype == GMT_F32) {
-      double* tf = scratch64(h, &h.s_x64);
-      double* tu = scratch64(h, &h.s_t64);
-      launch_convert<float, double>((const float*)d_f, tf, tot, s);
-      launch_convert<float, double>((const float*)d_u, tu, tot, s);
-      f = tf;
-      u = tu;
-    }
+    const double* f = to_soa64(h, d_f, dtype, &h.s_x64, s);
+    const double* u = to_soa64(h, d_u, dtype, &h.s_t64, s);
     rel_residual64(h, f, u, scratch64(h, &h.s_r64), h_rel, nullptr, s);
   });
 }
@@ -1138,13 +1334,7 @@ gmt_status gmt_homogenize(gmt_hier_t H, const void* d_u, int32_t dtype, double* 
     Hier& h = H->h;
     hipStream_t s = S(stream);
     const int n = h.lv[0].n_n, C = h.C;
-    const size_t tot = (size_t)n * h.Q;
-    const double* u = (const double*)d_u;
-    if (dtype == GMT_F32) {
-      double* tu = scratch64(h, &h.s_t64);
-      launch_convert<float, double>((const float*)d_u, tu, tot, s);
-      u = tu;
-    }
+    const double* u = to_soa64(h, d_u, dtype, &h.s_t64, s);
     double* y = scratch64(h, &h.s_r64);
     apply<double>(h, 0, EPI_KU, u, nullptr, y, C, s);
     double* A = h.red_out + 96;
@@ -1162,4 +1352,177 @@ gmt_status gmt_homogenize(gmt_hier_t H, const void* d_u, int32_t dtype, double* 
   });
 }
 
-}  // extern "C"
+
+// ================================================================ learned initializer
+
+gmt_status gmt_nn_param_count(const gmt_nn_config* cfg, int32_t physics, size_t* n_params) {
+  return guarded([&] {
+    if (!cfg || !n_params) fail(GMT_E_INVAL, "null pointer");
+    if (cfg->levels < 2 || cfg->levels > GMT_NN_MAX_LEVELS) fail(GMT_E_INVAL, "bad levels");
+    *n_params = nn_param_count(*cfg, physics == GMT_ELASTIC ? 18 : 3);
+  });
+}
+
+gmt_status gmt_nn_setup(gmt_hier_t H, const gmt_nn_config* cfg, void* stream) {
+  return guarded([&] {
+    check_level(H, 1);
+    if (!cfg) fail(GMT_E_INVAL, "cfg is NULL");
+    nn_setup(H->h, *cfg, S(stream));
+  });
+}
+
+gmt_status gmt_nn_forward(gmt_hier_t H, const float* d_params, float* const* d_out, void* stream) {
+  return guarded([&] {
+    check_level(H, 1);
+    if (!d_params || !d_out) fail(GMT_E_INVAL, "null pointer");
+    nn_forward(H->h, d_params, d_out, S(stream));
+  });
+}
+
+gmt_status gmt_nn_backward(gmt_hier_t H, const float* const* d_gout, float* d_grad, void* stream) {
+  return guarded([&] {
+    check_level(H, 1);
+    if (!d_gout || !d_grad) fail(GMT_E_INVAL, "null pointer");
+    nn_backward(H->h, d_gout, d_grad, S(stream));
+  });
+}
+
+gmt_status gmt_nn_adamw(float* d_params, const float* d_grad, float* d_m, float* d_v, size_t n, double lr,
+                        double beta1, double beta2, double eps, double wd, int32_t step, double grad_scale,
+                        void* stream) {
+  return guarded([&] {
+    if (!d_params || !d_grad || !d_m || !d_v) fail(GMT_E_INVAL, "null pointer");
+    if (step < 1) fail(GMT_E_INVAL, "step must be >= 1");
+    nn_adamw(d_params, d_grad, d_m, d_v, n, lr, beta1, beta2, eps, wd, step, grad_scale, S(stream));
+  });
+}
+
+gmt_status gmt_nn_norm2(const float* d_x, size_t n, double* h_out, void* stream) {
+  return guarded([&] {
+    if (!d_x || !h_out) fail(GMT_E_INVAL, "null pointer");
+    *h_out = nn_norm2(nullptr, d_x, n, S(stream));
+  });
+}
+
+gmt_status gmt_nn_ema(float* d_ema, const float* d_x, size_t n, double decay, void* stream) {
+  return guarded([&] {
+    if (!d_ema || !d_x) fail(GMT_E_INVAL, "null pointer");
+    nn_ema(d_ema, d_x, n, decay, S(stream));
+  });
+}
+
+namespace gmt {
+// Loss of Sec. 4.5 after one Alg. 2 V-cycle from the predictions, and its gradient
+// through the exact adjoint of the (affine) V-cycle:
+//   u^1 = E_V u_hat + sum_l B_l e_hat^l + c,   E_V = I - M^-1 K   (M^-1 the V-cycle, symmetric)
+//   dL/du_hat = E_V^T g = g - K M^-1 g
+//   dL/de_hat^l = (I - K_l M_l^-1) R Post_{l-1}^T ... R Post_1^T g
+// with Post_k^T = p(K D^-1) = D p(D^-1 K) D^-1 the transposed post-smoothing polynomial.
+static void vcycle_loss(Hier& h, const float* const* d_pred, const gmt_cycle_opts* opts, double lambda,
+                        float* d_u1, double* h_out, float* const* d_gpred, hipStream_t s) {
+  const CycleCfg cfg = make_cycle(h, opts);
+  h.ensure_work<float>();
+  h.ensure_io<float>(0);
+  Work<float>& W = h.work<float>();
+  const int L = h.L, C = h.C, D = h.D, Q = h.Q;
+  const int n = h.lv[0].n_n;
+  const size_t tot = (size_t)n * Q;
+  float* f = W.io1[0];
+  launch_convert<double, float>(h.f64, f, tot, s);
+  float* u = stage_in<float>(h, 0, d_pred[0], W.io2[0], s);
+  std::vector<const float*> e(L, nullptr);
+  bool any = false;
+  for (int l = 1; l < L - 1; ++l)
+    if (d_pred[l]) {
+      h.ensure_io<float>(l);
+      e[l] = stage_in<float>(h, l, d_pred[l], W.io3[l], s);
+      any = true;
+    }
+  vcycle<float>(h, f, u, false, any ? e.data() : nullptr, cfg, s);
+  if (d_u1) stage_out<float>(h, 0, u, d_u1, s);
+  float* r = W.pr;
+  apply<float>(h, 0, EPI_RESID, u, f, r, C, s);
+  double* sc = h.red_out;
+  double *rr = sc + 40, *ff = sc + 48, *sums = sc + 200, *add = sc + 224;
+  launch_dot<float>(r, r, n, C, D, h.red_partial, rr, s);
+  launch_dot<float>(f, f, n, C, D, h.red_partial, ff, s);
+  launch_colsum<float>(u, n, Q, D, h.red_partial, sums, s);
+  double rh[8], fh[8], sh[18];
+  host_dot(h, rr, C, rh, s);
+  host_dot(h, ff, C, fh, s);
+  host_dot(h, sums, Q, sh, s);
+  double r2 = 0, fmax = 0, pen = 0;
+  for (int c = 0; c < C; ++c) {
+    r2 += rh[c];
+    fmax = std::max(fmax, std::sqrt(fh[c]));
+  }
+  for (int q = 0; q < Q; ++q) pen += sh[q] * sh[q];
+  const double rn = std::sqrt(r2);
+  if (h_out) {
+    h_out[0] = std::log10(rn + 1e-12) + lambda * pen;
+    h_out[1] = rn;
+    for (int c = 0; c < C; ++c) {
+      double den = std::sqrt(fh[c]);
+      if (den <= 1e-12 * fmax) den = fmax;
+      h_out[2 + c] = den > 0 ? std::sqrt(rh[c]) / den : 0.0;
+    }
+  }
+  if (!d_gpred) return;
+  // g = dL/du^1 = -K r / (ln10 (||r|| + 1e-12) ||r||) + 2 lambda (sum_i u^1_i) per component
+  float* g = W.pz;
+  apply<float>(h, 0, EPI_KU, r, nullptr, g, C, s);
+  const double alpha = rn > 0 ? -1.0 / (std::log(10.0) * (rn + 1e-12) * rn) : 0.0;
+  double addh[18];
+  for (int q = 0; q < Q; ++q) addh[q] = 2.0 * lambda * sh[q];
+  GMT_HIP(hipMemcpyAsync(add, addh, Q * sizeof(double), hipMemcpyHostToDevice, s));
+  launch_scale_add_comp<float>(g, g, (float)alpha, add, n, C, D, s);
+  // adjoint sweep down the levels
+  float* w = g;
+  for (int l = 0; l < L - 1; ++l) {
+    const int nl = h.lv[l].n_n;
+    const size_t tl = (size_t)nl * Q;
+    float *z, *kz;
+    if (l == 0) {
+      z = W.pq;
+      kz = W.px;
+    } else {
+      z = W.io2[l];
+      kz = W.io3[l];
+    }
+    if (d_gpred[l]) {
+      vcycle<float>(h, w, z, true, nullptr, cfg, s, l);
+      apply<float>(h, l, EPI_KU, z, nullptr, kz, C, s);
+      launch_axpby<float>(kz, w, 1.f, -1.f, tl, s);  // kz = w - K V(w)
+      stage_out<float>(h, l, kz, d_gpred[l], s);
+    }
+    bool deeper = false;
+    for (int k = l + 1; k < L - 1; ++k) deeper |= d_gpred[k] != nullptr;
+    if (!deeper) break;
+    // w_{l+1} = R Post_l^T w_l,  Post_l^T w = D p(D^-1 K) (D^-1 w)
+    h.ensure_io<float>(l + 1);
+    float* t = l == 0 ? W.pr : z;
+    float* zero = kz;
+    launch_copy<float>(w, t, tl, s);
+    launch_mul_nodewise<float>(t, h.lv[l].dinv32, nl, C, D, 0, s);
+    launch_fill<float>(zero, tl, 0.f, s);
+    float* cur = t;
+    float* alt = W.ualt[l];
+    const double q1 = cfg.smoother == GMT_SMOOTH_JACOBI ? cfg.omega[l] : cfg.lo[l];
+    smooth<float>(h, l, zero, cur, alt, W.dvec[l], cfg.nu2, false, cfg.smoother, q1, cfg.hi[l], s);
+    launch_mul_nodewise<float>(cur, h.lv[l].dinv32, nl, C, D, 1, s);
+    launch_restrict<float>(h.view<float>(l), h.view<float>(l + 1), Q, D, cur, W.io1[l + 1], s);
+    w = W.io1[l + 1];
+  }
+  GMT_HIP(hipStreamSynchronize(s));
+}
+}  // namespace gmt
+
+gmt_status gmt_vcycle_loss(gmt_hier_t H, const float* const* d_pred, const gmt_cycle_opts* opts, double lambda,
+                           float* d_u1, double* h_out, float* const* d_gpred, void* stream) {
+  return guarded([&] {
+    check_level(H, 1);
+    if (!d_pred || !d_pred[0]) fail(GMT_E_INVAL, "d_pred[0] (u_hat^1) is required");
+    if (H->h.L < 2) fail(GMT_E_INVAL, "the learned path needs at least 2 levels");
+    vcycle_loss(H->h, d_pred, opts, lambda, d_u1, h_out, d_gpred, S(stream));
+  });
+}

@@ -6,6 +6,10 @@
 // i's local corner, times the element vector u_e.  Summed over all nodes this
 // performs exactly the element products of sum_e A_e^T K_e A_e u, without
 // atomics, so every result is deterministic.
+//
+// Solver vectors are stored case-major: value (case c, DOF d) of node i lives
+// at v[(c*n + i)*D + d].  The 64 lanes of a wave that gather one neighbour's
+// D DOFs of one case read one contiguous run of 64*D words.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -18,54 +22,140 @@ constexpr int kBlock = 256;
 
 __device__ __forceinline__ int wrapm(int v, int N) { return v < 0 ? v + N : (v >= N ? v - N : v); }
 
+// Read-only operator coefficients are read through the constant address space:
+// together with a wave-uniform address this gives scalar loads even inside loops
+// that store to other buffers.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+  return (cptr<T>)(p);
+}
+
+// index of (case c, node i, DOF d) in a case-major solver vector of n nodes
+__device__ __forceinline__ size_t vix(int c, size_t n, size_t i, int D, int d) { return ((size_t)c * n + i) * D + d; }
+
 // ---------------------------------------------------------------- operator sweeps
 
-// Epilogue for one (case, dof) value.
+// Epilogue for one (case, dof) value; idx = (c*n + i)*D + d, di = i*D + d.
 template <typename T, int EPI>
-__device__ __forceinline__ void epilogue(const EpiArgs<T>& e, size_t idx, T acc, T uself, T dinv) {
+__device__ __forceinline__ void epilogue(const EpiArgs<T>& e, size_t idx, T acc, T uself, size_t di) {
   if constexpr (EPI == EPI_KU) {
     e.out[idx] = acc;
   } else if constexpr (EPI == EPI_RESID) {
     e.out[idx] = e.f[idx] - acc;
   } else if constexpr (EPI == EPI_JACOBI) {
-    e.out[idx] = uself + e.omega * dinv * (e.f[idx] - acc);
-  } else {
-    T dn = e.rho2 * dinv * (e.f[idx] - acc);
-    if (e.rho1 != T(0)) dn += e.rho1 * e.dvec[idx];
+    e.out[idx] = uself + e.omega * e.dinv[di] * (e.f[idx] - acc);
+  } else if constexpr (EPI == EPI_CHEB) {
+    const T dn = e.rho1 * e.dvec[idx] + e.rho2 * e.dinv[di] * (e.f[idx] - acc);
+    e.dvec[idx] = dn;
+    e.out[idx] = uself + dn;
+  } else {  // EPI_CHEB0
+    const T dn = e.rho2 * e.dinv[di] * (e.f[idx] - acc);
     e.dvec[idx] = dn;
     e.out[idx] = uself + dn;
   }
 }
 
-// Level 1: the shared voxel K_e, element activity from the node's occupancy byte.
-// One thread per node; for each case the 27 neighbour values live in registers
-// and the K_e coefficients are wave-uniform (scalar loads).
-template <typename T, int D, int EPI>
-__global__ __launch_bounds__(kBlock) void k_apply_shared(LevelView<T> L, int C,
-                                                         const T* __restrict__ u, EpiArgs<T> e) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= L.n_n) return;
-  const int N = L.N;
-  const int lin = L.node_lin[i];
-  const int x = lin % N;
-  const int t = lin / N;
-  const int y = t % N;
-  const int z = t / N;
+// Structural zeros of the assembled interior stencil of the isotropic voxel
+// element: block (offset j, row d, column d2) vanishes unless d == d2 or the
+// offset has nonzero components along both d and d2 (elastic); for the
+// scalar problem the six face neighbours vanish.  Checked on the host.
+template <int D>
+__host__ __device__ constexpr bool stencil_nonzero(int j, int d, int d2) {
+  const int o[3] = {j % 3 - 1, (j / 3) % 3 - 1, j / 9 - 1};
+  if constexpr (D == 1) {
+    const int nz = (o[0] != 0) + (o[1] != 0) + (o[2] != 0);
+    return nz != 1;
+  } else {
+    return d == d2 || (o[d] != 0 && o[d2] != 0);
+  }
+}
+
+// 27 neighbour ids of node (x,y,z) from the dense node map; runs along x of an
+// all-active row are consecutive ids, so an interior node needs 9 lookups.
+template <bool INTERIOR>
+__device__ __forceinline__ void neighbour_ids(const int* __restrict__ map, int N, int x, int y, int z, int nb[27]) {
   const int xs[3] = {wrapm(x - 1, N), x, wrapm(x + 1, N)};
   const int ys[3] = {wrapm(y - 1, N), y, wrapm(y + 1, N)};
   const int zs[3] = {wrapm(z - 1, N), z, wrapm(z + 1, N)};
-  int nb[27];
+  const bool run = INTERIOR && x > 0 && x < N - 1;
 #pragma unroll
-  for (int j = 0; j < 27; ++j) nb[j] = L.node_map[xs[j % 3] + N * (ys[(j / 3) % 3] + N * zs[j / 9])];
-  const unsigned occ = L.occ8[i];
-  const T* __restrict__ K = L.K;
+  for (int r = 0; r < 9; ++r) {
+    const int row = N * (ys[r % 3] + N * zs[r / 3]);
+    if (run) {
+      const int b = map[xs[0] + row];
+      nb[3 * r + 0] = b;
+      nb[3 * r + 1] = b + 1;
+      nb[3 * r + 2] = b + 2;
+    } else {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) nb[3 * r + a] = map[xs[a] + row];
+    }
+  }
+}
+
+// Level 1, interior nodes (all 8 surrounding voxels solid): the assembled
+// 27-point stencil S of the shared K_e, wave-uniform coefficients.
+template <typename T, int D, int EPI>
+__global__ __launch_bounds__(kBlock) void k_apply_interior(LevelView<T> L, int C, const T* __restrict__ u, EpiArgs<T> e) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= L.n_int) return;
+  const int i = L.interior[t];
+  const int N = L.N;
+  const size_t n = (size_t)L.n_n;
+  const int lin = L.node_lin[i];
+  const int x = lin % N, y = (lin / N) % N, z = lin / (N * N);
+  int nb[27];
+  neighbour_ids<true>(L.node_map, N, x, y, z, nb);
+#pragma unroll 1
   for (int c = 0; c < C; ++c) {
-    T uv[27][D];
+    // L.zero is 0 at run time: the coefficient address stays wave-uniform (scalar
+    // loads) but depends on c, so the 27 x D x D loads are not hoisted out of the
+    // case loop into VGPRs
+    const cptr<T> S = as_const(L.S + (c & L.zero));
+    T acc[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) acc[q] = T(0);
+    T uself[D];
 #pragma unroll
     for (int j = 0; j < 27; ++j) {
 #pragma unroll
-      for (int q = 0; q < D; ++q) uv[j][q] = nb[j] >= 0 ? u[((size_t)nb[j] * C + c) * D + q] : T(0);
+      for (int q2 = 0; q2 < D; ++q2) {
+        const T v = u[vix(c, n, nb[j], D, q2)];
+        if (j == 13) uself[q2] = v;
+#pragma unroll
+        for (int q = 0; q < D; ++q)
+          if constexpr (true)
+            if (stencil_nonzero<D>(j, q, q2)) acc[q] = fma(S[(j * D + q) * D + q2], v, acc[q]);
+      }
     }
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+      epilogue<T, EPI>(e, vix(c, n, i, D, q), acc[q], uself[q], (size_t)i * D + q);
+  }
+}
+
+// Level 1, boundary nodes: element-by-element over the active octant
+// elements (occupancy bits), shared K_e with wave-uniform coefficients.  The 8
+// corner values of an element are loaded inside that element's branch, which
+// keeps the live register set to one element.
+template <typename T, int D, int EPI>
+__global__ __launch_bounds__(kBlock) void k_apply_boundary(LevelView<T> L, int C, const T* __restrict__ u, EpiArgs<T> e) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= L.n_bnd) return;
+  const int i = L.boundary[t];
+  const int N = L.N;
+  const size_t n = (size_t)L.n_n;
+  const int lin = L.node_lin[i];
+  const int x = lin % N, y = (lin / N) % N, z = lin / (N * N);
+  int nb[27];
+  neighbour_ids<false>(L.node_map, N, x, y, z, nb);
+  const unsigned occ = L.occ8[i];
+  constexpr int M = 8 * D;
+#pragma unroll 1
+  for (int c = 0; c < C; ++c) {
+    const cptr<T> K = as_const(L.K + (c & L.zero));  // see k_apply_interior
     T acc[D];
 #pragma unroll
     for (int q = 0; q < D; ++q) acc[q] = T(0);
@@ -74,29 +164,37 @@ __global__ __launch_bounds__(kBlock) void k_apply_shared(LevelView<T> L, int C,
       if (occ & (1u << k)) {
         const int a = 7 - k;
         const int ak = k & 1, bk = (k >> 1) & 1, ck = (k >> 2) & 1;
+        T ue[8][D];
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
+          // corners of an active element are active: nb >= 0
           const int j = (ak + (m & 1)) + 3 * (bk + ((m >> 1) & 1)) + 9 * (ck + ((m >> 2) & 1));
 #pragma unroll
-          for (int q = 0; q < D; ++q) {
-#pragma unroll
-            for (int q2 = 0; q2 < D; ++q2)
-              acc[q] = fma(K[(a * D + q) * (8 * D) + m * D + q2], uv[j][q2], acc[q]);
-          }
+          for (int q = 0; q < D; ++q) ue[m][q] = u[vix(c, n, nb[j], D, q)];
         }
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+          for (int q = 0; q < D; ++q)
+#pragma unroll
+            for (int q2 = 0; q2 < D; ++q2) acc[q] = fma(K[(a * D + q) * M + m * D + q2], ue[m][q2], acc[q]);
       }
     }
+    T uself[D];
 #pragma unroll
-    for (int q = 0; q < D; ++q) {
-      T dv = T(0);
-      if constexpr (EPI == EPI_JACOBI || EPI == EPI_CHEB) dv = e.dinv[(size_t)i * D + q];
-      epilogue<T, EPI>(e, ((size_t)i * C + c) * D + q, acc[q], uv[13][q], dv);
+    for (int q = 0; q < D; ++q) uself[q] = T(0);
+    if constexpr (EPI == EPI_JACOBI || EPI == EPI_CHEB || EPI == EPI_CHEB0) {
+#pragma unroll
+      for (int q = 0; q < D; ++q) uself[q] = u[vix(c, n, i, D, q)];
     }
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+      epilogue<T, EPI>(e, vix(c, n, i, D, q), acc[q], uself[q], (size_t)i * D + q);
   }
 }
 
 // Levels >= 2: per-element matrices (mask table or stored), element ids from
-// the dense element map.  Element-outer loop: the 3 coefficient rows of an
+// the dense element map.  Element-outer loop: the D coefficient rows of an
 // element are loaded once and used for all C cases.
 template <typename T, int D, int C, int KIND, int EPI>
 __global__ __launch_bounds__(kBlock) void k_apply_coarse(LevelView<T> L, const T* __restrict__ u,
@@ -104,6 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_coarse(LevelView<T> L, const T
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= L.n_n) return;
   const int N = L.N;
+  const size_t n = (size_t)L.n_n;
   const int lin = L.node_lin[i];
   const int x = lin % N;
   const int t = lin / N;
@@ -139,28 +238,25 @@ __global__ __launch_bounds__(kBlock) void k_apply_coarse(LevelView<T> L, const T
       for (int q = 0; q < D; ++q)
 #pragma unroll
         for (int q2 = 0; q2 < D; ++q2) coef[q][q2] = Km[q * M + m * D + q2];
-      const T* __restrict__ un = u + (size_t)id * C * D;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
 #pragma unroll
         for (int q2 = 0; q2 < D; ++q2) {
-          const T v = un[c * D + q2];
+          const T v = u[vix(c, n, id, D, q2)];
 #pragma unroll
           for (int q = 0; q < D; ++q) acc[c][q] = fma(coef[q][q2], v, acc[c][q]);
         }
       }
     }
   }
-  const T* __restrict__ us = u + (size_t)i * C * D;
 #pragma unroll
   for (int c = 0; c < C; ++c)
 #pragma unroll
     for (int q = 0; q < D; ++q) {
-      T dv = T(0);
-      if constexpr (EPI == EPI_JACOBI || EPI == EPI_CHEB) dv = e.dinv[(size_t)i * D + q];
+      const size_t idx = vix(c, n, i, D, q);
       T uself = T(0);
-      if constexpr (EPI == EPI_JACOBI || EPI == EPI_CHEB) uself = us[c * D + q];
-      epilogue<T, EPI>(e, ((size_t)i * C + c) * D + q, acc[c][q], uself, dv);
+      if constexpr (EPI == EPI_JACOBI || EPI == EPI_CHEB || EPI == EPI_CHEB0) uself = u[idx];
+      epilogue<T, EPI>(e, idx, acc[c][q], uself, (size_t)i * D + q);
     }
 }
 
@@ -171,8 +267,8 @@ __global__ void k_smooth_zero(int n, int D, int C, const T* __restrict__ f, cons
   const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
   const size_t total = (size_t)n * C * D;
   if (idx >= total) return;
-  const size_t node = idx / ((size_t)C * D);
   const int q = (int)(idx % D);
+  const size_t node = (idx / D) % n;
   const T v = scale * dinv[node * D + q] * f[idx];
   out[idx] = v;
   if (dvec) dvec[idx] = v;
@@ -182,12 +278,13 @@ __global__ void k_smooth_zero(int n, int D, int C, const T* __restrict__ f, cons
 
 // Restriction in gather form: coarse node X collects the fine nodes 2X + delta,
 // delta in {-1,0,1}^3, with weight prod_d (1 - |delta_d|/2): exactly R = P^T.
-template <typename T, int Q>
+template <typename T, int Q, int D>
 __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> F, LevelView<T> Cv, const T* __restrict__ rf,
                                                      T* __restrict__ fc) {
   const int J = blockIdx.x * kBlock + threadIdx.x;
   if (J >= Cv.n_n) return;
   const int Nc = Cv.N, Nf = F.N;
+  const size_t nf = (size_t)F.n_n, nc = (size_t)Cv.n_n;
   const int lin = Cv.node_lin[J];
   const int X = lin % Nc;
   const int t = lin / Nc;
@@ -206,23 +303,23 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> F, LevelView<T
         const int id = F.node_map[fx + Nf * (fy + Nf * fz)];
         if (id < 0) continue;
         const T w = T((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
-        const T* __restrict__ r = rf + (size_t)id * Q;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) acc[q] = fma(w, r[q], acc[q]);
+        for (int q = 0; q < Q; ++q) acc[q] = fma(w, rf[vix(q / D, nf, id, D, q % D)], acc[q]);
       }
     }
   }
 #pragma unroll
-  for (int q = 0; q < Q; ++q) fc[(size_t)J * Q + q] = acc[q];
+  for (int q = 0; q < Q; ++q) fc[vix(q / D, nc, J, D, q % D)] = acc[q];
 }
 
 // Prolongation + correction: u_f(i) += sum_k W_ik u_c(I_ik) (App. E.1 weights).
-template <typename T, int Q>
+template <typename T, int Q, int D>
 __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView<T> F, LevelView<T> Cv, const T* __restrict__ uc,
                                                         T* __restrict__ uf) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= F.n_n) return;
   const int Nc = Cv.N, Nf = F.N;
+  const size_t nf = (size_t)F.n_n, nc = (size_t)Cv.n_n;
   const int lin = F.node_lin[i];
   const int x = lin % Nf;
   const int t = lin / Nf;
@@ -233,7 +330,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView<T> F, LevelVie
   const int nx = (x & 1) ? 2 : 1, ny = (y & 1) ? 2 : 1, nz = (z & 1) ? 2 : 1;
   T acc[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) acc[q] = uf[(size_t)i * Q + q];
+  for (int q = 0; q < Q; ++q) acc[q] = uf[vix(q / D, nf, i, D, q % D)];
   const T w = T(1.0 / (nx * ny * nz));
 #pragma unroll 1
   for (int oz = 0; oz < nz; ++oz)
@@ -242,23 +339,23 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView<T> F, LevelVie
         const int X = wrapm(cx0 + ox, Nc), Y = wrapm(cy0 + oy, Nc), Z = wrapm(cz0 + oz, Nc);
         const int id = Cv.node_map[X + Nc * (Y + Nc * Z)];
         if (id < 0) continue;  // cannot happen for a consistent hierarchy
-        const T* __restrict__ v = uc + (size_t)id * Q;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) acc[q] = fma(w, v[q], acc[q]);
+        for (int q = 0; q < Q; ++q) acc[q] = fma(w, uc[vix(q / D, nc, id, D, q % D)], acc[q]);
       }
 #pragma unroll
-  for (int q = 0; q < Q; ++q) uf[(size_t)i * Q + q] = acc[q];
+  for (int q = 0; q < Q; ++q) uf[vix(q / D, nf, i, D, q % D)] = acc[q];
 }
 
 // ---------------------------------------------------------------- coarsest solve
 
 // u = Kinv f with Kinv the pinned inverse (symmetric, pinned rows/cols zero).
-// One thread per DOF row; reads Kinv column-wise (= row-wise by symmetry).
+// One thread per DOF row (node*D + d); reads Kinv column-wise (= row-wise by symmetry).
 template <typename T, int C>
 __global__ void k_coarse_solve(const T* __restrict__ Kinv, int cn, int D, const T* __restrict__ f,
                                T* __restrict__ u) {
   const int row = blockIdx.x * kBlock + threadIdx.x;
   if (row >= cn) return;
+  const int n = cn / D;
   double acc[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = 0.0;
@@ -266,11 +363,34 @@ __global__ void k_coarse_solve(const T* __restrict__ Kinv, int cn, int D, const 
     const double kv = (double)Kinv[(size_t)j * cn + row];
     const int node = j / D, q = j % D;
 #pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] += kv * (double)f[((size_t)node * C + c) * D + q];
+    for (int c = 0; c < C; ++c) acc[c] += kv * (double)f[vix(c, n, node, D, q)];
   }
   const int node = row / D, q = row % D;
 #pragma unroll
-  for (int c = 0; c < C; ++c) u[((size_t)node * C + c) * D + q] = (T)acc[c];
+  for (int c = 0; c < C; ++c) u[vix(c, n, node, D, q)] = (T)acc[c];
+}
+
+// Layout changes between the ABI's [n][Q] and the solver's [Q][n].
+// ABI [n][C][D] -> solver [C][n][D]
+template <typename Tin, typename Tout>
+__global__ void k_aos_to_soa(const Tin* __restrict__ a, Tout* __restrict__ b, int n, int C, int D) {
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;  // index into b
+  if (idx >= (size_t)n * C * D) return;
+  const int d = (int)(idx % D);
+  const size_t t = idx / D;
+  const size_t i = t % n, c = t / n;
+  b[idx] = (Tout)a[(i * C + c) * D + d];
+}
+
+// solver [C][n][D] -> ABI [n][C][D]
+template <typename Tin, typename Tout>
+__global__ void k_soa_to_aos(const Tin* __restrict__ a, Tout* __restrict__ b, int n, int C, int D) {
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;  // index into b
+  if (idx >= (size_t)n * C * D) return;
+  const int d = (int)(idx % D);
+  const size_t t = idx / D;
+  const size_t c = t % C, i = t / C;
+  b[idx] = (Tout)a[(c * n + i) * D + d];
 }
 
 // ---------------------------------------------------------------- vector kernels
@@ -329,7 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_dot(const T* __restrict__ a, const T
     for (int c = 0; c < C; ++c)
 #pragma unroll
       for (int q = 0; q < D; ++q) {
-        const size_t idx = ((size_t)i * C + c) * D + q;
+        const size_t idx = vix(c, n, i, D, q);
         v[c] += (double)a[idx] * (double)b[idx];
       }
   }
@@ -348,8 +468,8 @@ __global__ __launch_bounds__(kBlock) void k_gram(const Ta* __restrict__ a, const
     for (int c = 0; c < C; ++c)
 #pragma unroll
       for (int q = 0; q < D; ++q) {
-        av[c][q] = (double)a[((size_t)i * C + c) * D + q];
-        bv[c][q] = (double)b[((size_t)i * C + c) * D + q];
+        av[c][q] = (double)a[vix(c, n, i, D, q)];
+        bv[c][q] = (double)b[vix(c, n, i, D, q)];
       }
 #pragma unroll
     for (int c1 = 0; c1 < C; ++c1)
@@ -361,24 +481,49 @@ __global__ __launch_bounds__(kBlock) void k_gram(const Ta* __restrict__ a, const
   block_reduce_store<C * C>(v, partial);
 }
 
-// Column sums over nodes: partial[block][q] = sum_i v[i][q] (FP64 accumulation).
-template <typename T, int Q>
+// Column sums over nodes: partial[block][q] = sum_i v[q][i] (FP64 accumulation).
+template <typename T, int Q, int D>
 __global__ __launch_bounds__(kBlock) void k_colsum(const T* __restrict__ v, int n, double* __restrict__ partial) {
   double acc[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) acc[q] = 0.0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) acc[q] += (double)v[(size_t)i * Q + q];
+    for (int q = 0; q < Q; ++q) acc[q] += (double)v[vix(q / D, n, i, D, q % D)];
   }
   block_reduce_store<Q>(acc, partial);
 }
 
-// v[i][q] -= sums[q] / n : removes the rigid-translation (constant) component.
+// v[q][i] -= sums[q] / n : removes the rigid-translation (constant) component.
 template <typename T>
-__global__ void k_sub_mean(T* __restrict__ v, size_t total, int Q, const double* __restrict__ sums, double inv_n) {
+__global__ void k_sub_mean(T* __restrict__ v, size_t total, int n, int D, const double* __restrict__ sums,
+                           double inv_n) {
   size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < total) v[i] -= (T)(sums[i % Q] * inv_n);
+  if (i < total) v[i] -= (T)(sums[(i / ((size_t)n * D)) * D + i % D] * inv_n);
+}
+
+template <typename T>
+__global__ void k_axpby(T* __restrict__ y, const T* __restrict__ x, T alpha, T beta, size_t n) {
+  const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) y[i] = alpha * x[i] + beta * y[i];
+}
+
+template <typename T>
+__global__ void k_scale_add_comp(T* __restrict__ y, const T* __restrict__ x, T alpha, const double* __restrict__ add,
+                                 int n, int D, size_t total) {
+  const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= total) return;
+  const size_t c = i / ((size_t)n * D);
+  y[i] = alpha * x[i] + (T)add[c * D + i % D];
+}
+
+template <typename T>
+__global__ void k_mul_nodewise(T* __restrict__ v, const T* __restrict__ w, int n, int D, int divide, size_t total) {
+  const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= total) return;
+  const size_t node = (i / D) % n;
+  const T ww = w[node * D + i % D];
+  v[i] = divide ? v[i] / ww : v[i] * ww;
 }
 
 // Second stage: out[k] = sum over blocks of partial[b][k], fixed order.
@@ -400,21 +545,21 @@ __global__ void k_reduce_final(const double* __restrict__ partial, int nblocks, 
 
 template <typename T>
 __global__ void k_pcg_update(T* __restrict__ u, T* __restrict__ r, const T* __restrict__ p,
-                             const T* __restrict__ q, const double* __restrict__ alpha, size_t n, int C,
+                             const T* __restrict__ q, const double* __restrict__ alpha, size_t total, int n,
                              int D) {
   size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const T a = (T)alpha[(i / D) % C];
+  if (i >= total) return;
+  const T a = (T)alpha[i / ((size_t)n * D)];
   u[i] = fma(a, p[i], u[i]);
   r[i] = fma(-a, q[i], r[i]);
 }
 
 template <typename T>
 __global__ void k_pcg_direction(T* __restrict__ p, const T* __restrict__ z, const double* __restrict__ beta,
-                                size_t n, int C, int D) {
+                                size_t total, int n, int D) {
   size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const T b = (T)beta[(i / D) % C];
+  if (i >= total) return;
+  const T b = (T)beta[i / ((size_t)n * D)];
   p[i] = fma(b, p[i], z[i]);
 }
 
@@ -432,14 +577,15 @@ __global__ void k_pcg_beta(const double* rz_new, double* rz, double* beta, int C
 }
 
 template <typename T>
-__global__ void k_copy_node(const T* __restrict__ u, int Q, T* __restrict__ tmp) {
-  if ((int)threadIdx.x < Q) tmp[threadIdx.x] = u[threadIdx.x];
+__global__ void k_copy_node(const T* __restrict__ u, int n, int Q, int D, T* __restrict__ tmp) {
+  const int q = threadIdx.x;
+  if (q < Q) tmp[q] = u[vix(q / D, n, 0, D, q % D)];
 }
 
 template <typename T>
-__global__ void k_sub_node(T* __restrict__ u, size_t n, int Q, const T* __restrict__ tmp) {
+__global__ void k_sub_node(T* __restrict__ u, size_t total, int n, int D, const T* __restrict__ tmp) {
   size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) u[i] -= tmp[i % Q];
+  if (i < total) u[i] -= tmp[(i / ((size_t)n * D)) * D + i % D];
 }
 
 template <typename T>
@@ -591,6 +737,12 @@ __global__ void k_occ8(const int* __restrict__ node_lin, int n_n, const int* __r
     if (emap[ex + N * (ey + N * ez)] >= 0) m |= 1u << k;
   }
   occ8[i] = (uint8_t)m;
+}
+
+// flags[i] = (occ8[i] == 255) == want_full
+__global__ void k_occ_flags(const uint8_t* __restrict__ occ8, int n, int want_full, int* __restrict__ flags) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) flags[i] = ((occ8[i] == 255) ? 1 : 0) == want_full;
 }
 
 __global__ void k_gather_cmask(const int* __restrict__ elem_lin, int n_e, const uint8_t* __restrict__ dense,
@@ -754,7 +906,7 @@ __global__ void k_load_vector(const int* __restrict__ node_lin, const uint8_t* _
       double s = 0.0;
       for (int k = 0; k < 8; ++k)
         if (occ & (1u << k)) s += fe[((7 - k) * D + q) * C + c];
-      f[((size_t)i * C + c) * D + q] = s;
+      f[vix(c, n_n, i, D, q)] = s;
     }
 }
 
@@ -777,14 +929,19 @@ inline unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlo
 
 template <typename T, int D, int C, int EPI>
 static void apply_dispatch_kind(const LevelView<T>& L, int kind, const T* u, const EpiArgs<T>& e, hipStream_t s) {
-  const unsigned g = blocks_for(L.n_n);
-  if (g == 0) return;
-  if (kind == KIND_SHARED)
-    hipLaunchKernelGGL((k_apply_shared<T, D, EPI>), dim3(g), dim3(kBlock), 0, s, L, C, u, e);
-  else if (kind == KIND_TABLE)
-    hipLaunchKernelGGL((k_apply_coarse<T, D, C, KIND_TABLE, EPI>), dim3(g), dim3(kBlock), 0, s, L, u, e);
-  else
-    hipLaunchKernelGGL((k_apply_coarse<T, D, C, KIND_PERELEM, EPI>), dim3(g), dim3(kBlock), 0, s, L, u, e);
+  if (kind == KIND_SHARED) {
+    if (L.n_int > 0)
+      hipLaunchKernelGGL((k_apply_interior<T, D, EPI>), dim3(blocks_for(L.n_int)), dim3(kBlock), 0, s, L, C, u, e);
+    if (L.n_bnd > 0)
+      hipLaunchKernelGGL((k_apply_boundary<T, D, EPI>), dim3(blocks_for(L.n_bnd)), dim3(kBlock), 0, s, L, C, u, e);
+  } else {
+    const unsigned g = blocks_for(L.n_n);
+    if (g == 0) return;
+    if (kind == KIND_TABLE)
+      hipLaunchKernelGGL((k_apply_coarse<T, D, C, KIND_TABLE, EPI>), dim3(g), dim3(kBlock), 0, s, L, u, e);
+    else
+      hipLaunchKernelGGL((k_apply_coarse<T, D, C, KIND_PERELEM, EPI>), dim3(g), dim3(kBlock), 0, s, L, u, e);
+  }
   GMT_LAUNCH_CHECK();
 }
 
@@ -795,7 +952,8 @@ static void apply_dispatch_epi(const LevelView<T>& L, int kind, int epi, const T
     case EPI_KU: apply_dispatch_kind<T, D, C, EPI_KU>(L, kind, u, e, s); break;
     case EPI_RESID: apply_dispatch_kind<T, D, C, EPI_RESID>(L, kind, u, e, s); break;
     case EPI_JACOBI: apply_dispatch_kind<T, D, C, EPI_JACOBI>(L, kind, u, e, s); break;
-    default: apply_dispatch_kind<T, D, C, EPI_CHEB>(L, kind, u, e, s); break;
+    case EPI_CHEB: apply_dispatch_kind<T, D, C, EPI_CHEB>(L, kind, u, e, s); break;
+    default: apply_dispatch_kind<T, D, C, EPI_CHEB0>(L, kind, u, e, s); break;
   }
 }
 
@@ -820,28 +978,26 @@ void launch_smooth_zero(int n, int D, int C, const T* f, const T* dinv, T scale,
 }
 
 template <typename T>
-void launch_restrict(const LevelView<T>& F, const LevelView<T>& Cv, int Q, const T* rf, T* fc, hipStream_t s) {
+void launch_restrict(const LevelView<T>& F, const LevelView<T>& Cv, int Q, int D, const T* rf, T* fc, hipStream_t s) {
   const unsigned g = blocks_for(Cv.n_n);
   if (!g) return;
-  switch (Q) {
-    case 18: hipLaunchKernelGGL((k_restrict<T, 18>), dim3(g), dim3(kBlock), 0, s, F, Cv, rf, fc); break;
-    case 3: hipLaunchKernelGGL((k_restrict<T, 3>), dim3(g), dim3(kBlock), 0, s, F, Cv, rf, fc); break;
-    case 1: hipLaunchKernelGGL((k_restrict<T, 1>), dim3(g), dim3(kBlock), 0, s, F, Cv, rf, fc); break;
-    default: fail(GMT_E_INVAL, "unsupported Q=%d", Q);
-  }
+  if (Q == 18 && D == 3) hipLaunchKernelGGL((k_restrict<T, 18, 3>), dim3(g), dim3(kBlock), 0, s, F, Cv, rf, fc);
+  else if (Q == 3 && D == 1) hipLaunchKernelGGL((k_restrict<T, 3, 1>), dim3(g), dim3(kBlock), 0, s, F, Cv, rf, fc);
+  else if (Q == 3 && D == 3) hipLaunchKernelGGL((k_restrict<T, 3, 3>), dim3(g), dim3(kBlock), 0, s, F, Cv, rf, fc);
+  else if (Q == 1 && D == 1) hipLaunchKernelGGL((k_restrict<T, 1, 1>), dim3(g), dim3(kBlock), 0, s, F, Cv, rf, fc);
+  else fail(GMT_E_INVAL, "unsupported (Q, D) = (%d, %d)", Q, D);
   GMT_LAUNCH_CHECK();
 }
 
 template <typename T>
-void launch_prolong_add(const LevelView<T>& F, const LevelView<T>& Cv, int Q, const T* uc, T* uf, hipStream_t s) {
+void launch_prolong_add(const LevelView<T>& F, const LevelView<T>& Cv, int Q, int D, const T* uc, T* uf, hipStream_t s) {
   const unsigned g = blocks_for(F.n_n);
   if (!g) return;
-  switch (Q) {
-    case 18: hipLaunchKernelGGL((k_prolong_add<T, 18>), dim3(g), dim3(kBlock), 0, s, F, Cv, uc, uf); break;
-    case 3: hipLaunchKernelGGL((k_prolong_add<T, 3>), dim3(g), dim3(kBlock), 0, s, F, Cv, uc, uf); break;
-    case 1: hipLaunchKernelGGL((k_prolong_add<T, 1>), dim3(g), dim3(kBlock), 0, s, F, Cv, uc, uf); break;
-    default: fail(GMT_E_INVAL, "unsupported Q=%d", Q);
-  }
+  if (Q == 18 && D == 3) hipLaunchKernelGGL((k_prolong_add<T, 18, 3>), dim3(g), dim3(kBlock), 0, s, F, Cv, uc, uf);
+  else if (Q == 3 && D == 1) hipLaunchKernelGGL((k_prolong_add<T, 3, 1>), dim3(g), dim3(kBlock), 0, s, F, Cv, uc, uf);
+  else if (Q == 3 && D == 3) hipLaunchKernelGGL((k_prolong_add<T, 3, 3>), dim3(g), dim3(kBlock), 0, s, F, Cv, uc, uf);
+  else if (Q == 1 && D == 1) hipLaunchKernelGGL((k_prolong_add<T, 1, 1>), dim3(g), dim3(kBlock), 0, s, F, Cv, uc, uf);
+  else fail(GMT_E_INVAL, "unsupported (Q, D) = (%d, %d)", Q, D);
   GMT_LAUNCH_CHECK();
 }
 
@@ -912,34 +1068,85 @@ void launch_gram(const Ta* a, const Tb* b, int n, int C, int D, double* partial,
 }
 
 template <typename T>
-void launch_project(T* v, int n, int Q, double* partial, double* sums, hipStream_t s) {
+void launch_colsum(const T* v, int n, int Q, int D, double* partial, double* sums, hipStream_t s) {
   const unsigned g = red_grid(n);
-  switch (Q) {
-    case 18: hipLaunchKernelGGL((k_colsum<T, 18>), dim3(g), dim3(kBlock), 0, s, v, n, partial); break;
-    case 3: hipLaunchKernelGGL((k_colsum<T, 3>), dim3(g), dim3(kBlock), 0, s, v, n, partial); break;
-    case 1: hipLaunchKernelGGL((k_colsum<T, 1>), dim3(g), dim3(kBlock), 0, s, v, n, partial); break;
-    default: fail(GMT_E_INVAL, "unsupported Q=%d", Q);
-  }
+  if (Q == 18 && D == 3) hipLaunchKernelGGL((k_colsum<T, 18, 3>), dim3(g), dim3(kBlock), 0, s, v, n, partial);
+  else if (Q == 3 && D == 1) hipLaunchKernelGGL((k_colsum<T, 3, 1>), dim3(g), dim3(kBlock), 0, s, v, n, partial);
+  else fail(GMT_E_INVAL, "unsupported (Q, D) = (%d, %d)", Q, D);
+  GMT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, partial, (int)g, Q, sums);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_axpby(T* y, const T* x, T alpha, T beta, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_axpby<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, y, x, alpha, beta, n);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_scale_add_comp(T* y, const T* x, T alpha, const double* add, int n, int C, int D, hipStream_t s) {
+  const size_t tot = (size_t)n * C * D;
+  if (!tot) return;
+  hipLaunchKernelGGL(k_scale_add_comp<T>, dim3(blocks_for(tot)), dim3(kBlock), 0, s, y, x, alpha, add, n, D, tot);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_mul_nodewise(T* v, const T* w, int n, int C, int D, int divide, hipStream_t s) {
+  const size_t tot = (size_t)n * C * D;
+  if (!tot) return;
+  hipLaunchKernelGGL(k_mul_nodewise<T>, dim3(blocks_for(tot)), dim3(kBlock), 0, s, v, w, n, D, divide, tot);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_project(T* v, int n, int Q, int D, double* partial, double* sums, hipStream_t s) {
+  const unsigned g = red_grid(n);
+  if (Q == 18 && D == 3) hipLaunchKernelGGL((k_colsum<T, 18, 3>), dim3(g), dim3(kBlock), 0, s, v, n, partial);
+  else if (Q == 3 && D == 1) hipLaunchKernelGGL((k_colsum<T, 3, 1>), dim3(g), dim3(kBlock), 0, s, v, n, partial);
+  else if (Q == 3 && D == 3) hipLaunchKernelGGL((k_colsum<T, 3, 3>), dim3(g), dim3(kBlock), 0, s, v, n, partial);
+  else if (Q == 1 && D == 1) hipLaunchKernelGGL((k_colsum<T, 1, 1>), dim3(g), dim3(kBlock), 0, s, v, n, partial);
+  else fail(GMT_E_INVAL, "unsupported (Q, D) = (%d, %d)", Q, D);
   GMT_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, partial, (int)g, Q, sums);
   GMT_LAUNCH_CHECK();
   const size_t tot = (size_t)n * Q;
-  hipLaunchKernelGGL(k_sub_mean<T>, dim3(blocks_for(tot)), dim3(kBlock), 0, s, v, tot, Q, sums, 1.0 / n);
+  hipLaunchKernelGGL(k_sub_mean<T>, dim3(blocks_for(tot)), dim3(kBlock), 0, s, v, tot, n, D, sums, 1.0 / n);
   GMT_LAUNCH_CHECK();
 }
 
 template <typename T>
-void launch_pcg_update(T* u, T* r, const T* p, const T* q, const double* alpha, size_t n, int C, int D,
+void launch_pcg_update(T* u, T* r, const T* p, const T* q, const double* alpha, int n, int Q, int D,
                        hipStream_t s) {
-  if (!n) return;
-  hipLaunchKernelGGL(k_pcg_update<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, u, r, p, q, alpha, n, C, D);
+  const size_t tot = (size_t)n * Q;
+  if (!tot) return;
+  hipLaunchKernelGGL(k_pcg_update<T>, dim3(blocks_for(tot)), dim3(kBlock), 0, s, u, r, p, q, alpha, tot, n, D);
   GMT_LAUNCH_CHECK();
 }
 
 template <typename T>
-void launch_pcg_direction(T* p, const T* z, const double* beta, size_t n, int C, int D, hipStream_t s) {
-  if (!n) return;
-  hipLaunchKernelGGL(k_pcg_direction<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, p, z, beta, n, C, D);
+void launch_pcg_direction(T* p, const T* z, const double* beta, int n, int Q, int D, hipStream_t s) {
+  const size_t tot = (size_t)n * Q;
+  if (!tot) return;
+  hipLaunchKernelGGL(k_pcg_direction<T>, dim3(blocks_for(tot)), dim3(kBlock), 0, s, p, z, beta, tot, n, D);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename Tin, typename Tout>
+void launch_aos_to_soa(const Tin* a, Tout* b, int n, int C, int D, hipStream_t s) {
+  const size_t tot = (size_t)n * C * D;
+  if (!tot) return;
+  hipLaunchKernelGGL((k_aos_to_soa<Tin, Tout>), dim3(blocks_for(tot)), dim3(kBlock), 0, s, a, b, n, C, D);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename Tin, typename Tout>
+void launch_soa_to_aos(const Tin* a, Tout* b, int n, int C, int D, hipStream_t s) {
+  const size_t tot = (size_t)n * C * D;
+  if (!tot) return;
+  hipLaunchKernelGGL((k_soa_to_aos<Tin, Tout>), dim3(blocks_for(tot)), dim3(kBlock), 0, s, a, b, n, C, D);
   GMT_LAUNCH_CHECK();
 }
 
@@ -954,11 +1161,11 @@ void launch_pcg_beta(const double* rz_new, double* rz, double* beta, int C, hipS
 }
 
 template <typename T>
-void launch_gauge_shift(T* u, int n, int Q, T* tmp, hipStream_t s) {
-  hipLaunchKernelGGL(k_copy_node<T>, dim3(1), dim3(64), 0, s, u, Q, tmp);
+void launch_gauge_shift(T* u, int n, int Q, int D, T* tmp, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_node<T>, dim3(1), dim3(64), 0, s, u, n, Q, D, tmp);
   GMT_LAUNCH_CHECK();
   const size_t tot = (size_t)n * Q;
-  hipLaunchKernelGGL(k_sub_node<T>, dim3(blocks_for(tot)), dim3(kBlock), 0, s, u, tot, Q, tmp);
+  hipLaunchKernelGGL(k_sub_node<T>, dim3(blocks_for(tot)), dim3(kBlock), 0, s, u, tot, n, D, tmp);
   GMT_LAUNCH_CHECK();
 }
 
@@ -1009,6 +1216,12 @@ int64_t scan_compact(const int* flags, size_t n, int* map_out, int* lin_out, int
 void launch_occ8(const int* node_lin, int n_n, const int* emap, int N, uint8_t* occ8, hipStream_t s) {
   if (!n_n) return;
   hipLaunchKernelGGL(k_occ8, dim3(blocks_for(n_n)), dim3(kBlock), 0, s, node_lin, n_n, emap, N, occ8);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_occ_flags(const uint8_t* occ8, int n, int want_full, int* flags, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_occ_flags, dim3(blocks_for(n)), dim3(kBlock), 0, s, occ8, n, want_full, flags);
   GMT_LAUNCH_CHECK();
 }
 
@@ -1100,25 +1313,35 @@ void launch_random(double* x, size_t n, uint64_t seed, hipStream_t s) {
   template void launch_apply<T>(const LevelView<T>&, int, int, int, int, const T*, const EpiArgs<T>&,         \
                                 hipStream_t);                                                                \
   template void launch_smooth_zero<T>(int, int, int, const T*, const T*, T, T*, T*, hipStream_t);            \
-  template void launch_restrict<T>(const LevelView<T>&, const LevelView<T>&, int, const T*, T*, hipStream_t); \
-  template void launch_prolong_add<T>(const LevelView<T>&, const LevelView<T>&, int, const T*, T*,           \
+  template void launch_restrict<T>(const LevelView<T>&, const LevelView<T>&, int, int, const T*, T*,         \
+                                   hipStream_t);                                                              \
+  template void launch_prolong_add<T>(const LevelView<T>&, const LevelView<T>&, int, int, const T*, T*,      \
                                       hipStream_t);                                                          \
   template void launch_coarse_solve<T>(const T*, int, int, int, const T*, T*, hipStream_t);                  \
   template void launch_fill<T>(T*, size_t, T, hipStream_t);                                                  \
   template void launch_copy<T>(const T*, T*, size_t, hipStream_t);                                           \
   template void launch_inv<T>(const T*, T*, size_t, hipStream_t);                                            \
   template void launch_dot<T>(const T*, const T*, int, int, int, double*, double*, hipStream_t);             \
-  template void launch_pcg_update<T>(T*, T*, const T*, const T*, const double*, size_t, int, int,            \
-                                     hipStream_t);                                                           \
-  template void launch_pcg_direction<T>(T*, const T*, const double*, size_t, int, int, hipStream_t);         \
-  template void launch_gauge_shift<T>(T*, int, int, T*, hipStream_t);                                        \
-  template void launch_project<T>(T*, int, int, double*, double*, hipStream_t);                               \
+  template void launch_pcg_update<T>(T*, T*, const T*, const T*, const double*, int, int, int, hipStream_t);  \
+  template void launch_pcg_direction<T>(T*, const T*, const double*, int, int, int, hipStream_t);            \
+  template void launch_aos_to_soa<T, T>(const T*, T*, int, int, int, hipStream_t);                           \
+  template void launch_soa_to_aos<T, T>(const T*, T*, int, int, int, hipStream_t);                           \
+  template void launch_gauge_shift<T>(T*, int, int, int, T*, hipStream_t);                                   \
+  template void launch_project<T>(T*, int, int, int, double*, double*, hipStream_t);                          \
+  template void launch_colsum<T>(const T*, int, int, int, double*, double*, hipStream_t);                     \
+  template void launch_axpby<T>(T*, const T*, T, T, size_t, hipStream_t);                                    \
+  template void launch_scale_add_comp<T>(T*, const T*, T, const double*, int, int, int, hipStream_t);         \
+  template void launch_mul_nodewise<T>(T*, const T*, int, int, int, int, hipStream_t);                        \
   template void launch_accumulate<T>(double*, const T*, size_t, hipStream_t);                                \
   template void launch_diagonal<T>(const LevelView<T>&, int, int, T*, hipStream_t);
 
 GMT_INST_T(float)
 GMT_INST_T(double)
 template void launch_convert<double, float>(const double*, float*, size_t, hipStream_t);
+template void launch_aos_to_soa<double, float>(const double*, float*, int, int, int, hipStream_t);
+template void launch_aos_to_soa<float, double>(const float*, double*, int, int, int, hipStream_t);
+template void launch_soa_to_aos<double, float>(const double*, float*, int, int, int, hipStream_t);
+template void launch_soa_to_aos<float, double>(const float*, double*, int, int, int, hipStream_t);
 template void launch_convert<float, double>(const float*, double*, size_t, hipStream_t);
 template void launch_gram<double, double>(const double*, const double*, int, int, int, double*, double*,
                                           hipStream_t);

@@ -1,0 +1,706 @@
+// gfx950 kernels and host orchestration of the learned initializer: a sparse
+// 3D conv U-Net on the GMG hierarchy (see include/gmt.h, gmt_nn_*).
+//
+// All layers are "gather convolutions": out[i] = sum_t x[tab[i][t]] W[t] with
+// a per-level neighbour table tab (27 periodic neighbours on one level, the 27
+// fine nodes 2X + o_t of a coarse node for pooling, or the parents of a fine
+// node for unpooling; one identity tap for the pointwise head layers).
+// Activations are stored in BF16 (round to nearest even), weights are the BF16
+// rounding of the FP32 master weights, every sum is accumulated in FP32.
+// The backward pass uses the same gather kernel with transposed per-tap
+// weights and the inverse table (mirrored taps on one level, the unpooling
+// table for pooling and vice versa), and a node-chunked reduction for the
+// weight gradients.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace gmt {
+
+namespace {
+
+constexpr int kB = 256;
+constexpr float kSlope = 0.1f;
+
+template <typename T>
+using cp = const __attribute__((address_space(4))) T*;
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return 0x7FC0;  // NaN
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+template <typename T>
+__device__ __forceinline__ float ldf(const T* p);
+template <>
+__device__ __forceinline__ float ldf<float>(const float* p) {
+  return *p;
+}
+template <>
+__device__ __forceinline__ float ldf<uint16_t>(const uint16_t* p) {
+  return bf2f(*p);
+}
+
+template <typename T>
+__device__ __forceinline__ void stf(T* p, float v);
+template <>
+__device__ __forceinline__ void stf<float>(float* p, float v) {
+  *p = v;
+}
+template <>
+__device__ __forceinline__ void stf<uint16_t>(uint16_t* p, float v) {
+  *p = f2bf(v);
+}
+
+__device__ __forceinline__ int wrapi(int v, int N) { return v < 0 ? v + N : (v >= N ? v - N : v); }
+
+enum Flags { F_BIAS = 1, F_SKIP = 2, F_ACT = 4, F_SCALE = 8 };
+
+// out[i][co] = epilogue( sum_t sum_ci x[tab[i][t]][ci] W[t][ci][co] )
+template <typename Tin, typename Tout, int CIN, int COUT, int NTAP, int FLAGS>
+__global__ __launch_bounds__(kB) void k_gconv(int n, const int* __restrict__ tab, const Tin* __restrict__ x,
+                                               const float* __restrict__ W, const float* __restrict__ b,
+                                               const uint16_t* __restrict__ skip, float scale, Tout* __restrict__ y,
+                                               int zero) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  float acc[COUT];
+#pragma unroll
+  for (int co = 0; co < COUT; ++co) acc[co] = 0.f;
+#pragma unroll 1
+  for (int t = 0; t < NTAP; ++t) {
+    const int src = (NTAP == 1 && tab == nullptr) ? i : tab[(size_t)i * NTAP + t];
+    if (src < 0) continue;
+    float xin[CIN];
+#pragma unroll
+    for (int ci = 0; ci < CIN; ++ci) xin[ci] = ldf<Tin>(x + (size_t)src * CIN + ci);
+    // wave-uniform weights of tap t through the constant address space (scalar loads)
+    const cp<float> Wt = (cp<float>)(W + (size_t)(t + (t & zero)) * CIN * COUT);
+#pragma unroll
+    for (int ci = 0; ci < CIN; ++ci)
+#pragma unroll
+      for (int co = 0; co < COUT; ++co) acc[co] = fmaf(xin[ci], Wt[ci * COUT + co], acc[co]);
+  }
+#pragma unroll
+  for (int co = 0; co < COUT; ++co) {
+    float v = acc[co];
+    if constexpr (FLAGS & F_BIAS) v += b[co];
+    if constexpr (FLAGS & F_SKIP) v += bf2f(skip[(size_t)i * COUT + co]);
+    if constexpr (FLAGS & F_ACT) v = v > 0.f ? v : kSlope * v;
+    if constexpr (FLAGS & F_SCALE) v *= scale;
+    stf<Tout>(y + (size_t)i * COUT + co, v);
+  }
+}
+
+// dW[t][ci][co] += sum_i x[tab[i][t]][ci] g[i][co]; grid (node chunks, taps).
+constexpr int kWChunk = 64;
+template <typename Tin, int CIN, int COUT, int NTAP>
+__global__ __launch_bounds__(kB) void k_wgrad(int n, const int* __restrict__ tab, const Tin* __restrict__ x,
+                                               const float* __restrict__ g, float* __restrict__ dW,
+                                               int nodes_per_block) {
+  constexpr int P = CIN * COUT;
+  constexpr int PPT = (P + kB - 1) / kB;
+  __shared__ float xs[kWChunk][CIN];
+  __shared__ float gs[kWChunk][COUT];
+  const int t = blockIdx.y;
+  const int beg = blockIdx.x * nodes_per_block;
+  const int end = min(n, beg + nodes_per_block);
+  float acc[PPT];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) acc[k] = 0.f;
+  for (int base = beg; base < end; base += kWChunk) {
+    for (int e = threadIdx.x; e < kWChunk * CIN; e += kB) {
+      const int r = e / CIN, ci = e % CIN, node = base + r;
+      float v = 0.f;
+      if (node < end) {
+        const int src = (NTAP == 1 && tab == nullptr) ? node : tab[(size_t)node * NTAP + t];
+        if (src >= 0) v = ldf<Tin>(x + (size_t)src * CIN + ci);
+      }
+      xs[r][ci] = v;
+    }
+    for (int e = threadIdx.x; e < kWChunk * COUT; e += kB) {
+      const int r = e / COUT, co = e % COUT, node = base + r;
+      gs[r][co] = node < end ? g[(size_t)node * COUT + co] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const int p = threadIdx.x + k * kB;
+      if (p < P) {
+        const int ci = p / COUT, co = p % COUT;
+        float s = acc[k];
+#pragma unroll 8
+        for (int r = 0; r < kWChunk; ++r) s = fmaf(xs[r][ci], gs[r][co], s);
+        acc[k] = s;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int p = threadIdx.x + k * kB;
+    if (p < P) atomicAdd(dW + (size_t)t * P + p, acc[k]);
+  }
+}
+
+// db[co] += sum_i g[i][co]
+template <int COUT>
+__global__ __launch_bounds__(kB) void k_bgrad(int n, const float* __restrict__ g, float* __restrict__ db) {
+  __shared__ float sh[kB / 64][COUT];
+  float acc[COUT];
+#pragma unroll
+  for (int co = 0; co < COUT; ++co) acc[co] = 0.f;
+  for (int i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB)
+#pragma unroll
+    for (int co = 0; co < COUT; ++co) acc[co] += g[(size_t)i * COUT + co];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int co = 0; co < COUT; ++co) {
+    float v = acc[co];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if (lane == 0) sh[w][co] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < COUT) {
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < kB / 64; ++k) s += sh[k][threadIdx.x];
+    atomicAdd(db + threadIdx.x, s);
+  }
+}
+
+// g[i] *= act'(y[i]) from the stored (BF16) activation output
+__global__ void k_act_grad(size_t total, float* __restrict__ g, const uint16_t* __restrict__ y) {
+  const size_t i = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (i < total) g[i] *= bf2f(y[i]) > 0.f ? 1.f : kSlope;
+}
+
+__global__ void k_add(size_t total, float* __restrict__ a, const float* __restrict__ b) {
+  const size_t i = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (i < total) a[i] += b[i];
+}
+
+__global__ void k_zero(size_t total, float* __restrict__ a) {
+  const size_t i = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (i < total) a[i] = 0.f;
+}
+
+__global__ void k_round_bf16(size_t total, const float* __restrict__ a, float* __restrict__ b) {
+  const size_t i = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (i < total) b[i] = bf2f(f2bf(a[i]));
+}
+
+// Wt[t'][co][ci] = W[perm(t)][ci][co] with perm(t) = mirror ? NTAP-1-t : t
+__global__ void k_transpose_taps(int ntap, int cin, int cout, int mirror, const float* __restrict__ W,
+                                 float* __restrict__ Wt) {
+  const size_t e = (size_t)blockIdx.x * kB + threadIdx.x;
+  const size_t per = (size_t)cin * cout;
+  if (e >= (size_t)ntap * per) return;
+  const int t = (int)(e / per);
+  const int r = (int)(e % per);
+  const int co = r / cin, ci = r % cin;  // Wt[t][co][ci]
+  const int ts = mirror ? ntap - 1 - t : t;
+  Wt[e] = W[(size_t)ts * per + (size_t)ci * cout + co];
+}
+
+__global__ void k_embed(int n, const uint8_t* __restrict__ occ8, const float* __restrict__ E, int C,
+                        uint16_t* __restrict__ y) {
+  const size_t e = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (e >= (size_t)n * C) return;
+  const size_t i = e / C;
+  const int c = (int)(e % C);
+  y[e] = f2bf(E[(size_t)occ8[i] * C + c]);
+}
+
+// dE[occ][c] += g[i][c]: per-block histogram in LDS, then one atomic per entry
+template <int C>
+__global__ __launch_bounds__(kB) void k_embed_grad(int n, const uint8_t* __restrict__ occ8, const float* __restrict__ g,
+                                                   float* __restrict__ dE) {
+  __shared__ float hist[256 * C];
+  for (int e = threadIdx.x; e < 256 * C; e += kB) hist[e] = 0.f;
+  __syncthreads();
+  for (int i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB) {
+    const int o = occ8[i];
+#pragma unroll
+    for (int c = 0; c < C; ++c) atomicAdd(&hist[o * C + c], g[(size_t)i * C + c]);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 256 * C; e += kB)
+    if (hist[e] != 0.f) atomicAdd(dE + e, hist[e]);
+}
+
+// tables ----------------------------------------------------------------------
+
+// tab[i][t] = id of node x_i + o_t on the same level (periodic), -1 if inactive
+__global__ void k_conv_table(int n, const int* __restrict__ node_lin, const int* __restrict__ map, int N,
+                             int* __restrict__ tab) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const int lin = node_lin[i];
+  const int x = lin % N, y = (lin / N) % N, z = lin / (N * N);
+  for (int t = 0; t < 27; ++t) {
+    const int ox = t % 3 - 1, oy = (t / 3) % 3 - 1, oz = t / 9 - 1;
+    tab[(size_t)i * 27 + t] = map[wrapi(x + ox, N) + N * (wrapi(y + oy, N) + N * wrapi(z + oz, N))];
+  }
+}
+
+// coarse node X: tab[X][t] = fine node 2X + o_t (periodic), -1 if inactive
+__global__ void k_pool_table(int nc, const int* __restrict__ cnode_lin, int Nc, const int* __restrict__ fmap,
+                             int* __restrict__ tab) {
+  const int X = blockIdx.x * kB + threadIdx.x;
+  if (X >= nc) return;
+  const int Nf = 2 * Nc;
+  const int lin = cnode_lin[X];
+  const int x = lin % Nc, y = (lin / Nc) % Nc, z = lin / (Nc * Nc);
+  for (int t = 0; t < 27; ++t) {
+    const int ox = t % 3 - 1, oy = (t / 3) % 3 - 1, oz = t / 9 - 1;
+    tab[(size_t)X * 27 + t] =
+        fmap[wrapi(2 * x + ox, Nf) + Nf * (wrapi(2 * y + oy, Nf) + Nf * wrapi(2 * z + oz, Nf))];
+  }
+}
+
+// fine node i: tab[i][t] = coarse X with 2X + o_t = x_i (periodic), -1 if none
+__global__ void k_unpool_table(int nf, const int* __restrict__ fnode_lin, int Nf, const int* __restrict__ cmap,
+                               int* __restrict__ tab) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= nf) return;
+  const int Nc = Nf / 2;
+  const int lin = fnode_lin[i];
+  const int x = lin % Nf, y = (lin / Nf) % Nf, z = lin / (Nf * Nf);
+  for (int t = 0; t < 27; ++t) {
+    const int px = wrapi(x - (t % 3 - 1), Nf), py = wrapi(y - ((t / 3) % 3 - 1), Nf), pz = wrapi(z - (t / 9 - 1), Nf);
+    int id = -1;
+    if (!(px & 1) && !(py & 1) && !(pz & 1)) id = cmap[(px >> 1) + Nc * ((py >> 1) + Nc * (pz >> 1))];
+    tab[(size_t)i * 27 + t] = id;
+  }
+}
+
+// AdamW on the FP32 master weights (decoupled weight decay on every parameter)
+__global__ void k_adamw(size_t total, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                        float* __restrict__ v, float lr, float b1, float b2, float eps, float wd, float c1, float c2,
+                        float gscale) {
+  const size_t i = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (i >= total) return;
+  const float gi = g[i] * gscale;
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] = p[i] * (1.f - lr * wd) - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ __launch_bounds__(kB) void k_norm2(const float* __restrict__ x, size_t n, double* __restrict__ partial) {
+  __shared__ double sh[kB / 64];
+  double v = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kB + threadIdx.x; i < n; i += (size_t)gridDim.x * kB) v += (double)x[i] * x[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < kB / 64; ++k) s += sh[k];
+    partial[blockIdx.x] = s;
+  }
+}
+
+__global__ void k_ema(float* __restrict__ e, const float* __restrict__ x, size_t n, float decay) {
+  const size_t i = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (i < n) e[i] = decay * e[i] + (1.f - decay) * x[i];
+}
+
+inline unsigned nblk(size_t n) { return (unsigned)((n + kB - 1) / kB); }
+
+}  // namespace
+
+// ============================================================================ launchers
+
+template <typename Tin, typename Tout, int FLAGS>
+static void gconv_dispatch(int cin, int cout, int ntap, int n, const int* tab, const void* x, const float* W,
+                           const float* b, const uint16_t* skip, float scale, void* y, hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned g = nblk(n);
+#define GC(CI, CO, NT)                                                                                       \
+  if (cin == CI && cout == CO && ntap == NT) {                                                              \
+    hipLaunchKernelGGL((k_gconv<Tin, Tout, CI, CO, NT, FLAGS>), dim3(g), dim3(kB), 0, s, n, tab, (const Tin*)x, \
+                       W, b, skip, scale, (Tout*)y, 0);                                                      \
+    GMT_LAUNCH_CHECK();                                                                                      \
+    return;                                                                                                  \
+  }
+  GC(16, 16, 27) GC(32, 32, 27) GC(64, 64, 27) GC(16, 32, 27) GC(32, 64, 27) GC(32, 16, 27) GC(64, 32, 27)
+  GC(16, 32, 1) GC(32, 32, 1) GC(64, 32, 1) GC(32, 18, 1) GC(32, 3, 1)
+  GC(32, 16, 1) GC(32, 64, 1) GC(18, 32, 1) GC(3, 32, 1)
+#undef GC
+  fail(GMT_E_INVAL, "gather conv (%d -> %d, %d taps) not instantiated", cin, cout, ntap);
+}
+
+template <typename Tin>
+static void wgrad_dispatch(int cin, int cout, int ntap, int n, const int* tab, const void* x, const float* g,
+                           float* dW, hipStream_t s) {
+  if (n <= 0) return;
+  const int per_block = 1024;
+  const dim3 grid((unsigned)((n + per_block - 1) / per_block), (unsigned)ntap);
+#define WG(CI, CO, NT)                                                                                     \
+  if (cin == CI && cout == CO && ntap == NT) {                                                            \
+    hipLaunchKernelGGL((k_wgrad<Tin, CI, CO, NT>), grid, dim3(kB), 0, s, n, tab, (const Tin*)x, g, dW, per_block); \
+    GMT_LAUNCH_CHECK();                                                                                    \
+    return;                                                                                                \
+  }
+  WG(16, 16, 27) WG(32, 32, 27) WG(64, 64, 27) WG(16, 32, 27) WG(32, 64, 27) WG(32, 16, 27) WG(64, 32, 27)
+  WG(16, 32, 1) WG(32, 32, 1) WG(64, 32, 1) WG(32, 18, 1) WG(32, 3, 1)
+#undef WG
+  fail(GMT_E_INVAL, "weight gradient (%d -> %d, %d taps) not instantiated", cin, cout, ntap);
+}
+
+static void bgrad_dispatch(int cout, int n, const float* g, float* db, hipStream_t s) {
+  if (n <= 0) return;
+  unsigned grid = nblk(n);
+  if (grid > 1024) grid = 1024;
+#define BG(CO)                                                                 \
+  if (cout == CO) {                                                            \
+    hipLaunchKernelGGL(k_bgrad<CO>, dim3(grid), dim3(kB), 0, s, n, g, db);     \
+    GMT_LAUNCH_CHECK();                                                        \
+    return;                                                                    \
+  }
+  BG(16) BG(32) BG(64) BG(18) BG(3)
+#undef BG
+  fail(GMT_E_INVAL, "bias gradient of width %d not instantiated", cout);
+}
+
+// ============================================================================ network
+
+// Parameter layout (flat FP32), in this order -- identical to the reference:
+//   E [256][C0]
+//   for l < L:      We_l [27][C_l][C_l], be_l [C_l]
+//   for l < L-1:    Wp_l [27][C_l][C_{l+1}], bp_l [C_{l+1}]
+//                   Wu_l [27][C_{l+1}][C_l], bu_l [C_l]
+//                   Wd_l [27][C_l][C_l],     bd_l [C_l]
+//                   W1_l [C_l][H], b1_l [H], W2_l [H][H], b2_l [H], W3_l [H][q], b3_l [q]
+struct NetLayout {
+  int L = 0, H = 0, q = 0;
+  int C[GMT_NN_MAX_LEVELS] = {0};
+  size_t E = 0, We[GMT_NN_MAX_LEVELS], be[GMT_NN_MAX_LEVELS];
+  size_t Wp[GMT_NN_MAX_LEVELS], bp[GMT_NN_MAX_LEVELS], Wu[GMT_NN_MAX_LEVELS], bu[GMT_NN_MAX_LEVELS];
+  size_t Wd[GMT_NN_MAX_LEVELS], bd[GMT_NN_MAX_LEVELS];
+  size_t W1[GMT_NN_MAX_LEVELS], b1[GMT_NN_MAX_LEVELS], W2[GMT_NN_MAX_LEVELS], b2[GMT_NN_MAX_LEVELS];
+  size_t W3[GMT_NN_MAX_LEVELS], b3[GMT_NN_MAX_LEVELS];
+  size_t total = 0;
+};
+
+static NetLayout make_layout(const gmt_nn_config& cfg, int q) {
+  NetLayout nl;
+  nl.L = cfg.levels;
+  nl.H = cfg.head;
+  nl.q = q;
+  for (int l = 0; l < nl.L; ++l) nl.C[l] = cfg.channels[l];
+  size_t o = 0;
+  auto take = [&](size_t n) {
+    const size_t r = o;
+    o += n;
+    return r;
+  };
+  const int* C = nl.C;
+  nl.E = take((size_t)256 * C[0]);
+  for (int l = 0; l < nl.L; ++l) {
+    nl.We[l] = take((size_t)27 * C[l] * C[l]);
+    nl.be[l] = take(C[l]);
+  }
+  for (int l = 0; l + 1 < nl.L; ++l) {
+    nl.Wp[l] = take((size_t)27 * C[l] * C[l + 1]);
+    nl.bp[l] = take(C[l + 1]);
+    nl.Wu[l] = take((size_t)27 * C[l + 1] * C[l]);
+    nl.bu[l] = take(C[l]);
+    nl.Wd[l] = take((size_t)27 * C[l] * C[l]);
+    nl.bd[l] = take(C[l]);
+    nl.W1[l] = take((size_t)C[l] * nl.H);
+    nl.b1[l] = take(nl.H);
+    nl.W2[l] = take((size_t)nl.H * nl.H);
+    nl.b2[l] = take(nl.H);
+    nl.W3[l] = take((size_t)nl.H * q);
+    nl.b3[l] = take(q);
+  }
+  nl.total = o;
+  return nl;
+}
+
+struct NNState {
+  NetLayout nl;
+  std::vector<int*> conv, pool, unpool;                  // neighbour tables
+  std::vector<uint16_t*> h, a, t, d, z1, z2;             // BF16 activations
+  float* Wb = nullptr;                                   // BF16-rounded weights (FP32 storage)
+  float* Wt = nullptr;                                   // transposed weights of one layer
+  float *g0 = nullptr, *g1 = nullptr, *g2 = nullptr;     // FP32 gradient scratch (max n_l * max C)
+  std::vector<float*> gd;                                // dL/dd_l accumulators
+  std::vector<float*> ga;                                // dL/da_l accumulators
+};
+
+static NNState& nn_state(Hier& h) {
+  if (!h.nn) fail(GMT_E_STATE, "gmt_nn_setup has not been called for this hierarchy");
+  return *reinterpret_cast<NNState*>(h.nn);
+}
+
+void nn_release(Hier& h) {
+  delete reinterpret_cast<NNState*>(h.nn);
+  h.nn = nullptr;
+}
+
+void nn_setup(Hier& h, const gmt_nn_config& cfg, hipStream_t s) {
+  if (cfg.levels != h.L) fail(GMT_E_INVAL, "network levels (%d) must equal the hierarchy's (%d)", cfg.levels, h.L);
+  if (h.L < 2 || h.L > GMT_NN_MAX_LEVELS) fail(GMT_E_INVAL, "network needs 2..%d levels", GMT_NN_MAX_LEVELS);
+  for (int l = 0; l < h.L; ++l)
+    if (cfg.channels[l] != 16 && cfg.channels[l] != 32 && cfg.channels[l] != 64)
+      fail(GMT_E_INVAL, "channels must be 16, 32 or 64");
+  if (cfg.head != 32) fail(GMT_E_INVAL, "head width must be 32");
+  if (h.nn) nn_release(h);
+  NNState* S = new NNState();
+  h.nn = S;
+  S->nl = make_layout(cfg, h.Q);
+  const int L = h.L;
+  size_t maxnc = 0;
+  S->conv.resize(L);
+  S->pool.assign(L, nullptr);
+  S->unpool.assign(L, nullptr);
+  S->h.resize(L);
+  S->a.resize(L);
+  S->t.assign(L, nullptr);
+  S->d.assign(L, nullptr);
+  S->z1.assign(L, nullptr);
+  S->z2.assign(L, nullptr);
+  S->gd.assign(L, nullptr);
+  S->ga.assign(L, nullptr);
+  for (int l = 0; l < L; ++l) {
+    const LevelData& d = h.lv[l];
+    const int C = S->nl.C[l];
+    maxnc = std::max(maxnc, (size_t)d.n_n * std::max(C, std::max(S->nl.H, h.Q)));
+    S->conv[l] = h.alloc<int>((size_t)d.n_n * 27);
+    hipLaunchKernelGGL(k_conv_table, dim3(nblk(d.n_n)), dim3(kB), 0, s, d.n_n, d.node_lin, d.node_map, d.N,
+                       S->conv[l]);
+    GMT_LAUNCH_CHECK();
+    S->h[l] = h.alloc<uint16_t>((size_t)d.n_n * C);
+    S->a[l] = h.alloc<uint16_t>((size_t)d.n_n * C);
+    S->ga[l] = h.alloc<float>((size_t)d.n_n * C);
+    if (l + 1 < L) {
+      const LevelData& c = h.lv[l + 1];
+      S->pool[l] = h.alloc<int>((size_t)c.n_n * 27);
+      hipLaunchKernelGGL(k_pool_table, dim3(nblk(c.n_n)), dim3(kB), 0, s, c.n_n, c.node_lin, c.N, d.node_map,
+                         S->pool[l]);
+      GMT_LAUNCH_CHECK();
+      S->unpool[l] = h.alloc<int>((size_t)d.n_n * 27);
+      hipLaunchKernelGGL(k_unpool_table, dim3(nblk(d.n_n)), dim3(kB), 0, s, d.n_n, d.node_lin, d.N, c.node_map,
+                         S->unpool[l]);
+      GMT_LAUNCH_CHECK();
+      S->t[l] = h.alloc<uint16_t>((size_t)d.n_n * C);
+      S->d[l] = h.alloc<uint16_t>((size_t)d.n_n * C);
+      S->z1[l] = h.alloc<uint16_t>((size_t)d.n_n * S->nl.H);
+      S->z2[l] = h.alloc<uint16_t>((size_t)d.n_n * S->nl.H);
+    }
+    S->gd[l] = h.alloc<float>((size_t)d.n_n * C);
+  }
+  S->Wb = h.alloc<float>(S->nl.total);
+  size_t maxw = 0;
+  for (int l = 0; l < L; ++l) maxw = std::max(maxw, (size_t)27 * 64 * 64);
+  S->Wt = h.alloc<float>(maxw);
+  S->g0 = h.alloc<float>(maxnc);
+  S->g1 = h.alloc<float>(maxnc);
+  S->g2 = h.alloc<float>(maxnc);
+  GMT_HIP(hipStreamSynchronize(s));
+}
+
+size_t nn_param_count(const gmt_nn_config& cfg, int q) { return make_layout(cfg, q).total; }
+
+// out[l]: level l (0-based, l < L-1) prediction [n_l][q] FP32 (u_hat^1 for l = 0, e_hat^{l+1} otherwise)
+void nn_forward(Hier& h, const float* params, float* const* out, hipStream_t s) {
+  NNState& S = nn_state(h);
+  const NetLayout& N = S.nl;
+  const int L = N.L;
+  hipLaunchKernelGGL(k_round_bf16, dim3(nblk(N.total)), dim3(kB), 0, s, N.total, params, S.Wb);
+  GMT_LAUNCH_CHECK();
+  const float* W = S.Wb;
+  const int n0 = h.lv[0].n_n;
+  hipLaunchKernelGGL(k_embed, dim3(nblk((size_t)n0 * N.C[0])), dim3(kB), 0, s, n0, h.lv[0].occ8, W + N.E, N.C[0],
+                     S.h[0]);
+  GMT_LAUNCH_CHECK();
+  for (int l = 0; l < L; ++l) {
+    const int n = h.lv[l].n_n, C = N.C[l];
+    gconv_dispatch<uint16_t, uint16_t, F_BIAS | F_ACT>(C, C, 27, n, S.conv[l], S.h[l], W + N.We[l], W + N.be[l],
+                                                       nullptr, 1.f, S.a[l], s);
+    if (l + 1 < L)
+      gconv_dispatch<uint16_t, uint16_t, F_BIAS | F_ACT>(C, N.C[l + 1], 27, h.lv[l + 1].n_n, S.pool[l], S.a[l],
+                                                         W + N.Wp[l], W + N.bp[l], nullptr, 1.f, S.h[l + 1], s);
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    const int n = h.lv[l].n_n, C = N.C[l];
+    const uint16_t* dn = l + 1 == L - 1 ? S.a[L - 1] : S.d[l + 1];
+    gconv_dispatch<uint16_t, uint16_t, F_BIAS | F_SKIP | F_ACT>(N.C[l + 1], C, 27, n, S.unpool[l], dn, W + N.Wu[l],
+                                                                W + N.bu[l], S.a[l], 1.f, S.t[l], s);
+    gconv_dispatch<uint16_t, uint16_t, F_BIAS | F_ACT>(C, C, 27, n, S.conv[l], S.t[l], W + N.Wd[l], W + N.bd[l],
+                                                       nullptr, 1.f, S.d[l], s);
+    gconv_dispatch<uint16_t, uint16_t, F_BIAS | F_ACT>(C, N.H, 1, n, nullptr, S.d[l], W + N.W1[l], W + N.b1[l],
+                                                       nullptr, 1.f, S.z1[l], s);
+    gconv_dispatch<uint16_t, uint16_t, F_BIAS | F_ACT>(N.H, N.H, 1, n, nullptr, S.z1[l], W + N.W2[l], W + N.b2[l],
+                                                       nullptr, 1.f, S.z2[l], s);
+    if (out[l])
+      gconv_dispatch<uint16_t, float, F_BIAS | F_SCALE>(N.H, N.q, 1, n, nullptr, S.z2[l], W + N.W3[l], W + N.b3[l],
+                                                        nullptr, (float)h.N, out[l], s);
+  }
+}
+
+static void transpose_taps(NNState& S, const float* W, int ntap, int cin, int cout, bool mirror, hipStream_t s) {
+  const size_t tot = (size_t)ntap * cin * cout;
+  hipLaunchKernelGGL(k_transpose_taps, dim3(nblk(tot)), dim3(kB), 0, s, ntap, cin, cout, mirror ? 1 : 0, W, S.Wt);
+  GMT_LAUNCH_CHECK();
+}
+
+static void act_grad(float* g, const uint16_t* y, size_t tot, hipStream_t s) {
+  if (!tot) return;
+  hipLaunchKernelGGL(k_act_grad, dim3(nblk(tot)), dim3(kB), 0, s, tot, g, y);
+  GMT_LAUNCH_CHECK();
+}
+
+static void addv(float* a, const float* b, size_t tot, hipStream_t s) {
+  if (!tot) return;
+  hipLaunchKernelGGL(k_add, dim3(nblk(tot)), dim3(kB), 0, s, tot, a, b);
+  GMT_LAUNCH_CHECK();
+}
+
+static void zerov(float* a, size_t tot, hipStream_t s) {
+  if (!tot) return;
+  hipLaunchKernelGGL(k_zero, dim3(nblk(tot)), dim3(kB), 0, s, tot, a);
+  GMT_LAUNCH_CHECK();
+}
+
+__global__ void k_scale_copy(size_t total, const float* __restrict__ a, float sc, float* __restrict__ b) {
+  const size_t i = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (i < total) b[i] = sc * a[i];
+}
+
+// y = gather-conv of an FP32 gradient with the transposed per-tap weights held in S.Wt
+static void dgrad(NNState& S, int cin, int cout, int ntap, int n_out, const int* tab, const float* g, float* y,
+                  hipStream_t s) {
+  gconv_dispatch<float, float, 0>(cin, cout, ntap, n_out, tab, g, S.Wt, nullptr, nullptr, 1.f, y, s);
+}
+
+// grad += d/dparams sum_l <gout[l], out[l]> (activations of the last forward)
+void nn_backward(Hier& h, const float* const* gout, float* grad, hipStream_t s) {
+  NNState& S = nn_state(h);
+  const NetLayout& N = S.nl;
+  const int L = N.L, H = N.H, q = N.q;
+  const float* W = S.Wb;
+  for (int l = 0; l < L; ++l) zerov(S.gd[l], (size_t)h.lv[l].n_n * N.C[l], s);
+  // heads: out = N (z2 W3 + b3), z2 = act(z1 W2 + b2), z1 = act(d W1 + b1)
+  for (int l = 0; l + 1 < L; ++l) {
+    if (!gout[l]) continue;
+    const int n = h.lv[l].n_n, C = N.C[l];
+    const size_t tq = (size_t)n * q;
+    hipLaunchKernelGGL(k_scale_copy, dim3(nblk(tq)), dim3(kB), 0, s, tq, gout[l], (float)h.N, S.g2);
+    GMT_LAUNCH_CHECK();
+    wgrad_dispatch<uint16_t>(H, q, 1, n, nullptr, S.z2[l], S.g2, grad + N.W3[l], s);
+    bgrad_dispatch(q, n, S.g2, grad + N.b3[l], s);
+    transpose_taps(S, W + N.W3[l], 1, H, q, false, s);
+    dgrad(S, q, H, 1, n, nullptr, S.g2, S.g0, s);
+    act_grad(S.g0, S.z2[l], (size_t)n * H, s);
+    wgrad_dispatch<uint16_t>(H, H, 1, n, nullptr, S.z1[l], S.g0, grad + N.W2[l], s);
+    bgrad_dispatch(H, n, S.g0, grad + N.b2[l], s);
+    transpose_taps(S, W + N.W2[l], 1, H, H, false, s);
+    dgrad(S, H, H, 1, n, nullptr, S.g0, S.g1, s);
+    act_grad(S.g1, S.z1[l], (size_t)n * H, s);
+    wgrad_dispatch<uint16_t>(C, H, 1, n, nullptr, S.d[l], S.g1, grad + N.W1[l], s);
+    bgrad_dispatch(H, n, S.g1, grad + N.b1[l], s);
+    transpose_taps(S, W + N.W1[l], 1, C, H, false, s);
+    dgrad(S, H, C, 1, n, nullptr, S.g1, S.g2, s);
+    addv(S.gd[l], S.g2, (size_t)n * C, s);
+  }
+  // decoder, finest first: d_l = act(conv(t_l) + bd), t_l = act(unpool(d_{l+1}) + bu + a_l)
+  for (int l = 0; l + 1 < L; ++l) {
+    const int n = h.lv[l].n_n, C = N.C[l], Cn = N.C[l + 1], nn = h.lv[l + 1].n_n;
+    const size_t tc = (size_t)n * C;
+    GMT_HIP(hipMemcpyAsync(S.g0, S.gd[l], tc * sizeof(float), hipMemcpyDeviceToDevice, s));
+    act_grad(S.g0, S.d[l], tc, s);
+    wgrad_dispatch<uint16_t>(C, C, 27, n, S.conv[l], S.t[l], S.g0, grad + N.Wd[l], s);
+    bgrad_dispatch(C, n, S.g0, grad + N.bd[l], s);
+    transpose_taps(S, W + N.Wd[l], 27, C, C, true, s);
+    dgrad(S, C, C, 27, n, S.conv[l], S.g0, S.g1, s);
+    act_grad(S.g1, S.t[l], tc, s);
+    // skip path into a_l, bias bu
+    GMT_HIP(hipMemcpyAsync(S.ga[l], S.g1, tc * sizeof(float), hipMemcpyDeviceToDevice, s));
+    bgrad_dispatch(C, n, S.g1, grad + N.bu[l], s);
+    const uint16_t* dn = l + 1 == L - 1 ? S.a[L - 1] : S.d[l + 1];
+    wgrad_dispatch<uint16_t>(Cn, C, 27, n, S.unpool[l], dn, S.g1, grad + N.Wu[l], s);
+    transpose_taps(S, W + N.Wu[l], 27, Cn, C, false, s);
+    dgrad(S, C, Cn, 27, nn, S.pool[l], S.g1, S.g2, s);
+    addv(S.gd[l + 1], S.g2, (size_t)nn * Cn, s);
+  }
+  // a_{L-1} = d_{L-1}
+  GMT_HIP(hipMemcpyAsync(S.ga[L - 1], S.gd[L - 1], (size_t)h.lv[L - 1].n_n * N.C[L - 1] * sizeof(float),
+                         hipMemcpyDeviceToDevice, s));
+  // encoder, coarsest first: a_l = act(conv(h_l) + be), h_{l+1} = act(pool(a_l) + bp)
+  for (int l = L - 1; l >= 0; --l) {
+    const int n = h.lv[l].n_n, C = N.C[l];
+    const size_t tc = (size_t)n * C;
+    GMT_HIP(hipMemcpyAsync(S.g0, S.ga[l], tc * sizeof(float), hipMemcpyDeviceToDevice, s));
+    act_grad(S.g0, S.a[l], tc, s);
+    wgrad_dispatch<uint16_t>(C, C, 27, n, S.conv[l], S.h[l], S.g0, grad + N.We[l], s);
+    bgrad_dispatch(C, n, S.g0, grad + N.be[l], s);
+    transpose_taps(S, W + N.We[l], 27, C, C, true, s);
+    dgrad(S, C, C, 27, n, S.conv[l], S.g0, S.g1, s);
+    if (l > 0) {
+      const int Cp = N.C[l - 1], np = h.lv[l - 1].n_n;
+      act_grad(S.g1, S.h[l], tc, s);
+      wgrad_dispatch<uint16_t>(Cp, C, 27, n, S.pool[l - 1], S.a[l - 1], S.g1, grad + N.Wp[l - 1], s);
+      bgrad_dispatch(C, n, S.g1, grad + N.bp[l - 1], s);
+      transpose_taps(S, W + N.Wp[l - 1], 27, Cp, C, false, s);
+      dgrad(S, C, Cp, 27, np, S.unpool[l - 1], S.g1, S.g2, s);
+      addv(S.ga[l - 1], S.g2, (size_t)np * Cp, s);
+    } else {
+      const int n0 = h.lv[0].n_n;
+      unsigned grid = nblk(n0);
+      if (grid > 512) grid = 512;
+      if (C == 16) hipLaunchKernelGGL(k_embed_grad<16>, dim3(grid), dim3(kB), 0, s, n0, h.lv[0].occ8, S.g1, grad + N.E);
+      else if (C == 32) hipLaunchKernelGGL(k_embed_grad<32>, dim3(grid), dim3(kB), 0, s, n0, h.lv[0].occ8, S.g1, grad + N.E);
+      else fail(GMT_E_INVAL, "embedding width %d not instantiated", C);
+      GMT_LAUNCH_CHECK();
+    }
+  }
+}
+
+double nn_norm2(Hier* h, const float* x, size_t n, hipStream_t s) {
+  (void)h;
+  const unsigned g = 256;
+  double* partial = nullptr;
+  GMT_HIP(hipMallocAsync((void**)&partial, g * sizeof(double), s));
+  hipLaunchKernelGGL(k_norm2, dim3(g), dim3(kB), 0, s, x, n, partial);
+  GMT_LAUNCH_CHECK();
+  double hp[256];
+  GMT_HIP(hipMemcpyAsync(hp, partial, g * sizeof(double), hipMemcpyDeviceToHost, s));
+  GMT_HIP(hipFreeAsync(partial, s));
+  GMT_HIP(hipStreamSynchronize(s));
+  double sum = 0.0;
+  for (unsigned k = 0; k < g; ++k) sum += hp[k];
+  return sum;
+}
+
+void nn_ema(float* e, const float* x, size_t n, double decay, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_ema, dim3(nblk(n)), dim3(kB), 0, s, e, x, n, (float)decay);
+  GMT_LAUNCH_CHECK();
+}
+
+void nn_adamw(float* p, const float* g, float* m, float* v, size_t n, double lr, double b1, double b2, double eps,
+              double wd, int step, double gscale, hipStream_t s) {
+  if (!n) return;
+  const float c1 = (float)(1.0 - std::pow(b1, step)), c2 = (float)(1.0 - std::pow(b2, step));
+  hipLaunchKernelGGL(k_adamw, dim3(nblk(n)), dim3(kB), 0, s, n, p, g, m, v, (float)lr, (float)b1, (float)b2, (float)eps,
+                     (float)wd, c1, c2, (float)gscale);
+  GMT_LAUNCH_CHECK();
+}
+
+}  // namespace gmt

@@ -1,0 +1,111 @@
+"""Learned initializer: training loop and the learned solve path.
+
+Sequencing only: the network forward/backward, the V-cycle, the physics loss
+and its adjoint, AdamW and the solver all run in libgmt (gmt_nn_*,
+gmt_vcycle_loss, gmt_vcycle, gmt_solve).
+
+Learned solve (Alg. 2 + fallback): predictions u_hat^1, e_hat^l -> one V-cycle
+-> FP64 residual check -> if above tol, warm-started GMG-PCG from the
+V-cycle result (never a restart from zero).
+"""
+
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+DEFAULT_CHANNELS = (16, 32, 64, 64, 64, 64, 64, 64)
+
+
+def channels_for(levels: int):
+    return list(DEFAULT_CHANNELS[:levels])
+
+
+def init_params(n_params: int, levels: int, physics: str = "elastic", seed: int = 0, device="cuda"):
+    """He-style uniform initialisation with the oracle's parameter order (small last head layer)."""
+    from math import sqrt
+    q = 18 if physics == "elastic" else 3
+    C = channels_for(levels)
+    H = 32
+    shapes = [("E", (256, C[0]))]
+    for l in range(levels):
+        shapes += [("We", (27, C[l], C[l])), ("b", (C[l],))]
+    for l in range(levels - 1):
+        shapes += [("Wp", (27, C[l], C[l + 1])), ("b", (C[l + 1],)), ("Wu", (27, C[l + 1], C[l])), ("b", (C[l],)),
+                   ("Wd", (27, C[l], C[l])), ("b", (C[l],)), ("W1", (C[l], H)), ("b", (H,)), ("W2", (H, H)),
+                   ("b", (H,)), ("W3", (H, q)), ("b", (q,))]
+    g = torch.Generator().manual_seed(seed)
+    parts = []
+    for name, sh in shapes:
+        n = int(np.prod(sh))
+        if name == "b":
+            parts.append(torch.zeros(n))
+            continue
+        fan_in = 1 if name == "E" else (sh[0] * sh[1] if len(sh) == 3 else sh[0])
+        bound = sqrt(3.0 / fan_in) * (0.1 if name == "W3" else 1.0)
+        parts.append((torch.rand(n, generator=g) * 2 - 1) * bound)
+    flat = torch.cat(parts)
+    assert flat.numel() == n_params, (flat.numel(), n_params)
+    return flat.to(device=device, dtype=torch.float32).contiguous()
+
+
+class Trainer:
+    """AdamW on FP32 master weights with a cosine schedule, global-norm clipping and an EMA copy."""
+
+    def __init__(self, n_params, levels, physics="elastic", lr=1e-3, wd=1e-2, clip=1.0, ema=0.999, seed=0,
+                 lam=1e-2, device="cuda"):
+        self.params = init_params(n_params, levels, physics, seed, device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.ema = self.params.clone()
+        self.lr, self.wd, self.clip, self.ema_decay = lr, wd, clip, ema
+        self.lam = lam
+        self.step = 0
+
+    def lr_at(self, k, total):
+        return self.lr * 0.5 * (1 + math.cos(math.pi * min(k, total) / max(total, 1)))
+
+    def train_cell(self, H: B.Hierarchy, total_steps: int, inject: bool = True):
+        """One optimisation step on one cell; returns (loss, ||r||, max relative residual)."""
+        preds = H.nn_forward(self.params)
+        if not inject:
+            preds = preds[:1]
+        lr = self.lr_at(self.step, total_steps)
+        # gauge penalty lambda (sum_i u_i)^2 with lambda = lam * lr / n^2, i.e. on the per-component mean
+        loss, rn, rel, _, grads = H.vcycle_loss(preds, lam=self.lam * lr / float(H.n_n(1)) ** 2)
+        self.grad.zero_()  # memory fill
+        H.nn_backward(grads + [None] * (H.L - 1 - len(grads)), self.grad)
+        gn = math.sqrt(B.norm2(self.grad))
+        scale = min(1.0, self.clip / gn) if gn > 0 and math.isfinite(gn) else 0.0
+        self.step += 1
+        B.adamw(self.params, self.grad, self.m, self.v, lr, self.step, wd=self.wd, grad_scale=scale)
+        B.ema(self.ema, self.params, self.ema_decay)
+        return loss, rn, float(np.max(rel))
+
+
+def learned_solve(H: B.Hierarchy, params, tol=1e-5, inject=True, max_iter=3000, f64=None):
+    """u_hat -> one Alg. 2 V-cycle -> FP64 check -> warm GMG-PCG fallback. Returns (u, info)."""
+    f64 = H.load_vector() if f64 is None else f64
+    f32 = f64.to(torch.float32)
+    preds = H.nn_forward(params)
+    u = preds[0]
+    e = [None] + (list(preds[1:]) if inject else [None] * (H.L - 2)) + [None]
+    H.vcycle(f32, u, e_init=e)
+    u64 = u.to(torch.float64)
+    u64, rep = H.solve(f64, u=u64, tol=tol, precision="f32", max_iter=max_iter)
+    return u64, {"rel_after_vcycle": max(rep["rel_res_init"]), "iterations": rep["iterations"],
+                 "converged": rep["converged"], "fallback": rep["iterations"] > 0}
+
+
+def timed(fn):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t
