@@ -235,6 +235,14 @@ gmt_status gmt_nn_forward(gmt_hier_t h, const float* d_params, float* const* d_o
  * (same indexing as gmt_nn_forward; NULL entries contribute nothing). */
 gmt_status gmt_nn_backward(gmt_hier_t h, const float* const* d_gout, float* d_grad, void* stream);
 
+/* Inspection of the last forward: copies one stored BF16 activation of
+ * level l (1..L), widened to FP32 [n_l][width], into d_out.  which: 0 = h
+ * (encoder input), 1 = a (encoder output), 2 = t (decoder merge), 3 = d
+ * (decoder output), 4 = z1, 5 = z2 (head hidden layers); 2..5 exist for
+ * l < L only.  h_width receives the row width (C_l, or the head width). */
+gmt_status gmt_nn_activation(gmt_hier_t h, int32_t level, int32_t which, float* d_out, int32_t* h_width,
+                             void* stream);
+
 /* AdamW step on FP32 master weights (bias-corrected moments, step >= 1,
  * decoupled weight decay wd, gradient multiplied by grad_scale first). */
 gmt_status gmt_nn_adamw(float* d_params, const float* d_grad, float* d_m, float* d_v, size_t n, double lr,

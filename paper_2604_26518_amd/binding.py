@@ -108,6 +108,7 @@ SIGNATURES = {
     "gmt_nn_setup": (_P, ct.POINTER(GmtNNConfig), _P),
     "gmt_nn_forward": (_P, _P, _P, _P),
     "gmt_nn_backward": (_P, _P, _P, _P),
+    "gmt_nn_activation": (_P, _I, _I, _P, ct.POINTER(ct.c_int32), _P),
     "gmt_nn_adamw": (_P, _P, _P, _P, ct.c_size_t, ct.c_double, ct.c_double, ct.c_double, ct.c_double,
                      ct.c_double, _I, ct.c_double, _P),
     "gmt_nn_norm2": (_P, ct.c_size_t, ct.POINTER(ct.c_double), _P),
@@ -429,6 +430,15 @@ class Hierarchy:
             if g is not None:
                 self._v(g, l, torch.float32, f"gout[{l}]")
         _check(lib().gmt_nn_backward(self._h, _ptr_array(gl), _ptr(grad), _stream()))
+
+    def nn_activation(self, level: int, which: int):
+        """Stored activation of the last forward (0 h, 1 a, 2 t, 3 d, 4 z1, 5 z2) as float32 [n_l][width]."""
+        self._level(level)
+        w = ct.c_int32()
+        _check(lib().gmt_nn_activation(self._h, level, which, None, ct.byref(w), _stream()))
+        out = torch.empty(self.n_n(level), w.value, dtype=torch.float32, device=self._vox.device)
+        _check(lib().gmt_nn_activation(self._h, level, which, _ptr(out), ct.byref(w), _stream()))
+        return out
 
     def vcycle_loss(self, preds, lam=0.0, want_grad=True, want_u1=False, nu1=2, nu2=2, smoother="chebyshev",
                     omega=None, lo=None, hi=None):

@@ -247,6 +247,7 @@ void nn_backward(Hier& h, const float* const* gout, float* grad, hipStream_t s);
 void nn_adamw(float* p, const float* g, float* m, float* v, size_t n, double lr, double b1, double b2, double eps,
               double wd, int step, double gscale, hipStream_t s);
 double nn_norm2(Hier* h, const float* x, size_t n, hipStream_t s);
+int nn_activation(Hier& h, int l, int which, float* out, hipStream_t s);
 void nn_ema(float* e, const float* x, size_t n, double decay, hipStream_t s);
 // column sums over nodes of a [C][n][D] vector -> sums[Q] (FP64)
 template <typename T>

@@ -1387,6 +1387,15 @@ gmt_status gmt_nn_backward(gmt_hier_t H, const float* const* d_gout, float* d_gr
   });
 }
 
+gmt_status gmt_nn_activation(gmt_hier_t H, int32_t level, int32_t which, float* d_out, int32_t* h_width,
+                             void* stream) {
+  return guarded([&] {
+    check_level(H, level);
+    const int w = nn_activation(H->h, level - 1, which, d_out, S(stream));
+    if (h_width) *h_width = w;
+  });
+}
+
 gmt_status gmt_nn_adamw(float* d_params, const float* d_grad, float* d_m, float* d_v, size_t n, double lr,
                         double beta1, double beta2, double eps, double wd, int32_t step, double grad_scale,
                         void* stream) {

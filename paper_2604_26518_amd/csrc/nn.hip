@@ -672,6 +672,29 @@ void nn_backward(Hier& h, const float* const* gout, float* grad, hipStream_t s) 
   }
 }
 
+__global__ void k_widen(size_t total, const uint16_t* __restrict__ a, float* __restrict__ b) {
+  const size_t i = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (i < total) b[i] = bf2f(a[i]);
+}
+
+int nn_activation(Hier& h, int l, int which, float* out, hipStream_t s) {
+  NNState& S = nn_state(h);
+  const NetLayout& N = S.nl;
+  if (which < 0 || which > 5) fail(GMT_E_INVAL, "activation kind %d outside 0..5", which);
+  if (which >= 2 && l >= N.L - 1) fail(GMT_E_INVAL, "decoder/head activations exist below the coarsest level only");
+  const uint16_t* src = which == 0 ? S.h[l] : which == 1 ? S.a[l] : which == 2 ? S.t[l] : which == 3 ? S.d[l]
+                        : which == 4 ? S.z1[l] : S.z2[l];
+  const int width = which >= 4 ? N.H : N.C[l];
+  if (out) {
+    const size_t tot = (size_t)h.lv[l].n_n * width;
+    if (tot) {
+      hipLaunchKernelGGL(k_widen, dim3(nblk(tot)), dim3(kB), 0, s, tot, src, out);
+      GMT_LAUNCH_CHECK();
+    }
+  }
+  return width;
+}
+
 double nn_norm2(Hier* h, const float* x, size_t n, hipStream_t s) {
   (void)h;
   const unsigned g = 256;

@@ -32,14 +32,38 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-# FP32 vs FP64 accumulation changes a BF16-rounded activation only where a sum lands within
-# ~1e-7 relative of a rounding boundary; emulating FP32 sums in the oracle moves outputs and
-# gradients by < 1e-6 relative at this size.  The bounds leave room for a few such flips.
-FWD_TOL = 1e-3
-BWD_TOL = 2e-3
+# Rounding every activation to BF16 makes the network's outputs depend on the exact
+# FP32 summation order: a sum that lands next to a BF16 rounding boundary rounds the
+# other way, the changed value moves the sums downstream, and with 27 * C inputs per
+# output such one-ulp changes spread through the whole network.  Where activations
+# change sign the leaky-ReLU derivative jumps by 10x, so element-wise gradient
+# comparisons with the FP64-summed oracle carry a spread of several percent for
+# generic weights (the oracle itself moves that much under 6e-8 relative noise added
+# before each rounding).  The sharp tests therefore use sign-definite regimes
+# (all pre-activations > 0, or all < 0) where the derivative pattern is fixed: there the
+# oracle's own spread under that noise is <= 3e-5 on outputs and <= 7.4e-4 on
+# gradients (16^3 gyroid, channels up to 64), and the bounds below sit above it.
+FWD_TOL = 5e-4
+BWD_TOL = 5e-3
+CONFIGS = [[16, 16, 16], [32, 32, 32], [16, 32, 64], [32, 64, 64]]
 
 
-def _make(CHs, L):
+def regime_params(net, seed, sign, wscale=0.12, bias=1.2):
+    """Weights small against the biases so every pre-activation has the sign `sign`."""
+    rng = np.random.default_rng(seed)
+    p = {}
+    for name, sh in net.shapes():
+        if name.startswith("b"):
+            p[name] = sign * bias + 0.1 * rng.standard_normal(sh)
+        elif name == "E":
+            p[name] = sign * rng.uniform(0.5, 1.5, sh)
+        else:
+            fan = sh[0] * sh[1] if len(sh) == 3 else sh[0]
+            p[name] = rng.uniform(-1, 1, sh) * np.sqrt(3.0 / fan) * wscale
+    return net.flatten(p)
+
+
+def _make(CHs, L, sign=0):
     vox = gyroid_sheet(16, 7, 0.4)
     H = _gmt().Hierarchy(vox, L)
     H.nn_setup(CHs)
@@ -47,64 +71,91 @@ def _make(CHs, L):
     net = onn.UNet(CHs, 32, 18)
     g = onn.Graph(lv)
     assert H.n_params == net.n_params()
-    flat = net.init(3)
-    flat += 0.02 * np.random.default_rng(4).standard_normal(flat.size)  # nonzero biases
-    print(f"[nn] channels={CHs} n_params={net.n_params()} n_n={[x.n_n for x in lv]}", flush=True)
+    if sign:
+        flat = regime_params(net, 5, sign)
+    else:
+        flat = net.init(3)
+        flat += 0.02 * np.random.default_rng(4).standard_normal(flat.size)  # nonzero biases
+    print(f"[nn] channels={CHs} sign={sign} n_params={net.n_params()} n_n={[x.n_n for x in lv]}", flush=True)
     return vox, H, net, g, flat
+
+
+def _activation_order(L):
+    order = []
+    for l in range(L):
+        order += [("h", 0, l), ("a", 1, l)]
+    for l in range(L - 2, -1, -1):
+        order += [("t", 2, l), ("d", 3, l)]
+    for l in range(L - 1):
+        order += [("z1", 4, l), ("z2", 5, l)]
+    return order
+
+
+def _fwd_bwd(H, net, g, flat):
+    outs = H.nn_forward(_t(flat))
+    ref, cache = onn.forward(net, flat, g)
+    rng = np.random.default_rng(9)
+    gouts = [rng.standard_normal(r.shape) for r in ref]
+    grad = torch.zeros(net.n_params(), dtype=torch.float32, device=DEV)
+    acts = {(k, l): _np(H.nn_activation(l + 1, w)) for k, w, l in _activation_order(H.L)}
+    H.nn_backward([_t(x.reshape(o.shape)) for x, o in zip(gouts, outs)], grad)
+    gref = onn.backward(net, g, cache, gouts)
+    return outs, ref, cache, acts, _np(grad), gref
+
+
+@pytest.mark.parametrize("sign", [1, -1])
+@pytest.mark.parametrize("chs", CONFIGS)
+def test_sign_definite_forward_backward(chs, sign):
+    vox, H, net, g, flat = _make(chs, 3, sign)
+    outs, ref, cache, acts, gg, gref = _fwd_bwd(H, net, g, flat)
+    H.close()
+    # the regime holds in the oracle: every stored activation has the intended sign
+    for (k, l), _ in acts.items():
+        assert np.all(sign * cache[k][l] > 0), (k, l)
+    aerr = {f"{k}{l}": _rel(a, cache[k][l]) for (k, l), a in acts.items()}
+    ferr = [_rel(_np(o).reshape(r.shape), r) for o, r in zip(outs, ref)]
+    P, Gg = net.unflatten(gref), net.unflatten(gg)
+    berr = {name: _rel(Gg[name], P[name]) for name, _ in net.shapes()}
+    print(f"[nn] {chs} sign {sign}: activations " + " ".join(f"{k}:{v:.1e}" for k, v in aerr.items()), flush=True)
+    print(f"[nn]   outputs {['%.1e' % e for e in ferr]} grads " + " ".join(f"{k}:{v:.1e}" for k, v in berr.items()),
+          flush=True)
+    assert max(aerr.values()) <= FWD_TOL, aerr
+    assert max(ferr) <= FWD_TOL, ferr
+    bad = {k: v for k, v in berr.items() if v > BWD_TOL}
+    assert not bad, bad
+    assert _rel(gg, gref) <= BWD_TOL
+
+
+def test_generic_weights_within_rounding_spread():
+    """Generic weights (sign changes): the GPU stays within the oracle's own rounding spread."""
+    vox, H, net, g, flat = _make(CH, 3)
+    outs, ref, cache, acts, gg, gref = _fwd_bwd(H, net, g, flat)
+    H.close()
+    rng = np.random.default_rng(9)
+    gouts = [rng.standard_normal(r.shape) for r in ref]
+    spread_f, spread_g = 0.0, 0.0
+    for trial in range(2):
+        nrng = np.random.default_rng(100 + trial)
+        base = onn.bf16
+        try:
+            onn.bf16 = lambda x: base(np.asarray(x, dtype=np.float64) * (1 + 6e-8 * nrng.standard_normal(np.shape(x))))
+            r2, c2 = onn.forward(net, flat, g)
+            g2 = onn.backward(net, g, c2, gouts)
+        finally:
+            onn.bf16 = base
+        spread_f = max(spread_f, max(_rel(a, b) for a, b in zip(r2, ref)))
+        spread_g = max(spread_g, _rel(g2, gref))
+    ferr = max(_rel(_np(o).reshape(r.shape), r) for o, r in zip(outs, ref))
+    gerr = _rel(gg, gref)
+    print(f"[nn] generic: outputs {ferr:.2e} (oracle spread {spread_f:.2e}), grads {gerr:.2e} "
+          f"(oracle spread {spread_g:.2e})", flush=True)
+    assert ferr <= 3 * spread_f + 1e-4
+    assert gerr <= 3 * spread_g + 1e-3
 
 
 @pytest.fixture(scope="module")
 def setup():
-    return _make(CH, 3)
-
-
-@pytest.mark.parametrize("chs", [[16, 16, 16], [32, 32, 32], [16, 32, 64], [32, 64, 64]])
-def test_forward_backward_channel_configs(chs):
-    vox, H, net, g, flat = _make(chs, 3)
-    outs = H.nn_forward(_t(flat))
-    ref, cache = onn.forward(net, flat, g)
-    ferr = [_rel(_np(o).reshape(r.shape), r) for o, r in zip(outs, ref)]
-    rng = np.random.default_rng(9)
-    gouts = [rng.standard_normal(r.shape) for r in ref]
-    grad = torch.zeros(net.n_params(), dtype=torch.float32, device=DEV)
-    H.nn_backward([_t(x.reshape(o.shape)) for x, o in zip(gouts, outs)], grad)
-    gref = onn.backward(net, g, cache, gouts)
-    P, Gg = net.unflatten(gref), net.unflatten(_np(grad))
-    berr = {name: _rel(Gg[name], P[name]) for name, _ in net.shapes()}
-    print(f"[nn] {chs} forward errors {['%.2e' % e for e in ferr]}", flush=True)
-    print("[nn] " + " ".join(f"{k}:{v:.1e}" for k, v in berr.items()), flush=True)
-    H.close()
-    assert max(ferr) <= FWD_TOL, ferr
-    bad = {k: v for k, v in berr.items() if v > BWD_TOL}
-    assert not bad, bad
-
-
-def test_forward_matches_bf16_reference(setup):
-    vox, H, net, g, flat = setup
-    outs = H.nn_forward(_t(flat))
-    ref, _ = onn.forward(net, flat, g)
-    for l, (o, r) in enumerate(zip(outs, ref)):
-        err = _rel(_np(o).reshape(r.shape), r)
-        assert err <= FWD_TOL, (l, err)
-
-
-def test_backward_matches_reference(setup):
-    vox, H, net, g, flat = setup
-    outs = H.nn_forward(_t(flat))
-    ref, cache = onn.forward(net, flat, g)
-    rng = np.random.default_rng(9)
-    gouts = [rng.standard_normal(r.shape) for r in ref]
-    grad = torch.zeros(net.n_params(), dtype=torch.float32, device=DEV)
-    H.nn_backward([_t(x.reshape(o.shape)) for x, o in zip(gouts, outs)], grad)
-    gref = onn.backward(net, g, cache, gouts)
-    gg = _np(grad)
-    P = net.unflatten(gref)
-    Gg = net.unflatten(gg)
-    errs = {name: _rel(Gg[name], P[name]) for name, _ in net.shapes()}
-    print("[nn] " + " ".join(f"{k}:{v:.1e}" for k, v in errs.items()), flush=True)
-    bad = {k: v for k, v in errs.items() if v > BWD_TOL}
-    assert not bad, bad
-    assert _rel(gg, gref) <= BWD_TOL
+    return _make(CH, 3, 1)
 
 
 def test_backward_accumulates(setup):
