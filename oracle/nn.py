@@ -23,11 +23,15 @@ Definition (0-based level index l, channels C[l], head width H, q = c*d):
   d_{L-1} = a_{L-1}
   t_l = act(unpool_l(d_{l+1}; Wu_l) + bu_l + a_l)           l = L-2..0
   d_l = act(conv_l(t_l; Wd_l) + bd_l)
-  z1 = act(d_l W1_l + b1_l); z2 = act(z1 W2_l + b2_l); out_l = scale * (z2 W3_l + b3_l)
+  z1 = act(d_l W1_l + b1_l); z2 = act(z1 W2_l + b2_l); out_l = center(scale * (z2 W3_l + b3_l))
 with act = leaky ReLU (slope 0.1), conv_l(x)(i) = sum_j x(nb_j(i)) W[j] over the
 27 periodic neighbours (absent nodes contribute 0), pool_l(x)(X) = sum_j
 x(2X + o_j) W[j], unpool_l(y)(i) = sum over parents X with i = 2X + o_j of
-y(X) W[j], and scale = N (displacements are measured in voxels).
+y(X) W[j], and scale = N (displacements are measured in voxels).  center()
+removes the mean over the level's nodes from every output column: the
+periodic problem fixes displacements only up to a translation, and the
+zero-mean gauge (Sec. 4.5) is imposed on every prediction exactly instead of
+through the penalty alone.
 """
 
 from __future__ import annotations
@@ -141,6 +145,11 @@ class UNet:
         return self.flatten(p)
 
 
+def center(y):
+    """Removes the mean over nodes of every output column (the zero-mean gauge of Sec. 4.5)."""
+    return y - y.mean(axis=0, keepdims=True)
+
+
 def _conv(x, nbmap, W):
     """sum_j x[nb_j] @ W[j] with absent neighbours contributing zero."""
     n = nbmap.shape[0]
@@ -209,7 +218,7 @@ def forward(net: UNet, flat, g: Graph, emulate_bf16: bool = True):
     for l in range(L - 1):
         z1 = rb(act(d[l] @ W[f"W1_{l}"] + W[f"b1_{l}"]))
         z2 = rb(act(z1 @ W[f"W2_{l}"] + W[f"b2_{l}"]))
-        outs.append(g.N * (z2 @ W[f"W3_{l}"] + W[f"b3_{l}"]))
+        outs.append(center(g.N * (z2 @ W[f"W3_{l}"] + W[f"b3_{l}"])))
         z1s.append(z1)
         z2s.append(z2)
     cache.update(h=h, a=a, d=d, t=t, z1=z1s, z2=z2s)
@@ -224,7 +233,7 @@ def backward(net: UNet, g: Graph, cache, gouts):
     G = {k: np.zeros_like(v) for k, v in W.items()}
     gd = [np.zeros_like(x) if x is not None else None for x in d]
     for l in range(L - 1):
-        go = g.N * gouts[l]
+        go = g.N * center(gouts[l])  # the centring is symmetric: its adjoint is itself
         G[f"W3_{l}"] += z2s[l].T @ go
         G[f"b3_{l}"] += go.sum(0)
         gz2 = (go @ W[f"W3_{l}"].T) * act_grad(z2s[l])

@@ -83,3 +83,21 @@ def test_unpool_is_adjoint_of_pool_connectivity():
     lhs = (nn._conv(x, g.pool[0], W) * y).sum()
     rhs = (x * nn._conv_T(y, g.pool[0], W, g.levels[0].n_n)).sum()
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_predictions_are_zero_mean_and_bias_free():
+    # every prediction is centred over its level's nodes (zero-mean gauge), so a
+    # constant shift of the head's last bias changes nothing and gets no gradient
+    net, g, _ = _net_graph()
+    rng = np.random.default_rng(5)
+    flat = net.init(3) + 0.05 * rng.standard_normal(net.n_params())
+    outs, cache = nn.forward(net, flat, g, emulate_bf16=False)
+    for o in outs:
+        assert np.abs(o.mean(axis=0)).max() <= 1e-12 * max(1.0, np.abs(o).max())
+    P = net.unflatten(flat)
+    P["b3_0"] = P["b3_0"] + 0.7
+    outs2, _ = nn.forward(net, net.flatten(P), g, emulate_bf16=False)
+    assert np.abs(outs2[0] - outs[0]).max() <= 1e-12 * np.abs(outs[0]).max()
+    grad = net.unflatten(nn.backward(net, g, cache, [rng.standard_normal(o.shape) for o in outs]))
+    for l in range(len(outs)):
+        assert np.abs(grad[f"b3_{l}"]).max() <= 1e-10
