@@ -30,6 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # read u 72 + f 72 + D^-1 12 + d 72, write u' 72 + d 72
 CHEB_BYTES_PER_NODE = 372
 COPY_BYTES = 512 << 20
+WEIGHTS = os.path.join(ROOT, "paper_2604_26518_amd", "weights", "unet128_elastic.npz")
 
 
 def _gen(seed_n):
@@ -61,6 +62,32 @@ def cpu_baseline(tol):
             "n_n": int(P.levels[0].n_n), "family": fam, "vf": vf, "iterations": its}
 
 
+def learned_leg(B, vox_dev, levels, args, cells):
+    """The learned path on the same cells: network forward -> one V-cycle -> FP64 check -> warm
+    GMG-PCG fallback, against plain zero-init GMG-PCG, solve-only times (hierarchy built outside)."""
+    import torch
+
+    from paper_2604_26518_amd.evaluate import compare, summarize
+    from paper_2604_26518_amd.learned import channels_for, load_weights
+
+    params, info = load_weights(WEIGHTS)
+    if info["levels"] != levels or info["N"] != args.N:
+        return {"skipped": f"weights are for N={info['N']} L={info['levels']}"}
+    recs = []
+    for k, vox in enumerate(vox_dev):
+        H = B.Hierarchy(vox, levels, "elastic")
+        H.nn_setup(channels_for(levels))
+        if k == 0:
+            compare(H, params, args.tol, reference=False)  # warm-up
+        recs.append(compare(H, params, args.tol, reference=(k < 8)))
+        H.close()
+    torch.cuda.synchronize()
+    s = summarize(recs)
+    s["weights"] = {"file": os.path.relpath(WEIGHTS, ROOT), "train_steps": info.get("step")}
+    s["note"] = "solve-only ms/cell (hierarchy build excluded) for both paths on the bench cells"
+    return s
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +98,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--max-iter", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -162,6 +190,10 @@ def main():
     copy_gbs = 2 * COPY_BYTES * 20 / (e0.elapsed_time(e1) / 1e3) / 1e9
     del src, dst
 
+    learned = None
+    if os.path.exists(WEIGHTS) and not args.no_learned:
+        learned = learned_leg(B, vox_dev, levels, args, cells)
+
     out = {
         "metric": METRIC,
         "value": round(ms_cell, 3),
@@ -188,6 +220,8 @@ def main():
                      "kernel": "level-1 Chebyshev sweep", **kernel_info,
                      "copy_GBps": round(copy_gbs, 1)},
     }
+    if learned is not None:
+        out["learned"] = learned
     if not args.no_cpu_baseline:
         cb = cpu_baseline(args.tol)
         n_n_128 = float(np.mean([r["n_n"] for r in record]))

@@ -103,6 +103,9 @@ typedef struct {
   int32_t max_outer;  /* FP64 refinement steps; default 8 */
   int32_t check_every;/* inner convergence check period (host sync); default 1 */
   gmt_cycle_opts cycle;
+  int32_t graph;      /* 1: inner PCG iterations run as replays of captured hipGraph
+                         blocks of 1 or 4 iterations (host check between blocks);
+                         0: kernel-by-kernel launches, check every check_every */
 } gmt_solve_opts;
 
 typedef struct {
@@ -188,6 +191,22 @@ gmt_status gmt_vcycle(gmt_hier_t h, const void* d_f, void* d_u, const void* cons
 gmt_status gmt_solve(gmt_hier_t h, const void* d_f, void* d_u, const gmt_solve_opts* opts,
                      gmt_solve_report* report, void* stream);
 
+/* Batched solve of n independent cells (each its own hierarchy: any N,
+ * elastic or thermal, any number of levels), the same problem as gmt_solve
+ * for each: d_f[i] / d_u[i] are that cell's FP64 level-1 vectors.  Cells are
+ * taken largest first from one shared queue by n_workers host threads (<= 0:
+ * 4), each driving its own HIP stream, so small cells overlap on the GPU; each
+ * cell's inner PCG replays captured hipGraph blocks when opts->graph is set.
+ * All work buffers are allocated on the calling thread before the workers
+ * start.  reports[i] / status[i] (either may be NULL) receive each cell's
+ * outcome; the call returns the first non-OK status (GMT_E_NOCONV included)
+ * or GMT_OK.  The caller's stream is synchronized first; the call returns when
+ * every cell is done. */
+gmt_status gmt_solve_batch(gmt_hier_t const* hs, int32_t n, const void* const* d_f, void* const* d_u,
+                           const gmt_solve_opts* opts, int32_t n_workers, gmt_solve_report* reports,
+                           gmt_status* status, void* stream);
+
+
 /* h_rel[c] = ||f_m - K u_m||_2 / ||f_m||_2 per case in FP64 (a case whose load
  * is below 1e-12 of the largest case is normalised by the largest ||f||). */
 gmt_status gmt_relative_residual(gmt_hier_t h, const void* d_f, const void* d_u, int32_t dtype,
@@ -228,7 +247,9 @@ gmt_status gmt_nn_setup(gmt_hier_t h, const gmt_nn_config* cfg, void* stream);
 
 /* Forward pass.  d_out: array of L pointers indexed by level-1; entry l-1
  * (l = 1..L-1) receives the level-l prediction [n_l][c][d] FP32 (u_hat^1 for
- * l = 1, e_hat^l otherwise) or is NULL to skip it; entry L-1 is unused. */
+ * l = 1, e_hat^l otherwise) or is NULL to skip it; entry L-1 is unused.
+ * Every prediction is centred: the mean over the level's nodes of each of its
+ * c*d columns is removed (zero-mean gauge, Sec. 4.5). */
 gmt_status gmt_nn_forward(gmt_hier_t h, const float* d_params, float* const* d_out, void* stream);
 
 /* Backward pass of the last forward: d_grad += d/dparams sum_l <d_gout[l], out[l]>

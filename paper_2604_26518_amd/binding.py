@@ -50,7 +50,8 @@ class GmtCycleOpts(ct.Structure):
 
 class GmtSolveOpts(ct.Structure):
     _fields_ = [("tol", ct.c_double), ("max_iter", ct.c_int32), ("precision", ct.c_int32),
-                ("max_outer", ct.c_int32), ("check_every", ct.c_int32), ("cycle", GmtCycleOpts)]
+                ("max_outer", ct.c_int32), ("check_every", ct.c_int32), ("cycle", GmtCycleOpts),
+                ("graph", ct.c_int32)]
 
 
 class GmtSolveReport(ct.Structure):
@@ -101,6 +102,8 @@ SIGNATURES = {
     "gmt_coarse_solve": (_P, _P, _P, _I, _P),
     "gmt_vcycle": (_P, _P, _P, _P, ct.POINTER(GmtCycleOpts), _I, _P),
     "gmt_solve": (_P, _P, _P, ct.POINTER(GmtSolveOpts), ct.POINTER(GmtSolveReport), _P),
+    "gmt_solve_batch": (_P, _I, _P, _P, ct.POINTER(GmtSolveOpts), _I, ct.POINTER(GmtSolveReport),
+                        ct.POINTER(ct.c_int32), _P),
     "gmt_relative_residual": (_P, _P, _P, _I, ct.POINTER(ct.c_double), _P),
     "gmt_homogenize": (_P, _P, _I, ct.POINTER(ct.c_double), _P),
     "gmt_time_sweep": (_P, _I, _I, _I, ct.POINTER(ct.c_double), _P),
@@ -376,21 +379,28 @@ class Hierarchy:
         _check(lib().gmt_vcycle(self._h, _ptr(f), _ptr(u), arr, ct.byref(o), _DT[u.dtype], _stream()))
         return u
 
-    def solve(self, f, u=None, tol=1e-5, max_iter=500, precision="f64", max_outer=8, check_every=1,
-              nu1=2, nu2=2, smoother="chebyshev", omega=None, lo=None, hi=None, raise_on_noconv=True):
-        self._v(f, 1, torch.float64, "f")
-        if u is None:
-            u = torch.zeros_like(f)
-        self._v(u, 1, torch.float64, "u")
+    def solve_opts(self, tol=1e-5, max_iter=500, precision="f64", max_outer=8, check_every=1, nu1=2, nu2=2,
+                   smoother="chebyshev", omega=None, lo=None, hi=None, graph=True):
+        """(gmt_solve_opts, buffers to keep alive during the call)."""
         o = GmtSolveOpts()
         o.tol, o.max_iter, o.max_outer, o.check_every = tol, max_iter, max_outer, check_every
         o.precision = GMT_F64 if precision == "f64" else GMT_F32
         o.cycle, keep = self._cycle(nu1, nu2, smoother, omega, lo, hi)
+        o.graph = 1 if graph else 0
+        return o, keep
+
+    def solve(self, f, u=None, tol=1e-5, max_iter=500, precision="f64", max_outer=8, check_every=1,
+              nu1=2, nu2=2, smoother="chebyshev", omega=None, lo=None, hi=None, raise_on_noconv=True,
+              graph=True):
+        self._v(f, 1, torch.float64, "f")
+        if u is None:
+            u = torch.zeros_like(f)
+        self._v(u, 1, torch.float64, "u")
+        o, keep = self.solve_opts(tol, max_iter, precision, max_outer, check_every, nu1, nu2, smoother, omega, lo,
+                                  hi, graph)
         rep = GmtSolveReport()
         st = lib().gmt_solve(self._h, _ptr(f), _ptr(u), ct.byref(o), ct.byref(rep), _stream())
-        report = {"iterations": rep.iterations, "outer": rep.outer, "converged": bool(rep.converged),
-                  "rel_res": list(rep.rel_res)[:self.c], "rel_res_init": list(rep.rel_res_init)[:self.c],
-                  "status": st}
+        report = _report(rep, self.c, st)
         if st != GMT_OK and (st != GMT_E_NOCONV or raise_on_noconv):
             _check(st)
         return u, report
@@ -475,6 +485,40 @@ class Hierarchy:
         out = (ct.c_double * 36)()
         _check(lib().gmt_homogenize(self._h, _ptr(u), _DT[u.dtype], out, _stream()))
         return np.array(out[:self.c * self.c]).reshape(self.c, self.c)
+
+
+def _report(rep, c, st):
+    return {"iterations": rep.iterations, "outer": rep.outer, "converged": bool(rep.converged),
+            "rel_res": list(rep.rel_res)[:c], "rel_res_init": list(rep.rel_res_init)[:c], "status": st}
+
+
+def solve_batch(hs, fs, us=None, n_workers=4, raise_on_noconv=True, **opts):
+    """gmt_solve_batch over hierarchies hs with FP64 loads fs (initial guesses us, zeros if None).
+
+    All cells share one option set (tol, precision, ...; Chebyshev bounds default per cell).
+    Returns (us, reports)."""
+    n = len(hs)
+    if len(fs) != n or (us is not None and len(us) != n):
+        raise ValueError("hs, fs and us must have the same length")
+    if us is None:
+        us = [torch.zeros_like(f) for f in fs]
+    for H, f, u in zip(hs, fs, us):
+        H._v(f, 1, torch.float64, "f")
+        H._v(u, 1, torch.float64, "u")
+    for k in ("omega", "lo", "hi"):
+        if opts.get(k) is not None:
+            raise ValueError(f"{k} is per cell; the batch uses each cell's defaults")
+    o, keep = hs[0].solve_opts(**opts) if n else (GmtSolveOpts(), [])
+    harr = (ct.c_void_p * max(n, 1))(*[H._h for H in hs])
+    farr = (ct.c_void_p * max(n, 1))(*[f.data_ptr() for f in fs])
+    uarr = (ct.c_void_p * max(n, 1))(*[u.data_ptr() for u in us])
+    reps = (GmtSolveReport * max(n, 1))()
+    stat = (ct.c_int32 * max(n, 1))()
+    st = lib().gmt_solve_batch(harr, n, farr, uarr, ct.byref(o), n_workers, reps, stat, _stream())
+    reports = [_report(reps[i], hs[i].c, stat[i]) for i in range(n)]
+    if st != GMT_OK and (st != GMT_E_NOCONV or raise_on_noconv):
+        _check(st)
+    return us, reports
 
 
 def nn_param_count(levels, channels, head=32, physics="elastic") -> int:

@@ -57,6 +57,10 @@ struct LevelView {
   const int* interior;
   const int* boundary;
   const T* S;
+  // launch shape of this level's operator sweeps (chosen by the autotuner):
+  // workgroup size (64 or 256), cases per thread (1, or all c) -- levels >= 2
+  // only -- and XCD-contiguous numbering
+  int bs, xcd, cb;
 };
 
 // Epilogue of a node-centric operator sweep.
@@ -81,6 +85,7 @@ void launch_apply(const LevelView<T>& L, int kind, int D, int C, int epi, const 
 template <typename T>
 void launch_smooth_zero(int n, int D, int C, const T* f, const T* dinv, T scale, T* out, T* dvec,
                         hipStream_t s);
+void launch_normalize(const double* src, size_t n, const double* nrm2, double* dst, hipStream_t s);
 template <typename T>
 void launch_restrict(const LevelView<T>& fine, const LevelView<T>& coarse, int Q, int D, const T* rf, T* fc,
                      hipStream_t s);
@@ -176,6 +181,9 @@ struct LevelData {
   double* dinv64 = nullptr;
   float* dinv32 = nullptr;
   double lam = 0.0;           // lambda_max(D^-1 K) estimate
+  int bs32 = 256, xcd32 = 1, cb32 = 0;  // launch shape of the FP32 / FP64 sweeps (autotuned;
+  int bs64 = 256, xcd64 = 1, cb64 = 0;  // cb 0 = all cases per thread)
+  bool tuned32 = false, tuned64 = false;
 };
 
 template <typename T>
@@ -217,6 +225,15 @@ struct Hier {
   float *s_b32 = nullptr, *s_x32 = nullptr;
   std::vector<void*> owned;
   void* nn = nullptr;  // learned-initializer state (nn.hip)
+  // captured blocks of inner PCG iterations (1 and 4 iterations), per precision;
+  // valid while `key` (cycle parameters and iterate buffer) is unchanged
+  struct PcgGraphs {
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    std::vector<double> key;
+  };
+  PcgGraphs g32, g64;
+  hipStream_t cap = nullptr;  // non-blocking stream used only to record the captures
+  void release_graphs();
 
   void* raw_alloc(size_t bytes);
   void release(void* ptr);  // frees one buffer obtained from raw_alloc

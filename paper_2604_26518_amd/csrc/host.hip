@@ -8,7 +8,11 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <atomic>
+#include <map>
 #include <memory>
+#include <mutex>
+#include <thread>
 
 #include "common.h"
 
@@ -72,6 +76,15 @@ void Hier::release(void* q) {
     (void)hipFree(q);
 }
 
+void Hier::release_graphs() {
+  for (PcgGraphs* g : {&g32, &g64}) {
+    for (auto& e : g->exec)
+      if (e) (void)hipGraphExecDestroy(e), e = nullptr;
+    g->key.clear();
+  }
+  if (cap) (void)hipStreamDestroy(cap), cap = nullptr;
+}
+
 void Hier::release_all() {
   for (void* q : owned) {
     if (p.release)
@@ -100,9 +113,15 @@ LevelView<T> Hier::view(int l) const {
   if constexpr (std::is_same<T, double>::value) {
     v.K = d.kind == KIND_SHARED ? Ke64 : (d.kind == KIND_TABLE ? table64 : d.Kel64);
     v.S = S64;
+    v.bs = d.bs64;
+    v.xcd = d.xcd64;
+    v.cb = d.cb64;
   } else {
     v.K = d.kind == KIND_SHARED ? Ke32 : (d.kind == KIND_TABLE ? table32 : d.Kel32);
     v.S = S32;
+    v.bs = d.bs32;
+    v.xcd = d.xcd32;
+    v.cb = d.cb32;
   }
   return v;
 }
@@ -521,6 +540,97 @@ static void vcycle(Hier& h, const T* f0, T* u0, bool u0_zero, const T* const* e_
   if (cur[l0] != u0) launch_copy<T>(cur[l0], u0, (size_t)h.lv[l0].n_n * h.Q, s);
 }
 
+// ------------------------------------------------------------ launch-shape autotuner
+// The operator sweeps of a level have a launch shape: workgroup size (256 or
+// 64), cases per thread (all c, or 1 with one grid row per case) and plain or
+// XCD-contiguous workgroup numbering; level 1 always uses 256-wide groups and
+// all cases per thread.  Before the first solve of a hierarchy, every
+// candidate is timed on every level (K.u on the work vectors: 2 warm-up and 3
+// timed launches between HIP events) and the fastest is kept.  Choices are
+// cached per (d, c, precision, operator kind, log2 of the node count, node
+// density class), so later hierarchies of the same class reuse them without
+// timing.  GMT_AUTOTUNE=0 keeps the defaults (256 wide, all cases, XCD order).
+struct Shape {
+  int bs, cb, xcd;
+};
+static std::mutex g_tune_mu;
+static std::map<std::vector<int>, Shape> g_tune;
+
+template <typename T>
+static void autotune(Hier& h, hipStream_t s) {
+  const bool f32 = !std::is_same<T, double>::value;
+  const char* env = std::getenv("GMT_AUTOTUNE");
+  const bool off = env && std::string(env) == "0";
+  h.ensure_work<T>();
+  Work<T>& W = h.work<T>();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  for (int l = 0; l < h.L; ++l) {
+    LevelData& d = h.lv[l];
+    bool& tuned = f32 ? d.tuned32 : d.tuned64;
+    int& bs = f32 ? d.bs32 : d.bs64;
+    int& xcd = f32 ? d.xcd32 : d.xcd64;
+    int& cb = f32 ? d.cb32 : d.cb64;
+    if (tuned) continue;
+    tuned = true;
+    if (off || d.n_n == 0) continue;
+    int nb = 0;
+    while ((1 << (nb + 1)) <= d.n_n) ++nb;
+    const double dens = (double)d.n_n / ((double)d.N * d.N * d.N);
+    const std::vector<int> key = {h.D, h.C, f32 ? 32 : 64, d.kind, nb, (int)(dens * 8.0)};
+    {
+      std::lock_guard<std::mutex> g(g_tune_mu);
+      auto it = g_tune.find(key);
+      if (it != g_tune.end()) {
+        bs = it->second.bs;
+        cb = it->second.cb;
+        xcd = it->second.xcd;
+        continue;
+      }
+    }
+    if (!e0) {
+      GMT_HIP(hipEventCreate(&e0));
+      GMT_HIP(hipEventCreate(&e1));
+    }
+    T* x = l == 0 ? W.pr : W.u[l];
+    T* y = l == 0 ? W.pz : W.r[l];
+    launch_fill<T>(x, (size_t)d.n_n * h.Q, T(0), s);
+    std::vector<Shape> cand = {{256, 0, 1}, {256, 0, 0}};
+    if (l > 0) {
+      cand.insert(cand.end(), {{64, 0, 1}, {64, 0, 0}});
+      if (h.C > 1) cand.insert(cand.end(), {{256, 1, 1}, {256, 1, 0}, {64, 1, 1}, {64, 1, 0}});
+    }
+    float best = INFINITY;
+    Shape pick = cand[0];
+    for (const Shape& c : cand) {
+      bs = c.bs;
+      cb = c.cb;
+      xcd = c.xcd;
+      for (int r = 0; r < 5; ++r) {
+        if (r == 2) GMT_HIP(hipEventRecord(e0, s));
+        apply<T>(h, l, EPI_KU, x, nullptr, y, h.C, s);
+      }
+      GMT_HIP(hipEventRecord(e1, s));
+      GMT_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      GMT_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        pick = c;
+      }
+    }
+    bs = pick.bs;
+    cb = pick.cb;
+    xcd = pick.xcd;
+    if (std::getenv("GMT_TIMING"))
+      fprintf(stderr, "[gmt tune] level %d (%s, n_n %d): bs %d cb %d xcd %d, %.1f us\n", l + 1,
+              f32 ? "f32" : "f64", d.n_n, bs, cb, xcd, best * 1e3 / 3);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[key] = pick;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+}
+
 static void host_dot(Hier& h, const double* dev, int n, double* out, hipStream_t s) {
   GMT_HIP(hipMemcpyAsync(out, dev, n * sizeof(double), hipMemcpyDeviceToHost, s));
   GMT_HIP(hipStreamSynchronize(s));
@@ -535,9 +645,39 @@ static void host_dot(Hier& h, const double* dev, int n, double* out, hipStream_t
 // column means (symmetric, so CG stays valid).
 // Stops when ||r_m|| <= tol[m] * ||b_m|| for every case, after maxit
 // iterations, or when the residual stagnates.
+// Records body() on the hierarchy's capture stream as an executable graph.
+template <typename F>
+static hipGraphExec_t capture_graph(Hier& h, F&& body) {
+  if (!h.cap) GMT_HIP(hipStreamCreateWithFlags(&h.cap, hipStreamNonBlocking));
+  GMT_HIP(hipStreamBeginCapture(h.cap, hipStreamCaptureModeThreadLocal));
+  try {
+    body(h.cap);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(h.cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  hipGraph_t g = nullptr;
+  GMT_HIP(hipStreamEndCapture(h.cap, &g));
+  hipGraphExec_t e = nullptr;
+  const hipError_t err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (err != hipSuccess) fail(GMT_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(err));
+  return e;
+}
+
 template <typename T>
-static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int check_every, const CycleCfg& cfg,
-               hipStream_t s) {
+static Hier::PcgGraphs& graphs_of(Hier& h) {
+  if constexpr (std::is_same<T, double>::value)
+    return h.g64;
+  else
+    return h.g32;
+}
+
+template <typename T>
+static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int check_every, bool graph,
+               const CycleCfg& cfg, hipStream_t s) {
   h.ensure_work<T>();
   Work<T>& W = h.work<T>();
   const int n = h.lv[0].n_n, C = h.C, D = h.D, Q = h.Q;
@@ -561,6 +701,76 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
   int it = 0;
   double best = INFINITY;
   int since_best = 0;
+  // convergence test on the host copy rr_h: returns true when every case is done;
+  // tracks the progress measure max_m ||r_m|| / (tol_m ||b_m||) for stagnation
+  double worst = INFINITY;
+  auto converged = [&]() {
+    bool done = true;
+    worst = 0;
+    for (int c = 0; c < C; ++c) {
+      if (!std::isfinite(rr_h[c])) fail(GMT_E_NOCONV, "PCG residual of case %d is not finite", c);
+      const double target = tol[c] * std::sqrt(bn2[c]);
+      if (std::sqrt(rr_h[c]) > target) done = false;
+      if (target > 0) worst = std::max(worst, std::sqrt(rr_h[c]) / target);
+    }
+    return done;
+  };
+  if (graph) {
+    // one iteration after the initial preconditioning, as in the launch-by-launch
+    // loop below; a block ends with ||r_m||^2 for the host check
+    auto step = [&](hipStream_t st) {
+      apply<T>(h, 0, EPI_KU, W.pp, nullptr, W.pq, C, st);
+      launch_dot<T>(W.pp, W.pq, n, C, D, h.red_partial, pq, st);
+      launch_pcg_alpha(rz, pq, alpha, C, st);
+      launch_pcg_update<T>(x, W.pr, W.pp, W.pq, alpha, n, Q, D, st);
+      launch_project<T>(W.pr, n, Q, D, h.red_partial, sums, st);
+      vcycle<T>(h, W.pr, W.pz, true, nullptr, cfg, st);
+      launch_project<T>(W.pz, n, Q, D, h.red_partial, sums, st);
+      launch_dot<T>(W.pr, W.pz, n, C, D, h.red_partial, rzn, st);
+      launch_pcg_beta(rzn, rz, beta, C, st);
+      launch_pcg_direction<T>(W.pp, W.pz, beta, n, Q, D, st);
+    };
+    Hier::PcgGraphs& G = graphs_of<T>(h);
+    std::vector<double> key = {(double)(uintptr_t)x, (double)cfg.nu1, (double)cfg.nu2, (double)cfg.smoother};
+    for (int l = 0; l < h.L; ++l) key.insert(key.end(), {cfg.omega[l], cfg.lo[l], cfg.hi[l]});
+    if (G.key != key) {
+      for (auto& e : G.exec)
+        if (e) (void)hipGraphExecDestroy(e), e = nullptr;
+      G.key.clear();
+      const int steps[2] = {1, 4};
+      for (int k = 0; k < 2; ++k)
+        G.exec[k] = capture_graph(h, [&](hipStream_t st) {
+          for (int i = 0; i < steps[k]; ++i) step(st);
+          launch_dot<T>(W.pr, W.pr, n, C, D, h.red_partial, rr, st);
+        });
+      G.key = key;
+    }
+    double prev = -1;
+    int prev_k = 1;
+    while (it < maxit) {
+      // four-iteration blocks while the observed rate predicts more than two
+      // iterations to go, single iterations near the end
+      int k = 4;
+      if (maxit - it < 4) k = 1;
+      if (prev > 0 && worst < prev && std::isfinite(worst)) {
+        const double rate = std::pow(worst / prev, 1.0 / prev_k);
+        if (rate < 1 && std::log(worst) / -std::log(rate) <= 2.0) k = 1;
+      }
+      GMT_HIP(hipGraphLaunch(G.exec[k == 1 ? 0 : 1], s));
+      it += k;
+      prev = worst;
+      prev_k = k;
+      host_dot(h, rr, C, rr_h, s);
+      if (converged()) break;
+      if (worst < 0.98 * best) {
+        best = worst;
+        since_best = 0;
+      } else if ((since_best += k) >= 100) {
+        break;  // stagnation: hand back to the FP64 refinement loop
+      }
+    }
+    return it;
+  }
   while (it < maxit) {
     ++it;
     apply<T>(h, 0, EPI_KU, W.pp, nullptr, W.pq, C, s);
@@ -571,15 +781,7 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
     if (it % check_every == 0 || it == maxit) {
       launch_dot<T>(W.pr, W.pr, n, C, D, h.red_partial, rr, s);
       host_dot(h, rr, C, rr_h, s);
-      bool done = true;
-      double worst = 0;  // progress measure: max_m ||r_m|| / (tol_m ||b_m||)
-      for (int c = 0; c < C; ++c) {
-        if (!std::isfinite(rr_h[c])) fail(GMT_E_NOCONV, "PCG residual of case %d is not finite", c);
-        const double target = tol[c] * std::sqrt(bn2[c]);
-        if (std::sqrt(rr_h[c]) > target) done = false;
-        if (target > 0) worst = std::max(worst, std::sqrt(rr_h[c]) / target);
-      }
-      if (done) break;
+      if (converged()) break;
       if (worst < 0.98 * best) {
         best = worst;
         since_best = 0;
@@ -809,22 +1011,22 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
       LevelData& d = h.lv[l];
       const int n = d.n_n;
       launch_random(x, (size_t)n * D, h.p.seed + 0x1000193ull * (l + 1), s);
-      double lam = 0;
+      double* o = h.red_out + 64;
+      // x <- D^-1 K x / ||D^-1 K x||, normalised on the device (no host round trip)
       for (int it = 0; it < iters; ++it) {
         apply<double>(h, l, EPI_KU, x, nullptr, y, 1, s);
-        launch_smooth_zero<double>(n, D, 1, x, d.diag64, 1.0, t, nullptr, s);  // t = D x
-        double* o = h.red_out + 64;
-        launch_dot<double>(x, y, n, 1, D, h.red_partial, o, s);
-        launch_dot<double>(x, t, n, 1, D, h.red_partial, o + 1, s);
         launch_smooth_zero<double>(n, D, 1, y, d.dinv64, 1.0, t, nullptr, s);  // t = D^-1 K x
         launch_dot<double>(t, t, n, 1, D, h.red_partial, o + 2, s);
-        double hv[3];
-        host_dot(h, o, 3, hv, s);
-        lam = hv[1] > 0 ? hv[0] / hv[1] : 0.0;
-        const double nrm = std::sqrt(hv[2]);
-        if (!(nrm > 0) || !std::isfinite(nrm)) break;
-        launch_smooth_zero<double>(n, D, 1, y, d.dinv64, 1.0 / nrm, x, nullptr, s);
+        launch_normalize(t, (size_t)n * D, o + 2, x, s);
       }
+      // Rayleigh quotient x.Kx / x.Dx (a lower bound of lambda_max)
+      apply<double>(h, l, EPI_KU, x, nullptr, y, 1, s);
+      launch_smooth_zero<double>(n, D, 1, x, d.diag64, 1.0, t, nullptr, s);  // t = D x
+      launch_dot<double>(x, y, n, 1, D, h.red_partial, o, s);
+      launch_dot<double>(x, t, n, 1, D, h.red_partial, o + 1, s);
+      double hv[2];
+      host_dot(h, o, 2, hv, s);
+      const double lam = hv[1] > 0 ? hv[0] / hv[1] : 0.0;
       if (!(lam > 0) || !std::isfinite(lam)) fail(GMT_E_SINGULAR, "lambda_max estimate failed on level %d", l + 1);
       d.lam = lam;
     }
@@ -848,9 +1050,15 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
   const int max_outer = o && o->max_outer > 0 ? o->max_outer : 8;
   const int prec = o ? o->precision : GMT_F64;
   const int check = o && o->check_every > 0 ? o->check_every : 1;
+  const bool graph = o && o->graph;
   if (prec != GMT_F64 && prec != GMT_F32) fail(GMT_E_INVAL, "bad precision");
   const CycleCfg cfg = make_cycle(h, o ? &o->cycle : nullptr);
   double* r64 = scratch64(h, &h.s_r64);
+  // (in mixed precision the few FP64 residual sweeps keep the default shape)
+  if (prec == GMT_F32)
+    autotune<float>(h, s);
+  else
+    autotune<double>(h, s);
   const int C = h.C;
   const size_t tot = (size_t)h.lv[0].n_n * h.Q;
   gmt_solve_report R{};
@@ -891,11 +1099,11 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
       if (!h.s_b32) h.s_b32 = h.alloc<float>(tot);
       if (!h.s_x32) h.s_x32 = h.alloc<float>(tot);
       launch_convert<double, float>(r64, h.s_b32, tot, s);
-      its += pcg<float>(h, h.s_b32, h.s_x32, itol, max_iter - its, check, cfg, s);
+      its += pcg<float>(h, h.s_b32, h.s_x32, itol, max_iter - its, check, graph, cfg, s);
       launch_accumulate<float>(u, h.s_x32, tot, s);
     } else {
       double* x64 = scratch64(h, &h.s_x64);
-      its += pcg<double>(h, r64, x64, itol, max_iter - its, check, cfg, s);
+      its += pcg<double>(h, r64, x64, itol, max_iter - its, check, graph, cfg, s);
       launch_accumulate<double>(u, x64, tot, s);
     }
   }
@@ -1029,6 +1237,7 @@ void gmt_destroy(gmt_hier_t H) {
   if (!H) return;
   (void)hipDeviceSynchronize();
   nn_release(H->h);
+  H->h.release_graphs();
   H->h.release_all();
   delete H;
 }
@@ -1300,6 +1509,100 @@ gmt_status gmt_solve(gmt_hier_t H, const void* d_f, void* d_u, const gmt_solve_o
     GMT_HIP(hipStreamSynchronize(s));
   });
   return g != GMT_OK ? g : st;
+}
+
+// Every buffer solve() may allocate, allocated up front (batched workers never
+// allocate: the allocation callback may not be callable from their threads).
+static void prepare_solve(Hier& h, int prec, hipStream_t s) {
+  const size_t tot = (size_t)h.lv[0].n_n * h.Q;
+  scratch64(h, &h.s_f64s);
+  scratch64(h, &h.s_u64s);
+  scratch64(h, &h.s_r64);
+  if (prec == GMT_F32) {
+    if (!h.s_b32) h.s_b32 = h.alloc<float>(tot);
+    if (!h.s_x32) h.s_x32 = h.alloc<float>(tot);
+    autotune<float>(h, s);
+  } else {
+    scratch64(h, &h.s_x64);
+    autotune<double>(h, s);
+  }
+}
+
+gmt_status gmt_solve_batch(gmt_hier_t const* hs, int32_t n, const void* const* d_f, void* const* d_u,
+                           const gmt_solve_opts* opts, int32_t n_workers, gmt_solve_report* reports,
+                           gmt_status* status, void* stream) {
+  std::vector<gmt_status> st((size_t)std::max(n, 0), GMT_OK);
+  std::vector<std::string> msg((size_t)std::max(n, 0));
+  gmt_status g = guarded([&] {
+    if (n < 0 || (n > 0 && (!hs || !d_f || !d_u))) fail(GMT_E_INVAL, "bad batch arguments");
+    const int prec = opts ? opts->precision : GMT_F64;
+    if (prec != GMT_F64 && prec != GMT_F32) fail(GMT_E_INVAL, "bad precision");
+    for (int i = 0; i < n; ++i) {
+      check_level(hs[i], 1);
+      if (!d_f[i] || !d_u[i] || d_f[i] == d_u[i]) fail(GMT_E_INVAL, "cell %d: null or aliased vector", i);
+      for (int j = 0; j < i; ++j)
+        if (hs[j] == hs[i]) fail(GMT_E_INVAL, "cell %d repeats the hierarchy of cell %d", i, j);
+    }
+    GMT_HIP(hipStreamSynchronize(S(stream)));
+    for (int i = 0; i < n; ++i) prepare_solve(hs[i]->h, prec, S(stream));
+    GMT_HIP(hipStreamSynchronize(S(stream)));
+    // largest cells first (longest-processing-time order balances the workers)
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      return (size_t)hs[a]->h.lv[0].n_n * hs[a]->h.Q > (size_t)hs[b]->h.lv[0].n_n * hs[b]->h.Q;
+    });
+    int dev = 0;
+    GMT_HIP(hipGetDevice(&dev));
+    const int nw = std::max(1, std::min(n_workers > 0 ? n_workers : 4, std::max(n, 1)));
+    std::atomic<int> next{0};
+    auto worker = [&]() {
+      hipStream_t ws = nullptr;
+      const gmt_status ok = guarded([&] {
+        GMT_HIP(hipSetDevice(dev));
+        GMT_HIP(hipStreamCreateWithFlags(&ws, hipStreamNonBlocking));
+      });
+      for (;;) {
+        const int k = next.fetch_add(1);
+        if (k >= n) break;
+        const int i = order[k];
+        if (ok != GMT_OK) {
+          st[i] = ok;
+          msg[i] = g_last_error;
+          continue;
+        }
+        gmt_status cell = GMT_OK;
+        gmt_solve_report rep{};
+        st[i] = guarded([&] {
+          Hier& h = hs[i]->h;
+          const int nn = h.lv[0].n_n;
+          double* f = h.s_f64s;
+          double* u = h.s_u64s;
+          launch_aos_to_soa<double, double>((const double*)d_f[i], f, nn, h.C, h.D, ws);
+          launch_aos_to_soa<double, double>((const double*)d_u[i], u, nn, h.C, h.D, ws);
+          solve(h, f, u, opts, &rep, ws, &cell);
+          launch_soa_to_aos<double, double>(u, (double*)d_u[i], nn, h.C, h.D, ws);
+          GMT_HIP(hipStreamSynchronize(ws));
+        });
+        if (st[i] == GMT_OK) st[i] = cell;
+        if (st[i] != GMT_OK) msg[i] = g_last_error;
+        if (reports) reports[i] = rep;
+      }
+      if (ws) (void)hipStreamDestroy(ws);
+    };
+    std::vector<std::thread> pool;
+    for (int w = 0; w < nw; ++w) pool.emplace_back(worker);
+    for (auto& t : pool) t.join();
+  });
+  if (status)
+    for (int i = 0; i < n; ++i) status[i] = st[i];
+  if (g != GMT_OK) return g;
+  for (int i = 0; i < n; ++i)
+    if (st[i] != GMT_OK) {
+      g_last_error = "cell " + std::to_string(i) + ": " + msg[i];
+      return st[i];
+    }
+  return GMT_OK;
 }
 
 // caller vector (level 1, dtype) -> FP64 [Q][n] scratch

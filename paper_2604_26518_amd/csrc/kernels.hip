@@ -22,6 +22,19 @@ constexpr int kBlock = 256;
 
 __device__ __forceinline__ int wrapm(int v, int N) { return v < 0 ? v + N : (v >= N ? v - N : v); }
 
+// Workgroups of a launch are handed to the 8 XCDs round-robin (workgroup b runs
+// on XCD b mod 8).  This renumbering gives XCD k the k-th contiguous share of
+// the index range instead, so that nodes that are neighbours on the grid (and
+// therefore read the same vector entries) are processed under one XCD's L2.
+// It is a bijection of [0, gridDim.x).
+__device__ __forceinline__ int xcd_block() {
+  const int B = (int)gridDim.x, b = (int)blockIdx.x;
+  const int x = b & 7, q = B >> 3, r = B & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
+__device__ __forceinline__ int block_index(int xcd) { return xcd ? xcd_block() : (int)blockIdx.x; }
+
 // Read-only operator coefficients are read through the constant address space:
 // together with a wave-uniform address this gives scalar loads even inside loops
 // that store to other buffers.
@@ -99,7 +112,7 @@ __device__ __forceinline__ void neighbour_ids(const int* __restrict__ map, int N
 // 27-point stencil S of the shared K_e, wave-uniform coefficients.
 template <typename T, int D, int EPI>
 __global__ __launch_bounds__(kBlock) void k_apply_interior(LevelView<T> L, int C, const T* __restrict__ u, EpiArgs<T> e) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int t = block_index(L.xcd) * kBlock + threadIdx.x;
   if (t >= L.n_int) return;
   const int i = L.interior[t];
   const int N = L.N;
@@ -142,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_interior(LevelView<T> L, int C
 // keeps the live register set to one element.
 template <typename T, int D, int EPI>
 __global__ __launch_bounds__(kBlock) void k_apply_boundary(LevelView<T> L, int C, const T* __restrict__ u, EpiArgs<T> e) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int t = block_index(L.xcd) * kBlock + threadIdx.x;
   if (t >= L.n_bnd) return;
   const int i = L.boundary[t];
   const int N = L.N;
@@ -194,13 +207,16 @@ __global__ __launch_bounds__(kBlock) void k_apply_boundary(LevelView<T> L, int C
 }
 
 // Levels >= 2: per-element matrices (mask table or stored), element ids from
-// the dense element map.  Element-outer loop: the D coefficient rows of an
-// element are loaded once and used for all C cases.
-template <typename T, int D, int C, int KIND, int EPI>
-__global__ __launch_bounds__(kBlock) void k_apply_coarse(LevelView<T> L, const T* __restrict__ u,
-                                                         EpiArgs<T> e) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+// the dense element map.  All index loads (27 neighbour ids, 8 element ids) are
+// issued up front and the element/corner loops are unrolled, so the gathers of
+// the 64 (element, corner) blocks are independent and overlap in flight; the
+// D x D coefficient block of a corner is loaded once for the CB cases a thread
+// owns (CB = c, or 1 with one grid row per case on small levels).
+template <typename T, int D, int CB, int KIND, int EPI, int BS>
+__global__ __launch_bounds__(BS) void k_apply_coarse(LevelView<T> L, const T* __restrict__ u, EpiArgs<T> e) {
+  const int i = block_index(L.xcd) * BS + threadIdx.x;
   if (i >= L.n_n) return;
+  const int c0 = (int)blockIdx.y * CB;  // this thread's cases: c0 .. c0 + CB - 1
   const int N = L.N;
   const size_t n = (size_t)L.n_n;
   const int lin = L.node_lin[i];
@@ -208,41 +224,43 @@ __global__ __launch_bounds__(kBlock) void k_apply_coarse(LevelView<T> L, const T
   const int t = lin / N;
   const int y = t % N;
   const int z = t / N;
-  const int xs[3] = {wrapm(x - 1, N), x, wrapm(x + 1, N)};
-  const int ys[3] = {wrapm(y - 1, N), y, wrapm(y + 1, N)};
-  const int zs[3] = {wrapm(z - 1, N), z, wrapm(z + 1, N)};
-  T acc[C][D];
+  int nb[27];
+  neighbour_ids<false>(L.node_map, N, x, y, z, nb);
+  const int xm = wrapm(x - 1, N), ym = wrapm(y - 1, N), zm = wrapm(z - 1, N);
+  int eid[8];
 #pragma unroll
-  for (int c = 0; c < C; ++c)
+  for (int k = 0; k < 8; ++k)
+    eid[k] = L.elem_map[((k & 1) ? x : xm) + N * ((((k >> 1) & 1) ? y : ym) + N * ((k >> 2) ? z : zm))];
+  T acc[CB][D];
+#pragma unroll
+  for (int c = 0; c < CB; ++c)
 #pragma unroll
     for (int q = 0; q < D; ++q) acc[c][q] = T(0);
   constexpr int M = 8 * D;
-#pragma unroll 1
+#pragma unroll
   for (int k = 0; k < 8; ++k) {
+    if (eid[k] < 0) continue;
     const int ak = k & 1, bk = (k >> 1) & 1, ck = (k >> 2) & 1;
-    const int eid = L.elem_map[xs[ak] + N * (ys[bk] + N * zs[ck])];
-    if (eid < 0) continue;
     const T* __restrict__ Km;
     if constexpr (KIND == KIND_TABLE)
-      Km = L.K + (size_t)L.cmask[eid] * M * M;
+      Km = L.K + (size_t)L.cmask[eid[k]] * M * M;
     else
-      Km = L.K + (size_t)eid * M * M;
+      Km = L.K + (size_t)eid[k] * M * M;
     Km += (7 - k) * D * M;
-#pragma unroll 1
+#pragma unroll
     for (int m = 0; m < 8; ++m) {
-      const int nx = xs[ak + (m & 1)], ny = ys[bk + ((m >> 1) & 1)], nz = zs[ck + ((m >> 2) & 1)];
-      const int id = L.node_map[nx + N * (ny + N * nz)];
-      if (id < 0) continue;  // cannot happen: corners of active elements are active
+      // corners of an active element are active: nb >= 0
+      const int id = nb[(ak + (m & 1)) + 3 * (bk + ((m >> 1) & 1)) + 9 * (ck + ((m >> 2) & 1))];
       T coef[D][D];
 #pragma unroll
       for (int q = 0; q < D; ++q)
 #pragma unroll
         for (int q2 = 0; q2 < D; ++q2) coef[q][q2] = Km[q * M + m * D + q2];
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
+      for (int c = 0; c < CB; ++c) {
 #pragma unroll
         for (int q2 = 0; q2 < D; ++q2) {
-          const T v = u[vix(c, n, id, D, q2)];
+          const T v = u[vix(c0 + c, n, id, D, q2)];
 #pragma unroll
           for (int q = 0; q < D; ++q) acc[c][q] = fma(coef[q][q2], v, acc[c][q]);
         }
@@ -250,14 +268,24 @@ __global__ __launch_bounds__(kBlock) void k_apply_coarse(LevelView<T> L, const T
     }
   }
 #pragma unroll
-  for (int c = 0; c < C; ++c)
+  for (int c = 0; c < CB; ++c)
 #pragma unroll
     for (int q = 0; q < D; ++q) {
-      const size_t idx = vix(c, n, i, D, q);
+      const size_t idx = vix(c0 + c, n, i, D, q);
       T uself = T(0);
       if constexpr (EPI == EPI_JACOBI || EPI == EPI_CHEB || EPI == EPI_CHEB0) uself = u[idx];
       epilogue<T, EPI>(e, idx, acc[c][q], uself, (size_t)i * D + q);
     }
+}
+
+// dst = src / sqrt(*nrm2), the squared norm read on the device; a zero or
+// non-finite norm leaves a zero vector (the caller's estimate then fails).
+__global__ void k_normalize(size_t n, const double* __restrict__ src, const double* __restrict__ nrm2,
+                            double* __restrict__ dst) {
+  const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double v = *nrm2;
+  dst[i] = (v > 0.0 && v < INFINITY) ? src[i] / sqrt(v) : 0.0;
 }
 
 // First smoothing step from a zero iterate: u = scale * D^-1 f (K 0 = 0).
@@ -281,7 +309,7 @@ __global__ void k_smooth_zero(int n, int D, int C, const T* __restrict__ f, cons
 template <typename T, int Q, int D>
 __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> F, LevelView<T> Cv, const T* __restrict__ rf,
                                                      T* __restrict__ fc) {
-  const int J = blockIdx.x * kBlock + threadIdx.x;
+  const int J = xcd_block() * kBlock + threadIdx.x;
   if (J >= Cv.n_n) return;
   const int Nc = Cv.N, Nf = F.N;
   const size_t nf = (size_t)F.n_n, nc = (size_t)Cv.n_n;
@@ -316,7 +344,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> F, LevelView<T
 template <typename T, int Q, int D>
 __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView<T> F, LevelView<T> Cv, const T* __restrict__ uc,
                                                         T* __restrict__ uf) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = xcd_block() * kBlock + threadIdx.x;
   if (i >= F.n_n) return;
   const int Nc = Cv.N, Nf = F.N;
   const size_t nf = (size_t)F.n_n, nc = (size_t)Cv.n_n;
@@ -927,6 +955,24 @@ inline unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlo
 
 // ================================================================ launchers
 
+// coarse-level sweep: CB cases per thread, C / CB grid rows, workgroup size L.bs
+template <typename T, int D, int CB, int EPI>
+static void launch_coarse(const LevelView<T>& L, int kind, int rows, const T* u, const EpiArgs<T>& e, hipStream_t s) {
+  if (L.bs == 64) {
+    const dim3 g((unsigned)((L.n_n + 63) / 64), (unsigned)rows);
+    if (kind == KIND_TABLE)
+      hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_TABLE, EPI, 64>), g, dim3(64), 0, s, L, u, e);
+    else
+      hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_PERELEM, EPI, 64>), g, dim3(64), 0, s, L, u, e);
+  } else {
+    const dim3 g(blocks_for(L.n_n), (unsigned)rows);
+    if (kind == KIND_TABLE)
+      hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_TABLE, EPI, kBlock>), g, dim3(kBlock), 0, s, L, u, e);
+    else
+      hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_PERELEM, EPI, kBlock>), g, dim3(kBlock), 0, s, L, u, e);
+  }
+}
+
 template <typename T, int D, int C, int EPI>
 static void apply_dispatch_kind(const LevelView<T>& L, int kind, const T* u, const EpiArgs<T>& e, hipStream_t s) {
   if (kind == KIND_SHARED) {
@@ -935,12 +981,11 @@ static void apply_dispatch_kind(const LevelView<T>& L, int kind, const T* u, con
     if (L.n_bnd > 0)
       hipLaunchKernelGGL((k_apply_boundary<T, D, EPI>), dim3(blocks_for(L.n_bnd)), dim3(kBlock), 0, s, L, C, u, e);
   } else {
-    const unsigned g = blocks_for(L.n_n);
-    if (g == 0) return;
-    if (kind == KIND_TABLE)
-      hipLaunchKernelGGL((k_apply_coarse<T, D, C, KIND_TABLE, EPI>), dim3(g), dim3(kBlock), 0, s, L, u, e);
+    if (L.n_n == 0) return;
+    if (L.cb == 1 && C > 1)
+      launch_coarse<T, D, 1, EPI>(L, kind, C, u, e, s);
     else
-      hipLaunchKernelGGL((k_apply_coarse<T, D, C, KIND_PERELEM, EPI>), dim3(g), dim3(kBlock), 0, s, L, u, e);
+      launch_coarse<T, D, C, EPI>(L, kind, 1, u, e, s);
   }
   GMT_LAUNCH_CHECK();
 }
@@ -974,6 +1019,12 @@ void launch_smooth_zero(int n, int D, int C, const T* f, const T* dinv, T scale,
   if (!tot) return;
   hipLaunchKernelGGL(k_smooth_zero<T>, dim3(blocks_for(tot)), dim3(kBlock), 0, s, n, D, C, f, dinv, scale, out,
                      dvec);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_normalize(const double* src, size_t n, const double* nrm2, double* dst, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_normalize, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, src, nrm2, dst);
   GMT_LAUNCH_CHECK();
 }
 

@@ -313,6 +313,48 @@ __global__ __launch_bounds__(kB) void k_norm2(const float* __restrict__ x, size_
   }
 }
 
+// Column sums of a node-major [n][Q] FP32 array: per-block FP64 partials
+// (fixed grid, deterministic order), then one block sums them into the means.
+constexpr int kColBlocks = 128;
+template <int Q>
+__global__ __launch_bounds__(kB) void k_colsum_rows(int n, const float* __restrict__ x, double* __restrict__ partial) {
+  __shared__ double sh[kB / 64][Q];
+  double acc[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) acc[q] = 0.0;
+  for (int i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q] += x[(size_t)i * Q + q];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    double v = acc[q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if (lane == 0) sh[w][q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < Q) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < kB / 64; ++k) t += sh[k][threadIdx.x];
+    partial[(size_t)blockIdx.x * Q + threadIdx.x] = t;
+  }
+}
+
+__global__ void k_colmean_final(const double* __restrict__ partial, int nblk, int Q, int n, double* __restrict__ mean) {
+  const int q = threadIdx.x;
+  if (q >= Q) return;
+  double t = 0.0;
+  for (int b = 0; b < nblk; ++b) t += partial[(size_t)b * Q + q];
+  mean[q] = n > 0 ? t / n : 0.0;
+}
+
+__global__ void k_sub_colmean(size_t total, int Q, float* __restrict__ x, const double* __restrict__ mean) {
+  const size_t i = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (i < total) x[i] = (float)((double)x[i] - mean[i % Q]);
+}
+
 __global__ void k_ema(float* __restrict__ e, const float* __restrict__ x, size_t n, float decay) {
   const size_t i = (size_t)blockIdx.x * kB + threadIdx.x;
   if (i < n) e[i] = decay * e[i] + (1.f - decay) * x[i];
@@ -439,6 +481,7 @@ struct NNState {
   float* Wb = nullptr;                                   // BF16-rounded weights (FP32 storage)
   float* Wt = nullptr;                                   // transposed weights of one layer
   float *g0 = nullptr, *g1 = nullptr, *g2 = nullptr;     // FP32 gradient scratch (max n_l * max C)
+  double* colred = nullptr;                              // column-mean partials + means
   std::vector<float*> gd;                                // dL/dd_l accumulators
   std::vector<float*> ga;                                // dL/da_l accumulators
 };
@@ -509,6 +552,7 @@ void nn_setup(Hier& h, const gmt_nn_config& cfg, hipStream_t s) {
   size_t maxw = 0;
   for (int l = 0; l < L; ++l) maxw = std::max(maxw, (size_t)27 * 64 * 64);
   S->Wt = h.alloc<float>(maxw);
+  S->colred = h.alloc<double>((size_t)(kColBlocks + 1) * 32);
   S->g0 = h.alloc<float>(maxnc);
   S->g1 = h.alloc<float>(maxnc);
   S->g2 = h.alloc<float>(maxnc);
@@ -516,6 +560,26 @@ void nn_setup(Hier& h, const gmt_nn_config& cfg, hipStream_t s) {
 }
 
 size_t nn_param_count(const gmt_nn_config& cfg, int q) { return make_layout(cfg, q).total; }
+
+// x[n][Q] -= column means over the n rows (the zero-mean gauge of a prediction;
+// the same map is its own adjoint, so the backward applies it to the gradient)
+static void center_rows(NNState& S, float* x, int n, int Q, hipStream_t s) {
+  if (n <= 0) return;
+  double* partial = S.colred;
+  double* mean = S.colred + (size_t)kColBlocks * 32;
+  if (Q == 18)
+    hipLaunchKernelGGL(k_colsum_rows<18>, dim3(kColBlocks), dim3(kB), 0, s, n, x, partial);
+  else if (Q == 3)
+    hipLaunchKernelGGL(k_colsum_rows<3>, dim3(kColBlocks), dim3(kB), 0, s, n, x, partial);
+  else
+    fail(GMT_E_INVAL, "prediction width %d not instantiated", Q);
+  GMT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_colmean_final, dim3(1), dim3(64), 0, s, partial, kColBlocks, Q, n, mean);
+  GMT_LAUNCH_CHECK();
+  const size_t tot = (size_t)n * Q;
+  hipLaunchKernelGGL(k_sub_colmean, dim3(nblk(tot)), dim3(kB), 0, s, tot, Q, x, mean);
+  GMT_LAUNCH_CHECK();
+}
 
 // out[l]: level l (0-based, l < L-1) prediction [n_l][q] FP32 (u_hat^1 for l = 0, e_hat^{l+1} otherwise)
 void nn_forward(Hier& h, const float* params, float* const* out, hipStream_t s) {
@@ -548,9 +612,11 @@ void nn_forward(Hier& h, const float* params, float* const* out, hipStream_t s) 
                                                        nullptr, 1.f, S.z1[l], s);
     gconv_dispatch<uint16_t, uint16_t, F_BIAS | F_ACT>(N.H, N.H, 1, n, nullptr, S.z1[l], W + N.W2[l], W + N.b2[l],
                                                        nullptr, 1.f, S.z2[l], s);
-    if (out[l])
+    if (out[l]) {
       gconv_dispatch<uint16_t, float, F_BIAS | F_SCALE>(N.H, N.q, 1, n, nullptr, S.z2[l], W + N.W3[l], W + N.b3[l],
                                                         nullptr, (float)h.N, out[l], s);
+      center_rows(S, out[l], n, N.q, s);
+    }
   }
 }
 
@@ -603,6 +669,7 @@ void nn_backward(Hier& h, const float* const* gout, float* grad, hipStream_t s) 
     const size_t tq = (size_t)n * q;
     hipLaunchKernelGGL(k_scale_copy, dim3(nblk(tq)), dim3(kB), 0, s, tq, gout[l], (float)h.N, S.g2);
     GMT_LAUNCH_CHECK();
+    center_rows(S, S.g2, n, q, s);
     wgrad_dispatch<uint16_t>(H, q, 1, n, nullptr, S.z2[l], S.g2, grad + N.W3[l], s);
     bgrad_dispatch(q, n, S.g2, grad + N.b3[l], s);
     transpose_taps(S, W + N.W3[l], 1, H, q, false, s);

@@ -11,6 +11,7 @@ V-cycle result (never a restart from zero).
 
 from __future__ import annotations
 
+import json
 import math
 import time
 
@@ -58,7 +59,7 @@ class Trainer:
     """AdamW on FP32 master weights with a cosine schedule, global-norm clipping and an EMA copy."""
 
     def __init__(self, n_params, levels, physics="elastic", lr=1e-3, wd=1e-2, clip=1.0, ema=0.999, seed=0,
-                 lam=1e-2, device="cuda"):
+                 lam=0.0, device="cuda"):
         self.params = init_params(n_params, levels, physics, seed, device)
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
@@ -68,8 +69,20 @@ class Trainer:
         self.lam = lam
         self.step = 0
 
-    def lr_at(self, k, total):
-        return self.lr * 0.5 * (1 + math.cos(math.pi * min(k, total) / max(total, 1)))
+    def save(self, path):
+        torch.save({"params": self.params.cpu(), "m": self.m.cpu(), "v": self.v.cpu(), "ema": self.ema.cpu(),
+                    "step": self.step}, path)
+
+    def load(self, path):
+        ck = torch.load(path, map_location="cpu", weights_only=True)
+        for name in ("params", "m", "v", "ema"):
+            getattr(self, name).copy_(ck[name].to(self.params.device))
+        self.step = int(ck["step"])
+
+    def lr_at(self, k, total, warmup=300):
+        """Linear warm-up over `warmup` steps, then cosine decay to zero at `total`."""
+        w = min(1.0, (k + 1) / warmup) if warmup > 0 else 1.0
+        return self.lr * w * 0.5 * (1 + math.cos(math.pi * min(k, total) / max(total, 1)))
 
     def train_cell(self, H: B.Hierarchy, total_steps: int, inject: bool = True):
         """One optimisation step on one cell; returns (loss, ||r||, max relative residual)."""
@@ -77,8 +90,9 @@ class Trainer:
         if not inject:
             preds = preds[:1]
         lr = self.lr_at(self.step, total_steps)
-        # gauge penalty lambda (sum_i u_i)^2 with lambda = lam * lr / n^2, i.e. on the per-component mean
-        loss, rn, rel, _, grads = H.vcycle_loss(preds, lam=self.lam * lr / float(H.n_n(1)) ** 2)
+        # gauge penalty lambda (sum_i u_i)^2 with lambda = lam / n^2: lam times the squared
+        # per-component mean of u^1 (the residual does not see rigid translations)
+        loss, rn, rel, _, grads = H.vcycle_loss(preds, lam=self.lam / float(H.n_n(1)) ** 2)
         self.grad.zero_()  # memory fill
         H.nn_backward(grads + [None] * (H.L - 1 - len(grads)), self.grad)
         gn = math.sqrt(B.norm2(self.grad))
@@ -87,6 +101,26 @@ class Trainer:
         B.adamw(self.params, self.grad, self.m, self.v, lr, self.step, wd=self.wd, grad_scale=scale)
         B.ema(self.ema, self.params, self.ema_decay)
         return loss, rn, float(np.max(rel))
+
+
+def save_weights(path, flat, levels, N, physics, meta=None):
+    """Inference weights: the BF16 rounding of `flat` (the network only ever uses BF16 weights)."""
+    x = flat.detach().to("cpu", torch.float32).contiguous()
+    bits = x.view(torch.int32).numpy().astype(np.uint32)
+    bf = ((bits + 0x7FFF + ((bits >> 16) & 1)) >> 16).astype(np.uint16)
+    info = {"levels": int(levels), "N": int(N), "physics": physics, "channels": channels_for(levels), "head": 32}
+    if meta:
+        info.update(meta)
+    np.savez(path, bf16=bf, info=np.frombuffer(json.dumps(info).encode(), dtype=np.uint8))
+
+
+def load_weights(path, device="cuda"):
+    """(flat FP32 tensor holding BF16 values, info dict) from save_weights' file."""
+    with np.load(path, allow_pickle=False) as z:
+        bf = z["bf16"].astype(np.uint32) << 16
+        info = json.loads(bytes(z["info"]).decode())
+    flat = torch.from_numpy(bf.view(np.float32).copy()).to(device)
+    return flat, info
 
 
 def learned_solve(H: B.Hierarchy, params, tol=1e-5, inject=True, max_iter=3000, f64=None):

@@ -1,12 +1,15 @@
 """Trains the learned initializer on seeded synthetic cells (label-free physics loss).
 
-    python -m paper_2604_26518_amd.train --N 128 --cells 256 --steps 3000 --out weights.pt
+    python -m paper_2604_26518_amd.train --N 128 --cells 1024 --time-budget 900 --ckpt run.pt
 
-Every step: network forward (gmt_nn_forward) -> one Alg. 2 V-cycle from its
-predictions + the log-residual loss and its adjoint (gmt_vcycle_loss) ->
-backward (gmt_nn_backward) -> global-norm clipping -> AdamW (gmt_nn_adamw) ->
-EMA.  The saved file holds the FP32 master weights, the EMA weights (used for
-inference) and the configuration.
+Every step, on one cell: network forward (gmt_nn_forward) -> one Alg. 2
+V-cycle from its predictions + the log-residual loss and its adjoint
+(gmt_vcycle_loss) -> backward (gmt_nn_backward) -> global-norm clipping ->
+AdamW (gmt_nn_adamw) -> EMA (gmt_nn_ema).  Cells come from the mixed lattice
+families (family = seed mod 5, VF ~ U(0.15, 0.5)); hierarchies are kept on
+the GPU up to a memory budget and rebuilt otherwise.  The checkpoint holds
+the FP32 master weights, the AdamW moments, the EMA weights and the step, so
+a run can be resumed; --export writes the EMA weights as BF16 for inference.
 """
 
 from __future__ import annotations
@@ -23,19 +26,20 @@ import numpy as np
 import torch
 
 from . import binding as B
-from .learned import Trainer, channels_for, learned_solve
+from .learned import Trainer, channels_for, save_weights
 
 
 def _gen(args):
     seed, N = args
     from gmt_inputs.lattices import workload_cell
-    return workload_cell(N, seed)
+    fam, vf, vox = workload_cell(N, seed)
+    return seed, fam, vf, vox
 
 
 def make_cells(N, seeds, procs=16):
     procs = max(1, min(procs, os.cpu_count() or 1))
     with mp.get_context("fork").Pool(procs) as pool:
-        return pool.map(_gen, [(s, N) for s in seeds])
+        return pool.map(_gen, [(s, N) for s in seeds], chunksize=4)
 
 
 def build(vox, levels, physics="elastic"):
@@ -56,20 +60,35 @@ def evaluate(params, hs, inject=True):
     return np.array(out)
 
 
+def evaluate_zero(hs):
+    """Post-V-cycle relative residual from a zero initial guess (the method without the network)."""
+    out = []
+    for H in hs:
+        u0 = H.vec(1, torch.float32).zero_()
+        _, _, rel, _, _ = H.vcycle_loss([u0], want_grad=False)
+        out.append(float(np.max(rel)))
+    return np.array(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--levels", type=int, default=0)
-    ap.add_argument("--cells", type=int, default=256)
-    ap.add_argument("--cache", type=int, default=96, help="hierarchies kept on the GPU")
+    ap.add_argument("--cells", type=int, default=1024)
     ap.add_argument("--held-out", type=int, default=16)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=20000, help="length of the cosine schedule")
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--seed0", type=int, default=10000)
-    ap.add_argument("--test-seed0", type=int, default=20000)
-    ap.add_argument("--out", default="weights.pt")
+    ap.add_argument("--lam", type=float, default=0.0,
+                    help="gauge penalty on the per-component mean of u^1 (predictions are centred already)")
+    ap.add_argument("--seed0", type=int, default=100000)
+    ap.add_argument("--test-seed0", type=int, default=900000)
+    ap.add_argument("--ckpt", default="unet.pt")
+    ap.add_argument("--resume", action="store_true")
+    ap.add_argument("--export", default="", help="write the EMA weights (BF16) to this .npz at the end")
     ap.add_argument("--log", default="")
-    ap.add_argument("--time-budget", type=float, default=0.0, help="stop after this many seconds")
+    ap.add_argument("--time-budget", type=float, default=0.0, help="stop after this many seconds of training")
+    ap.add_argument("--cache-gb", type=float, default=120.0, help="GPU memory for cached hierarchies")
+    ap.add_argument("--eval-every", type=int, default=1000)
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
     levels = args.levels or B.default_levels(args.N)
@@ -79,48 +98,64 @@ def main(argv=None):
     print(f"# {len(cells)} train + {len(test)} held-out cells at {args.N}^3 in {time.time() - t0:.1f} s, "
           f"levels {levels}", flush=True)
     n_params = B.nn_param_count(levels, channels_for(levels))
-    tr = Trainer(n_params, levels, lr=args.lr)
+    tr = Trainer(n_params, levels, lr=args.lr, lam=args.lam)
+    if args.resume and os.path.exists(args.ckpt):
+        tr.load(args.ckpt)
+        print(f"# resumed {args.ckpt} at step {tr.step}", flush=True)
+    hs_test = [build(v, levels) for (_, _, _, v) in test]
+    base0 = evaluate(tr.ema, hs_test)
+    zero = evaluate_zero(hs_test)
+    print(f"# params {n_params}; held-out post-V-cycle residual: zero init median {np.median(zero):.3e}, "
+          f"network (EMA weights) at start median {np.median(base0):.3e}", flush=True)
     cache = {}
-    hs_test = [build(v, levels) for (_, _, v) in test]
-    base = evaluate(tr.params, hs_test)
+    budget = args.cache_gb * 2**30
     log = []
-    print(f"# params {n_params}; held-out post-V-cycle residual at init: median {np.median(base):.3e}", flush=True)
     t_start = time.time()
-    rng = np.random.default_rng(0)
-    order = rng.permutation(len(cells))
-    for k in range(args.steps):
-        idx = int(order[k % len(cells)])
+    t_last = t_start
+    rng = np.random.default_rng(tr.step)
+    k = 0
+    while tr.step < args.steps:
+        idx = int(rng.integers(len(cells)))
         H = cache.get(idx)
-        if H is None:
-            H = build(cells[idx][2], levels)
-            if len(cache) < args.cache:
+        fresh = H is None
+        if fresh:
+            H = build(cells[idx][3], levels)
+            if torch.cuda.memory_allocated() < budget:
                 cache[idx] = H
         loss, rn, rel = tr.train_cell(H, args.steps)
-        if idx not in cache:
+        if fresh and idx not in cache:
             H.close()
         if not math.isfinite(loss):
-            raise RuntimeError(f"non-finite loss at step {k}")
-        log.append({"step": k, "loss": loss, "rel": rel, "family": cells[idx][0]})
-        if (k + 1) % 100 == 0 or k == args.steps - 1:
-            recent = np.array([x["rel"] for x in log[-100:]])
-            msg = (f"step {k + 1}/{args.steps} lr {tr.lr_at(tr.step, args.steps):.2e} loss "
-                   f"{np.mean([x['loss'] for x in log[-100:]]):.3f} train rel median {np.median(recent):.3e} "
-                   f"({time.time() - t_start:.0f} s)")
-            if (k + 1) % 500 == 0 or k == args.steps - 1:
+            raise RuntimeError(f"non-finite loss at step {tr.step}")
+        log.append({"step": tr.step, "loss": loss, "rel": rel, "family": cells[idx][1]})
+        k += 1
+        now = time.time()
+        if now - t_last > 20 or tr.step % args.eval_every == 0:
+            t_last = now
+            recent = log[-200:]
+            msg = (f"step {tr.step} lr {tr.lr_at(tr.step, args.steps):.2e} loss "
+                   f"{np.mean([x['loss'] for x in recent]):.3f} train rel median "
+                   f"{np.median([x['rel'] for x in recent]):.3e} ({(now - t_start) / k * 1e3:.0f} ms/step, "
+                   f"{len(cache)} cached, {torch.cuda.memory_allocated() / 2**30:.0f} GiB)")
+            if tr.step % args.eval_every == 0:
                 ev = evaluate(tr.ema, hs_test)
                 msg += f" | held-out EMA median {np.median(ev):.3e} max {ev.max():.3e}"
+                tr.save(args.ckpt)
             print(msg, flush=True)
-        if args.time_budget and time.time() - t_start > args.time_budget:
-            print(f"# time budget reached after {k + 1} steps", flush=True)
+        if args.time_budget and now - t_start > args.time_budget:
+            print(f"# time budget reached at step {tr.step}", flush=True)
             break
+    tr.save(args.ckpt)
     ev = evaluate(tr.ema, hs_test)
     ev_noinj = evaluate(tr.ema, hs_test, inject=False)
-    torch.save({"params": tr.params.cpu(), "ema": tr.ema.cpu(), "levels": levels, "N": args.N,
-                "channels": channels_for(levels), "head": 32, "steps": tr.step}, args.out)
-    summary = {"held_out_init_median": float(np.median(base)), "held_out_median": float(np.median(ev)),
+    summary = {"held_out_zero_init_median": float(np.median(zero)),
+               "held_out_start_median": float(np.median(base0)), "held_out_median": float(np.median(ev)),
                "held_out_max": float(ev.max()), "held_out_no_injection_median": float(np.median(ev_noinj)),
-               "steps": tr.step, "seconds": time.time() - t_start}
+               "step": tr.step, "seconds": time.time() - t_start, "ms_per_step": (time.time() - t_start) / max(k, 1) * 1e3}
     print("# " + json.dumps(summary), flush=True)
+    if args.export:
+        save_weights(args.export, tr.ema, levels, args.N, "elastic", meta={"step": tr.step, **summary})
+        print(f"# exported EMA weights to {args.export}", flush=True)
     if args.log:
         with open(args.log, "w") as fh:
             json.dump({"summary": summary, "log": log}, fh)

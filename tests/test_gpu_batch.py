@@ -1,0 +1,106 @@
+"""GPU: captured-graph PCG and the batched solve of uneven cells.
+
+The graph path replays captured blocks of PCG iterations; it must reach the
+same FP64-checked tolerance and the same C_H as launch-by-launch PCG and as
+the oracle.  Replays are interleaved with other work on the same hierarchy
+and checked after every call.  The batched solve (worker threads, one stream
+each) must give every cell the result of its own single-cell solve.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gmt_inputs import gyroid_sheet, spinodal, truss, workload_cell  # noqa: E402
+from oracle import solve as osolve  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _gmt():
+    from paper_2604_26518_amd import binding
+    return binding
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def gyroid():
+    vox = gyroid_sheet(32, 0, 0.3)
+    P = osolve.Problem(vox, 4, "elastic")
+    u_ref, _ = osolve.pcg(P, tol=1e-11)
+    return vox, osolve.homogenize(P, u_ref)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_graph_matches_eager_and_oracle(gyroid, precision):
+    vox, C_ref = gyroid
+    H = _gmt().Hierarchy(vox, 4)
+    f = H.load_vector()
+    tol = 1e-9 if precision == "f64" else 1e-6
+    u_e, rep_e = H.solve(f, tol=tol, precision=precision, graph=False)
+    C_e = H.homogenize(u_e)
+    for rep_no in range(3):
+        # other work on the same hierarchy between the replays
+        H.apply_K(u_e.to(torch.float32) if precision == "f32" else u_e, 1)
+        u_g, rep_g = H.solve(f, tol=tol, precision=precision, graph=True)
+        C_g = H.homogenize(u_g)
+        print(f"[graph {precision}] replay {rep_no}: its {rep_g['iterations']} (eager {rep_e['iterations']}) "
+              f"res {max(rep_g['rel_res']):.2e}", flush=True)
+        assert rep_g["converged"] and max(rep_g["rel_res"]) <= tol
+        # blocks of 4 may overshoot the eager count by at most 3 iterations per inner solve
+        assert rep_g["iterations"] <= rep_e["iterations"] + 3 * rep_g["outer"]
+        bound = 1e-8 if precision == "f64" else 1e-4
+        assert _rel(C_g, C_ref) <= bound and _rel(C_e, C_ref) <= bound
+        assert _rel(C_g, C_e) <= bound
+    H.close()
+
+
+def _batch_cells():
+    cells = [
+        (gyroid_sheet(32, 1, 0.3), 4, "elastic"),
+        (truss(16, 3, 0.35), 3, "elastic"),
+        (spinodal(24, 5, 0.4), 3, "thermal"),
+        (gyroid_sheet(16, 2, 0.25), 3, "thermal"),
+        (workload_cell(32, 1004)[2], 4, "elastic"),
+        (workload_cell(24, 1003)[2], 3, "elastic"),
+    ]
+    return cells
+
+
+@pytest.mark.parametrize("precision,workers", [("f64", 3), ("f32", 4), ("f32", 1)])
+def test_batch_matches_single_cell_solves(precision, workers):
+    B = _gmt()
+    hs, fs, singles = [], [], []
+    tol = 1e-8 if precision == "f64" else 1e-5
+    for vox, L, phys in _batch_cells():
+        H = B.Hierarchy(vox, L, phys)
+        f = H.load_vector()
+        u, rep = H.solve(f, tol=tol, precision=precision)
+        singles.append(H.homogenize(u))
+        hs.append(H)
+        fs.append(f)
+    us, reps = B.solve_batch(hs, fs, tol=tol, precision=precision, n_workers=workers)
+    torch.cuda.synchronize()
+    for k, (H, u, rep, C1) in enumerate(zip(hs, us, reps, singles)):
+        res = H.relative_residual(fs[k], u)
+        Cb = H.homogenize(u)
+        print(f"[batch {precision} w{workers}] cell {k} N={H.N} {H.physics}: its {rep['iterations']} "
+              f"res {res.max():.2e} dC {_rel(Cb, C1):.1e}", flush=True)
+        assert rep["converged"] and rep["status"] == 0
+        assert res.max() <= tol * (1 + 1e-6)
+        assert _rel(Cb, C1) <= (1e-8 if precision == "f64" else 1e-4)
+    for H in hs:
+        H.close()
+
+
+def test_batch_rejects_repeated_hierarchy():
+    B = _gmt()
+    H = B.Hierarchy(gyroid_sheet(16, 0, 0.3), 3)
+    f = H.load_vector()
+    with pytest.raises(B.GmtError):
+        B.solve_batch([H, H], [f, f.clone()])
+    H.close()
