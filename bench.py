@@ -5,7 +5,8 @@ lattice families (gyroid / Schwarz-P / diamond sheets, periodic truss,
 spinodal; family = seed mod 5, VF ~ U(0.15, 0.5), seeds 1000..1063).  Every
 cell goes through the whole path: sparse hierarchy + Galerkin operators +
 coarse factor, load vector, mixed-precision GMG-PCG (FP32 bulk, FP64
-refinement) to relative residual 1e-5, and the FP64 C_H reduction.
+refinement) to relative residual 1e-5 -- all cells in one batched call
+(gmt_solve_batch) -- and the FP64 C_H reduction.
 
 Prints one JSON line (see the design doc for the field definitions).
 """
@@ -44,6 +45,87 @@ def make_cells(N, seeds):
     procs = max(1, min(16, os.cpu_count() or 1))
     with mp.get_context("fork").Pool(procs) as pool:
         return pool.map(_gen, [(s, N) for s in seeds])
+
+
+UNEVEN_SIZES = (64, 96, 128, 192, 256)
+
+
+def _gen_uneven(seed):
+    from gmt_inputs.lattices import workload_cell
+    N = UNEVEN_SIZES[(seed // 5) % 5]  # independent of the family (seed mod 5)
+    fam, vf, vox = workload_cell(N, seed)
+    return seed, fam, vf, vox, ("elastic" if seed % 2 == 0 else "thermal")
+
+
+def uneven_batch(args):
+    """The uneven batched workload: 256 cells, N uniform over {64, 96, 128, 192, 256}, mixed
+    families, even seeds elastic (6 cases) and odd seeds thermal (3 cases), FP32 bulk + FP64
+    refinement to 1e-5.  Cells go to gmt_solve_batch in chunks that fit a memory budget."""
+    import torch
+
+    from paper_2604_26518_amd import binding as B
+
+    seeds = list(range(2000, 2000 + args.cells))
+    procs = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(procs) as pool:
+        cells = pool.map(_gen_uneven, seeds, chunksize=2)
+    print(f"# generated {len(cells)} uneven cells in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    budget = args.mem_gb * 2**30
+
+    def run(record):
+        order = sorted(range(len(cells)), key=lambda k: -cells[k][3].size)
+        t_all = time.perf_counter()
+        solve_s, dofs, its, k = 0.0, 0, [], 0
+        while k < len(order):
+            hs, fs, idx = [], [], []
+            while k < len(order) and (not hs or torch.cuda.memory_allocated() < budget):
+                seed, fam, vf, vox, phys = cells[order[k]]
+                H = B.Hierarchy(vox, B.default_levels(vox.shape[0]), phys)
+                hs.append(H)
+                fs.append(H.load_vector())
+                idx.append(order[k])
+                k += 1
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            us, reps = B.solve_batch(hs, fs, tol=args.tol, precision="f32", max_iter=args.max_iter,
+                                     n_workers=args.workers, graph=not args.no_graph, raise_on_noconv=False)
+            solve_s += time.perf_counter() - ts
+            for H, u, rep, j in zip(hs, us, reps, idx):
+                H.homogenize(u)
+                if not rep["converged"]:
+                    raise RuntimeError(f"cell seed {cells[j][0]} did not converge: {rep}")
+                dofs += H.n_n(1) * H.c * H.d
+                its.append(rep["iterations"])
+                if record is not None:
+                    record.append({"seed": cells[j][0], "N": H.N, "physics": H.physics, "its": rep["iterations"]})
+                H.close()
+            del us, fs, hs
+            print(f"# {k}/{len(order)} cells done", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t_all, solve_s, dofs, its
+
+    for w in range(args.warmup):
+        run(None)
+    record = []
+    wall, solve_s, dofs, its = 0.0, 0.0, 0, []
+    for _ in range(args.steps):
+        a, b, c, d = run(record if not record else None)
+        wall, solve_s, dofs, its = wall + a, solve_s + b, dofs + c, its + d
+    ncell = args.steps * len(cells)
+    out = {"metric": "ms per cell, uneven batched solve to 1e-5 (whole path incl. build and C_H)",
+           "value": round(wall / ncell * 1e3, 3), "unit": "ms/cell", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 2), "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{len(cells)} cells, N uniform over {list(UNEVEN_SIZES)}, mixed families, VF "
+                                  f"U(0.15,0.5), half elasticity (6 cases) half heat conduction (3 cases), FP32 "
+                                  f"bulk + FP64 refinement to {args.tol:g}, gmt_solve_batch in memory-bounded "
+                                  f"chunks", "cells": len(cells), "workers": args.workers,
+                      "graph": not args.no_graph},
+           "ms_per_cell_solve_only": round(solve_s / ncell * 1e3, 3),
+           "dof_solves_per_s": round(dofs / wall, 1), "iterations_mean": float(np.mean(its)),
+           "iterations_max": int(np.max(its))}
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(tol):
@@ -99,6 +181,11 @@ def main():
     ap.add_argument("--max-iter", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--workers", type=int, default=4, help="host threads / streams of the batched solve")
+    ap.add_argument("--no-graph", action="store_true", help="launch PCG kernel by kernel")
+    ap.add_argument("--workload", default="cells128", choices=["cells128", "uneven"],
+                    help="cells128: the headline 64-cell 128^3 batch; uneven: 256 cells of mixed size and physics")
+    ap.add_argument("--mem-gb", type=float, default=120.0, help="uneven workload: GPU memory per solve chunk")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -110,6 +197,12 @@ def main():
     from paper_2604_26518_amd import binding as B
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "uneven":
+        if args.cells == 64:
+            args.cells = 256
+        torch.cuda.set_device(0)
+        uneven_batch(args)
+        return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
@@ -123,16 +216,18 @@ def main():
           file=sys.stderr, flush=True)
 
     def step(record=None):
-        solve_s = 0.0
+        """One pass of the path over the batch: hierarchies, loads, one batched mixed-precision
+        solve (worker threads x streams, captured-graph PCG blocks), C_H per cell."""
+        hs = [B.Hierarchy(vox, levels, "elastic") for vox in vox_dev]
+        fs = [H.load_vector() for H in hs]
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        us, reps = B.solve_batch(hs, fs, tol=args.tol, precision="f32", max_iter=args.max_iter,
+                                 n_workers=args.workers, graph=not args.no_graph, raise_on_noconv=False)
+        solve_s = time.perf_counter() - ts
         dofs = 0
         its = []
-        for k, vox in enumerate(vox_dev):
-            H = B.Hierarchy(vox, levels, "elastic")
-            f = H.load_vector()
-            torch.cuda.synchronize()
-            ts = time.perf_counter()
-            u, rep = H.solve(f, tol=args.tol, precision="f32", max_iter=args.max_iter)
-            solve_s += time.perf_counter() - ts
+        for k, (H, u, rep) in enumerate(zip(hs, us, reps)):
             CH = H.homogenize(u)
             if not rep["converged"]:
                 raise RuntimeError(f"cell {k} did not converge: {rep}")
@@ -142,7 +237,9 @@ def main():
                 record.append({"seed": cells[k][0], "family": cells[k][1], "n_n": H.n_n(1),
                                "its": rep["iterations"], "outer": rep["outer"],
                                "res": max(rep["rel_res"]), "C11": float(CH[0, 0])})
+        for H in hs:
             H.close()
+        del us, fs
         return solve_s, dofs, its
 
     for w in range(args.warmup):
@@ -209,8 +306,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{len(vox_dev)} elasticity cells at {args.N}^3, mixed TPMS-sheet/truss/"
                                f"spinodal families, VF U(0.15,0.5), plain GMG-PCG (FP32 bulk, FP64 "
-                               f"refinement) to {args.tol:g}, whole path incl. hierarchy build",
-                   "cells": len(vox_dev), "N": args.N, "levels": levels, "tol": args.tol},
+                               f"refinement) to {args.tol:g}, batched solve, whole path incl. hierarchy "
+                               f"build and C_H",
+                   "cells": len(vox_dev), "N": args.N, "levels": levels, "tol": args.tol,
+                   "workers": args.workers, "graph": not args.no_graph},
         "ms_per_cell_solve_only": round(ms_cell_solve, 3),
         "dof_solves_per_s": round(dofs / wall, 1),
         "iterations_mean": float(np.mean(its_all)),

@@ -544,7 +544,8 @@ static void vcycle(Hier& h, const T* f0, T* u0, bool u0_zero, const T* const* e_
 // The operator sweeps of a level have a launch shape: workgroup size (256 or
 // 64), cases per thread (all c, or 1 with one grid row per case) and plain or
 // XCD-contiguous workgroup numbering; level 1 always uses 256-wide groups and
-// all cases per thread.  Before the first solve of a hierarchy, every
+// chooses between one pass over the neighbourhood for all cases and one pass
+// per case.  Before the first solve of a hierarchy, every
 // candidate is timed on every level (K.u on the work vectors: 2 warm-up and 3
 // timed launches between HIP events) and the fastest is kept.  Choices are
 // cached per (d, c, precision, operator kind, log2 of the node count, node
@@ -595,6 +596,7 @@ static void autotune(Hier& h, hipStream_t s) {
     T* y = l == 0 ? W.pz : W.r[l];
     launch_fill<T>(x, (size_t)d.n_n * h.Q, T(0), s);
     std::vector<Shape> cand = {{256, 0, 1}, {256, 0, 0}};
+    if (l == 0 && h.C > 1) cand.insert(cand.end(), {{256, 1, 1}, {256, 1, 0}});
     if (l > 0) {
       cand.insert(cand.end(), {{64, 0, 1}, {64, 0, 0}});
       if (h.C > 1) cand.insert(cand.end(), {{256, 1, 1}, {256, 1, 0}, {64, 1, 1}, {64, 1, 0}});
@@ -745,21 +747,24 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
         });
       G.key = key;
     }
+    // progress measure before the first iteration: ||r_m|| = ||b_m||
+    worst = 0;
+    for (int c = 0; c < C; ++c)
+      if (bn2[c] > 0 && tol[c] > 0) worst = std::max(worst, 1.0 / tol[c]);
     double prev = -1;
     int prev_k = 1;
     while (it < maxit) {
-      // four-iteration blocks while the observed rate predicts more than two
-      // iterations to go, single iterations near the end
-      int k = 4;
-      if (maxit - it < 4) k = 1;
-      if (prev > 0 && worst < prev && std::isfinite(worst)) {
+      // one iteration first; then four-iteration blocks while the observed
+      // convergence rate predicts more than four iterations to go
+      int k = 1;
+      if (prev > 0 && worst < prev && std::isfinite(worst) && maxit - it >= 4) {
         const double rate = std::pow(worst / prev, 1.0 / prev_k);
-        if (rate < 1 && std::log(worst) / -std::log(rate) <= 2.0) k = 1;
+        if (rate < 1 && std::log(worst) / -std::log(rate) > 4.0) k = 4;
       }
       GMT_HIP(hipGraphLaunch(G.exec[k == 1 ? 0 : 1], s));
       it += k;
       prev = worst;
-      prev_k = k;
+      prev_k = k;  // (worst is refreshed by converged() below)
       host_dot(h, rr, C, rr_h, s);
       if (converged()) break;
       if (worst < 0.98 * best) {

@@ -149,6 +149,113 @@ __global__ __launch_bounds__(kBlock) void k_apply_interior(LevelView<T> L, int C
   }
 }
 
+// The same two level-1 operators with the loop order turned round: each
+// neighbour (interior) or element corner (boundary) is loaded for all C cases
+// at once and its coefficient block is applied to every case, so a node's
+// neighbourhood is read in one pass instead of C passes (shorter reuse
+// distance for the neighbouring waves' gathers, one scalar load per
+// coefficient per wave).  The autotuner picks between the two orders.
+template <typename T, int D, int C, int EPI>
+__global__ __launch_bounds__(kBlock) void k_apply_interior_nc(LevelView<T> L, const T* __restrict__ u, EpiArgs<T> e) {
+  const int t = block_index(L.xcd) * kBlock + threadIdx.x;
+  if (t >= L.n_int) return;
+  const int i = L.interior[t];
+  const int N = L.N;
+  const size_t n = (size_t)L.n_n;
+  const int lin = L.node_lin[i];
+  const int x = lin % N, y = (lin / N) % N, z = lin / (N * N);
+  int nb[27];
+  neighbour_ids<true>(L.node_map, N, x, y, z, nb);
+  const cptr<T> S = as_const(L.S);
+  T acc[C][D], uself[C][D];
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int q = 0; q < D; ++q) acc[c][q] = T(0);
+#pragma unroll
+  for (int j = 0; j < 27; ++j) {
+    T v[C][D];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int q2 = 0; q2 < D; ++q2) v[c][q2] = u[vix(c, n, nb[j], D, q2)];
+    if (j == 13) {
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int q = 0; q < D; ++q) uself[c][q] = v[c][q];
+    }
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+#pragma unroll
+      for (int q2 = 0; q2 < D; ++q2)
+        if (stencil_nonzero<D>(j, q, q2)) {
+          const T sc = S[(j * D + q) * D + q2];
+#pragma unroll
+          for (int c = 0; c < C; ++c) acc[c][q] = fma(sc, v[c][q2], acc[c][q]);
+        }
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int q = 0; q < D; ++q) epilogue<T, EPI>(e, vix(c, n, i, D, q), acc[c][q], uself[c][q], (size_t)i * D + q);
+}
+
+template <typename T, int D, int C, int EPI>
+__global__ __launch_bounds__(kBlock) void k_apply_boundary_nc(LevelView<T> L, const T* __restrict__ u, EpiArgs<T> e) {
+  const int t = block_index(L.xcd) * kBlock + threadIdx.x;
+  if (t >= L.n_bnd) return;
+  const int i = L.boundary[t];
+  const int N = L.N;
+  const size_t n = (size_t)L.n_n;
+  const int lin = L.node_lin[i];
+  const int x = lin % N, y = (lin / N) % N, z = lin / (N * N);
+  int nb[27];
+  neighbour_ids<false>(L.node_map, N, x, y, z, nb);
+  const unsigned occ = L.occ8[i];
+  constexpr int M = 8 * D;
+  const cptr<T> K = as_const(L.K);
+  T acc[C][D];
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int q = 0; q < D; ++q) acc[c][q] = T(0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (occ & (1u << k)) {
+      const int a = 7 - k;
+      const int ak = k & 1, bk = (k >> 1) & 1, ck = (k >> 2) & 1;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        // corners of an active element are active: nb >= 0
+        const int id = nb[(ak + (m & 1)) + 3 * (bk + ((m >> 1) & 1)) + 9 * (ck + ((m >> 2) & 1))];
+        T v[C][D];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+          for (int q2 = 0; q2 < D; ++q2) v[c][q2] = u[vix(c, n, id, D, q2)];
+#pragma unroll
+        for (int q = 0; q < D; ++q)
+#pragma unroll
+          for (int q2 = 0; q2 < D; ++q2) {
+            const T kc = K[(a * D + q) * M + m * D + q2];
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c][q] = fma(kc, v[c][q2], acc[c][q]);
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const size_t idx = vix(c, n, i, D, q);
+      T uself = T(0);
+      if constexpr (EPI == EPI_JACOBI || EPI == EPI_CHEB || EPI == EPI_CHEB0) uself = u[idx];
+      epilogue<T, EPI>(e, idx, acc[c][q], uself, (size_t)i * D + q);
+    }
+}
+
 // Level 1, boundary nodes: element-by-element over the active octant
 // elements (occupancy bits), shared K_e with wave-uniform coefficients.  The 8
 // corner values of an element are loaded inside that element's branch, which
@@ -976,10 +1083,17 @@ static void launch_coarse(const LevelView<T>& L, int kind, int rows, const T* u,
 template <typename T, int D, int C, int EPI>
 static void apply_dispatch_kind(const LevelView<T>& L, int kind, const T* u, const EpiArgs<T>& e, hipStream_t s) {
   if (kind == KIND_SHARED) {
-    if (L.n_int > 0)
-      hipLaunchKernelGGL((k_apply_interior<T, D, EPI>), dim3(blocks_for(L.n_int)), dim3(kBlock), 0, s, L, C, u, e);
-    if (L.n_bnd > 0)
-      hipLaunchKernelGGL((k_apply_boundary<T, D, EPI>), dim3(blocks_for(L.n_bnd)), dim3(kBlock), 0, s, L, C, u, e);
+    if (L.cb == 0) {  // all cases per neighbour load
+      if (L.n_int > 0)
+        hipLaunchKernelGGL((k_apply_interior_nc<T, D, C, EPI>), dim3(blocks_for(L.n_int)), dim3(kBlock), 0, s, L, u, e);
+      if (L.n_bnd > 0)
+        hipLaunchKernelGGL((k_apply_boundary_nc<T, D, C, EPI>), dim3(blocks_for(L.n_bnd)), dim3(kBlock), 0, s, L, u, e);
+    } else {          // one case per pass over the neighbourhood
+      if (L.n_int > 0)
+        hipLaunchKernelGGL((k_apply_interior<T, D, EPI>), dim3(blocks_for(L.n_int)), dim3(kBlock), 0, s, L, C, u, e);
+      if (L.n_bnd > 0)
+        hipLaunchKernelGGL((k_apply_boundary<T, D, EPI>), dim3(blocks_for(L.n_bnd)), dim3(kBlock), 0, s, L, C, u, e);
+    }
   } else {
     if (L.n_n == 0) return;
     if (L.cb == 1 && C > 1)
