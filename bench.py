@@ -31,6 +31,11 @@ HBM_PEAK_GBS = 8000.0
 # read u 72 + f 72 + D^-1 12 + d 72, write u' 72 + d 72
 CHEB_BYTES_PER_NODE = 372
 COPY_BYTES = 512 << 20
+# HBM bytes of one level-1 Chebyshev sweep on the first bench cell (seed 1000, 128^3), from the
+# FETCH_SIZE / write-request counters of the interior + boundary kernels, each scaled by what the
+# counter reports for a copy of known size (profiles/level1_chebyshev_sweep_gyroid128_hbm_traffic.txt).
+# It describes the kernels as they were profiled; re-profile after changing them.
+SWEEP_TRAFFIC_BYTES = {1000: 374_789_215}
 WEIGHTS = os.path.join(ROOT, "paper_2604_26518_amd", "weights", "unet128_elastic.npz")
 
 
@@ -73,6 +78,8 @@ def uneven_batch(args):
     print(f"# generated {len(cells)} uneven cells in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     budget = args.mem_gb * 2**30
 
+    failed = []
+
     def run(record):
         order = sorted(range(len(cells)), key=lambda k: -cells[k][3].size)
         t_all = time.perf_counter()
@@ -89,12 +96,14 @@ def uneven_batch(args):
             torch.cuda.synchronize()
             ts = time.perf_counter()
             us, reps = B.solve_batch(hs, fs, tol=args.tol, precision="f32", max_iter=args.max_iter,
-                                     n_workers=args.workers, graph=not args.no_graph, raise_on_noconv=False)
+                                     max_outer=16, n_workers=args.workers, graph=not args.no_graph,
+                                     raise_on_noconv=False)
             solve_s += time.perf_counter() - ts
             for H, u, rep, j in zip(hs, us, reps, idx):
                 H.homogenize(u)
                 if not rep["converged"]:
-                    raise RuntimeError(f"cell seed {cells[j][0]} did not converge: {rep}")
+                    failed.append({"seed": cells[j][0], "N": H.N, "physics": H.physics,
+                                   "residual": max(rep["rel_res"]), "iterations": rep["iterations"]})
                 dofs += H.n_n(1) * H.c * H.d
                 its.append(rep["iterations"])
                 if record is not None:
@@ -124,7 +133,7 @@ def uneven_batch(args):
                       "graph": not args.no_graph},
            "ms_per_cell_solve_only": round(solve_s / ncell * 1e3, 3),
            "dof_solves_per_s": round(dofs / wall, 1), "iterations_mean": float(np.mean(its)),
-           "iterations_max": int(np.max(its))}
+           "iterations_max": int(np.max(its)), "not_converged": failed}
     print(json.dumps(out), flush=True)
 
 
@@ -315,7 +324,8 @@ def main():
         "iterations_mean": float(np.mean(its_all)),
         "iterations_max": int(np.max(its_all)),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": SWEEP_TRAFFIC_BYTES.get(cells[0][0]) if args.N == 128 else None,
                      "kernel": "level-1 Chebyshev sweep", **kernel_info,
                      "copy_GBps": round(copy_gbs, 1)},
     }

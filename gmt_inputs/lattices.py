@@ -275,11 +275,21 @@ def cell(family: str, N: int, seed: int, vf: float) -> np.ndarray:
 
 
 def workload_cell(N: int, seed: int):
-    """Mixed-family cell of the batched workloads: family = seed mod 5, VF ~ U(0.15, 0.5)."""
+    """Mixed-family cell of the batched workloads: family = seed mod 5, VF ~ U(0.15, 0.5).
+
+    A draw that cannot be made at the sampled VF (a thin spinodal that does not
+    percolate after cleanup) is repeated at VF + 0.05; the returned VF is the one used.
+    """
     rng = np.random.default_rng([seed, 7])
     vf = float(rng.uniform(0.15, 0.5))
     fam = FAMILIES[seed % 5]
-    return fam, vf, cell(fam, N, seed, vf)
+    while True:
+        try:
+            return fam, vf, cell(fam, N, seed, vf)
+        except RuntimeError:
+            if vf >= 0.5:
+                raise
+            vf = min(0.5, vf + 0.05)
 
 
 def random_vectors(n: int, q: int, seed: int, dtype=np.float64) -> np.ndarray:

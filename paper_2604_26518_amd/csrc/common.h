@@ -56,6 +56,10 @@ struct LevelView {
   int zero;  // always 0 (defeats loop-invariant hoisting of coefficient loads)
   const int* interior;
   const int* boundary;
+  // level 1: chunk starts of the interior list (runs of consecutive nodes along x),
+  // n_runs + 1 entries with runs[n_runs] = n_int
+  int n_runs;
+  const int* runs;
   const T* S;
   // launch shape of this level's operator sweeps (chosen by the autotuner):
   // workgroup size (64 or 256), cases per thread (1, or all c) -- levels >= 2
@@ -127,9 +131,9 @@ void launch_gauge_shift(T* u, int n, int Q, int D, T* tmp, hipStream_t s);
 // v -= column mean over nodes (projection off the rigid translations)
 template <typename T>
 void launch_project(T* v, int n, int Q, int D, double* partial, double* sums, hipStream_t s);
-// u64 += (double) d
+// u64 += a * (double) d
 template <typename T>
-void launch_accumulate(double* u, const T* d, size_t n, hipStream_t s);
+void launch_accumulate(double* u, const T* d, size_t n, hipStream_t s, double a = 1.0);
 
 // hierarchy construction kernels
 void launch_voxel_elem_flags(const uint8_t* vox, size_t n, int* flags, hipStream_t s);
@@ -142,6 +146,7 @@ size_t scan_scratch_ints(size_t n);
 void launch_occ8(const int* node_lin, int n_n, const int* elem_map, int N, uint8_t* occ8,
                  hipStream_t s);
 void launch_occ_flags(const uint8_t* occ8, int n, int want_full, int* flags, hipStream_t s);
+void launch_run_flags(const int* interior, int n_int, const int* node_lin, int N, int* flags, hipStream_t s);
 void launch_gather_cmask(const int* elem_lin, int n_e, const uint8_t* dense_cmask, uint8_t* cmask,
                          hipStream_t s);
 void launch_elem_nodes(const int* elem_lin, int n_e, const int* node_map, int N, int* out,
@@ -175,6 +180,8 @@ struct LevelData {
   int* interior = nullptr;    // level 1: nodes with occupancy 255
   int* boundary = nullptr;    // level 1: the other nodes
   int n_int = 0, n_bnd = 0;
+  int* runs = nullptr;        // level 1: chunk starts of `interior` (+ sentinel)
+  int n_runs = 0;
   double* Kel64 = nullptr;    // per element, levels >= 3
   float* Kel32 = nullptr;
   double* diag64 = nullptr;   // [n_n][d]
@@ -223,7 +230,9 @@ struct Hier {
   // FP64 / FP32 level-1 scratch vectors of the solve and query entry points
   double *s_r64 = nullptr, *s_t64 = nullptr, *s_x64 = nullptr, *s_f64s = nullptr, *s_u64s = nullptr;
   float *s_b32 = nullptr, *s_x32 = nullptr;
-  std::vector<void*> owned;
+  std::vector<void*> owned;      // from the caller's allocation callback
+  std::vector<void*> owned_hip;  // from hipMalloc (no callback, or local_alloc)
+  bool local_alloc = false;      // allocate with hipMalloc even when a callback is set
   void* nn = nullptr;  // learned-initializer state (nn.hip)
   // captured blocks of inner PCG iterations (1 and 4 iterations), per precision;
   // valid while `key` (cycle parameters and iterate buffer) is unchanged

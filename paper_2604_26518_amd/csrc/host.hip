@@ -52,28 +52,34 @@ static gmt_status guarded(F&& fn) {
 
 void* Hier::raw_alloc(size_t bytes) {
   void* ptr = nullptr;
-  if (p.alloc) {
+  const bool callback = p.alloc && !local_alloc;
+  if (callback) {
     ptr = p.alloc(bytes, p.alloc_ctx);
     if (!ptr) fail(GMT_E_NOMEM, "allocator callback returned NULL for %zu bytes", bytes);
+    owned.push_back(ptr);
   } else {
     hipError_t e = hipMalloc(&ptr, bytes);
     if (e != hipSuccess || !ptr) {
       (void)hipGetLastError();
       fail(GMT_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     }
+    owned_hip.push_back(ptr);
   }
-  owned.push_back(ptr);
   return ptr;
 }
 
 void Hier::release(void* q) {
   auto it = std::find(owned.begin(), owned.end(), q);
-  if (it == owned.end()) return;
-  owned.erase(it);
-  if (p.release)
-    p.release(q, p.alloc_ctx);
-  else
+  if (it != owned.end()) {
+    owned.erase(it);
+    if (p.release) p.release(q, p.alloc_ctx);
+    return;
+  }
+  auto jt = std::find(owned_hip.begin(), owned_hip.end(), q);
+  if (jt != owned_hip.end()) {
+    owned_hip.erase(jt);
     (void)hipFree(q);
+  }
 }
 
 void Hier::release_graphs() {
@@ -86,13 +92,18 @@ void Hier::release_graphs() {
 }
 
 void Hier::release_all() {
-  for (void* q : owned) {
-    if (p.release)
-      p.release(q, p.alloc_ctx);
-    else if (!p.alloc)
-      (void)hipFree(q);
-  }
+  for (void* q : owned)
+    if (p.release) p.release(q, p.alloc_ctx);
   owned.clear();
+  for (void* q : owned_hip) (void)hipFree(q);
+  owned_hip.clear();
+}
+
+// GMT_FORCE_L1_VARIANT=<cb> pins the level-1 sweep variant (0..3, see the
+// autotuner) for tests that compare every variant with the oracle.
+static int forced_l1_variant() {
+  const char* e = std::getenv("GMT_FORCE_L1_VARIANT");
+  return e && *e ? std::atoi(e) : -1;
 }
 
 template <typename T>
@@ -110,6 +121,8 @@ LevelView<T> Hier::view(int l) const {
   v.n_bnd = d.n_bnd;
   v.interior = d.interior;
   v.boundary = d.boundary;
+  v.n_runs = d.n_runs;
+  v.runs = d.runs;
   if constexpr (std::is_same<T, double>::value) {
     v.K = d.kind == KIND_SHARED ? Ke64 : (d.kind == KIND_TABLE ? table64 : d.Kel64);
     v.S = S64;
@@ -122,6 +135,10 @@ LevelView<T> Hier::view(int l) const {
     v.bs = d.bs32;
     v.xcd = d.xcd32;
     v.cb = d.cb32;
+  }
+  if (l == 0) {
+    const int f = forced_l1_variant();
+    if (f >= 0 && f <= 3) v.cb = f;
   }
   return v;
 }
@@ -544,8 +561,9 @@ static void vcycle(Hier& h, const T* f0, T* u0, bool u0_zero, const T* const* e_
 // The operator sweeps of a level have a launch shape: workgroup size (256 or
 // 64), cases per thread (all c, or 1 with one grid row per case) and plain or
 // XCD-contiguous workgroup numbering; level 1 always uses 256-wide groups and
-// chooses between one pass over the neighbourhood for all cases and one pass
-// per case.  Before the first solve of a hierarchy, every
+// chooses between one pass over the neighbourhood for all cases (boundary
+// nodes as a masked stencil, cb 0, or element by element, cb 2) and one pass
+// per case (cb 1, or cb 3 with interior nodes in runs along x).  Before the first solve of a hierarchy, every
 // candidate is timed on every level (K.u on the work vectors: 2 warm-up and 3
 // timed launches between HIP events) and the fastest is kept.  Choices are
 // cached per (d, c, precision, operator kind, log2 of the node count, node
@@ -596,7 +614,8 @@ static void autotune(Hier& h, hipStream_t s) {
     T* y = l == 0 ? W.pz : W.r[l];
     launch_fill<T>(x, (size_t)d.n_n * h.Q, T(0), s);
     std::vector<Shape> cand = {{256, 0, 1}, {256, 0, 0}};
-    if (l == 0 && h.C > 1) cand.insert(cand.end(), {{256, 1, 1}, {256, 1, 0}});
+    if (l == 0 && h.C > 1)
+      cand.insert(cand.end(), {{256, 1, 1}, {256, 1, 0}, {256, 2, 1}, {256, 2, 0}, {256, 3, 1}, {256, 3, 0}});
     if (l > 0) {
       cand.insert(cand.end(), {{64, 0, 1}, {64, 0, 0}});
       if (h.C > 1) cand.insert(cand.end(), {{256, 1, 1}, {256, 1, 0}, {64, 1, 1}, {64, 1, 0}});
@@ -615,6 +634,9 @@ static void autotune(Hier& h, hipStream_t s) {
       GMT_HIP(hipEventSynchronize(e1));
       float ms = 0;
       GMT_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (std::getenv("GMT_TIMING"))
+        fprintf(stderr, "[gmt tune]   level %d candidate bs %d cb %d xcd %d: %.1f us\n", l + 1, c.bs, c.cb, c.xcd,
+                ms * 1e3 / 3);
       if (ms < best) {
         best = ms;
         pick = c;
@@ -676,6 +698,11 @@ static Hier::PcgGraphs& graphs_of(Hier& h) {
   else
     return h.g32;
 }
+
+// inner PCG gives up after this many iterations without a 2 % gain in the
+// worst case's residual ratio (ill-conditioned cells plateau for a while
+// before converging, so the window is generous)
+constexpr int kStagnation = 300;
 
 template <typename T>
 static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int check_every, bool graph,
@@ -770,7 +797,7 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
       if (worst < 0.98 * best) {
         best = worst;
         since_best = 0;
-      } else if ((since_best += k) >= 100) {
+      } else if ((since_best += k) >= kStagnation) {
         break;  // stagnation: hand back to the FP64 refinement loop
       }
     }
@@ -790,7 +817,7 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
       if (worst < 0.98 * best) {
         best = worst;
         since_best = 0;
-      } else if ((since_best += check_every) >= 100) {
+      } else if ((since_best += check_every) >= kStagnation) {
         break;  // stagnation: hand back to the FP64 refinement loop
       }
     }
@@ -935,6 +962,16 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
         d.n_bnd = (int)cnt;
       }
     }
+    // runs of consecutive interior nodes along x (chunks of at most kRun)
+    if (d.n_int > 0) {
+      launch_run_flags(d.interior, d.n_int, d.node_lin, d.N, flags, s);
+      const int64_t nr = scan_compact(flags, d.n_int, nullptr, nullptr, scr, d_total, s);
+      d.runs = h.alloc<int>(nr + 1);
+      scan_compact(flags, d.n_int, tmpmap, d.runs, scr, d_total, s);
+      const int sentinel = d.n_int;
+      GMT_HIP(hipMemcpyAsync(d.runs + nr, &sentinel, sizeof(int), hipMemcpyHostToDevice, s));
+      d.n_runs = (int)nr;
+    }
     GMT_HIP(hipStreamSynchronize(s));
     h.release(tmpmap);
   }
@@ -1052,7 +1089,7 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
                   hipStream_t s, gmt_status* st) {
   const double tol = o && o->tol > 0 ? o->tol : 1e-5;
   const int max_iter = o && o->max_iter > 0 ? o->max_iter : 500;
-  const int max_outer = o && o->max_outer > 0 ? o->max_outer : 8;
+  const int max_outer = o && o->max_outer > 0 ? o->max_outer : 8;  // (+ one FP64 fallback switch)
   const int prec = o ? o->precision : GMT_F64;
   const int check = o && o->check_every > 0 ? o->check_every : 1;
   const bool graph = o && o->graph;
@@ -1070,6 +1107,9 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
   R.c = C;
   double rel[8], den[8];
   int its = 0;
+  int inner_prec = prec;          // precision of the next inner solve
+  bool last_f32 = false;          // the last accepted update came from an FP32 inner solve
+  double prev_worst = INFINITY;
   for (int outer = 0;; ++outer) {
     rel_residual64(h, f, u, r64, rel, den, s);
     if (outer == 0 && zero_load(h, den)) {
@@ -1089,27 +1129,45 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
       R.converged = 1;
       break;
     }
+    if (last_f32 && !(worst < 0.5 * prev_worst)) {
+      // the FP32 inner solve did not halve the FP64 residual (an ill-conditioned
+      // cell where FP32 rounding stalls or diverges): undo that update and finish
+      // with FP64 inner solves
+      launch_accumulate<float>(u, h.s_x32, tot, s, -1.0);
+      inner_prec = GMT_F64;
+      last_f32 = false;
+      rel_residual64(h, f, u, r64, rel, den, s);
+      worst = 0;
+      for (int c = 0; c < C; ++c) {
+        worst = std::isfinite(rel[c]) ? std::max(worst, rel[c]) : INFINITY;
+        R.rel_res[c] = rel[c];
+      }
+    }
     if (!std::isfinite(worst) || outer >= max_outer || its >= max_iter) break;
+    prev_worst = worst;
     double itol[8];
     // an FP32 inner solve is asked for at most four orders of reduction; the
     // FP64 refinement step recovers the rest
-    const double floor = prec == GMT_F32 ? 1e-4 : 1e-14;
+    const double floor = inner_prec == GMT_F32 ? 1e-4 : 1e-14;
     for (int c = 0; c < C; ++c) {
       // target ||r_m|| <= tol/2 * den_m after this step; relative to the current ||r_m||
       const double rn = rel[c] * den[c];
       double t = rn > 0 ? 0.5 * tol * den[c] / rn : 1.0;
       itol[c] = std::min(0.9, std::max(floor, t));
     }
-    if (prec == GMT_F32) {
+    if (inner_prec == GMT_F32) {
       if (!h.s_b32) h.s_b32 = h.alloc<float>(tot);
       if (!h.s_x32) h.s_x32 = h.alloc<float>(tot);
       launch_convert<double, float>(r64, h.s_b32, tot, s);
       its += pcg<float>(h, h.s_b32, h.s_x32, itol, max_iter - its, check, graph, cfg, s);
-      launch_accumulate<float>(u, h.s_x32, tot, s);
+      launch_accumulate<float>(u, h.s_x32, tot, s, 1.0);
+      last_f32 = true;
     } else {
+      if (prec == GMT_F32) autotune<double>(h, s);
       double* x64 = scratch64(h, &h.s_x64);
       its += pcg<double>(h, r64, x64, itol, max_iter - its, check, graph, cfg, s);
-      launch_accumulate<double>(u, x64, tot, s);
+      launch_accumulate<double>(u, x64, tot, s, 1.0);
+      last_f32 = false;
     }
   }
   launch_gauge_shift<double>(u, h.lv[0].n_n, h.Q, h.D, h.gauge_tmp64, s);
@@ -1152,6 +1210,7 @@ const char* gmt_last_error(void) { return g_last_error.c_str(); }
 
 template <typename T>
 static double time_sweep(Hier& h, int l, int reps, hipStream_t s) {
+  autotune<T>(h, s);  // time the launch shape the solver uses
   h.ensure_io<T>(l);
   Work<T>& W = h.work<T>();
   const size_t n = (size_t)h.lv[l].n_n * h.Q;
@@ -1580,6 +1639,13 @@ gmt_status gmt_solve_batch(gmt_hier_t const* hs, int32_t n, const void* const* d
         gmt_solve_report rep{};
         st[i] = guarded([&] {
           Hier& h = hs[i]->h;
+          // buffers allocated from this thread (an FP64 fallback's work vectors)
+          // come from hipMalloc, not from the caller's allocation callback
+          struct LocalAlloc {
+            Hier& h;
+            explicit LocalAlloc(Hier& hh) : h(hh) { h.local_alloc = true; }
+            ~LocalAlloc() { h.local_alloc = false; }
+          } local(h);
           const int nn = h.lv[0].n_n;
           double* f = h.s_f64s;
           double* u = h.s_u64s;

@@ -70,6 +70,31 @@ __device__ __forceinline__ void epilogue(const EpiArgs<T>& e, size_t idx, T acc,
   }
 }
 
+// The same epilogue with D^-1 of the node already loaded (it is shared by the C cases).
+template <typename T, int EPI>
+__device__ __forceinline__ void epilogue_d(const EpiArgs<T>& e, size_t idx, T acc, T uself, T dinv) {
+  if constexpr (EPI == EPI_KU) {
+    e.out[idx] = acc;
+  } else if constexpr (EPI == EPI_RESID) {
+    e.out[idx] = e.f[idx] - acc;
+  } else if constexpr (EPI == EPI_JACOBI) {
+    e.out[idx] = uself + e.omega * dinv * (e.f[idx] - acc);
+  } else if constexpr (EPI == EPI_CHEB) {
+    const T dn = e.rho1 * e.dvec[idx] + e.rho2 * dinv * (e.f[idx] - acc);
+    e.dvec[idx] = dn;
+    e.out[idx] = uself + dn;
+  } else {  // EPI_CHEB0
+    const T dn = e.rho2 * dinv * (e.f[idx] - acc);
+    e.dvec[idx] = dn;
+    e.out[idx] = uself + dn;
+  }
+}
+
+template <int EPI>
+constexpr bool needs_dinv() {
+  return EPI == EPI_JACOBI || EPI == EPI_CHEB || EPI == EPI_CHEB0;
+}
+
 // Structural zeros of the assembled interior stencil of the isotropic voxel
 // element: block (offset j, row d, column d2) vanishes unless d == d2 or the
 // offset has nonzero components along both d and d2 (elastic); for the
@@ -121,6 +146,9 @@ __global__ __launch_bounds__(kBlock) void k_apply_interior(LevelView<T> L, int C
   const int x = lin % N, y = (lin / N) % N, z = lin / (N * N);
   int nb[27];
   neighbour_ids<true>(L.node_map, N, x, y, z, nb);
+  T dv[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) dv[q] = needs_dinv<EPI>() ? e.dinv[(size_t)i * D + q] : T(0);
 #pragma unroll 1
   for (int c = 0; c < C; ++c) {
     // L.zero is 0 at run time: the coefficient address stays wave-uniform (scalar
@@ -144,9 +172,103 @@ __global__ __launch_bounds__(kBlock) void k_apply_interior(LevelView<T> L, int C
       }
     }
 #pragma unroll
-    for (int q = 0; q < D; ++q)
-      epilogue<T, EPI>(e, vix(c, n, i, D, q), acc[q], uself[q], (size_t)i * D + q);
+    for (int q = 0; q < D; ++q) epilogue_d<T, EPI>(e, vix(c, n, i, D, q), acc[q], uself[q], dv[q]);
   }
+}
+
+// Level 1, interior nodes in runs: a thread takes up to kRun consecutive
+// interior nodes of one x-row (consecutive ids).  Their 27-point stencils
+// overlap, so each of the 9 neighbour rows is read once as kRun + 2 columns
+// (instead of 3 columns per node) and the 9 row lookups are shared by the run.
+constexpr int kRun = 4;
+template <typename T, int D, int EPI>
+__global__ __launch_bounds__(kBlock) void k_apply_interior_run(LevelView<T> L, int C, const T* __restrict__ u,
+                                                               EpiArgs<T> e) {
+  const int k = block_index(L.xcd) * kBlock + threadIdx.x;
+  if (k >= L.n_runs) return;
+  const int t0 = L.runs[k];
+  const int len = L.runs[k + 1] - t0;  // 1 .. kRun
+  const int i0 = L.interior[t0];       // the run's ids are i0 .. i0 + len - 1
+  const int N = L.N;
+  const size_t n = (size_t)L.n_n;
+  const int lin = L.node_lin[i0];
+  const int x0 = lin % N, y = (lin / N) % N, z = lin / (N * N);
+  const int ys[3] = {wrapm(y - 1, N), y, wrapm(y + 1, N)};
+  const int zs[3] = {wrapm(z - 1, N), z, wrapm(z + 1, N)};
+  // columns x0 - 1 .. x0 + len of each row are active; without a periodic wrap
+  // inside that span their ids are consecutive
+  const bool fast = x0 > 0 && x0 + len < N;
+  int rb[9];
+#pragma unroll
+  for (int r = 0; r < 9; ++r) {
+    const int row = N * (ys[r % 3] + N * zs[r / 3]);
+    rb[r] = fast ? L.node_map[x0 - 1 + row] : row;
+  }
+  T dv[kRun][D];
+#pragma unroll
+  for (int m = 0; m < kRun; ++m)
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+      dv[m][q] = (needs_dinv<EPI>() && m < len) ? e.dinv[(size_t)(i0 + m) * D + q] : T(0);
+#pragma unroll 1
+  for (int c = 0; c < C; ++c) {
+    const cptr<T> S = as_const(L.S + (c & L.zero));  // see k_apply_interior
+    T acc[kRun][D], uself[kRun][D];
+#pragma unroll
+    for (int m = 0; m < kRun; ++m)
+#pragma unroll
+      for (int q = 0; q < D; ++q) acc[m][q] = uself[m][q] = T(0);
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+#pragma unroll
+      for (int col = 0; col < kRun + 2; ++col) {
+        if (col > len + 1) break;
+        const int id = fast ? rb[r] + col : L.node_map[wrapm(x0 - 1 + col, N) + rb[r]];
+        T v[D];
+#pragma unroll
+        for (int q2 = 0; q2 < D; ++q2) v[q2] = u[vix(c, n, id, D, q2)];
+#pragma unroll
+        for (int m = 0; m < kRun; ++m) {
+          const int jx = col - m;  // this column's offset + 1 from node m
+          if (jx < 0 || jx > 2) continue;
+          const int j = 9 * (r / 3) + 3 * (r % 3) + jx;
+          if (r == 4 && jx == 1) {
+#pragma unroll
+            for (int q = 0; q < D; ++q) uself[m][q] = v[q];
+          }
+#pragma unroll
+          for (int q = 0; q < D; ++q)
+#pragma unroll
+            for (int q2 = 0; q2 < D; ++q2)
+              if (stencil_nonzero<D>(j, q, q2)) acc[m][q] = fma(S[(j * D + q) * D + q2], v[q2], acc[m][q]);
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kRun; ++m)
+      if (m < len) {
+#pragma unroll
+        for (int q = 0; q < D; ++q)
+          epilogue_d<T, EPI>(e, vix(c, n, i0 + m, D, q), acc[m][q], uself[m][q], dv[m][q]);
+      }
+  }
+}
+
+// chunk starts of the interior list: t begins a run unless it continues the
+// previous interior node along x (next id, next linear index) and x is not a
+// multiple of kRun
+__global__ void k_run_flags(const int* __restrict__ interior, int n_int, const int* __restrict__ node_lin, int N,
+                            int* __restrict__ flags) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n_int) return;
+  const int i = interior[t];
+  const int lin = node_lin[i];
+  int f = 1;
+  if (t > 0) {
+    const int ip = interior[t - 1];
+    f = !(ip == i - 1 && node_lin[ip] == lin - 1 && (lin % N) % kRun != 0);
+  }
+  flags[t] = f;
 }
 
 // The same two level-1 operators with the loop order turned round: each
@@ -256,6 +378,75 @@ __global__ __launch_bounds__(kBlock) void k_apply_boundary_nc(LevelView<T> L, co
     }
 }
 
+// Level 1, boundary nodes, as a masked stencil: the 3x3 coefficient block of
+// neighbour j is the sum, over the active octant elements that contain both
+// the node and j, of the matching block of K_e (wave-uniform scalar loads
+// times a per-lane 0/1 occupancy factor).  Each neighbour is then loaded once
+// for all C cases, as in the interior kernel, and no lane diverges on the
+// occupancy pattern.  The neighbour loop is not unrolled (uniform trip count),
+// which keeps the live set to one neighbour's values and one coefficient block.
+template <typename T, int D, int C, int EPI>
+__global__ __launch_bounds__(kBlock) void k_apply_boundary_st(LevelView<T> L, const T* __restrict__ u, EpiArgs<T> e) {
+  const int t = block_index(L.xcd) * kBlock + threadIdx.x;
+  if (t >= L.n_bnd) return;
+  const int i = L.boundary[t];
+  const int N = L.N;
+  const size_t n = (size_t)L.n_n;
+  const int lin = L.node_lin[i];
+  const int x = lin % N, y = (lin / N) % N, z = lin / (N * N);
+  const unsigned occ = L.occ8[i];
+  constexpr int M = 8 * D;
+  const cptr<T> K = as_const(L.K);
+  T acc[C][D];
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int q = 0; q < D; ++q) acc[c][q] = T(0);
+#pragma unroll 1
+  for (int j = 0; j < 27; ++j) {
+    const int jx = j % 3, jy = (j / 3) % 3, jz = j / 9;
+    const int id = L.node_map[wrapm(x + jx - 1, N) + N * (wrapm(y + jy - 1, N) + N * wrapm(z + jz - 1, N))];
+    T cj[D][D];
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+#pragma unroll
+      for (int q2 = 0; q2 < D; ++q2) cj[q][q2] = T(0);
+#pragma unroll 1
+    for (int k = 0; k < 8; ++k) {
+      const int dx = jx - (k & 1), dy = jy - ((k >> 1) & 1), dz = jz - (k >> 2);
+      if (dx < 0 || dx > 1 || dy < 0 || dy > 1 || dz < 0 || dz > 1) continue;  // j is not a corner of element k
+      const T mk = (occ >> k) & 1u ? T(1) : T(0);
+      const cptr<T> Kb = K + ((7 - k) * D) * M + (dx + 2 * dy + 4 * dz) * D;
+#pragma unroll
+      for (int q = 0; q < D; ++q)
+#pragma unroll
+        for (int q2 = 0; q2 < D; ++q2) cj[q][q2] = fma(mk, Kb[q * M + q2], cj[q][q2]);
+    }
+    if (id >= 0) {
+      T v[C][D];
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int q2 = 0; q2 < D; ++q2) v[c][q2] = u[vix(c, n, id, D, q2)];
+#pragma unroll
+      for (int q = 0; q < D; ++q)
+#pragma unroll
+        for (int q2 = 0; q2 < D; ++q2)
+#pragma unroll
+          for (int c = 0; c < C; ++c) acc[c][q] = fma(cj[q][q2], v[c][q2], acc[c][q]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const size_t idx = vix(c, n, i, D, q);
+      T uself = T(0);
+      if constexpr (EPI == EPI_JACOBI || EPI == EPI_CHEB || EPI == EPI_CHEB0) uself = u[idx];
+      epilogue<T, EPI>(e, idx, acc[c][q], uself, (size_t)i * D + q);
+    }
+}
+
 // Level 1, boundary nodes: element-by-element over the active octant
 // elements (occupancy bits), shared K_e with wave-uniform coefficients.  The 8
 // corner values of an element are loaded inside that element's branch, which
@@ -273,6 +464,9 @@ __global__ __launch_bounds__(kBlock) void k_apply_boundary(LevelView<T> L, int C
   neighbour_ids<false>(L.node_map, N, x, y, z, nb);
   const unsigned occ = L.occ8[i];
   constexpr int M = 8 * D;
+  T dv[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) dv[q] = needs_dinv<EPI>() ? e.dinv[(size_t)i * D + q] : T(0);
 #pragma unroll 1
   for (int c = 0; c < C; ++c) {
     const cptr<T> K = as_const(L.K + (c & L.zero));  // see k_apply_interior
@@ -308,8 +502,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_boundary(LevelView<T> L, int C
       for (int q = 0; q < D; ++q) uself[q] = u[vix(c, n, i, D, q)];
     }
 #pragma unroll
-    for (int q = 0; q < D; ++q)
-      epilogue<T, EPI>(e, vix(c, n, i, D, q), acc[q], uself[q], (size_t)i * D + q);
+    for (int q = 0; q < D; ++q) epilogue_d<T, EPI>(e, vix(c, n, i, D, q), acc[q], uself[q], dv[q]);
   }
 }
 
@@ -484,22 +677,37 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView<T> F, LevelVie
 // ---------------------------------------------------------------- coarsest solve
 
 // u = Kinv f with Kinv the pinned inverse (symmetric, pinned rows/cols zero).
-// One thread per DOF row (node*D + d); reads Kinv column-wise (= row-wise by symmetry).
+// One thread per DOF row (node*D + d), 64 rows per workgroup; f (all C cases)
+// is staged in LDS in chunks of kCoarseChunk DOFs, so the column loop reads it
+// by broadcast while the Kinv column reads (= rows by symmetry) stay coalesced.
+constexpr int kCoarseChunk = 256;
 template <typename T, int C>
-__global__ void k_coarse_solve(const T* __restrict__ Kinv, int cn, int D, const T* __restrict__ f,
-                               T* __restrict__ u) {
-  const int row = blockIdx.x * kBlock + threadIdx.x;
-  if (row >= cn) return;
+__global__ __launch_bounds__(64) void k_coarse_solve(const T* __restrict__ Kinv, int cn, int D,
+                                                     const T* __restrict__ f, T* __restrict__ u) {
+  __shared__ T fs[kCoarseChunk * C];
   const int n = cn / D;
+  const int row = blockIdx.x * 64 + threadIdx.x;
   double acc[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = 0.0;
-  for (int j = 0; j < cn; ++j) {
-    const double kv = (double)Kinv[(size_t)j * cn + row];
-    const int node = j / D, q = j % D;
+  for (int j0 = 0; j0 < cn; j0 += kCoarseChunk) {
+    const int m = min(kCoarseChunk, cn - j0);
+    __syncthreads();
+    for (int k = threadIdx.x; k < m * C; k += 64) {
+      const int j = j0 + k / C, c = k % C;
+      fs[k] = f[vix(c, n, j / D, D, j % D)];
+    }
+    __syncthreads();
+    if (row < cn) {
+#pragma unroll 4
+      for (int jj = 0; jj < m; ++jj) {
+        const double kv = (double)Kinv[(size_t)(j0 + jj) * cn + row];
 #pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] += kv * (double)f[vix(c, n, node, D, q)];
+        for (int c = 0; c < C; ++c) acc[c] += kv * (double)fs[jj * C + c];
+      }
+    }
   }
+  if (row >= cn) return;
   const int node = row / D, q = row % D;
 #pragma unroll
   for (int c = 0; c < C; ++c) u[vix(c, n, node, D, q)] = (T)acc[c];
@@ -724,9 +932,9 @@ __global__ void k_sub_node(T* __restrict__ u, size_t total, int n, int D, const 
 }
 
 template <typename T>
-__global__ void k_accumulate(double* __restrict__ u, const T* __restrict__ d, size_t n) {
+__global__ void k_accumulate(double* __restrict__ u, const T* __restrict__ d, size_t n, double a) {
   size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) u[i] += (double)d[i];
+  if (i < n) u[i] += a * (double)d[i];
 }
 
 // ---------------------------------------------------------------- hierarchy construction
@@ -1083,13 +1291,22 @@ static void launch_coarse(const LevelView<T>& L, int kind, int rows, const T* u,
 template <typename T, int D, int C, int EPI>
 static void apply_dispatch_kind(const LevelView<T>& L, int kind, const T* u, const EpiArgs<T>& e, hipStream_t s) {
   if (kind == KIND_SHARED) {
-    if (L.cb == 0) {  // all cases per neighbour load
+    if (L.cb == 0 || L.cb == 2) {  // all cases per neighbour load
       if (L.n_int > 0)
         hipLaunchKernelGGL((k_apply_interior_nc<T, D, C, EPI>), dim3(blocks_for(L.n_int)), dim3(kBlock), 0, s, L, u, e);
-      if (L.n_bnd > 0)
-        hipLaunchKernelGGL((k_apply_boundary_nc<T, D, C, EPI>), dim3(blocks_for(L.n_bnd)), dim3(kBlock), 0, s, L, u, e);
+      if (L.n_bnd > 0) {
+        if (L.cb == 0)  // boundary as a masked stencil
+          hipLaunchKernelGGL((k_apply_boundary_st<T, D, C, EPI>), dim3(blocks_for(L.n_bnd)), dim3(kBlock), 0, s, L, u,
+                             e);
+        else            // boundary element by element
+          hipLaunchKernelGGL((k_apply_boundary_nc<T, D, C, EPI>), dim3(blocks_for(L.n_bnd)), dim3(kBlock), 0, s, L, u,
+                             e);
+      }
     } else {          // one case per pass over the neighbourhood
-      if (L.n_int > 0)
+      if (L.n_int > 0 && L.cb == 3 && L.n_runs > 0)
+        hipLaunchKernelGGL((k_apply_interior_run<T, D, EPI>), dim3(blocks_for(L.n_runs)), dim3(kBlock), 0, s, L, C, u,
+                           e);
+      else if (L.n_int > 0)
         hipLaunchKernelGGL((k_apply_interior<T, D, EPI>), dim3(blocks_for(L.n_int)), dim3(kBlock), 0, s, L, C, u, e);
       if (L.n_bnd > 0)
         hipLaunchKernelGGL((k_apply_boundary<T, D, EPI>), dim3(blocks_for(L.n_bnd)), dim3(kBlock), 0, s, L, C, u, e);
@@ -1168,10 +1385,10 @@ void launch_prolong_add(const LevelView<T>& F, const LevelView<T>& Cv, int Q, in
 
 template <typename T>
 void launch_coarse_solve(const T* cinv, int cn, int D, int C, const T* f, T* u, hipStream_t s) {
-  const unsigned g = blocks_for(cn);
-  if (C == 6) hipLaunchKernelGGL((k_coarse_solve<T, 6>), dim3(g), dim3(kBlock), 0, s, cinv, cn, D, f, u);
-  else if (C == 3) hipLaunchKernelGGL((k_coarse_solve<T, 3>), dim3(g), dim3(kBlock), 0, s, cinv, cn, D, f, u);
-  else if (C == 1) hipLaunchKernelGGL((k_coarse_solve<T, 1>), dim3(g), dim3(kBlock), 0, s, cinv, cn, D, f, u);
+  const unsigned g = (unsigned)((cn + 63) / 64);
+  if (C == 6) hipLaunchKernelGGL((k_coarse_solve<T, 6>), dim3(g), dim3(64), 0, s, cinv, cn, D, f, u);
+  else if (C == 3) hipLaunchKernelGGL((k_coarse_solve<T, 3>), dim3(g), dim3(64), 0, s, cinv, cn, D, f, u);
+  else if (C == 1) hipLaunchKernelGGL((k_coarse_solve<T, 1>), dim3(g), dim3(64), 0, s, cinv, cn, D, f, u);
   else fail(GMT_E_INVAL, "unsupported C=%d", C);
   GMT_LAUNCH_CHECK();
 }
@@ -1335,9 +1552,9 @@ void launch_gauge_shift(T* u, int n, int Q, int D, T* tmp, hipStream_t s) {
 }
 
 template <typename T>
-void launch_accumulate(double* u, const T* d, size_t n, hipStream_t s) {
+void launch_accumulate(double* u, const T* d, size_t n, hipStream_t s, double a) {
   if (!n) return;
-  hipLaunchKernelGGL(k_accumulate<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, u, d, n);
+  hipLaunchKernelGGL(k_accumulate<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, u, d, n, a);
   GMT_LAUNCH_CHECK();
 }
 
@@ -1381,6 +1598,12 @@ int64_t scan_compact(const int* flags, size_t n, int* map_out, int* lin_out, int
 void launch_occ8(const int* node_lin, int n_n, const int* emap, int N, uint8_t* occ8, hipStream_t s) {
   if (!n_n) return;
   hipLaunchKernelGGL(k_occ8, dim3(blocks_for(n_n)), dim3(kBlock), 0, s, node_lin, n_n, emap, N, occ8);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_run_flags(const int* interior, int n_int, const int* node_lin, int N, int* flags, hipStream_t s) {
+  if (!n_int) return;
+  hipLaunchKernelGGL(k_run_flags, dim3(blocks_for(n_int)), dim3(kBlock), 0, s, interior, n_int, node_lin, N, flags);
   GMT_LAUNCH_CHECK();
 }
 
@@ -1497,7 +1720,7 @@ void launch_random(double* x, size_t n, uint64_t seed, hipStream_t s) {
   template void launch_axpby<T>(T*, const T*, T, T, size_t, hipStream_t);                                    \
   template void launch_scale_add_comp<T>(T*, const T*, T, const double*, int, int, int, hipStream_t);         \
   template void launch_mul_nodewise<T>(T*, const T*, int, int, int, int, hipStream_t);                        \
-  template void launch_accumulate<T>(double*, const T*, size_t, hipStream_t);                                \
+  template void launch_accumulate<T>(double*, const T*, size_t, hipStream_t, double);                                \
   template void launch_diagonal<T>(const LevelView<T>&, int, int, T*, hipStream_t);
 
 GMT_INST_T(float)
