@@ -35,7 +35,19 @@ COPY_BYTES = 512 << 20
 # FETCH_SIZE / write-request counters of the interior + boundary kernels, each scaled by what the
 # counter reports for a copy of known size (profiles/level1_chebyshev_sweep_gyroid128_hbm_traffic.txt).
 # It describes the kernels as they were profiled; re-profile after changing them.
-SWEEP_TRAFFIC_BYTES = {1000: 374_789_215}
+# Keyed by (cell seed, level-1 sweep variant), so that a figure is reported only for the kernels
+# it was measured on.
+SWEEP_TRAFFIC_BYTES = {(1000, 7): 651_642_195}
+# level-1 sweep variants (the autotuner's choice) and the kernels each launches
+SWEEP_KERNELS = {
+    0: "k_apply_interior_nc + k_apply_boundary_st",
+    1: "k_apply_interior + k_apply_boundary",
+    2: "k_apply_interior_nc + k_apply_boundary_nc",
+    3: "k_apply_interior_run + k_apply_boundary",
+    5: "k_apply_interior + k_apply_boundary_cls",
+    6: "k_apply_interior_nc + k_apply_boundary_cls",
+    7: "k_apply_interior<PRE=1> + k_apply_boundary_cls<PRE=1>",
+}
 WEIGHTS = os.path.join(ROOT, "paper_2604_26518_amd", "weights", "unet128_elastic.npz")
 
 
@@ -279,8 +291,9 @@ def main():
     per_launch_s = H.time_sweep(1, reps=100) / 1e3
     nbytes = CHEB_BYTES_PER_NODE * H.n_n(1)
     achieved = nbytes / per_launch_s / 1e9
-    kernel_info = {"n_n": H.n_n(1), "us_per_sweep": round(per_launch_s * 1e6, 2),
-                   "kernels": "k_apply_interior<float,3,EPI_CHEB> + k_apply_boundary<float,3,EPI_CHEB>"}
+    variant = H.level_info(1)["sweep_variant"][0]
+    kernel_info = {"n_n": H.n_n(1), "us_per_sweep": round(per_launch_s * 1e6, 2), "variant": variant,
+                   "kernels": SWEEP_KERNELS.get(variant, "?") + " (float, 3 DOF, EPI_CHEB)"}
     H.close()
     # plain device copy of known size: what HBM sustains here, and the calibration run for the
     # FETCH_SIZE / WRITE_SIZE counters
@@ -325,7 +338,7 @@ def main():
         "iterations_max": int(np.max(its_all)),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": SWEEP_TRAFFIC_BYTES.get(cells[0][0]) if args.N == 128 else None,
+                     "traffic": SWEEP_TRAFFIC_BYTES.get((cells[0][0], variant)) if args.N == 128 else None,
                      "kernel": "level-1 Chebyshev sweep", **kernel_info,
                      "copy_GBps": round(copy_gbs, 1)},
     }

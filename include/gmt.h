@@ -81,6 +81,13 @@ typedef struct {
   int32_t c;   /* load cases (6 elastic, 3 thermal) */
   int32_t d;   /* DOFs per node (3 elastic, 1 thermal) */
   double lambda_max; /* power-iteration estimate of the largest eigenvalue of D^-1 K */
+  /* launch shape of this level's FP32 operator sweeps (the FP64 ones in
+   * [1]), as chosen by the timing autotuner before the first solve (or the
+   * defaults before it ran): kernel variant, workgroup size, 1 = workgroups
+   * numbered XCD-contiguously */
+  int32_t sweep_variant[2];
+  int32_t sweep_block[2];
+  int32_t sweep_xcd[2];
 } gmt_level_desc;
 
 /* Smoothing of one V-cycle.  For every level l (1..L-1) the smoother is either

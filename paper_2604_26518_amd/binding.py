@@ -39,7 +39,8 @@ class GmtParams(ct.Structure):
 
 class GmtLevelDesc(ct.Structure):
     _fields_ = [("N", ct.c_int32), ("n_e", ct.c_int32), ("n_n", ct.c_int32),
-                ("c", ct.c_int32), ("d", ct.c_int32), ("lambda_max", ct.c_double)]
+                ("c", ct.c_int32), ("d", ct.c_int32), ("lambda_max", ct.c_double),
+                ("sweep_variant", ct.c_int32 * 2), ("sweep_block", ct.c_int32 * 2), ("sweep_xcd", ct.c_int32 * 2)]
 
 
 class GmtCycleOpts(ct.Structure):
@@ -230,7 +231,9 @@ class Hierarchy:
     def level_info(self, level: int) -> dict:
         d = GmtLevelDesc()
         _check(lib().gmt_level_info(self._h, level, ct.byref(d)))
-        return {"N": d.N, "n_e": d.n_e, "n_n": d.n_n, "c": d.c, "d": d.d, "lambda_max": d.lambda_max}
+        return {"N": d.N, "n_e": d.n_e, "n_n": d.n_n, "c": d.c, "d": d.d, "lambda_max": d.lambda_max,
+                "sweep_variant": tuple(d.sweep_variant), "sweep_block": tuple(d.sweep_block),
+                "sweep_xcd": tuple(d.sweep_xcd)}
 
     def n_n(self, level: int = 1) -> int:
         return self.levels[level - 1]["n_n"]

@@ -40,6 +40,53 @@ struct Failure {
 //   PERELEM: level >= 3, one Galerkin matrix per coarse element.
 enum Kind { KIND_SHARED = 0, KIND_TABLE = 1, KIND_PERELEM = 2 };
 
+// Symmetry classes of the isotropic voxel element.  Reflecting the unit cube
+// along axis d maps corner a to a ^ (1 << d) and flips the sign of DOF d, so
+// block (a, m) of K_e equals, up to the sign (-1)^(a_d + a_d2) of entry
+// (d, d2), block (0, a ^ m); with the axis permutations, an entry of block
+// (0, delta) depends only on (delta_d, the number of other set bits of delta)
+// on the diagonal and on (delta_d, delta_d2, delta_third) off it: 14 values for
+// the elastic element, 4 for the scalar one (the bit count of delta).  The host
+// derives the table from K_e and checks every entry against it.
+template <int D>
+__host__ __device__ constexpr int kcls_index(int delta, int d, int d2) {
+  if (D == 1) return ((delta & 1) + ((delta >> 1) & 1) + (delta >> 2));
+  if (d == d2) {
+    const int o = delta & ~(1 << d) & 7;
+    return ((delta >> d) & 1) * 3 + ((o & 1) + ((o >> 1) & 1) + (o >> 2));
+  }
+  const int t = 3 - d - d2;
+  return 6 + ((delta >> d) & 1) * 4 + ((delta >> d2) & 1) * 2 + ((delta >> t) & 1);
+}
+template <int D>
+__host__ __device__ constexpr bool kcls_negative(int a, int d, int d2) {
+  return D == 3 && ((((a >> d) & 1) + ((a >> d2) & 1)) & 1);
+}
+
+// Symmetry classes of the assembled interior stencil S (27 offsets o, D x D
+// blocks).  By the same reflections and axis permutations, entry (d, d2) of
+// the block of offset o is, on the diagonal, a function of (o_d != 0, the
+// number of other nonzero components) and, off it, sign(o_d o_d2) times a
+// function of (o_third != 0), and zero when o_d o_d2 = 0: 8 values for the
+// elastic element, 4 for the scalar one (the number of nonzero components).
+template <int D>
+__host__ __device__ constexpr int scls_index(int j, int d, int d2) {
+  const int o0 = j % 3 - 1, o1 = (j / 3) % 3 - 1, o2 = j / 9 - 1;
+  const int nz = (o0 != 0) + (o1 != 0) + (o2 != 0);
+  if (D == 1) return nz;
+  const int od = d == 0 ? o0 : (d == 1 ? o1 : o2);
+  if (d == d2) return (od != 0) * 3 + nz - (od != 0);
+  const int t = 3 - d - d2;
+  const int ot = t == 0 ? o0 : (t == 1 ? o1 : o2);
+  return 6 + (ot != 0);
+}
+template <int D>
+__host__ __device__ constexpr bool scls_negative(int j, int d, int d2) {
+  if (D == 1 || d == d2) return false;
+  const int o[3] = {j % 3 - 1, (j / 3) % 3 - 1, j / 9 - 1};
+  return o[d] * o[d2] < 0;
+}
+
 template <typename T>
 struct LevelView {
   int N;
@@ -61,6 +108,8 @@ struct LevelView {
   int n_runs;
   const int* runs;
   const T* S;
+  const T* kcls;  // symmetry-class values of K_e (14 elastic, 4 scalar)
+  const T* scls;  // symmetry-class values of S (8 elastic, 4 scalar)
   // launch shape of this level's operator sweeps (chosen by the autotuner):
   // workgroup size (64 or 256), cases per thread (1, or all c) -- levels >= 2
   // only -- and XCD-contiguous numbering
@@ -213,6 +262,10 @@ struct Hier {
   float* Ke32 = nullptr;
   double* S64 = nullptr;  // assembled interior stencil, 27 x D x D
   float* S32 = nullptr;
+  double* kcls64 = nullptr;  // symmetry-class values of K_e
+  float* kcls32 = nullptr;
+  double* scls64 = nullptr;  // symmetry-class values of S
+  float* scls32 = nullptr;
   double* fe64 = nullptr;
   double* table64 = nullptr;
   float* table32 = nullptr;

@@ -99,7 +99,7 @@ void Hier::release_all() {
   owned_hip.clear();
 }
 
-// GMT_FORCE_L1_VARIANT=<cb> pins the level-1 sweep variant (0..3, see the
+// GMT_FORCE_L1_VARIANT=<cb> pins the level-1 sweep variant (0..3, 5..7, see the
 // autotuner) for tests that compare every variant with the oracle.
 static int forced_l1_variant() {
   const char* e = std::getenv("GMT_FORCE_L1_VARIANT");
@@ -126,19 +126,23 @@ LevelView<T> Hier::view(int l) const {
   if constexpr (std::is_same<T, double>::value) {
     v.K = d.kind == KIND_SHARED ? Ke64 : (d.kind == KIND_TABLE ? table64 : d.Kel64);
     v.S = S64;
+    v.kcls = kcls64;
+    v.scls = scls64;
     v.bs = d.bs64;
     v.xcd = d.xcd64;
     v.cb = d.cb64;
   } else {
     v.K = d.kind == KIND_SHARED ? Ke32 : (d.kind == KIND_TABLE ? table32 : d.Kel32);
     v.S = S32;
+    v.kcls = kcls32;
+    v.scls = scls32;
     v.bs = d.bs32;
     v.xcd = d.xcd32;
     v.cb = d.cb32;
   }
   if (l == 0) {
     const int f = forced_l1_variant();
-    if (f >= 0 && f <= 3) v.cb = f;
+    if (f >= 0 && f <= 7 && f != 4) v.cb = f;
   }
   return v;
 }
@@ -563,7 +567,12 @@ static void vcycle(Hier& h, const T* f0, T* u0, bool u0_zero, const T* const* e_
 // XCD-contiguous workgroup numbering; level 1 always uses 256-wide groups and
 // chooses between one pass over the neighbourhood for all cases (boundary
 // nodes as a masked stencil, cb 0, or element by element, cb 2) and one pass
-// per case (cb 1, or cb 3 with interior nodes in runs along x).  Before the first solve of a hierarchy, every
+// per case (cb 1, or cb 3 with interior nodes in runs along x), or takes the
+// boundary nodes as a masked stencil assembled in registers from the symmetry
+// classes of K_e, with the interior one case per pass (cb 5; cb 7 with all 27
+// neighbours of a case loaded before the arithmetic) or all cases per
+// neighbour load (cb 6).
+// Before the first solve of a hierarchy, every
 // candidate is timed on every level (K.u on the work vectors: 2 warm-up and 3
 // timed launches between HIP events) and the fastest is kept.  Choices are
 // cached per (d, c, precision, operator kind, log2 of the node count, node
@@ -613,9 +622,13 @@ static void autotune(Hier& h, hipStream_t s) {
     T* x = l == 0 ? W.pr : W.u[l];
     T* y = l == 0 ? W.pz : W.r[l];
     launch_fill<T>(x, (size_t)d.n_n * h.Q, T(0), s);
+    // level 1: the variants that have won on some cell shape (the others stay
+    // selectable through GMT_FORCE_L1_VARIANT)
     std::vector<Shape> cand = {{256, 0, 1}, {256, 0, 0}};
-    if (l == 0 && h.C > 1)
-      cand.insert(cand.end(), {{256, 1, 1}, {256, 1, 0}, {256, 2, 1}, {256, 2, 0}, {256, 3, 1}, {256, 3, 0}});
+    if (l == 0) {
+      cand = {{256, 7, 1}, {256, 7, 0}, {256, 6, 1}, {256, 6, 0}};
+      if (h.C > 1) cand.insert(cand.end(), {{256, 1, 1}, {256, 1, 0}});
+    }
     if (l > 0) {
       cand.insert(cand.end(), {{64, 0, 1}, {64, 0, 0}});
       if (h.C > 1) cand.insert(cand.end(), {{256, 1, 1}, {256, 1, 0}, {64, 1, 1}, {64, 1, 0}});
@@ -706,7 +719,8 @@ constexpr int kStagnation = 300;
 
 template <typename T>
 static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int check_every, bool graph,
-               const CycleCfg& cfg, hipStream_t s) {
+               const CycleCfg& cfg, hipStream_t s, bool* reached = nullptr) {
+  if (reached) *reached = false;
   h.ensure_work<T>();
   Work<T>& W = h.work<T>();
   const int n = h.lv[0].n_n, C = h.C, D = h.D, Q = h.Q;
@@ -793,7 +807,10 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
       prev = worst;
       prev_k = k;  // (worst is refreshed by converged() below)
       host_dot(h, rr, C, rr_h, s);
-      if (converged()) break;
+      if (converged()) {
+        if (reached) *reached = true;
+        break;
+      }
       if (worst < 0.98 * best) {
         best = worst;
         since_best = 0;
@@ -813,7 +830,10 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
     if (it % check_every == 0 || it == maxit) {
       launch_dot<T>(W.pr, W.pr, n, C, D, h.red_partial, rr, s);
       host_dot(h, rr, C, rr_h, s);
-      if (converged()) break;
+      if (converged()) {
+        if (reached) *reached = true;
+        break;
+      }
       if (worst < 0.98 * best) {
         best = worst;
         since_best = 0;
@@ -999,6 +1019,65 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
             fail(GMT_E_STATE, "interior stencil entry (%d,%d,%d) expected zero", j, d, d2);
         }
     }
+    // symmetry-class values of K_e (taken from block row 0, where the sign is
+    // +1), then every entry of K_e checked against its class value
+    const int NK = D == 1 ? 4 : 14;
+    std::vector<double> kc(NK, 0.0);
+    std::vector<char> have(NK, 0);
+    double kmax = 0;
+    for (int r = 0; r < M * M; ++r) kmax = std::max(kmax, std::fabs(h.Ke[r]));
+    auto cls = [&](int delta, int d, int d2) {
+      return D == 1 ? kcls_index<1>(delta, d, d2) : kcls_index<3>(delta, d, d2);
+    };
+    for (int m = 0; m < 8; ++m)
+      for (int d = 0; d < D; ++d)
+        for (int d2 = 0; d2 < D; ++d2) {
+          const int c = cls(m, d, d2);
+          if (!have[c]) kc[c] = h.Ke[d * M + m * D + d2], have[c] = 1;
+        }
+    for (int a = 0; a < 8; ++a)
+      for (int m = 0; m < 8; ++m)
+        for (int d = 0; d < D; ++d)
+          for (int d2 = 0; d2 < D; ++d2) {
+            const bool neg = D == 1 ? kcls_negative<1>(a, d, d2) : kcls_negative<3>(a, d, d2);
+            const double v = (neg ? -1.0 : 1.0) * h.Ke[(a * D + d) * M + m * D + d2];
+            if (std::fabs(v - kc[cls(a ^ m, d, d2)]) > 1e-12 * kmax)
+              fail(GMT_E_STATE, "K_e entry (%d,%d,%d,%d) is not its symmetry-class value", a, m, d, d2);
+          }
+    // symmetry-class values of S, and every stencil entry checked against them
+    const int NS = D == 1 ? 4 : 8;
+    std::vector<double> sc(NS, 0.0);
+    std::vector<char> shave(NS, 0);
+    auto scl = [&](int j, int d, int d2) {
+      return D == 1 ? scls_index<1>(j, d, d2) : scls_index<3>(j, d, d2);
+    };
+    auto sneg = [&](int j, int d, int d2) {
+      return D == 1 ? scls_negative<1>(j, d, d2) : scls_negative<3>(j, d, d2);
+    };
+    for (int pass = 0; pass < 2; ++pass)
+      for (int j = 0; j < 27; ++j)
+        for (int d = 0; d < D; ++d)
+          for (int d2 = 0; d2 < D; ++d2) {
+            const int o[3] = {j % 3 - 1, (j / 3) % 3 - 1, j / 9 - 1};
+            const double v = S[(j * D + d) * D + d2];
+            const bool zero = D == 3 && d != d2 && o[d] * o[d2] == 0;
+            if (zero) continue;  // a structural zero (checked above)
+            const double w = (sneg(j, d, d2) ? -1.0 : 1.0) * v;
+            const int c = scl(j, d, d2);
+            if (pass == 0) {
+              if (!shave[c]) sc[c] = w, shave[c] = 1;
+            } else if (std::fabs(w - sc[c]) > 1e-12 * smax) {
+              fail(GMT_E_STATE, "stencil entry (%d,%d,%d) is not its symmetry-class value", j, d, d2);
+            }
+          }
+    h.scls64 = h.alloc<double>(NS);
+    h.scls32 = h.alloc<float>(NS);
+    GMT_HIP(hipMemcpyAsync(h.scls64, sc.data(), NS * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_convert<double, float>(h.scls64, h.scls32, NS, s);
+    h.kcls64 = h.alloc<double>(NK);
+    h.kcls32 = h.alloc<float>(NK);
+    GMT_HIP(hipMemcpyAsync(h.kcls64, kc.data(), NK * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_convert<double, float>(h.kcls64, h.kcls32, NK, s);
     h.S64 = h.alloc<double>(S.size());
     h.S32 = h.alloc<float>(S.size());
     GMT_HIP(hipMemcpyAsync(h.S64, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice, s));
@@ -1085,6 +1164,13 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
 
 // ================================================================ solve
 
+// An FP32 inner solve that needs more than this many iterations marks an
+// ill-conditioned cell (thin, nearly mechanism-like members), where the FP32
+// recurrence drifts from the true residual and each refinement step gains
+// little: such a cell needs about three times as many FP32 iterations as FP64
+// ones in total, so it continues in FP64.
+constexpr int kMaxInner32 = 200;
+
 static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, gmt_solve_report* rep,
                   hipStream_t s, gmt_status* st) {
   const double tol = o && o->tol > 0 ? o->tol : 1e-5;
@@ -1109,6 +1195,7 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
   int its = 0;
   int inner_prec = prec;          // precision of the next inner solve
   bool last_f32 = false;          // the last accepted update came from an FP32 inner solve
+  bool stalled32 = false;         // an FP32 inner solve stopped on stagnation
   double prev_worst = INFINITY;
   for (int outer = 0;; ++outer) {
     rel_residual64(h, f, u, r64, rel, den, s);
@@ -1128,6 +1215,10 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
     if (worst <= tol) {
       R.converged = 1;
       break;
+    }
+    if (stalled32 && inner_prec == GMT_F32 && worst < 0.5 * prev_worst) {
+      inner_prec = GMT_F64;
+      last_f32 = false;
     }
     if (last_f32 && !(worst < 0.5 * prev_worst)) {
       // the FP32 inner solve did not halve the FP64 residual (an ill-conditioned
@@ -1159,9 +1250,15 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
       if (!h.s_b32) h.s_b32 = h.alloc<float>(tot);
       if (!h.s_x32) h.s_x32 = h.alloc<float>(tot);
       launch_convert<double, float>(r64, h.s_b32, tot, s);
-      its += pcg<float>(h, h.s_b32, h.s_x32, itol, max_iter - its, check, graph, cfg, s);
+      bool reached = false;
+      its += pcg<float>(h, h.s_b32, h.s_x32, itol, std::min(max_iter - its, kMaxInner32), check, graph, cfg, s,
+                        &reached);
       launch_accumulate<float>(u, h.s_x32, tot, s, 1.0);
       last_f32 = true;
+      // an FP32 inner solve that stalled, or ran into kMaxInner32, short of its
+      // target: keep its update (checked above on the next pass) and take FP64
+      // inner solves from here
+      if (!reached && its < max_iter) stalled32 = true;
     } else {
       if (prec == GMT_F32) autotune<double>(h, s);
       double* x64 = scratch64(h, &h.s_x64);
@@ -1317,6 +1414,12 @@ gmt_status gmt_level_info(gmt_hier_t H, int32_t level, gmt_level_desc* out) {
     out->c = H->h.C;
     out->d = H->h.D;
     out->lambda_max = d.lam;
+    out->sweep_variant[0] = d.cb32;
+    out->sweep_variant[1] = d.cb64;
+    out->sweep_block[0] = d.bs32;
+    out->sweep_block[1] = d.bs64;
+    out->sweep_xcd[0] = d.xcd32;
+    out->sweep_xcd[1] = d.xcd64;
   });
 }
 

@@ -12,6 +12,8 @@
 // D DOFs of one case read one contiguous run of 64*D words.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace gmt {
@@ -50,27 +52,8 @@ __device__ __forceinline__ size_t vix(int c, size_t n, size_t i, int D, int d) {
 
 // ---------------------------------------------------------------- operator sweeps
 
-// Epilogue for one (case, dof) value; idx = (c*n + i)*D + d, di = i*D + d.
-template <typename T, int EPI>
-__device__ __forceinline__ void epilogue(const EpiArgs<T>& e, size_t idx, T acc, T uself, size_t di) {
-  if constexpr (EPI == EPI_KU) {
-    e.out[idx] = acc;
-  } else if constexpr (EPI == EPI_RESID) {
-    e.out[idx] = e.f[idx] - acc;
-  } else if constexpr (EPI == EPI_JACOBI) {
-    e.out[idx] = uself + e.omega * e.dinv[di] * (e.f[idx] - acc);
-  } else if constexpr (EPI == EPI_CHEB) {
-    const T dn = e.rho1 * e.dvec[idx] + e.rho2 * e.dinv[di] * (e.f[idx] - acc);
-    e.dvec[idx] = dn;
-    e.out[idx] = uself + dn;
-  } else {  // EPI_CHEB0
-    const T dn = e.rho2 * e.dinv[di] * (e.f[idx] - acc);
-    e.dvec[idx] = dn;
-    e.out[idx] = uself + dn;
-  }
-}
-
-// The same epilogue with D^-1 of the node already loaded (it is shared by the C cases).
+// Epilogue of one (case, DOF) value at idx = (c*n + i)*D + d, with D^-1 of the
+// node already loaded (it is shared by the C cases).
 template <typename T, int EPI>
 __device__ __forceinline__ void epilogue_d(const EpiArgs<T>& e, size_t idx, T acc, T uself, T dinv) {
   if constexpr (EPI == EPI_KU) {
@@ -95,6 +78,52 @@ constexpr bool needs_dinv() {
   return EPI == EPI_JACOBI || EPI == EPI_CHEB || EPI == EPI_CHEB0;
 }
 
+// Epilogue of node i for the CC cases c0, c0 + 1, .. and the D DOFs, with the
+// accumulated K.u in acc[c*D + q].  Every input (f, the Chebyshev direction,
+// D^-1 and the node's own values, each from registers when the caller has
+// them, else from memory) is loaded before the first store: the outputs may
+// alias the inputs as far as the compiler can tell, so a load placed after a
+// store could not be moved above it, and each value would cost its own
+// round trip.  The arithmetic is that of epilogue_d.
+template <typename T, int EPI, int CC, int D>
+__device__ __forceinline__ void epilogue_node(const EpiArgs<T>& e, const T* __restrict__ u, size_t n, size_t i, int c0,
+                                              const T* acc, const T* uself, const T* dv) {
+  T fv[CC][D], dd[CC][D], us[CC][D], di[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) di[q] = needs_dinv<EPI>() ? (dv ? dv[q] : e.dinv[i * D + q]) : T(0);
+#pragma unroll
+  for (int c = 0; c < CC; ++c)
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const size_t idx = vix(c0 + c, n, i, D, q);
+      fv[c][q] = EPI != EPI_KU ? e.f[idx] : T(0);
+      dd[c][q] = EPI == EPI_CHEB ? e.dvec[idx] : T(0);
+      us[c][q] = needs_dinv<EPI>() ? (uself ? uself[c * D + q] : u[idx]) : T(0);
+    }
+#pragma unroll
+  for (int c = 0; c < CC; ++c)
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const size_t idx = vix(c0 + c, n, i, D, q);
+      const T a = acc[c * D + q];
+      if constexpr (EPI == EPI_KU) {
+        e.out[idx] = a;
+      } else if constexpr (EPI == EPI_RESID) {
+        e.out[idx] = fv[c][q] - a;
+      } else if constexpr (EPI == EPI_JACOBI) {
+        e.out[idx] = us[c][q] + e.omega * di[q] * (fv[c][q] - a);
+      } else if constexpr (EPI == EPI_CHEB) {
+        const T dn = e.rho1 * dd[c][q] + e.rho2 * di[q] * (fv[c][q] - a);
+        e.dvec[idx] = dn;
+        e.out[idx] = us[c][q] + dn;
+      } else {  // EPI_CHEB0
+        const T dn = e.rho2 * di[q] * (fv[c][q] - a);
+        e.dvec[idx] = dn;
+        e.out[idx] = us[c][q] + dn;
+      }
+    }
+}
+
 // Structural zeros of the assembled interior stencil of the isotropic voxel
 // element: block (offset j, row d, column d2) vanishes unless d == d2 or the
 // offset has nonzero components along both d and d2 (elastic); for the
@@ -109,6 +138,23 @@ __host__ __device__ constexpr bool stencil_nonzero(int j, int d, int d2) {
     return d == d2 || (o[d] != 0 && o[d2] != 0);
   }
 }
+
+// The symmetry-class values of the interior stencil, wave-uniform (scalar
+// registers), and the signed coefficient of block entry (j, q, q2).
+template <typename T, int D>
+struct StencilClasses {
+  static constexpr int NS = D == 1 ? 4 : 8;
+  T v[NS];
+  __device__ __forceinline__ explicit StencilClasses(const T* p) {
+    const cptr<T> c = as_const(p);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) v[k] = c[k];
+  }
+  __device__ __forceinline__ T operator()(int j, int q, int q2) const {
+    const T a = v[scls_index<D>(j, q, q2)];
+    return scls_negative<D>(j, q, q2) ? -a : a;
+  }
+};
 
 // 27 neighbour ids of node (x,y,z) from the dense node map; runs along x of an
 // all-active row are consecutive ids, so an interior node needs 9 lookups.
@@ -135,7 +181,9 @@ __device__ __forceinline__ void neighbour_ids(const int* __restrict__ map, int N
 
 // Level 1, interior nodes (all 8 surrounding voxels solid): the assembled
 // 27-point stencil S of the shared K_e, wave-uniform coefficients.
-template <typename T, int D, int EPI>
+// PRE: all 27 x D values of a case are loaded before the first FMA, which
+// keeps 27 gathers per wave in flight at the cost of registers (occupancy).
+template <typename T, int D, int EPI, int PRE = 0>
 __global__ __launch_bounds__(kBlock) void k_apply_interior(LevelView<T> L, int C, const T* __restrict__ u, EpiArgs<T> e) {
   const int t = block_index(L.xcd) * kBlock + threadIdx.x;
   if (t >= L.n_int) return;
@@ -149,30 +197,33 @@ __global__ __launch_bounds__(kBlock) void k_apply_interior(LevelView<T> L, int C
   T dv[D];
 #pragma unroll
   for (int q = 0; q < D; ++q) dv[q] = needs_dinv<EPI>() ? e.dinv[(size_t)i * D + q] : T(0);
+  const StencilClasses<T, D> S(L.scls);
 #pragma unroll 1
   for (int c = 0; c < C; ++c) {
-    // L.zero is 0 at run time: the coefficient address stays wave-uniform (scalar
-    // loads) but depends on c, so the 27 x D x D loads are not hoisted out of the
-    // case loop into VGPRs
-    const cptr<T> S = as_const(L.S + (c & L.zero));
     T acc[D];
 #pragma unroll
     for (int q = 0; q < D; ++q) acc[q] = T(0);
     T uself[D];
+    T w[PRE ? 27 : 1][D];
+    if constexpr (PRE) {
+#pragma unroll
+      for (int j = 0; j < 27; ++j)
+#pragma unroll
+        for (int q2 = 0; q2 < D; ++q2) w[j][q2] = u[vix(c, n, nb[j], D, q2)];
+      __builtin_amdgcn_sched_barrier(0);  // keep the scheduler from sinking the loads into the FMA chain
+    }
 #pragma unroll
     for (int j = 0; j < 27; ++j) {
 #pragma unroll
       for (int q2 = 0; q2 < D; ++q2) {
-        const T v = u[vix(c, n, nb[j], D, q2)];
+        const T v = PRE ? w[PRE ? j : 0][q2] : u[vix(c, n, nb[j], D, q2)];
         if (j == 13) uself[q2] = v;
 #pragma unroll
         for (int q = 0; q < D; ++q)
-          if constexpr (true)
-            if (stencil_nonzero<D>(j, q, q2)) acc[q] = fma(S[(j * D + q) * D + q2], v, acc[q]);
+          if (stencil_nonzero<D>(j, q, q2)) acc[q] = fma(S(j, q, q2), v, acc[q]);
       }
     }
-#pragma unroll
-    for (int q = 0; q < D; ++q) epilogue_d<T, EPI>(e, vix(c, n, i, D, q), acc[q], uself[q], dv[q]);
+    epilogue_node<T, EPI, 1, D>(e, u, n, i, c, acc, uself, dv);
   }
 }
 
@@ -212,7 +263,9 @@ __global__ __launch_bounds__(kBlock) void k_apply_interior_run(LevelView<T> L, i
       dv[m][q] = (needs_dinv<EPI>() && m < len) ? e.dinv[(size_t)(i0 + m) * D + q] : T(0);
 #pragma unroll 1
   for (int c = 0; c < C; ++c) {
-    const cptr<T> S = as_const(L.S + (c & L.zero));  // see k_apply_interior
+    // L.zero is 0 at run time: the coefficient address stays wave-uniform (scalar
+    // loads) but depends on c, so the loads are not hoisted out of the case loop
+    const cptr<T> S = as_const(L.S + (c & L.zero));
     T acc[kRun][D], uself[kRun][D];
 #pragma unroll
     for (int m = 0; m < kRun; ++m)
@@ -288,7 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_interior_nc(LevelView<T> L, co
   const int x = lin % N, y = (lin / N) % N, z = lin / (N * N);
   int nb[27];
   neighbour_ids<true>(L.node_map, N, x, y, z, nb);
-  const cptr<T> S = as_const(L.S);
+  const StencilClasses<T, D> S(L.scls);
   T acc[C][D], uself[C][D];
 #pragma unroll
   for (int c = 0; c < C; ++c)
@@ -312,15 +365,12 @@ __global__ __launch_bounds__(kBlock) void k_apply_interior_nc(LevelView<T> L, co
 #pragma unroll
       for (int q2 = 0; q2 < D; ++q2)
         if (stencil_nonzero<D>(j, q, q2)) {
-          const T sc = S[(j * D + q) * D + q2];
+          const T sc = S(j, q, q2);
 #pragma unroll
           for (int c = 0; c < C; ++c) acc[c][q] = fma(sc, v[c][q2], acc[c][q]);
         }
   }
-#pragma unroll
-  for (int c = 0; c < C; ++c)
-#pragma unroll
-    for (int q = 0; q < D; ++q) epilogue<T, EPI>(e, vix(c, n, i, D, q), acc[c][q], uself[c][q], (size_t)i * D + q);
+  epilogue_node<T, EPI, C, D>(e, u, n, i, 0, &acc[0][0], &uself[0][0], nullptr);
 }
 
 template <typename T, int D, int C, int EPI>
@@ -367,15 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_boundary_nc(LevelView<T> L, co
       }
     }
   }
-#pragma unroll
-  for (int c = 0; c < C; ++c)
-#pragma unroll
-    for (int q = 0; q < D; ++q) {
-      const size_t idx = vix(c, n, i, D, q);
-      T uself = T(0);
-      if constexpr (EPI == EPI_JACOBI || EPI == EPI_CHEB || EPI == EPI_CHEB0) uself = u[idx];
-      epilogue<T, EPI>(e, idx, acc[c][q], uself, (size_t)i * D + q);
-    }
+  epilogue_node<T, EPI, C, D>(e, u, n, i, 0, &acc[0][0], nullptr, nullptr);
 }
 
 // Level 1, boundary nodes, as a masked stencil: the 3x3 coefficient block of
@@ -436,15 +478,98 @@ __global__ __launch_bounds__(kBlock) void k_apply_boundary_st(LevelView<T> L, co
           for (int c = 0; c < C; ++c) acc[c][q] = fma(cj[q][q2], v[c][q2], acc[c][q]);
     }
   }
+  epilogue_node<T, EPI, C, D>(e, u, n, i, 0, &acc[0][0], nullptr, nullptr);
+}
+
+// Level 1, boundary nodes, as a masked stencil assembled in registers: the
+// block of neighbour j is the sum of the K_e blocks of the active octant
+// elements that contain both the node and j; every K_e entry is a symmetry-class
+// value (wave-uniform, loaded once) with a compile-time sign, so the assembly
+// is straight-line FMAs with the per-lane 0/1 occupancy factors and no memory
+// traffic.  A thread takes C consecutive cases (grid row y: cases y*C ..),
+// gathering each neighbour once for them.  The
+// neighbour loads are issued from a clamped index and the values of an
+// inactive neighbour (whose block is zero) are selected away, so no load sits
+// in a branch.
+template <typename T, int D, int C, int EPI, int PRE = 0>
+__global__ __launch_bounds__(kBlock) void k_apply_boundary_cls(LevelView<T> L, const T* __restrict__ u, EpiArgs<T> e) {
+  const int t = block_index(L.xcd) * kBlock + threadIdx.x;
+  if (t >= L.n_bnd) return;
+  const int c0 = (int)blockIdx.y * C;  // this grid row's first case
+  const int i = L.boundary[t];
+  const int N = L.N;
+  const size_t n = (size_t)L.n_n;
+  const int lin = L.node_lin[i];
+  const int x = lin % N, y = (lin / N) % N, z = lin / (N * N);
+  const unsigned occ = L.occ8[i];
+  constexpr int NK = D == 1 ? 4 : 14;
+  T kc[NK];
+#pragma unroll
+  for (int c = 0; c < NK; ++c) kc[c] = L.kcls[c];
+  T mk[8], mkn[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    mk[k] = (occ >> k) & 1u ? T(1) : T(0);
+    mkn[k] = -mk[k];
+  }
+  int nb[27];
+  neighbour_ids<false>(L.node_map, N, x, y, z, nb);
+  T acc[C][D];
 #pragma unroll
   for (int c = 0; c < C; ++c)
 #pragma unroll
-    for (int q = 0; q < D; ++q) {
-      const size_t idx = vix(c, n, i, D, q);
-      T uself = T(0);
-      if constexpr (EPI == EPI_JACOBI || EPI == EPI_CHEB || EPI == EPI_CHEB0) uself = u[idx];
-      epilogue<T, EPI>(e, idx, acc[c][q], uself, (size_t)i * D + q);
+    for (int q = 0; q < D; ++q) acc[c][q] = T(0);
+  // PRE: every neighbour's values are loaded before the assembly starts
+  T w[PRE ? 27 : 1][C][D];
+  if constexpr (PRE) {
+#pragma unroll
+    for (int j = 0; j < 27; ++j) {
+      const size_t id = nb[j] >= 0 ? nb[j] : 0;
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int q2 = 0; q2 < D; ++q2) w[j][c][q2] = u[vix(c0 + c, n, id, D, q2)];
     }
+    __builtin_amdgcn_sched_barrier(0);  // keep the scheduler from sinking the loads into the assembly
+  }
+#pragma unroll
+  for (int j = 0; j < 27; ++j) {
+    const int jx = j % 3, jy = (j / 3) % 3, jz = j / 9;
+    T cj[D][D];
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+#pragma unroll
+      for (int q2 = 0; q2 < D; ++q2) cj[q][q2] = T(0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int dx = jx - (k & 1), dy = jy - ((k >> 1) & 1), dz = jz - (k >> 2);
+      if (dx < 0 || dx > 1 || dy < 0 || dy > 1 || dz < 0 || dz > 1) continue;  // j is not a corner of element k
+      const int a = 7 - k, m = dx + 2 * dy + 4 * dz;
+#pragma unroll
+      for (int q = 0; q < D; ++q)
+#pragma unroll
+        for (int q2 = 0; q2 < D; ++q2)
+          cj[q][q2] = fma(kcls_negative<D>(a, q, q2) ? mkn[k] : mk[k], kc[kcls_index<D>(a ^ m, q, q2)], cj[q][q2]);
+    }
+    const bool act = nb[j] >= 0;
+    const size_t id = act ? nb[j] : 0;
+    T v[C][D];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int q2 = 0; q2 < D; ++q2) v[c][q2] = PRE ? w[PRE ? j : 0][c][q2] : u[vix(c0 + c, n, id, D, q2)];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int q2 = 0; q2 < D; ++q2) v[c][q2] = act ? v[c][q2] : T(0);
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+#pragma unroll
+      for (int q2 = 0; q2 < D; ++q2)
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c][q] = fma(cj[q][q2], v[c][q2], acc[c][q]);
+  }
+  epilogue_node<T, EPI, C, D>(e, u, n, i, c0, &acc[0][0], nullptr, nullptr);
 }
 
 // Level 1, boundary nodes: element-by-element over the active octant
@@ -469,7 +594,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_boundary(LevelView<T> L, int C
   for (int q = 0; q < D; ++q) dv[q] = needs_dinv<EPI>() ? e.dinv[(size_t)i * D + q] : T(0);
 #pragma unroll 1
   for (int c = 0; c < C; ++c) {
-    const cptr<T> K = as_const(L.K + (c & L.zero));  // see k_apply_interior
+    const cptr<T> K = as_const(L.K + (c & L.zero));  // (see k_apply_interior_run)
     T acc[D];
 #pragma unroll
     for (int q = 0; q < D; ++q) acc[q] = T(0);
@@ -494,15 +619,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_boundary(LevelView<T> L, int C
             for (int q2 = 0; q2 < D; ++q2) acc[q] = fma(K[(a * D + q) * M + m * D + q2], ue[m][q2], acc[q]);
       }
     }
-    T uself[D];
-#pragma unroll
-    for (int q = 0; q < D; ++q) uself[q] = T(0);
-    if constexpr (EPI == EPI_JACOBI || EPI == EPI_CHEB || EPI == EPI_CHEB0) {
-#pragma unroll
-      for (int q = 0; q < D; ++q) uself[q] = u[vix(c, n, i, D, q)];
-    }
-#pragma unroll
-    for (int q = 0; q < D; ++q) epilogue_d<T, EPI>(e, vix(c, n, i, D, q), acc[q], uself[q], dv[q]);
+    epilogue_node<T, EPI, 1, D>(e, u, n, i, c, acc, nullptr, dv);
   }
 }
 
@@ -567,15 +684,7 @@ __global__ __launch_bounds__(BS) void k_apply_coarse(LevelView<T> L, const T* __
       }
     }
   }
-#pragma unroll
-  for (int c = 0; c < CB; ++c)
-#pragma unroll
-    for (int q = 0; q < D; ++q) {
-      const size_t idx = vix(c0 + c, n, i, D, q);
-      T uself = T(0);
-      if constexpr (EPI == EPI_JACOBI || EPI == EPI_CHEB || EPI == EPI_CHEB0) uself = u[idx];
-      epilogue<T, EPI>(e, idx, acc[c][q], uself, (size_t)i * D + q);
-    }
+  epilogue_node<T, EPI, CB, D>(e, u, n, i, c0, &acc[0][0], nullptr, nullptr);
 }
 
 // dst = src / sqrt(*nrm2), the squared norm read on the device; a zero or
@@ -1291,7 +1400,27 @@ static void launch_coarse(const LevelView<T>& L, int kind, int rows, const T* u,
 template <typename T, int D, int C, int EPI>
 static void apply_dispatch_kind(const LevelView<T>& L, int kind, const T* u, const EpiArgs<T>& e, hipStream_t s) {
   if (kind == KIND_SHARED) {
-    if (L.cb == 0 || L.cb == 2) {  // all cases per neighbour load
+    if (L.cb >= 5 && L.cb <= 7) {  // boundary as a register-assembled masked stencil
+      if (L.n_int > 0) {
+        if (L.cb == 5)
+          hipLaunchKernelGGL((k_apply_interior<T, D, EPI>), dim3(blocks_for(L.n_int)), dim3(kBlock), 0, s, L, C, u, e);
+        else if (L.cb == 7)
+          hipLaunchKernelGGL((k_apply_interior<T, D, EPI, 1>), dim3(blocks_for(L.n_int)), dim3(kBlock), 0, s, L, C, u, e);
+        else
+          hipLaunchKernelGGL((k_apply_interior_nc<T, D, C, EPI>), dim3(blocks_for(L.n_int)), dim3(kBlock), 0, s, L, u,
+                             e);
+      }
+      if (L.n_bnd > 0) {
+        // one case per thread (C grid rows): the assembly is repeated per case,
+        // but the live set stays small (with several cases per thread the
+        // compiler hoists every neighbour's loads and spills)
+        const dim3 g(blocks_for(L.n_bnd), C);
+        if (L.cb == 7)
+          hipLaunchKernelGGL((k_apply_boundary_cls<T, D, 1, EPI, 1>), g, dim3(kBlock), 0, s, L, u, e);
+        else
+          hipLaunchKernelGGL((k_apply_boundary_cls<T, D, 1, EPI>), g, dim3(kBlock), 0, s, L, u, e);
+      }
+    } else if (L.cb == 0 || L.cb == 2) {  // all cases per neighbour load
       if (L.n_int > 0)
         hipLaunchKernelGGL((k_apply_interior_nc<T, D, C, EPI>), dim3(blocks_for(L.n_int)), dim3(kBlock), 0, s, L, u, e);
       if (L.n_bnd > 0) {
