@@ -494,8 +494,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_boundary_st(LevelView<T> L, co
 template <typename T, int D, int C, int EPI, int PRE = 0>
 __global__ __launch_bounds__(kBlock) void k_apply_boundary_cls(LevelView<T> L, const T* __restrict__ u, EpiArgs<T> e) {
   const int t = block_index(L.xcd) * kBlock + threadIdx.x;
-  if (t >= L.n_bnd) return;
   const int c0 = (int)blockIdx.y * C;  // this grid row's first case
+  if (t >= L.n_bnd) return;
   const int i = L.boundary[t];
   const int N = L.N;
   const size_t n = (size_t)L.n_n;
@@ -786,37 +786,52 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView<T> F, LevelVie
 // ---------------------------------------------------------------- coarsest solve
 
 // u = Kinv f with Kinv the pinned inverse (symmetric, pinned rows/cols zero).
-// One thread per DOF row (node*D + d), 64 rows per workgroup; f (all C cases)
-// is staged in LDS in chunks of kCoarseChunk DOFs, so the column loop reads it
-// by broadcast while the Kinv column reads (= rows by symmetry) stay coalesced.
+// A workgroup owns 64 DOF rows (node*D + d); its 4 waves split the columns
+// (wave w takes columns w, w + 4, ..), so that four times as many column loads
+// are in flight for the small coarsest systems, and add their FP64 partial
+// sums through LDS at the end.  f (all C cases) is staged in LDS in chunks of
+// kCoarseChunk DOFs, read by broadcast; the Kinv column reads (= rows by
+// symmetry) are coalesced over the 64 rows.
 constexpr int kCoarseChunk = 256;
+constexpr int kCoarseSplit = 4;
 template <typename T, int C>
-__global__ __launch_bounds__(64) void k_coarse_solve(const T* __restrict__ Kinv, int cn, int D,
-                                                     const T* __restrict__ f, T* __restrict__ u) {
+__global__ __launch_bounds__(64 * kCoarseSplit) void k_coarse_solve(const T* __restrict__ Kinv, int cn, int D,
+                                                                   const T* __restrict__ f, T* __restrict__ u) {
   __shared__ T fs[kCoarseChunk * C];
+  __shared__ double part[kCoarseSplit - 1][C][64];
   const int n = cn / D;
-  const int row = blockIdx.x * 64 + threadIdx.x;
+  const int lane = threadIdx.x & 63, split = threadIdx.x >> 6;
+  const int row = blockIdx.x * 64 + lane;
   double acc[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = 0.0;
   for (int j0 = 0; j0 < cn; j0 += kCoarseChunk) {
     const int m = min(kCoarseChunk, cn - j0);
     __syncthreads();
-    for (int k = threadIdx.x; k < m * C; k += 64) {
+    for (int k = threadIdx.x; k < m * C; k += 64 * kCoarseSplit) {
       const int j = j0 + k / C, c = k % C;
       fs[k] = f[vix(c, n, j / D, D, j % D)];
     }
     __syncthreads();
     if (row < cn) {
 #pragma unroll 4
-      for (int jj = 0; jj < m; ++jj) {
+      for (int jj = split; jj < m; jj += kCoarseSplit) {
         const double kv = (double)Kinv[(size_t)(j0 + jj) * cn + row];
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] += kv * (double)fs[jj * C + c];
       }
     }
   }
-  if (row >= cn) return;
+  if (split > 0) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) part[split - 1][c][lane] = acc[c];
+  }
+  __syncthreads();
+  if (split > 0 || row >= cn) return;
+#pragma unroll
+  for (int s2 = 0; s2 < kCoarseSplit - 1; ++s2)
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] += part[s2][c][lane];
   const int node = row / D, q = row % D;
 #pragma unroll
   for (int c = 0; c < C; ++c) u[vix(c, n, node, D, q)] = (T)acc[c];
@@ -1515,9 +1530,10 @@ void launch_prolong_add(const LevelView<T>& F, const LevelView<T>& Cv, int Q, in
 template <typename T>
 void launch_coarse_solve(const T* cinv, int cn, int D, int C, const T* f, T* u, hipStream_t s) {
   const unsigned g = (unsigned)((cn + 63) / 64);
-  if (C == 6) hipLaunchKernelGGL((k_coarse_solve<T, 6>), dim3(g), dim3(64), 0, s, cinv, cn, D, f, u);
-  else if (C == 3) hipLaunchKernelGGL((k_coarse_solve<T, 3>), dim3(g), dim3(64), 0, s, cinv, cn, D, f, u);
-  else if (C == 1) hipLaunchKernelGGL((k_coarse_solve<T, 1>), dim3(g), dim3(64), 0, s, cinv, cn, D, f, u);
+  const dim3 b(64 * kCoarseSplit);
+  if (C == 6) hipLaunchKernelGGL((k_coarse_solve<T, 6>), dim3(g), b, 0, s, cinv, cn, D, f, u);
+  else if (C == 3) hipLaunchKernelGGL((k_coarse_solve<T, 3>), dim3(g), b, 0, s, cinv, cn, D, f, u);
+  else if (C == 1) hipLaunchKernelGGL((k_coarse_solve<T, 1>), dim3(g), b, 0, s, cinv, cn, D, f, u);
   else fail(GMT_E_INVAL, "unsupported C=%d", C);
   GMT_LAUNCH_CHECK();
 }
