@@ -293,7 +293,7 @@ struct Hier {
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     std::vector<double> key;
   };
-  PcgGraphs g32, g64;
+  PcgGraphs g32, g64, gmx;  // FP32, FP64, FP64 Krylov with the FP32 V-cycle
   hipStream_t cap = nullptr;  // non-blocking stream used only to record the captures
   void release_graphs();
 

@@ -83,7 +83,7 @@ void Hier::release(void* q) {
 }
 
 void Hier::release_graphs() {
-  for (PcgGraphs* g : {&g32, &g64}) {
+  for (PcgGraphs* g : {&g32, &g64, &gmx}) {
     for (auto& e : g->exec)
       if (e) (void)hipGraphExecDestroy(e), e = nullptr;
     g->key.clear();
@@ -717,12 +717,20 @@ static Hier::PcgGraphs& graphs_of(Hier& h) {
 // before converging, so the window is generous)
 constexpr int kStagnation = 300;
 
-template <typename T>
+// MIXED (T = double only): the Krylov vectors, dot products and the K.p
+// product stay FP64, and only the preconditioner runs in FP32 — the residual
+// is rounded to FP32, one FP32 V-cycle is applied and its result widened
+// again.  The CG recurrence then keeps FP64 accuracy (its iteration count
+// is the FP64 one) at close to the FP32 cost of a V-cycle.
+template <typename T, bool MIXED = false>
 static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int check_every, bool graph,
                const CycleCfg& cfg, hipStream_t s, bool* reached = nullptr) {
+  static_assert(!MIXED || std::is_same<T, double>::value, "the mixed PCG keeps FP64 Krylov vectors");
   if (reached) *reached = false;
   h.ensure_work<T>();
+  if (MIXED) h.ensure_work<float>();
   Work<T>& W = h.work<T>();
+  Work<float>& W32 = h.work<float>();
   const int n = h.lv[0].n_n, C = h.C, D = h.D, Q = h.Q;
   const size_t tot = (size_t)n * Q;
   double* sc = h.red_out;
@@ -734,8 +742,18 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
   launch_project<T>(W.pr, n, Q, D, h.red_partial, sums, s);
   launch_dot<T>(W.pr, W.pr, n, C, D, h.red_partial, rr, s);
   host_dot(h, rr, C, bn2, s);
+  // z = Pi V(r): the V-cycle in T, or (MIXED) in FP32 on the rounded residual
+  auto vc = [&](hipStream_t st) {
+    if constexpr (MIXED) {
+      launch_convert<double, float>(W.pr, W32.pr, tot, st);
+      vcycle<float>(h, W32.pr, W32.pz, true, nullptr, cfg, st);
+      launch_convert<float, double>(W32.pz, W.pz, tot, st);
+    } else {
+      vcycle<T>(h, W.pr, W.pz, true, nullptr, cfg, st);
+    }
+  };
   auto precond = [&]() {
-    vcycle<T>(h, W.pr, W.pz, true, nullptr, cfg, s);
+    vc(s);
     launch_project<T>(W.pz, n, Q, D, h.red_partial, sums, s);
   };
   precond();
@@ -767,13 +785,13 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
       launch_pcg_alpha(rz, pq, alpha, C, st);
       launch_pcg_update<T>(x, W.pr, W.pp, W.pq, alpha, n, Q, D, st);
       launch_project<T>(W.pr, n, Q, D, h.red_partial, sums, st);
-      vcycle<T>(h, W.pr, W.pz, true, nullptr, cfg, st);
+      vc(st);
       launch_project<T>(W.pz, n, Q, D, h.red_partial, sums, st);
       launch_dot<T>(W.pr, W.pz, n, C, D, h.red_partial, rzn, st);
       launch_pcg_beta(rzn, rz, beta, C, st);
       launch_pcg_direction<T>(W.pp, W.pz, beta, n, Q, D, st);
     };
-    Hier::PcgGraphs& G = graphs_of<T>(h);
+    Hier::PcgGraphs& G = MIXED ? h.gmx : graphs_of<T>(h);
     std::vector<double> key = {(double)(uintptr_t)x, (double)cfg.nu1, (double)cfg.nu2, (double)cfg.smoother};
     for (int l = 0; l < h.L; ++l) key.insert(key.end(), {cfg.omega[l], cfg.lo[l], cfg.hi[l]});
     if (G.key != key) {
@@ -1168,8 +1186,11 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
 // ill-conditioned cell (thin, nearly mechanism-like members), where the FP32
 // recurrence drifts from the true residual and each refinement step gains
 // little: such a cell needs about three times as many FP32 iterations as FP64
-// ones in total, so it continues in FP64.
+// ones in total, so it continues with the FP64 recurrence.
 constexpr int kMaxInner32 = 200;
+// inner-solve mode after such a switch: FP64 Krylov recurrence and K.p, FP32
+// V-cycle (pcg<double, true>)
+constexpr int kInnerMixed = 100;
 
 static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, gmt_solve_report* rep,
                   hipStream_t s, gmt_status* st) {
@@ -1180,6 +1201,11 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
   const int check = o && o->check_every > 0 ? o->check_every : 1;
   const bool graph = o && o->graph;
   if (prec != GMT_F64 && prec != GMT_F32) fail(GMT_E_INVAL, "bad precision");
+  // GMT_MAX_INNER32=<k> lowers the FP32 inner-iteration cap (tests use it to
+  // reach the FP64-recurrence path on small cells)
+  int max_inner32 = kMaxInner32;
+  if (const char* e = std::getenv("GMT_MAX_INNER32"))
+    if (*e && std::atoi(e) > 0) max_inner32 = std::min(kMaxInner32, std::atoi(e));
   const CycleCfg cfg = make_cycle(h, o ? &o->cycle : nullptr);
   double* r64 = scratch64(h, &h.s_r64);
   // (in mixed precision the few FP64 residual sweeps keep the default shape)
@@ -1217,15 +1243,15 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
       break;
     }
     if (stalled32 && inner_prec == GMT_F32 && worst < 0.5 * prev_worst) {
-      inner_prec = GMT_F64;
+      inner_prec = kInnerMixed;  // FP64 Krylov, FP32 V-cycle
       last_f32 = false;
     }
     if (last_f32 && !(worst < 0.5 * prev_worst)) {
       // the FP32 inner solve did not halve the FP64 residual (an ill-conditioned
-      // cell where FP32 rounding stalls or diverges): undo that update and finish
-      // with FP64 inner solves
+      // cell where the FP32 recurrence stalls or diverges): undo that update and
+      // finish with the FP64 recurrence (FP32 V-cycle)
       launch_accumulate<float>(u, h.s_x32, tot, s, -1.0);
-      inner_prec = GMT_F64;
+      inner_prec = kInnerMixed;
       last_f32 = false;
       rel_residual64(h, f, u, r64, rel, den, s);
       worst = 0;
@@ -1251,7 +1277,7 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
       if (!h.s_x32) h.s_x32 = h.alloc<float>(tot);
       launch_convert<double, float>(r64, h.s_b32, tot, s);
       bool reached = false;
-      its += pcg<float>(h, h.s_b32, h.s_x32, itol, std::min(max_iter - its, kMaxInner32), check, graph, cfg, s,
+      its += pcg<float>(h, h.s_b32, h.s_x32, itol, std::min(max_iter - its, max_inner32), check, graph, cfg, s,
                         &reached);
       launch_accumulate<float>(u, h.s_x32, tot, s, 1.0);
       last_f32 = true;
@@ -1259,6 +1285,12 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
       // target: keep its update (checked above on the next pass) and take FP64
       // inner solves from here
       if (!reached && its < max_iter) stalled32 = true;
+    } else if (inner_prec == kInnerMixed) {
+      autotune<double>(h, s);
+      double* x64 = scratch64(h, &h.s_x64);
+      its += pcg<double, true>(h, r64, x64, itol, max_iter - its, check, graph, cfg, s);
+      launch_accumulate<double>(u, x64, tot, s, 1.0);
+      last_f32 = false;
     } else {
       if (prec == GMT_F32) autotune<double>(h, s);
       double* x64 = scratch64(h, &h.s_x64);

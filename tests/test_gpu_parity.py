@@ -253,6 +253,21 @@ def test_solve_mixed(solved):
     assert np.linalg.norm(CH - CH_ref) <= 1e-4 * np.linalg.norm(CH_ref)
 
 
+def test_solve_fp64_recurrence_fp32_vcycle(solved, monkeypatch):
+    """The path an ill-conditioned cell takes: the FP32 inner solve is cut off (here after 2
+    iterations) and the solve continues with FP64 CG vectors, dots and K.p around the FP32
+    V-cycle; it must reach the same tolerance and C_H as the other paths."""
+    name, vox, P, H, u_ref, CH_ref = solved
+    monkeypatch.setenv("GMT_MAX_INNER32", "2")
+    f = H.load_vector()
+    for graph in (False, True):
+        u, rep = H.solve(f, tol=1e-7, precision="f32", graph=graph)
+        assert rep["converged"]
+        assert np.max(osolve.relative_residual(P, _np(u))) <= 1e-7
+        CH = H.homogenize(u)  # (C_H error is quadratic in the solution error)
+        assert np.linalg.norm(CH - CH_ref) <= 1e-6 * np.linalg.norm(CH_ref)
+
+
 def test_solve_deterministic(solved):
     name, vox, P, H, u_ref, CH_ref = solved
     f = H.load_vector()
