@@ -1187,7 +1187,7 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
 // recurrence drifts from the true residual and each refinement step gains
 // little: such a cell needs about three times as many FP32 iterations as FP64
 // ones in total, so it continues with the FP64 recurrence.
-constexpr int kMaxInner32 = 200;
+constexpr int kMaxInner32 = 120;
 // inner-solve mode after such a switch: FP64 Krylov recurrence and K.p, FP32
 // V-cycle (pcg<double, true>)
 constexpr int kInnerMixed = 100;

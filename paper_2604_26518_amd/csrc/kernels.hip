@@ -701,12 +701,11 @@ __global__ void k_normalize(size_t n, const double* __restrict__ src, const doub
 template <typename T>
 __global__ void k_smooth_zero(int n, int D, int C, const T* __restrict__ f, const T* __restrict__ dinv,
                               T scale, T* __restrict__ out, T* __restrict__ dvec) {
-  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  const size_t total = (size_t)n * C * D;
-  if (idx >= total) return;
-  const int q = (int)(idx % D);
-  const size_t node = (idx / D) % n;
-  const T v = scale * dinv[node * D + q] * f[idx];
+  // grid row = case (32-bit index arithmetic within a case)
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n * D) return;
+  const size_t idx = (size_t)blockIdx.y * n * D + j;
+  const T v = scale * dinv[j] * f[idx];
   out[idx] = v;
   if (dvec) dvec[idx] = v;
 }
@@ -962,11 +961,13 @@ __global__ __launch_bounds__(kBlock) void k_colsum(const T* __restrict__ v, int 
 }
 
 // v[q][i] -= sums[q] / n : removes the rigid-translation (constant) component.
+// Grid row = case, 32-bit index arithmetic within a case.
 template <typename T>
-__global__ void k_sub_mean(T* __restrict__ v, size_t total, int n, int D, const double* __restrict__ sums,
-                           double inv_n) {
-  size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < total) v[i] -= (T)(sums[(i / ((size_t)n * D)) * D + i % D] * inv_n);
+__global__ void k_sub_mean(T* __restrict__ v, int n, int D, const double* __restrict__ sums, double inv_n) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n * D) return;
+  const int c = blockIdx.y;
+  v[(size_t)c * n * D + j] -= (T)(sums[c * D + j % D] * inv_n);
 }
 
 template <typename T>
@@ -994,9 +995,11 @@ __global__ void k_mul_nodewise(T* __restrict__ v, const T* __restrict__ w, int n
 }
 
 // Second stage: out[k] = sum over blocks of partial[b][k], fixed order.
+// One workgroup per reduced value k (grid = nv).
 __global__ void k_reduce_final(const double* __restrict__ partial, int nblocks, int nv, double* __restrict__ out) {
   __shared__ double sh[kBlock];
-  for (int k = 0; k < nv; ++k) {
+  {
+    const int k = blockIdx.x;
     double s = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += kBlock) s += partial[(size_t)b * nv + k];
     sh[threadIdx.x] = s;
@@ -1006,27 +1009,29 @@ __global__ void k_reduce_final(const double* __restrict__ partial, int nblocks, 
       __syncthreads();
     }
     if (threadIdx.x == 0) out[k] = sh[0];
-    __syncthreads();
   }
 }
 
 template <typename T>
 __global__ void k_pcg_update(T* __restrict__ u, T* __restrict__ r, const T* __restrict__ p,
-                             const T* __restrict__ q, const double* __restrict__ alpha, size_t total, int n,
-                             int D) {
-  size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= total) return;
-  const T a = (T)alpha[i / ((size_t)n * D)];
+                             const T* __restrict__ q, const double* __restrict__ alpha, int n, int D) {
+  // grid row = case
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n * D) return;
+  const size_t i = (size_t)blockIdx.y * n * D + j;
+  const T a = (T)alpha[blockIdx.y];
   u[i] = fma(a, p[i], u[i]);
   r[i] = fma(-a, q[i], r[i]);
 }
 
 template <typename T>
-__global__ void k_pcg_direction(T* __restrict__ p, const T* __restrict__ z, const double* __restrict__ beta,
-                                size_t total, int n, int D) {
-  size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= total) return;
-  const T b = (T)beta[i / ((size_t)n * D)];
+__global__ void k_pcg_direction(T* __restrict__ p, const T* __restrict__ z, const double* __restrict__ beta, int n,
+                                int D) {
+  // grid row = case
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n * D) return;
+  const size_t i = (size_t)blockIdx.y * n * D + j;
+  const T b = (T)beta[blockIdx.y];
   p[i] = fma(b, p[i], z[i]);
 }
 
@@ -1492,8 +1497,8 @@ void launch_smooth_zero(int n, int D, int C, const T* f, const T* dinv, T scale,
                         hipStream_t s) {
   const size_t tot = (size_t)n * C * D;
   if (!tot) return;
-  hipLaunchKernelGGL(k_smooth_zero<T>, dim3(blocks_for(tot)), dim3(kBlock), 0, s, n, D, C, f, dinv, scale, out,
-                     dvec);
+  hipLaunchKernelGGL(k_smooth_zero<T>, dim3(blocks_for((size_t)n * D), C), dim3(kBlock), 0, s, n, D, C, f, dinv,
+                     scale, out, dvec);
   GMT_LAUNCH_CHECK();
 }
 
@@ -1579,7 +1584,7 @@ void launch_dot(const T* a, const T* b, int n, int C, int D, double* partial, do
   else if (C == 1 && D == 1) hipLaunchKernelGGL((k_dot<T, 1, 1>), dim3(g), dim3(kBlock), 0, s, a, b, n, partial);
   else fail(GMT_E_INVAL, "unsupported (c, d)");
   GMT_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, partial, (int)g, C, out);
+  hipLaunchKernelGGL(k_reduce_final, dim3(C), dim3(kBlock), 0, s, partial, (int)g, C, out);
   GMT_LAUNCH_CHECK();
 }
 
@@ -1590,7 +1595,7 @@ void launch_gram(const Ta* a, const Tb* b, int n, int C, int D, double* partial,
   else if (C == 3 && D == 1) hipLaunchKernelGGL((k_gram<Ta, Tb, 3, 1>), dim3(g), dim3(kBlock), 0, s, a, b, n, partial);
   else fail(GMT_E_INVAL, "unsupported (c, d)");
   GMT_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, partial, (int)g, C * C, out);
+  hipLaunchKernelGGL(k_reduce_final, dim3(C * C), dim3(kBlock), 0, s, partial, (int)g, C * C, out);
   GMT_LAUNCH_CHECK();
 }
 
@@ -1601,7 +1606,7 @@ void launch_colsum(const T* v, int n, int Q, int D, double* partial, double* sum
   else if (Q == 3 && D == 1) hipLaunchKernelGGL((k_colsum<T, 3, 1>), dim3(g), dim3(kBlock), 0, s, v, n, partial);
   else fail(GMT_E_INVAL, "unsupported (Q, D) = (%d, %d)", Q, D);
   GMT_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, partial, (int)g, Q, sums);
+  hipLaunchKernelGGL(k_reduce_final, dim3(Q), dim3(kBlock), 0, s, partial, (int)g, Q, sums);
   GMT_LAUNCH_CHECK();
 }
 
@@ -1637,10 +1642,11 @@ void launch_project(T* v, int n, int Q, int D, double* partial, double* sums, hi
   else if (Q == 1 && D == 1) hipLaunchKernelGGL((k_colsum<T, 1, 1>), dim3(g), dim3(kBlock), 0, s, v, n, partial);
   else fail(GMT_E_INVAL, "unsupported (Q, D) = (%d, %d)", Q, D);
   GMT_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, partial, (int)g, Q, sums);
+  hipLaunchKernelGGL(k_reduce_final, dim3(Q), dim3(kBlock), 0, s, partial, (int)g, Q, sums);
   GMT_LAUNCH_CHECK();
-  const size_t tot = (size_t)n * Q;
-  hipLaunchKernelGGL(k_sub_mean<T>, dim3(blocks_for(tot)), dim3(kBlock), 0, s, v, tot, n, D, sums, 1.0 / n);
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_sub_mean<T>, dim3(blocks_for((size_t)n * D), Q / D), dim3(kBlock), 0, s, v, n, D, sums,
+                     1.0 / n);
   GMT_LAUNCH_CHECK();
 }
 
@@ -1649,7 +1655,8 @@ void launch_pcg_update(T* u, T* r, const T* p, const T* q, const double* alpha, 
                        hipStream_t s) {
   const size_t tot = (size_t)n * Q;
   if (!tot) return;
-  hipLaunchKernelGGL(k_pcg_update<T>, dim3(blocks_for(tot)), dim3(kBlock), 0, s, u, r, p, q, alpha, tot, n, D);
+  hipLaunchKernelGGL(k_pcg_update<T>, dim3(blocks_for((size_t)n * D), Q / D), dim3(kBlock), 0, s, u, r, p, q, alpha, n,
+                     D);
   GMT_LAUNCH_CHECK();
 }
 
@@ -1657,7 +1664,7 @@ template <typename T>
 void launch_pcg_direction(T* p, const T* z, const double* beta, int n, int Q, int D, hipStream_t s) {
   const size_t tot = (size_t)n * Q;
   if (!tot) return;
-  hipLaunchKernelGGL(k_pcg_direction<T>, dim3(blocks_for(tot)), dim3(kBlock), 0, s, p, z, beta, tot, n, D);
+  hipLaunchKernelGGL(k_pcg_direction<T>, dim3(blocks_for((size_t)n * D), Q / D), dim3(kBlock), 0, s, p, z, beta, n, D);
   GMT_LAUNCH_CHECK();
 }
 
