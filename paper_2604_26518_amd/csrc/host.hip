@@ -626,7 +626,7 @@ static void autotune(Hier& h, hipStream_t s) {
     // selectable through GMT_FORCE_L1_VARIANT)
     std::vector<Shape> cand = {{256, 0, 1}, {256, 0, 0}};
     if (l == 0) {
-      cand = {{256, 7, 1}, {256, 7, 0}, {256, 6, 1}, {256, 6, 0}};
+      cand = {{256, 7, 1}, {256, 7, 0}, {256, 5, 1}, {256, 6, 1}, {256, 6, 0}};
       if (h.C > 1) cand.insert(cand.end(), {{256, 1, 1}, {256, 1, 0}});
     }
     if (l > 0) {
