@@ -197,6 +197,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cells", type=int, default=64)
+    ap.add_argument("--seed0", type=int, default=1000, help="first cell seed (cells seed0 .. seed0 + cells - 1)")
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--max-iter", type=int, default=3000)
@@ -228,7 +229,7 @@ def main():
     torch.cuda.set_device(dev)
 
     t0 = time.perf_counter()
-    cells = make_cells(args.N, list(range(1000, 1000 + args.cells)))
+    cells = make_cells(args.N, list(range(args.seed0, args.seed0 + args.cells)))
     gen_s = time.perf_counter() - t0
     vox_dev = [torch.from_numpy(v).to(dev) for (_, _, _, v) in cells]
     torch.cuda.synchronize()
@@ -330,7 +331,7 @@ def main():
                                f"spinodal families, VF U(0.15,0.5), plain GMG-PCG (FP32 bulk, FP64 "
                                f"refinement) to {args.tol:g}, batched solve, whole path incl. hierarchy "
                                f"build and C_H",
-                   "cells": len(vox_dev), "N": args.N, "levels": levels, "tol": args.tol,
+                   "cells": len(vox_dev), "seed0": args.seed0, "N": args.N, "levels": levels, "tol": args.tol,
                    "workers": args.workers, "graph": not args.no_graph},
         "ms_per_cell_solve_only": round(ms_cell_solve, 3),
         "dof_solves_per_s": round(dofs / wall, 1),
