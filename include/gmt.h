@@ -106,9 +106,12 @@ typedef struct {
 typedef struct {
   double tol;         /* stop when max_m ||f_m - K u_m|| / ||f_m|| <= tol (FP64); default 1e-5 */
   int32_t max_iter;   /* total inner PCG iterations; default 500 */
-  int32_t precision;  /* GMT_F64: all-FP64; GMT_F32: FP32 inner PCG + FP64 refinement
-                         (an FP32 step that does not halve the FP64 residual is undone
-                         and the solve continues with FP64 inner PCG) */
+  int32_t precision;  /* GMT_F64: all-FP64; GMT_F32: FP32 inner PCG + FP64 refinement.
+                         An ill-conditioned cell leaves the FP32 recurrence: when an FP32
+                         inner solve stalls or passes 120 iterations short of its target
+                         (its update is kept), or an FP32 step does not halve the FP64
+                         residual (that step is undone), the solve continues with FP64
+                         CG vectors, dot products and K.p around the FP32 V-cycle. */
   int32_t max_outer;  /* FP64 refinement steps; default 8 */
   int32_t check_every;/* inner convergence check period (host sync); default 1 */
   gmt_cycle_opts cycle;
