@@ -71,3 +71,65 @@ def test_thermal_closed_form():
     X = fem.X0_thermal()
     assert np.abs(X.T @ K @ X - np.eye(3)).max() < 1e-15
     assert np.abs(fem.Ke_thermal(2.0) - 2.0 * K).max() < 1e-15
+
+
+def _corner_map(perm=(0, 1, 2), flip=0):
+    """Image of the hex8 corner a + 2b + 4c under the cube symmetry that permutes the axes
+    (new axis k takes old axis perm[k]) and then reflects the axes set in the bit mask flip."""
+    out = []
+    for a in range(8):
+        bits = [(a >> k) & 1 for k in range(3)]
+        nb = [bits[perm[k]] ^ ((flip >> k) & 1) for k in range(3)]
+        out.append(nb[0] + 2 * nb[1] + 4 * nb[2])
+    return out
+
+
+def test_Ke_invariant_under_cube_symmetries():
+    """The isotropic voxel element is invariant under the 48 symmetries of the cube: a
+    reflection of axis k maps corner a to a ^ 2^k and negates displacement component k, and
+    an axis permutation permutes corners and components alike.  So K_e[g(a), g(m)] equals
+    K_e[a, m] up to the component map and signs, for every symmetry g (elastic and thermal)."""
+    import itertools
+    for E, nu in ((1.0, 0.3), (2.5, 0.45)):
+        K = fem.Ke_elastic(E, nu).reshape(8, 3, 8, 3)
+        for perm in itertools.permutations(range(3)):
+            for flip in range(8):
+                cm = _corner_map(perm, flip)
+                # component k of the image is component perm[k] of the original, with sign
+                sign = np.array([-1.0 if (flip >> k) & 1 else 1.0 for k in range(3)])
+                P = np.zeros((3, 3))
+                for k in range(3):
+                    P[k, perm[k]] = sign[k]
+                for a in range(8):
+                    for m in range(8):
+                        img = K[cm[a], :, cm[m], :]
+                        assert np.allclose(img, P @ K[a, :, m, :] @ P.T, atol=1e-13 * np.abs(K).max())
+    Kt = fem.Ke_thermal(1.0)
+    for perm in itertools.permutations(range(3)):
+        for flip in range(8):
+            cm = _corner_map(perm, flip)
+            assert np.allclose(Kt[np.ix_(cm, cm)], Kt, atol=1e-14)
+
+
+def test_Ke_has_14_symmetry_classes():
+    """Consequence used by the GPU operator kernels: after the reflection taking corner a to
+    corner 0 (signs (-1)^(a_d + a_d2)), entry (d, d2) of block (a, m) depends only on
+    (delta_d, number of other set bits of delta) on the diagonal and on
+    (delta_d, delta_d2, delta_third) off it, delta = a xor m: 6 + 8 = 14 values."""
+    K = fem.Ke_elastic(1.0, 0.3).reshape(8, 3, 8, 3)
+    vals = {}
+    for a in range(8):
+        for m in range(8):
+            dl = a ^ m
+            for d in range(3):
+                for d2 in range(3):
+                    s = (-1) ** (((a >> d) & 1) + ((a >> d2) & 1))
+                    if d == d2:
+                        key = ("diag", (dl >> d) & 1, bin(dl & ~(1 << d) & 7).count("1"))
+                    else:
+                        t = 3 - d - d2
+                        key = ("off", (dl >> d) & 1, (dl >> d2) & 1, (dl >> t) & 1)
+                    vals.setdefault(key, []).append(s * K[a, d, m, d2])
+    assert len(vals) == 14
+    for key, v in vals.items():
+        assert np.ptp(v) <= 1e-13 * np.abs(K).max(), key
