@@ -119,7 +119,8 @@ def uneven_batch(args):
                 dofs += H.n_n(1) * H.c * H.d
                 its.append(rep["iterations"])
                 if record is not None:
-                    record.append({"seed": cells[j][0], "N": H.N, "physics": H.physics, "its": rep["iterations"]})
+                    record.append({"seed": cells[j][0], "family": cells[j][1], "vf": cells[j][2], "N": H.N,
+                                   "physics": H.physics, "its": rep["iterations"], "outer": rep["outer"]})
                 H.close()
             del us, fs, hs
             print(f"# {k}/{len(order)} cells done", file=sys.stderr, flush=True)
@@ -147,6 +148,9 @@ def uneven_batch(args):
            "dof_solves_per_s": round(dofs / wall, 1), "iterations_mean": float(np.mean(its)),
            "iterations_max": int(np.max(its)), "not_converged": failed}
     print(json.dumps(out), flush=True)
+    if os.environ.get("GMT_BENCH_CELLS"):
+        with open(os.environ["GMT_BENCH_CELLS"], "w") as fh:
+            json.dump(record, fh, indent=1)
 
 
 def cpu_baseline(tol):
