@@ -87,6 +87,9 @@ __host__ __device__ constexpr bool scls_negative(int j, int d, int d2) {
   return o[d] * o[d2] < 0;
 }
 
+// ints per row of the level-1 boundary neighbour table (27 ids + 1 pad)
+constexpr int kBndStride = 28;
+
 template <typename T>
 struct LevelView {
   int N;
@@ -107,6 +110,8 @@ struct LevelView {
   // n_runs + 1 entries with runs[n_runs] = n_int
   int n_runs;
   const int* runs;
+  // level 1: the 27 neighbour ids of boundary node t at bnd_nbrs[t * kBndStride ..]
+  const int* bnd_nbrs;
   const T* S;
   const T* kcls;  // symmetry-class values of K_e (14 elastic, 4 scalar)
   const T* scls;  // symmetry-class values of S (8 elastic, 4 scalar)
@@ -196,6 +201,8 @@ void launch_occ8(const int* node_lin, int n_n, const int* elem_map, int N, uint8
                  hipStream_t s);
 void launch_occ_flags(const uint8_t* occ8, int n, int want_full, int* flags, hipStream_t s);
 void launch_run_flags(const int* interior, int n_int, const int* node_lin, int N, int* flags, hipStream_t s);
+void launch_boundary_nbrs(const int* boundary, int n_bnd, const int* node_lin, const int* node_map, int N, int* table,
+                          hipStream_t s);
 void launch_gather_cmask(const int* elem_lin, int n_e, const uint8_t* dense_cmask, uint8_t* cmask,
                          hipStream_t s);
 void launch_elem_nodes(const int* elem_lin, int n_e, const int* node_map, int N, int* out,
@@ -231,6 +238,7 @@ struct LevelData {
   int n_int = 0, n_bnd = 0;
   int* runs = nullptr;        // level 1: chunk starts of `interior` (+ sentinel)
   int n_runs = 0;
+  int* bnd_nbrs = nullptr;    // level 1: neighbour ids of the boundary nodes (kBndStride per node)
   double* Kel64 = nullptr;    // per element, levels >= 3
   float* Kel32 = nullptr;
   double* diag64 = nullptr;   // [n_n][d]

@@ -123,6 +123,7 @@ LevelView<T> Hier::view(int l) const {
   v.boundary = d.boundary;
   v.n_runs = d.n_runs;
   v.runs = d.runs;
+  v.bnd_nbrs = d.bnd_nbrs;
   if constexpr (std::is_same<T, double>::value) {
     v.K = d.kind == KIND_SHARED ? Ke64 : (d.kind == KIND_TABLE ? table64 : d.Kel64);
     v.S = S64;
@@ -1009,6 +1010,12 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
       const int sentinel = d.n_int;
       GMT_HIP(hipMemcpyAsync(d.runs + nr, &sentinel, sizeof(int), hipMemcpyHostToDevice, s));
       d.n_runs = (int)nr;
+    }
+    if (d.n_bnd > 0) {
+      d.bnd_nbrs = h.alloc<int>((size_t)d.n_bnd * kBndStride);
+      if (reinterpret_cast<uintptr_t>(d.bnd_nbrs) % 16 != 0)  // the sweeps read its rows as int4
+        fail(GMT_E_STATE, "boundary neighbour table is not 16-byte aligned");
+      launch_boundary_nbrs(d.boundary, d.n_bnd, d.node_lin, d.node_map, d.N, d.bnd_nbrs, s);
     }
     GMT_HIP(hipStreamSynchronize(s));
     h.release(tmpmap);

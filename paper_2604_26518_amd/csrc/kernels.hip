@@ -100,28 +100,39 @@ __device__ __forceinline__ void epilogue_node(const EpiArgs<T>& e, const T* __re
       dd[c][q] = EPI == EPI_CHEB ? e.dvec[idx] : T(0);
       us[c][q] = needs_dinv<EPI>() ? (uself ? uself[c * D + q] : u[idx]) : T(0);
     }
+  // results first, then each output array's D values of a case as one run of
+  // stores (interleaving stores to the two possibly aliasing arrays would keep
+  // them from merging into one wide store)
+  T o[CC][D], dn[CC][D];
 #pragma unroll
   for (int c = 0; c < CC; ++c)
 #pragma unroll
     for (int q = 0; q < D; ++q) {
-      const size_t idx = vix(c0 + c, n, i, D, q);
       const T a = acc[c * D + q];
+      dn[c][q] = T(0);
       if constexpr (EPI == EPI_KU) {
-        e.out[idx] = a;
+        o[c][q] = a;
       } else if constexpr (EPI == EPI_RESID) {
-        e.out[idx] = fv[c][q] - a;
+        o[c][q] = fv[c][q] - a;
       } else if constexpr (EPI == EPI_JACOBI) {
-        e.out[idx] = us[c][q] + e.omega * di[q] * (fv[c][q] - a);
+        o[c][q] = us[c][q] + e.omega * di[q] * (fv[c][q] - a);
       } else if constexpr (EPI == EPI_CHEB) {
-        const T dn = e.rho1 * dd[c][q] + e.rho2 * di[q] * (fv[c][q] - a);
-        e.dvec[idx] = dn;
-        e.out[idx] = us[c][q] + dn;
+        dn[c][q] = e.rho1 * dd[c][q] + e.rho2 * di[q] * (fv[c][q] - a);
+        o[c][q] = us[c][q] + dn[c][q];
       } else {  // EPI_CHEB0
-        const T dn = e.rho2 * di[q] * (fv[c][q] - a);
-        e.dvec[idx] = dn;
-        e.out[idx] = us[c][q] + dn;
+        dn[c][q] = e.rho2 * di[q] * (fv[c][q] - a);
+        o[c][q] = us[c][q] + dn[c][q];
       }
     }
+#pragma unroll
+  for (int c = 0; c < CC; ++c) {
+    if constexpr (EPI == EPI_CHEB || EPI == EPI_CHEB0) {
+#pragma unroll
+      for (int q = 0; q < D; ++q) e.dvec[vix(c0 + c, n, i, D, q)] = dn[c][q];
+    }
+#pragma unroll
+    for (int q = 0; q < D; ++q) e.out[vix(c0 + c, n, i, D, q)] = o[c][q];
+  }
 }
 
 // Structural zeros of the assembled interior stencil of the isotropic voxel
@@ -310,6 +321,22 @@ __global__ __launch_bounds__(kBlock) void k_apply_interior_run(LevelView<T> L, i
 // chunk starts of the interior list: t begins a run unless it continues the
 // previous interior node along x (next id, next linear index) and x is not a
 // multiple of kRun
+// Level 1: the 27 neighbour ids (-1: inactive) of every boundary node, in
+// rows of kBndStride ints (16-byte aligned), so that a sweep reads them with
+// a few wide loads instead of 27 dense-map lookups.
+__global__ void k_boundary_nbrs(const int* __restrict__ boundary, int n_bnd, const int* __restrict__ node_lin,
+                                const int* __restrict__ node_map, int N, int* __restrict__ table) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n_bnd) return;
+  const int lin = node_lin[boundary[t]];
+  int nb[27];
+  neighbour_ids<false>(node_map, N, lin % N, (lin / N) % N, lin / (N * N), nb);
+  int* row = table + (size_t)t * kBndStride;
+#pragma unroll
+  for (int j = 0; j < 27; ++j) row[j] = nb[j];
+  row[27] = -1;
+}
+
 __global__ void k_run_flags(const int* __restrict__ interior, int n_int, const int* __restrict__ node_lin, int N,
                             int* __restrict__ flags) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -497,23 +524,30 @@ __global__ __launch_bounds__(kBlock) void k_apply_boundary_cls(LevelView<T> L, c
   const int c0 = (int)blockIdx.y * C;  // this grid row's first case
   if (t >= L.n_bnd) return;
   const int i = L.boundary[t];
-  const int N = L.N;
   const size_t n = (size_t)L.n_n;
-  const int lin = L.node_lin[i];
-  const int x = lin % N, y = (lin / N) % N, z = lin / (N * N);
   const unsigned occ = L.occ8[i];
   constexpr int NK = D == 1 ? 4 : 14;
   T kc[NK];
 #pragma unroll
   for (int c = 0; c < NK; ++c) kc[c] = L.kcls[c];
+  int nb[kBndStride];
+  {
+    const int4* row = reinterpret_cast<const int4*>(L.bnd_nbrs + (size_t)t * kBndStride);
+#pragma unroll
+    for (int k = 0; k < kBndStride / 4; ++k) {
+      const int4 v = row[k];
+      nb[4 * k] = v.x;
+      nb[4 * k + 1] = v.y;
+      nb[4 * k + 2] = v.z;
+      nb[4 * k + 3] = v.w;
+    }
+  }
   T mk[8], mkn[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     mk[k] = (occ >> k) & 1u ? T(1) : T(0);
     mkn[k] = -mk[k];
   }
-  int nb[27];
-  neighbour_ids<false>(L.node_map, N, x, y, z, nb);
   T acc[C][D];
 #pragma unroll
   for (int c = 0; c < C; ++c)
@@ -1750,6 +1784,14 @@ int64_t scan_compact(const int* flags, size_t n, int* map_out, int* lin_out, int
 void launch_occ8(const int* node_lin, int n_n, const int* emap, int N, uint8_t* occ8, hipStream_t s) {
   if (!n_n) return;
   hipLaunchKernelGGL(k_occ8, dim3(blocks_for(n_n)), dim3(kBlock), 0, s, node_lin, n_n, emap, N, occ8);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_boundary_nbrs(const int* boundary, int n_bnd, const int* node_lin, const int* node_map, int N, int* table,
+                          hipStream_t s) {
+  if (!n_bnd) return;
+  hipLaunchKernelGGL(k_boundary_nbrs, dim3(blocks_for(n_bnd)), dim3(kBlock), 0, s, boundary, n_bnd, node_lin, node_map,
+                     N, table);
   GMT_LAUNCH_CHECK();
 }
 
