@@ -106,6 +106,13 @@ static int forced_l1_variant() {
   return e && *e ? std::atoi(e) : -1;
 }
 
+// GMT_FORCE_COARSE_VARIANT=<cb> pins the sweep variant of levels >= 2 (0..3:
+// all cases or one case per thread, element- or neighbour-major) for tests.
+static int forced_coarse_variant() {
+  const char* e = std::getenv("GMT_FORCE_COARSE_VARIANT");
+  return e && *e ? std::atoi(e) : -1;
+}
+
 template <typename T>
 LevelView<T> Hier::view(int l) const {
   const LevelData& d = lv[l];
@@ -140,6 +147,10 @@ LevelView<T> Hier::view(int l) const {
     v.bs = d.bs32;
     v.xcd = d.xcd32;
     v.cb = d.cb32;
+  }
+  if (l > 0) {
+    const int f = forced_coarse_variant();
+    if (f >= 0 && f <= 3) v.cb = f;
   }
   if (l == 0) {
     const int f = forced_l1_variant();
@@ -631,8 +642,8 @@ static void autotune(Hier& h, hipStream_t s) {
       if (h.C > 1) cand.insert(cand.end(), {{256, 1, 1}, {256, 1, 0}});
     }
     if (l > 0) {
-      cand.insert(cand.end(), {{64, 0, 1}, {64, 0, 0}});
-      if (h.C > 1) cand.insert(cand.end(), {{256, 1, 1}, {256, 1, 0}, {64, 1, 1}, {64, 1, 0}});
+      cand.insert(cand.end(), {{64, 0, 1}, {64, 0, 0}, {64, 2, 1}, {256, 2, 1}});
+      if (h.C > 1) cand.insert(cand.end(), {{256, 1, 1}, {256, 1, 0}, {64, 1, 1}, {64, 1, 0}, {64, 3, 1}, {256, 3, 1}});
     }
     float best = INFINITY;
     Shape pick = cand[0];

@@ -663,7 +663,13 @@ __global__ __launch_bounds__(kBlock) void k_apply_boundary(LevelView<T> L, int C
 // the 64 (element, corner) blocks are independent and overlap in flight; the
 // D x D coefficient block of a corner is loaded once for the CB cases a thread
 // owns (CB = c, or 1 with one grid row per case on small levels).
-template <typename T, int D, int CB, int KIND, int EPI, int BS>
+// NM (neighbour-major): the block of each of the 27 neighbours is first summed
+// over the elements that contain both nodes, then the neighbour's values are
+// gathered once for the CB cases — 27 gathers per case instead of one per
+// (element, corner) pair (64), the sweep cost following the number of memory
+// instructions.  An inactive element enters with weight 0 (its loads read a
+// valid matrix), an inactive neighbour with a zero block.
+template <typename T, int D, int CB, int KIND, int EPI, int BS, int NM = 0>
 __global__ __launch_bounds__(BS) void k_apply_coarse(LevelView<T> L, const T* __restrict__ u, EpiArgs<T> e) {
   const int i = block_index(L.xcd) * BS + threadIdx.x;
   if (i >= L.n_n) return;
@@ -688,6 +694,50 @@ __global__ __launch_bounds__(BS) void k_apply_coarse(LevelView<T> L, const T* __
 #pragma unroll
     for (int q = 0; q < D; ++q) acc[c][q] = T(0);
   constexpr int M = 8 * D;
+  if constexpr (NM) {
+    const T* Kk[8];
+    T mk[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const bool act = eid[k] >= 0;
+      mk[k] = act ? T(1) : T(0);
+      const int ek = act ? eid[k] : 0;
+      if constexpr (KIND == KIND_TABLE)
+        Kk[k] = L.K + (size_t)(act ? L.cmask[ek] : 0) * M * M + (7 - k) * D * M;
+      else
+        Kk[k] = L.K + (size_t)ek * M * M + (7 - k) * D * M;
+    }
+#pragma unroll
+    for (int j = 0; j < 27; ++j) {
+      const int jx = j % 3, jy = (j / 3) % 3, jz = j / 9;
+      T cj[D][D];
+#pragma unroll
+      for (int q = 0; q < D; ++q)
+#pragma unroll
+        for (int q2 = 0; q2 < D; ++q2) cj[q][q2] = T(0);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int dx = jx - (k & 1), dy = jy - ((k >> 1) & 1), dz = jz - (k >> 2);
+        if (dx < 0 || dx > 1 || dy < 0 || dy > 1 || dz < 0 || dz > 1) continue;  // j is not a corner of element k
+        const int m = dx + 2 * dy + 4 * dz;
+#pragma unroll
+        for (int q = 0; q < D; ++q)
+#pragma unroll
+          for (int q2 = 0; q2 < D; ++q2) cj[q][q2] = fma(mk[k], Kk[k][q * M + m * D + q2], cj[q][q2]);
+      }
+      const size_t id = nb[j] >= 0 ? nb[j] : 0;
+#pragma unroll
+      for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int q2 = 0; q2 < D; ++q2) {
+          const T v = u[vix(c0 + c, n, id, D, q2)];
+#pragma unroll
+          for (int q = 0; q < D; ++q) acc[c][q] = fma(cj[q][q2], v, acc[c][q]);
+        }
+    }
+    epilogue_node<T, EPI, CB, D>(e, u, n, i, c0, &acc[0][0], nullptr, nullptr);
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     if (eid[k] < 0) continue;
@@ -1436,18 +1486,26 @@ inline unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlo
 // coarse-level sweep: CB cases per thread, C / CB grid rows, workgroup size L.bs
 template <typename T, int D, int CB, int EPI>
 static void launch_coarse(const LevelView<T>& L, int kind, int rows, const T* u, const EpiArgs<T>& e, hipStream_t s) {
+  const bool nm = L.cb >= 2;  // neighbour-major variants
   if (L.bs == 64) {
     const dim3 g((unsigned)((L.n_n + 63) / 64), (unsigned)rows);
-    if (kind == KIND_TABLE)
-      hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_TABLE, EPI, 64>), g, dim3(64), 0, s, L, u, e);
-    else
-      hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_PERELEM, EPI, 64>), g, dim3(64), 0, s, L, u, e);
+    if (kind == KIND_TABLE) {
+      if (nm) hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_TABLE, EPI, 64, 1>), g, dim3(64), 0, s, L, u, e);
+      else hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_TABLE, EPI, 64>), g, dim3(64), 0, s, L, u, e);
+    } else {
+      if (nm) hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_PERELEM, EPI, 64, 1>), g, dim3(64), 0, s, L, u, e);
+      else hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_PERELEM, EPI, 64>), g, dim3(64), 0, s, L, u, e);
+    }
   } else {
     const dim3 g(blocks_for(L.n_n), (unsigned)rows);
-    if (kind == KIND_TABLE)
-      hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_TABLE, EPI, kBlock>), g, dim3(kBlock), 0, s, L, u, e);
-    else
-      hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_PERELEM, EPI, kBlock>), g, dim3(kBlock), 0, s, L, u, e);
+    if (kind == KIND_TABLE) {
+      if (nm) hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_TABLE, EPI, kBlock, 1>), g, dim3(kBlock), 0, s, L, u, e);
+      else hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_TABLE, EPI, kBlock>), g, dim3(kBlock), 0, s, L, u, e);
+    } else {
+      if (nm)
+        hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_PERELEM, EPI, kBlock, 1>), g, dim3(kBlock), 0, s, L, u, e);
+      else hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_PERELEM, EPI, kBlock>), g, dim3(kBlock), 0, s, L, u, e);
+    }
   }
 }
 
@@ -1496,7 +1554,8 @@ static void apply_dispatch_kind(const LevelView<T>& L, int kind, const T* u, con
     }
   } else {
     if (L.n_n == 0) return;
-    if (L.cb == 1 && C > 1)
+    // cb 0 / 2: all cases per thread; cb 1 / 3: one grid row per case (2, 3: neighbour-major)
+    if ((L.cb == 1 || L.cb == 3) && C > 1)
       launch_coarse<T, D, 1, EPI>(L, kind, C, u, e, s);
     else
       launch_coarse<T, D, C, EPI>(L, kind, 1, u, e, s);

@@ -175,6 +175,29 @@ def test_level1_sweep_variants(pair, variant, monkeypatch):
     assert np.abs(out - osolve.chebyshev(P, 0, u0, P.f, 3, lo, hi)).max() <= 1e-12 * np.abs(out).max()
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_coarse_sweep_variants(pair, variant, monkeypatch):
+    """Every sweep variant of levels >= 2 (all cases or one case per thread; element-major,
+    or neighbour-major with the coefficient blocks summed before one gather per neighbour):
+    K.u in both precisions and the Chebyshev smoother on every coarse level."""
+    name, vox, P, H = pair
+    monkeypatch.setenv("GMT_FORCE_COARSE_VARIANT", str(variant))
+    lam = _bounds(P, H)
+    for l in range(2, P.L):
+        n = P.levels[l - 1].n_n
+        u0 = random_vectors(n, P.c * P.d, 51 + l).reshape(n, P.c, P.d)
+        ref = oops.apply_K(P.levels[l - 1], P.mats[l - 1], u0)
+        scale = np.abs(ref).max()
+        for dtype, tol in ((torch.float64, 1e-13), (torch.float32, 2e-6)):
+            y = _np(H.apply_K(_t(u0, dtype), l)).astype(np.float64)
+            assert np.abs(y - ref).max() <= tol * scale * 50, (l, variant, dtype)
+        lo, hi = lam[l - 1] / 30, 1.1 * lam[l - 1]
+        fl = random_vectors(n, P.c * P.d, 61 + l).reshape(n, P.c, P.d)
+        out = _np(H.smooth(_t(fl), _t(u0), 2, "chebyshev", lo, hi, level=l))
+        ref_s = osolve.chebyshev(P, l - 1, u0, fl, 2, lo, hi)
+        assert np.abs(out - ref_s).max() <= 1e-12 * np.abs(ref_s).max(), (l, variant)
+
+
 def test_lambda_estimate(pair):
     name, vox, P, H = pair
     for l in range(1, P.L + 1):
