@@ -642,8 +642,8 @@ static void autotune(Hier& h, hipStream_t s) {
       if (h.C > 1) cand.insert(cand.end(), {{256, 1, 1}, {256, 1, 0}});
     }
     if (l > 0) {
-      cand.insert(cand.end(), {{64, 0, 1}, {64, 0, 0}, {64, 2, 1}, {256, 2, 1}});
-      if (h.C > 1) cand.insert(cand.end(), {{256, 1, 1}, {256, 1, 0}, {64, 1, 1}, {64, 1, 0}, {64, 3, 1}, {256, 3, 1}});
+      cand.insert(cand.end(), {{64, 0, 1}, {64, 0, 0}, {64, 2, 1}, {64, 2, 0}});
+      if (h.C > 1) cand.insert(cand.end(), {{256, 1, 1}, {256, 1, 0}, {64, 1, 1}, {64, 1, 0}, {64, 3, 1}});
     }
     float best = INFINITY;
     Shape pick = cand[0];

@@ -1486,8 +1486,8 @@ inline unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlo
 // coarse-level sweep: CB cases per thread, C / CB grid rows, workgroup size L.bs
 template <typename T, int D, int CB, int EPI>
 static void launch_coarse(const LevelView<T>& L, int kind, int rows, const T* u, const EpiArgs<T>& e, hipStream_t s) {
-  const bool nm = L.cb >= 2;  // neighbour-major variants
-  if (L.bs == 64) {
+  const bool nm = L.cb >= 2;  // neighbour-major variants (64-wide workgroups only)
+  if (L.bs == 64 || nm) {
     const dim3 g((unsigned)((L.n_n + 63) / 64), (unsigned)rows);
     if (kind == KIND_TABLE) {
       if (nm) hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_TABLE, EPI, 64, 1>), g, dim3(64), 0, s, L, u, e);
@@ -1498,14 +1498,10 @@ static void launch_coarse(const LevelView<T>& L, int kind, int rows, const T* u,
     }
   } else {
     const dim3 g(blocks_for(L.n_n), (unsigned)rows);
-    if (kind == KIND_TABLE) {
-      if (nm) hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_TABLE, EPI, kBlock, 1>), g, dim3(kBlock), 0, s, L, u, e);
-      else hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_TABLE, EPI, kBlock>), g, dim3(kBlock), 0, s, L, u, e);
-    } else {
-      if (nm)
-        hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_PERELEM, EPI, kBlock, 1>), g, dim3(kBlock), 0, s, L, u, e);
-      else hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_PERELEM, EPI, kBlock>), g, dim3(kBlock), 0, s, L, u, e);
-    }
+    if (kind == KIND_TABLE)
+      hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_TABLE, EPI, kBlock>), g, dim3(kBlock), 0, s, L, u, e);
+    else
+      hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_PERELEM, EPI, kBlock>), g, dim3(kBlock), 0, s, L, u, e);
   }
 }
 
