@@ -8,7 +8,13 @@ coarse factor, load vector, mixed-precision GMG-PCG (FP32 bulk, FP64
 refinement) to relative residual 1e-5 -- all cells in one batched call
 (gmt_solve_batch) -- and the FP64 C_H reduction.
 
-Prints one JSON line (see the design doc for the field definitions).
+Prints one JSON line: metric, value (ms per cell, whole path), ms_per_step, the
+batch config, solve-only time, DOF-solves/s, PCG iteration counts; "roofline" for
+the level-1 Chebyshev sweep (372 algorithmic bytes per node over its duration,
+timed with HIP events on the launch stream, against 8 TB/s; "traffic" is the
+counter-measured HBM bytes per sweep of the cell and variant it was measured on,
+else null); "learned" (plain vs learned initializer on the same cells) when the
+weights exist; "cpu_baseline" (the CPU oracle on a 64^3 sample, scaled by nodes).
 """
 
 from __future__ import annotations
@@ -214,8 +220,8 @@ def main():
     ap.add_argument("--mem-gb", type=float, default=120.0, help="uneven workload: GPU memory per solve chunk")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "sharding is a design note in DESIGN.md, not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding the "
+              "path over several GPUs is not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch

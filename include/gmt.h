@@ -171,7 +171,7 @@ gmt_status gmt_residual(gmt_hier_t h, int32_t level, const void* d_f, const void
                         int32_t dtype, void* stream);
 
 /* nu smoothing steps on level l in place on d_u (weighted Jacobi with omega = p1,
- * or Chebyshev on [lo, hi] = [p1, p2]); the smoother of Alg. 1 lines 3 and 12. */
+ * or Chebyshev on [lo, hi] = [p1, p2]); the pre- and post-smoother of Alg. 1. */
 gmt_status gmt_smooth(gmt_hier_t h, int32_t level, const void* d_f, void* d_u, int32_t nu,
                       int32_t smoother, double p1, double p2, int32_t dtype, void* stream);
 
@@ -190,7 +190,8 @@ gmt_status gmt_coarse_solve(gmt_hier_t h, const void* d_f, void* d_u, int32_t dt
 /* One V-cycle (Alg. 2) in place on d_u (level-1 vector, its initial guess u^1).
  * d_e_init: NULL, or an array of L pointers indexed by level-1 whose entries
  * 2..L-1 (indices 1..L-2) may be NULL or point to injected corrections
- * e^l[n_n^l][c][d] (Alg. 2 line 6); entry L is unused (exact coarsest solve). */
+ * e^l[n_n^l][c][d] (the coarse-level injection of Alg. 2); entry L is unused (exact
+ * coarsest solve). */
 gmt_status gmt_vcycle(gmt_hier_t h, const void* d_f, void* d_u, const void* const* d_e_init,
                       const gmt_cycle_opts* opts, int32_t dtype, void* stream);
 
