@@ -143,7 +143,8 @@ void launch_apply(const LevelView<T>& L, int kind, int D, int C, int epi, const 
 template <typename T>
 void launch_smooth_zero(int n, int D, int C, const T* f, const T* dinv, T scale, T* out, T* dvec,
                         hipStream_t s);
-void launch_normalize(const double* src, size_t n, const double* nrm2, double* dst, hipStream_t s);
+template <typename T>
+void launch_normalize(const T* src, size_t n, const double* nrm2, T* dst, hipStream_t s);
 template <typename T>
 void launch_restrict(const LevelView<T>& fine, const LevelView<T>& coarse, int Q, int D, const T* rf, T* fc,
                      hipStream_t s);

@@ -1156,26 +1156,42 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
   launch_load_vector(h.lv[0].node_lin, h.lv[0].occ8, h.lv[0].n_n, D, h.C, h.fe64, h.f64, s);
 
   timer.mark("diag+load");
-  // lambda_max(D^-1 K) per level by power iteration (FP64, one vector)
+  void* pw[6] = {};
+  // lambda_max(D^-1 K) per level by power iteration. The iterate only has to
+  // point at the top of the spectrum, so the iterations run in FP32 (half the
+  // operator bytes); the Rayleigh quotient that becomes the estimate is taken in
+  // FP64, so the estimate stays below lambda_max up to FP64 rounding.
   {
     const int iters = h.p.power_iters > 0 ? h.p.power_iters : 20;
     size_t nmax = 0;
     for (auto& d : h.lv) nmax = std::max(nmax, (size_t)d.n_n * D);
+    float* x32 = h.alloc<float>(nmax);  // released after the stream sync below
+    float* y32 = h.alloc<float>(nmax);
+    float* t32 = h.alloc<float>(nmax);
     double* x = h.alloc<double>(nmax);
     double* y = h.alloc<double>(nmax);
     double* t = h.alloc<double>(nmax);
     for (int l = 0; l < h.L; ++l) {
       LevelData& d = h.lv[l];
       const int n = d.n_n;
-      launch_random(x, (size_t)n * D, h.p.seed + 0x1000193ull * (l + 1), s);
+      const size_t nd = (size_t)n * D;
+      launch_random(x, nd, h.p.seed + 0x1000193ull * (l + 1), s);
+      launch_convert<double, float>(x, x32, nd, s);
       double* o = h.red_out + 64;
-      // x <- D^-1 K x / ||D^-1 K x||, normalised on the device (no host round trip)
+      // x <- D^-1 K x, normalised on the device (no host round trip) every
+      // fourth step and after the last; D^-1 K has eigenvalues of order one, so
+      // four unnormalised steps stay far inside the FP32 range.
       for (int it = 0; it < iters; ++it) {
-        apply<double>(h, l, EPI_KU, x, nullptr, y, 1, s);
-        launch_smooth_zero<double>(n, D, 1, y, d.dinv64, 1.0, t, nullptr, s);  // t = D^-1 K x
-        launch_dot<double>(t, t, n, 1, D, h.red_partial, o + 2, s);
-        launch_normalize(t, (size_t)n * D, o + 2, x, s);
+        apply<float>(h, l, EPI_KU, x32, nullptr, y32, 1, s);
+        launch_smooth_zero<float>(n, D, 1, y32, d.dinv32, 1.0f, t32, nullptr, s);  // t = D^-1 K x
+        if ((it + 1) % 4 == 0 || it + 1 == iters) {
+          launch_dot<float>(t32, t32, n, 1, D, h.red_partial, o + 2, s);
+          launch_normalize<float>(t32, nd, o + 2, x32, s);
+        } else {
+          std::swap(x32, t32);
+        }
       }
+      launch_convert<float, double>(x32, x, nd, s);
       // Rayleigh quotient x.Kx / x.Dx (a lower bound of lambda_max)
       apply<double>(h, l, EPI_KU, x, nullptr, y, 1, s);
       launch_smooth_zero<double>(n, D, 1, x, d.diag64, 1.0, t, nullptr, s);  // t = D x
@@ -1187,9 +1203,11 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
       if (!(lam > 0) || !std::isfinite(lam)) fail(GMT_E_SINGULAR, "lambda_max estimate failed on level %d", l + 1);
       d.lam = lam;
     }
+    pw[0] = x32, pw[1] = y32, pw[2] = t32, pw[3] = x, pw[4] = y, pw[5] = t;
   }
   timer.mark("lambda");
   GMT_HIP(hipStreamSynchronize(s));
+  for (void* b : pw) h.release(b);
   h.release(flags);
   h.release(scr);
   h.release(d_total);

@@ -773,12 +773,13 @@ __global__ __launch_bounds__(BS) void k_apply_coarse(LevelView<T> L, const T* __
 
 // dst = src / sqrt(*nrm2), the squared norm read on the device; a zero or
 // non-finite norm leaves a zero vector (the caller's estimate then fails).
-__global__ void k_normalize(size_t n, const double* __restrict__ src, const double* __restrict__ nrm2,
-                            double* __restrict__ dst) {
+template <typename T>
+__global__ void k_normalize(size_t n, const T* __restrict__ src, const double* __restrict__ nrm2,
+                            T* __restrict__ dst) {
   const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const double v = *nrm2;
-  dst[i] = (v > 0.0 && v < INFINITY) ? src[i] / sqrt(v) : 0.0;
+  dst[i] = (v > 0.0 && v < INFINITY) ? T(double(src[i]) / sqrt(v)) : T(0);
 }
 
 // First smoothing step from a zero iterate: u = scale * D^-1 f (K 0 = 0).
@@ -1591,9 +1592,10 @@ void launch_smooth_zero(int n, int D, int C, const T* f, const T* dinv, T scale,
   GMT_LAUNCH_CHECK();
 }
 
-void launch_normalize(const double* src, size_t n, const double* nrm2, double* dst, hipStream_t s) {
+template <typename T>
+void launch_normalize(const T* src, size_t n, const double* nrm2, T* dst, hipStream_t s) {
   if (!n) return;
-  hipLaunchKernelGGL(k_normalize, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, src, nrm2, dst);
+  hipLaunchKernelGGL(k_normalize<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, src, nrm2, dst);
   GMT_LAUNCH_CHECK();
 }
 
@@ -1959,6 +1961,7 @@ void launch_random(double* x, size_t n, uint64_t seed, hipStream_t s) {
   template void launch_copy<T>(const T*, T*, size_t, hipStream_t);                                           \
   template void launch_inv<T>(const T*, T*, size_t, hipStream_t);                                            \
   template void launch_dot<T>(const T*, const T*, int, int, int, double*, double*, hipStream_t);             \
+  template void launch_normalize<T>(const T*, size_t, const double*, T*, hipStream_t);                     \
   template void launch_pcg_update<T>(T*, T*, const T*, const T*, const double*, int, int, int, hipStream_t);  \
   template void launch_pcg_direction<T>(T*, const T*, const double*, int, int, int, hipStream_t);            \
   template void launch_aos_to_soa<T, T>(const T*, T*, int, int, int, hipStream_t);                           \
