@@ -1171,13 +1171,13 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
     double* x = h.alloc<double>(nmax);
     double* y = h.alloc<double>(nmax);
     double* t = h.alloc<double>(nmax);
+    double* o = h.red_out + 64;
     for (int l = 0; l < h.L; ++l) {
       LevelData& d = h.lv[l];
       const int n = d.n_n;
       const size_t nd = (size_t)n * D;
       launch_random(x, nd, h.p.seed + 0x1000193ull * (l + 1), s);
       launch_convert<double, float>(x, x32, nd, s);
-      double* o = h.red_out + 64;
       // x <- D^-1 K x, normalised on the device (no host round trip) every
       // fourth step and after the last; D^-1 K has eigenvalues of order one, so
       // four unnormalised steps stay far inside the FP32 range.
@@ -1195,13 +1195,16 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
       // Rayleigh quotient x.Kx / x.Dx (a lower bound of lambda_max)
       apply<double>(h, l, EPI_KU, x, nullptr, y, 1, s);
       launch_smooth_zero<double>(n, D, 1, x, d.diag64, 1.0, t, nullptr, s);  // t = D x
-      launch_dot<double>(x, y, n, 1, D, h.red_partial, o, s);
-      launch_dot<double>(x, t, n, 1, D, h.red_partial, o + 1, s);
-      double hv[2];
-      host_dot(h, o, 2, hv, s);
-      const double lam = hv[1] > 0 ? hv[0] / hv[1] : 0.0;
+      launch_dot<double>(x, y, n, 1, D, h.red_partial, o + 4 + 2 * l, s);
+      launch_dot<double>(x, t, n, 1, D, h.red_partial, o + 5 + 2 * l, s);
+    }
+    // one host round trip for the quotients of all levels
+    double hv[2 * 12];
+    host_dot(h, o + 4, 2 * h.L, hv, s);
+    for (int l = 0; l < h.L; ++l) {
+      const double lam = hv[2 * l + 1] > 0 ? hv[2 * l] / hv[2 * l + 1] : 0.0;
       if (!(lam > 0) || !std::isfinite(lam)) fail(GMT_E_SINGULAR, "lambda_max estimate failed on level %d", l + 1);
-      d.lam = lam;
+      h.lv[l].lam = lam;
     }
     pw[0] = x32, pw[1] = y32, pw[2] = t32, pw[3] = x, pw[4] = y, pw[5] = t;
   }
