@@ -1172,6 +1172,11 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
     double* y = h.alloc<double>(nmax);
     double* t = h.alloc<double>(nmax);
     double* o = h.red_out + 64;
+    // One vector: on level 1 the class-assembled boundary sweep (cb 7) costs
+    // in proportion to the number of cases, the masked-stencil one (cb 0, the
+    // default before the autotuner runs) does not.
+    const int cb_keep = h.lv[0].cb32, cb_keep64 = h.lv[0].cb64;
+    if (h.lv[0].kind == KIND_SHARED) h.lv[0].cb32 = h.lv[0].cb64 = 7;
     for (int l = 0; l < h.L; ++l) {
       LevelData& d = h.lv[l];
       const int n = d.n_n;
@@ -1198,6 +1203,8 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
       launch_dot<double>(x, y, n, 1, D, h.red_partial, o + 4 + 2 * l, s);
       launch_dot<double>(x, t, n, 1, D, h.red_partial, o + 5 + 2 * l, s);
     }
+    h.lv[0].cb32 = cb_keep;
+    h.lv[0].cb64 = cb_keep64;
     // one host round trip for the quotients of all levels
     double hv[2 * 12];
     host_dot(h, o + 4, 2 * h.L, hv, s);
