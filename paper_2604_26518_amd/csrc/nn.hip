@@ -420,7 +420,8 @@ static void bgrad_dispatch(int cout, int n, const float* g, float* db, hipStream
 
 // ============================================================================ network
 
-// Parameter layout (flat FP32), in this order -- identical to the reference:
+// Parameter layout (flat FP32), in this order; the weight files and the oracle's FP64
+// network use the same flat vector:
 //   E [256][C0]
 //   for l < L:      We_l [27][C_l][C_l], be_l [C_l]
 //   for l < L-1:    Wp_l [27][C_l][C_{l+1}], bp_l [C_{l+1}]
