@@ -366,6 +366,42 @@ static void mask_table(const Hier& h, const double Ps[8][8][8], std::vector<doub
 // ================================================================ coarsest level
 
 // Dense FP64 Cholesky of the pinned coarsest matrix and its explicit inverse.
+// Auxiliary streams for independent setup work of one hierarchy (the power
+// iterations of its levels), four per device, created on first use and kept
+// for the life of the process; default priority, non-blocking.  Work on them
+// is ordered against the caller's stream by events only, so hierarchies built
+// at the same time from several threads may share them safely.
+static hipStream_t aux_stream(int k) {
+  static std::mutex mu;
+  static std::map<int, std::vector<hipStream_t>> pool;
+  int dev = 0;
+  GMT_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  std::vector<hipStream_t>& v = pool[dev];
+  if (v.empty()) {
+    for (int i = 0; i < 4; ++i) {
+      hipStream_t x = nullptr;
+      GMT_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+      v.push_back(x);
+    }
+  }
+  return v[(size_t)k % v.size()];
+}
+
+// Events (no timing) owned by a scope; destroyed when it ends.
+struct EventSet {
+  std::vector<hipEvent_t> ev;
+  hipEvent_t make() {
+    hipEvent_t e = nullptr;
+    GMT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ev.push_back(e);
+    return e;
+  }
+  ~EventSet() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
 static void coarse_factor(Hier& h, hipStream_t s) {
   const int l = h.L - 1;
   LevelData& d = h.lv[l];
@@ -1156,52 +1192,79 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
   launch_load_vector(h.lv[0].node_lin, h.lv[0].occ8, h.lv[0].n_n, D, h.C, h.fe64, h.f64, s);
 
   timer.mark("diag+load");
-  void* pw[6] = {};
+  void* pw[7] = {};
   // lambda_max(D^-1 K) per level by power iteration. The iterate only has to
   // point at the top of the spectrum, so the iterations run in FP32 (half the
   // operator bytes); the Rayleigh quotient that becomes the estimate is taken in
-  // FP64, so the estimate stays below lambda_max up to FP64 rounding.
+  // FP64, so the estimate stays below lambda_max up to FP64 rounding.  The
+  // levels are independent and their sweeps short (one vector, latency-bound
+  // on the coarse levels): level 1 runs on s, the others on auxiliary streams
+  // forked from s by an event and joined back before the host reads the
+  // quotients.  Each level has buffers and reduction slots of its own.
   {
     const int iters = h.p.power_iters > 0 ? h.p.power_iters : 20;
-    size_t nmax = 0;
-    for (auto& d : h.lv) nmax = std::max(nmax, (size_t)d.n_n * D);
-    float* x32 = h.alloc<float>(nmax);  // released after the stream sync below
-    float* y32 = h.alloc<float>(nmax);
-    float* t32 = h.alloc<float>(nmax);
-    double* x = h.alloc<double>(nmax);
-    double* y = h.alloc<double>(nmax);
-    double* t = h.alloc<double>(nmax);
-    double* o = h.red_out + 64;
+    std::vector<size_t> off(h.L + 1, 0);
+    for (int l = 0; l < h.L; ++l) off[l + 1] = off[l] + ((size_t)h.lv[l].n_n * D + 63) / 64 * 64;
+    float* X32 = h.alloc<float>(off[h.L]);  // released after the stream sync below
+    float* Y32 = h.alloc<float>(off[h.L]);
+    float* T32 = h.alloc<float>(off[h.L]);
+    double* X64 = h.alloc<double>(off[h.L]);
+    double* Y64 = h.alloc<double>(off[h.L]);
+    double* T64 = h.alloc<double>(off[h.L]);
+    double* part = h.alloc<double>((size_t)h.L * kRedBlocks);
+    pw[0] = X32, pw[1] = Y32, pw[2] = T32, pw[3] = X64, pw[4] = Y64, pw[5] = T64, pw[6] = part;
+    double* o = h.red_out + 64;  // [4 + 2l, 5 + 2l]: quotient of level l; [40 + l]: its norm
     // One vector: on level 1 the class-assembled boundary sweep (cb 7) costs
     // in proportion to the number of cases, the masked-stencil one (cb 0, the
     // default before the autotuner runs) does not.
     const int cb_keep = h.lv[0].cb32, cb_keep64 = h.lv[0].cb64;
     if (h.lv[0].kind == KIND_SHARED) h.lv[0].cb32 = h.lv[0].cb64 = 7;
+    EventSet evs;
+    hipEvent_t fork = evs.make();
+    GMT_HIP(hipEventRecord(fork, s));
     for (int l = 0; l < h.L; ++l) {
       LevelData& d = h.lv[l];
       const int n = d.n_n;
       const size_t nd = (size_t)n * D;
-      launch_random(x, nd, h.p.seed + 0x1000193ull * (l + 1), s);
-      launch_convert<double, float>(x, x32, nd, s);
+      hipStream_t sl = s;
+      if (l > 0) {
+        sl = aux_stream(l - 1);
+        GMT_HIP(hipStreamWaitEvent(sl, fork, 0));
+      }
+      float* x32 = X32 + off[l];
+      float* y32 = Y32 + off[l];
+      float* t32 = T32 + off[l];
+      double* x = X64 + off[l];
+      double* y = Y64 + off[l];
+      double* t = T64 + off[l];
+      double* pl = part + (size_t)l * kRedBlocks;
+      double* nrm = o + 40 + l;
+      launch_random(x, nd, h.p.seed + 0x1000193ull * (l + 1), sl);
+      launch_convert<double, float>(x, x32, nd, sl);
       // x <- D^-1 K x, normalised on the device (no host round trip) every
       // fourth step and after the last; D^-1 K has eigenvalues of order one, so
       // four unnormalised steps stay far inside the FP32 range.
       for (int it = 0; it < iters; ++it) {
-        apply<float>(h, l, EPI_KU, x32, nullptr, y32, 1, s);
-        launch_smooth_zero<float>(n, D, 1, y32, d.dinv32, 1.0f, t32, nullptr, s);  // t = D^-1 K x
+        apply<float>(h, l, EPI_KU, x32, nullptr, y32, 1, sl);
+        launch_smooth_zero<float>(n, D, 1, y32, d.dinv32, 1.0f, t32, nullptr, sl);  // t = D^-1 K x
         if ((it + 1) % 4 == 0 || it + 1 == iters) {
-          launch_dot<float>(t32, t32, n, 1, D, h.red_partial, o + 2, s);
-          launch_normalize<float>(t32, nd, o + 2, x32, s);
+          launch_dot<float>(t32, t32, n, 1, D, pl, nrm, sl);
+          launch_normalize<float>(t32, nd, nrm, x32, sl);
         } else {
           std::swap(x32, t32);
         }
       }
-      launch_convert<float, double>(x32, x, nd, s);
+      launch_convert<float, double>(x32, x, nd, sl);
       // Rayleigh quotient x.Kx / x.Dx (a lower bound of lambda_max)
-      apply<double>(h, l, EPI_KU, x, nullptr, y, 1, s);
-      launch_smooth_zero<double>(n, D, 1, x, d.diag64, 1.0, t, nullptr, s);  // t = D x
-      launch_dot<double>(x, y, n, 1, D, h.red_partial, o + 4 + 2 * l, s);
-      launch_dot<double>(x, t, n, 1, D, h.red_partial, o + 5 + 2 * l, s);
+      apply<double>(h, l, EPI_KU, x, nullptr, y, 1, sl);
+      launch_smooth_zero<double>(n, D, 1, x, d.diag64, 1.0, t, nullptr, sl);  // t = D x
+      launch_dot<double>(x, y, n, 1, D, pl, o + 4 + 2 * l, sl);
+      launch_dot<double>(x, t, n, 1, D, pl, o + 5 + 2 * l, sl);
+      if (l > 0) {
+        hipEvent_t done = evs.make();
+        GMT_HIP(hipEventRecord(done, sl));
+        GMT_HIP(hipStreamWaitEvent(s, done, 0));
+      }
     }
     h.lv[0].cb32 = cb_keep;
     h.lv[0].cb64 = cb_keep64;
@@ -1213,7 +1276,6 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
       if (!(lam > 0) || !std::isfinite(lam)) fail(GMT_E_SINGULAR, "lambda_max estimate failed on level %d", l + 1);
       h.lv[l].lam = lam;
     }
-    pw[0] = x32, pw[1] = y32, pw[2] = t32, pw[3] = x, pw[4] = y, pw[5] = t;
   }
   timer.mark("lambda");
   GMT_HIP(hipStreamSynchronize(s));
