@@ -402,23 +402,47 @@ struct EventSet {
   }
 };
 
-static void coarse_factor(Hier& h, hipStream_t s) {
+// The coarsest level's element matrices and connectivity on the host.
+struct CoarseHost {
+  std::vector<double> Ke;
+  std::vector<int> en;
+  double* dK = nullptr;
+  int* dEN = nullptr;
+  hipEvent_t ready = nullptr;
+};
+
+// Queues the copies of the coarsest level's element matrices and connectivity
+// to the host on s; c.ready marks their completion.
+static void coarse_fetch(Hier& h, hipStream_t s, CoarseHost& c, EventSet& evs) {
   const int l = h.L - 1;
   LevelData& d = h.lv[l];
   const int D = h.D, M = 8 * D;
   const int n = d.n_n * D;
   if (n > 2048) fail(GMT_E_INVAL, "coarsest level has %d DOFs (> 2048): use more levels", n);
   h.cn = n;
-  // element matrices and connectivity of the coarsest level
-  double* dK = h.alloc<double>((size_t)d.n_e * M * M);
-  int* dEN = h.alloc<int>((size_t)d.n_e * 8);
-  launch_expand_elem_matrices(h.view<double>(l), d.kind, d.n_e, D, d.elem_lin, dK, s);
-  launch_elem_nodes(d.elem_lin, d.n_e, d.node_map, d.N, dEN, s);
-  std::vector<double> Ke((size_t)d.n_e * M * M);
-  std::vector<int> en((size_t)d.n_e * 8);
-  GMT_HIP(hipMemcpyAsync(Ke.data(), dK, Ke.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-  GMT_HIP(hipMemcpyAsync(en.data(), dEN, en.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-  GMT_HIP(hipStreamSynchronize(s));
+  c.dK = h.alloc<double>((size_t)d.n_e * M * M);
+  c.dEN = h.alloc<int>((size_t)d.n_e * 8);
+  launch_expand_elem_matrices(h.view<double>(l), d.kind, d.n_e, D, d.elem_lin, c.dK, s);
+  launch_elem_nodes(d.elem_lin, d.n_e, d.node_map, d.N, c.dEN, s);
+  c.Ke.resize((size_t)d.n_e * M * M);
+  c.en.resize((size_t)d.n_e * 8);
+  GMT_HIP(hipMemcpyAsync(c.Ke.data(), c.dK, c.Ke.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  GMT_HIP(hipMemcpyAsync(c.en.data(), c.dEN, c.en.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+  c.ready = evs.make();
+  GMT_HIP(hipEventRecord(c.ready, s));
+}
+
+// Assembles, pins and inverts the coarsest operator on the host once the
+// copies of coarse_fetch have landed (work queued on s after them keeps
+// running meanwhile), then uploads the inverse on s and waits for s.
+static void coarse_factor(Hier& h, hipStream_t s, CoarseHost& c) {
+  const int l = h.L - 1;
+  LevelData& d = h.lv[l];
+  const int D = h.D, M = 8 * D;
+  const int n = h.cn;
+  GMT_HIP(hipEventSynchronize(c.ready));
+  const std::vector<double>& Ke = c.Ke;
+  const std::vector<int>& en = c.en;
   std::vector<double> A((size_t)n * n, 0.0);
   for (int e = 0; e < d.n_e; ++e)
     for (int a = 0; a < 8; ++a)
@@ -473,8 +497,8 @@ static void coarse_factor(Hier& h, hipStream_t s) {
   GMT_HIP(hipMemcpyAsync(h.cinv64, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice, s));
   launch_convert<double, float>(h.cinv64, h.cinv32, inv.size(), s);
   GMT_HIP(hipStreamSynchronize(s));
-  h.release(dK);
-  h.release(dEN);
+  h.release(c.dK);
+  h.release(c.dEN);
 }
 
 // ================================================================ building blocks
@@ -1192,6 +1216,9 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
   launch_load_vector(h.lv[0].node_lin, h.lv[0].occ8, h.lv[0].n_n, D, h.C, h.fe64, h.f64, s);
 
   timer.mark("diag+load");
+  EventSet evs;
+  CoarseHost ch;
+  coarse_fetch(h, s, ch, evs);
   void* pw[7] = {};
   // lambda_max(D^-1 K) per level by power iteration. The iterate only has to
   // point at the top of the spectrum, so the iterations run in FP32 (half the
@@ -1219,7 +1246,6 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
     // default before the autotuner runs) does not.
     const int cb_keep = h.lv[0].cb32, cb_keep64 = h.lv[0].cb64;
     if (h.lv[0].kind == KIND_SHARED) h.lv[0].cb32 = h.lv[0].cb64 = 7;
-    EventSet evs;
     hipEvent_t fork = evs.make();
     GMT_HIP(hipEventRecord(fork, s));
     for (int l = 0; l < h.L; ++l) {
@@ -1268,6 +1294,8 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
     }
     h.lv[0].cb32 = cb_keep;
     h.lv[0].cb64 = cb_keep64;
+    // the host factors the coarsest operator while the iterations run
+    coarse_factor(h, s, ch);
     // one host round trip for the quotients of all levels
     double hv[2 * 12];
     host_dot(h, o + 4, 2 * h.L, hv, s);
@@ -1277,15 +1305,13 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
       h.lv[l].lam = lam;
     }
   }
-  timer.mark("lambda");
+  timer.mark("lambda+coarse");
   GMT_HIP(hipStreamSynchronize(s));
   for (void* b : pw) h.release(b);
   h.release(flags);
   h.release(scr);
   h.release(d_total);
   h.release(dmask);
-  coarse_factor(h, s);
-  timer.mark("coarse");
 }
 
 // ================================================================ solve
