@@ -121,6 +121,40 @@ def build(voxels: np.ndarray, levels: int):
     return out
 
 
+def node_components(elem_active: np.ndarray) -> int:
+    """Number of node-connected components of the active elements (periodic).
+
+    Two active elements are connected when they share at least one node, i.e.
+    when their voxel coordinates differ by at most one (mod N) along every
+    axis.  Every such component can translate freely, so the periodic
+    stiffness matrix has (components x d) rigid translations in its null space
+    (one pinned node fixes only one of them).  Graph search by scipy's
+    connected_components over that adjacency.
+    """
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+
+    act = np.asarray(elem_active, dtype=bool)
+    lin = np.flatnonzero(act.ravel())
+    if lin.size == 0:
+        return 0
+    flat = np.full(act.size, -1, dtype=np.int64)
+    flat[lin] = np.arange(lin.size)
+    eid = flat.reshape(act.shape)
+    rows, cols = [], []
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                nb = np.roll(eid, shift=(-dz, -dy, -dx), axis=(0, 1, 2))  # nb[z,y,x] = eid[z+dz, y+dy, x+dx]
+                m = (eid >= 0) & (nb >= 0)
+                rows.append(eid[m])
+                cols.append(nb[m])
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    A = sp.csr_matrix((np.ones(r.size), (r, c)), shape=(lin.size, lin.size))
+    return int(connected_components(A, directed=False)[0])
+
+
 def pinned_node(level: Level) -> int:
     """Gauge node: the lowest-id active node (id 0)."""
     return 0

@@ -9,8 +9,14 @@ sparse Galerkin operators for one voxel cell.
   interval [lo, hi].
 * ``coarse_solve``: exact solve at level L of the pinned coarsest operator
   (the lowest-id node's DOFs replaced by identity rows/columns, zero RHS).
+* ``gauss_seidel``: the 8-colour Gauss-Seidel / SOR smoother of Sec. 4.6
+  (parallel smoothing): nodes coloured by the parity of their coordinates,
+  the colours updated one after the other with u_i += omega D_i^-1 r_i.
 * ``vcycle``: Alg. 2 -- Alg. 1 with u^1 <- u_hat^1 and u^{l+1} <- e_hat^{l+1}
   instead of 0 when corrections are given.
+* ``cycle``: the same recursion with the W- and F-schedules of the schedule
+  study (Sec. 6.3): a coarse level is visited twice (W) or by an F-cycle
+  followed by a V-cycle (F) per visit of the level above it.
 * ``pcg``: CG on the pinned fine system (gauge: lowest-id node fixed),
   preconditioned by Jacobi or by the V-cycle, stopped on the true residual.
 * ``relative_residual``: r_m = ||f_m - K u_m||_2 / ||f_m||_2 per load case.
@@ -92,6 +98,42 @@ def chebyshev(prob: Problem, l: int, u, f, nu: int, lo: float, hi: float):
     return u
 
 
+def colours(level) -> np.ndarray:
+    """Colour of every active node: (x mod 2) + 2 (y mod 2) + 4 (z mod 2) (Sec. 4.6).
+
+    Two nodes of one colour differ by an even amount along every axis, so on a
+    level with an even number of voxels per axis (periodic wrap included) they
+    never share an element: each colour class is free of couplings.
+    """
+    N = level.N
+    lin = level.node_lin
+    return (lin % N) % 2 + 2 * (((lin // N) % N) % 2) + 4 * ((lin // (N * N)) % 2)
+
+
+def gauss_seidel(prob: Problem, l: int, u, f, nu: int, omega: float, reverse: bool = False):
+    """nu sweeps of the 8-colour Gauss-Seidel smoother (SOR with weight omega), Sec. 4.6.
+
+    One sweep visits the colours 0..7 (7..0 when ``reverse``); the nodes of a
+    colour are updated together, u_i += omega D_i^-1 r_i, from the residual
+    r = f - K u of the current iterate (so a colour sees the updates of the
+    colours before it).  D is the diagonal of K.  The backward sweep is the
+    adjoint of the forward one in the K inner product, so a cycle with forward
+    pre- and backward post-smoothing is a symmetric preconditioner.
+    """
+    col = colours(prob.levels[l])
+    Dinv = 1.0 / prob.D[l][:, None, :]
+    order = range(7, -1, -1) if reverse else range(8)
+    u = np.array(u, dtype=np.float64)
+    for _ in range(nu):
+        for c in order:
+            m = col == c
+            if not m.any():
+                continue
+            r = f - prob.Kmul(l, u)
+            u[m] = u[m] + omega * Dinv[m] * r[m]
+    return u
+
+
 def coarse_solve(prob: Problem, f):
     (cf, pin) = prob.coarse_factor()
     F = ops.to_dofs(f).copy()
@@ -99,9 +141,13 @@ def coarse_solve(prob: Problem, f):
     return ops.from_dofs(sla.cho_solve(cf, F), prob.d)
 
 
-def smooth(prob, l, u, f, nu, sm):
+def smooth(prob, l, u, f, nu, sm, post: bool = False):
+    """Pre- (post=False) or post-smoothing on level l; Gauss-Seidel runs its colours
+    forward before and backward after the coarse correction."""
     if sm["kind"] == "jacobi":
         return jacobi(prob, l, u, f, nu, sm["omega"][l])
+    if sm["kind"] == "gs":
+        return gauss_seidel(prob, l, u, f, nu, sm["omega"][l], reverse=post)
     return chebyshev(prob, l, u, f, nu, sm["lo"][l], sm["hi"][l])
 
 
@@ -128,12 +174,58 @@ def vcycle(prob: Problem, f, u, sm, nu1: int = 2, nu2: int = 2, e_init=None):
     ul[L - 1] = coarse_solve(prob, fl[L - 1])
     for l in range(L - 2, -1, -1):
         ul[l] = ul[l] + ops.prolong(prob.levels[l], ul[l + 1])
-        ul[l] = smooth(prob, l, ul[l], fl[l], nu2, sm)
+        ul[l] = smooth(prob, l, ul[l], fl[l], nu2, sm, post=True)
     return ul[0]
 
 
+def cycle(prob: Problem, f, u, sm, nu1: int = 2, nu2: int = 2, e_init=None, kind: str = "V"):
+    """One multigrid cycle with the V-, W- or F-schedule (Sec. 6.3 schedule study).
+
+    Visiting level l: pre-smooth, restrict the residual, approximately solve the
+    coarse correction problem on level l+1 starting from zero, prolong and add,
+    post-smooth.  The coarse problem is treated by one visit (V), two visits in
+    a row (W), or an F-visit followed by a V-visit (F); the coarsest level is
+    solved exactly (so a repeated visit there is skipped: it changes nothing).
+    Injection (Alg. 2 with several stages): e_hat^{l+1} replaces the zero start
+    of level l+1 at its first entry in the cycle only; later entries start
+    from zero and repeated visits continue from the current iterate.
+    """
+    if kind not in ("V", "W", "F"):
+        raise ValueError("kind must be V, W or F")
+    L = prob.L
+    entered = [False] * L
+
+    def visit(l, fl, ul, how):
+        if l == L - 1:
+            return coarse_solve(prob, fl)
+        ul = smooth(prob, l, ul, fl, nu1, sm)
+        r = fl - prob.Kmul(l, ul)
+        fc = ops.restrict(prob.levels[l], r, prob.levels[l + 1].n_n)
+        if e_init is not None and e_init[l + 1] is not None and not entered[l + 1] and l + 1 < L - 1:
+            uc = np.array(e_init[l + 1], dtype=np.float64)
+        else:
+            uc = np.zeros_like(fc)
+        entered[l + 1] = True
+        if how == "V":
+            uc = visit(l + 1, fc, uc, "V")
+        elif how == "W":
+            uc = visit(l + 1, fc, uc, "W")
+            if l + 1 < L - 1:
+                uc = visit(l + 1, fc, uc, "W")
+        else:
+            uc = visit(l + 1, fc, uc, "F")
+            if l + 1 < L - 1:
+                uc = visit(l + 1, fc, uc, "V")
+        ul = ul + ops.prolong(prob.levels[l], uc)
+        return smooth(prob, l, ul, fl, nu2, sm, post=True)
+
+    return visit(0, f, np.array(u, dtype=np.float64), kind)
+
+
 def default_smoother(prob: Problem, kind: str = "chebyshev", lo_frac: float = 1.0 / 30.0,
-                     hi_frac: float = 1.1):
+                     hi_frac: float = 1.1, omega: float = 1.0):
+    if kind == "gs":
+        return {"kind": "gs", "omega": [omega] * prob.L}
     lam = [prob.lambda_max(l) for l in range(prob.L)]
     if kind == "jacobi":
         return {"kind": "jacobi", "omega": [4.0 / (3.0 * x) for x in lam]}
@@ -165,11 +257,12 @@ def zero_load(prob: Problem) -> bool:
 
 
 def pcg(prob: Problem, tol: float = 1e-11, maxit: int = 20000, precond: str = "vcycle",
-        sm=None, nu: int = 2):
+        sm=None, nu: int = 2, kind: str = "V"):
     """Zero-initial-guess PCG on the pinned fine system, all load cases at once.
 
     Pinned system: rows/columns of the gauge node's DOFs replaced by identity,
-    RHS zeroed there.  Stops when every case's true relative residual
+    RHS zeroed there.  ``kind`` selects the cycle of the preconditioner (V or
+    W: both symmetric).  Stops when every case's true relative residual
     ||f - K u|| / ||f|| (unpinned K, full f) is <= tol.  Returns (u, iters).
     """
     d = prob.d
@@ -187,7 +280,9 @@ def pcg(prob: Problem, tol: float = 1e-11, maxit: int = 20000, precond: str = "v
     def M(r):
         if precond == "jacobi":
             return mask * Dinv * r
-        return mask * vcycle(prob, mask * r, np.zeros_like(r), sm, nu, nu)
+        if kind == "V":
+            return mask * vcycle(prob, mask * r, np.zeros_like(r), sm, nu, nu)
+        return mask * cycle(prob, mask * r, np.zeros_like(r), sm, nu, nu, kind=kind)
 
     u = np.zeros_like(f)
     if zero_load(prob):
