@@ -55,7 +55,19 @@ typedef enum {
 
 typedef enum { GMT_ELASTIC = 0, GMT_THERMAL = 1 } gmt_physics;
 typedef enum { GMT_F64 = 0, GMT_F32 = 1 } gmt_dtype;
-typedef enum { GMT_SMOOTH_CHEBYSHEV = 0, GMT_SMOOTH_JACOBI = 1 } gmt_smoother;
+/* Smoothers: Chebyshev iteration for D^-1 K, weighted Jacobi, and the
+ * 8-colour Gauss-Seidel / SOR smoother of Sec. 4.6 (parallel smoothing): nodes
+ * coloured by the parities of their coordinates, the colours updated in turn
+ * with u_i += omega D_i^-1 r_i (D = diag K); the pre-smoother runs the colours
+ * 0..7, the post-smoother 7..0 (its adjoint), so the cycle stays symmetric. */
+typedef enum { GMT_SMOOTH_CHEBYSHEV = 0, GMT_SMOOTH_JACOBI = 1, GMT_SMOOTH_GS = 2 } gmt_smoother;
+
+/* Multigrid schedules (Sec. 6.3, schedule study): per visit of a level, its
+ * coarse correction problem gets one visit of the next level (V), two visits
+ * in a row (W), or an F-visit followed by a V-visit (F).  The exact coarsest
+ * solve is never repeated.  Injected corrections (Alg. 2) start a level at its
+ * first entry in the cycle only. */
+typedef enum { GMT_CYCLE_V = 0, GMT_CYCLE_W = 1, GMT_CYCLE_F = 2 } gmt_schedule;
 
 typedef struct gmt_hier* gmt_hier_t;
 
@@ -90,17 +102,21 @@ typedef struct {
   int32_t sweep_xcd[2];
 } gmt_level_desc;
 
-/* Smoothing of one V-cycle.  For every level l (1..L-1) the smoother is either
- * weighted Jacobi u += omega D^-1 (f - K u) (nu sweeps) or the degree-nu
- * Chebyshev iteration for D^-1 K on [lo, hi].  Host arrays of length L
- * indexed by level-1; NULL arrays take the defaults omega = 4/(3 lambda_max),
- * lo = lambda_max / 30, hi = 1.1 lambda_max. */
+/* Smoothing and schedule of one cycle.  For every level l (1..L-1) the
+ * smoother is weighted Jacobi u += omega D^-1 (f - K u) (nu sweeps), the
+ * degree-nu Chebyshev iteration for D^-1 K on [lo, hi], or nu 8-colour
+ * Gauss-Seidel / SOR sweeps with weight omega.  Host arrays of length L
+ * indexed by level-1; NULL arrays take the defaults omega = 4/(3 lambda_max)
+ * (Jacobi) or 1 (Gauss-Seidel; SOR weights must lie in (0, 2)),
+ * lo = lambda_max / 30, hi = 1.1 lambda_max.  Zero-initialised options give a
+ * V-cycle with degree-2 Chebyshev smoothing. */
 typedef struct {
   int32_t nu1, nu2;   /* pre / post smoothing degree; default 2 / 2 when both 0 */
   int32_t smoother;   /* gmt_smoother */
   const double* omega;
   const double* lo;
   const double* hi;
+  int32_t schedule;   /* gmt_schedule */
 } gmt_cycle_opts;
 
 typedef struct {
@@ -133,7 +149,11 @@ typedef struct {
  * stencils), plus the Galerkin operators of Sec. 4.6, the Jacobi diagonal, a
  * lambda_max estimate per level and the factor of the pinned coarsest matrix.
  * d_voxels: N^3 uint8 on the device.  Fails with GMT_E_INVAL for an empty
- * cell or bad N / levels, GMT_E_SINGULAR if the coarsest factorisation fails. */
+ * cell or bad N / levels, and for a cell whose solid voxels form more than one
+ * node-connected component (periodic; voxels sharing a node are connected):
+ * each component could translate on its own and one pinned node fixes only
+ * one of them (the message names the count).  GMT_E_SINGULAR if the coarsest
+ * factorisation fails. */
 gmt_status gmt_build_hierarchy(const uint8_t* d_voxels, int32_t N, const gmt_params* params,
                                void* stream, gmt_hier_t* out);
 
@@ -170,8 +190,10 @@ gmt_status gmt_apply_K(gmt_hier_t h, int32_t level, const void* d_u, void* d_y, 
 gmt_status gmt_residual(gmt_hier_t h, int32_t level, const void* d_f, const void* d_u, void* d_r,
                         int32_t dtype, void* stream);
 
-/* nu smoothing steps on level l in place on d_u (weighted Jacobi with omega = p1,
- * or Chebyshev on [lo, hi] = [p1, p2]); the pre- and post-smoother of Alg. 1. */
+/* nu smoothing steps on level l < L in place on d_u (weighted Jacobi with
+ * omega = p1; Chebyshev on [lo, hi] = [p1, p2]; Gauss-Seidel / SOR with
+ * omega = p1, colours 0..7 when p2 = 0 (pre-smoother) or 7..0 when p2 = 1
+ * (post-smoother)); the pre- and post-smoother of Alg. 1. */
 gmt_status gmt_smooth(gmt_hier_t h, int32_t level, const void* d_f, void* d_u, int32_t nu,
                       int32_t smoother, double p1, double p2, int32_t dtype, void* stream);
 
@@ -187,7 +209,8 @@ gmt_status gmt_prolong_add(gmt_hier_t h, int32_t level, const void* d_uc, void* 
  * ignored, u = K_L,pinned^-1 f (replaces the coarsest GS of Alg. 1/2). */
 gmt_status gmt_coarse_solve(gmt_hier_t h, const void* d_f, void* d_u, int32_t dtype, void* stream);
 
-/* One V-cycle (Alg. 2) in place on d_u (level-1 vector, its initial guess u^1).
+/* One cycle (Alg. 2; V, W or F by opts->schedule) in place on d_u (level-1
+ * vector, its initial guess u^1).
  * d_e_init: NULL, or an array of L pointers indexed by level-1 whose entries
  * 2..L-1 (indices 1..L-2) may be NULL or point to injected corrections
  * e^l[n_n^l][c][d] (the coarse-level injection of Alg. 2); entry L is unused (exact
@@ -196,11 +219,15 @@ gmt_status gmt_vcycle(gmt_hier_t h, const void* d_f, void* d_u, const void* cons
                       const gmt_cycle_opts* opts, int32_t dtype, void* stream);
 
 /* Solve K u = f to opts->tol (relative residual, Sec. 5.2, evaluated in FP64)
- * by conjugate gradients preconditioned with one V-cycle per iteration,
+ * by conjugate gradients preconditioned with one cycle per iteration
+ * (opts->cycle: V or W, both symmetric; F is rejected with GMT_E_INVAL),
  * starting from the guess in d_u (zeros = the plain solver).  d_f and d_u are
  * FP64 level-1 vectors; on return d_u holds the solution in the gauge
- * u(node 0) = 0.  Returns GMT_E_NOCONV (with the report filled) when the
- * budget is spent.  Synchronizes the stream. */
+ * u(node 0) = 0.  A guess whose residual is not finite, or larger than the
+ * load itself (worse than the zero guess), is replaced by zero before the
+ * first iteration (rel_res_init still reports it).  Returns GMT_E_NOCONV
+ * (with the report filled) when the budget is spent.  Synchronizes the
+ * stream. */
 gmt_status gmt_solve(gmt_hier_t h, const void* d_f, void* d_u, const gmt_solve_opts* opts,
                      gmt_solve_report* report, void* stream);
 
@@ -288,7 +315,8 @@ gmt_status gmt_nn_adamw(float* d_params, const float* d_grad, float* d_m, float*
 gmt_status gmt_nn_norm2(const float* d_x, size_t n, double* h_out, void* stream);
 gmt_status gmt_nn_ema(float* d_ema, const float* d_x, size_t n, double decay, void* stream);
 
-/* One V-cycle of Alg. 2 started from network outputs, in FP32, and the
+/* One V-cycle of Alg. 2 (Chebyshev or Jacobi smoothing; other smoothers and
+ * schedules are rejected with GMT_E_INVAL) started from network outputs, in FP32, and the
  * physics loss of Sec. 4.5:  L = log10(||f - K u^1||_2 + 1e-12)
  * + lambda * sum_{case,dof} (sum_i u^1_i)^2  (norm over all cases and DOFs).
  * d_pred: L pointers by level-1 (entry 0 = u_hat^1 [n_1][c][d], required;

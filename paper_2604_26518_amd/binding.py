@@ -21,7 +21,10 @@ LIB_PATH = os.path.join(_HERE, "libgmt.so")
 GMT_OK, GMT_E_INVAL, GMT_E_NOMEM, GMT_E_HIP, GMT_E_NOCONV, GMT_E_SINGULAR, GMT_E_STATE = range(7)
 GMT_ELASTIC, GMT_THERMAL = 0, 1
 GMT_F64, GMT_F32 = 0, 1
-GMT_SMOOTH_CHEBYSHEV, GMT_SMOOTH_JACOBI = 0, 1
+GMT_SMOOTH_CHEBYSHEV, GMT_SMOOTH_JACOBI, GMT_SMOOTH_GS = 0, 1, 2
+GMT_CYCLE_V, GMT_CYCLE_W, GMT_CYCLE_F = 0, 1, 2
+_SMOOTHERS = {"chebyshev": GMT_SMOOTH_CHEBYSHEV, "jacobi": GMT_SMOOTH_JACOBI, "gs": GMT_SMOOTH_GS}
+_SCHEDULES = {"V": GMT_CYCLE_V, "W": GMT_CYCLE_W, "F": GMT_CYCLE_F}
 
 _STATUS = {1: "GMT_E_INVAL", 2: "GMT_E_NOMEM", 3: "GMT_E_HIP", 4: "GMT_E_NOCONV",
            5: "GMT_E_SINGULAR", 6: "GMT_E_STATE"}
@@ -46,7 +49,7 @@ class GmtLevelDesc(ct.Structure):
 class GmtCycleOpts(ct.Structure):
     _fields_ = [("nu1", ct.c_int32), ("nu2", ct.c_int32), ("smoother", ct.c_int32),
                 ("omega", ct.POINTER(ct.c_double)), ("lo", ct.POINTER(ct.c_double)),
-                ("hi", ct.POINTER(ct.c_double))]
+                ("hi", ct.POINTER(ct.c_double)), ("schedule", ct.c_int32)]
 
 
 class GmtSolveOpts(ct.Structure):
@@ -316,11 +319,12 @@ class Hierarchy:
 
     def smooth(self, f, u, nu: int, smoother: str = "chebyshev", p1: float = 0.0, p2: float = 0.0,
                level: int = 1):
-        """nu smoothing steps in place on u: Jacobi (omega = p1) or Chebyshev on [p1, p2]."""
+        """nu smoothing steps in place on u: Jacobi (omega = p1), Chebyshev on [p1, p2], or
+        8-colour Gauss-Seidel / SOR (omega = p1; colours 0..7 for p2 = 0, 7..0 for p2 = 1)."""
         self._level(level)
         self._v(u, level, name="u")
         self._v(f, level, u.dtype, "f")
-        sm = GMT_SMOOTH_JACOBI if smoother == "jacobi" else GMT_SMOOTH_CHEBYSHEV
+        sm = _SMOOTHERS[smoother]
         _check(lib().gmt_smooth(self._h, level, _ptr(f), _ptr(u), nu, sm, p1, p2, _DT[u.dtype], _stream()))
         return u
 
@@ -348,10 +352,11 @@ class Hierarchy:
         _check(lib().gmt_coarse_solve(self._h, _ptr(f), _ptr(u), _DT[f.dtype], _stream()))
         return u
 
-    def _cycle(self, nu1=2, nu2=2, smoother="chebyshev", omega=None, lo=None, hi=None):
+    def _cycle(self, nu1=2, nu2=2, smoother="chebyshev", omega=None, lo=None, hi=None, schedule="V"):
         o = GmtCycleOpts()
         o.nu1, o.nu2 = nu1, nu2
-        o.smoother = GMT_SMOOTH_JACOBI if smoother == "jacobi" else GMT_SMOOTH_CHEBYSHEV
+        o.smoother = _SMOOTHERS[smoother]
+        o.schedule = _SCHEDULES[schedule]
         keep = []
         for name, vals in (("omega", omega), ("lo", lo), ("hi", hi)):
             if vals is not None:
@@ -362,11 +367,13 @@ class Hierarchy:
                 keep.append(arr)
         return o, keep
 
-    def vcycle(self, f, u, e_init=None, nu1=2, nu2=2, smoother="chebyshev", omega=None, lo=None, hi=None):
-        """One V-cycle (Alg. 2) in place on u; e_init: list indexed by level-1 of corrections or None."""
+    def vcycle(self, f, u, e_init=None, nu1=2, nu2=2, smoother="chebyshev", omega=None, lo=None, hi=None,
+               schedule="V"):
+        """One cycle (Alg. 2; schedule V, W or F) in place on u; e_init: list indexed by level-1 of
+        corrections or None."""
         self._v(u, 1, name="u")
         self._v(f, 1, u.dtype, "f")
-        o, keep = self._cycle(nu1, nu2, smoother, omega, lo, hi)
+        o, keep = self._cycle(nu1, nu2, smoother, omega, lo, hi, schedule)
         arr = None
         if e_init is not None:
             if len(e_init) != self.L:
@@ -383,24 +390,24 @@ class Hierarchy:
         return u
 
     def solve_opts(self, tol=1e-5, max_iter=500, precision="f64", max_outer=8, check_every=1, nu1=2, nu2=2,
-                   smoother="chebyshev", omega=None, lo=None, hi=None, graph=True):
+                   smoother="chebyshev", omega=None, lo=None, hi=None, graph=True, schedule="V"):
         """(gmt_solve_opts, buffers to keep alive during the call)."""
         o = GmtSolveOpts()
         o.tol, o.max_iter, o.max_outer, o.check_every = tol, max_iter, max_outer, check_every
         o.precision = GMT_F64 if precision == "f64" else GMT_F32
-        o.cycle, keep = self._cycle(nu1, nu2, smoother, omega, lo, hi)
+        o.cycle, keep = self._cycle(nu1, nu2, smoother, omega, lo, hi, schedule)
         o.graph = 1 if graph else 0
         return o, keep
 
     def solve(self, f, u=None, tol=1e-5, max_iter=500, precision="f64", max_outer=8, check_every=1,
               nu1=2, nu2=2, smoother="chebyshev", omega=None, lo=None, hi=None, raise_on_noconv=True,
-              graph=True):
+              graph=True, schedule="V"):
         self._v(f, 1, torch.float64, "f")
         if u is None:
             u = torch.zeros_like(f)
         self._v(u, 1, torch.float64, "u")
         o, keep = self.solve_opts(tol, max_iter, precision, max_outer, check_every, nu1, nu2, smoother, omega, lo,
-                                  hi, graph)
+                                  hi, graph, schedule)
         rep = GmtSolveReport()
         st = lib().gmt_solve(self._h, _ptr(f), _ptr(u), ct.byref(o), ct.byref(rep), _stream())
         report = _report(rep, self.c, st)

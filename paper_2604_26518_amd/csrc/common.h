@@ -119,7 +119,21 @@ struct LevelView {
   // workgroup size (64 or 256), cases per thread (1, or all c) -- levels >= 2
   // only -- and XCD-contiguous numbering
   int bs, xcd, cb;
+  // levels >= 2: when `list` is set, the sweep covers only the n_list nodes
+  // list[0 .. n_list) (one colour class of the Gauss-Seidel smoother)
+  const int* list;
+  int n_list;
 };
+
+// node-connected components of the active elements of level 1 (periodic;
+// elements sharing a node are connected); parent: n_e ints of scratch
+int count_components(const int* elem_lin, int n_e, const int* elem_map, int N, int* parent, int* d_count,
+                     hipStream_t s);
+// u[c][i][:] += omega D^-1 r[c][i][:] for the n_list nodes i of `list` (one
+// colour of the Gauss-Seidel smoother)
+template <typename T>
+void launch_gs_update(const int* list, int n_list, int n, int D, int C, const T* dinv, const T* r, T* u, T omega,
+                      hipStream_t s);
 
 // Epilogue of a node-centric operator sweep.
 // EPI_CHEB0 is the first Chebyshev step (d = rho2 D^-1 r, the previous d is not read).
@@ -246,6 +260,17 @@ struct LevelData {
   double* dinv64 = nullptr;
   float* dinv32 = nullptr;
   double lam = 0.0;           // lambda_max(D^-1 K) estimate
+  // node ids sorted by colour (x mod 2 + 2 (y mod 2) + 4 (z mod 2)), with the
+  // start of every colour in col_off; level 1 also keeps the interior and
+  // boundary lists split by colour and the boundary neighbour table in the
+  // order of col_bnd (built on the first Gauss-Seidel use)
+  int* col_nodes = nullptr;
+  int col_off[9] = {0};
+  int* col_int = nullptr;
+  int col_int_off[9] = {0};
+  int* col_bnd = nullptr;
+  int col_bnd_off[9] = {0};
+  int* col_bnd_nbrs = nullptr;
   int bs32 = 256, xcd32 = 1, cb32 = 0;  // launch shape of the FP32 / FP64 sweeps (autotuned;
   int bs64 = 256, xcd64 = 1, cb64 = 0;  // cb 0 = all cases per thread)
   bool tuned32 = false, tuned64 = false;
@@ -291,6 +316,7 @@ struct Hier {
   Work<double> w64;
   // FP64 / FP32 level-1 scratch vectors of the solve and query entry points
   double *s_r64 = nullptr, *s_t64 = nullptr, *s_x64 = nullptr, *s_f64s = nullptr, *s_u64s = nullptr;
+  double* s_usave = nullptr;  // the iterate before an FP32 refinement step (exact undo)
   float *s_b32 = nullptr, *s_x32 = nullptr;
   std::vector<void*> owned;      // from the caller's allocation callback
   std::vector<void*> owned_hip;  // from hipMalloc (no callback, or local_alloc)
@@ -335,6 +361,9 @@ void nn_backward(Hier& h, const float* const* gout, float* grad, hipStream_t s);
 void nn_adamw(float* p, const float* g, float* m, float* v, size_t n, double lr, double b1, double b2, double eps,
               double wd, int step, double gscale, hipStream_t s);
 double nn_norm2(Hier* h, const float* x, size_t n, hipStream_t s);
+// the same norm with partial sums in a fixed device array (no allocation)
+double nn_norm2_noalloc(const float* x, size_t n, hipStream_t s);
+size_t nn_norm2_noalloc_max();
 int nn_activation(Hier& h, int l, int which, float* out, hipStream_t s);
 void nn_ema(float* e, const float* x, size_t n, double decay, hipStream_t s);
 // column sums over nodes of a [C][n][D] vector -> sums[Q] (FP64)

@@ -513,7 +513,7 @@ static const T* dinv_of(const Hier& h, int l) {
 
 template <typename T>
 static void apply(Hier& h, int l, int epi, const T* u, const T* f, T* out, int C, hipStream_t s,
-                  T omega = 0, T rho1 = 0, T rho2 = 0, T* dvec = nullptr) {
+                  T omega = 0, T rho1 = 0, T rho2 = 0, T* dvec = nullptr, const LevelView<T>* view = nullptr) {
   EpiArgs<T> e{};
   e.f = f;
   e.dinv = dinv_of<T>(h, l);
@@ -522,13 +522,95 @@ static void apply(Hier& h, int l, int epi, const T* u, const T* f, T* out, int C
   e.omega = omega;
   e.rho1 = rho1;
   e.rho2 = rho2;
-  launch_apply<T>(h.view<T>(l), h.lv[l].kind, h.D, C, epi, u, e, s);
+  launch_apply<T>(view ? *view : h.view<T>(l), h.lv[l].kind, h.D, C, epi, u, e, s);
 }
 
 struct CycleCfg {
-  int nu1 = 2, nu2 = 2, smoother = GMT_SMOOTH_CHEBYSHEV;
+  int nu1 = 2, nu2 = 2, smoother = GMT_SMOOTH_CHEBYSHEV, schedule = GMT_CYCLE_V;
   std::vector<double> omega, lo, hi;
 };
+
+// ------------------------------------------------------------ colour classes (Gauss-Seidel)
+// Node ids of every level split by colour x mod 2 + 2 (y mod 2) + 4 (z mod 2)
+// (stable: ascending id inside a colour); level 1 splits its interior and
+// boundary lists the same way and rebuilds the boundary neighbour table in the
+// order of the split list.  Built once per hierarchy, on the calling thread.
+static void split_by_colour(const std::vector<int>& ids, const std::vector<int>& lin, int N, std::vector<int>& out,
+                            int off[9]) {
+  int cnt[8] = {0};
+  auto colour = [&](int i) {
+    const int v = lin[i];
+    return (v % N) % 2 + 2 * (((v / N) % N) % 2) + 4 * ((v / (N * N)) % 2);
+  };
+  for (int i : ids) ++cnt[colour(i)];
+  off[0] = 0;
+  for (int c = 0; c < 8; ++c) off[c + 1] = off[c] + cnt[c];
+  out.assign(ids.size(), 0);
+  int pos[8];
+  for (int c = 0; c < 8; ++c) pos[c] = off[c];
+  for (int i : ids) out[pos[colour(i)]++] = i;
+}
+
+static void ensure_colours(Hier& h, hipStream_t s) {
+  for (int l = 0; l + 1 < h.L; ++l) {
+    LevelData& d = h.lv[l];
+    if (d.col_nodes) continue;
+    std::vector<int> lin(d.n_n), ids(d.n_n), out;
+    GMT_HIP(hipMemcpyAsync(lin.data(), d.node_lin, d.n_n * sizeof(int), hipMemcpyDeviceToHost, s));
+    GMT_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < d.n_n; ++i) ids[i] = i;
+    split_by_colour(ids, lin, d.N, out, d.col_off);
+    d.col_nodes = h.alloc<int>(d.n_n);
+    GMT_HIP(hipMemcpyAsync(d.col_nodes, out.data(), d.n_n * sizeof(int), hipMemcpyHostToDevice, s));
+    GMT_HIP(hipStreamSynchronize(s));
+    if (l > 0) continue;
+    for (int part = 0; part < 2; ++part) {
+      const int cnt = part == 0 ? d.n_int : d.n_bnd;
+      const int* src = part == 0 ? d.interior : d.boundary;
+      int* off = part == 0 ? d.col_int_off : d.col_bnd_off;
+      for (int c = 0; c < 9; ++c) off[c] = 0;
+      if (cnt == 0) continue;
+      ids.resize(cnt);
+      GMT_HIP(hipMemcpyAsync(ids.data(), src, cnt * sizeof(int), hipMemcpyDeviceToHost, s));
+      GMT_HIP(hipStreamSynchronize(s));
+      split_by_colour(ids, lin, d.N, out, off);
+      int* dst = h.alloc<int>(cnt);
+      GMT_HIP(hipMemcpyAsync(dst, out.data(), cnt * sizeof(int), hipMemcpyHostToDevice, s));
+      GMT_HIP(hipStreamSynchronize(s));
+      if (part == 0) {
+        d.col_int = dst;
+      } else {
+        d.col_bnd = dst;
+        d.col_bnd_nbrs = h.alloc<int>((size_t)cnt * kBndStride);
+        if (reinterpret_cast<uintptr_t>(d.col_bnd_nbrs) % 16 != 0)
+          fail(GMT_E_STATE, "boundary neighbour table is not 16-byte aligned");
+        launch_boundary_nbrs(d.col_bnd, cnt, d.node_lin, d.node_map, d.N, d.col_bnd_nbrs, s);
+        GMT_HIP(hipStreamSynchronize(s));
+      }
+    }
+  }
+}
+
+// The operator sweep of level l restricted to the nodes of colour c.
+template <typename T>
+static LevelView<T> colour_view(const Hier& h, int l, int c) {
+  const LevelData& d = h.lv[l];
+  LevelView<T> v = h.view<T>(l);
+  if (l == 0) {
+    v.interior = d.col_int ? d.col_int + d.col_int_off[c] : nullptr;
+    v.n_int = d.col_int_off[c + 1] - d.col_int_off[c];
+    v.boundary = d.col_bnd ? d.col_bnd + d.col_bnd_off[c] : nullptr;
+    v.n_bnd = d.col_bnd_off[c + 1] - d.col_bnd_off[c];
+    v.bnd_nbrs = d.col_bnd_nbrs ? d.col_bnd_nbrs + (size_t)d.col_bnd_off[c] * kBndStride : nullptr;
+    v.n_runs = 0;
+    v.runs = nullptr;
+    if (v.cb < 5 || v.cb > 7) v.cb = 7;  // the list-driven variants
+  } else {
+    v.list = d.col_nodes + d.col_off[c];
+    v.n_list = d.col_off[c + 1] - d.col_off[c];
+  }
+  return v;
+}
 
 static CycleCfg make_cycle(const Hier& h, const gmt_cycle_opts* o) {
   CycleCfg c;
@@ -537,12 +619,19 @@ static CycleCfg make_cycle(const Hier& h, const gmt_cycle_opts* o) {
     c.nu2 = o->nu2;
     if (c.nu1 == 0 && c.nu2 == 0) c.nu1 = c.nu2 = 2;
     c.smoother = o->smoother;
+    c.schedule = o->schedule;
   }
   if (c.nu1 < 0 || c.nu2 < 0 || c.nu1 > 64 || c.nu2 > 64) fail(GMT_E_INVAL, "smoothing degree out of range");
-  if (c.smoother != GMT_SMOOTH_CHEBYSHEV && c.smoother != GMT_SMOOTH_JACOBI) fail(GMT_E_INVAL, "bad smoother");
+  if (c.smoother != GMT_SMOOTH_CHEBYSHEV && c.smoother != GMT_SMOOTH_JACOBI && c.smoother != GMT_SMOOTH_GS)
+    fail(GMT_E_INVAL, "bad smoother");
+  if (c.schedule != GMT_CYCLE_V && c.schedule != GMT_CYCLE_W && c.schedule != GMT_CYCLE_F)
+    fail(GMT_E_INVAL, "bad cycle schedule");
   for (int l = 0; l < h.L; ++l) {
     const double lam = h.lv[l].lam;
-    c.omega.push_back(o && o->omega ? o->omega[l] : 4.0 / (3.0 * lam));
+    const double w0 = c.smoother == GMT_SMOOTH_GS ? 1.0 : 4.0 / (3.0 * lam);
+    c.omega.push_back(o && o->omega ? o->omega[l] : w0);
+    if (c.smoother == GMT_SMOOTH_GS && !(c.omega[l] > 0 && c.omega[l] < 2))
+      fail(GMT_E_INVAL, "Gauss-Seidel / SOR weight of level %d outside (0, 2)", l + 1);
     c.lo.push_back(o && o->lo ? o->lo[l] : lam / 30.0);
     c.hi.push_back(o && o->hi ? o->hi[l] : 1.1 * lam);
     if (c.smoother == GMT_SMOOTH_CHEBYSHEV && !(c.hi[l] > c.lo[l] && c.lo[l] > 0))
@@ -552,15 +641,34 @@ static CycleCfg make_cycle(const Hier& h, const gmt_cycle_opts* o) {
 }
 
 // nu smoothing steps on level l; u / ualt are swapped so that u holds the result.
+// Gauss-Seidel (p1 = omega) runs the colours 0..7, or 7..0 when `post` (the
+// adjoint order, for the post-smoother), each colour as the residual at its
+// nodes followed by the in-place update there.
 template <typename T>
 static void smooth(Hier& h, int l, const T* f, T*& u, T*& ualt, T* dvec, int nu, bool zero_start,
-                   int smoother, double p1, double p2, hipStream_t s) {
+                   int smoother, double p1, double p2, hipStream_t s, bool post = false) {
   const int n = h.lv[l].n_n;
   if (nu <= 0) {
     if (zero_start) launch_fill<T>(u, (size_t)n * h.Q, T(0), s);
     return;
   }
   const T* dinv = dinv_of<T>(h, l);
+  if (smoother == GMT_SMOOTH_GS) {
+    const LevelData& d = h.lv[l];
+    if (!d.col_nodes) fail(GMT_E_STATE, "colour classes of level %d are not built", l + 1);
+    if (zero_start) launch_fill<T>(u, (size_t)n * h.Q, T(0), s);
+    T* r = h.work<T>().r[l];
+    for (int it = 0; it < nu; ++it)
+      for (int k = 0; k < 8; ++k) {
+        const int c = post ? 7 - k : k;
+        const int cnt = d.col_off[c + 1] - d.col_off[c];
+        if (cnt == 0) continue;
+        const LevelView<T> v = colour_view<T>(h, l, c);
+        apply<T>(h, l, EPI_RESID, u, f, r, h.C, s, T(0), T(0), T(0), nullptr, &v);
+        launch_gs_update<T>(d.col_nodes + d.col_off[c], cnt, n, h.D, h.C, dinv, r, u, (T)p1, s);
+      }
+    return;
+  }
   if (smoother == GMT_SMOOTH_JACOBI) {
     const T omega = (T)p1;
     for (int it = 0; it < nu; ++it) {
@@ -598,39 +706,78 @@ static const T* cinv_of(const Hier& h) {
     return h.cinv32;
 }
 
-// One V-cycle (Alg. 2) in precision T on caller buffers f0 / u0 of level l0
-// (the finest level for the solver; l0 > 0 runs the sub-cycle of the coarser
-// levels, used by the adjoint of the learned path).
+// Iterates and right-hand sides of the levels during one cycle.
+template <typename T>
+struct CycleState {
+  std::vector<T*> cur, alt;
+  std::vector<const T*> f;
+  std::vector<char> entered;
+  const T* const* e_init;
+};
+
+// One visit of level l (Alg. 1 / Alg. 2 recursion): pre-smoothing, residual,
+// restriction, the coarse correction problem treated by the schedule (one
+// visit of level l+1 for V, two in a row for W, an F-visit then a V-visit for
+// F; the exact coarsest solve is never repeated: a second one changes
+// nothing), prolongation and post-smoothing.  Level l+1 starts from zero, or
+// from its injected correction e_hat^{l+1} at its first entry in the cycle.
+template <typename T>
+static void cycle_visit(Hier& h, int l, bool zero_start, int sched, CycleState<T>& st, const CycleCfg& cfg,
+                        hipStream_t s) {
+  Work<T>& W = h.work<T>();
+  const int L = h.L;
+  if (l == L - 1) {
+    launch_coarse_solve<T>(cinv_of<T>(h), h.cn, h.D, h.C, st.f[l], st.cur[l], s);
+    return;
+  }
+  const double p1 = cfg.smoother == GMT_SMOOTH_CHEBYSHEV ? cfg.lo[l] : cfg.omega[l];
+  const double p2 = cfg.hi[l];
+  smooth<T>(h, l, st.f[l], st.cur[l], st.alt[l], W.dvec[l], cfg.nu1, zero_start, cfg.smoother, p1, p2, s);
+  apply<T>(h, l, EPI_RESID, st.cur[l], st.f[l], W.r[l], h.C, s);
+  const int c = l + 1;
+  launch_restrict<T>(h.view<T>(l), h.view<T>(c), h.Q, h.D, W.r[l], W.f[c], s);
+  st.f[c] = W.f[c];
+  st.cur[c] = W.u[c];
+  st.alt[c] = W.ualt[c];
+  bool zs = true;
+  if (st.e_init && st.e_init[c] && c < L - 1 && !st.entered[c]) {
+    launch_copy<T>(st.e_init[c], st.cur[c], (size_t)h.lv[c].n_n * h.Q, s);
+    zs = false;
+  }
+  st.entered[c] = 1;
+  if (sched == GMT_CYCLE_V) {
+    cycle_visit<T>(h, c, zs, GMT_CYCLE_V, st, cfg, s);
+  } else if (sched == GMT_CYCLE_W) {
+    cycle_visit<T>(h, c, zs, GMT_CYCLE_W, st, cfg, s);
+    if (c < L - 1) cycle_visit<T>(h, c, false, GMT_CYCLE_W, st, cfg, s);
+  } else {
+    cycle_visit<T>(h, c, zs, GMT_CYCLE_F, st, cfg, s);
+    if (c < L - 1) cycle_visit<T>(h, c, false, GMT_CYCLE_V, st, cfg, s);
+  }
+  launch_prolong_add<T>(h.view<T>(l), h.view<T>(c), h.Q, h.D, st.cur[c], st.cur[l], s);
+  smooth<T>(h, l, st.f[l], st.cur[l], st.alt[l], W.dvec[l], cfg.nu2, false, cfg.smoother, p1, p2, s, true);
+}
+
+// One multigrid cycle (Alg. 2; the schedule of cfg) in precision T on caller
+// buffers f0 / u0 of level l0 (the finest level for the solver; l0 > 0 runs the
+// sub-cycle of the coarser levels, used by the adjoint of the learned path).
 template <typename T>
 static void vcycle(Hier& h, const T* f0, T* u0, bool u0_zero, const T* const* e_init, const CycleCfg& cfg,
                    hipStream_t s, int l0 = 0) {
   h.ensure_work<T>();
   Work<T>& W = h.work<T>();
   const int L = h.L;
-  std::vector<T*> cur(L), alt(L);
-  std::vector<const T*> fl(L);
-  cur[l0] = u0;
-  alt[l0] = W.ualt[l0];
-  fl[l0] = f0;
-  auto p1 = [&](int l) { return cfg.smoother == GMT_SMOOTH_JACOBI ? cfg.omega[l] : cfg.lo[l]; };
-  auto p2 = [&](int l) { return cfg.hi[l]; };
-  for (int l = l0; l < L - 1; ++l) {
-    const bool zs = l == l0 ? u0_zero : !(e_init && e_init[l]);
-    smooth<T>(h, l, fl[l], cur[l], alt[l], W.dvec[l], cfg.nu1, zs, cfg.smoother, p1(l), p2(l), s);
-    apply<T>(h, l, EPI_RESID, cur[l], fl[l], W.r[l], h.C, s);
-    launch_restrict<T>(h.view<T>(l), h.view<T>(l + 1), h.Q, h.D, W.r[l], W.f[l + 1], s);
-    fl[l + 1] = W.f[l + 1];
-    cur[l + 1] = W.u[l + 1];
-    alt[l + 1] = W.ualt[l + 1];
-    if (e_init && e_init[l + 1] && l + 1 < L - 1)
-      launch_copy<T>(e_init[l + 1], cur[l + 1], (size_t)h.lv[l + 1].n_n * h.Q, s);
-  }
-  launch_coarse_solve<T>(cinv_of<T>(h), h.cn, h.D, h.C, fl[L - 1], cur[L - 1], s);
-  for (int l = L - 2; l >= l0; --l) {
-    launch_prolong_add<T>(h.view<T>(l), h.view<T>(l + 1), h.Q, h.D, cur[l + 1], cur[l], s);
-    smooth<T>(h, l, fl[l], cur[l], alt[l], W.dvec[l], cfg.nu2, false, cfg.smoother, p1(l), p2(l), s);
-  }
-  if (cur[l0] != u0) launch_copy<T>(cur[l0], u0, (size_t)h.lv[l0].n_n * h.Q, s);
+  CycleState<T> st;
+  st.cur.assign(L, nullptr);
+  st.alt.assign(L, nullptr);
+  st.f.assign(L, nullptr);
+  st.entered.assign(L, 0);
+  st.e_init = e_init;
+  st.cur[l0] = u0;
+  st.alt[l0] = W.ualt[l0];
+  st.f[l0] = f0;
+  cycle_visit<T>(h, l0, u0_zero, cfg.schedule, st, cfg, s);
+  if (st.cur[l0] != u0) launch_copy<T>(st.cur[l0], u0, (size_t)h.lv[l0].n_n * h.Q, s);
 }
 
 // ------------------------------------------------------------ launch-shape autotuner
@@ -864,7 +1011,8 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
       launch_pcg_direction<T>(W.pp, W.pz, beta, n, Q, D, st);
     };
     Hier::PcgGraphs& G = MIXED ? h.gmx : graphs_of<T>(h);
-    std::vector<double> key = {(double)(uintptr_t)x, (double)cfg.nu1, (double)cfg.nu2, (double)cfg.smoother};
+    std::vector<double> key = {(double)(uintptr_t)x, (double)cfg.nu1, (double)cfg.nu2, (double)cfg.smoother,
+                               (double)cfg.schedule};
     for (int l = 0; l < h.L; ++l) key.insert(key.end(), {cfg.omega[l], cfg.lo[l], cfg.hi[l]});
     if (G.key != key) {
       for (auto& e : G.exec)
@@ -1041,6 +1189,17 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
     d.n_e = (int)ne;
     d.elem_lin = h.alloc<int>(ne);
     scan_compact(flags, nl3, d.elem_map, d.elem_lin, scr, d_total, s);
+    if (l == 0) {
+      // one rigid body: every solid voxel reachable through shared nodes (the
+      // flags buffer holds the union-find parents of the n_e elements)
+      const int ncomp = count_components(d.elem_lin, d.n_e, d.elem_map, d.N, flags, d_total, s);
+      timer.mark("components");
+      if (ncomp != 1)
+        fail(GMT_E_INVAL,
+             "the solid voxels form %d node-connected components; each could translate on its own and the "
+             "solver pins one node: reduce the cell to one component",
+             ncomp);
+    }
     launch_node_flags(d.elem_map, d.N, flags, s);
     const int64_t nn = scan_compact(flags, nl3, nullptr, nullptr, scr, d_total, s);
     d.n_n = (int)nn;
@@ -1341,6 +1500,8 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
   if (const char* e = std::getenv("GMT_MAX_INNER32"))
     if (*e && std::atoi(e) > 0) max_inner32 = std::min(kMaxInner32, std::atoi(e));
   const CycleCfg cfg = make_cycle(h, o ? &o->cycle : nullptr);
+  if (cfg.schedule == GMT_CYCLE_F)
+    fail(GMT_E_INVAL, "the F-cycle is not symmetric: it cannot precondition conjugate gradients");
   double* r64 = scratch64(h, &h.s_r64);
   // (in mixed precision the few FP64 residual sweeps keep the default shape)
   if (prec == GMT_F32)
@@ -1371,6 +1532,17 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
       R.rel_res[c] = rel[c];
       if (outer == 0) R.rel_res_init[c] = rel[c];
     }
+    if (outer == 0 && !(worst <= 1.0)) {
+      // the initial guess is not finite or is farther from the solution than
+      // zero (the zero guess has residual ||f||): start from zero instead
+      launch_fill<double>(u, tot, 0.0, s);
+      rel_residual64(h, f, u, r64, rel, den, s);
+      worst = 0;
+      for (int c = 0; c < C; ++c) {
+        worst = std::isfinite(rel[c]) ? std::max(worst, rel[c]) : INFINITY;
+        R.rel_res[c] = rel[c];
+      }
+    }
     R.outer = outer + 1;
     if (worst <= tol) {
       R.converged = 1;
@@ -1383,8 +1555,9 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
     if (last_f32 && !(worst < 0.5 * prev_worst)) {
       // the FP32 inner solve did not halve the FP64 residual (an ill-conditioned
       // cell where the FP32 recurrence stalls or diverges): undo that update and
-      // finish with the FP64 recurrence (FP32 V-cycle)
-      launch_accumulate<float>(u, h.s_x32, tot, s, -1.0);
+      // finish with the FP64 recurrence (FP32 V-cycle); the iterate before the
+      // step was kept, so the undo is exact
+      launch_copy<double>(h.s_usave, u, tot, s);
       inner_prec = kInnerMixed;
       last_f32 = false;
       rel_residual64(h, f, u, r64, rel, den, s);
@@ -1413,6 +1586,7 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
       bool reached = false;
       its += pcg<float>(h, h.s_b32, h.s_x32, itol, std::min(max_iter - its, max_inner32), check, graph, cfg, s,
                         &reached);
+      launch_copy<double>(u, scratch64(h, &h.s_usave), tot, s);
       launch_accumulate<float>(u, h.s_x32, tot, s, 1.0);
       last_f32 = true;
       // an FP32 inner solve that stalled, or ran into kMaxInner32, short of its
@@ -1699,7 +1873,7 @@ static void smooth_abi(Hier& h, int l, const void* d_f, void* d_u, int nu, int s
   const T* f = stage_in<T>(h, l, d_f, W.io1[l], s);
   T* u = stage_in<T>(h, l, d_u, W.io2[l], s);
   T* alt = W.io3[l];
-  smooth<T>(h, l, f, u, alt, W.dvec[l], nu, false, sm, p1, p2, s);
+  smooth<T>(h, l, f, u, alt, W.dvec[l], nu, false, sm, p1, p2, s, sm == GMT_SMOOTH_GS && p2 != 0.0);
   stage_out<T>(h, l, u, d_u, s);
 }
 
@@ -1711,7 +1885,14 @@ gmt_status gmt_smooth(gmt_hier_t H, int32_t level, const void* d_f, void* d_u, i
     if (!d_f || !d_u) fail(GMT_E_INVAL, "null vector");
     if (nu < 0 || nu > 64) fail(GMT_E_INVAL, "nu out of range");
     if (smoother == GMT_SMOOTH_CHEBYSHEV && !(p2 > p1 && p1 > 0)) fail(GMT_E_INVAL, "need 0 < lo < hi");
-    if (smoother != GMT_SMOOTH_CHEBYSHEV && smoother != GMT_SMOOTH_JACOBI) fail(GMT_E_INVAL, "bad smoother");
+    if (smoother != GMT_SMOOTH_CHEBYSHEV && smoother != GMT_SMOOTH_JACOBI && smoother != GMT_SMOOTH_GS)
+      fail(GMT_E_INVAL, "bad smoother");
+    if (smoother == GMT_SMOOTH_GS) {
+      if (!(p1 > 0 && p1 < 2)) fail(GMT_E_INVAL, "Gauss-Seidel / SOR weight outside (0, 2)");
+      if (p2 != 0.0 && p2 != 1.0) fail(GMT_E_INVAL, "Gauss-Seidel direction p2 must be 0 or 1");
+      if (level == H->h.L) fail(GMT_E_INVAL, "the coarsest level is not smoothed");
+      ensure_colours(H->h, S(stream));
+    }
     if (dtype == GMT_F64)
       smooth_abi<double>(H->h, level - 1, d_f, d_u, nu, smoother, p1, p2, S(stream));
     else
@@ -1817,6 +1998,7 @@ gmt_status gmt_vcycle(gmt_hier_t H, const void* d_f, void* d_u, const void* cons
     if (!d_f || !d_u || d_f == d_u) fail(GMT_E_INVAL, "null or aliased vector");
     Hier& h = H->h;
     const CycleCfg cfg = make_cycle(h, opts);
+    if (cfg.smoother == GMT_SMOOTH_GS) ensure_colours(h, S(stream));
     if (dtype == GMT_F64)
       vcycle_abi<double>(h, d_f, d_u, d_e_init, cfg, S(stream));
     else
@@ -1833,6 +2015,7 @@ gmt_status gmt_solve(gmt_hier_t H, const void* d_f, void* d_u, const gmt_solve_o
     Hier& h = H->h;
     hipStream_t s = S(stream);
     const int n = h.lv[0].n_n;
+    if (opts && opts->cycle.smoother == GMT_SMOOTH_GS) ensure_colours(h, s);
     double* f = scratch64(h, &h.s_f64s);
     double* u = scratch64(h, &h.s_u64s);
     launch_aos_to_soa<double, double>((const double*)d_f, f, n, h.C, h.D, s);
@@ -1846,14 +2029,16 @@ gmt_status gmt_solve(gmt_hier_t H, const void* d_f, void* d_u, const gmt_solve_o
 
 // Every buffer solve() may allocate, allocated up front (batched workers never
 // allocate: the allocation callback may not be callable from their threads).
-static void prepare_solve(Hier& h, int prec, hipStream_t s) {
+static void prepare_solve(Hier& h, int prec, const gmt_solve_opts* o, hipStream_t s) {
   const size_t tot = (size_t)h.lv[0].n_n * h.Q;
+  if (o && o->cycle.smoother == GMT_SMOOTH_GS) ensure_colours(h, s);
   scratch64(h, &h.s_f64s);
   scratch64(h, &h.s_u64s);
   scratch64(h, &h.s_r64);
   if (prec == GMT_F32) {
     if (!h.s_b32) h.s_b32 = h.alloc<float>(tot);
     if (!h.s_x32) h.s_x32 = h.alloc<float>(tot);
+    scratch64(h, &h.s_usave);
     autotune<float>(h, s);
   } else {
     scratch64(h, &h.s_x64);
@@ -1877,7 +2062,7 @@ gmt_status gmt_solve_batch(gmt_hier_t const* hs, int32_t n, const void* const* d
         if (hs[j] == hs[i]) fail(GMT_E_INVAL, "cell %d repeats the hierarchy of cell %d", i, j);
     }
     GMT_HIP(hipStreamSynchronize(S(stream)));
-    for (int i = 0; i < n; ++i) prepare_solve(hs[i]->h, prec, S(stream));
+    for (int i = 0; i < n; ++i) prepare_solve(hs[i]->h, prec, opts, S(stream));
     GMT_HIP(hipStreamSynchronize(S(stream)));
     // Longest-processing-time order balances the workers.  A cell's cost is its
     // unknowns times its iteration count, and the count rises steeply with the
@@ -2065,6 +2250,13 @@ gmt_status gmt_nn_norm2(const float* d_x, size_t n, double* h_out, void* stream)
   });
 }
 
+extern "C" gmt_status gmt_nn_norm2_noalloc(const float* d_x, size_t n, double* h_out, void* stream) {
+  return guarded([&] {
+    if (!d_x || !h_out) fail(GMT_E_INVAL, "null pointer");
+    *h_out = nn_norm2_noalloc(d_x, n, S(stream));
+  });
+}
+
 gmt_status gmt_nn_ema(float* d_ema, const float* d_x, size_t n, double decay, void* stream) {
   return guarded([&] {
     if (!d_ema || !d_x) fail(GMT_E_INVAL, "null pointer");
@@ -2082,6 +2274,8 @@ namespace gmt {
 static void vcycle_loss(Hier& h, const float* const* d_pred, const gmt_cycle_opts* opts, double lambda,
                         float* d_u1, double* h_out, float* const* d_gpred, hipStream_t s) {
   const CycleCfg cfg = make_cycle(h, opts);
+  if (cfg.smoother == GMT_SMOOTH_GS || cfg.schedule != GMT_CYCLE_V)
+    fail(GMT_E_INVAL, "the loss adjoint covers the V-cycle with Chebyshev or Jacobi smoothing");
   h.ensure_work<float>();
   h.ensure_io<float>(0);
   Work<float>& W = h.work<float>();

@@ -671,8 +671,9 @@ __global__ __launch_bounds__(kBlock) void k_apply_boundary(LevelView<T> L, int C
 // valid matrix), an inactive neighbour with a zero block.
 template <typename T, int D, int CB, int KIND, int EPI, int BS, int NM = 0>
 __global__ __launch_bounds__(BS) void k_apply_coarse(LevelView<T> L, const T* __restrict__ u, EpiArgs<T> e) {
-  const int i = block_index(L.xcd) * BS + threadIdx.x;
-  if (i >= L.n_n) return;
+  const int row = block_index(L.xcd) * BS + threadIdx.x;
+  if (row >= (L.list ? L.n_list : L.n_n)) return;
+  const int i = L.list ? L.list[row] : row;
   const int c0 = (int)blockIdx.y * CB;  // this thread's cases: c0 .. c0 + CB - 1
   const int N = L.N;
   const size_t n = (size_t)L.n_n;
@@ -1480,6 +1481,85 @@ __global__ void k_random(double* __restrict__ x, size_t n, uint64_t seed) {
 
 inline unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// One colour of the Gauss-Seidel smoother (Sec. 4.6): u_i += omega D_i^-1 r_i
+// for the listed nodes, r the residual of the current iterate at those nodes.
+// No two listed nodes share an element, so the updates are independent.
+template <typename T>
+__global__ void k_gs_update(const int* __restrict__ list, int n_list, int n, int D, const T* __restrict__ dinv,
+                            const T* __restrict__ r, T* __restrict__ u, T omega) {
+  const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= (size_t)n_list * D) return;
+  const int i = list[t / D];
+  const int q = (int)(t % D);
+  const size_t idx = vix((int)blockIdx.y, (size_t)n, (size_t)i, D, q);
+  u[idx] += omega * dinv[(size_t)i * D + q] * r[idx];
+}
+
+// ---------------------------------------------------------------- connected components
+// Union-find over the active elements of level 1 with lock-free hooking (the
+// scheme of Jaiganesh and Burtscher's ECL-CC): every element points to an
+// element of smaller id in its set (parent[v] <= v), a root to itself; a union
+// hooks the larger of the two roots under the smaller one by compare-and-swap
+// and retries from the value it found when another thread hooked that root
+// first.  Ids only decrease along every chain, so each loop ends.
+__device__ __forceinline__ int cc_load(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// root of v's set, shortening the chain on the way (each element is pointed
+// past its parent to its grandparent, which is also in the set)
+__device__ int cc_root(int* parent, int v) {
+  int cur = cc_load(parent + v);
+  if (cur != v) {
+    int prev = v, next;
+    while (cur > (next = cc_load(parent + cur))) {
+      __hip_atomic_store(parent + prev, next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      prev = cur;
+      cur = next;
+    }
+  }
+  return cur;
+}
+
+__global__ void k_cc_init(int* __restrict__ parent, int n_e) {
+  const int v = blockIdx.x * kBlock + threadIdx.x;
+  if (v < n_e) parent[v] = v;
+}
+
+// element v is joined to every active element among its 26 periodic
+// neighbours (all of them share at least one node with v)
+__global__ void k_cc_hook(const int* __restrict__ elem_lin, int n_e, const int* __restrict__ elem_map, int N,
+                          int* parent) {
+  const int v = blockIdx.x * kBlock + threadIdx.x;
+  if (v >= n_e) return;
+  const int lin = elem_lin[v];
+  const int x = lin % N, y = (lin / N) % N, z = lin / (N * N);
+  for (int j = 0; j < 27; ++j) {
+    if (j == 13) continue;
+    const int w = elem_map[wrapm(x + j % 3 - 1, N) + N * (wrapm(y + (j / 3) % 3 - 1, N) + N * wrapm(z + j / 9 - 1, N))];
+    if (w < 0 || w == v) continue;
+    int a = cc_root(parent, v), b = cc_root(parent, w);
+    while (a != b) {
+      if (a < b) {
+        const int got = atomicCAS(parent + b, b, a);
+        if (got == b) break;
+        b = got;  // b was hooked meanwhile: continue from its new parent (smaller)
+      } else {
+        const int got = atomicCAS(parent + a, a, b);
+        if (got == a) break;
+        a = got;
+      }
+    }
+  }
+}
+
+__global__ void k_cc_count(const int* __restrict__ parent, int n_e, int* __restrict__ count) {
+  const int v = blockIdx.x * kBlock + threadIdx.x;
+  const bool root = v < n_e && parent[v] == v;
+  const unsigned long long m = __ballot(root);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(count, __popcll(m));
+}
+
 }  // namespace
 
 // ================================================================ launchers
@@ -1488,8 +1568,10 @@ inline unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlo
 template <typename T, int D, int CB, int EPI>
 static void launch_coarse(const LevelView<T>& L, int kind, int rows, const T* u, const EpiArgs<T>& e, hipStream_t s) {
   const bool nm = L.cb >= 2;  // neighbour-major variants (64-wide workgroups only)
+  const int nrows = L.list ? L.n_list : L.n_n;
+  if (nrows <= 0) return;
   if (L.bs == 64 || nm) {
-    const dim3 g((unsigned)((L.n_n + 63) / 64), (unsigned)rows);
+    const dim3 g((unsigned)((nrows + 63) / 64), (unsigned)rows);
     if (kind == KIND_TABLE) {
       if (nm) hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_TABLE, EPI, 64, 1>), g, dim3(64), 0, s, L, u, e);
       else hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_TABLE, EPI, 64>), g, dim3(64), 0, s, L, u, e);
@@ -1498,7 +1580,7 @@ static void launch_coarse(const LevelView<T>& L, int kind, int rows, const T* u,
       else hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_PERELEM, EPI, 64>), g, dim3(64), 0, s, L, u, e);
     }
   } else {
-    const dim3 g(blocks_for(L.n_n), (unsigned)rows);
+    const dim3 g(blocks_for(nrows), (unsigned)rows);
     if (kind == KIND_TABLE)
       hipLaunchKernelGGL((k_apply_coarse<T, D, CB, KIND_TABLE, EPI, kBlock>), g, dim3(kBlock), 0, s, L, u, e);
     else
@@ -1658,6 +1740,32 @@ void launch_inv(const T* a, T* b, size_t n, hipStream_t s) {
   if (!n) return;
   hipLaunchKernelGGL(k_inv<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, b, n);
   GMT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_gs_update(const int* list, int n_list, int n, int D, int C, const T* dinv, const T* r, T* u, T omega,
+                      hipStream_t s) {
+  if (n_list <= 0) return;
+  hipLaunchKernelGGL(k_gs_update<T>, dim3(blocks_for((size_t)n_list * D), C), dim3(kBlock), 0, s, list, n_list, n, D,
+                     dinv, r, u, omega);
+  GMT_LAUNCH_CHECK();
+}
+
+int count_components(const int* elem_lin, int n_e, const int* elem_map, int N, int* parent, int* d_count,
+                     hipStream_t s) {
+  if (n_e <= 0) return 0;
+  const unsigned g = blocks_for(n_e);
+  hipLaunchKernelGGL(k_cc_init, dim3(g), dim3(kBlock), 0, s, parent, n_e);
+  GMT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_cc_hook, dim3(g), dim3(kBlock), 0, s, elem_lin, n_e, elem_map, N, parent);
+  GMT_LAUNCH_CHECK();
+  GMT_HIP(hipMemsetAsync(d_count, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_cc_count, dim3(g), dim3(kBlock), 0, s, parent, n_e, d_count);
+  GMT_LAUNCH_CHECK();
+  int h = 0;
+  GMT_HIP(hipMemcpyAsync(&h, d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+  GMT_HIP(hipStreamSynchronize(s));
+  return h;
 }
 
 static unsigned red_grid(int n) {
@@ -1973,7 +2081,8 @@ void launch_random(double* x, size_t n, uint64_t seed, hipStream_t s) {
   template void launch_scale_add_comp<T>(T*, const T*, T, const double*, int, int, int, hipStream_t);         \
   template void launch_mul_nodewise<T>(T*, const T*, int, int, int, int, hipStream_t);                        \
   template void launch_accumulate<T>(double*, const T*, size_t, hipStream_t, double);                                \
-  template void launch_diagonal<T>(const LevelView<T>&, int, int, T*, hipStream_t);
+  template void launch_diagonal<T>(const LevelView<T>&, int, int, T*, hipStream_t);                            \
+  template void launch_gs_update<T>(const int*, int, int, int, int, const T*, const T*, T*, T, hipStream_t);
 
 GMT_INST_T(float)
 GMT_INST_T(double)

@@ -15,6 +15,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -776,6 +778,68 @@ double nn_norm2(Hier* h, const float* x, size_t n, hipStream_t s) {
   GMT_HIP(hipStreamSynchronize(s));
   double sum = 0.0;
   for (unsigned k = 0; k < g; ++k) sum += hp[k];
+  return sum;
+}
+
+// ---------------------------------------------------------------- norm without allocation
+// gmt_nn_norm2_noalloc keeps its per-block partial sums in this file-scope
+// device array instead of a buffer allocated per call.  Every GPU holds its
+// own copy at its own address; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device (the array's name is a
+// host-side stand-in, not a device pointer).  Calls that overlap on one GPU
+// share it and race.
+constexpr int kNoAllocPartials = 8192;      // 64 KiB of FP64 partial sums (+ the total)
+constexpr size_t kNoAllocChunk = 2048;      // values per workgroup (8 per thread)
+static __device__ __align__(256) double scratch[kNoAllocPartials + 32];
+
+// total of the g partials into partial[kNoAllocPartials] (one workgroup, fixed order)
+__global__ __launch_bounds__(kB) void k_sum_partials(double* __restrict__ partial, int g) {
+  __shared__ double sh[kB / 64];
+  double v = 0.0;
+  for (int k = threadIdx.x; k < g; k += kB) v += partial[k];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < kB / 64; ++k) t += sh[k];
+    partial[kNoAllocPartials] = t;
+  }
+}
+
+static double* scratch_ptr() {
+  static std::mutex mu;
+  static std::map<int, double*> ptrs;
+  int dev = 0;
+  GMT_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(mu);
+  auto it = ptrs.find(dev);
+  if (it != ptrs.end()) return it->second;
+  double* p = nullptr;
+  GMT_HIP(hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch)));
+  ptrs[dev] = p;
+  return p;
+}
+
+size_t nn_norm2_noalloc_max() { return (size_t)kNoAllocPartials * kNoAllocChunk; }
+
+double nn_norm2_noalloc(const float* x, size_t n, hipStream_t s) {
+  if (n > nn_norm2_noalloc_max())
+    fail(GMT_E_INVAL, "n = %zu exceeds the %zu values the fixed scratch of gmt_nn_norm2_noalloc covers", n,
+         nn_norm2_noalloc_max());
+  double* partial = scratch_ptr();
+  if (n == 0) return 0.0;
+  const unsigned g = (unsigned)((n + kNoAllocChunk - 1) / kNoAllocChunk);
+  // every one of the g partials is written by its workgroup and the total
+  // overwrites its slot: nothing left from an earlier call is read
+  hipLaunchKernelGGL(k_norm2, dim3(g), dim3(kB), 0, s, x, n, partial);
+  GMT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kB), 0, s, partial, (int)g);
+  GMT_LAUNCH_CHECK();
+  double sum = 0.0;
+  GMT_HIP(hipMemcpyAsync(&sum, partial + kNoAllocPartials, sizeof(double), hipMemcpyDeviceToHost, s));
+  GMT_HIP(hipStreamSynchronize(s));
   return sum;
 }
 

@@ -243,3 +243,145 @@ def test_adamw_step():
     pr = p0 * (1 - lr * wd) - lr * (mr / (1 - b1 ** step)) / (np.sqrt(vr / (1 - b2 ** step)) + eps)
     assert np.abs(_np(p) - pr).max() <= 1e-5 * np.abs(pr).max()
     assert np.abs(_np(m) - mr).max() <= 1e-6 and np.abs(_np(v) - vr).max() <= 1e-6
+
+
+# ---------------------------------------------------------------------------- layer-local parity
+# Every stored BF16 activation is checked element by element against the oracle's
+# layer applied to the GPU's own (BF16, hence exact) layer inputs, so no rounding
+# decision upstream can make the two sides diverge.  Bound per element, from the
+# arithmetic: the GPU sums n FP32 terms (plus bias / skip adds and the slope
+# multiply), so its pre-activation is within delta = (n + 3) 2^-24 S of the exact
+# one, S the sum of the terms' magnitudes; the leaky ReLU is 1-Lipschitz; BF16
+# round-to-nearest-even moves a value by at most 2^-8 of itself.  Hence
+# |gpu - act(x)| <= 2^-8 (|act(x)| + delta) + delta.
+U32 = 2.0 ** -24
+
+
+def _act_bound(x, S, nterms):
+    delta = (nterms + 3) * U32 * S
+    return 2.0 ** -8 * (np.abs(onn.act(x)) + delta) + delta
+
+
+def _check_layer(name, gpu, x, S, nterms):
+    ref = onn.act(x)
+    err = np.abs(gpu - ref)
+    bound = _act_bound(x, S, nterms)
+    worst = float((err / np.maximum(bound, 1e-300)).max())
+    frac = float((gpu != onn.bf16(ref)).mean())
+    print(f"[layer] {name}: max err / bound {worst:.3f}, elements off the exact rounding {frac:.1e}", flush=True)
+    assert np.all(err <= bound), name
+
+
+@pytest.mark.parametrize("chs", [[16, 32, 64], [32, 64, 64]])
+def test_every_layer_element_wise(chs):
+    vox, H, net, g, flat = _make(chs, 3)
+    H.nn_forward(_t(flat))
+    L = H.L
+    W = {k: onn.bf16(v) for k, v in net.unflatten(flat).items()}
+    A = {(k, l): _np(H.nn_activation(l + 1, w)) for k, w, l in _activation_order(L)}
+    absW = {k: np.abs(v) for k, v in W.items()}
+    # embedding: a table lookup, bit-exact
+    assert np.array_equal(A[("h", 0)], onn.bf16(W["E"][g.occ8]))
+    C = net.C
+    for l in range(L):
+        h = A[("h", l)]
+        x = onn._conv(h, g.conv[l], W[f"We{l}"]) + W[f"be{l}"]
+        S = onn._conv(np.abs(h), g.conv[l], absW[f"We{l}"]) + absW[f"be{l}"]
+        _check_layer(f"a{l}", A[("a", l)], x, S, 27 * C[l])
+        if l + 1 < L:
+            a = A[("a", l)]
+            x = onn._conv(a, g.pool[l], W[f"Wp{l}"]) + W[f"bp{l}"]
+            S = onn._conv(np.abs(a), g.pool[l], absW[f"Wp{l}"]) + absW[f"bp{l}"]
+            _check_layer(f"h{l + 1}", A[("h", l + 1)], x, S, 27 * C[l])
+    for l in range(L - 2, -1, -1):
+        dn = A[("a", L - 1)] if l + 1 == L - 1 else A[("d", l + 1)]
+        n_l = g.levels[l].n_n
+        up = onn._conv_T(dn, g.pool[l], np.transpose(W[f"Wu{l}"], (0, 2, 1)), n_l)
+        Su = onn._conv_T(np.abs(dn), g.pool[l], np.transpose(absW[f"Wu{l}"], (0, 2, 1)), n_l)
+        a = A[("a", l)]
+        _check_layer(f"t{l}", A[("t", l)], up + W[f"bu{l}"] + a, Su + absW[f"bu{l}"] + np.abs(a), 27 * C[l + 1])
+        t = A[("t", l)]
+        x = onn._conv(t, g.conv[l], W[f"Wd{l}"]) + W[f"bd{l}"]
+        S = onn._conv(np.abs(t), g.conv[l], absW[f"Wd{l}"]) + absW[f"bd{l}"]
+        _check_layer(f"d{l}", A[("d", l)], x, S, 27 * C[l])
+        d = A[("d", l)]
+        _check_layer(f"z1_{l}", A[("z1", l)], d @ W[f"W1_{l}"] + W[f"b1_{l}"],
+                     np.abs(d) @ absW[f"W1_{l}"] + absW[f"b1_{l}"], C[l])
+        z1 = A[("z1", l)]
+        _check_layer(f"z2_{l}", A[("z2", l)], z1 @ W[f"W2_{l}"] + W[f"b2_{l}"],
+                     np.abs(z1) @ absW[f"W2_{l}"] + absW[f"b2_{l}"], net.H)
+    # predictions: FP32 head sums scaled by N, centred with FP64 column means
+    outs = H.nn_forward(_t(flat))
+    for l in range(L - 1):
+        z2 = A[("z2", l)]
+        raw = g.N * (z2 @ W[f"W3_{l}"] + W[f"b3_{l}"])
+        S3 = g.N * (np.abs(z2) @ absW[f"W3_{l}"] + absW[f"b3_{l}"])
+        ref = onn.center(raw)
+        delta = (net.H + 3) * U32 * S3
+        bound = 2 * delta.max(axis=0, keepdims=True) + delta + 2 * U32 * np.abs(ref)
+        err = np.abs(_np(outs[l]).reshape(ref.shape) - ref)
+        print(f"[layer] out{l}: max err / bound {(err / bound).max():.3f}", flush=True)
+        assert np.all(err <= bound), l
+    H.close()
+
+
+@pytest.mark.parametrize("chs", [[16, 32, 64], [32, 64, 64]])
+def test_backward_element_wise_on_gpu_activations(chs):
+    """Gradients against the oracle's backward run on the GPU's own stored activations (so the
+    leaky-ReLU derivative pattern is the same on both sides), element by element: every entry
+    of a parameter tensor within 1e-3 of that tensor's largest entry.  The GPU gradient is a
+    chain of FP32 sums (per layer up to 27 x 64 terms in the data gradients and a few thousand
+    node products in the weight gradients, over up to ten layers), each adding relative
+    rounding of about sqrt(terms) 2^-24 = 3e-6 of its partial sums; the bound leaves more than
+    ten times that over the whole chain.  Tensors whose exact gradient vanishes (the head's last
+    biases, which the centring removes) are held to 1e-3 of the whole gradient's largest entry.
+    (A bound from the magnitudes of all products is valid but vacuous here: through ten layers
+    of 27 x C terms the magnitudes exceed the cancelling sums by 1e4 to 1e7.)"""
+    vox, H, net, g, flat = _make(chs, 3)
+    outs = H.nn_forward(_t(flat))
+    L = H.L
+    W = {k: onn.bf16(v) for k, v in net.unflatten(flat).items()}
+    A = {(k, l): _np(H.nn_activation(l + 1, w)) for k, w, l in _activation_order(L)}
+    cache = {"W": W,
+             "h": [A[("h", l)] for l in range(L)], "a": [A[("a", l)] for l in range(L)],
+             "t": [A[("t", l)] for l in range(L - 1)] + [None],
+             "d": [A[("d", l)] for l in range(L - 1)] + [A[("a", L - 1)]],
+             "z1": [A[("z1", l)] for l in range(L - 1)], "z2": [A[("z2", l)] for l in range(L - 1)]}
+    rng = np.random.default_rng(19)
+    gouts = [rng.standard_normal((o.shape[0], 18)) for o in outs]
+    grad = torch.zeros(net.n_params(), dtype=torch.float32, device=DEV)
+    H.nn_backward([_t(x.reshape(o.shape)) for x, o in zip(gouts, outs)], grad)
+    H.close()
+    gref = onn.backward(net, g, cache, gouts)
+    Gg, Gr = net.unflatten(_np(grad)), net.unflatten(gref)
+    total = np.abs(gref).max()
+    worst = {}
+    for name, _ in net.shapes():
+        err = np.abs(Gg[name] - Gr[name]).max()
+        if name.startswith("b3_"):
+            assert err <= 1e-3 * total, name
+            continue
+        worst[name] = err / np.abs(Gr[name]).max()
+    print(f"[grad] {chs}: " + " ".join(f"{k}:{v:.1e}" for k, v in worst.items()), flush=True)
+    bad = {k: v for k, v in worst.items() if v > 1e-3}
+    assert not bad, bad
+
+
+def test_norm2_and_ema():
+    B = _gmt()
+    rng = np.random.default_rng(2)
+    for n in (1, 255, 256 * 256 + 17, 3_000_001):
+        x = rng.standard_normal(n).astype(np.float32)
+        ref = float((x.astype(np.float64) ** 2).sum())
+        got = B.norm2(_t(x))
+        assert abs(got - ref) <= 1e-12 * ref, (n, got, ref)
+    assert B.norm2(_t(np.zeros(1000, dtype=np.float32))) == 0.0
+    n = 100_003
+    e0 = rng.standard_normal(n).astype(np.float32)
+    x = rng.standard_normal(n).astype(np.float32)
+    e = _t(e0)
+    for decay in (0.999, 0.5, 0.0):
+        ref = np.float32(decay) * _np(e).astype(np.float32) + (np.float32(1) - np.float32(decay)) * x
+        B.ema(e, _t(x), decay)
+        assert np.abs(_np(e) - ref).max() <= 2 * 2.0 ** -24 * np.abs(ref).max()
+    assert np.abs(_np(e) - x).max() == 0.0  # decay 0 copies x

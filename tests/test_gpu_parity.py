@@ -392,3 +392,47 @@ def test_full_size_mixed_solve(big):
     assert rep64["converged"]
     CH32, CH64 = H.homogenize(u32), H.homogenize(u64)
     assert np.linalg.norm(CH32 - CH64) <= 1e-4 * np.linalg.norm(CH64)
+
+
+def test_lambda_estimate_many_levels():
+    """lambda_max(D^-1 K) of every level of a six-level hierarchy (64^3), where the power
+    iterations of the levels run concurrently on the auxiliary streams."""
+    vox = gyroid_sheet(64, 5, 0.3)
+    P = osolve.Problem(vox, 6)
+    H = _gmt().Hierarchy(vox, 6)
+    for l in range(1, 7):
+        est = H.level_info(l)["lambda_max"]
+        ref = P.lambda_max(l - 1)
+        print(f"[lambda 64^3] level {l}: {est:.6f} (oracle {ref:.6f})", flush=True)
+        assert 0.8 * ref <= est <= ref * (1 + 1e-9), (l, est, ref)
+    H.close()
+
+
+def test_components_detected():
+    """A cell of several node-connected components is refused with the count in the message;
+    the count agrees with the oracle's; cells joined through a single shared node are one."""
+    B = _gmt()
+    two = laminate(16, 3, axis=2) | np.roll(laminate(16, 3, axis=2), 8, axis=0)
+    three = two | np.roll(laminate(16, 2, axis=2), 5, axis=0)
+    for vox, want in ((two, 2), (three, 3)):
+        assert ohier.node_components(vox) == want
+        with pytest.raises(B.GmtError) as ei:
+            B.Hierarchy(vox, 3)
+        assert ei.value.status == B.GMT_E_INVAL
+        assert f"form {want} node-connected components" in str(ei.value)
+    chain = np.zeros((16, 16, 16), dtype=np.uint8)
+    for k in range(16):
+        chain[k, k, k] = 1  # a periodic diagonal chain: consecutive voxels share one node
+    assert ohier.node_components(chain) == 1
+    H = B.Hierarchy(chain, 3)
+    assert H.level_info(1)["n_e"] == 16
+    H.close()
+    for seed in range(4):
+        vox = (np.random.default_rng(seed).random((16, 16, 16)) < 0.03).astype(np.uint8)
+        k = ohier.node_components(vox)
+        if k == 1:
+            B.Hierarchy(vox, 3).close()
+        else:
+            with pytest.raises(B.GmtError) as ei:
+                B.Hierarchy(vox, 3)
+            assert f"form {k} node-connected components" in str(ei.value)
