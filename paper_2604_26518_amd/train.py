@@ -37,9 +37,16 @@ def _gen(args):
 
 
 def make_cells(N, seeds, procs=16):
+    """Generates cells in worker processes.  Call it before anything touches the GPU: the
+    workers are forked, and a process that has initialised HIP must not fork.  The pool is
+    closed and joined (not terminated), so every worker exits on its own."""
     procs = max(1, min(procs, os.cpu_count() or 1))
-    with mp.get_context("fork").Pool(procs) as pool:
+    pool = mp.get_context("fork").Pool(procs)
+    try:
         return pool.map(_gen, [(s, N) for s in seeds], chunksize=4)
+    finally:
+        pool.close()
+        pool.join()
 
 
 def build(vox, levels, physics="elastic"):
@@ -90,11 +97,12 @@ def main(argv=None):
     ap.add_argument("--cache-gb", type=float, default=120.0, help="GPU memory for cached hierarchies")
     ap.add_argument("--eval-every", type=int, default=1000)
     args = ap.parse_args(argv)
-    torch.cuda.set_device(0)
     levels = args.levels or B.default_levels(args.N)
     t0 = time.time()
+    # all cells are generated (forked workers) before the first GPU call
     cells = make_cells(args.N, range(args.seed0, args.seed0 + args.cells))
     test = make_cells(args.N, range(args.test_seed0, args.test_seed0 + args.held_out))
+    torch.cuda.set_device(0)
     print(f"# {len(cells)} train + {len(test)} held-out cells at {args.N}^3 in {time.time() - t0:.1f} s, "
           f"levels {levels}", flush=True)
     n_params = B.nn_param_count(levels, channels_for(levels))

@@ -160,5 +160,8 @@ def test_bad_weights_rejected(pair):
         H.smooth(_t(P.f), u, 1, "gs", 2.5, 0.0)
     with pytest.raises(B.GmtError):
         H.smooth(_t(P.f), u, 1, "gs", 1.0, 0.5)
+    # the coarsest level has no smoother (its system is solved exactly)
+    nL = P.levels[P.L - 1].n_n
+    uL = _t(np.zeros((nL, P.c, P.d)))
     with pytest.raises(B.GmtError):
-        H.smooth(_t(P.f), u, 1, "gs", 1.0, 0.0, level=P.L)
+        H.smooth(_t(np.ones((nL, P.c, P.d))), uL, 1, "gs", 1.0, 0.0, level=P.L)
