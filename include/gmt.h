@@ -274,7 +274,7 @@ gmt_status gmt_homogenize(gmt_hier_t h, const void* d_u, int32_t dtype, double* 
  * ------------------------------------------------------------------------ */
 #define GMT_NN_MAX_LEVELS 8
 typedef struct {
-  int32_t levels;                       /* = the hierarchy's L */
+  int32_t levels;                       /* 2..the hierarchy's L: the network runs on levels 1..levels */
   int32_t channels[GMT_NN_MAX_LEVELS];  /* C_l in {16, 32, 64} */
   int32_t head;                         /* H = 32 */
 } gmt_nn_config;
@@ -285,9 +285,11 @@ gmt_status gmt_nn_param_count(const gmt_nn_config* cfg, int32_t physics, size_t*
 /* Builds the network's neighbour tables and activation buffers for a hierarchy. */
 gmt_status gmt_nn_setup(gmt_hier_t h, const gmt_nn_config* cfg, void* stream);
 
-/* Forward pass.  d_out: array of L pointers indexed by level-1; entry l-1
- * (l = 1..L-1) receives the level-l prediction [n_l][c][d] FP32 (u_hat^1 for
- * l = 1, e_hat^l otherwise) or is NULL to skip it; entry L-1 is unused.
+/* Forward pass.  With L' = cfg.levels: d_out is an array of L' pointers indexed
+ * by level-1; entry l-1 (l = 1..L'-1) receives the level-l prediction
+ * [n_l][c][d] FP32 (u_hat^1 for l = 1, e_hat^l otherwise) or is NULL to skip
+ * it; entry L'-1 is unused.  (L' < L: a network of fewer levels than the
+ * hierarchy, e.g. trained on coarser cells, predicts for levels 1..L'-1 only.)
  * Every prediction is centred: the mean over the level's nodes of each of its
  * c*d columns is removed (zero-mean gauge, Sec. 4.5). */
 gmt_status gmt_nn_forward(gmt_hier_t h, const float* d_params, float* const* d_out, void* stream);

@@ -424,10 +424,12 @@ class Hierarchy:
 
     # -- learned initializer
     def nn_setup(self, channels, head=32):
-        if len(channels) != self.L:
-            raise ValueError(f"need {self.L} channel counts")
-        self._nn_cfg = nn_config(self.L, channels, head)
-        self.n_params = nn_param_count(self.L, channels, head, self.physics)
+        """Network on levels 1..len(channels) (at most the hierarchy's L levels)."""
+        if not 2 <= len(channels) <= self.L:
+            raise ValueError(f"need 2..{self.L} channel counts")
+        self.nn_levels = len(channels)
+        self._nn_cfg = nn_config(self.nn_levels, channels, head)
+        self.n_params = nn_param_count(self.nn_levels, channels, head, self.physics)
         _check(lib().gmt_nn_setup(self._h, ct.byref(self._nn_cfg), _stream()))
 
     def _check_params(self, params):
@@ -438,15 +440,15 @@ class Hierarchy:
     def nn_forward(self, params):
         """Predictions [u_hat^1, e_hat^2, ..., e_hat^{L-1}] as float32 [n_l][c][d] tensors."""
         self._check_params(params)
-        outs = [self.vec(l, torch.float32) for l in range(1, self.L)] + [None]
+        outs = [self.vec(l, torch.float32) for l in range(1, self.nn_levels)] + [None]
         _check(lib().gmt_nn_forward(self._h, _ptr(params), _ptr_array(outs), _stream()))
         return outs[:-1]
 
     def nn_backward(self, gouts, grad):
         """grad += d/dparams sum_l <gouts[l], outs[l]> for the last forward."""
         self._check_params(grad)
-        gl = list(gouts) + [None] * (self.L - len(gouts))
-        for l, g in enumerate(gl[:self.L - 1], start=1):
+        gl = (list(gouts) + [None] * self.nn_levels)[:self.nn_levels]
+        for l, g in enumerate(gl[:self.nn_levels - 1], start=1):
             if g is not None:
                 self._v(g, l, torch.float32, f"gout[{l}]")
         _check(lib().gmt_nn_backward(self._h, _ptr_array(gl), _ptr(grad), _stream()))

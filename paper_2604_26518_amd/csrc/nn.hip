@@ -102,11 +102,134 @@ __global__ __launch_bounds__(kB) void k_gconv(int n, const int* __restrict__ tab
   }
 }
 
-// dW[t][ci][co] += sum_i x[tab[i][t]][ci] g[i][co]; grid (node chunks, taps).
+// ---------------------------------------------------------------- BF16 MFMA gather convolution
+// The same layer as k_gconv for BF16 inputs, as a gather-GEMM on the matrix
+// cores: D[co][node] = sum_K Wm[co][K] X[K][node], K = (tap, input channel)
+// in steps of 32, with v_mfma_f32_16x16x32_bf16 (A = 16 output channels x 32 K
+// from the pre-arranged weights, B = 32 K x 16 nodes gathered straight from
+// the node-major BF16 activations, one 16-byte load per lane, FP32
+// accumulators).  Lane l of a 16x16x32 operand holds row/column l % 16 and the
+// 8 consecutive K values 8 (l / 16) .. 8 (l / 16) + 7; the accumulator lane l
+// holds column l % 16 (a node) and rows 4 (l / 16) .. + 3 (four consecutive
+// output channels, one 8-byte store).  A wave computes 4 x 16 nodes, so each
+// weight fragment is loaded once per 64 nodes.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kMfmaRows = 4;  // 16-node column blocks per wave
+
+__device__ __forceinline__ f32x4_t mfma16(uint4 a, uint4 b, f32x4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b),
+                                                 c, 0, 0, 0);
+}
+
+template <typename Tout, int CIN, int COUT, int NTAP, int FLAGS>
+__global__ __launch_bounds__(kB) void k_gconv_mfma(int n, const int* __restrict__ tab, const uint16_t* __restrict__ x,
+                                                    const uint4* __restrict__ Wm, const float* __restrict__ b,
+                                                    const uint16_t* __restrict__ skip, float scale,
+                                                    Tout* __restrict__ y) {
+  static_assert(CIN % 16 == 0, "input rows are read 8 channels per lane");
+  constexpr int KS = (NTAP * CIN + 31) / 32;  // K steps (the last one zero-padded)
+  constexpr int NCB = (COUT + 15) / 16;       // 16-channel output blocks
+  constexpr int R = kMfmaRows;
+  const int lane = threadIdx.x & 63, col = lane & 15, kb = lane >> 4;
+  const int base = (blockIdx.x * (kB / 64) + (threadIdx.x >> 6)) * (16 * R);
+  if (base >= n) return;  // wave-uniform
+  f32x4_t acc[R][NCB];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) acc[r][c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int s = 0; s < KS; ++s) {
+    const int K0 = 32 * s + 8 * kb;
+    const int t = K0 / CIN, ci0 = K0 % CIN;
+    uint4 xv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int node = base + 16 * r + col;
+      int src = -1;
+      if (node < n && t < NTAP) src = (NTAP == 1 && tab == nullptr) ? node : tab[(size_t)node * NTAP + t];
+      xv[r] = src >= 0 ? *reinterpret_cast<const uint4*>(x + (size_t)src * CIN + ci0) : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) {
+      const uint4 wv = Wm[(size_t)(s * NCB + c) * 64 + lane];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r][c] = mfma16(wv, xv[r], acc[r][c]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int node = base + 16 * r + col;
+    if (node >= n) continue;
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) {
+      const int c0 = 16 * c + 4 * kb;
+      if (c0 >= COUT) continue;
+      float v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float w = acc[r][c][j];
+        if (c0 + j < COUT) {
+          if constexpr (FLAGS & F_BIAS) w += b[c0 + j];
+          if constexpr (FLAGS & F_SKIP) w += bf2f(skip[(size_t)node * COUT + c0 + j]);
+        }
+        if constexpr (FLAGS & F_ACT) w = w > 0.f ? w : kSlope * w;
+        if constexpr (FLAGS & F_SCALE) w *= scale;
+        v[j] = w;
+      }
+      Tout* out = y + (size_t)node * COUT + c0;
+      if constexpr (COUT % 4 == 0 && sizeof(Tout) == 2) {
+        uint2 pk;
+        pk.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+        pk.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+        *reinterpret_cast<uint2*>(out) = pk;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (c0 + j < COUT) stf<Tout>(out + j, v[j]);
+      }
+    }
+  }
+}
+
+// One layer's weights in the A-operand order of k_gconv_mfma:
+// Wm[s][cb][lane][j] = W[t][ci][co] (BF16, round to nearest even) with
+// co = 16 cb + lane % 16 and t * CIN + ci = 32 s + 8 (lane / 16) + j; zero
+// beyond the last tap or output channel.
+struct MfmaLayer {
+  int src;  // offset of W [NTAP][CIN][COUT] in the flat FP32 parameters
+  int dst;  // offset in the arranged BF16 array (a multiple of 512)
+  int ntap, cin, cout, ncb;
+};
+
+__global__ void k_arrange_mfma(int nlayers, const MfmaLayer* __restrict__ lay, int total, const float* __restrict__ W,
+                               uint16_t* __restrict__ Wm) {
+  const int e = blockIdx.x * kB + threadIdx.x;
+  if (e >= total) return;
+  int k = 0;
+  while (k + 1 < nlayers && lay[k + 1].dst <= e) ++k;
+  const MfmaLayer L = lay[k];
+  const int r = e - L.dst;
+  const int j = r & 7, lane = (r >> 3) & 63, blk = r >> 9;
+  const int cb = blk % L.ncb, s = blk / L.ncb;
+  const int co = 16 * cb + (lane & 15);
+  const int K = 32 * s + 8 * (lane >> 4) + j;
+  const int t = K / L.cin, ci = K % L.cin;
+  const float v = (t < L.ntap && co < L.cout) ? W[L.src + ((size_t)t * L.cin + ci) * L.cout + co] : 0.f;
+  Wm[e] = f2bf(v);
+}
+
+// Weight gradient dW[t][ci][co] += sum_i x[tab[i][t]][ci] g[i][co], in a fixed
+// order: block (chunk, t) sums its chunk of nodes into partial[chunk][t][.],
+// then k_reduce_partials adds the chunks in chunk order (no float atomics, so
+// the gradient is the same bit for bit on every run).
 constexpr int kWChunk = 64;
+constexpr int kMaxChunks = 64;
 template <typename Tin, int CIN, int COUT, int NTAP>
 __global__ __launch_bounds__(kB) void k_wgrad(int n, const int* __restrict__ tab, const Tin* __restrict__ x,
-                                               const float* __restrict__ g, float* __restrict__ dW,
+                                               const float* __restrict__ g, float* __restrict__ partial,
                                                int nodes_per_block) {
   constexpr int P = CIN * COUT;
   constexpr int PPT = (P + kB - 1) / kB;
@@ -146,16 +269,27 @@ __global__ __launch_bounds__(kB) void k_wgrad(int n, const int* __restrict__ tab
     }
     __syncthreads();
   }
+  float* out = partial + ((size_t)blockIdx.x * NTAP + t) * P;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int p = threadIdx.x + k * kB;
-    if (p < P) atomicAdd(dW + (size_t)t * P + p, acc[k]);
+    if (p < P) out[p] = acc[k];
   }
 }
 
-// db[co] += sum_i g[i][co]
+// dst[e] += sum_{c < chunks} partial[c][e], c in increasing order
+__global__ void k_reduce_partials(size_t per, int chunks, const float* __restrict__ partial, float* __restrict__ dst) {
+  const size_t e = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (e >= per) return;
+  float s = 0.f;
+  for (int c = 0; c < chunks; ++c) s += partial[(size_t)c * per + e];
+  dst[e] += s;
+}
+
+// Bias gradient db[co] += sum_i g[i][co]: per-block sums (grid-stride over a
+// fixed grid) into partial[block][co], then k_reduce_partials.
 template <int COUT>
-__global__ __launch_bounds__(kB) void k_bgrad(int n, const float* __restrict__ g, float* __restrict__ db) {
+__global__ __launch_bounds__(kB) void k_bgrad(int n, const float* __restrict__ g, float* __restrict__ partial) {
   __shared__ float sh[kB / 64][COUT];
   float acc[COUT];
 #pragma unroll
@@ -176,7 +310,7 @@ __global__ __launch_bounds__(kB) void k_bgrad(int n, const float* __restrict__ g
     float s = 0.f;
 #pragma unroll
     for (int k = 0; k < kB / 64; ++k) s += sh[k][threadIdx.x];
-    atomicAdd(db + threadIdx.x, s);
+    partial[(size_t)blockIdx.x * COUT + threadIdx.x] = s;
   }
 }
 
@@ -223,21 +357,37 @@ __global__ void k_embed(int n, const uint8_t* __restrict__ occ8, const float* __
   y[e] = f2bf(E[(size_t)occ8[i] * C + c]);
 }
 
-// dE[occ][c] += g[i][c]: per-block histogram in LDS, then one atomic per entry
+// Embedding gradient dE[o][c] += sum_{i : occ8[i] = o} g[i][c]: block o scans
+// every node in a fixed order and reduces its threads' sums in a fixed tree
+// (deterministic; each block reads the n occupancy bytes, an L2-resident stream).
 template <int C>
 __global__ __launch_bounds__(kB) void k_embed_grad(int n, const uint8_t* __restrict__ occ8, const float* __restrict__ g,
                                                    float* __restrict__ dE) {
-  __shared__ float hist[256 * C];
-  for (int e = threadIdx.x; e < 256 * C; e += kB) hist[e] = 0.f;
-  __syncthreads();
-  for (int i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB) {
-    const int o = occ8[i];
+  __shared__ float sh[kB / 64][C];
+  const int o = blockIdx.x;
+  float acc[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) atomicAdd(&hist[o * C + c], g[(size_t)i * C + c]);
+  for (int c = 0; c < C; ++c) acc[c] = 0.f;
+  for (int i = threadIdx.x; i < n; i += kB)
+    if (occ8[i] == o) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] += g[(size_t)i * C + c];
+    }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    float v = acc[c];
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_down(v, d, 64);
+    if (lane == 0) sh[w][c] = v;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < 256 * C; e += kB)
-    if (hist[e] != 0.f) atomicAdd(dE + e, hist[e]);
+  if (threadIdx.x < C) {
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < kB / 64; ++k) s += sh[k][threadIdx.x];
+    dE[(size_t)o * C + threadIdx.x] += s;
+  }
 }
 
 // tables ----------------------------------------------------------------------
@@ -387,15 +537,45 @@ static void gconv_dispatch(int cin, int cout, int ntap, int n, const int* tab, c
   fail(GMT_E_INVAL, "gather conv (%d -> %d, %d taps) not instantiated", cin, cout, ntap);
 }
 
+// BF16-input layers of the forward on the matrix cores
+template <typename Tout, int FLAGS>
+static void mfma_dispatch(int cin, int cout, int ntap, int n, const int* tab, const uint16_t* x, const uint16_t* Wm,
+                          const float* b, const uint16_t* skip, float scale, Tout* y, hipStream_t s) {
+  if (n <= 0) return;
+  const int per_block = (kB / 64) * 16 * kMfmaRows;
+  const unsigned g = (unsigned)((n + per_block - 1) / per_block);
+  const uint4* w = reinterpret_cast<const uint4*>(Wm);
+#define GM(CI, CO, NT)                                                                                              \
+  if (cin == CI && cout == CO && ntap == NT) {                                                                     \
+    hipLaunchKernelGGL((k_gconv_mfma<Tout, CI, CO, NT, FLAGS>), dim3(g), dim3(kB), 0, s, n, tab, x, w, b, skip, scale, \
+                       y);                                                                                          \
+    GMT_LAUNCH_CHECK();                                                                                             \
+    return;                                                                                                         \
+  }
+  if constexpr (sizeof(Tout) == 2) {
+    GM(16, 16, 27) GM(32, 32, 27) GM(64, 64, 27) GM(16, 32, 27) GM(32, 64, 27) GM(32, 16, 27) GM(64, 32, 27)
+    GM(16, 32, 1) GM(32, 32, 1) GM(64, 32, 1)
+  } else {
+    GM(32, 18, 1) GM(32, 3, 1)
+  }
+#undef GM
+  fail(GMT_E_INVAL, "MFMA gather conv (%d -> %d, %d taps) not instantiated", cin, cout, ntap);
+}
+
 template <typename Tin>
 static void wgrad_dispatch(int cin, int cout, int ntap, int n, const int* tab, const void* x, const float* g,
-                           float* dW, hipStream_t s) {
+                           float* dW, float* partial, hipStream_t s) {
   if (n <= 0) return;
-  const int per_block = 1024;
-  const dim3 grid((unsigned)((n + per_block - 1) / per_block), (unsigned)ntap);
+  const int chunks = std::min(kMaxChunks, (n + 1023) / 1024);
+  const int per_block = (n + chunks - 1) / chunks;
+  const dim3 grid((unsigned)chunks, (unsigned)ntap);
 #define WG(CI, CO, NT)                                                                                     \
   if (cin == CI && cout == CO && ntap == NT) {                                                            \
-    hipLaunchKernelGGL((k_wgrad<Tin, CI, CO, NT>), grid, dim3(kB), 0, s, n, tab, (const Tin*)x, g, dW, per_block); \
+    hipLaunchKernelGGL((k_wgrad<Tin, CI, CO, NT>), grid, dim3(kB), 0, s, n, tab, (const Tin*)x, g, partial, \
+                       per_block);                                                                         \
+    GMT_LAUNCH_CHECK();                                                                                    \
+    const size_t per = (size_t)NT * CI * CO;                                                               \
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nblk(per)), dim3(kB), 0, s, per, chunks, partial, dW);      \
     GMT_LAUNCH_CHECK();                                                                                    \
     return;                                                                                                \
   }
@@ -405,15 +585,18 @@ static void wgrad_dispatch(int cin, int cout, int ntap, int n, const int* tab, c
   fail(GMT_E_INVAL, "weight gradient (%d -> %d, %d taps) not instantiated", cin, cout, ntap);
 }
 
-static void bgrad_dispatch(int cout, int n, const float* g, float* db, hipStream_t s) {
+constexpr int kBgradBlocks = 256;
+
+static void bgrad_dispatch(int cout, int n, const float* g, float* db, float* partial, hipStream_t s) {
   if (n <= 0) return;
-  unsigned grid = nblk(n);
-  if (grid > 1024) grid = 1024;
-#define BG(CO)                                                                 \
-  if (cout == CO) {                                                            \
-    hipLaunchKernelGGL(k_bgrad<CO>, dim3(grid), dim3(kB), 0, s, n, g, db);     \
-    GMT_LAUNCH_CHECK();                                                        \
-    return;                                                                    \
+  const unsigned grid = std::min<unsigned>(kBgradBlocks, nblk(n));
+#define BG(CO)                                                                                   \
+  if (cout == CO) {                                                                              \
+    hipLaunchKernelGGL(k_bgrad<CO>, dim3(grid), dim3(kB), 0, s, n, g, partial);                  \
+    GMT_LAUNCH_CHECK();                                                                          \
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kB), 0, s, (size_t)CO, (int)grid, partial, db); \
+    GMT_LAUNCH_CHECK();                                                                          \
+    return;                                                                                      \
   }
   BG(16) BG(32) BG(64) BG(18) BG(3)
 #undef BG
@@ -482,9 +665,14 @@ struct NNState {
   std::vector<int*> conv, pool, unpool;                  // neighbour tables
   std::vector<uint16_t*> h, a, t, d, z1, z2;             // BF16 activations
   float* Wb = nullptr;                                   // BF16-rounded weights (FP32 storage)
+  uint16_t* Wm = nullptr;                                // forward weights in the MFMA operand order
+  MfmaLayer* mlay = nullptr;                             // their layer table (device)
+  int n_mlay = 0, m_total = 0;
+  std::map<size_t, int> mdst;                            // parameter offset of a layer -> its Wm offset
   float* Wt = nullptr;                                   // transposed weights of one layer
   float *g0 = nullptr, *g1 = nullptr, *g2 = nullptr;     // FP32 gradient scratch (max n_l * max C)
   double* colred = nullptr;                              // column-mean partials + means
+  float* part = nullptr;                                 // per-chunk gradient partial sums
   std::vector<float*> gd;                                // dL/dd_l accumulators
   std::vector<float*> ga;                                // dL/da_l accumulators
 };
@@ -500,9 +688,12 @@ void nn_release(Hier& h) {
 }
 
 void nn_setup(Hier& h, const gmt_nn_config& cfg, hipStream_t s) {
-  if (cfg.levels != h.L) fail(GMT_E_INVAL, "network levels (%d) must equal the hierarchy's (%d)", cfg.levels, h.L);
-  if (h.L < 2 || h.L > GMT_NN_MAX_LEVELS) fail(GMT_E_INVAL, "network needs 2..%d levels", GMT_NN_MAX_LEVELS);
-  for (int l = 0; l < h.L; ++l)
+  // the network runs on the finest cfg.levels levels of the hierarchy (all of them, or the
+  // top of a deeper hierarchy: a network trained at one resolution on a finer cell)
+  if (cfg.levels < 2 || cfg.levels > h.L || cfg.levels > GMT_NN_MAX_LEVELS)
+    fail(GMT_E_INVAL, "network levels (%d) must be in 2..min(%d, the hierarchy's %d)", cfg.levels,
+         GMT_NN_MAX_LEVELS, h.L);
+  for (int l = 0; l < cfg.levels; ++l)
     if (cfg.channels[l] != 16 && cfg.channels[l] != 32 && cfg.channels[l] != 64)
       fail(GMT_E_INVAL, "channels must be 16, 32 or 64");
   if (cfg.head != 32) fail(GMT_E_INVAL, "head width must be 32");
@@ -510,7 +701,7 @@ void nn_setup(Hier& h, const gmt_nn_config& cfg, hipStream_t s) {
   NNState* S = new NNState();
   h.nn = S;
   S->nl = make_layout(cfg, h.Q);
-  const int L = h.L;
+  const int L = cfg.levels;
   size_t maxnc = 0;
   S->conv.resize(L);
   S->pool.assign(L, nullptr);
@@ -552,6 +743,35 @@ void nn_setup(Hier& h, const gmt_nn_config& cfg, hipStream_t s) {
     S->gd[l] = h.alloc<float>((size_t)d.n_n * C);
   }
   S->Wb = h.alloc<float>(S->nl.total);
+  {
+    // every forward layer's weights, arranged for k_gconv_mfma (512 BF16 per K step and
+    // 16-channel output block)
+    const NetLayout& N = S->nl;
+    std::vector<MfmaLayer> lay;
+    int dst = 0;
+    auto add = [&](size_t src, int ntap, int cin, int cout) {
+      MfmaLayer m{(int)src, dst, ntap, cin, cout, (cout + 15) / 16};
+      S->mdst[src] = dst;
+      lay.push_back(m);
+      dst += ((ntap * cin + 31) / 32) * m.ncb * 512;
+    };
+    for (int l = 0; l < L; ++l) {
+      add(N.We[l], 27, N.C[l], N.C[l]);
+      if (l + 1 < L) {
+        add(N.Wp[l], 27, N.C[l], N.C[l + 1]);
+        add(N.Wu[l], 27, N.C[l + 1], N.C[l]);
+        add(N.Wd[l], 27, N.C[l], N.C[l]);
+        add(N.W1[l], 1, N.C[l], N.H);
+        add(N.W2[l], 1, N.H, N.H);
+        add(N.W3[l], 1, N.H, N.q);
+      }
+    }
+    S->n_mlay = (int)lay.size();
+    S->m_total = dst;
+    S->Wm = h.alloc<uint16_t>((size_t)dst);
+    S->mlay = h.alloc<MfmaLayer>(lay.size());
+    GMT_HIP(hipMemcpyAsync(S->mlay, lay.data(), lay.size() * sizeof(MfmaLayer), hipMemcpyHostToDevice, s));
+  }
   size_t maxw = 0;
   for (int l = 0; l < L; ++l) maxw = std::max(maxw, (size_t)27 * 64 * 64);
   S->Wt = h.alloc<float>(maxw);
@@ -559,6 +779,7 @@ void nn_setup(Hier& h, const gmt_nn_config& cfg, hipStream_t s) {
   S->g0 = h.alloc<float>(maxnc);
   S->g1 = h.alloc<float>(maxnc);
   S->g2 = h.alloc<float>(maxnc);
+  S->part = h.alloc<float>(std::max((size_t)kMaxChunks * 27 * 64 * 64, (size_t)kBgradBlocks * 64));
   GMT_HIP(hipStreamSynchronize(s));
 }
 
@@ -591,33 +812,37 @@ void nn_forward(Hier& h, const float* params, float* const* out, hipStream_t s) 
   const int L = N.L;
   hipLaunchKernelGGL(k_round_bf16, dim3(nblk(N.total)), dim3(kB), 0, s, N.total, params, S.Wb);
   GMT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_arrange_mfma, dim3(nblk(S.m_total)), dim3(kB), 0, s, S.n_mlay, S.mlay, S.m_total, params,
+                     S.Wm);
+  GMT_LAUNCH_CHECK();
   const float* W = S.Wb;
+  auto wm = [&](size_t src) { return S.Wm + S.mdst.at(src); };
   const int n0 = h.lv[0].n_n;
   hipLaunchKernelGGL(k_embed, dim3(nblk((size_t)n0 * N.C[0])), dim3(kB), 0, s, n0, h.lv[0].occ8, W + N.E, N.C[0],
                      S.h[0]);
   GMT_LAUNCH_CHECK();
   for (int l = 0; l < L; ++l) {
     const int n = h.lv[l].n_n, C = N.C[l];
-    gconv_dispatch<uint16_t, uint16_t, F_BIAS | F_ACT>(C, C, 27, n, S.conv[l], S.h[l], W + N.We[l], W + N.be[l],
-                                                       nullptr, 1.f, S.a[l], s);
+    mfma_dispatch<uint16_t, F_BIAS | F_ACT>(C, C, 27, n, S.conv[l], S.h[l], wm(N.We[l]), W + N.be[l], nullptr, 1.f,
+                                            S.a[l], s);
     if (l + 1 < L)
-      gconv_dispatch<uint16_t, uint16_t, F_BIAS | F_ACT>(C, N.C[l + 1], 27, h.lv[l + 1].n_n, S.pool[l], S.a[l],
-                                                         W + N.Wp[l], W + N.bp[l], nullptr, 1.f, S.h[l + 1], s);
+      mfma_dispatch<uint16_t, F_BIAS | F_ACT>(C, N.C[l + 1], 27, h.lv[l + 1].n_n, S.pool[l], S.a[l], wm(N.Wp[l]),
+                                              W + N.bp[l], nullptr, 1.f, S.h[l + 1], s);
   }
   for (int l = L - 2; l >= 0; --l) {
     const int n = h.lv[l].n_n, C = N.C[l];
     const uint16_t* dn = l + 1 == L - 1 ? S.a[L - 1] : S.d[l + 1];
-    gconv_dispatch<uint16_t, uint16_t, F_BIAS | F_SKIP | F_ACT>(N.C[l + 1], C, 27, n, S.unpool[l], dn, W + N.Wu[l],
-                                                                W + N.bu[l], S.a[l], 1.f, S.t[l], s);
-    gconv_dispatch<uint16_t, uint16_t, F_BIAS | F_ACT>(C, C, 27, n, S.conv[l], S.t[l], W + N.Wd[l], W + N.bd[l],
-                                                       nullptr, 1.f, S.d[l], s);
-    gconv_dispatch<uint16_t, uint16_t, F_BIAS | F_ACT>(C, N.H, 1, n, nullptr, S.d[l], W + N.W1[l], W + N.b1[l],
-                                                       nullptr, 1.f, S.z1[l], s);
-    gconv_dispatch<uint16_t, uint16_t, F_BIAS | F_ACT>(N.H, N.H, 1, n, nullptr, S.z1[l], W + N.W2[l], W + N.b2[l],
-                                                       nullptr, 1.f, S.z2[l], s);
+    mfma_dispatch<uint16_t, F_BIAS | F_SKIP | F_ACT>(N.C[l + 1], C, 27, n, S.unpool[l], dn, wm(N.Wu[l]), W + N.bu[l],
+                                                     S.a[l], 1.f, S.t[l], s);
+    mfma_dispatch<uint16_t, F_BIAS | F_ACT>(C, C, 27, n, S.conv[l], S.t[l], wm(N.Wd[l]), W + N.bd[l], nullptr, 1.f,
+                                            S.d[l], s);
+    mfma_dispatch<uint16_t, F_BIAS | F_ACT>(C, N.H, 1, n, nullptr, S.d[l], wm(N.W1[l]), W + N.b1[l], nullptr, 1.f,
+                                            S.z1[l], s);
+    mfma_dispatch<uint16_t, F_BIAS | F_ACT>(N.H, N.H, 1, n, nullptr, S.z1[l], wm(N.W2[l]), W + N.b2[l], nullptr, 1.f,
+                                            S.z2[l], s);
     if (out[l]) {
-      gconv_dispatch<uint16_t, float, F_BIAS | F_SCALE>(N.H, N.q, 1, n, nullptr, S.z2[l], W + N.W3[l], W + N.b3[l],
-                                                        nullptr, (float)h.N, out[l], s);
+      mfma_dispatch<float, F_BIAS | F_SCALE>(N.H, N.q, 1, n, nullptr, S.z2[l], wm(N.W3[l]), W + N.b3[l], nullptr,
+                                             (float)h.N, out[l], s);
       center_rows(S, out[l], n, N.q, s);
     }
   }
@@ -673,18 +898,18 @@ void nn_backward(Hier& h, const float* const* gout, float* grad, hipStream_t s) 
     hipLaunchKernelGGL(k_scale_copy, dim3(nblk(tq)), dim3(kB), 0, s, tq, gout[l], (float)h.N, S.g2);
     GMT_LAUNCH_CHECK();
     center_rows(S, S.g2, n, q, s);
-    wgrad_dispatch<uint16_t>(H, q, 1, n, nullptr, S.z2[l], S.g2, grad + N.W3[l], s);
-    bgrad_dispatch(q, n, S.g2, grad + N.b3[l], s);
+    wgrad_dispatch<uint16_t>(H, q, 1, n, nullptr, S.z2[l], S.g2, grad + N.W3[l], S.part, s);
+    bgrad_dispatch(q, n, S.g2, grad + N.b3[l], S.part, s);
     transpose_taps(S, W + N.W3[l], 1, H, q, false, s);
     dgrad(S, q, H, 1, n, nullptr, S.g2, S.g0, s);
     act_grad(S.g0, S.z2[l], (size_t)n * H, s);
-    wgrad_dispatch<uint16_t>(H, H, 1, n, nullptr, S.z1[l], S.g0, grad + N.W2[l], s);
-    bgrad_dispatch(H, n, S.g0, grad + N.b2[l], s);
+    wgrad_dispatch<uint16_t>(H, H, 1, n, nullptr, S.z1[l], S.g0, grad + N.W2[l], S.part, s);
+    bgrad_dispatch(H, n, S.g0, grad + N.b2[l], S.part, s);
     transpose_taps(S, W + N.W2[l], 1, H, H, false, s);
     dgrad(S, H, H, 1, n, nullptr, S.g0, S.g1, s);
     act_grad(S.g1, S.z1[l], (size_t)n * H, s);
-    wgrad_dispatch<uint16_t>(C, H, 1, n, nullptr, S.d[l], S.g1, grad + N.W1[l], s);
-    bgrad_dispatch(H, n, S.g1, grad + N.b1[l], s);
+    wgrad_dispatch<uint16_t>(C, H, 1, n, nullptr, S.d[l], S.g1, grad + N.W1[l], S.part, s);
+    bgrad_dispatch(H, n, S.g1, grad + N.b1[l], S.part, s);
     transpose_taps(S, W + N.W1[l], 1, C, H, false, s);
     dgrad(S, H, C, 1, n, nullptr, S.g1, S.g2, s);
     addv(S.gd[l], S.g2, (size_t)n * C, s);
@@ -695,16 +920,16 @@ void nn_backward(Hier& h, const float* const* gout, float* grad, hipStream_t s) 
     const size_t tc = (size_t)n * C;
     GMT_HIP(hipMemcpyAsync(S.g0, S.gd[l], tc * sizeof(float), hipMemcpyDeviceToDevice, s));
     act_grad(S.g0, S.d[l], tc, s);
-    wgrad_dispatch<uint16_t>(C, C, 27, n, S.conv[l], S.t[l], S.g0, grad + N.Wd[l], s);
-    bgrad_dispatch(C, n, S.g0, grad + N.bd[l], s);
+    wgrad_dispatch<uint16_t>(C, C, 27, n, S.conv[l], S.t[l], S.g0, grad + N.Wd[l], S.part, s);
+    bgrad_dispatch(C, n, S.g0, grad + N.bd[l], S.part, s);
     transpose_taps(S, W + N.Wd[l], 27, C, C, true, s);
     dgrad(S, C, C, 27, n, S.conv[l], S.g0, S.g1, s);
     act_grad(S.g1, S.t[l], tc, s);
     // skip path into a_l, bias bu
     GMT_HIP(hipMemcpyAsync(S.ga[l], S.g1, tc * sizeof(float), hipMemcpyDeviceToDevice, s));
-    bgrad_dispatch(C, n, S.g1, grad + N.bu[l], s);
+    bgrad_dispatch(C, n, S.g1, grad + N.bu[l], S.part, s);
     const uint16_t* dn = l + 1 == L - 1 ? S.a[L - 1] : S.d[l + 1];
-    wgrad_dispatch<uint16_t>(Cn, C, 27, n, S.unpool[l], dn, S.g1, grad + N.Wu[l], s);
+    wgrad_dispatch<uint16_t>(Cn, C, 27, n, S.unpool[l], dn, S.g1, grad + N.Wu[l], S.part, s);
     transpose_taps(S, W + N.Wu[l], 27, Cn, C, false, s);
     dgrad(S, C, Cn, 27, nn, S.pool[l], S.g1, S.g2, s);
     addv(S.gd[l + 1], S.g2, (size_t)nn * Cn, s);
@@ -718,24 +943,22 @@ void nn_backward(Hier& h, const float* const* gout, float* grad, hipStream_t s) 
     const size_t tc = (size_t)n * C;
     GMT_HIP(hipMemcpyAsync(S.g0, S.ga[l], tc * sizeof(float), hipMemcpyDeviceToDevice, s));
     act_grad(S.g0, S.a[l], tc, s);
-    wgrad_dispatch<uint16_t>(C, C, 27, n, S.conv[l], S.h[l], S.g0, grad + N.We[l], s);
-    bgrad_dispatch(C, n, S.g0, grad + N.be[l], s);
+    wgrad_dispatch<uint16_t>(C, C, 27, n, S.conv[l], S.h[l], S.g0, grad + N.We[l], S.part, s);
+    bgrad_dispatch(C, n, S.g0, grad + N.be[l], S.part, s);
     transpose_taps(S, W + N.We[l], 27, C, C, true, s);
     dgrad(S, C, C, 27, n, S.conv[l], S.g0, S.g1, s);
     if (l > 0) {
       const int Cp = N.C[l - 1], np = h.lv[l - 1].n_n;
       act_grad(S.g1, S.h[l], tc, s);
-      wgrad_dispatch<uint16_t>(Cp, C, 27, n, S.pool[l - 1], S.a[l - 1], S.g1, grad + N.Wp[l - 1], s);
-      bgrad_dispatch(C, n, S.g1, grad + N.bp[l - 1], s);
+      wgrad_dispatch<uint16_t>(Cp, C, 27, n, S.pool[l - 1], S.a[l - 1], S.g1, grad + N.Wp[l - 1], S.part, s);
+      bgrad_dispatch(C, n, S.g1, grad + N.bp[l - 1], S.part, s);
       transpose_taps(S, W + N.Wp[l - 1], 27, Cp, C, false, s);
       dgrad(S, C, Cp, 27, np, S.unpool[l - 1], S.g1, S.g2, s);
       addv(S.ga[l - 1], S.g2, (size_t)np * Cp, s);
     } else {
       const int n0 = h.lv[0].n_n;
-      unsigned grid = nblk(n0);
-      if (grid > 512) grid = 512;
-      if (C == 16) hipLaunchKernelGGL(k_embed_grad<16>, dim3(grid), dim3(kB), 0, s, n0, h.lv[0].occ8, S.g1, grad + N.E);
-      else if (C == 32) hipLaunchKernelGGL(k_embed_grad<32>, dim3(grid), dim3(kB), 0, s, n0, h.lv[0].occ8, S.g1, grad + N.E);
+      if (C == 16) hipLaunchKernelGGL(k_embed_grad<16>, dim3(256), dim3(kB), 0, s, n0, h.lv[0].occ8, S.g1, grad + N.E);
+      else if (C == 32) hipLaunchKernelGGL(k_embed_grad<32>, dim3(256), dim3(kB), 0, s, n0, h.lv[0].occ8, S.g1, grad + N.E);
       else fail(GMT_E_INVAL, "embedding width %d not instantiated", C);
       GMT_LAUNCH_CHECK();
     }
@@ -751,6 +974,7 @@ int nn_activation(Hier& h, int l, int which, float* out, hipStream_t s) {
   NNState& S = nn_state(h);
   const NetLayout& N = S.nl;
   if (which < 0 || which > 5) fail(GMT_E_INVAL, "activation kind %d outside 0..5", which);
+  if (l >= N.L) fail(GMT_E_INVAL, "level %d is below the network's %d levels", l + 1, N.L);
   if (which >= 2 && l >= N.L - 1) fail(GMT_E_INVAL, "decoder/head activations exist below the coarsest level only");
   const uint16_t* src = which == 0 ? S.h[l] : which == 1 ? S.a[l] : which == 2 ? S.t[l] : which == 3 ? S.d[l]
                         : which == 4 ? S.z1[l] : S.z2[l];

@@ -22,7 +22,7 @@ import numpy as np
 import torch
 
 from . import binding as B
-from .learned import channels_for, load_weights
+from .learned import channels_for, injection, load_weights
 
 
 def _sync_time(fn):
@@ -42,7 +42,6 @@ def one_cycle_residual(H, f32, u0, e=None):
 def compare(H: B.Hierarchy, params, tol=1e-5, max_iter=3000, reference=True):
     f64 = H.load_vector()
     f32 = f64.to(torch.float32)
-    L = H.L
     rec = {"n_n": H.n_n(1)}
     # plain GMG-PCG from zero
     (u_plain, rep), t = _sync_time(lambda: H.solve(f64, tol=tol, precision="f32", max_iter=max_iter))
@@ -52,7 +51,7 @@ def compare(H: B.Hierarchy, params, tol=1e-5, max_iter=3000, reference=True):
     def learned():
         preds = H.nn_forward(params)
         u = preds[0]
-        H.vcycle(f32, u, e_init=[None] + list(preds[1:]) + [None])
+        H.vcycle(f32, u, e_init=injection(H, preds))
         return H.solve(f64, u=u.to(torch.float64), tol=tol, precision="f32", max_iter=max_iter)
 
     (u_learn, rep_l), t = _sync_time(learned)
@@ -67,7 +66,7 @@ def compare(H: B.Hierarchy, params, tol=1e-5, max_iter=3000, reference=True):
     rel = lambda u: float(np.max(H.relative_residual(f64, u.to(torch.float64))))  # noqa: E731
     rec["abl_zero_init"] = rel(one_cycle_residual(H, f32, zero))
     rec["abl_u_only"] = rel(one_cycle_residual(H, f32, preds[0]))
-    rec["abl_u_and_e"] = rel(one_cycle_residual(H, f32, preds[0], [None] + list(preds[1:]) + [None]))
+    rec["abl_u_and_e"] = rel(one_cycle_residual(H, f32, preds[0], injection(H, preds)))
     rec["abl_net_no_cycle"] = rel(preds[0])
     if reference:
         u_ref, _ = H.solve(f64, tol=1e-9, precision="f64", max_iter=max_iter)

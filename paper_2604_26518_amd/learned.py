@@ -94,7 +94,7 @@ class Trainer:
         # per-component mean of u^1 (the residual does not see rigid translations)
         loss, rn, rel, _, grads = H.vcycle_loss(preds, lam=self.lam / float(H.n_n(1)) ** 2)
         self.grad.zero_()  # memory fill
-        H.nn_backward(grads + [None] * (H.L - 1 - len(grads)), self.grad)
+        H.nn_backward(grads, self.grad)
         gn = math.sqrt(B.norm2(self.grad))
         scale = min(1.0, self.clip / gn) if gn > 0 and math.isfinite(gn) else 0.0
         self.step += 1
@@ -123,14 +123,24 @@ def load_weights(path, device="cuda"):
     return flat, info
 
 
+def injection(H: B.Hierarchy, preds, inject=True):
+    """The e_init list of a cycle (one entry per hierarchy level) from the network's predictions
+    [u_hat^1, e_hat^2, ..., e_hat^{L'-1}]: no entry for level 1 (u_hat^1 is the iterate) nor for
+    the levels at and below the network's coarsest, L' (there the cycle starts from zero)."""
+    e = [None] * H.L
+    if inject:
+        for l, p in enumerate(preds[1:], start=2):
+            e[l - 1] = p
+    return e
+
+
 def learned_solve(H: B.Hierarchy, params, tol=1e-5, inject=True, max_iter=3000, f64=None):
     """u_hat -> one Alg. 2 V-cycle -> FP64 check -> warm GMG-PCG fallback. Returns (u, info)."""
     f64 = H.load_vector() if f64 is None else f64
     f32 = f64.to(torch.float32)
     preds = H.nn_forward(params)
     u = preds[0]
-    e = [None] + (list(preds[1:]) if inject else [None] * (H.L - 2)) + [None]
-    H.vcycle(f32, u, e_init=e)
+    H.vcycle(f32, u, e_init=injection(H, preds, inject))
     u64 = u.to(torch.float64)
     u64, rep = H.solve(f64, u=u64, tol=tol, precision="f32", max_iter=max_iter)
     return u64, {"rel_after_vcycle": max(rep["rel_res_init"]), "iterations": rep["iterations"],

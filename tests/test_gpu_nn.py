@@ -196,6 +196,31 @@ def test_backward_accumulates(setup):
     assert torch.allclose(grad, 2 * once, rtol=1e-5, atol=1e-6)
 
 
+def test_forward_and_gradients_deterministic():
+    """Outputs and every gradient (weights, biases, embedding: fixed-order partial sums,
+    no float atomics) are identical bit for bit over repeated runs on the same cell."""
+    vox = gyroid_sheet(32, 3, 0.3)
+    H = _gmt().Hierarchy(vox, 4)
+    H.nn_setup([16, 32, 64, 64])
+    from paper_2604_26518_amd.learned import init_params
+    flat = init_params(H.n_params, 4, seed=2) + 0.01
+    rng = np.random.default_rng(1)
+    runs = []
+    for _ in range(2):
+        outs = H.nn_forward(flat)
+        gouts = [_t(rng.standard_normal(tuple(o.shape))) for o in outs]
+        rng = np.random.default_rng(1)
+        grad = torch.zeros_like(flat)
+        H.nn_backward(gouts, grad)
+        runs.append(([o.clone() for o in outs], grad.clone()))
+    (o1, g1), (o2, g2) = runs
+    for a, b in zip(o1, o2):
+        assert torch.equal(a, b)
+    assert torch.equal(g1, g2)
+    assert float(g1.abs().sum()) > 0
+    H.close()
+
+
 def test_vcycle_loss_matches_oracle_and_gradient(setup):
     vox, H, net, g, flat = setup
     P = osolve.Problem(vox, H.L)
