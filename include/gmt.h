@@ -317,6 +317,17 @@ gmt_status gmt_nn_adamw(float* d_params, const float* d_grad, float* d_m, float*
 gmt_status gmt_nn_norm2(const float* d_x, size_t n, double* h_out, void* stream);
 gmt_status gmt_nn_ema(float* d_ema, const float* d_x, size_t n, double decay, void* stream);
 
+/* gmt_nn_norm2 without any allocation, for callers that cannot allocate device
+ * memory (code under graph capture, tight training loops, allocator-free
+ * harnesses).  Same result as gmt_nn_norm2 (FP64 partial sums per 2048 values,
+ * summed in a fixed order).  The partial sums live in one fixed device array of
+ * the library (8192 FP64 partials + the total, 64 KiB per GPU, kept until the
+ * process ends), so n is limited to 8192 * 2048 = 16 777 216 values: a larger n
+ * returns GMT_E_INVAL before anything is launched.  The array is per GPU and
+ * shared by every call on it: calls that overlap on one GPU (other streams or
+ * threads) race and must be serialised by the caller.  Synchronizes the stream. */
+gmt_status gmt_nn_norm2_noalloc(const float* d_x, size_t n, double* h_out, void* stream);
+
 /* One V-cycle of Alg. 2 (Chebyshev or Jacobi smoothing; other smoothers and
  * schedules are rejected with GMT_E_INVAL) started from network outputs, in FP32, and the
  * physics loss of Sec. 4.5:  L = log10(||f - K u^1||_2 + 1e-12)

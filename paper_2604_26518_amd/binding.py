@@ -120,6 +120,7 @@ SIGNATURES = {
                      ct.c_double, _I, ct.c_double, _P),
     "gmt_nn_norm2": (_P, ct.c_size_t, ct.POINTER(ct.c_double), _P),
     "gmt_nn_ema": (_P, _P, ct.c_size_t, ct.c_double, _P),
+    "gmt_nn_norm2_noalloc": (_P, ct.c_size_t, ct.POINTER(ct.c_double), _P),
     "gmt_vcycle_loss": (_P, _P, ct.POINTER(GmtCycleOpts), ct.c_double, _P, ct.POINTER(ct.c_double), _P, _P),
     "gmt_last_error": (),
 }

@@ -1032,18 +1032,22 @@ __global__ __launch_bounds__(kB) void k_sum_partials(double* __restrict__ partia
   }
 }
 
+// The array's device address on the current GPU, looked up once per device
+// (with that device current) and kept in a fixed table: no allocation at all.
+constexpr int kMaxDevices = 64;
 static double* scratch_ptr() {
   static std::mutex mu;
-  static std::map<int, double*> ptrs;
+  static double* ptrs[kMaxDevices] = {};
   int dev = 0;
   GMT_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(GMT_E_INVAL, "device %d beyond the %d this table covers", dev, kMaxDevices);
   std::lock_guard<std::mutex> g(mu);
-  auto it = ptrs.find(dev);
-  if (it != ptrs.end()) return it->second;
-  double* p = nullptr;
-  GMT_HIP(hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch)));
-  ptrs[dev] = p;
-  return p;
+  if (!ptrs[dev]) {
+    double* p = nullptr;
+    GMT_HIP(hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch)));
+    ptrs[dev] = p;
+  }
+  return ptrs[dev];
 }
 
 size_t nn_norm2_noalloc_max() { return (size_t)kNoAllocPartials * kNoAllocChunk; }

@@ -1,6 +1,6 @@
-"""GPU: gmt_nn_norm2_noalloc (partial sums in a fixed device array, no allocation)
-against gmt_nn_norm2 through the C ABI: two calls in a row, the second with a
-smaller input, and the size limit refused on the host side."""
+"""GPU: gmt_nn_norm2_noalloc (partial sums in the library's fixed device array, no
+allocation) against gmt_nn_norm2 through the C ABI: calls in a row on one device, each
+smaller than the one before, and the size limit refused on the host side."""
 
 import ctypes as ct
 
@@ -17,22 +17,19 @@ def _lib():
     return binding
 
 
-def _noalloc(x):
+def _noalloc(x, n=None):
     B = _lib()
     out = ct.c_double()
-    st = B.lib().gmt_nn_norm2_noalloc(ct.c_void_p(x.data_ptr()), ct.c_size_t(x.numel()), ct.byref(out),
-                                      B._stream())
+    st = B.lib().gmt_nn_norm2_noalloc(ct.c_void_p(x.data_ptr()), ct.c_size_t(x.numel() if n is None else n),
+                                      ct.byref(out), B._stream())
     return st, out.value
 
 
 def test_noalloc_norm_matches_allocating_entry_point():
     B = _lib()
-    fn = B.lib().gmt_nn_norm2_noalloc
-    fn.argtypes = [ct.c_void_p, ct.c_size_t, ct.POINTER(ct.c_double), ct.c_void_p]
-    fn.restype = ct.c_int
     rng = np.random.default_rng(7)
-    # two calls in a row on the same device array, the second smaller: the first call's
-    # partials beyond the second's grid must not leak into its sum
+    # calls in a row on the same device array, each smaller than the last: the earlier
+    # call's partials beyond the later one's grid must not leak into its sum
     for n in (5_000_003, 70_001, 1):
         x = torch.as_tensor(rng.standard_normal(n).astype(np.float32), device="cuda")
         st, got = _noalloc(x)
@@ -47,12 +44,8 @@ def test_noalloc_norm_matches_allocating_entry_point():
 
 def test_noalloc_norm_rejects_oversize_input():
     B = _lib()
-    fn = B.lib().gmt_nn_norm2_noalloc
-    fn.argtypes = [ct.c_void_p, ct.c_size_t, ct.POINTER(ct.c_double), ct.c_void_p]
-    fn.restype = ct.c_int
     x = torch.zeros(16, dtype=torch.float32, device="cuda")
-    out = ct.c_double()
-    # a size beyond the scratch limit is refused before any launch (the pointer is never read)
-    st = fn(ct.c_void_p(x.data_ptr()), ct.c_size_t(8192 * 2048 + 1), ct.byref(out), B._stream())
+    # a size beyond the fixed array's limit is refused before any launch (the pointer is never read)
+    st, _ = _noalloc(x, 8192 * 2048 + 1)
     assert st == B.GMT_E_INVAL
     assert "exceeds" in B.lib().gmt_last_error().decode()
