@@ -1,28 +1,34 @@
 """Benchmark of the periodic GMG homogenization path on one MI355X.
 
-Workload (one "step"): a batch of 64 elasticity cells at 128^3 from the mixed
-lattice families (gyroid / Schwarz-P / diamond sheets, periodic truss,
-spinodal; family = seed mod 5, VF ~ U(0.15, 0.5), seeds 1000..1063).  Every
-cell goes through the whole path: sparse hierarchy + Galerkin operators +
-coarse factor, load vector, mixed-precision GMG-PCG (FP32 bulk, FP64
-refinement) to relative residual 1e-5 -- all cells in one batched call
-(gmt_solve_batch) -- and the FP64 C_H reduction.
+Default workload (one "step" = one cell through the whole path): a single
+512^3 gyroid-sheet elasticity cell (seed 30001, VF 0.25, 6 load cases, L = 8
+levels) homogenized to relative residual 1e-5 by the learned path --
+hierarchy + Galerkin operators + coarse factor, load vector, network feature
+tables, BF16 network forward (u_hat^1, e_hat^l), one Alg. 2 V-cycle, FP64
+residual check, warm-started mixed-precision GMG-PCG fallback (FP32 bulk, FP64
+refinement), FP64 C_H.  The plain path (zero-init GMG-PCG, same kernels) is
+timed on the same cell for the comparison the metric names.
 
-Prints one JSON line: metric, value (ms per cell, whole path), ms_per_step, the
-batch config, solve-only time, DOF-solves/s, PCG iteration counts; "roofline" for
-the level-1 Chebyshev sweep (372 algorithmic bytes per node over its duration,
-timed with HIP events on the launch stream, against 8 TB/s; "traffic" is the
-counter-measured HBM bytes per sweep of the cell and variant it was measured on,
-else null); "learned" (plain vs learned initializer on the same cells) when the
-weights exist; "cpu_baseline" (the CPU oracle on a 64^3 sample, scaled by nodes).
+Prints one JSON line: metric, value (ms per cell, learned path, whole path),
+the plain path's time and the gain, DOF-solves/s, C_H of both paths against an
+FP64 solve, "roofline" for the level-1 Chebyshev sweep on this cell (372
+algorithmic bytes per node over its duration, timed with HIP events on the
+launch stream, against 8 TB/s), "extras" (the 512^3 spinodal, seed 30000, once
+per path; the mixed-precision versus all-FP64 batch of 64 cells at 128^3), and
+"cpu_baseline" (the CPU FP64 oracle on a bounded sample, scaled to this cell).
+
+Other workloads: --workload cells128 (the 64-cell 128^3 batch, plain path) and
+--workload uneven (256 cells of mixed size and physics).
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import multiprocessing as mp
 import os
+import platform
 import sys
 import time
 
@@ -37,14 +43,11 @@ HBM_PEAK_GBS = 8000.0
 # read u 72 + f 72 + D^-1 12 + d 72, write u' 72 + d 72
 CHEB_BYTES_PER_NODE = 372
 COPY_BYTES = 512 << 20
-# HBM bytes of one level-1 Chebyshev sweep on the first bench cell (seed 1000, 128^3), from the
-# FETCH_SIZE / write-request counters of the interior + boundary kernels, each scaled by what the
-# counter reports for a copy of known size (profiles/level1_chebyshev_sweep_gyroid128_hbm_traffic.txt).
-# It describes the kernels as they were profiled; re-profile after changing them.
-# Keyed by (cell seed, level-1 sweep variant), so that a figure is reported only for the kernels
-# it was measured on.
-SWEEP_TRAFFIC_BYTES = {(1000, 7): 482_315_397}
-# level-1 sweep variants (the autotuner's choice) and the kernels each launches
+# HBM bytes of one level-1 Chebyshev sweep, from the FETCH_SIZE / WRITE_SIZE counters of its two
+# kernels, each scaled by what the counter reports for a copy of known size; keyed by (workload,
+# sweep variant, SHA-256 prefix of the kernel source the counters were taken on), so that a changed
+# kernel reports null until it is profiled again.
+SWEEP_TRAFFIC_BYTES = {}
 SWEEP_KERNELS = {
     0: "k_apply_interior_nc + k_apply_boundary_st",
     1: "k_apply_interior + k_apply_boundary",
@@ -55,6 +58,23 @@ SWEEP_KERNELS = {
     7: "k_apply_interior<PRE=1> + k_apply_boundary_cls<PRE=1>",
 }
 WEIGHTS = os.path.join(ROOT, "paper_2604_26518_amd", "weights", "unet128_elastic.npz")
+HEADLINE = {"family": "gyroid", "N": 512, "seed": 30001, "vf": 0.25}
+SPINODAL = {"family": "spinodal", "N": 512, "seed": 30000, "vf": 0.25}
+UNEVEN_SIZES = (64, 96, 128, 192, 256)
+
+
+def kernel_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_2604_26518_amd", "csrc", "kernels.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+# --------------------------------------------------------------------------- host-side inputs
+# Every input is generated in worker processes forked before the first GPU call (a process that
+# has initialised HIP must not fork); pools are closed and joined, never terminated.
+
+def _gen_named(spec):
+    from gmt_inputs import cell
+    return cell(spec["family"], spec["N"], spec["seed"], spec["vf"])
 
 
 def _gen(seed_n):
@@ -64,15 +84,6 @@ def _gen(seed_n):
     return seed, fam, vf, vox
 
 
-def make_cells(N, seeds):
-    procs = max(1, min(16, os.cpu_count() or 1))
-    with mp.get_context("fork").Pool(procs) as pool:
-        return pool.map(_gen, [(s, N) for s in seeds])
-
-
-UNEVEN_SIZES = (64, 96, 128, 192, 256)
-
-
 def _gen_uneven(seed):
     from gmt_inputs.lattices import workload_cell
     N = UNEVEN_SIZES[(seed // 5) % 5]  # independent of the family (seed mod 5)
@@ -80,25 +91,389 @@ def _gen_uneven(seed):
     return seed, fam, vf, vox, ("elastic" if seed % 2 == 0 else "thermal")
 
 
-def uneven_batch(args):
-    """The uneven batched workload: 256 cells, N uniform over {64, 96, 128, 192, 256}, mixed
-    families, even seeds elastic (6 cases) and odd seeds thermal (3 cases), FP32 bulk + FP64
-    refinement to 1e-5.  Cells go to gmt_solve_batch in chunks that fit a memory budget."""
+def _pool(procs=16):
+    return mp.get_context("fork").Pool(max(1, min(procs, os.cpu_count() or 1)))
+
+
+def _finish(pool):
+    pool.close()
+    pool.join()
+
+
+def cpu_info():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline_sample(tol):
+    """The CPU FP64 oracle as it stands (numpy, matrix-free GMG-PCG, zero start) on a bounded
+    sample of the headline workload: the same gyroid-sheet family, seed and VF at 64^3, solved
+    to tol (hierarchy setup and solve timed separately), plus C_H."""
+    from gmt_inputs import gyroid_sheet
+    from oracle import solve as osolve
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:  # noqa: BLE001
+        blas = None
+    vox = gyroid_sheet(64, HEADLINE["seed"], HEADLINE["vf"])
+    w0, c0 = time.perf_counter(), time.process_time()
+    P = osolve.Problem(vox, 4)
+    w1 = time.perf_counter()
+    u, its = osolve.pcg(P, tol=tol)
+    w2 = time.perf_counter()
+    osolve.homogenize(P, u)
+    w3 = time.perf_counter()
+    cpu = time.process_time() - c0
+    return {"setup_s": w1 - w0, "solve_s": w2 - w1, "ch_s": w3 - w2, "wall_s": w3 - w0,
+            "threads": max(1, round(cpu / (w3 - w0))), "blas_threads": blas, "n_n": int(P.levels[0].n_n),
+            "iterations": int(its), **cpu_info()}
+
+
+# --------------------------------------------------------------------------- GPU legs
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def learned_cell(B, vox, levels, params, net_levels, tol, max_iter):
+    """Whole learned path on one cell; returns timings (s) and the solve record."""
+    from paper_2604_26518_amd.learned import channels_for, learned_solve
+    _sync()
+    t0 = time.perf_counter()
+    H = B.Hierarchy(vox, levels, "elastic")
+    H.nn_setup(channels_for(net_levels))
+    f = H.load_vector()
+    _sync()
+    t1 = time.perf_counter()
+    u, info = learned_solve(H, params, tol=tol, max_iter=max_iter, f64=f)
+    CH = H.homogenize(u)
+    _sync()
+    t2 = time.perf_counter()
+    rec = {"whole_s": t2 - t0, "solve_s": t2 - t1, "n_n": H.n_n(1), "CH": CH, **info}
+    return H, u, rec
+
+
+def plain_cell(B, vox, levels, tol, max_iter):
+    _sync()
+    t0 = time.perf_counter()
+    H = B.Hierarchy(vox, levels, "elastic")
+    f = H.load_vector()
+    _sync()
+    t1 = time.perf_counter()
+    u, rep = H.solve(f, tol=tol, precision="f32", max_iter=max_iter)
+    CH = H.homogenize(u)
+    _sync()
+    t2 = time.perf_counter()
+    if not rep["converged"]:
+        raise RuntimeError(f"plain path did not converge: {rep}")
+    rec = {"whole_s": t2 - t0, "solve_s": t2 - t1, "n_n": H.n_n(1), "CH": CH, "iterations": rep["iterations"],
+           "rel_res": max(rep["rel_res"])}
+    return H, u, rec
+
+
+def sweep_roofline(B, H, workload):
+    import torch
+    per_launch_s = H.time_sweep(1, reps=20) / 1e3
+    nbytes = CHEB_BYTES_PER_NODE * H.n_n(1)
+    achieved = nbytes / per_launch_s / 1e9
+    variant = H.level_info(1)["sweep_variant"][0]
+    src = kernel_source_hash()
+    traffic = SWEEP_TRAFFIC_BYTES.get((workload, variant, src))
+    # plain device copy of known size: what HBM sustains here, and the calibration run of the counters
+    src_t = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst_t = torch.empty_like(src_t)
+    dst_t.copy_(src_t)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        dst_t.copy_(src_t)
+    e1.record()
+    e1.synchronize()
+    copy_gbs = 2 * COPY_BYTES * 20 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "level-1 Chebyshev sweep", "n_n": H.n_n(1), "algorithmic_bytes": nbytes,
+            "us_per_sweep": round(per_launch_s * 1e6, 2), "variant": variant,
+            "kernels": SWEEP_KERNELS.get(variant, "?") + " (float, 3 DOF, EPI_CHEB)", "kernel_source": src,
+            "copy_GBps": round(copy_gbs, 1)}
+
+
+def mixed_vs_fp64(B, cells, levels, tol, max_iter, workers):
+    """C_H and time of the mixed-precision batch against the all-FP64 batch on the same cells."""
+    import torch
+    vox_dev = [torch.from_numpy(v).cuda() for (_, _, _, v) in cells]
+    out = {}
+    CHs = {}
+    for prec in ("f32", "f64"):
+        hs = [B.Hierarchy(v, levels, "elastic") for v in vox_dev]
+        fs = [H.load_vector() for H in hs]
+        _sync()
+        t = time.perf_counter()
+        us, reps = B.solve_batch(hs, fs, tol=tol, precision=prec, max_iter=max_iter, n_workers=workers,
+                                 raise_on_noconv=False)
+        _sync()
+        dt = time.perf_counter() - t
+        CHs[prec] = [H.homogenize(u) for H, u in zip(hs, us)]
+        out[prec] = {"ms_per_cell_solve_only": round(dt / len(hs) * 1e3, 2),
+                     "iterations_mean": float(np.mean([r["iterations"] for r in reps])),
+                     "converged": int(sum(bool(r["converged"]) for r in reps)),
+                     "max_rel_res": float(max(max(r["rel_res"]) for r in reps))}
+        for H in hs:
+            H.close()
+        del us, fs
+    err = [np.linalg.norm(a - b) / np.linalg.norm(b) for a, b in zip(CHs["f32"], CHs["f64"])]
+    out["CH_mixed_vs_fp64_max"] = float(max(err))
+    out["speedup_mixed_over_fp64"] = round(out["f64"]["ms_per_cell_solve_only"] /
+                                           out["f32"]["ms_per_cell_solve_only"], 3)
+    out["workload"] = (f"{len(cells)} elasticity cells at 128^3 (seeds {cells[0][0]}..{cells[-1][0]}, mixed "
+                       f"families, VF U(0.15,0.5)), batched GMG-PCG to {tol:g}, mixed (FP32 bulk + FP64 "
+                       f"refinement) vs all-FP64")
+    return out
+
+
+def cell512(args):
+    import torch
+
+    from paper_2604_26518_amd import binding as B
+    from paper_2604_26518_amd.learned import load_weights
+
+    t0 = time.perf_counter()
+    pool = _pool()
+    jobs = {"gyroid": pool.apply_async(_gen_named, (dict(HEADLINE, N=args.N),))}
+    if args.extras:
+        jobs["spinodal"] = pool.apply_async(_gen_named, (dict(SPINODAL, N=args.N),))
+        jobs["c2"] = pool.map_async(_gen, [(s, 128) for s in range(1000, 1000 + args.c2_cells)])
+    if not args.no_cpu_baseline:
+        jobs["cpu"] = pool.apply_async(cpu_baseline_sample, (args.tol,))
+    res = {k: j.get() for k, j in jobs.items()}
+    _finish(pool)
+    print(f"# inputs generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    levels = B.default_levels(args.N)
+    params, info = load_weights(WEIGHTS)
+    net_levels = min(info["levels"], levels)
+    vox = torch.from_numpy(res["gyroid"]).cuda()
+
+    def lstep():
+        H, u, rec = learned_cell(B, vox, levels, params, net_levels, args.tol, args.max_iter)
+        H.close()
+        return rec
+
+    def pstep():
+        H, u, rec = plain_cell(B, vox, levels, args.tol, args.max_iter)
+        H.close()
+        return rec
+
+    for w in range(args.warmup):
+        lstep()
+        pstep()
+        print(f"# warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    # timed region: K steps of the learned path
+    _sync()
+    t = time.perf_counter()
+    lrecs = []
+    for k in range(args.steps):
+        lrecs.append(lstep())
+        print(f"# learned step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    _sync()
+    wall = time.perf_counter() - t
+    # the comparison: K steps of the plain path on the same cell
+    _sync()
+    t = time.perf_counter()
+    precs = []
+    for k in range(args.steps):
+        precs.append(pstep())
+    _sync()
+    wall_plain = time.perf_counter() - t
+    print("# plain steps done", file=sys.stderr, flush=True)
+
+    # C_H of both paths against an FP64 solve to 1e-9 on the same hierarchy
+    H = B.Hierarchy(vox, levels, "elastic")
+    f = H.load_vector()
+    u64, rep64 = H.solve(f, tol=1e-9, precision="f64", max_iter=args.max_iter)
+    C_ref = H.homogenize(u64)
+    nref = np.linalg.norm(C_ref)
+    err_l = float(np.linalg.norm(lrecs[0]["CH"] - C_ref) / nref)
+    err_p = float(np.linalg.norm(precs[0]["CH"] - C_ref) / nref)
+    del u64
+    # network time alone, and the dominant kernel's roofline on this cell
+    from paper_2604_26518_amd.learned import channels_for
+    H.nn_setup(channels_for(net_levels))
+    H.nn_forward(params)
+    _sync()
+    t = time.perf_counter()
+    for _ in range(5):
+        H.nn_forward(params)
+    _sync()
+    net_ms = (time.perf_counter() - t) / 5 * 1e3
+    roof = sweep_roofline(B, H, f"gyroid512_seed{HEADLINE['seed']}")
+    H.close()
+
+    n_n = lrecs[0]["n_n"]
+    ms_l = wall / args.steps * 1e3
+    ms_p = wall_plain / args.steps * 1e3
+    out = {
+        "metric": METRIC,
+        "value": round(ms_l, 2),
+        "unit": "ms/cell",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_l, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"one {args.N}^3 gyroid-sheet elasticity cell (seed {HEADLINE['seed']}, VF "
+                               f"{HEADLINE['vf']}, 6 load cases, L={levels}): learned init (BF16 U-Net on levels "
+                               f"1..{net_levels}) + one V-cycle + warm mixed-precision GMG-PCG fallback to "
+                               f"{args.tol:g}, whole path incl. hierarchy build, network tables and C_H",
+                   "N": args.N, "levels": levels, "net_levels": net_levels, "tol": args.tol,
+                   "n_n": n_n, "dof": 18 * n_n},
+        "dof_solves_per_s": round(18 * n_n / (ms_l / 1e3), 1),
+        "ms_per_cell_solve_only": round(float(np.mean([r["solve_s"] for r in lrecs])) * 1e3, 2),
+        "plain": {"ms_per_cell": round(ms_p, 2),
+                  "ms_per_cell_solve_only": round(float(np.mean([r["solve_s"] for r in precs])) * 1e3, 2),
+                  "iterations": precs[0]["iterations"], "dof_solves_per_s": round(18 * n_n / (ms_p / 1e3), 1)},
+        "gain_plain_over_learned": round(ms_p / ms_l, 4),
+        "learned": {"rel_after_vcycle": lrecs[0]["rel_after_vcycle"], "fallback": lrecs[0]["fallback"],
+                    "fallback_iterations": lrecs[0]["iterations"], "net_ms": round(net_ms, 2),
+                    "weights": {"file": os.path.relpath(WEIGHTS, ROOT), "trained_N": info["N"],
+                                "trained_levels": info["levels"], "train_steps": info.get("step")}},
+        "CH_rel_err_vs_fp64": {"learned": err_l, "plain": err_p, "fp64_tol": 1e-9,
+                               "fp64_iterations": rep64["iterations"]},
+        "roofline": roof,
+    }
+    if args.extras:
+        sv = torch.from_numpy(res["spinodal"]).cuda()
+        Hl, _, rl = learned_cell(B, sv, levels, params, net_levels, args.tol, args.max_iter)
+        Hl.close()
+        Hp, _, rp = plain_cell(B, sv, levels, args.tol, args.max_iter)
+        Hp.close()
+        out["extras"] = {"spinodal512": {
+            "seed": SPINODAL["seed"], "vf": float(res["spinodal"].mean()), "n_n": rl["n_n"],
+            "learned_ms": round(rl["whole_s"] * 1e3, 1), "plain_ms": round(rp["whole_s"] * 1e3, 1),
+            "learned_fallback_iterations": rl["iterations"], "plain_iterations": rp["iterations"],
+            "rel_after_vcycle": rl["rel_after_vcycle"],
+            "CH_learned_vs_plain": float(np.linalg.norm(rl["CH"] - rp["CH"]) / np.linalg.norm(rp["CH"]))}}
+        del sv
+        print("# spinodal done", file=sys.stderr, flush=True)
+        out["extras"]["mixed_vs_fp64_128"] = mixed_vs_fp64(B, res["c2"], B.default_levels(128), args.tol,
+                                                           args.max_iter, args.workers)
+        print("# mixed vs FP64 batch done", file=sys.stderr, flush=True)
+    if "cpu" in res:
+        cb = res["cpu"]
+        scale = n_n / cb["n_n"]
+        its512 = precs[0]["iterations"]
+        est_s = (cb["setup_s"] + cb["ch_s"]) * scale + cb["solve_s"] / max(cb["iterations"], 1) * its512 * scale
+        out["cpu_baseline"] = {
+            "value": round(est_s * 1e3, 1), "unit": "ms/cell", "cores": cb["threads"], "kind": "oracle",
+            "sample": (f"numpy FP64 oracle GMG-PCG (zero start, tol {args.tol:g}) + C_H on the same gyroid "
+                       f"(seed {HEADLINE['seed']}, VF {HEADLINE['vf']}) at 64^3: setup {cb['setup_s']:.1f} s, "
+                       f"{cb['iterations']} iterations in {cb['solve_s']:.1f} s, C_H {cb['ch_s']:.1f} s, "
+                       f"{cb['n_n']} nodes; scaled per node by {scale:.1f} to the {args.N}^3 cell and per "
+                       f"iteration to the {its512} iterations the plain path takes there"),
+            "nproc": cb["nproc"], "cpu_model": cb["cpu_model"], "blas_threads": cb["blas_threads"]}
+    print(json.dumps(out), flush=True)
+
+
+def cells128(args):
+    """The 64-cell 128^3 batch (plain path): hierarchies, loads, one batched mixed-precision solve
+    (worker threads x streams, captured-graph PCG blocks), C_H per cell."""
+    import torch
+
+    from paper_2604_26518_amd import binding as B
+
+    t0 = time.perf_counter()
+    pool = _pool()
+    cells = pool.map(_gen, [(s, args.N) for s in range(args.seed0, args.seed0 + args.cells)])
+    _finish(pool)
+    gen_s = time.perf_counter() - t0
+    torch.cuda.set_device(0)
+    vox_dev = [torch.from_numpy(v).cuda() for (_, _, _, v) in cells]
+    levels = B.default_levels(args.N)
+    print(f"# generated {len(cells)} cells at {args.N}^3 in {gen_s:.1f} s; levels={levels}", file=sys.stderr,
+          flush=True)
+
+    def step():
+        hs = [B.Hierarchy(vox, levels, "elastic") for vox in vox_dev]
+        fs = [H.load_vector() for H in hs]
+        _sync()
+        ts = time.perf_counter()
+        us, reps = B.solve_batch(hs, fs, tol=args.tol, precision="f32", max_iter=args.max_iter,
+                                 n_workers=args.workers, graph=not args.no_graph, raise_on_noconv=False)
+        solve_s = time.perf_counter() - ts
+        dofs, its = 0, []
+        for k, (H, u, rep) in enumerate(zip(hs, us, reps)):
+            H.homogenize(u)
+            if not rep["converged"]:
+                raise RuntimeError(f"cell {k} did not converge: {rep}")
+            dofs += H.n_n(1) * 18
+            its.append(rep["iterations"])
+        for H in hs:
+            H.close()
+        return solve_s, dofs, its
+
+    for w in range(args.warmup):
+        step()
+    _sync()
+    t0 = time.perf_counter()
+    solve_total, dofs, its_all = 0.0, 0, []
+    for k in range(args.steps):
+        s, d, its = step()
+        solve_total, dofs, its_all = solve_total + s, dofs + d, its_all + its
+        print(f"# step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    _sync()
+    wall = time.perf_counter() - t0
+    ncell = args.steps * len(vox_dev)
+    H = B.Hierarchy(vox_dev[0], levels, "elastic")
+    roof = sweep_roofline(B, H, f"cell128_seed{args.seed0}")
+    H.close()
+    out = {"metric": "ms per cell, batched plain GMG-PCG to 1e-5 (whole path incl. build and C_H)",
+           "value": round(wall / ncell * 1e3, 3), "unit": "ms/cell", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 2), "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{len(vox_dev)} elasticity cells at {args.N}^3, mixed families, VF U(0.15,0.5), "
+                                  f"plain GMG-PCG (FP32 bulk, FP64 refinement) to {args.tol:g}, batched",
+                      "cells": len(vox_dev), "seed0": args.seed0, "N": args.N, "levels": levels},
+           "ms_per_cell_solve_only": round(solve_total / ncell * 1e3, 3),
+           "dof_solves_per_s": round(dofs / wall, 1), "iterations_mean": float(np.mean(its_all)),
+           "iterations_max": int(np.max(its_all)), "roofline": roof}
+    print(json.dumps(out), flush=True)
+
+
+def uneven(args):
+    """256 cells, N uniform over {64, 96, 128, 192, 256}, mixed families, even seeds elastic (6
+    cases) and odd seeds thermal (3 cases), FP32 bulk + FP64 refinement to 1e-5; cells go to
+    gmt_solve_batch in chunks that fit a memory budget."""
     import torch
 
     from paper_2604_26518_amd import binding as B
 
     seeds = list(range(2000, 2000 + args.cells))
-    procs = max(1, min(16, os.cpu_count() or 1))
     t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(procs) as pool:
-        cells = pool.map(_gen_uneven, seeds, chunksize=2)
+    pool = _pool()
+    cells = pool.map(_gen_uneven, seeds, chunksize=2)
+    _finish(pool)
     print(f"# generated {len(cells)} uneven cells in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.set_device(0)
     budget = args.mem_gb * 2**30
-
     failed = []
 
-    def run(record):
+    def run():
         order = sorted(range(len(cells)), key=lambda k: -cells[k][3].size)
         t_all = time.perf_counter()
         solve_s, dofs, its, k = 0.0, 0, [], 0
@@ -111,7 +486,7 @@ def uneven_batch(args):
                 fs.append(H.load_vector())
                 idx.append(order[k])
                 k += 1
-            torch.cuda.synchronize()
+            _sync()
             ts = time.perf_counter()
             us, reps = B.solve_batch(hs, fs, tol=args.tol, precision="f32", max_iter=args.max_iter,
                                      max_outer=16, n_workers=args.workers, graph=not args.no_graph,
@@ -124,21 +499,17 @@ def uneven_batch(args):
                                    "residual": max(rep["rel_res"]), "iterations": rep["iterations"]})
                 dofs += H.n_n(1) * H.c * H.d
                 its.append(rep["iterations"])
-                if record is not None:
-                    record.append({"seed": cells[j][0], "family": cells[j][1], "vf": cells[j][2], "N": H.N,
-                                   "physics": H.physics, "its": rep["iterations"], "outer": rep["outer"]})
                 H.close()
             del us, fs, hs
             print(f"# {k}/{len(order)} cells done", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
+        _sync()
         return time.perf_counter() - t_all, solve_s, dofs, its
 
-    for w in range(args.warmup):
-        run(None)
-    record = []
+    for _ in range(args.warmup):
+        run()
     wall, solve_s, dofs, its = 0.0, 0.0, 0, []
     for _ in range(args.steps):
-        a, b, c, d = run(record if not record else None)
+        a, b, c, d = run()
         wall, solve_s, dofs, its = wall + a, solve_s + b, dofs + c, its + d
     ncell = args.steps * len(cells)
     out = {"metric": "ms per cell, uneven batched solve to 1e-5 (whole path incl. build and C_H)",
@@ -146,228 +517,50 @@ def uneven_batch(args):
            "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 2), "higher_is_better": False,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{len(cells)} cells, N uniform over {list(UNEVEN_SIZES)}, mixed families, VF "
-                                  f"U(0.15,0.5), half elasticity (6 cases) half heat conduction (3 cases), FP32 "
-                                  f"bulk + FP64 refinement to {args.tol:g}, gmt_solve_batch in memory-bounded "
-                                  f"chunks", "cells": len(cells), "workers": args.workers,
-                      "graph": not args.no_graph},
+                                  f"U(0.15,0.5), half elasticity half heat conduction, FP32 bulk + FP64 "
+                                  f"refinement to {args.tol:g}, gmt_solve_batch in memory-bounded chunks",
+                      "cells": len(cells), "workers": args.workers, "graph": not args.no_graph},
            "ms_per_cell_solve_only": round(solve_s / ncell * 1e3, 3),
            "dof_solves_per_s": round(dofs / wall, 1), "iterations_mean": float(np.mean(its)),
            "iterations_max": int(np.max(its)), "not_converged": failed}
     print(json.dumps(out), flush=True)
-    if os.environ.get("GMT_BENCH_CELLS"):
-        with open(os.environ["GMT_BENCH_CELLS"], "w") as fh:
-            json.dump(record, fh, indent=1)
-
-
-def cpu_baseline(tol):
-    """The CPU FP64 oracle on a bounded sample: one 64^3 workload cell, GMG-PCG to tol + C_H."""
-    from gmt_inputs.lattices import workload_cell
-    from oracle import solve as osolve
-
-    fam, vf, vox = workload_cell(64, 1000)
-    w0, c0 = time.perf_counter(), time.process_time()
-    P = osolve.Problem(vox, 5)
-    u, its = osolve.pcg(P, tol=tol)
-    osolve.homogenize(P, u)
-    wall = time.perf_counter() - w0
-    cpu = time.process_time() - c0
-    return {"wall_s": wall, "threads": max(1, round(cpu / wall)), "n_e": int(P.levels[0].n_e),
-            "n_n": int(P.levels[0].n_n), "family": fam, "vf": vf, "iterations": its}
-
-
-def learned_leg(B, vox_dev, levels, args, cells):
-    """The learned path on the same cells: network forward -> one V-cycle -> FP64 check -> warm
-    GMG-PCG fallback, against plain zero-init GMG-PCG, solve-only times (hierarchy built outside)."""
-    import torch
-
-    from paper_2604_26518_amd.evaluate import compare, summarize
-    from paper_2604_26518_amd.learned import channels_for, load_weights
-
-    params, info = load_weights(WEIGHTS)
-    if info["levels"] != levels or info["N"] != args.N:
-        return {"skipped": f"weights are for N={info['N']} L={info['levels']}"}
-    recs = []
-    for k, vox in enumerate(vox_dev):
-        H = B.Hierarchy(vox, levels, "elastic")
-        H.nn_setup(channels_for(levels))
-        if k == 0:
-            compare(H, params, args.tol, reference=False)  # warm-up
-        recs.append(compare(H, params, args.tol, reference=(k < 8)))
-        H.close()
-    torch.cuda.synchronize()
-    s = summarize(recs)
-    s["weights"] = {"file": os.path.relpath(WEIGHTS, ROOT), "train_steps": info.get("step")}
-    s["note"] = "solve-only ms/cell (hierarchy build excluded) for both paths on the bench cells"
-    return s
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cells", type=int, default=64)
-    ap.add_argument("--seed0", type=int, default=1000, help="first cell seed (cells seed0 .. seed0 + cells - 1)")
-    ap.add_argument("--N", type=int, default=128)
+    ap.add_argument("--workload", default="cell512", choices=["cell512", "cells128", "uneven"],
+                    help="cell512: the 512^3 learned-vs-plain headline; cells128: 64 cells at 128^3; uneven: "
+                         "256 cells of mixed size and physics")
+    ap.add_argument("--N", type=int, default=0, help="cell size (cell512: 512, cells128: 128)")
+    ap.add_argument("--cells", type=int, default=0)
+    ap.add_argument("--seed0", type=int, default=1000)
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--max-iter", type=int, default=3000)
+    ap.add_argument("--no-extras", dest="extras", action="store_false",
+                    help="cell512: skip the spinodal cell and the mixed-vs-FP64 128^3 batch")
+    ap.add_argument("--c2-cells", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--workers", type=int, default=4, help="host threads / streams of the batched solve")
     ap.add_argument("--no-graph", action="store_true", help="launch PCG kernel by kernel")
-    ap.add_argument("--workload", default="cells128", choices=["cells128", "uneven"],
-                    help="cells128: the headline 64-cell 128^3 batch; uneven: 256 cells of mixed size and physics")
     ap.add_argument("--mem-gb", type=float, default=120.0, help="uneven workload: GPU memory per solve chunk")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding the "
               "path over several GPUs is not built.", file=sys.stderr)
         sys.exit(2)
-
-    import torch
-
-    from paper_2604_26518_amd import binding as B
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    if args.workload == "uneven":
-        if args.cells == 64:
-            args.cells = 256
-        torch.cuda.set_device(0)
-        uneven_batch(args)
-        return
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-
-    t0 = time.perf_counter()
-    cells = make_cells(args.N, list(range(args.seed0, args.seed0 + args.cells)))
-    gen_s = time.perf_counter() - t0
-    vox_dev = [torch.from_numpy(v).to(dev) for (_, _, _, v) in cells]
-    torch.cuda.synchronize()
-    levels = B.default_levels(args.N)
-    print(f"# generated {len(cells)} cells at {args.N}^3 in {gen_s:.1f} s; levels={levels}",
-          file=sys.stderr, flush=True)
-
-    def step(record=None):
-        """One pass of the path over the batch: hierarchies, loads, one batched mixed-precision
-        solve (worker threads x streams, captured-graph PCG blocks), C_H per cell."""
-        hs = [B.Hierarchy(vox, levels, "elastic") for vox in vox_dev]
-        fs = [H.load_vector() for H in hs]
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        us, reps = B.solve_batch(hs, fs, tol=args.tol, precision="f32", max_iter=args.max_iter,
-                                 n_workers=args.workers, graph=not args.no_graph, raise_on_noconv=False)
-        solve_s = time.perf_counter() - ts
-        dofs = 0
-        its = []
-        for k, (H, u, rep) in enumerate(zip(hs, us, reps)):
-            CH = H.homogenize(u)
-            if not rep["converged"]:
-                raise RuntimeError(f"cell {k} did not converge: {rep}")
-            dofs += H.n_n(1) * 3 * 6
-            its.append(rep["iterations"])
-            if record is not None:
-                record.append({"seed": cells[k][0], "family": cells[k][1], "n_n": H.n_n(1),
-                               "its": rep["iterations"], "outer": rep["outer"],
-                               "res": max(rep["rel_res"]), "C11": float(CH[0, 0])})
-        for H in hs:
-            H.close()
-        del us, fs
-        return solve_s, dofs, its
-
-    for w in range(args.warmup):
-        step()
-        print(f"# warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    solve_total = 0.0
-    dofs = 0
-    its_all = []
-    record = []
-    for k in range(args.steps):
-        s, d, its = step(record if k == 0 else None)
-        solve_total += s
-        dofs += d
-        its_all += its
-        print(f"# step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ncell = args.steps * len(vox_dev)
-    ms_cell = wall / ncell * 1e3
-    ms_cell_solve = solve_total / ncell * 1e3
-
-    # --- dominant kernel: the level-1 Chebyshev sweep (interior + boundary kernels, FP32),
-    # timed with HIP events on the launch stream by the library
-    H = B.Hierarchy(vox_dev[0], levels, "elastic")
-    per_launch_s = H.time_sweep(1, reps=100) / 1e3
-    nbytes = CHEB_BYTES_PER_NODE * H.n_n(1)
-    achieved = nbytes / per_launch_s / 1e9
-    variant = H.level_info(1)["sweep_variant"][0]
-    kernel_info = {"n_n": H.n_n(1), "us_per_sweep": round(per_launch_s * 1e6, 2), "variant": variant,
-                   "kernels": SWEEP_KERNELS.get(variant, "?") + " (float, 3 DOF, EPI_CHEB)"}
-    H.close()
-    # plain device copy of known size: what HBM sustains here, and the calibration run for the
-    # FETCH_SIZE / WRITE_SIZE counters
-    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(20):
-        dst.copy_(src)
-    e1.record()
-    e1.synchronize()
-    copy_gbs = 2 * COPY_BYTES * 20 / (e0.elapsed_time(e1) / 1e3) / 1e9
-    del src, dst
-
-    learned = None
-    if os.path.exists(WEIGHTS) and not args.no_learned:
-        learned = learned_leg(B, vox_dev, levels, args, cells)
-
-    out = {
-        "metric": METRIC,
-        "value": round(ms_cell, 3),
-        "unit": "ms/cell",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(wall / args.steps * 1e3, 2),
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"{len(vox_dev)} elasticity cells at {args.N}^3, mixed TPMS-sheet/truss/"
-                               f"spinodal families, VF U(0.15,0.5), plain GMG-PCG (FP32 bulk, FP64 "
-                               f"refinement) to {args.tol:g}, batched solve, whole path incl. hierarchy "
-                               f"build and C_H",
-                   "cells": len(vox_dev), "seed0": args.seed0, "N": args.N, "levels": levels, "tol": args.tol,
-                   "workers": args.workers, "graph": not args.no_graph},
-        "ms_per_cell_solve_only": round(ms_cell_solve, 3),
-        "dof_solves_per_s": round(dofs / wall, 1),
-        "iterations_mean": float(np.mean(its_all)),
-        "iterations_max": int(np.max(its_all)),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": SWEEP_TRAFFIC_BYTES.get((cells[0][0], variant)) if args.N == 128 else None,
-                     "kernel": "level-1 Chebyshev sweep", **kernel_info,
-                     "copy_GBps": round(copy_gbs, 1)},
-    }
-    if learned is not None:
-        out["learned"] = learned
-    if not args.no_cpu_baseline:
-        cb = cpu_baseline(args.tol)
-        n_n_128 = float(np.mean([r["n_n"] for r in record]))
-        scale = n_n_128 / cb["n_n"]
-        out["cpu_baseline"] = {"value": round(cb["wall_s"] * 1e3 * scale, 1), "unit": "ms/cell", "cores": cb["threads"],
-                               "kind": "oracle",
-                               "sample": f"one 64^3 {cb['family']} cell (VF {cb['vf']:.2f}, seed 1000), oracle "
-                                         f"GMG-PCG to {args.tol:g} + C_H in {cb['wall_s']:.1f} s, scaled by the "
-                                         f"node ratio {scale:.2f} to a mean 128^3 cell"}
-    print(json.dumps(out), flush=True)
-    if os.environ.get("GMT_BENCH_CELLS"):
-        with open(os.environ["GMT_BENCH_CELLS"], "w") as fh:
-            json.dump(record, fh, indent=1)
+    if args.workload == "cell512":
+        args.N = args.N or 512
+        cell512(args)
+    elif args.workload == "cells128":
+        args.N = args.N or 128
+        args.cells = args.cells or 64
+        cells128(args)
+    else:
+        args.cells = args.cells or 256
+        uneven(args)
 
 
 if __name__ == "__main__":
