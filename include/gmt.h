@@ -259,6 +259,59 @@ gmt_status gmt_relative_residual(gmt_hier_t h, const void* d_f, const void* d_u,
 gmt_status gmt_homogenize(gmt_hier_t h, const void* d_u, int32_t dtype, double* h_CH, void* stream);
 
 /* ------------------------------------------------------------------------
+ * SIMP inverse homogenization (App. F.3).  A density field rho (one value per
+ * voxel element, rho_min <= rho <= 1) gives every element the tensor
+ * C_e = (rho_min + rho_e^p) C0 (eq. ch): element matrix s_e K0.  Elements with
+ * rho_e <= prune are left out of the active set (pruning of near-void voxels).
+ * The hierarchy of such a cell is built by gmt_build_density_hierarchy and then
+ * used with every call above (gmt_load_vector gives f = sum_e s_e A_e^T K0 X0,
+ * gmt_homogenize the C_H of the scaled elements, gmt_solve the GMG-PCG with
+ * Galerkin operators of the scaled elements), except the learned initializer
+ * (gmt_nn_setup: binary cells only) and level-1 gmt_export_element_matrices.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  double p;        /* penalization exponent, >= 1 (e.g. 3) */
+  double rho_min;  /* additive stiffness floor, > 0 */
+  double prune;    /* elements with rho <= prune are inactive, 0 <= prune < 1 */
+} gmt_simp_params;
+
+/* d_rho: device FP64 [N^3], x fastest (the voxel order of gmt_build_hierarchy).
+ * params->levels >= 2.  Errors as gmt_build_hierarchy. */
+gmt_status gmt_build_density_hierarchy(const double* d_rho, int32_t N, const gmt_simp_params* sp,
+                                       const gmt_params* params, void* stream, gmt_hier_t* out);
+
+/* Analytic sensitivities (App. F.3) from a solution d_u (device FP64, ABI
+ * layout [n_n][c][d], level 1): with d_e = X0 - u_e and g_e = p rho_e^(p-1) / N^3,
+ * d_dC (device [N^3][c][c] or NULL) receives dC_H[i][j]/drho_e = g_e d_e^(i)T K0 d_e^(j),
+ * d_dJ (device [N^3] or NULL) receives dJ/drho_e = sum_ij h_G[i][j] dC_H[i][j]/drho_e
+ * for host weights h_G = dJ/dC_H (c x c row-major; required with d_dJ).  Both are
+ * dense over the voxel grid, zero for inactive elements.  Synchronizes the stream.
+ * GMT_E_STATE for a binary hierarchy. */
+gmt_status gmt_simp_sensitivity(gmt_hier_t h, const double* d_u, const double* h_G, double* d_dJ, double* d_dC,
+                                void* stream);
+
+/* Objectives of App. F.3 on the compliance S = C_H^-1 (elastic 6x6, host):
+ * GMT_SIMP_YOUNG  J = (S00 + S11 + S22) / 3,  GMT_SIMP_SHEAR  J = (S33 + S44 + S55) / 3,
+ * GMT_SIMP_BULK   J = sum_{i,j < 3} Sij;  h_G = dJ/dC_H = -S^T W S^T (6x6 row-major).
+ * GMT_E_SINGULAR when C_H is singular. */
+typedef enum { GMT_SIMP_YOUNG = 0, GMT_SIMP_SHEAR = 1, GMT_SIMP_BULK = 2 } gmt_simp_objective_kind;
+gmt_status gmt_simp_objective(const double* h_CH, int32_t kind, double* h_J, double* h_G);
+
+/* Sensitivity filter on the dense periodic N^3 grid (device FP64, x fastest):
+ * out_e = sum_f H_ef rho_f dc_f / (max(1e-3, rho_e) sum_f H_ef),
+ * H_ef = max(0, rmin - |x_e - x_f|) over periodic voxel distances, 1 < rmin <= 8.
+ * d_out must not alias the inputs. */
+gmt_status gmt_simp_filter(const double* d_rho, const double* d_dc, int32_t N, double rmin, double* d_out,
+                           void* stream);
+
+/* Optimality-Criteria step with move limits on n densities (device FP64):
+ * rho_new = min(1, rho + move, max(rho_lo, rho - move, rho (max(-dc, 0) / lam)^eta)),
+ * lam found by bisection on [0, 1e9] so that sum(rho_new) = volfrac * n
+ * (h_lambda receives it).  Synchronizes the stream; d_rho_new must not alias. */
+gmt_status gmt_simp_oc(const double* d_rho, const double* d_dc, size_t n, double volfrac, double move, double eta,
+                       double rho_lo, double* d_rho_new, double* h_lambda, void* stream);
+
+/* ------------------------------------------------------------------------
  * Learned initializer (Sec. 4.2-4.5 with a sparse-convolution backbone): a
  * U-Net on the same active node sets P_1..P_L, periodic neighbour maps, the
  * 8-bit occupancy embedded by a 256-entry table, learned 27-tap pooling from

@@ -40,6 +40,10 @@ class GmtParams(ct.Structure):
                 ("alloc_ctx", ct.c_void_p)]
 
 
+class GmtSimpParams(ct.Structure):
+    _fields_ = [("p", ct.c_double), ("rho_min", ct.c_double), ("prune", ct.c_double)]
+
+
 class GmtLevelDesc(ct.Structure):
     _fields_ = [("N", ct.c_int32), ("n_e", ct.c_int32), ("n_n", ct.c_int32),
                 ("c", ct.c_int32), ("d", ct.c_int32), ("lambda_max", ct.c_double),
@@ -122,6 +126,12 @@ SIGNATURES = {
     "gmt_nn_ema": (_P, _P, ct.c_size_t, ct.c_double, _P),
     "gmt_nn_norm2_noalloc": (_P, ct.c_size_t, ct.POINTER(ct.c_double), _P),
     "gmt_vcycle_loss": (_P, _P, ct.POINTER(GmtCycleOpts), ct.c_double, _P, ct.POINTER(ct.c_double), _P, _P),
+    "gmt_build_density_hierarchy": (_P, _I, ct.c_void_p, ct.POINTER(GmtParams), _P, ct.POINTER(_P)),
+    "gmt_simp_sensitivity": (_P, _P, _P, _P, _P, _P),
+    "gmt_simp_objective": (_P, _I, ct.POINTER(ct.c_double), _P),
+    "gmt_simp_filter": (_P, _P, _I, ct.c_double, _P, _P),
+    "gmt_simp_oc": (_P, _P, ct.c_size_t, ct.c_double, ct.c_double, ct.c_double, ct.c_double, _P,
+                    ct.POINTER(ct.c_double), _P),
     "gmt_last_error": (),
 }
 
@@ -191,9 +201,19 @@ class Hierarchy:
 
     def __init__(self, voxels, levels: int, physics: str = "elastic", E: float = 1.0,
                  nu: float = 0.3, kappa: float = 1.0, power_iters: int = 20, seed: int = 0,
-                 device="cuda", torch_memory: bool = True):
+                 device="cuda", torch_memory: bool = True, density=None, p: float = 3.0,
+                 rho_min: float = 1e-3, prune: float = 0.0):
+        """voxels: binary N^3 cell; or voxels=None and density = an N^3 field rho for the
+        SIMP cell problem (App. F.3) with penalization p, floor rho_min and pruning threshold."""
         if physics not in ("elastic", "thermal"):
             raise ValueError(physics)
+        self.density = None
+        if density is not None:
+            if isinstance(density, np.ndarray):
+                density = torch.from_numpy(np.ascontiguousarray(density, dtype=np.float64))
+            self.density = density.to(device=device, dtype=torch.float64).contiguous()
+            voxels = (self.density > prune).to(torch.uint8)
+            self.simp = (p, rho_min, prune)
         if isinstance(voxels, np.ndarray):
             voxels = torch.from_numpy(np.ascontiguousarray(voxels, dtype=np.uint8))
         N = int(voxels.shape[0])
@@ -215,7 +235,12 @@ class Hierarchy:
             p.alloc = self._arena.alloc_cb
             p.release = self._arena.release_cb
         h = ct.c_void_p()
-        _check(lib().gmt_build_hierarchy(_ptr(self._vox), N, ct.byref(p), _stream(), ct.byref(h)))
+        if self.density is not None:
+            sp = GmtSimpParams(*self.simp)
+            _check(lib().gmt_build_density_hierarchy(_ptr(self.density), N, ct.byref(sp), ct.byref(p), _stream(),
+                                                     ct.byref(h)))
+        else:
+            _check(lib().gmt_build_hierarchy(_ptr(self._vox), N, ct.byref(p), _stream(), ct.byref(h)))
         self._h = h
         self.L = levels
         self.levels = [self.level_info(l) for l in range(1, levels + 1)]
@@ -493,6 +518,21 @@ class Hierarchy:
         _check(lib().gmt_time_sweep(self._h, level, reps, _DT[dtype], ct.byref(out), _stream()))
         return out.value
 
+    def simp_sensitivity(self, u, G=None, want_dC=False):
+        """(dJ [N^3] or None, dC [N^3][c][c] or None) of App. F.3 for a density hierarchy."""
+        self._v(u, 1, torch.float64, "u")
+        dev = self._vox.device
+        n3 = self.N ** 3
+        dJ = torch.empty(n3, dtype=torch.float64, device=dev) if G is not None else None
+        dC = torch.empty(n3, self.c, self.c, dtype=torch.float64, device=dev) if want_dC else None
+        g = None
+        if G is not None:
+            g = np.ascontiguousarray(G, dtype=np.float64).reshape(self.c * self.c)
+        _check(lib().gmt_simp_sensitivity(self._h, _ptr(u), g.ctypes.data if g is not None else None,
+                                          _ptr(dJ) if dJ is not None else None,
+                                          _ptr(dC) if dC is not None else None, _stream()))
+        return dJ, dC
+
     def homogenize(self, u):
         self._v(u, 1, name="u")
         out = (ct.c_double * 36)()
@@ -532,6 +572,41 @@ def solve_batch(hs, fs, us=None, n_workers=4, raise_on_noconv=True, **opts):
     if st != GMT_OK and (st != GMT_E_NOCONV or raise_on_noconv):
         _check(st)
     return us, reports
+
+
+SIMP_OBJECTIVES = {"young": 0, "shear": 1, "bulk": 2}
+
+
+def simp_objective(CH, kind: str):
+    """(J, G = dJ/dC_H) of an App. F.3 target on the 6x6 C_H (host, in the library)."""
+    c = np.ascontiguousarray(CH, dtype=np.float64).reshape(36)
+    J = ct.c_double()
+    G = np.zeros(36)
+    _check(lib().gmt_simp_objective(c.ctypes.data, SIMP_OBJECTIVES[kind], ct.byref(J), G.ctypes.data))
+    return J.value, G.reshape(6, 6)
+
+
+def simp_filter(rho, dc, rmin: float):
+    """Sensitivity filter on the dense periodic grid (float64 CUDA tensors of N^3 values)."""
+    N = round(rho.numel() ** (1 / 3))
+    for t, name in ((rho, "rho"), (dc, "dc")):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == N ** 3):
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of N^3 values")
+    out = torch.empty_like(dc)
+    _check(lib().gmt_simp_filter(_ptr(rho), _ptr(dc), N, rmin, _ptr(out), _stream()))
+    return out
+
+
+def simp_oc(rho, dc, volfrac: float, move: float = 0.2, eta: float = 0.5, rho_lo: float = 1e-3):
+    """Optimality-Criteria step with move limits; returns (rho_new, lam)."""
+    for t, name in ((rho, "rho"), (dc, "dc")):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == rho.numel()):
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    out = torch.empty_like(rho)
+    lam = ct.c_double()
+    _check(lib().gmt_simp_oc(_ptr(rho), _ptr(dc), rho.numel(), volfrac, move, eta, rho_lo, _ptr(out),
+                             ct.byref(lam), _stream()))
+    return out, lam.value
 
 
 def nn_param_count(levels, channels, head=32, physics="elastic") -> int:

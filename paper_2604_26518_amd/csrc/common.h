@@ -113,6 +113,10 @@ struct LevelView {
   // level 1: the 27 neighbour ids of boundary node t at bnd_nbrs[t * kBndStride ..]
   const int* bnd_nbrs;
   const T* S;
+  // level 1 of a density (SIMP) hierarchy: per node the 8 octant elements'
+  // stiffness scales s = rho_min + rho^p (0 where inactive), [n_n][8]; null
+  // for a binary cell (scale 1 where the occupancy bit is set)
+  const T* oscale;
   const T* kcls;  // symmetry-class values of K_e (14 elastic, 4 scalar)
   const T* scls;  // symmetry-class values of S (8 elastic, 4 scalar)
   // launch shape of this level's operator sweeps (chosen by the autotuner):
@@ -224,13 +228,32 @@ void launch_elem_nodes(const int* elem_lin, int n_e, const int* node_map, int N,
                        hipStream_t s);
 void launch_prol_maps(const int* node_lin, int n_n, int Nf, const int* coarse_node_map, int Nc,
                       int* idx, double* w, hipStream_t s);
+// fscale (nullable, SHARED source only): per fine element scale of the shared K_e
 void launch_galerkin(const int* elem_lin_c, int n_e_c, int Nc, const int* elem_map_f,
                      const uint8_t* cmask_f, const double* Ksrc, int src_kind, int D,
-                     const double* Ps, double* out64, float* out32, hipStream_t s);
+                     const double* Ps, const double* fscale, double* out64, float* out32, hipStream_t s);
 template <typename T>
 void launch_diagonal(const LevelView<T>& L, int kind, int D, T* diag, hipStream_t s);
-void launch_load_vector(const int* node_lin, const uint8_t* occ8, int n_n, int D, int C,
+// oscale (nullable): per node octant scales of a density hierarchy
+void launch_load_vector(const int* node_lin, const uint8_t* occ8, const double* oscale, int n_n, int D, int C,
                         const double* fe, double* f, hipStream_t s);
+// SIMP (App. F.3): density -> active voxels, per element rho and scale, per node octant scales
+void launch_density_flags(const double* rho, size_t n, double prune, uint8_t* vox, hipStream_t s);
+void launch_element_scale(const int* elem_lin, int n_e, const double* rho, double p, double rho_min, double* erho,
+                          double* escale, hipStream_t s);
+void launch_node_oscale(const int* node_lin, int n_n, const int* elem_map, int N, const double* escale,
+                        double* o64, float* o32, hipStream_t s);
+void launch_iota(int* a, int n, hipStream_t s);
+// per element energies d_i^T K0 d_j (d = X0 - u_e) of a density hierarchy, scaled by
+// p rho^(p-1) / N^3 into dense dC [N^3][C][C] and contracted with G into dense dJ [N^3]
+void launch_simp_sensitivity(const int* elem_lin, int n_e, const int* node_map, int N, int D, int C,
+                             const double* u_aos, const double* Ke, const double* X0, const double* erho, double p,
+                             const double* G, double* dJ, double* dC, hipStream_t s);
+void launch_simp_filter(const double* rho, const double* dc, int N, double rmin, double gamma, double* out,
+                        hipStream_t s);
+// sum over i of the OC update of element i for multiplier lam (and the update itself into out, if set)
+void launch_oc_eval(const double* rho, const double* dc, size_t n, double lam, double move, double eta, double lo,
+                    double* out, double* partial, double* total, hipStream_t s);
 void launch_random(double* x, size_t n, uint64_t seed, hipStream_t s);
 void launch_expand_elem_matrices(const LevelView<double>& L, int kind, int n_e, int D,
                                  const int* elem_lin, double* out, hipStream_t s);
@@ -254,7 +277,11 @@ struct LevelData {
   int* runs = nullptr;        // level 1: chunk starts of `interior` (+ sentinel)
   int n_runs = 0;
   int* bnd_nbrs = nullptr;    // level 1: neighbour ids of the boundary nodes (kBndStride per node)
-  double* Kel64 = nullptr;    // per element, levels >= 3
+  double* oscale64 = nullptr; // level 1 of a density hierarchy: [n_n][8] octant scales
+  float* oscale32 = nullptr;
+  double* erho = nullptr;     // level 1 of a density hierarchy: rho and scale per element
+  double* escale = nullptr;
+  double* Kel64 = nullptr;    // per element, levels >= 3 (>= 2 for a density hierarchy)
   float* Kel32 = nullptr;
   double* diag64 = nullptr;   // [n_n][d]
   double* dinv64 = nullptr;
@@ -291,6 +318,12 @@ struct Hier {
   double Ke[576] = {0};
   double fe[576] = {0};  // K_e X0, (8d) x c row-major
   double C0[36] = {0};   // X0^T K_e X0 (= base tensor)
+  double X0[576] = {0};  // nodal affine fields, (8d) x c row-major
+  double* X064 = nullptr;
+  // density (SIMP) hierarchy: K_e of element e is s_e K0, s_e = rho_min + rho_e^p
+  bool density = false;
+  double simp_p = 3.0, simp_rho_min = 1e-3, simp_prune = 0.0;
+  double scale_sum = 0.0;  // sum_e s_e (the n_e of a binary cell)
   double fe_norm = 0;    // ||f_e||_F, the scale of a nonzero load
   double* Ke64 = nullptr;
   float* Ke32 = nullptr;

@@ -131,6 +131,10 @@ LevelView<T> Hier::view(int l) const {
   v.n_runs = d.n_runs;
   v.runs = d.runs;
   v.bnd_nbrs = d.bnd_nbrs;
+  if constexpr (std::is_same<T, double>::value)
+    v.oscale = d.oscale64;
+  else
+    v.oscale = d.oscale32;
   if constexpr (std::is_same<T, double>::value) {
     v.K = d.kind == KIND_SHARED ? Ke64 : (d.kind == KIND_TABLE ? table64 : d.Kel64);
     v.S = S64;
@@ -154,7 +158,9 @@ LevelView<T> Hier::view(int l) const {
   }
   if (l == 0) {
     const int f = forced_l1_variant();
-    if (f >= 0 && f <= 7 && f != 4) v.cb = f;
+    if (f >= 0 && f <= 8 && f != 4) v.cb = f;
+    // a density hierarchy has only the scaled class-assembled boundary sweeps
+    if (density && v.cb != 5 && v.cb != 7 && v.cb != 8) v.cb = 7;
   }
   return v;
 }
@@ -302,6 +308,7 @@ static void element_constants(Hier& h) {
     }
   }
   for (int i = 0; i < M * M; ++i) h.Ke[i] = K[i];
+  for (int i = 0; i < M * C; ++i) h.X0[i] = X[i];
   for (int i = 0; i < M; ++i)
     for (int c = 0; c < C; ++c) {
       double s = 0;
@@ -604,7 +611,7 @@ static LevelView<T> colour_view(const Hier& h, int l, int c) {
     v.bnd_nbrs = d.col_bnd_nbrs ? d.col_bnd_nbrs + (size_t)d.col_bnd_off[c] * kBndStride : nullptr;
     v.n_runs = 0;
     v.runs = nullptr;
-    if (v.cb < 5 || v.cb > 7) v.cb = 7;  // the list-driven variants
+    if (v.cb < 5 || v.cb > 8) v.cb = 7;  // the list-driven variants
   } else {
     v.list = d.col_nodes + d.col_off[c];
     v.n_list = d.col_off[c + 1] - d.col_off[c];
@@ -823,7 +830,7 @@ static void autotune(Hier& h, hipStream_t s) {
     int nb = 0;
     while ((1 << (nb + 1)) <= d.n_n) ++nb;
     const double dens = (double)d.n_n / ((double)d.N * d.N * d.N);
-    const std::vector<int> key = {h.D, h.C, f32 ? 32 : 64, d.kind, nb, (int)(dens * 8.0)};
+    const std::vector<int> key = {h.D, h.C, f32 ? 32 : 64, d.kind, nb, (int)(dens * 8.0), h.density ? 1 : 0};
     {
       std::lock_guard<std::mutex> g(g_tune_mu);
       auto it = g_tune.find(key);
@@ -844,8 +851,10 @@ static void autotune(Hier& h, hipStream_t s) {
     // level 1: the variants that have won on some cell shape (the others stay
     // selectable through GMT_FORCE_L1_VARIANT)
     std::vector<Shape> cand = {{256, 0, 1}, {256, 0, 0}};
-    if (l == 0) {
-      cand = {{256, 7, 1}, {256, 7, 0}, {256, 5, 1}, {256, 6, 1}, {256, 6, 0}};
+    if (l == 0 && h.density) {
+      cand = {{256, 7, 1}, {256, 7, 0}, {256, 5, 1}, {256, 8, 1}, {256, 8, 0}};
+    } else if (l == 0) {
+      cand = {{256, 8, 1}, {256, 8, 0}, {256, 7, 1}, {256, 7, 0}, {256, 5, 1}, {256, 6, 1}, {256, 6, 0}};
       if (h.C > 1) cand.insert(cand.end(), {{256, 1, 1}, {256, 1, 0}});
     }
     if (l > 0) {
@@ -1145,11 +1154,14 @@ struct PhaseTimer {
   }
 };
 
-static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
+// rho (nullable): a density field (SIMP, App. F.3) on the N^3 voxels; its active
+// set is rho > prune and `vox` is then that set (built by the caller)
+static void build(Hier& h, const uint8_t* vox, hipStream_t s, const double* rho = nullptr) {
   PhaseTimer timer(s);
   const int N = h.N;
   const size_t n3 = (size_t)N * N * N;
   element_constants(h);
+  h.density = rho != nullptr;
   const int D = h.D, M = 8 * D;
   h.Ke64 = h.alloc<double>(M * M);
   h.Ke32 = h.alloc<float>(M * M);
@@ -1157,6 +1169,8 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
   GMT_HIP(hipMemcpyAsync(h.Ke64, h.Ke, M * M * sizeof(double), hipMemcpyHostToDevice, s));
   launch_convert<double, float>(h.Ke64, h.Ke32, M * M, s);
   GMT_HIP(hipMemcpyAsync(h.fe64, h.fe, M * h.C * sizeof(double), hipMemcpyHostToDevice, s));
+  h.X064 = h.alloc<double>(M * h.C);
+  GMT_HIP(hipMemcpyAsync(h.X064, h.X0, M * h.C * sizeof(double), hipMemcpyHostToDevice, s));
   double Ps[8][8][8];
   local_prolongation(Ps);
   h.Ps = h.alloc<double>(512);
@@ -1211,14 +1225,36 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
       d.cmask = h.alloc<uint8_t>(ne);
       launch_gather_cmask(d.elem_lin, d.n_e, dmask, d.cmask, s);
     }
-    d.kind = l == 0 ? KIND_SHARED : (l == 1 ? KIND_TABLE : KIND_PERELEM);
+    // a density hierarchy's level-2 matrices depend on the children's scales: per element
+    d.kind = l == 0 ? KIND_SHARED : (l == 1 && !h.density ? KIND_TABLE : KIND_PERELEM);
+  }
+  if (h.density) {
+    // per element rho and scale s = rho_min + rho^p, per node the octant scales
+    LevelData& d = h.lv[0];
+    d.erho = h.alloc<double>(d.n_e);
+    d.escale = h.alloc<double>(d.n_e);
+    launch_element_scale(d.elem_lin, d.n_e, rho, h.simp_p, h.simp_rho_min, d.erho, d.escale, s);
+    d.oscale64 = h.alloc<double>((size_t)d.n_n * 8);
+    d.oscale32 = h.alloc<float>((size_t)d.n_n * 8);
+    launch_node_oscale(d.node_lin, d.n_n, d.elem_map, d.N, d.escale, d.oscale64, d.oscale32, s);
+    double* ones = h.alloc<double>(d.n_e);
+    launch_fill<double>(ones, d.n_e, 1.0, s);
+    launch_dot<double>(d.escale, ones, d.n_e, 1, 1, h.red_partial, h.red_out, s);
+    host_dot(h, h.red_out, 1, &h.scale_sum, s);
+    h.release(ones);
   }
 
-  // level 1: interior (occupancy 255) and boundary node lists
+  // level 1: interior (occupancy 255) and boundary node lists; in a density
+  // hierarchy every node goes through the scaled masked stencil (boundary list)
   {
     LevelData& d = h.lv[0];
     int* tmpmap = h.alloc<int>(d.n_n);
-    for (int full = 1; full >= 0; --full) {
+    if (h.density) {
+      d.boundary = h.alloc<int>(d.n_n);
+      d.n_bnd = d.n_n;
+      launch_iota(d.boundary, d.n_n, s);
+    }
+    for (int full = 1; full >= 0 && !h.density; --full) {
       launch_occ_flags(d.occ8, d.n_n, full, flags, s);
       const int64_t cnt = scan_compact(flags, d.n_n, nullptr, nullptr, scr, d_total, s);
       int* list = cnt > 0 ? h.alloc<int>(cnt) : nullptr;
@@ -1350,13 +1386,14 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
     launch_convert<double, float>(h.table64, h.table32, tab.size(), s);
     GMT_HIP(hipStreamSynchronize(s));
   }
-  for (int l = 2; l < h.L; ++l) {
+  for (int l = h.density ? 1 : 2; l < h.L; ++l) {
     LevelData& d = h.lv[l];
     const LevelData& f = h.lv[l - 1];
     d.Kel64 = h.alloc<double>((size_t)d.n_e * M * M);
     d.Kel32 = h.alloc<float>((size_t)d.n_e * M * M);
-    const double* src = f.kind == KIND_TABLE ? h.table64 : f.Kel64;
-    launch_galerkin(d.elem_lin, d.n_e, d.N, f.elem_map, f.cmask, src, f.kind, D, h.Ps, d.Kel64, d.Kel32, s);
+    const double* src = f.kind == KIND_SHARED ? h.Ke64 : (f.kind == KIND_TABLE ? h.table64 : f.Kel64);
+    launch_galerkin(d.elem_lin, d.n_e, d.N, f.elem_map, f.cmask, src, f.kind, D, h.Ps,
+                    l == 1 ? h.lv[0].escale : nullptr, d.Kel64, d.Kel32, s);
   }
   timer.mark("galerkin");
   // Jacobi diagonals
@@ -1372,7 +1409,7 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s) {
   }
   // load vector
   h.f64 = h.alloc<double>((size_t)h.lv[0].n_n * h.Q);
-  launch_load_vector(h.lv[0].node_lin, h.lv[0].occ8, h.lv[0].n_n, D, h.C, h.fe64, h.f64, s);
+  launch_load_vector(h.lv[0].node_lin, h.lv[0].occ8, h.lv[0].oscale64, h.lv[0].n_n, D, h.C, h.fe64, h.f64, s);
 
   timer.mark("diag+load");
   EventSet evs;
@@ -1691,6 +1728,39 @@ gmt_status gmt_time_sweep(gmt_hier_t H, int32_t level, int32_t reps, int32_t dty
   });
 }
 
+// Validates the parameters and sets up the hierarchy object (no device work).
+static gmt_hier* new_hierarchy(int32_t N, const gmt_params* params) {
+  if (!params) fail(GMT_E_INVAL, "params is NULL");
+  if (N < 2 || N > 1024) fail(GMT_E_INVAL, "N = %d outside 2..1024", N);
+  const int L = params->levels;
+  if (L < 1 || L > 12) fail(GMT_E_INVAL, "levels = %d outside 1..12", L);
+  if (N % (1 << (L - 1)) != 0 || (N >> (L - 1)) < 2)
+    fail(GMT_E_INVAL, "N = %d must be divisible by 2^(L-1) = %d with N_L >= 2", N, 1 << (L - 1));
+  if (params->physics != GMT_ELASTIC && params->physics != GMT_THERMAL) fail(GMT_E_INVAL, "bad physics");
+  if ((params->alloc == nullptr) != (params->release == nullptr))
+    fail(GMT_E_INVAL, "alloc and release must be given together");
+  gmt_hier* H = new gmt_hier();
+  Hier& h = H->h;
+  h.p = *params;
+  if (h.p.E == 0) h.p.E = 1.0;
+  if (h.p.nu == 0 && params->physics == GMT_ELASTIC) h.p.nu = 0.3;
+  if (h.p.kappa == 0) h.p.kappa = 1.0;
+  if (h.p.physics == GMT_ELASTIC && !(h.p.E > 0 && h.p.nu > -1.0 && h.p.nu < 0.5)) {
+    delete H;
+    fail(GMT_E_INVAL, "need E > 0 and -1 < nu < 0.5");
+  }
+  if (h.p.physics == GMT_THERMAL && !(h.p.kappa > 0)) {
+    delete H;
+    fail(GMT_E_INVAL, "need kappa > 0");
+  }
+  h.N = N;
+  h.L = L;
+  h.D = params->physics == GMT_ELASTIC ? 3 : 1;
+  h.C = params->physics == GMT_ELASTIC ? 6 : 3;
+  h.Q = h.C * h.D;
+  return H;
+}
+
 gmt_status gmt_build_hierarchy(const uint8_t* d_voxels, int32_t N, const gmt_params* params, void* stream,
                                gmt_hier_t* out) {
   gmt_hier* H = nullptr;
@@ -1698,32 +1768,42 @@ gmt_status gmt_build_hierarchy(const uint8_t* d_voxels, int32_t N, const gmt_par
     if (!out) fail(GMT_E_INVAL, "out is NULL");
     *out = nullptr;
     if (!d_voxels) fail(GMT_E_INVAL, "voxels is NULL");
-    if (!params) fail(GMT_E_INVAL, "params is NULL");
-    if (N < 2 || N > 1024) fail(GMT_E_INVAL, "N = %d outside 2..1024", N);
-    const int L = params->levels;
-    if (L < 1 || L > 12) fail(GMT_E_INVAL, "levels = %d outside 1..12", L);
-    if (N % (1 << (L - 1)) != 0 || (N >> (L - 1)) < 2)
-      fail(GMT_E_INVAL, "N = %d must be divisible by 2^(L-1) = %d with N_L >= 2", N, 1 << (L - 1));
-    if (params->physics != GMT_ELASTIC && params->physics != GMT_THERMAL) fail(GMT_E_INVAL, "bad physics");
-    if ((params->alloc == nullptr) != (params->release == nullptr))
-      fail(GMT_E_INVAL, "alloc and release must be given together");
-    H = new gmt_hier();
-    Hier& h = H->h;
-    h.p = *params;
-    if (h.p.E == 0) h.p.E = 1.0;
-    if (h.p.nu == 0 && params->physics == GMT_ELASTIC) h.p.nu = 0.3;
-    if (h.p.kappa == 0) h.p.kappa = 1.0;
-    if (h.p.physics == GMT_ELASTIC && !(h.p.E > 0 && h.p.nu > -1.0 && h.p.nu < 0.5))
-      fail(GMT_E_INVAL, "need E > 0 and -1 < nu < 0.5");
-    if (h.p.physics == GMT_THERMAL && !(h.p.kappa > 0)) fail(GMT_E_INVAL, "need kappa > 0");
-    h.N = N;
-    h.L = L;
-    h.D = params->physics == GMT_ELASTIC ? 3 : 1;
-    h.C = params->physics == GMT_ELASTIC ? 6 : 3;
-    h.Q = h.C * h.D;
+    H = new_hierarchy(N, params);
     (void)ilog2_exact;
-    build(h, d_voxels, S(stream));
+    build(H->h, d_voxels, S(stream));
     GMT_HIP(hipStreamSynchronize(S(stream)));
+    *out = H;
+  });
+  if (st != GMT_OK && H) {
+    (void)hipDeviceSynchronize();
+    H->h.release_all();
+    delete H;
+  }
+  return st;
+}
+
+gmt_status gmt_build_density_hierarchy(const double* d_rho, int32_t N, const gmt_simp_params* sp,
+                                       const gmt_params* params, void* stream, gmt_hier_t* out) {
+  gmt_hier* H = nullptr;
+  gmt_status st = guarded([&] {
+    if (!out) fail(GMT_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!d_rho || !sp) fail(GMT_E_INVAL, "null pointer");
+    if (!(sp->p >= 1.0) || !(sp->rho_min > 0.0) || !(sp->prune >= 0.0) || !(sp->prune < 1.0))
+      fail(GMT_E_INVAL, "need p >= 1, rho_min > 0 and 0 <= prune < 1");
+    if (params && params->levels < 2) fail(GMT_E_INVAL, "a density hierarchy needs at least 2 levels");
+    H = new_hierarchy(N, params);
+    Hier& h = H->h;
+    h.simp_p = sp->p;
+    h.simp_rho_min = sp->rho_min;
+    h.simp_prune = sp->prune;
+    hipStream_t s = S(stream);
+    const size_t n3 = (size_t)N * N * N;
+    uint8_t* vox = h.alloc<uint8_t>(n3);
+    launch_density_flags(d_rho, n3, sp->prune, vox, s);
+    build(h, vox, s, d_rho);
+    GMT_HIP(hipStreamSynchronize(s));
+    h.release(vox);
     *out = H;
   });
   if (st != GMT_OK && H) {
@@ -1788,6 +1868,8 @@ gmt_status gmt_export_element_matrices(gmt_hier_t H, int32_t level, double* d_K,
     if (!d_K) fail(GMT_E_INVAL, "d_K is NULL");
     Hier& h = H->h;
     const LevelData& d = h.lv[level - 1];
+    if (h.density && level == 1)
+      fail(GMT_E_INVAL, "level-1 matrices of a density hierarchy are s_e K0: export levels >= 2");
     launch_expand_elem_matrices(h.view<double>(level - 1), d.kind, d.n_e, h.D, d.elem_lin, d_K, S(stream));
   });
 }
@@ -2182,13 +2264,140 @@ gmt_status gmt_homogenize(gmt_hier_t H, const void* d_u, int32_t dtype, double* 
     host_dot(h, A, C * C, Ah, s);
     host_dot(h, B, C * C, Bh, s);
     const double vol = (double)h.N * h.N * h.N;
-    const double ne = h.lv[0].n_e;
+    // sum_e s_e X0^T K0 X0 = (sum_e s_e) C0 (s_e = 1 in a binary cell)
+    const double ne = h.density ? h.scale_sum : (double)h.lv[0].n_e;
     for (int i = 0; i < C; ++i)
       for (int j = 0; j < C; ++j)
         h_CH[i * C + j] = (ne * h.C0[i * C + j] - Ah[i * C + j] - Ah[j * C + i] + Bh[i * C + j]) / vol;
   });
 }
 
+
+// ================================================================ SIMP inverse homogenization (App. F.3)
+
+gmt_status gmt_simp_sensitivity(gmt_hier_t H, const double* d_u, const double* h_G, double* d_dJ, double* d_dC,
+                                void* stream) {
+  return guarded([&] {
+    check_level(H, 1);
+    Hier& h = H->h;
+    if (!h.density) fail(GMT_E_STATE, "not a density hierarchy (gmt_build_density_hierarchy)");
+    if (!d_u) fail(GMT_E_INVAL, "d_u is NULL");
+    if (!d_dJ && !d_dC) fail(GMT_E_INVAL, "nothing to compute: d_dJ and d_dC are both NULL");
+    if (d_dJ && !h_G) fail(GMT_E_INVAL, "d_dJ needs the weights h_G");
+    hipStream_t s = S(stream);
+    const LevelData& d = h.lv[0];
+    const size_t n3 = (size_t)h.N * h.N * h.N;
+    double* G = nullptr;
+    if (h_G) {
+      G = h.red_out + 200;  // c*c <= 36 values, past the reduction slots used here
+      GMT_HIP(hipMemcpyAsync(G, h_G, (size_t)h.C * h.C * sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    if (d_dJ) launch_fill<double>(d_dJ, n3, 0.0, s);
+    if (d_dC) launch_fill<double>(d_dC, n3 * h.C * h.C, 0.0, s);
+    launch_simp_sensitivity(d.elem_lin, d.n_e, d.node_map, h.N, h.D, h.C, d_u, h.Ke64, h.X064, d.erho, h.simp_p, G,
+                            d_dJ, d_dC, s);
+    GMT_HIP(hipStreamSynchronize(s));  // h_G is read by the copy above
+  });
+}
+
+gmt_status gmt_simp_objective(const double* h_CH, int32_t kind, double* h_J, double* h_G) {
+  return guarded([&] {
+    if (!h_CH || !h_J || !h_G) fail(GMT_E_INVAL, "null pointer");
+    if (kind < GMT_SIMP_YOUNG || kind > GMT_SIMP_BULK) fail(GMT_E_INVAL, "objective kind %d", kind);
+    // S = C_H^-1 by Gauss-Jordan elimination with partial pivoting
+    double A[6][12];
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 12; ++j) A[i][j] = j < 6 ? h_CH[i * 6 + j] : (j - 6 == i ? 1.0 : 0.0);
+    for (int c = 0; c < 6; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < 6; ++r)
+        if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+      if (!(std::fabs(A[piv][c]) > 0)) fail(GMT_E_SINGULAR, "C_H is singular");
+      if (piv != c)
+        for (int j = 0; j < 12; ++j) std::swap(A[c][j], A[piv][j]);
+      const double inv = 1.0 / A[c][c];
+      for (int j = 0; j < 12; ++j) A[c][j] *= inv;
+      for (int r = 0; r < 6; ++r)
+        if (r != c) {
+          const double f = A[r][c];
+          for (int j = 0; j < 12; ++j) A[r][j] -= f * A[c][j];
+        }
+    }
+    double Sm[6][6], W[6][6] = {{0}};
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) Sm[i][j] = A[i][j + 6];
+    if (kind == GMT_SIMP_YOUNG)
+      for (int i = 0; i < 3; ++i) W[i][i] = 1.0 / 3.0;
+    else if (kind == GMT_SIMP_SHEAR)
+      for (int i = 3; i < 6; ++i) W[i][i] = 1.0 / 3.0;
+    else
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) W[i][j] = 1.0;
+    double J = 0.0;
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) J += W[i][j] * Sm[i][j];
+    *h_J = J;
+    // dJ/dC = -S^T W S^T (dS = -S dC S)
+    double T[6][6];
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) {
+        double t = 0.0;
+        for (int k = 0; k < 6; ++k) t += Sm[k][i] * W[k][j];
+        T[i][j] = t;
+      }
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) {
+        double t = 0.0;
+        for (int k = 0; k < 6; ++k) t += T[i][k] * Sm[j][k];
+        h_G[i * 6 + j] = -t;
+      }
+  });
+}
+
+gmt_status gmt_simp_filter(const double* d_rho, const double* d_dc, int32_t N, double rmin, double* d_out,
+                           void* stream) {
+  return guarded([&] {
+    if (!d_rho || !d_dc || !d_out) fail(GMT_E_INVAL, "null pointer");
+    if (N < 1 || N > 1024) fail(GMT_E_INVAL, "N = %d outside 1..1024", N);
+    if (!(rmin > 1.0) || rmin > 8.0) fail(GMT_E_INVAL, "filter radius %g outside (1, 8]", rmin);
+    if (d_out == d_dc || d_out == d_rho) fail(GMT_E_INVAL, "d_out must not alias the inputs");
+    launch_simp_filter(d_rho, d_dc, N, rmin, 1e-3, d_out, S(stream));
+  });
+}
+
+gmt_status gmt_simp_oc(const double* d_rho, const double* d_dc, size_t n, double volfrac, double move, double eta,
+                       double rho_lo, double* d_rho_new, double* h_lambda, void* stream) {
+  return guarded([&] {
+    if (!d_rho || !d_dc || !d_rho_new) fail(GMT_E_INVAL, "null pointer");
+    if (n == 0) fail(GMT_E_INVAL, "n = 0");
+    if (!(volfrac > 0 && volfrac < 1) || !(move > 0) || !(eta > 0) || !(rho_lo > 0 && rho_lo < 1))
+      fail(GMT_E_INVAL, "need 0 < volfrac < 1, move > 0, eta > 0, 0 < rho_lo < 1");
+    if (d_rho_new == d_rho || d_rho_new == d_dc) fail(GMT_E_INVAL, "d_rho_new must not alias the inputs");
+    hipStream_t s = S(stream);
+    double* partial = nullptr;
+    double* total = nullptr;
+    GMT_HIP(hipMallocAsync((void**)&partial, (kRedBlocks + 1) * sizeof(double), s));
+    total = partial + kRedBlocks;
+    // bisection on the multiplier: the updated volume decreases with lam
+    double lo = 0.0, hi = 1e9, lam = hi, vol = 0.0;
+    const double target = volfrac * (double)n;
+    for (int it = 0; it < 200; ++it) {
+      lam = 0.5 * (lo + hi);
+      launch_oc_eval(d_rho, d_dc, n, lam, move, eta, rho_lo, nullptr, partial, total, s);
+      GMT_HIP(hipMemcpyAsync(&vol, total, sizeof(double), hipMemcpyDeviceToHost, s));
+      GMT_HIP(hipStreamSynchronize(s));
+      if (vol > target)
+        lo = lam;
+      else
+        hi = lam;
+      if (hi - lo <= 1e-10 * std::max(hi, 1e-30)) break;
+    }
+    launch_oc_eval(d_rho, d_dc, n, lam, move, eta, rho_lo, d_rho_new, partial, total, s);
+    GMT_HIP(hipFreeAsync(partial, s));
+    GMT_HIP(hipStreamSynchronize(s));
+    if (h_lambda) *h_lambda = lam;
+  });
+}
 
 // ================================================================ learned initializer
 

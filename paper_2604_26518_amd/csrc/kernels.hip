@@ -12,6 +12,8 @@
 // D DOFs of one case read one contiguous run of 64*D words.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <type_traits>
 
 #include "common.h"
@@ -543,11 +545,15 @@ __global__ __launch_bounds__(kBlock) void k_apply_boundary_cls(LevelView<T> L, c
     }
   }
   T mk[8], mkn[8];
+  if (L.oscale) {  // density hierarchy: the octant elements' stiffness scales (0 where inactive)
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    mk[k] = (occ >> k) & 1u ? T(1) : T(0);
-    mkn[k] = -mk[k];
+    for (int k = 0; k < 8; ++k) mk[k] = L.oscale[(size_t)i * 8 + k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) mk[k] = (occ >> k) & 1u ? T(1) : T(0);
   }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) mkn[k] = -mk[k];
   T acc[C][D];
 #pragma unroll
   for (int c = 0; c < C; ++c)
@@ -604,6 +610,102 @@ __global__ __launch_bounds__(kBlock) void k_apply_boundary_cls(LevelView<T> L, c
         for (int c = 0; c < C; ++c) acc[c][q] = fma(cj[q][q2], v[c][q2], acc[c][q]);
   }
   epilogue_node<T, EPI, C, D>(e, u, n, i, c0, &acc[0][0], nullptr, nullptr);
+}
+
+// Level 1, boundary nodes, all C cases per thread: the masked stencil block
+// of each neighbour is assembled once per node (not once per case) and the
+// neighbour table row is read once.  The C x D values of neighbour j + 1 are
+// loaded while neighbour j is assembled and applied (two register buffers);
+// a scheduling barrier per neighbour keeps the compiler from hoisting the
+// loads of all 27 neighbours (27 x C x D live values would spill).
+template <typename T, int D, int C, int EPI>
+__global__ __launch_bounds__(kBlock) void k_apply_boundary_all(LevelView<T> L, const T* __restrict__ u, EpiArgs<T> e) {
+  const int t = block_index(L.xcd) * kBlock + threadIdx.x;
+  if (t >= L.n_bnd) return;
+  const int i = L.boundary[t];
+  const size_t n = (size_t)L.n_n;
+  const unsigned occ = L.occ8[i];
+  constexpr int NK = D == 1 ? 4 : 14;
+  const cptr<T> kcp = as_const(L.kcls);
+  T kc[NK];
+#pragma unroll
+  for (int c = 0; c < NK; ++c) kc[c] = kcp[c];
+  int nb[kBndStride];
+  {
+    const int4* row = reinterpret_cast<const int4*>(L.bnd_nbrs + (size_t)t * kBndStride);
+#pragma unroll
+    for (int k = 0; k < kBndStride / 4; ++k) {
+      const int4 v = row[k];
+      nb[4 * k] = v.x;
+      nb[4 * k + 1] = v.y;
+      nb[4 * k + 2] = v.z;
+      nb[4 * k + 3] = v.w;
+    }
+  }
+  T mk[8];
+  if (L.oscale) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) mk[k] = L.oscale[(size_t)i * 8 + k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) mk[k] = (occ >> k) & 1u ? T(1) : T(0);
+  }
+  T acc[C][D];
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int q = 0; q < D; ++q) acc[c][q] = T(0);
+  T vb[2][C][D];
+  {
+    const size_t id = nb[0] >= 0 ? nb[0] : 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int q2 = 0; q2 < D; ++q2) vb[0][c][q2] = u[vix(c, n, id, D, q2)];
+  }
+#pragma unroll
+  for (int j = 0; j < 27; ++j) {
+    const int cur = j & 1;
+    if (j + 1 < 27) {
+      const size_t id = nb[j + 1] >= 0 ? nb[j + 1] : 0;
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int q2 = 0; q2 < D; ++q2) vb[cur ^ 1][c][q2] = u[vix(c, n, id, D, q2)];
+    }
+    const int jx = j % 3, jy = (j / 3) % 3, jz = j / 9;
+    T cj[D][D];
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+#pragma unroll
+      for (int q2 = 0; q2 < D; ++q2) cj[q][q2] = T(0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int dx = jx - (k & 1), dy = jy - ((k >> 1) & 1), dz = jz - (k >> 2);
+      if (dx < 0 || dx > 1 || dy < 0 || dy > 1 || dz < 0 || dz > 1) continue;  // j is not a corner of element k
+      const int a = 7 - k, m = dx + 2 * dy + 4 * dz;
+#pragma unroll
+      for (int q = 0; q < D; ++q)
+#pragma unroll
+        for (int q2 = 0; q2 < D; ++q2) {
+          const T w = kc[kcls_index<D>(a ^ m, q, q2)];
+          cj[q][q2] = fma(mk[k], kcls_negative<D>(a, q, q2) ? -w : w, cj[q][q2]);
+        }
+    }
+    const T act = nb[j] >= 0 ? T(1) : T(0);
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+#pragma unroll
+      for (int q2 = 0; q2 < D; ++q2) cj[q][q2] *= act;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int q = 0; q < D; ++q)
+#pragma unroll
+        for (int q2 = 0; q2 < D; ++q2) acc[c][q] = fma(cj[q][q2], vb[cur][c][q2], acc[c][q]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  epilogue_node<T, EPI, C, D>(e, u, n, i, 0, &acc[0][0], nullptr, nullptr);
 }
 
 // Level 1, boundary nodes: element-by-element over the active octant
@@ -1353,7 +1455,8 @@ __global__ __launch_bounds__(kBlock) void k_galerkin(const int* __restrict__ ele
                                                      const int* __restrict__ emap_f,
                                                      const uint8_t* __restrict__ cmask_f,
                                                      const double* __restrict__ Ksrc, int src_kind,
-                                                     const double* __restrict__ Ps, double* __restrict__ out64,
+                                                     const double* __restrict__ Ps,
+                                                     const double* __restrict__ fscale, double* __restrict__ out64,
                                                      float* __restrict__ out32) {
   constexpr int M = 8 * D;
   __shared__ double Kc[M * M];
@@ -1372,8 +1475,9 @@ __global__ __launch_bounds__(kBlock) void k_galerkin(const int* __restrict__ ele
     const double* src = src_kind == KIND_SHARED ? Ksrc
                         : src_kind == KIND_TABLE ? Ksrc + (size_t)cmask_f[fid] * M * M
                                                  : Ksrc + (size_t)fid * M * M;
+    const double sc = fscale ? fscale[fid] : 1.0;  // density hierarchy: the child's stiffness scale
     __syncthreads();
-    for (int t = threadIdx.x; t < M * M; t += kBlock) Kc[t] = src[t];
+    for (int t = threadIdx.x; t < M * M; t += kBlock) Kc[t] = sc * src[t];
     if (threadIdx.x < 64) P[threadIdx.x] = Ps[c * 64 + threadIdx.x];
     __syncthreads();
     // T1[(m,i),(p,j)] = sum_n Kc[(m,i),(n,j)] P[n][p]
@@ -1416,9 +1520,11 @@ __global__ void k_diagonal(LevelView<T> L, T* __restrict__ diag) {
   for (int q = 0; q < D; ++q) acc[q] = T(0);
   for (int k = 0; k < 8; ++k) {
     const T* Km;
+    T sc = T(1);
     if constexpr (KIND == KIND_SHARED) {
       if (!(L.occ8[i] & (1u << k))) continue;
       Km = L.K;
+      if (L.oscale) sc = L.oscale[(size_t)i * 8 + k];
     } else {
       const int ex = wrapm(x - 1 + (k & 1), N), ey = wrapm(y - 1 + ((k >> 1) & 1), N),
                 ez = wrapm(z - 1 + ((k >> 2) & 1), N);
@@ -1428,7 +1534,7 @@ __global__ void k_diagonal(LevelView<T> L, T* __restrict__ diag) {
     }
     const int a = 7 - k;
 #pragma unroll
-    for (int q = 0; q < D; ++q) acc[q] += Km[(a * D + q) * M + a * D + q];
+    for (int q = 0; q < D; ++q) acc[q] += sc * Km[(a * D + q) * M + a * D + q];
   }
 #pragma unroll
   for (int q = 0; q < D; ++q) diag[(size_t)i * D + q] = acc[q];
@@ -1454,8 +1560,10 @@ __global__ void k_expand_elem(LevelView<double> L, int n_e, const int* __restric
 }
 
 // f_i = sum over active octant elements of the rows of f_e = K_e X0 at i's corner
-__global__ void k_load_vector(const int* __restrict__ node_lin, const uint8_t* __restrict__ occ8, int n_n,
-                              int D, int C, const double* __restrict__ fe, double* __restrict__ f) {
+// (density hierarchy: each octant element's rows weighted by its stiffness scale)
+__global__ void k_load_vector(const int* __restrict__ node_lin, const uint8_t* __restrict__ occ8,
+                              const double* __restrict__ oscale, int n_n, int D, int C, const double* __restrict__ fe,
+                              double* __restrict__ f) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n_n) return;
   const unsigned occ = occ8[i];
@@ -1463,9 +1571,156 @@ __global__ void k_load_vector(const int* __restrict__ node_lin, const uint8_t* _
     for (int q = 0; q < D; ++q) {
       double s = 0.0;
       for (int k = 0; k < 8; ++k)
-        if (occ & (1u << k)) s += fe[((7 - k) * D + q) * C + c];
+        if (occ & (1u << k)) s += (oscale ? oscale[(size_t)i * 8 + k] : 1.0) * fe[((7 - k) * D + q) * C + c];
       f[vix(c, n_n, i, D, q)] = s;
     }
+}
+
+// ---------------------------------------------------------------- density (SIMP) cells, App. F.3
+
+__global__ void k_density_flags(const double* __restrict__ rho, size_t n, double prune, uint8_t* __restrict__ vox) {
+  const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) vox[i] = rho[i] > prune ? 1 : 0;
+}
+
+__global__ void k_element_scale(const int* __restrict__ elem_lin, int n_e, const double* __restrict__ rho, double p,
+                                double rho_min, double* __restrict__ erho, double* __restrict__ escale) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n_e) return;
+  const double r = rho[elem_lin[e]];
+  erho[e] = r;
+  escale[e] = rho_min + pow(r, p);
+}
+
+// o[i][k] = scale of octant element k of node i (element (x-1+a, y-1+b, z-1+c), k = a+2b+4c), 0 if inactive
+__global__ void k_node_oscale(const int* __restrict__ node_lin, int n_n, const int* __restrict__ emap, int N,
+                              const double* __restrict__ escale, double* __restrict__ o64, float* __restrict__ o32) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n_n) return;
+  const int lin = node_lin[i];
+  const int x = lin % N, y = (lin / N) % N, z = lin / (N * N);
+  for (int k = 0; k < 8; ++k) {
+    const int ex = wrapm(x - 1 + (k & 1), N), ey = wrapm(y - 1 + ((k >> 1) & 1), N),
+              ez = wrapm(z - 1 + ((k >> 2) & 1), N);
+    const int eid = emap[ex + N * (ey + N * ez)];
+    const double v = eid >= 0 ? escale[eid] : 0.0;
+    o64[(size_t)i * 8 + k] = v;
+    o32[(size_t)i * 8 + k] = (float)v;
+  }
+}
+
+__global__ void k_iota(int* __restrict__ a, int n) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) a[i] = i;
+}
+
+// One thread per active element: d_j = X0_j - u_e,j (corner values of case j),
+// y_j = K0 d_j, E_ij = d_i . y_j; dC[lin][i][j] = g E_ij and dJ[lin] = g sum_ij G_ij E_ij
+// with g = p rho^(p-1) / N^3 (App. F.3).  u in the ABI layout [n][C][D].
+template <int D, int C>
+__global__ __launch_bounds__(kBlock) void k_simp_sensitivity(const int* __restrict__ elem_lin, int n_e,
+                                                             const int* __restrict__ node_map, int N,
+                                                             const double* __restrict__ u,
+                                                             const double* __restrict__ Ke,
+                                                             const double* __restrict__ X0,
+                                                             const double* __restrict__ erho, double p,
+                                                             const double* __restrict__ G, double* __restrict__ dJ,
+                                                             double* __restrict__ dC) {
+  constexpr int M = 8 * D;
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n_e) return;
+  const int lin = elem_lin[e];
+  const int x = lin % N, y = (lin / N) % N, z = lin / (N * N);
+  int nd[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+    nd[a] = node_map[wrapm(x + (a & 1), N) + N * (wrapm(y + ((a >> 1) & 1), N) + N * wrapm(z + (a >> 2), N))];
+  const cptr<double> K = as_const(Ke);
+  const cptr<double> X = as_const(X0);
+  double E[C][C];
+#pragma unroll 1
+  for (int j = 0; j < C; ++j) {
+    double dj[M], yj[M];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int q = 0; q < D; ++q) dj[a * D + q] = X[(a * D + q) * C + j] - u[((size_t)nd[a] * C + j) * D + q];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) t = fma(K[r * M + k], dj[k], t);
+      yj[r] = t;
+    }
+#pragma unroll 1
+    for (int i = 0; i < C; ++i) {
+      double t = 0.0;
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int q = 0; q < D; ++q)
+          t = fma(X[(a * D + q) * C + i] - u[((size_t)nd[a] * C + i) * D + q], yj[a * D + q], t);
+      E[i][j] = t;
+    }
+  }
+  const double r = erho[e];
+  const double g = p * pow(r, p - 1.0) / ((double)N * N * N);
+  double sJ = 0.0;
+#pragma unroll
+  for (int i = 0; i < C; ++i)
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      if (dC) dC[((size_t)lin * C + i) * C + j] = g * E[i][j];
+      if (G) sJ = fma(G[i * C + j], E[i][j], sJ);
+    }
+  if (dJ) dJ[lin] = g * sJ;
+}
+
+// Sensitivity filter on the dense periodic grid (x fastest):
+// out_e = sum_f H_ef rho_f dc_f / (max(gamma, rho_e) sum_f H_ef), H_ef = max(0, rmin - |x_e - x_f|)
+__global__ void k_simp_filter(const double* __restrict__ rho, const double* __restrict__ dc, int N, double rmin,
+                              int r, double gamma, double* __restrict__ out) {
+  const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  const size_t n3 = (size_t)N * N * N;
+  if (e >= n3) return;
+  const int x = (int)(e % N), y = (int)((e / N) % N), z = (int)(e / ((size_t)N * N));
+  double num = 0.0, den = 0.0;
+  for (int dz = -r; dz <= r; ++dz)
+    for (int dy = -r; dy <= r; ++dy)
+      for (int dx = -r; dx <= r; ++dx) {
+        const double h = rmin - sqrt((double)(dx * dx + dy * dy + dz * dz));
+        if (h <= 0.0) continue;
+        const size_t f = (size_t)wrapm(x + dx, N) + (size_t)N * (wrapm(y + dy, N) + (size_t)N * wrapm(z + dz, N));
+        num += h * rho[f] * dc[f];
+        den += h;
+      }
+  out[e] = num / (fmax(gamma, rho[e]) * den);
+}
+
+// OC update of element i for multiplier lam, clipped to the move limit and [lo, 1];
+// per-block sums of the updated densities into partial[blockIdx.x]
+__global__ __launch_bounds__(kBlock) void k_oc_eval(const double* __restrict__ rho, const double* __restrict__ dc,
+                                                    size_t n, double lam, double move, double eta, double lo,
+                                                    double* __restrict__ out, double* __restrict__ partial) {
+  __shared__ double sh[kBlock / 64];
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    const double r = rho[i];
+    const double B = fmax(-dc[i], 0.0);
+    const double cand = r * pow(B / lam, eta);
+    const double v = fmin(fmin(1.0, r + move), fmax(cand, fmax(lo, r - move)));
+    if (out) out[i] = v;
+    acc += v;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < kBlock / 64; ++k) t += sh[k];
+    partial[blockIdx.x] = t;
+  }
 }
 
 // counter-based uniform(-1,1) values (splitmix64 finaliser of seed + index)
@@ -1591,11 +1846,11 @@ static void launch_coarse(const LevelView<T>& L, int kind, int rows, const T* u,
 template <typename T, int D, int C, int EPI>
 static void apply_dispatch_kind(const LevelView<T>& L, int kind, const T* u, const EpiArgs<T>& e, hipStream_t s) {
   if (kind == KIND_SHARED) {
-    if (L.cb >= 5 && L.cb <= 7) {  // boundary as a register-assembled masked stencil
+    if (L.cb >= 5 && L.cb <= 8) {  // boundary as a register-assembled masked stencil
       if (L.n_int > 0) {
         if (L.cb == 5)
           hipLaunchKernelGGL((k_apply_interior<T, D, EPI>), dim3(blocks_for(L.n_int)), dim3(kBlock), 0, s, L, C, u, e);
-        else if (L.cb == 7)
+        else if (L.cb == 7 || L.cb == 8)
           hipLaunchKernelGGL((k_apply_interior<T, D, EPI, 1>), dim3(blocks_for(L.n_int)), dim3(kBlock), 0, s, L, C, u, e);
         else
           hipLaunchKernelGGL((k_apply_interior_nc<T, D, C, EPI>), dim3(blocks_for(L.n_int)), dim3(kBlock), 0, s, L, u,
@@ -1606,7 +1861,10 @@ static void apply_dispatch_kind(const LevelView<T>& L, int kind, const T* u, con
         // but the live set stays small (with several cases per thread the
         // compiler hoists every neighbour's loads and spills)
         const dim3 g(blocks_for(L.n_bnd), C);
-        if (L.cb == 7)
+        if (L.cb == 8)  // all cases per thread: one assembly per node
+          hipLaunchKernelGGL((k_apply_boundary_all<T, D, C, EPI>), dim3(blocks_for(L.n_bnd)), dim3(kBlock), 0, s, L,
+                             u, e);
+        else if (L.cb == 7)
           hipLaunchKernelGGL((k_apply_boundary_cls<T, D, 1, EPI, 1>), g, dim3(kBlock), 0, s, L, u, e);
         else
           hipLaunchKernelGGL((k_apply_boundary_cls<T, D, 1, EPI>), g, dim3(kBlock), 0, s, L, u, e);
@@ -1992,15 +2250,15 @@ void launch_prol_maps(const int* node_lin, int n_n, int Nf, const int* cmap, int
 }
 
 void launch_galerkin(const int* elem_lin_c, int n_e_c, int Nc, const int* emap_f, const uint8_t* cmask_f,
-                     const double* Ksrc, int src_kind, int D, const double* Ps, double* out64, float* out32,
-                     hipStream_t s) {
+                     const double* Ksrc, int src_kind, int D, const double* Ps, const double* fscale, double* out64,
+                     float* out32, hipStream_t s) {
   if (!n_e_c) return;
   if (D == 3)
     hipLaunchKernelGGL(k_galerkin<3>, dim3(n_e_c), dim3(kBlock), 0, s, elem_lin_c, Nc, emap_f, cmask_f, Ksrc,
-                       src_kind, Ps, out64, out32);
+                       src_kind, Ps, fscale, out64, out32);
   else
     hipLaunchKernelGGL(k_galerkin<1>, dim3(n_e_c), dim3(kBlock), 0, s, elem_lin_c, Nc, emap_f, cmask_f, Ksrc,
-                       src_kind, Ps, out64, out32);
+                       src_kind, Ps, fscale, out64, out32);
   GMT_LAUNCH_CHECK();
 }
 
@@ -2041,10 +2299,74 @@ void launch_expand_elem_matrices(const LevelView<double>& L, int kind, int n_e, 
   GMT_LAUNCH_CHECK();
 }
 
-void launch_load_vector(const int* node_lin, const uint8_t* occ8, int n_n, int D, int C, const double* fe,
-                        double* f, hipStream_t s) {
+void launch_load_vector(const int* node_lin, const uint8_t* occ8, const double* oscale, int n_n, int D, int C,
+                        const double* fe, double* f, hipStream_t s) {
   if (!n_n) return;
-  hipLaunchKernelGGL(k_load_vector, dim3(blocks_for(n_n)), dim3(kBlock), 0, s, node_lin, occ8, n_n, D, C, fe, f);
+  hipLaunchKernelGGL(k_load_vector, dim3(blocks_for(n_n)), dim3(kBlock), 0, s, node_lin, occ8, oscale, n_n, D, C,
+                     fe, f);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_density_flags(const double* rho, size_t n, double prune, uint8_t* vox, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_density_flags, dim3(blocks_for(n)), dim3(kBlock), 0, s, rho, n, prune, vox);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_element_scale(const int* elem_lin, int n_e, const double* rho, double p, double rho_min, double* erho,
+                          double* escale, hipStream_t s) {
+  if (!n_e) return;
+  hipLaunchKernelGGL(k_element_scale, dim3(blocks_for(n_e)), dim3(kBlock), 0, s, elem_lin, n_e, rho, p, rho_min, erho,
+                     escale);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_node_oscale(const int* node_lin, int n_n, const int* elem_map, int N, const double* escale, double* o64,
+                        float* o32, hipStream_t s) {
+  if (!n_n) return;
+  hipLaunchKernelGGL(k_node_oscale, dim3(blocks_for(n_n)), dim3(kBlock), 0, s, node_lin, n_n, elem_map, N, escale,
+                     o64, o32);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_iota(int* a, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_iota, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, n);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_simp_sensitivity(const int* elem_lin, int n_e, const int* node_map, int N, int D, int C, const double* u,
+                             const double* Ke, const double* X0, const double* erho, double p, const double* G,
+                             double* dJ, double* dC, hipStream_t s) {
+  if (!n_e) return;
+  const unsigned g = blocks_for(n_e);
+  if (D == 3 && C == 6)
+    hipLaunchKernelGGL((k_simp_sensitivity<3, 6>), dim3(g), dim3(kBlock), 0, s, elem_lin, n_e, node_map, N, u, Ke, X0,
+                       erho, p, G, dJ, dC);
+  else if (D == 1 && C == 3)
+    hipLaunchKernelGGL((k_simp_sensitivity<1, 3>), dim3(g), dim3(kBlock), 0, s, elem_lin, n_e, node_map, N, u, Ke, X0,
+                       erho, p, G, dJ, dC);
+  else
+    fail(GMT_E_INVAL, "sensitivity for (d, c) = (%d, %d) not instantiated", D, C);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_simp_filter(const double* rho, const double* dc, int N, double rmin, double gamma, double* out,
+                        hipStream_t s) {
+  const size_t n3 = (size_t)N * N * N;
+  if (!n3) return;
+  const int r = (int)std::ceil(rmin) - 1;
+  hipLaunchKernelGGL(k_simp_filter, dim3(blocks_for(n3)), dim3(kBlock), 0, s, rho, dc, N, rmin, r, gamma, out);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_oc_eval(const double* rho, const double* dc, size_t n, double lam, double move, double eta, double lo,
+                    double* out, double* partial, double* total, hipStream_t s) {
+  if (!n) return;
+  const unsigned g = std::min<unsigned>(kRedBlocks, blocks_for(n));
+  hipLaunchKernelGGL(k_oc_eval, dim3(g), dim3(kBlock), 0, s, rho, dc, n, lam, move, eta, lo, out, partial);
+  GMT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, partial, (int)g, 1, total);
   GMT_LAUNCH_CHECK();
 }
 

@@ -688,6 +688,7 @@ void nn_release(Hier& h) {
 }
 
 void nn_setup(Hier& h, const gmt_nn_config& cfg, hipStream_t s) {
+  if (h.density) fail(GMT_E_INVAL, "the network takes binary occupancy: not a density hierarchy");
   // the network runs on the finest cfg.levels levels of the hierarchy (all of them, or the
   // top of a deeper hierarchy: a network trained at one resolution on a finer cell)
   if (cfg.levels < 2 || cfg.levels > h.L || cfg.levels > GMT_NN_MAX_LEVELS)

@@ -87,19 +87,40 @@ def test_load_vector(pair):
     assert np.abs(f32 - P.f).max() <= 1e-6 * np.abs(P.f).max()
 
 
-@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-13), (torch.float32, 2e-6)])
-def test_apply_K_every_level(pair, dtype, tol):
+# Forward-error bound of a computed row of K.u (or f - K.u): a row is a sum of at most
+# 27 x 3 products of assembled coefficients (each a sum over at most 8 element
+# matrices) and vector values, with the inputs and the element matrices rounded to the
+# working precision, so |computed - exact| <= gamma_n sum_e sum_j |K_e,ij| |u_j|
+# (+ |f_i| for the residual) with n = 81 + 8 + 3 <= 100 and gamma_n = n u / (1 - n u),
+# u the unit roundoff.  The bound is per entry; the tests assert it element by element.
+def _gamma(dtype, n=100):
+    u = 2.0 ** -24 if dtype == torch.float32 else 2.0 ** -53
+    return n * u / (1 - n * u)
+
+
+def _fwd_bound(P, l, u, dtype, f=None):
+    b = oops.apply_K(P.levels[l], np.abs(P.mats[l]), np.abs(u))
+    return _gamma(dtype) * (b if f is None else b + np.abs(f))
+
+
+def _within(got, ref, bound, what):
+    worst = float(np.max(np.abs(got - ref) / np.maximum(bound, 1e-300)))
+    print(f"[bound] {what}: max |err| / bound = {worst:.3f}", flush=True)
+    assert worst <= 1.0, (what, worst)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_apply_K_every_level(pair, dtype):
     name, vox, P, H = pair
     for l in range(1, P.L + 1):
         n = P.levels[l - 1].n_n
         u = random_vectors(n, P.c * P.d, 100 + l).reshape(n, P.c, P.d)
         y = _np(H.apply_K(_t(u, dtype), l)).astype(np.float64)
         ref = oops.apply_K(P.levels[l - 1], P.mats[l - 1], u)
-        scale = np.abs(ref).max()
-        assert np.abs(y - ref).max() <= tol * scale * 50, (l, np.abs(y - ref).max() / scale)
-        r = _np(H.residual(_t(P.f if l == 1 else u, dtype), _t(u, dtype), l)).astype(np.float64)
+        _within(y, ref, _fwd_bound(P, l - 1, u, dtype), f"{name} K.u level {l} {dtype}")
         fr = P.f if l == 1 else u
-        assert np.abs(r - (fr - ref)).max() <= tol * scale * 50
+        r = _np(H.residual(_t(fr, dtype), _t(u, dtype), l)).astype(np.float64)
+        _within(r, fr - ref, _fwd_bound(P, l - 1, u, dtype, fr), f"{name} residual level {l} {dtype}")
 
 
 def test_transfers(pair):
@@ -149,7 +170,7 @@ def test_smoother(pair, smoother):
     assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 5, 6, 7])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 5, 6, 7, 8])
 def test_level1_sweep_variants(pair, variant, monkeypatch):
     """Every level-1 kernel variant the autotuner may pick (all cases per neighbour load with
     the boundary as a masked stencil or element by element; one case per pass, with the
@@ -162,12 +183,11 @@ def test_level1_sweep_variants(pair, variant, monkeypatch):
     n = P.levels[0].n_n
     u0 = random_vectors(n, P.c * P.d, 31).reshape(n, P.c, P.d)
     ref = oops.apply_K(P.levels[0], P.mats[0], u0)
-    scale = np.abs(ref).max()
-    for dtype, tol in ((torch.float64, 1e-13), (torch.float32, 2e-6)):
+    for dtype in (torch.float64, torch.float32):
         y = _np(H.apply_K(_t(u0, dtype), 1)).astype(np.float64)
-        assert np.abs(y - ref).max() <= tol * scale * 50, (variant, dtype)
+        _within(y, ref, _fwd_bound(P, 0, u0, dtype), f"{name} variant {variant} K.u {dtype}")
         r = _np(H.residual(_t(P.f, dtype), _t(u0, dtype), 1)).astype(np.float64)
-        assert np.abs(r - (P.f - ref)).max() <= tol * scale * 50, (variant, dtype)
+        _within(r, P.f - ref, _fwd_bound(P, 0, u0, dtype, P.f), f"{name} variant {variant} residual {dtype}")
     out = _np(H.smooth(_t(P.f), _t(u0), 3, "jacobi", 0.6 / lam[0]))
     assert np.abs(out - osolve.jacobi(P, 0, u0, P.f, 3, 0.6 / lam[0])).max() <= 1e-12 * np.abs(out).max()
     lo, hi = lam[0] / 30, 1.1 * lam[0]
@@ -187,10 +207,9 @@ def test_coarse_sweep_variants(pair, variant, monkeypatch):
         n = P.levels[l - 1].n_n
         u0 = random_vectors(n, P.c * P.d, 51 + l).reshape(n, P.c, P.d)
         ref = oops.apply_K(P.levels[l - 1], P.mats[l - 1], u0)
-        scale = np.abs(ref).max()
-        for dtype, tol in ((torch.float64, 1e-13), (torch.float32, 2e-6)):
+        for dtype in (torch.float64, torch.float32):
             y = _np(H.apply_K(_t(u0, dtype), l)).astype(np.float64)
-            assert np.abs(y - ref).max() <= tol * scale * 50, (l, variant, dtype)
+            _within(y, ref, _fwd_bound(P, l - 1, u0, dtype), f"{name} coarse variant {variant} level {l} {dtype}")
         lo, hi = lam[l - 1] / 30, 1.1 * lam[l - 1]
         fl = random_vectors(n, P.c * P.d, 61 + l).reshape(n, P.c, P.d)
         out = _np(H.smooth(_t(fl), _t(u0), 2, "chebyshev", lo, hi, level=l))

@@ -70,12 +70,12 @@ def test_gauss_seidel_sweeps_every_level(pair, omega):
 
 
 def test_gauss_seidel_on_every_level1_variant(pair, monkeypatch):
-    """The colour classes of level 1 run through the list-driven sweep variants (5, 6, 7)."""
+    """The colour classes of level 1 run through the list-driven sweep variants (5, 6, 7, 8)."""
     name, vox, P, H = pair
     n = P.levels[0].n_n
     u0 = random_vectors(n, P.c * P.d, 91).reshape(n, P.c, P.d)
     ref = osolve.gauss_seidel(P, 0, u0, P.f, 1, 1.0)
-    for variant in (0, 1, 2, 3, 5, 6, 7):
+    for variant in (0, 1, 2, 3, 5, 6, 7, 8):
         monkeypatch.setenv("GMT_FORCE_L1_VARIANT", str(variant))
         out = _np(H.smooth(_t(P.f), _t(u0), 1, "gs", 1.0, 0.0))
         assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max(), variant
