@@ -14,7 +14,8 @@ the plain path's time and the gain, DOF-solves/s, C_H of both paths against an
 FP64 solve, "roofline" for the level-1 Chebyshev sweep on this cell (372
 algorithmic bytes per node over its duration, timed with HIP events on the
 launch stream, against 8 TB/s), "extras" (the 512^3 spinodal, seed 30000, once
-per path; the mixed-precision versus all-FP64 batch of 64 cells at 128^3), and
+per path; the mixed-precision versus all-FP64 batch of 64 cells at 128^3; an
+uneven batch of 40 cells of sizes 64^3..256^3, half elastic, half thermal), and
 "cpu_baseline" (the CPU FP64 oracle on a bounded sample, scaled to this cell).
 
 Other workloads: --workload cells128 (the 64-cell 128^3 batch, plain path) and
@@ -47,7 +48,10 @@ COPY_BYTES = 512 << 20
 # kernels, each scaled by what the counter reports for a copy of known size; keyed by (workload,
 # sweep variant, SHA-256 prefix of the kernel source the counters were taken on), so that a changed
 # kernel reports null until it is profiled again.
-SWEEP_TRAFFIC_BYTES = {}
+SWEEP_TRAFFIC_BYTES = {
+    # profiles/level1_chebyshev_sweep_gyroid512_hbm_traffic.txt
+    ("gyroid512_seed30001", 7, "23f2fd2b7604ee6f"): (27_780_058 + 5_212_515) * 1024,
+}
 SWEEP_KERNELS = {
     0: "k_apply_interior_nc + k_apply_boundary_st",
     1: "k_apply_interior + k_apply_boundary",
@@ -56,6 +60,7 @@ SWEEP_KERNELS = {
     5: "k_apply_interior + k_apply_boundary_cls",
     6: "k_apply_interior_nc + k_apply_boundary_cls",
     7: "k_apply_interior<PRE=1> + k_apply_boundary_cls<PRE=1>",
+    8: "k_apply_interior<PRE=1> + k_apply_boundary_all",
 }
 WEIGHTS = os.path.join(ROOT, "paper_2604_26518_amd", "weights", "unet128_elastic.npz")
 HEADLINE = {"family": "gyroid", "N": 512, "seed": 30001, "vf": 0.25}
@@ -64,8 +69,13 @@ UNEVEN_SIZES = (64, 96, 128, 192, 256)
 
 
 def kernel_source_hash() -> str:
+    """SHA-256 prefix of the operator-sweep section of the kernel source (the level-1 sweep
+    kernels and their epilogues), the code the stored counter figures describe."""
     with open(os.path.join(ROOT, "paper_2604_26518_amd", "csrc", "kernels.hip"), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+        src = fh.read()
+    a = src.index(b"// ---------------------------------------------------------------- operator sweeps")
+    b = src.index(b"// ---------------------------------------------------------------- transfers")
+    return hashlib.sha256(src[a:b]).hexdigest()[:16]
 
 
 # --------------------------------------------------------------------------- host-side inputs
@@ -253,6 +263,7 @@ def cell512(args):
     if args.extras:
         jobs["spinodal"] = pool.apply_async(_gen_named, (dict(SPINODAL, N=args.N),))
         jobs["c2"] = pool.map_async(_gen, [(s, 128) for s in range(1000, 1000 + args.c2_cells)])
+        jobs["uneven"] = pool.map_async(_gen_uneven, range(2000, 2000 + args.uneven_cells), chunksize=1)
     if not args.no_cpu_baseline:
         jobs["cpu"] = pool.apply_async(cpu_baseline_sample, (args.tol,))
     res = {k: j.get() for k, j in jobs.items()}
@@ -374,6 +385,19 @@ def cell512(args):
         out["extras"]["mixed_vs_fp64_128"] = mixed_vs_fp64(B, res["c2"], B.default_levels(128), args.tol,
                                                            args.max_iter, args.workers)
         print("# mixed vs FP64 batch done", file=sys.stderr, flush=True)
+        cells = res["uneven"]
+        wall_u, solve_u, dofs_u, its_u, failed_u = run_uneven(B, cells, args.tol, args.max_iter, args.workers,
+                                                              True, args.mem_gb)
+        out["extras"]["uneven_batch"] = {
+            "workload": f"{len(cells)} cells (seeds 2000..{1999 + len(cells)}), N over {list(UNEVEN_SIZES)}, mixed "
+                        f"families, even seeds elastic (6 cases), odd seeds thermal (3 cases), one gmt_solve_batch "
+                        f"call per memory chunk (captured-graph PCG blocks with device-side convergence flags), "
+                        f"FP32 bulk + FP64 refinement to {args.tol:g}, whole path incl. build and C_H",
+            "ms_per_cell": round(wall_u / len(cells) * 1e3, 2),
+            "ms_per_cell_solve_only": round(solve_u / len(cells) * 1e3, 2),
+            "dof_solves_per_s": round(dofs_u / wall_u, 1), "iterations_mean": float(np.mean(its_u)),
+            "iterations_max": int(np.max(its_u)), "not_converged": failed_u}
+        print("# uneven batch done", file=sys.stderr, flush=True)
     if "cpu" in res:
         cb = res["cpu"]
         scale = n_n / cb["n_n"]
@@ -455,6 +479,44 @@ def cells128(args):
     print(json.dumps(out), flush=True)
 
 
+def run_uneven(B, cells, tol, max_iter, workers, graph, mem_gb):
+    """One pass over uneven cells: hierarchies built in memory-bounded chunks, each chunk one
+    gmt_solve_batch call (FP32 bulk + FP64 refinement), C_H per cell.
+    Returns (wall_s, solve_s, dof_solves, iterations, not_converged)."""
+    import torch
+    budget = mem_gb * 2**30
+    order = sorted(range(len(cells)), key=lambda k: -cells[k][3].size)
+    failed = []
+    t_all = time.perf_counter()
+    solve_s, dofs, its, k = 0.0, 0, [], 0
+    while k < len(order):
+        hs, fs, idx = [], [], []
+        while k < len(order) and (not hs or torch.cuda.memory_allocated() < budget):
+            seed, fam, vf, vox, phys = cells[order[k]]
+            H = B.Hierarchy(vox, B.default_levels(vox.shape[0]), phys)
+            hs.append(H)
+            fs.append(H.load_vector())
+            idx.append(order[k])
+            k += 1
+        _sync()
+        ts = time.perf_counter()
+        us, reps = B.solve_batch(hs, fs, tol=tol, precision="f32", max_iter=max_iter, max_outer=16,
+                                 n_workers=workers, graph=graph, raise_on_noconv=False)
+        solve_s += time.perf_counter() - ts
+        for H, u, rep, j in zip(hs, us, reps, idx):
+            H.homogenize(u)
+            if not rep["converged"]:
+                failed.append({"seed": cells[j][0], "N": H.N, "physics": H.physics,
+                               "residual": max(rep["rel_res"]), "iterations": rep["iterations"]})
+            dofs += H.n_n(1) * H.c * H.d
+            its.append(rep["iterations"])
+            H.close()
+        del us, fs, hs
+        print(f"# {k}/{len(order)} uneven cells done", file=sys.stderr, flush=True)
+    _sync()
+    return time.perf_counter() - t_all, solve_s, dofs, its, failed
+
+
 def uneven(args):
     """256 cells, N uniform over {64, 96, 128, 192, 256}, mixed families, even seeds elastic (6
     cases) and odd seeds thermal (3 cases), FP32 bulk + FP64 refinement to 1e-5; cells go to
@@ -470,47 +532,12 @@ def uneven(args):
     _finish(pool)
     print(f"# generated {len(cells)} uneven cells in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
-    budget = args.mem_gb * 2**30
-    failed = []
-
-    def run():
-        order = sorted(range(len(cells)), key=lambda k: -cells[k][3].size)
-        t_all = time.perf_counter()
-        solve_s, dofs, its, k = 0.0, 0, [], 0
-        while k < len(order):
-            hs, fs, idx = [], [], []
-            while k < len(order) and (not hs or torch.cuda.memory_allocated() < budget):
-                seed, fam, vf, vox, phys = cells[order[k]]
-                H = B.Hierarchy(vox, B.default_levels(vox.shape[0]), phys)
-                hs.append(H)
-                fs.append(H.load_vector())
-                idx.append(order[k])
-                k += 1
-            _sync()
-            ts = time.perf_counter()
-            us, reps = B.solve_batch(hs, fs, tol=args.tol, precision="f32", max_iter=args.max_iter,
-                                     max_outer=16, n_workers=args.workers, graph=not args.no_graph,
-                                     raise_on_noconv=False)
-            solve_s += time.perf_counter() - ts
-            for H, u, rep, j in zip(hs, us, reps, idx):
-                H.homogenize(u)
-                if not rep["converged"]:
-                    failed.append({"seed": cells[j][0], "N": H.N, "physics": H.physics,
-                                   "residual": max(rep["rel_res"]), "iterations": rep["iterations"]})
-                dofs += H.n_n(1) * H.c * H.d
-                its.append(rep["iterations"])
-                H.close()
-            del us, fs, hs
-            print(f"# {k}/{len(order)} cells done", file=sys.stderr, flush=True)
-        _sync()
-        return time.perf_counter() - t_all, solve_s, dofs, its
-
     for _ in range(args.warmup):
-        run()
-    wall, solve_s, dofs, its = 0.0, 0.0, 0, []
+        run_uneven(B, cells, args.tol, args.max_iter, args.workers, not args.no_graph, args.mem_gb)
+    wall, solve_s, dofs, its, failed = 0.0, 0.0, 0, [], []
     for _ in range(args.steps):
-        a, b, c, d = run()
-        wall, solve_s, dofs, its = wall + a, solve_s + b, dofs + c, its + d
+        a, b, c, d, e = run_uneven(B, cells, args.tol, args.max_iter, args.workers, not args.no_graph, args.mem_gb)
+        wall, solve_s, dofs, its, failed = wall + a, solve_s + b, dofs + c, its + d, failed + e
     ncell = args.steps * len(cells)
     out = {"metric": "ms per cell, uneven batched solve to 1e-5 (whole path incl. build and C_H)",
            "value": round(wall / ncell * 1e3, 3), "unit": "ms/cell", "n_gpus": 1, "steps": args.steps,
@@ -542,6 +569,7 @@ def main():
     ap.add_argument("--no-extras", dest="extras", action="store_false",
                     help="cell512: skip the spinodal cell and the mixed-vs-FP64 128^3 batch")
     ap.add_argument("--c2-cells", type=int, default=64)
+    ap.add_argument("--uneven-cells", type=int, default=40, help="cell512 extras: cells of the uneven batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workers", type=int, default=4, help="host threads / streams of the batched solve")
     ap.add_argument("--no-graph", action="store_true", help="launch PCG kernel by kernel")

@@ -197,8 +197,13 @@ template <typename Tin, typename Tout>
 void launch_aos_to_soa(const Tin* a, Tout* b, int n, int C, int D, hipStream_t s);
 template <typename Tin, typename Tout>
 void launch_soa_to_aos(const Tin* a, Tout* b, int n, int C, int D, hipStream_t s);
-void launch_pcg_alpha(const double* rz, const double* pq, double* alpha, int C, hipStream_t s);
-void launch_pcg_beta(const double* rz_new, double* rz, double* beta, int C, hipStream_t s);
+// stop (nullable): device convergence flag; when set, alpha = beta = 0
+void launch_pcg_alpha(const double* rz, const double* pq, double* alpha, int C, hipStream_t s,
+                      const double* stop = nullptr);
+void launch_pcg_beta(const double* rz_new, double* rz, double* beta, int C, hipStream_t s,
+                     const double* stop = nullptr);
+// flags: [0] stop, [1] iterations run, [2 + m] squared residual target of case m
+void launch_pcg_check(const double* rr, int C, double* flags, hipStream_t s);
 template <typename T>
 void launch_gauge_shift(T* u, int n, int Q, int D, T* tmp, hipStream_t s);
 // v -= column mean over nodes (projection off the rigid translations)
@@ -343,6 +348,9 @@ struct Hier {
   double* f64 = nullptr;      // load vector (level 1)
   double* red_partial = nullptr;
   double* red_out = nullptr;  // small device scratch for reductions / PCG scalars
+  double* pcg_flags = nullptr;  // device convergence flags of the captured PCG blocks (16 values)
+  double* pcg_status = nullptr; // pinned host copies of [stop, iterations, ||r_m||^2 x 8], two slots
+  hipEvent_t pcg_ev[2] = {nullptr, nullptr};  // completion of the block whose status is in each slot
   double* gauge_tmp64 = nullptr;
   float* gauge_tmp32 = nullptr;
   Work<float> w32;

@@ -92,6 +92,9 @@ void Hier::release_graphs() {
 }
 
 void Hier::release_all() {
+  for (hipEvent_t& e : pcg_ev)
+    if (e) (void)hipEventDestroy(e), e = nullptr;
+  if (pcg_status) (void)hipHostFree(pcg_status), pcg_status = nullptr;
   for (void* q : owned)
     if (p.release) p.release(q, p.alloc_ctx);
   owned.clear();
@@ -1005,19 +1008,40 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
     return done;
   };
   if (graph) {
+    // Device-side convergence: flags [0] stop, [1] iterations run, [2 + m] the
+    // squared target of case m.  Every captured iteration ends with ||r_m||^2 and
+    // k_pcg_check, which sets the stop flag once every case meets its target;
+    // from then on alpha = beta = 0, so the rest of a block (and a block
+    // launched ahead) leaves x and r unchanged.
+    if (!h.pcg_flags) h.pcg_flags = h.alloc<double>(16);
+    if (!h.pcg_status) GMT_HIP(hipHostMalloc((void**)&h.pcg_status, 2 * 16 * sizeof(double), hipHostMallocDefault));
+    for (hipEvent_t& e : h.pcg_ev)
+      if (!e) GMT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    double* fl = h.pcg_flags;
+    {
+      double init[16] = {0};
+      for (int c = 0; c < C; ++c) {
+        const double t = tol[c] * std::sqrt(bn2[c]);
+        init[2 + c] = t * t;
+      }
+      GMT_HIP(hipMemcpyAsync(fl, init, sizeof(init), hipMemcpyHostToDevice, s));
+      GMT_HIP(hipStreamSynchronize(s));
+    }
     // one iteration after the initial preconditioning, as in the launch-by-launch
-    // loop below; a block ends with ||r_m||^2 for the host check
+    // loop below, ending with the residual norms and the convergence check
     auto step = [&](hipStream_t st) {
       apply<T>(h, 0, EPI_KU, W.pp, nullptr, W.pq, C, st);
       launch_dot<T>(W.pp, W.pq, n, C, D, h.red_partial, pq, st);
-      launch_pcg_alpha(rz, pq, alpha, C, st);
+      launch_pcg_alpha(rz, pq, alpha, C, st, fl);
       launch_pcg_update<T>(x, W.pr, W.pp, W.pq, alpha, n, Q, D, st);
       launch_project<T>(W.pr, n, Q, D, h.red_partial, sums, st);
       vc(st);
       launch_project<T>(W.pz, n, Q, D, h.red_partial, sums, st);
       launch_dot<T>(W.pr, W.pz, n, C, D, h.red_partial, rzn, st);
-      launch_pcg_beta(rzn, rz, beta, C, st);
+      launch_pcg_beta(rzn, rz, beta, C, st, fl);
       launch_pcg_direction<T>(W.pp, W.pz, beta, n, Q, D, st);
+      launch_dot<T>(W.pr, W.pr, n, C, D, h.red_partial, rr, st);
+      launch_pcg_check(rr, C, fl, st);
     };
     Hier::PcgGraphs& G = MIXED ? h.gmx : graphs_of<T>(h);
     std::vector<double> key = {(double)(uintptr_t)x, (double)cfg.nu1, (double)cfg.nu2, (double)cfg.smoother,
@@ -1031,7 +1055,6 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
       for (int k = 0; k < 2; ++k)
         G.exec[k] = capture_graph(h, [&](hipStream_t st) {
           for (int i = 0; i < steps[k]; ++i) step(st);
-          launch_dot<T>(W.pr, W.pr, n, C, D, h.red_partial, rr, st);
         });
       G.key = key;
     }
@@ -1041,30 +1064,76 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
       if (bn2[c] > 0 && tol[c] > 0) worst = std::max(worst, 1.0 / tol[c]);
     double prev = -1;
     int prev_k = 1;
-    while (it < maxit) {
-      // one iteration first; then four-iteration blocks while the observed
-      // convergence rate predicts more than four iterations to go
-      int k = 1;
-      if (prev > 0 && worst < prev && std::isfinite(worst) && maxit - it >= 4) {
-        const double rate = std::pow(worst / prev, 1.0 / prev_k);
-        if (rate < 1 && std::log(worst) / -std::log(rate) > 4.0) k = 4;
-      }
+    // Blocks of 1 or 4 iterations, each followed by an asynchronous copy of the
+    // flags and ||r_m||^2 into a pinned slot and an event.  While the observed
+    // convergence rate predicts more than four iterations beyond those already
+    // in flight, a second block is queued before the host waits for the first,
+    // so the GPU does not idle on the host round trip.
+    struct Pending {
+      int slot, k;
+    };
+    Pending q[2];
+    int nq = 0, launched = 0, inflight = 0, next_slot = 0;
+    auto remaining = [&]() -> double {  // predicted iterations to the target from the last observation
+      if (!(prev > 0 && worst < prev && std::isfinite(worst))) return 0.0;
+      const double rate = std::pow(worst / prev, 1.0 / prev_k);
+      if (!(rate < 1)) return 0.0;
+      return std::log(worst) / -std::log(rate);
+    };
+    auto launch_block = [&](int k) {
+      double* slot = h.pcg_status + 16 * next_slot;
       GMT_HIP(hipGraphLaunch(G.exec[k == 1 ? 0 : 1], s));
-      it += k;
+      GMT_HIP(hipMemcpyAsync(slot, fl, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      GMT_HIP(hipMemcpyAsync(slot + 2, rr, C * sizeof(double), hipMemcpyDeviceToHost, s));
+      GMT_HIP(hipEventRecord(h.pcg_ev[next_slot], s));
+      q[nq++] = {next_slot, k};
+      next_slot ^= 1;
+      launched += k;
+      inflight += k;
+    };
+    auto observe = [&]() -> bool {  // oldest block: true when its flag says stop
+      const Pending pb = q[0];
+      q[0] = q[1];
+      --nq;
+      GMT_HIP(hipEventSynchronize(h.pcg_ev[pb.slot]));
+      const double* slot = h.pcg_status + 16 * pb.slot;
+      it = (int)slot[1];
+      for (int c = 0; c < C; ++c) rr_h[c] = slot[2 + c];
+      inflight -= pb.k;
       prev = worst;
-      prev_k = k;  // (worst is refreshed by converged() below)
-      host_dot(h, rr, C, rr_h, s);
-      if (converged()) {
-        if (reached) *reached = true;
-        break;
+      prev_k = pb.k;
+      return slot[0] != 0.0;
+    };
+    try {
+      while (true) {
+        while (launched < maxit && nq < 2) {
+          const double rem = remaining() - inflight;
+          const int k = (rem > 4.0 && maxit - launched >= 4) ? 4 : 1;
+          if (nq > 0 && k == 1) break;  // near the target: one block at a time
+          launch_block(k);
+          if (k == 1) break;
+        }
+        if (nq == 0) break;  // maxit launched and observed
+        const bool stop = observe();
+        const bool done = converged();  // (fails on a non-finite residual)
+        if (stop || done) {
+          if (reached) *reached = true;
+          break;
+        }
+        if (worst < 0.98 * best) {
+          best = worst;
+          since_best = 0;
+        } else if ((since_best += prev_k) >= kStagnation) {
+          break;  // stagnation: hand back to the FP64 refinement loop
+        }
       }
-      if (worst < 0.98 * best) {
-        best = worst;
-        since_best = 0;
-      } else if ((since_best += k) >= kStagnation) {
-        break;  // stagnation: hand back to the FP64 refinement loop
-      }
+    } catch (...) {
+      (void)hipStreamSynchronize(s);
+      throw;
     }
+    // a block still in flight is gated once the flag is set; after a stagnation
+    // stop it runs on as ordinary iterations: wait for it and take its count
+    while (nq > 0) observe();
     return it;
   }
   while (it < maxit) {
@@ -2114,6 +2183,7 @@ gmt_status gmt_solve(gmt_hier_t H, const void* d_f, void* d_u, const gmt_solve_o
 static void prepare_solve(Hier& h, int prec, const gmt_solve_opts* o, hipStream_t s) {
   const size_t tot = (size_t)h.lv[0].n_n * h.Q;
   if (o && o->cycle.smoother == GMT_SMOOTH_GS) ensure_colours(h, s);
+  if (!h.pcg_flags) h.pcg_flags = h.alloc<double>(16);  // device convergence flags of the captured blocks
   scratch64(h, &h.s_f64s);
   scratch64(h, &h.s_u64s);
   scratch64(h, &h.s_r64);

@@ -1223,17 +1223,41 @@ __global__ void k_pcg_direction(T* __restrict__ p, const T* __restrict__ z, cons
   p[i] = fma(b, p[i], z[i]);
 }
 
-__global__ void k_pcg_alpha(const double* rz, const double* pq, double* alpha, int C) {
+// stop (nullable): the device-side convergence flag of captured PCG blocks; once
+// set, alpha = beta = 0 and the remaining iterations of a block change nothing
+__global__ void k_pcg_alpha(const double* rz, const double* pq, double* alpha, int C, const double* stop) {
   int c = threadIdx.x;
-  if (c < C) alpha[c] = (pq[c] > 0.0 && isfinite(rz[c] / pq[c])) ? rz[c] / pq[c] : 0.0;
+  const bool off = stop && *stop != 0.0;
+  if (c < C) alpha[c] = (!off && pq[c] > 0.0 && isfinite(rz[c] / pq[c])) ? rz[c] / pq[c] : 0.0;
 }
 
-__global__ void k_pcg_beta(const double* rz_new, double* rz, double* beta, int C) {
+__global__ void k_pcg_beta(const double* rz_new, double* rz, double* beta, int C, const double* stop) {
   int c = threadIdx.x;
   if (c < C) {
+    if (stop && *stop != 0.0) {
+      beta[c] = 0.0;
+      return;
+    }
     beta[c] = (rz[c] != 0.0 && isfinite(rz_new[c] / rz[c])) ? rz_new[c] / rz[c] : 0.0;
     rz[c] = rz_new[c];
   }
+}
+
+// End of a captured PCG iteration: flags[1] counts the iterations that ran with
+// the flag clear; flags[0] is set once every case meets ||r_m||^2 <= flags[2 + m]
+// (the squared target) or a residual is not finite (the host reports that).
+__global__ void k_pcg_check(const double* rr, int C, double* flags) {
+  if (threadIdx.x != 0 || flags[0] != 0.0) return;
+  flags[1] += 1.0;
+  bool done = true;
+  for (int c = 0; c < C; ++c) {
+    if (!isfinite(rr[c])) {
+      done = true;
+      break;
+    }
+    if (!(rr[c] <= flags[2 + c])) done = false;
+  }
+  if (done) flags[0] = 1.0;
 }
 
 template <typename T>
@@ -2141,13 +2165,18 @@ void launch_soa_to_aos(const Tin* a, Tout* b, int n, int C, int D, hipStream_t s
   GMT_LAUNCH_CHECK();
 }
 
-void launch_pcg_alpha(const double* rz, const double* pq, double* alpha, int C, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(64), 0, s, rz, pq, alpha, C);
+void launch_pcg_alpha(const double* rz, const double* pq, double* alpha, int C, hipStream_t s, const double* stop) {
+  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(64), 0, s, rz, pq, alpha, C, stop);
   GMT_LAUNCH_CHECK();
 }
 
-void launch_pcg_beta(const double* rz_new, double* rz, double* beta, int C, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(64), 0, s, rz_new, rz, beta, C);
+void launch_pcg_beta(const double* rz_new, double* rz, double* beta, int C, hipStream_t s, const double* stop) {
+  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(64), 0, s, rz_new, rz, beta, C, stop);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_pcg_check(const double* rr, int C, double* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(64), 0, s, rr, C, flags);
   GMT_LAUNCH_CHECK();
 }
 

@@ -59,7 +59,7 @@ class Trainer:
     """AdamW on FP32 master weights with a cosine schedule, global-norm clipping and an EMA copy."""
 
     def __init__(self, n_params, levels, physics="elastic", lr=1e-3, wd=1e-2, clip=1.0, ema=0.999, seed=0,
-                 lam=0.0, device="cuda"):
+                 lam=0.0, device="cuda", warmup=300):
         self.params = init_params(n_params, levels, physics, seed, device)
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
@@ -67,6 +67,7 @@ class Trainer:
         self.ema = self.params.clone()
         self.lr, self.wd, self.clip, self.ema_decay = lr, wd, clip, ema
         self.lam = lam
+        self.warmup = warmup
         self.step = 0
 
     def save(self, path):
@@ -79,8 +80,9 @@ class Trainer:
             getattr(self, name).copy_(ck[name].to(self.params.device))
         self.step = int(ck["step"])
 
-    def lr_at(self, k, total, warmup=300):
-        """Linear warm-up over `warmup` steps, then cosine decay to zero at `total`."""
+    def lr_at(self, k, total):
+        """Linear warm-up over the first `warmup` steps, then cosine decay to zero at `total`."""
+        warmup = self.warmup
         w = min(1.0, (k + 1) / warmup) if warmup > 0 else 1.0
         return self.lr * w * 0.5 * (1 + math.cos(math.pi * min(k, total) / max(total, 1)))
 

@@ -30,10 +30,15 @@ from .learned import Trainer, channels_for, save_weights
 
 
 def _gen(args):
+    """One workload cell, its voxels bit-packed (8x less host memory for thousands of cells)."""
     seed, N = args
     from gmt_inputs.lattices import workload_cell
     fam, vf, vox = workload_cell(N, seed)
-    return seed, fam, vf, vox
+    return seed, fam, vf, np.packbits(vox.ravel())
+
+
+def voxels(cell, N):
+    return np.unpackbits(cell[3])[: N ** 3].reshape(N, N, N)
 
 
 def make_cells(N, seeds, procs=16):
@@ -89,6 +94,8 @@ def main(argv=None):
                     help="gauge penalty on the per-component mean of u^1 (predictions are centred already)")
     ap.add_argument("--seed0", type=int, default=100000)
     ap.add_argument("--test-seed0", type=int, default=900000)
+    ap.add_argument("--init", default="", help="start from these exported (BF16) weights")
+    ap.add_argument("--warmup-steps", type=int, default=300)
     ap.add_argument("--ckpt", default="unet.pt")
     ap.add_argument("--resume", action="store_true")
     ap.add_argument("--export", default="", help="write the EMA weights (BF16) to this .npz at the end")
@@ -106,11 +113,19 @@ def main(argv=None):
     print(f"# {len(cells)} train + {len(test)} held-out cells at {args.N}^3 in {time.time() - t0:.1f} s, "
           f"levels {levels}", flush=True)
     n_params = B.nn_param_count(levels, channels_for(levels))
-    tr = Trainer(n_params, levels, lr=args.lr, lam=args.lam)
+    tr = Trainer(n_params, levels, lr=args.lr, lam=args.lam, warmup=args.warmup_steps)
+    if args.init:
+        from .learned import load_weights
+        w, winfo = load_weights(args.init)
+        if w.numel() != n_params:
+            raise ValueError(f"{args.init} holds {w.numel()} parameters, the network has {n_params}")
+        tr.params.copy_(w)
+        tr.ema.copy_(w)
+        print(f"# initialised from {args.init} ({winfo.get('step')} steps)", flush=True)
     if args.resume and os.path.exists(args.ckpt):
         tr.load(args.ckpt)
         print(f"# resumed {args.ckpt} at step {tr.step}", flush=True)
-    hs_test = [build(v, levels) for (_, _, _, v) in test]
+    hs_test = [build(voxels(c, args.N), levels) for c in test]
     base0 = evaluate(tr.ema, hs_test)
     zero = evaluate_zero(hs_test)
     print(f"# params {n_params}; held-out post-V-cycle residual: zero init median {np.median(zero):.3e}, "
@@ -127,7 +142,7 @@ def main(argv=None):
         H = cache.get(idx)
         fresh = H is None
         if fresh:
-            H = build(cells[idx][3], levels)
+            H = build(voxels(cells[idx], args.N), levels)
             if torch.cuda.memory_allocated() < budget:
                 cache[idx] = H
         loss, rn, rel = tr.train_cell(H, args.steps)

@@ -53,8 +53,9 @@ def test_graph_matches_eager_and_oracle(gyroid, precision):
         print(f"[graph {precision}] replay {rep_no}: its {rep_g['iterations']} (eager {rep_e['iterations']}) "
               f"res {max(rep_g['rel_res']):.2e}", flush=True)
         assert rep_g["converged"] and max(rep_g["rel_res"]) <= tol
-        # blocks of 4 may overshoot the eager count by at most 3 iterations per inner solve
-        assert rep_g["iterations"] <= rep_e["iterations"] + 3 * rep_g["outer"]
+        # the device-side convergence flag gates the iterations of a block past the
+        # target, so the replayed blocks run exactly the eager iterations
+        assert rep_g["iterations"] == rep_e["iterations"]
         bound = 1e-8 if precision == "f64" else 1e-4
         assert _rel(C_g, C_ref) <= bound and _rel(C_e, C_ref) <= bound
         assert _rel(C_g, C_e) <= bound
