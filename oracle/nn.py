@@ -92,11 +92,12 @@ def pool_map(fine, coarse) -> np.ndarray:
 
 
 class UNet:
-    def __init__(self, channels, head: int, q: int):
+    def __init__(self, channels, head: int, q: int, attention: bool = False):
         self.C = list(channels)
         self.L = len(channels)
         self.H = head
         self.q = q
+        self.attention = attention
 
     def shapes(self):
         """Ordered (name, shape) of every parameter (the flat layout shared with the GPU)."""
@@ -110,6 +111,10 @@ class UNet:
             s += [(f"Wd{l}", (27, C[l], C[l])), (f"bd{l}", (C[l],))]
             s += [(f"W1_{l}", (C[l], H)), (f"b1_{l}", (H,)), (f"W2_{l}", (H, H)), (f"b2_{l}", (H,)),
                   (f"W3_{l}", (H, q)), (f"b3_{l}", (q,))]
+        if self.attention:  # after every convolutional parameter: the layout without attention is unchanged
+            for l in range(L):
+                s += [(f"Wq{l}", (C[l], C[l])), (f"Wk{l}", (C[l], C[l])), (f"Wv{l}", (C[l], C[l])),
+                      (f"Wo{l}", (C[l], C[l]))]
         return s
 
     def n_params(self):
@@ -139,7 +144,7 @@ class UNet:
             if name == "E":
                 fan_in = 1
             bound = np.sqrt(3.0 / fan_in)
-            if name.startswith("W3"):
+            if name.startswith("W3") or name.startswith("Wo"):
                 bound *= 0.1
             p[name] = rng.uniform(-bound, bound, size=sh)
         return self.flatten(p)
@@ -182,15 +187,26 @@ def _conv_W(x, nbmap, gy):
 
 
 class Graph:
-    """Neighbour maps of one cell's hierarchy for the network."""
+    """Neighbour maps of one cell's hierarchy for the network (and, for the attention
+    blocks, every level's serialization order -- view l mod 3 -- and Ra-RoPE angles)."""
 
     def __init__(self, levels):
+        from . import attention as att
         self.levels = levels
         self.L = len(levels)
         self.conv = [conv_map(lv) for lv in levels]
         self.pool = [pool_map(levels[l], levels[l + 1]) for l in range(self.L - 1)]
         self.occ8 = levels[0].occ8.astype(np.int64)
         self.N = levels[0].N
+        self.order = [att.serialize(lv, l % 3) for l, lv in enumerate(levels)]
+        self.window = [att.window_size(l) for l in range(self.L)]
+        self._theta = {}
+
+    def theta(self, l, heads):
+        from . import attention as att
+        if (l, heads) not in self._theta:
+            self._theta[(l, heads)] = att.rope_angles(self.levels[l], heads)
+        return self._theta[(l, heads)]
 
 
 def forward(net: UNet, flat, g: Graph, emulate_bf16: bool = True):
@@ -203,16 +219,30 @@ def forward(net: UNet, flat, g: Graph, emulate_bf16: bool = True):
     h = [None] * L
     a = [None] * L
     h[0] = rb(W["E"][g.occ8])
+    s = [None] * L  # a_l after the attention block (a_l itself without attention)
+    att_cache = [None] * L
     for l in range(L):
         a[l] = rb(act(_conv(h[l], g.conv[l], W[f"We{l}"]) + W[f"be{l}"]))
+        if net.attention:
+            from . import attention as att
+            q = rb(a[l] @ W[f"Wq{l}"])
+            k = rb(a[l] @ W[f"Wk{l}"])
+            v = rb(a[l] @ W[f"Wv{l}"])
+            th = g.theta(l, net.C[l] // att.HEAD_DIM)
+            o_raw, ac = att.attention(q, k, v, g.order[l], g.window[l], th)
+            o = rb(o_raw)
+            s[l] = rb(a[l] + o @ W[f"Wo{l}"])
+            att_cache[l] = dict(q=q, k=k, v=v, o=o, theta=th, cache=ac)
+        else:
+            s[l] = a[l]
         if l < L - 1:
-            h[l + 1] = rb(act(_conv(a[l], g.pool[l], W[f"Wp{l}"]) + W[f"bp{l}"]))
+            h[l + 1] = rb(act(_conv(s[l], g.pool[l], W[f"Wp{l}"]) + W[f"bp{l}"]))
     d = [None] * L
     t = [None] * L
-    d[L - 1] = a[L - 1]
+    d[L - 1] = s[L - 1]
     for l in range(L - 2, -1, -1):
         up = _conv_T(d[l + 1], g.pool[l], np.transpose(W[f"Wu{l}"], (0, 2, 1)), g.levels[l].n_n)
-        t[l] = rb(act(up + W[f"bu{l}"] + a[l]))
+        t[l] = rb(act(up + W[f"bu{l}"] + s[l]))
         d[l] = rb(act(_conv(t[l], g.conv[l], W[f"Wd{l}"]) + W[f"bd{l}"]))
     outs, z1s, z2s = [], [], []
     for l in range(L - 1):
@@ -221,7 +251,7 @@ def forward(net: UNet, flat, g: Graph, emulate_bf16: bool = True):
         outs.append(center(g.N * (z2 @ W[f"W3_{l}"] + W[f"b3_{l}"])))
         z1s.append(z1)
         z2s.append(z2)
-    cache.update(h=h, a=a, d=d, t=t, z1=z1s, z2=z2s)
+    cache.update(h=h, a=a, s=s, d=d, t=t, z1=z1s, z2=z2s, att=att_cache)
     return outs, cache
 
 
@@ -243,30 +273,42 @@ def backward(net: UNet, g: Graph, cache, gouts):
         G[f"W1_{l}"] += d[l].T @ gz1
         G[f"b1_{l}"] += gz1.sum(0)
         gd[l] = gd[l] + gz1 @ W[f"W1_{l}"].T
-    ga = [np.zeros_like(x) for x in a]
+    s_ = cache.get("s") or a
+    gs = [np.zeros_like(x) for x in a]  # gradients of the attention blocks' outputs s_l
     for l in range(0, L - 1):
         gpre = gd[l] * act_grad(d[l])
         G[f"Wd{l}"] += _conv_W(t[l], g.conv[l], gpre)
         G[f"bd{l}"] += gpre.sum(0)
         gt = _conv_T(gpre, g.conv[l], W[f"Wd{l}"], g.levels[l].n_n)
         gpre_t = gt * act_grad(t[l])
-        ga[l] += gpre_t
+        gs[l] += gpre_t
         G[f"bu{l}"] += gpre_t.sum(0)
         # up = unpool(d[l+1]; Wu) = _conv_T(d[l+1], pool, Wu^T)
         G[f"Wu{l}"] += np.transpose(_conv_W(gpre_t, g.pool[l], d[l + 1]), (0, 2, 1))
         gd[l + 1] = gd[l + 1] + _conv(gpre_t, g.pool[l], np.transpose(W[f"Wu{l}"], (0, 2, 1)))
-    ga[L - 1] = ga[L - 1] + gd[L - 1]
+    gs[L - 1] = gs[L - 1] + gd[L - 1]
     gh = [None] * L
     for l in range(L - 1, -1, -1):
-        gpre = ga[l] * act_grad(a[l])
+        ga_l = gs[l].copy()  # residual branch of s = a + o Wo
+        if net.attention:
+            from . import attention as att
+            ac = cache["att"][l]
+            G[f"Wo{l}"] += ac["o"].T @ gs[l]
+            go = gs[l] @ W[f"Wo{l}"].T
+            gq, gk, gv = att.attention_backward(go, ac["q"], ac["k"], ac["v"], g.order[l], g.window[l],
+                                                ac["theta"], ac["cache"])
+            for name, gx in (("Wq", gq), ("Wk", gk), ("Wv", gv)):
+                G[f"{name}{l}"] += a[l].T @ gx
+                ga_l += gx @ W[f"{name}{l}"].T
+        gpre = ga_l * act_grad(a[l])
         G[f"We{l}"] += _conv_W(h[l], g.conv[l], gpre)
         G[f"be{l}"] += gpre.sum(0)
         gh[l] = _conv_T(gpre, g.conv[l], W[f"We{l}"], g.levels[l].n_n)
         if l > 0:
             gpre_h = gh[l] * act_grad(h[l])
-            G[f"Wp{l - 1}"] += _conv_W(a[l - 1], g.pool[l - 1], gpre_h)
+            G[f"Wp{l - 1}"] += _conv_W(s_[l - 1], g.pool[l - 1], gpre_h)
             G[f"bp{l - 1}"] += gpre_h.sum(0)
-            ga[l - 1] += _conv_T(gpre_h, g.pool[l - 1], W[f"Wp{l - 1}"], g.levels[l - 1].n_n)
+            gs[l - 1] += _conv_T(gpre_h, g.pool[l - 1], W[f"Wp{l - 1}"], g.levels[l - 1].n_n)
     np.add.at(G["E"], g.occ8, gh[0])
     return net.flatten(G)
 
