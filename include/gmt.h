@@ -323,13 +323,31 @@ gmt_status gmt_simp_oc(const double* d_rho, const double* d_dc, size_t n, double
  *   E [256][C1];  for l = 1..L: We_l [27][C_l][C_l], be_l [C_l];
  *   for l = 1..L-1: Wp_l [27][C_l][C_{l+1}], bp_l [C_{l+1}], Wu_l [27][C_{l+1}][C_l],
  *   bu_l [C_l], Wd_l [27][C_l][C_l], bd_l [C_l], W1_l [C_l][H], b1_l [H], W2_l [H][H],
- *   b2_l [H], W3_l [H][q], b3_l [q]      (q = c*d; tap t <-> offset (t%3-1, t/3%3-1, t/9-1)).
+ *   b2_l [H], W3_l [H][q], b3_l [q]      (q = c*d; tap t <-> offset (t%3-1, t/3%3-1, t/9-1));
+ *   with cfg.attention = 1, after all of the above: for l = 1..L: Wq_l, Wk_l, Wv_l,
+ *   Wo_l, each [C_l][C_l].
+ *
+ * Attention blocks (cfg.attention = 1; Sec. 4.2-4.3, the paper's serialized
+ * window attention with Ra-RoPE): after the encoder convolution of level l,
+ *   q = bf16(a Wq), k = bf16(a Wk), v = bf16(a Wv),
+ *   o = bf16(Attn(q, k, v)),  s = bf16(a + o Wo),
+ * and s takes the place of a as the pooling input, the decoder skip and (at
+ * the coarsest level) the decoder's start.  Attn is softmax attention with
+ * heads of 8 channels (C_l / 8 heads) inside windows of W_l = min(256 * 2^(l-1),
+ * 1024) consecutive nodes of the level's serialization: the Morton order of
+ * the node coordinates under the cyclic view (l-1) mod 3 of the axes
+ * ((x, y, z), (y, z, x), (z, x, y); bit b of the view's first, second, third
+ * coordinate at code bit 3b, 3b+1, 3b+2).  Queries and keys are rotated per
+ * channel pair k of a head by 2 pi (k div 3 + 1) p_{k mod 3} / N_l, p the
+ * node's coordinates on the level (Ra-RoPE: exactly periodic).  Scores are
+ * scaled by 1/sqrt(8); sums and the softmax in FP32.
  * ------------------------------------------------------------------------ */
 #define GMT_NN_MAX_LEVELS 8
 typedef struct {
   int32_t levels;                       /* 2..the hierarchy's L: the network runs on levels 1..levels */
   int32_t channels[GMT_NN_MAX_LEVELS];  /* C_l in {16, 32, 64} */
   int32_t head;                         /* H = 32 */
+  int32_t attention;                    /* 0: convolutional U-Net; 1: with an attention block per level */
 } gmt_nn_config;
 
 /* Number of FP32 parameters of the network for a physics (q = 18 or 3). */
@@ -355,9 +373,18 @@ gmt_status gmt_nn_backward(gmt_hier_t h, const float* const* d_gout, float* d_gr
  * level l (1..L), widened to FP32 [n_l][width], into d_out.  which: 0 = h
  * (encoder input), 1 = a (encoder output), 2 = t (decoder merge), 3 = d
  * (decoder output), 4 = z1, 5 = z2 (head hidden layers); 2..5 exist for
- * l < L only.  h_width receives the row width (C_l, or the head width). */
+ * l < L only.  With attention blocks also: 6 = s (block output, node order),
+ * and, in serialization order (row r is node order[r]), 7 = q, 8 = k, 9 = v
+ * (BF16) and 10 = the FP32 attention output before its BF16 rounding; 6 is a
+ * itself without attention, 7..10 fail with GMT_E_STATE.  h_width receives the
+ * row width (C_l, or the head width). */
 gmt_status gmt_nn_activation(gmt_hier_t h, int32_t level, int32_t which, float* d_out, int32_t* h_width,
                              void* stream);
+
+/* Serialization of level l (1..cfg.levels) of a network set up with attention:
+ * d_order[r] (n_l int32, device) receives the node id of rank r in the level's
+ * Morton order (view (l-1) mod 3).  GMT_E_STATE without attention blocks. */
+gmt_status gmt_nn_serialization(gmt_hier_t h, int32_t level, int32_t* d_order, void* stream);
 
 /* AdamW step on FP32 master weights (bias-corrected moments, step >= 1,
  * decoupled weight decay wd, gradient multiplied by grad_scale first). */

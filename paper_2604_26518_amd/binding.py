@@ -71,15 +71,17 @@ NN_MAX_LEVELS = 8
 
 
 class GmtNNConfig(ct.Structure):
-    _fields_ = [("levels", ct.c_int32), ("channels", ct.c_int32 * NN_MAX_LEVELS), ("head", ct.c_int32)]
+    _fields_ = [("levels", ct.c_int32), ("channels", ct.c_int32 * NN_MAX_LEVELS), ("head", ct.c_int32),
+                ("attention", ct.c_int32)]
 
 
-def nn_config(levels, channels, head=32):
+def nn_config(levels, channels, head=32, attention=False):
     cfg = GmtNNConfig()
     cfg.levels = levels
     for l, c in enumerate(channels):
         cfg.channels[l] = c
     cfg.head = head
+    cfg.attention = 1 if attention else 0
     return cfg
 
 
@@ -120,6 +122,7 @@ SIGNATURES = {
     "gmt_nn_forward": (_P, _P, _P, _P),
     "gmt_nn_backward": (_P, _P, _P, _P),
     "gmt_nn_activation": (_P, _I, _I, _P, ct.POINTER(ct.c_int32), _P),
+    "gmt_nn_serialization": (_P, _I, _P, _P),
     "gmt_nn_adamw": (_P, _P, _P, _P, ct.c_size_t, ct.c_double, ct.c_double, ct.c_double, ct.c_double,
                      ct.c_double, _I, ct.c_double, _P),
     "gmt_nn_norm2": (_P, ct.c_size_t, ct.POINTER(ct.c_double), _P),
@@ -449,13 +452,15 @@ class Hierarchy:
         return np.array(out[:self.c])
 
     # -- learned initializer
-    def nn_setup(self, channels, head=32):
-        """Network on levels 1..len(channels) (at most the hierarchy's L levels)."""
+    def nn_setup(self, channels, head=32, attention=False):
+        """Network on levels 1..len(channels) (at most the hierarchy's L levels), with an
+        attention block per level if `attention`."""
         if not 2 <= len(channels) <= self.L:
             raise ValueError(f"need 2..{self.L} channel counts")
         self.nn_levels = len(channels)
-        self._nn_cfg = nn_config(self.nn_levels, channels, head)
-        self.n_params = nn_param_count(self.nn_levels, channels, head, self.physics)
+        self.nn_attention = bool(attention)
+        self._nn_cfg = nn_config(self.nn_levels, channels, head, attention)
+        self.n_params = nn_param_count(self.nn_levels, channels, head, self.physics, attention)
         _check(lib().gmt_nn_setup(self._h, ct.byref(self._nn_cfg), _stream()))
 
     def _check_params(self, params):
@@ -480,12 +485,21 @@ class Hierarchy:
         _check(lib().gmt_nn_backward(self._h, _ptr_array(gl), _ptr(grad), _stream()))
 
     def nn_activation(self, level: int, which: int):
-        """Stored activation of the last forward (0 h, 1 a, 2 t, 3 d, 4 z1, 5 z2) as float32 [n_l][width]."""
+        """Stored activation of the last forward as float32 [n_l][width]: 0 h, 1 a, 2 t, 3 d, 4 z1,
+        5 z2, 6 s (attention block output, or a); with attention, in serialization order, 7 q,
+        8 k, 9 v and 10 the attention output before its BF16 rounding."""
         self._level(level)
         w = ct.c_int32()
         _check(lib().gmt_nn_activation(self._h, level, which, None, ct.byref(w), _stream()))
         out = torch.empty(self.n_n(level), w.value, dtype=torch.float32, device=self._vox.device)
         _check(lib().gmt_nn_activation(self._h, level, which, _ptr(out), ct.byref(w), _stream()))
+        return out
+
+    def nn_serialization(self, level: int):
+        """Node ids of level `level` in its serialization order (int32 [n_l]; attention only)."""
+        self._level(level)
+        out = torch.empty(self.n_n(level), dtype=torch.int32, device=self._vox.device)
+        _check(lib().gmt_nn_serialization(self._h, level, _ptr(out), _stream()))
         return out
 
     def vcycle_loss(self, preds, lam=0.0, want_grad=True, want_u1=False, nu1=2, nu2=2, smoother="chebyshev",
@@ -609,9 +623,9 @@ def simp_oc(rho, dc, volfrac: float, move: float = 0.2, eta: float = 0.5, rho_lo
     return out, lam.value
 
 
-def nn_param_count(levels, channels, head=32, physics="elastic") -> int:
+def nn_param_count(levels, channels, head=32, physics="elastic", attention=False) -> int:
     out = ct.c_size_t()
-    cfg = nn_config(levels, channels, head)
+    cfg = nn_config(levels, channels, head, attention)
     _check(lib().gmt_nn_param_count(ct.byref(cfg), GMT_ELASTIC if physics == "elastic" else GMT_THERMAL,
                                     ct.byref(out)))
     return int(out.value)

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgmt.so")
-SOURCES = ["kernels.hip", "host.hip", "nn.hip"]
+SOURCES = ["kernels.hip", "host.hip", "nn.hip", "attention.hip"]
 
 FLAGS = [
     "-O3",

@@ -406,7 +406,21 @@ double nn_norm2(Hier* h, const float* x, size_t n, hipStream_t s);
 double nn_norm2_noalloc(const float* x, size_t n, hipStream_t s);
 size_t nn_norm2_noalloc_max();
 int nn_activation(Hier& h, int l, int which, float* out, hipStream_t s);
+void nn_serialization(Hier& h, int l, int* out, hipStream_t s);
 void nn_ema(float* e, const float* x, size_t n, double decay, hipStream_t s);
+
+// attention block of the learned initializer (attention.hip): Morton serialization
+// of a level's nodes (order[rank] = node, inv[node] = rank, ser_lin[rank] = linear
+// index), the window of a level, and windowed Ra-RoPE attention over tensors kept
+// in serialization order
+int attention_window(int level);
+void attention_serialize(const int* node_map, int N, int n, int view, int* order, int* inv, int* ser_lin,
+                         hipStream_t s);
+void attention_forward(int n, int W, int C, int N, const int* ser_lin, const uint16_t* q, const uint16_t* k,
+                       const uint16_t* v, float* o32, uint16_t* o16, float* lse, hipStream_t s);
+void attention_backward(int n, int W, int C, int N, const int* ser_lin, const uint16_t* q, const uint16_t* k,
+                        const uint16_t* v, const float* o32, const float* lse, const float* go, float* dq, float* dk,
+                        float* dv, hipStream_t s);
 // column sums over nodes of a [C][n][D] vector -> sums[Q] (FP64)
 template <typename T>
 void launch_colsum(const T* v, int n, int Q, int D, double* partial, double* sums, hipStream_t s);

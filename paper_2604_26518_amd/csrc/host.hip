@@ -2475,6 +2475,7 @@ gmt_status gmt_nn_param_count(const gmt_nn_config* cfg, int32_t physics, size_t*
   return guarded([&] {
     if (!cfg || !n_params) fail(GMT_E_INVAL, "null pointer");
     if (cfg->levels < 2 || cfg->levels > GMT_NN_MAX_LEVELS) fail(GMT_E_INVAL, "bad levels");
+    if (cfg->attention != 0 && cfg->attention != 1) fail(GMT_E_INVAL, "attention must be 0 or 1");
     *n_params = nn_param_count(*cfg, physics == GMT_ELASTIC ? 18 : 3);
   });
 }
@@ -2509,6 +2510,14 @@ gmt_status gmt_nn_activation(gmt_hier_t H, int32_t level, int32_t which, float* 
     check_level(H, level);
     const int w = nn_activation(H->h, level - 1, which, d_out, S(stream));
     if (h_width) *h_width = w;
+  });
+}
+
+gmt_status gmt_nn_serialization(gmt_hier_t H, int32_t level, int32_t* d_order, void* stream) {
+  return guarded([&] {
+    check_level(H, level);
+    if (!d_order) fail(GMT_E_INVAL, "null pointer");
+    nn_serialization(H->h, level - 1, d_order, S(stream));
   });
 }
 

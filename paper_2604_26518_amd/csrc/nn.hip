@@ -532,7 +532,7 @@ static void gconv_dispatch(int cin, int cout, int ntap, int n, const int* tab, c
   }
   GC(16, 16, 27) GC(32, 32, 27) GC(64, 64, 27) GC(16, 32, 27) GC(32, 64, 27) GC(32, 16, 27) GC(64, 32, 27)
   GC(16, 32, 1) GC(32, 32, 1) GC(64, 32, 1) GC(32, 18, 1) GC(32, 3, 1)
-  GC(32, 16, 1) GC(32, 64, 1) GC(18, 32, 1) GC(3, 32, 1)
+  GC(32, 16, 1) GC(32, 64, 1) GC(18, 32, 1) GC(3, 32, 1) GC(16, 16, 1) GC(64, 64, 1)
 #undef GC
   fail(GMT_E_INVAL, "gather conv (%d -> %d, %d taps) not instantiated", cin, cout, ntap);
 }
@@ -554,7 +554,7 @@ static void mfma_dispatch(int cin, int cout, int ntap, int n, const int* tab, co
   }
   if constexpr (sizeof(Tout) == 2) {
     GM(16, 16, 27) GM(32, 32, 27) GM(64, 64, 27) GM(16, 32, 27) GM(32, 64, 27) GM(32, 16, 27) GM(64, 32, 27)
-    GM(16, 32, 1) GM(32, 32, 1) GM(64, 32, 1)
+    GM(16, 32, 1) GM(32, 32, 1) GM(64, 32, 1) GM(16, 16, 1) GM(64, 64, 1)
   } else {
     GM(32, 18, 1) GM(32, 3, 1)
   }
@@ -580,7 +580,7 @@ static void wgrad_dispatch(int cin, int cout, int ntap, int n, const int* tab, c
     return;                                                                                                \
   }
   WG(16, 16, 27) WG(32, 32, 27) WG(64, 64, 27) WG(16, 32, 27) WG(32, 64, 27) WG(32, 16, 27) WG(64, 32, 27)
-  WG(16, 32, 1) WG(32, 32, 1) WG(64, 32, 1) WG(32, 18, 1) WG(32, 3, 1)
+  WG(16, 32, 1) WG(32, 32, 1) WG(64, 32, 1) WG(32, 18, 1) WG(32, 3, 1) WG(16, 16, 1) WG(64, 64, 1)
 #undef WG
   fail(GMT_E_INVAL, "weight gradient (%d -> %d, %d taps) not instantiated", cin, cout, ntap);
 }
@@ -613,14 +613,17 @@ static void bgrad_dispatch(int cout, int n, const float* g, float* db, float* pa
 //                   Wu_l [27][C_{l+1}][C_l], bu_l [C_l]
 //                   Wd_l [27][C_l][C_l],     bd_l [C_l]
 //                   W1_l [C_l][H], b1_l [H], W2_l [H][H], b2_l [H], W3_l [H][q], b3_l [q]
+//   with attention blocks, then for l < L: Wq_l, Wk_l, Wv_l, Wo_l [C_l][C_l]
 struct NetLayout {
   int L = 0, H = 0, q = 0;
+  bool att = false;
   int C[GMT_NN_MAX_LEVELS] = {0};
   size_t E = 0, We[GMT_NN_MAX_LEVELS], be[GMT_NN_MAX_LEVELS];
   size_t Wp[GMT_NN_MAX_LEVELS], bp[GMT_NN_MAX_LEVELS], Wu[GMT_NN_MAX_LEVELS], bu[GMT_NN_MAX_LEVELS];
   size_t Wd[GMT_NN_MAX_LEVELS], bd[GMT_NN_MAX_LEVELS];
   size_t W1[GMT_NN_MAX_LEVELS], b1[GMT_NN_MAX_LEVELS], W2[GMT_NN_MAX_LEVELS], b2[GMT_NN_MAX_LEVELS];
   size_t W3[GMT_NN_MAX_LEVELS], b3[GMT_NN_MAX_LEVELS];
+  size_t Wq[GMT_NN_MAX_LEVELS], Wk[GMT_NN_MAX_LEVELS], Wv[GMT_NN_MAX_LEVELS], Wo[GMT_NN_MAX_LEVELS];
   size_t total = 0;
 };
 
@@ -629,6 +632,7 @@ static NetLayout make_layout(const gmt_nn_config& cfg, int q) {
   nl.L = cfg.levels;
   nl.H = cfg.head;
   nl.q = q;
+  nl.att = cfg.attention != 0;
   for (int l = 0; l < nl.L; ++l) nl.C[l] = cfg.channels[l];
   size_t o = 0;
   auto take = [&](size_t n) {
@@ -656,6 +660,13 @@ static NetLayout make_layout(const gmt_nn_config& cfg, int q) {
     nl.W3[l] = take((size_t)nl.H * q);
     nl.b3[l] = take(q);
   }
+  if (nl.att)
+    for (int l = 0; l < nl.L; ++l) {
+      nl.Wq[l] = take((size_t)C[l] * C[l]);
+      nl.Wk[l] = take((size_t)C[l] * C[l]);
+      nl.Wv[l] = take((size_t)C[l] * C[l]);
+      nl.Wo[l] = take((size_t)C[l] * C[l]);
+    }
   nl.total = o;
   return nl;
 }
@@ -674,7 +685,16 @@ struct NNState {
   double* colred = nullptr;                              // column-mean partials + means
   float* part = nullptr;                                 // per-chunk gradient partial sums
   std::vector<float*> gd;                                // dL/dd_l accumulators
-  std::vector<float*> ga;                                // dL/da_l accumulators
+  std::vector<float*> ga;                                // dL/ds_l, then dL/da_l accumulators
+  // attention blocks: per level the serialization (order[r] = node, inv[node] = r,
+  // ser_lin[r] = linear index), q, k, v and the BF16 attention output in that order,
+  // its FP32 value and log-sum-exp (backward), and the block output s (node order)
+  std::vector<int*> order, inv, ser_lin;
+  std::vector<uint16_t*> q, k, v, o16, sb;
+  std::vector<float*> o32, lse;
+  float* g3 = nullptr;
+  // the tensor that leaves level l's encoder: s_l with attention, a_l without
+  const uint16_t* out(int l) const { return nl.att ? sb[l] : a[l]; }
 };
 
 static NNState& nn_state(Hier& h) {
@@ -698,6 +718,7 @@ void nn_setup(Hier& h, const gmt_nn_config& cfg, hipStream_t s) {
     if (cfg.channels[l] != 16 && cfg.channels[l] != 32 && cfg.channels[l] != 64)
       fail(GMT_E_INVAL, "channels must be 16, 32 or 64");
   if (cfg.head != 32) fail(GMT_E_INVAL, "head width must be 32");
+  if (cfg.attention != 0 && cfg.attention != 1) fail(GMT_E_INVAL, "attention must be 0 or 1");
   if (h.nn) nn_release(h);
   NNState* S = new NNState();
   h.nn = S;
@@ -743,6 +764,27 @@ void nn_setup(Hier& h, const gmt_nn_config& cfg, hipStream_t s) {
     }
     S->gd[l] = h.alloc<float>((size_t)d.n_n * C);
   }
+  if (S->nl.att) {
+    for (auto* v : {&S->order, &S->inv, &S->ser_lin}) v->assign(L, nullptr);
+    for (auto* v : {&S->q, &S->k, &S->v, &S->o16, &S->sb}) v->assign(L, nullptr);
+    S->o32.assign(L, nullptr);
+    S->lse.assign(L, nullptr);
+    for (int l = 0; l < L; ++l) {
+      const LevelData& d = h.lv[l];
+      const size_t nc = (size_t)d.n_n * S->nl.C[l];
+      S->order[l] = h.alloc<int>(d.n_n);
+      S->inv[l] = h.alloc<int>(d.n_n);
+      S->ser_lin[l] = h.alloc<int>(d.n_n);
+      attention_serialize(d.node_map, d.N, d.n_n, l % 3, S->order[l], S->inv[l], S->ser_lin[l], s);
+      S->q[l] = h.alloc<uint16_t>(nc);
+      S->k[l] = h.alloc<uint16_t>(nc);
+      S->v[l] = h.alloc<uint16_t>(nc);
+      S->o16[l] = h.alloc<uint16_t>(nc);
+      S->sb[l] = h.alloc<uint16_t>(nc);
+      S->o32[l] = h.alloc<float>(nc);
+      S->lse[l] = h.alloc<float>((size_t)d.n_n * (S->nl.C[l] / 8));
+    }
+  }
   S->Wb = h.alloc<float>(S->nl.total);
   {
     // every forward layer's weights, arranged for k_gconv_mfma (512 BF16 per K step and
@@ -766,6 +808,12 @@ void nn_setup(Hier& h, const gmt_nn_config& cfg, hipStream_t s) {
         add(N.W2[l], 1, N.H, N.H);
         add(N.W3[l], 1, N.H, N.q);
       }
+      if (N.att) {
+        add(N.Wq[l], 1, N.C[l], N.C[l]);
+        add(N.Wk[l], 1, N.C[l], N.C[l]);
+        add(N.Wv[l], 1, N.C[l], N.C[l]);
+        add(N.Wo[l], 1, N.C[l], N.C[l]);
+      }
     }
     S->n_mlay = (int)lay.size();
     S->m_total = dst;
@@ -780,6 +828,7 @@ void nn_setup(Hier& h, const gmt_nn_config& cfg, hipStream_t s) {
   S->g0 = h.alloc<float>(maxnc);
   S->g1 = h.alloc<float>(maxnc);
   S->g2 = h.alloc<float>(maxnc);
+  if (S->nl.att) S->g3 = h.alloc<float>(maxnc);
   S->part = h.alloc<float>(std::max((size_t)kMaxChunks * 27 * 64 * 64, (size_t)kBgradBlocks * 64));
   GMT_HIP(hipStreamSynchronize(s));
 }
@@ -826,15 +875,25 @@ void nn_forward(Hier& h, const float* params, float* const* out, hipStream_t s) 
     const int n = h.lv[l].n_n, C = N.C[l];
     mfma_dispatch<uint16_t, F_BIAS | F_ACT>(C, C, 27, n, S.conv[l], S.h[l], wm(N.We[l]), W + N.be[l], nullptr, 1.f,
                                             S.a[l], s);
+    if (N.att) {
+      // q, k, v computed straight into serialization order (gathered through order),
+      // s = a + o Wo back in node order (o gathered through inv)
+      mfma_dispatch<uint16_t, 0>(C, C, 1, n, S.order[l], S.a[l], wm(N.Wq[l]), nullptr, nullptr, 1.f, S.q[l], s);
+      mfma_dispatch<uint16_t, 0>(C, C, 1, n, S.order[l], S.a[l], wm(N.Wk[l]), nullptr, nullptr, 1.f, S.k[l], s);
+      mfma_dispatch<uint16_t, 0>(C, C, 1, n, S.order[l], S.a[l], wm(N.Wv[l]), nullptr, nullptr, 1.f, S.v[l], s);
+      attention_forward(n, attention_window(l), C, h.lv[l].N, S.ser_lin[l], S.q[l], S.k[l], S.v[l], S.o32[l],
+                        S.o16[l], S.lse[l], s);
+      mfma_dispatch<uint16_t, F_SKIP>(C, C, 1, n, S.inv[l], S.o16[l], wm(N.Wo[l]), nullptr, S.a[l], 1.f, S.sb[l], s);
+    }
     if (l + 1 < L)
-      mfma_dispatch<uint16_t, F_BIAS | F_ACT>(C, N.C[l + 1], 27, h.lv[l + 1].n_n, S.pool[l], S.a[l], wm(N.Wp[l]),
+      mfma_dispatch<uint16_t, F_BIAS | F_ACT>(C, N.C[l + 1], 27, h.lv[l + 1].n_n, S.pool[l], S.out(l), wm(N.Wp[l]),
                                               W + N.bp[l], nullptr, 1.f, S.h[l + 1], s);
   }
   for (int l = L - 2; l >= 0; --l) {
     const int n = h.lv[l].n_n, C = N.C[l];
-    const uint16_t* dn = l + 1 == L - 1 ? S.a[L - 1] : S.d[l + 1];
+    const uint16_t* dn = l + 1 == L - 1 ? S.out(L - 1) : S.d[l + 1];
     mfma_dispatch<uint16_t, F_BIAS | F_SKIP | F_ACT>(N.C[l + 1], C, 27, n, S.unpool[l], dn, wm(N.Wu[l]), W + N.bu[l],
-                                                     S.a[l], 1.f, S.t[l], s);
+                                                     S.out(l), 1.f, S.t[l], s);
     mfma_dispatch<uint16_t, F_BIAS | F_ACT>(C, C, 27, n, S.conv[l], S.t[l], wm(N.Wd[l]), W + N.bd[l], nullptr, 1.f,
                                             S.d[l], s);
     mfma_dispatch<uint16_t, F_BIAS | F_ACT>(C, N.H, 1, n, nullptr, S.d[l], wm(N.W1[l]), W + N.b1[l], nullptr, 1.f,
@@ -884,6 +943,32 @@ static void dgrad(NNState& S, int cin, int cout, int ntap, int n_out, const int*
   gconv_dispatch<float, float, 0>(cin, cout, ntap, n_out, tab, g, S.Wt, nullptr, nullptr, 1.f, y, s);
 }
 
+// Backward of level l's attention block s = a + bf16(Attn(q, k, v)) Wo with q, k, v = a Wq, a Wk,
+// a Wv: on entry S.ga[l] holds dL/ds, on return dL/da (the residual path plus the three
+// projections); adds the gradients of Wq, Wk, Wv, Wo.
+static void attention_block_backward(Hier& h, NNState& S, int l, float* grad, hipStream_t s) {
+  const NetLayout& N = S.nl;
+  const float* W = S.Wb;
+  const int n = h.lv[l].n_n, C = N.C[l];
+  const size_t tc = (size_t)n * C;
+  float* gs = S.ga[l];
+  // Wo: rows are nodes, the input o is gathered through inv
+  wgrad_dispatch<uint16_t>(C, C, 1, n, S.inv[l], S.o16[l], gs, grad + N.Wo[l], S.part, s);
+  transpose_taps(S, W + N.Wo[l], 1, C, C, false, s);
+  dgrad(S, C, C, 1, n, S.order[l], gs, S.g0, s);  // dL/do in serialization order
+  attention_backward(n, attention_window(l), C, h.lv[l].N, S.ser_lin[l], S.q[l], S.k[l], S.v[l], S.o32[l],
+                     S.lse[l], S.g0, S.g1, S.g2, S.g3, s);
+  const size_t Wx[3] = {N.Wq[l], N.Wk[l], N.Wv[l]};
+  float* gx[3] = {S.g1, S.g2, S.g3};
+  for (int j = 0; j < 3; ++j) {
+    // rows in serialization order, the input a gathered through order; dL/da += gathered back through inv
+    wgrad_dispatch<uint16_t>(C, C, 1, n, S.order[l], S.a[l], gx[j], grad + Wx[j], S.part, s);
+    transpose_taps(S, W + Wx[j], 1, C, C, false, s);
+    dgrad(S, C, C, 1, n, S.inv[l], gx[j], S.g0, s);
+    addv(gs, S.g0, tc, s);
+  }
+}
+
 // grad += d/dparams sum_l <gout[l], out[l]> (activations of the last forward)
 void nn_backward(Hier& h, const float* const* gout, float* grad, hipStream_t s) {
   NNState& S = nn_state(h);
@@ -929,19 +1014,21 @@ void nn_backward(Hier& h, const float* const* gout, float* grad, hipStream_t s) 
     // skip path into a_l, bias bu
     GMT_HIP(hipMemcpyAsync(S.ga[l], S.g1, tc * sizeof(float), hipMemcpyDeviceToDevice, s));
     bgrad_dispatch(C, n, S.g1, grad + N.bu[l], S.part, s);
-    const uint16_t* dn = l + 1 == L - 1 ? S.a[L - 1] : S.d[l + 1];
+    const uint16_t* dn = l + 1 == L - 1 ? S.out(L - 1) : S.d[l + 1];
     wgrad_dispatch<uint16_t>(Cn, C, 27, n, S.unpool[l], dn, S.g1, grad + N.Wu[l], S.part, s);
     transpose_taps(S, W + N.Wu[l], 27, Cn, C, false, s);
     dgrad(S, C, Cn, 27, nn, S.pool[l], S.g1, S.g2, s);
     addv(S.gd[l + 1], S.g2, (size_t)nn * Cn, s);
   }
-  // a_{L-1} = d_{L-1}
+  // s_{L-1} = d_{L-1}
   GMT_HIP(hipMemcpyAsync(S.ga[L - 1], S.gd[L - 1], (size_t)h.lv[L - 1].n_n * N.C[L - 1] * sizeof(float),
                          hipMemcpyDeviceToDevice, s));
-  // encoder, coarsest first: a_l = act(conv(h_l) + be), h_{l+1} = act(pool(a_l) + bp)
+  // encoder, coarsest first: a_l = act(conv(h_l) + be), s_l = block(a_l) (or a_l),
+  // h_{l+1} = act(pool(s_l) + bp)
   for (int l = L - 1; l >= 0; --l) {
     const int n = h.lv[l].n_n, C = N.C[l];
     const size_t tc = (size_t)n * C;
+    if (N.att) attention_block_backward(h, S, l, grad, s);  // ga[l]: dL/ds_l -> dL/da_l
     GMT_HIP(hipMemcpyAsync(S.g0, S.ga[l], tc * sizeof(float), hipMemcpyDeviceToDevice, s));
     act_grad(S.g0, S.a[l], tc, s);
     wgrad_dispatch<uint16_t>(C, C, 27, n, S.conv[l], S.h[l], S.g0, grad + N.We[l], S.part, s);
@@ -951,7 +1038,7 @@ void nn_backward(Hier& h, const float* const* gout, float* grad, hipStream_t s) 
     if (l > 0) {
       const int Cp = N.C[l - 1], np = h.lv[l - 1].n_n;
       act_grad(S.g1, S.h[l], tc, s);
-      wgrad_dispatch<uint16_t>(Cp, C, 27, n, S.pool[l - 1], S.a[l - 1], S.g1, grad + N.Wp[l - 1], S.part, s);
+      wgrad_dispatch<uint16_t>(Cp, C, 27, n, S.pool[l - 1], S.out(l - 1), S.g1, grad + N.Wp[l - 1], S.part, s);
       bgrad_dispatch(C, n, S.g1, grad + N.bp[l - 1], S.part, s);
       transpose_taps(S, W + N.Wp[l - 1], 27, Cp, C, false, s);
       dgrad(S, C, Cp, 27, np, S.unpool[l - 1], S.g1, S.g2, s);
@@ -971,15 +1058,30 @@ __global__ void k_widen(size_t total, const uint16_t* __restrict__ a, float* __r
   if (i < total) b[i] = bf2f(a[i]);
 }
 
+void nn_serialization(Hier& h, int l, int* out, hipStream_t s) {
+  NNState& S = nn_state(h);
+  if (!S.nl.att) fail(GMT_E_STATE, "the network was set up without attention blocks");
+  if (l >= S.nl.L) fail(GMT_E_INVAL, "level %d is below the network's %d levels", l + 1, S.nl.L);
+  GMT_HIP(hipMemcpyAsync(out, S.order[l], (size_t)h.lv[l].n_n * sizeof(int), hipMemcpyDeviceToDevice, s));
+}
+
 int nn_activation(Hier& h, int l, int which, float* out, hipStream_t s) {
   NNState& S = nn_state(h);
   const NetLayout& N = S.nl;
-  if (which < 0 || which > 5) fail(GMT_E_INVAL, "activation kind %d outside 0..5", which);
+  if (which < 0 || which > 10) fail(GMT_E_INVAL, "activation kind %d outside 0..10", which);
+  if (which >= 7 && !N.att) fail(GMT_E_STATE, "activation kind %d exists with attention blocks only", which);
   if (l >= N.L) fail(GMT_E_INVAL, "level %d is below the network's %d levels", l + 1, N.L);
-  if (which >= 2 && l >= N.L - 1) fail(GMT_E_INVAL, "decoder/head activations exist below the coarsest level only");
+  if (which >= 2 && which <= 5 && l >= N.L - 1)
+    fail(GMT_E_INVAL, "decoder/head activations exist below the coarsest level only");
+  const int width = which == 4 || which == 5 ? N.H : N.C[l];
+  if (which == 10) {
+    if (out) GMT_HIP(hipMemcpyAsync(out, S.o32[l], (size_t)h.lv[l].n_n * width * sizeof(float),
+                                    hipMemcpyDeviceToDevice, s));
+    return width;
+  }
   const uint16_t* src = which == 0 ? S.h[l] : which == 1 ? S.a[l] : which == 2 ? S.t[l] : which == 3 ? S.d[l]
-                        : which == 4 ? S.z1[l] : S.z2[l];
-  const int width = which >= 4 ? N.H : N.C[l];
+                        : which == 4 ? S.z1[l] : which == 5 ? S.z2[l] : which == 6 ? S.out(l)
+                        : which == 7 ? S.q[l] : which == 8 ? S.k[l] : S.v[l];
   if (out) {
     const size_t tot = (size_t)h.lv[l].n_n * width;
     if (tot) {

@@ -118,7 +118,7 @@ def main(argv=None):
         seed = args.seed0 + k
         fam, vf, vox = workload_cell(N, seed)
         H = B.Hierarchy(vox, levels, "elastic")
-        H.nn_setup(channels_for(levels))
+        H.nn_setup(channels_for(levels), attention=info.get("attention", False))
         if k == 0:  # warm-up of every kernel on the first cell
             compare(H, params, args.tol, reference=False)
         r = compare(H, params, args.tol)

@@ -27,8 +27,10 @@ def channels_for(levels: int):
     return list(DEFAULT_CHANNELS[:levels])
 
 
-def init_params(n_params: int, levels: int, physics: str = "elastic", seed: int = 0, device="cuda"):
-    """He-style uniform initialisation with the oracle's parameter order (small last head layer)."""
+def init_params(n_params: int, levels: int, physics: str = "elastic", seed: int = 0, device="cuda",
+                attention: bool = False):
+    """He-style uniform initialisation with the oracle's parameter order (small last head layer and,
+    with attention blocks, small output projections Wo, so every block starts near the identity)."""
     from math import sqrt
     q = 18 if physics == "elastic" else 3
     C = channels_for(levels)
@@ -40,6 +42,9 @@ def init_params(n_params: int, levels: int, physics: str = "elastic", seed: int 
         shapes += [("Wp", (27, C[l], C[l + 1])), ("b", (C[l + 1],)), ("Wu", (27, C[l + 1], C[l])), ("b", (C[l],)),
                    ("Wd", (27, C[l], C[l])), ("b", (C[l],)), ("W1", (C[l], H)), ("b", (H,)), ("W2", (H, H)),
                    ("b", (H,)), ("W3", (H, q)), ("b", (q,))]
+    if attention:
+        for l in range(levels):
+            shapes += [("Wq", (C[l], C[l])), ("Wk", (C[l], C[l])), ("Wv", (C[l], C[l])), ("Wo", (C[l], C[l]))]
     g = torch.Generator().manual_seed(seed)
     parts = []
     for name, sh in shapes:
@@ -48,7 +53,7 @@ def init_params(n_params: int, levels: int, physics: str = "elastic", seed: int 
             parts.append(torch.zeros(n))
             continue
         fan_in = 1 if name == "E" else (sh[0] * sh[1] if len(sh) == 3 else sh[0])
-        bound = sqrt(3.0 / fan_in) * (0.1 if name == "W3" else 1.0)
+        bound = sqrt(3.0 / fan_in) * (0.1 if name in ("W3", "Wo") else 1.0)
         parts.append((torch.rand(n, generator=g) * 2 - 1) * bound)
     flat = torch.cat(parts)
     assert flat.numel() == n_params, (flat.numel(), n_params)
@@ -59,8 +64,8 @@ class Trainer:
     """AdamW on FP32 master weights with a cosine schedule, global-norm clipping and an EMA copy."""
 
     def __init__(self, n_params, levels, physics="elastic", lr=1e-3, wd=1e-2, clip=1.0, ema=0.999, seed=0,
-                 lam=0.0, device="cuda", warmup=300):
-        self.params = init_params(n_params, levels, physics, seed, device)
+                 lam=0.0, device="cuda", warmup=300, attention=False):
+        self.params = init_params(n_params, levels, physics, seed, device, attention)
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
         self.grad = torch.zeros_like(self.params)
@@ -105,12 +110,13 @@ class Trainer:
         return loss, rn, float(np.max(rel))
 
 
-def save_weights(path, flat, levels, N, physics, meta=None):
+def save_weights(path, flat, levels, N, physics, meta=None, attention=False):
     """Inference weights: the BF16 rounding of `flat` (the network only ever uses BF16 weights)."""
     x = flat.detach().to("cpu", torch.float32).contiguous()
     bits = x.view(torch.int32).numpy().astype(np.uint32)
     bf = ((bits + 0x7FFF + ((bits >> 16) & 1)) >> 16).astype(np.uint16)
-    info = {"levels": int(levels), "N": int(N), "physics": physics, "channels": channels_for(levels), "head": 32}
+    info = {"levels": int(levels), "N": int(N), "physics": physics, "channels": channels_for(levels), "head": 32,
+            "attention": bool(attention)}
     if meta:
         info.update(meta)
     np.savez(path, bf16=bf, info=np.frombuffer(json.dumps(info).encode(), dtype=np.uint8))

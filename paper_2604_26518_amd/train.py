@@ -54,9 +54,9 @@ def make_cells(N, seeds, procs=16):
         pool.join()
 
 
-def build(vox, levels, physics="elastic"):
+def build(vox, levels, physics="elastic", attention=False):
     H = B.Hierarchy(vox, levels, physics)
-    H.nn_setup(channels_for(levels))
+    H.nn_setup(channels_for(levels), attention=attention)
     return H
 
 
@@ -96,6 +96,7 @@ def main(argv=None):
     ap.add_argument("--test-seed0", type=int, default=900000)
     ap.add_argument("--init", default="", help="start from these exported (BF16) weights")
     ap.add_argument("--warmup-steps", type=int, default=300)
+    ap.add_argument("--attention", action="store_true", help="an attention block per level (Sec. 4.2-4.3)")
     ap.add_argument("--ckpt", default="unet.pt")
     ap.add_argument("--resume", action="store_true")
     ap.add_argument("--export", default="", help="write the EMA weights (BF16) to this .npz at the end")
@@ -112,8 +113,9 @@ def main(argv=None):
     torch.cuda.set_device(0)
     print(f"# {len(cells)} train + {len(test)} held-out cells at {args.N}^3 in {time.time() - t0:.1f} s, "
           f"levels {levels}", flush=True)
-    n_params = B.nn_param_count(levels, channels_for(levels))
-    tr = Trainer(n_params, levels, lr=args.lr, lam=args.lam, warmup=args.warmup_steps)
+    att = args.attention
+    n_params = B.nn_param_count(levels, channels_for(levels), attention=att)
+    tr = Trainer(n_params, levels, lr=args.lr, lam=args.lam, warmup=args.warmup_steps, attention=att)
     if args.init:
         from .learned import load_weights
         w, winfo = load_weights(args.init)
@@ -125,7 +127,7 @@ def main(argv=None):
     if args.resume and os.path.exists(args.ckpt):
         tr.load(args.ckpt)
         print(f"# resumed {args.ckpt} at step {tr.step}", flush=True)
-    hs_test = [build(voxels(c, args.N), levels) for c in test]
+    hs_test = [build(voxels(c, args.N), levels, attention=att) for c in test]
     base0 = evaluate(tr.ema, hs_test)
     zero = evaluate_zero(hs_test)
     print(f"# params {n_params}; held-out post-V-cycle residual: zero init median {np.median(zero):.3e}, "
@@ -142,7 +144,7 @@ def main(argv=None):
         H = cache.get(idx)
         fresh = H is None
         if fresh:
-            H = build(voxels(cells[idx], args.N), levels)
+            H = build(voxels(cells[idx], args.N), levels, attention=att)
             if torch.cuda.memory_allocated() < budget:
                 cache[idx] = H
         loss, rn, rel = tr.train_cell(H, args.steps)
@@ -177,7 +179,8 @@ def main(argv=None):
                "step": tr.step, "seconds": time.time() - t_start, "ms_per_step": (time.time() - t_start) / max(k, 1) * 1e3}
     print("# " + json.dumps(summary), flush=True)
     if args.export:
-        save_weights(args.export, tr.ema, levels, args.N, "elastic", meta={"step": tr.step, **summary})
+        save_weights(args.export, tr.ema, levels, args.N, "elastic", meta={"step": tr.step, **summary},
+                     attention=att)
         print(f"# exported EMA weights to {args.export}", flush=True)
     if args.log:
         with open(args.log, "w") as fh:

@@ -413,6 +413,45 @@ def test_full_size_mixed_solve(big):
     assert np.linalg.norm(CH32 - CH64) <= 1e-4 * np.linalg.norm(CH64)
 
 
+def test_full_size_maps_every_level(big):
+    """Every level of the 128^3 hierarchy (six levels) bit-exact against the oracle's
+    construction: element and node ids, occupancy, connectivity, transfer indices and weights."""
+    vox, H, lv = big
+    levels = ohier.build(vox, 6)
+    for l, ref in enumerate(levels, start=1):
+        m = H.export_maps(l)
+        assert np.array_equal(_np(m["elem_lin"]).astype(np.int64), ref.elem_lin), l
+        assert np.array_equal(_np(m["node_lin"]).astype(np.int64), ref.node_lin), l
+        assert np.array_equal(_np(m["occ8"]).astype(np.int64), ref.occ8.astype(np.int64)), l
+        assert np.array_equal(_np(m["elem_nodes"]).astype(np.int64), ref.elem_nodes), l
+        if l < 6:
+            assert np.array_equal(_np(m["prol_idx"]).astype(np.int64), ref.prol_idx), l
+            assert np.array_equal(_np(m["prol_w"]), ref.prol_w), l
+        print(f"[maps 128^3] level {l}: n_e {ref.n_e} n_n {ref.n_n} bit-exact", flush=True)
+
+
+def test_thermal_64_against_oracle():
+    """Heat conduction at 64^3 (spinodal, 5 levels): kappa_H of the FP64 and mixed solves
+    against the oracle's, residuals evaluated by the oracle in FP64."""
+    vox = spinodal(64, 7, 0.35)
+    P = osolve.Problem(vox, 5, "thermal")
+    u_ref, _ = osolve.pcg(P, tol=1e-11)
+    K_ref = osolve.homogenize(P, u_ref)
+    H = _gmt().Hierarchy(vox, 5, "thermal")
+    f = H.load_vector()
+    u64, rep64 = H.solve(f, tol=1e-9, precision="f64")
+    u32, rep32 = H.solve(f, tol=1e-5, precision="f32")
+    e64 = np.linalg.norm(H.homogenize(u64) - K_ref) / np.linalg.norm(K_ref)
+    e32 = np.linalg.norm(H.homogenize(u32) - K_ref) / np.linalg.norm(K_ref)
+    r64 = float(np.max(osolve.relative_residual(P, _np(u64))))
+    r32 = float(np.max(osolve.relative_residual(P, _np(u32))))
+    print(f"[thermal 64^3] FP64 its {rep64['iterations']} res {r64:.1e} dK {e64:.1e}; mixed its "
+          f"{rep32['iterations']} res {r32:.1e} dK {e32:.1e}", flush=True)
+    assert r64 <= 1e-9 and e64 <= 1e-8
+    assert r32 <= 1e-5 and e32 <= 1e-4
+    H.close()
+
+
 def test_lambda_estimate_many_levels():
     """lambda_max(D^-1 K) of every level of a six-level hierarchy (64^3), where the power
     iterations of the levels run concurrently on the auxiliary streams."""
