@@ -62,7 +62,12 @@ SWEEP_KERNELS = {
     7: "k_apply_interior<PRE=1> + k_apply_boundary_cls<PRE=1>",
     8: "k_apply_interior<PRE=1> + k_apply_boundary_all",
 }
-WEIGHTS = os.path.join(ROOT, "paper_2604_26518_amd", "weights", "unet128_elastic.npz")
+# one network per resolution (the 512^3 one fine-tuned at 512^3 from the 128^3 one)
+WEIGHTS_BY_N = {N: os.path.join(ROOT, "paper_2604_26518_amd", "weights", f"unet{N}_elastic.npz") for N in (128, 512)}
+
+
+def weights_for(N):
+    return WEIGHTS_BY_N.get(N, WEIGHTS_BY_N[128])
 HEADLINE = {"family": "gyroid", "N": 512, "seed": 30001, "vf": 0.25}
 SPINODAL = {"family": "spinodal", "N": 512, "seed": 30000, "vf": 0.25}
 UNEVEN_SIZES = (64, 96, 128, 192, 256)
@@ -273,6 +278,7 @@ def cell512(args):
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     levels = B.default_levels(args.N)
+    WEIGHTS = weights_for(args.N)
     params, info = load_weights(WEIGHTS)
     net_levels = min(info["levels"], levels)
     vox = torch.from_numpy(res["gyroid"]).cuda()

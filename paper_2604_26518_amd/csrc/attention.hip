@@ -23,9 +23,13 @@
 // handles one (window, head) pair; a thread owns kPer queries (forward, dq) or
 // keys (dk, dv) and streams the other side of the window through LDS in chunks
 // of kChunk tokens, so each LDS read serves kPer score evaluations.  The
-// softmax is computed online in base 2 (running maximum, rescaled when it
-// grows) in FP32; the forward stores the log-sum-exp per (token, head), and the
-// backward recomputes the probabilities from it.  The backward runs as two
+// softmax is computed online in base 2 in FP32 against a running offset m that
+// is raised (and the sums rescaled) only when a score exceeds it by more than 8:
+// every term 2^(s - m) stays below 2^8, and the rescaling branch, which a wave
+// takes whenever any of its lanes needs it, is rare after the first key.  The
+// log-sum-exp m + log2(sum) does not depend on m.  The forward stores it per
+// (token, head), and the backward recomputes the probabilities from it.  The
+// backward runs as two
 // passes, one per query (dq) and one per key (dk, dv), each thread summing its
 // own outputs in a fixed order: the gradients are deterministic.
 #include <hip/hip_runtime.h>
@@ -41,7 +45,8 @@ namespace {
 
 constexpr int kHd = 8;        // head dimension
 constexpr int kPer = 4;       // queries (or keys) per thread
-constexpr int kChunk = 256;   // tokens of the other side staged in LDS at a time
+constexpr int kChunk = 128;   // tokens of the other side staged in LDS at a time
+constexpr float kSlack = 8.f; // the running offset may trail the maximum score by 2^8
 constexpr int kThreads = 256;
 constexpr float kLog2e = 1.4426950408889634f;
 
@@ -92,6 +97,9 @@ __device__ __forceinline__ void rotate(float* x, const float* c, const float* s,
     x[2 * k + 1] = sn * a + c[k] * b;
   }
 }
+
+// 2^x on the transcendental unit (v_exp_f32; results below 2^-126 may flush to zero)
+__device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 
 __device__ __forceinline__ float dot8(const float* a, const float4 b0, const float4 b1) {
   float d = a[0] * b0.x;
@@ -208,14 +216,14 @@ __global__ __launch_bounds__(kThreads) void k_attn_fwd(int n, int W, int C, int 
 #pragma unroll
       for (int r = 0; r < kPer; ++r) {
         const float sc = dot8(qs[r], k0, k1);
-        if (sc > mx[r]) {
-          const float f = exp2f(mx[r] - sc);
+        if (sc > mx[r] + kSlack) {
+          const float f = ex2(mx[r] - sc);
           l[r] *= f;
 #pragma unroll
           for (int d = 0; d < kHd; ++d) acc[r][d] *= f;
           mx[r] = sc;
         }
-        const float p = exp2f(sc - mx[r]);
+        const float p = ex2(sc - mx[r]);
         l[r] += p;
         axpy8(acc[r], p, v0, v1);
       }
@@ -309,7 +317,7 @@ __global__ __launch_bounds__(kThreads) void k_attn_bwd_q(int n, int W, int C, in
       const float4 k0 = kv[j][0], k1 = kv[j][1], v0 = kv[j][2], v1 = kv[j][3];
 #pragma unroll
       for (int r = 0; r < kPer; ++r) {
-        const float p = exp2f(dot8(qs[r], k0, k1) - lq[r]);
+        const float p = ex2(dot8(qs[r], k0, k1) - lq[r]);
         const float ds = p * (dot8(g[r], v0, v1) - Dq[r]);
         axpy8(acc[r], ds, k0, k1);
       }
@@ -390,7 +398,7 @@ __global__ __launch_bounds__(kThreads) void k_attn_bwd_kv(int n, int W, int C, i
       const float2 lD = ld[j];
 #pragma unroll
       for (int r = 0; r < kPer; ++r) {
-        const float p = exp2f(dot8(kk[r], q0, q1) - lD.x);
+        const float p = ex2(dot8(kk[r], q0, q1) - lD.x);
         axpy8(av[r], p, g0, g1);
         const float ds = p * (dot8(vv[r], g0, g1) - lD.y);
         axpy8(ak[r], ds, q0, q1);

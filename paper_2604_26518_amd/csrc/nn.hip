@@ -66,17 +66,21 @@ __device__ __forceinline__ int wrapi(int v, int N) { return v < 0 ? v + N : (v >
 
 enum Flags { F_BIAS = 1, F_SKIP = 2, F_ACT = 4, F_SCALE = 8 };
 
-// out[i][co] = epilogue( sum_t sum_ci x[tab[i][t]][ci] W[t][ci][co] )
-template <typename Tin, typename Tout, int CIN, int COUT, int NTAP, int FLAGS>
+// out[i][co] = epilogue( sum_t sum_ci x[tab[i][t]][ci] W[t][ci][co] ); a thread
+// computes COUT / SPLIT outputs of one node (blockIdx.y picks which), so small
+// levels still launch enough threads
+template <typename Tin, typename Tout, int CIN, int COUT, int NTAP, int FLAGS, int SPLIT>
 __global__ __launch_bounds__(kB) void k_gconv(int n, const int* __restrict__ tab, const Tin* __restrict__ x,
                                                const float* __restrict__ W, const float* __restrict__ b,
-                                               const uint16_t* __restrict__ skip, float scale, Tout* __restrict__ y,
-                                               int zero) {
+                                               const uint16_t* __restrict__ skip, float scale, Tout* __restrict__ y) {
+  static_assert(COUT % SPLIT == 0, "output channels split evenly");
+  constexpr int CO = COUT / SPLIT;
   const int i = blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
-  float acc[COUT];
+  const int co0 = blockIdx.y * CO;
+  float acc[CO];
 #pragma unroll
-  for (int co = 0; co < COUT; ++co) acc[co] = 0.f;
+  for (int co = 0; co < CO; ++co) acc[co] = 0.f;
 #pragma unroll 1
   for (int t = 0; t < NTAP; ++t) {
     const int src = (NTAP == 1 && tab == nullptr) ? i : tab[(size_t)i * NTAP + t];
@@ -85,20 +89,20 @@ __global__ __launch_bounds__(kB) void k_gconv(int n, const int* __restrict__ tab
 #pragma unroll
     for (int ci = 0; ci < CIN; ++ci) xin[ci] = ldf<Tin>(x + (size_t)src * CIN + ci);
     // wave-uniform weights of tap t through the constant address space (scalar loads)
-    const cp<float> Wt = (cp<float>)(W + (size_t)(t + (t & zero)) * CIN * COUT);
+    const cp<float> Wt = (cp<float>)(W + (size_t)t * CIN * COUT + co0);
 #pragma unroll
     for (int ci = 0; ci < CIN; ++ci)
 #pragma unroll
-      for (int co = 0; co < COUT; ++co) acc[co] = fmaf(xin[ci], Wt[ci * COUT + co], acc[co]);
+      for (int co = 0; co < CO; ++co) acc[co] = fmaf(xin[ci], Wt[ci * COUT + co], acc[co]);
   }
 #pragma unroll
-  for (int co = 0; co < COUT; ++co) {
+  for (int co = 0; co < CO; ++co) {
     float v = acc[co];
-    if constexpr (FLAGS & F_BIAS) v += b[co];
-    if constexpr (FLAGS & F_SKIP) v += bf2f(skip[(size_t)i * COUT + co]);
+    if constexpr (FLAGS & F_BIAS) v += b[co0 + co];
+    if constexpr (FLAGS & F_SKIP) v += bf2f(skip[(size_t)i * COUT + co0 + co]);
     if constexpr (FLAGS & F_ACT) v = v > 0.f ? v : kSlope * v;
     if constexpr (FLAGS & F_SCALE) v *= scale;
-    stf<Tout>(y + (size_t)i * COUT + co, v);
+    stf<Tout>(y + (size_t)i * COUT + co0 + co, v);
   }
 }
 
@@ -221,70 +225,136 @@ __global__ void k_arrange_mfma(int nlayers, const MfmaLayer* __restrict__ lay, i
   Wm[e] = f2bf(v);
 }
 
-// Weight gradient dW[t][ci][co] += sum_i x[tab[i][t]][ci] g[i][co], in a fixed
-// order: block (chunk, t) sums its chunk of nodes into partial[chunk][t][.],
-// then k_reduce_partials adds the chunks in chunk order (no float atomics, so
-// the gradient is the same bit for bit on every run).
-constexpr int kWChunk = 64;
-constexpr int kMaxChunks = 64;
-template <typename Tin, int CIN, int COUT, int NTAP>
-__global__ __launch_bounds__(kB) void k_wgrad(int n, const int* __restrict__ tab, const Tin* __restrict__ x,
+// Weight gradient dW[t][ci][co] += sum_i x[tab[i][t]][ci] g[i][co] on the FP32
+// matrix cores (v_mfma_f32_16x16x4_f32, D[ci][co] += sum over 4 nodes): a wave
+// owns a contiguous chunk of nodes and TPW taps and keeps every 16x16 (ci, co)
+// tile of those taps in accumulators; per step of 4 nodes lane l loads one
+// input value (node l / 16, channel l % 16 of a tile: BF16, gathered through
+// the table) and one gradient value (node l / 16, output channel l % 16), and
+// the matrix core forms the 4-node outer-product sums.  The gradient rows are
+// loaded once per step for all TPW taps.  The four waves of a block (four
+// consecutive chunks) add their sums in LDS in wave order and the block writes
+// partial[block][t][.]; k_reduce_partials then adds the blocks in a fixed
+// order (no float atomics: the gradient is the same bit for bit on every run).
+constexpr int kWgradWaves = 4;                    // waves (chunks) per block
+constexpr int kWgradTargetWaves = 8192;           // waves per launch (8 per SIMD)
+constexpr size_t kPartFloats = (size_t)16 << 20;  // partial sums of one layer (64 MiB)
+
+__device__ __forceinline__ f32x4_t mfma4(float a, float b, f32x4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int CIN, int COUT, int NTAP, int TPW>
+__global__ __launch_bounds__(kB) void k_wgrad(int n, const int* __restrict__ tab, const uint16_t* __restrict__ x,
                                                const float* __restrict__ g, float* __restrict__ partial,
-                                               int nodes_per_block) {
-  constexpr int P = CIN * COUT;
-  constexpr int PPT = (P + kB - 1) / kB;
-  __shared__ float xs[kWChunk][CIN];
-  __shared__ float gs[kWChunk][COUT];
-  const int t = blockIdx.y;
-  const int beg = blockIdx.x * nodes_per_block;
-  const int end = min(n, beg + nodes_per_block);
-  float acc[PPT];
+                                               int nodes_per_chunk) {
+  static_assert(CIN % 16 == 0, "input channels in tiles of 16");
+  static_assert(NTAP % TPW == 0, "taps in groups of TPW");
+  constexpr int CIT = CIN / 16, COT = (COUT + 15) / 16, TILES = TPW * CIT * COT;
+  __shared__ f32x4_t red[TILES][64];
+  const int lane = threadIdx.x & 63, col = lane & 15, kq = lane >> 4, wave = threadIdx.x >> 6;
+  const int chunk = blockIdx.x * kWgradWaves + wave;
+  const int t0 = blockIdx.y * TPW;
+  const int beg = (int)min((long long)n, (long long)chunk * nodes_per_chunk);
+  const int end = min(n, beg + nodes_per_chunk);
+  f32x4_t acc[TPW][CIT][COT];
 #pragma unroll
-  for (int k = 0; k < PPT; ++k) acc[k] = 0.f;
-  for (int base = beg; base < end; base += kWChunk) {
-    for (int e = threadIdx.x; e < kWChunk * CIN; e += kB) {
-      const int r = e / CIN, ci = e % CIN, node = base + r;
-      float v = 0.f;
-      if (node < end) {
-        const int src = (NTAP == 1 && tab == nullptr) ? node : tab[(size_t)node * NTAP + t];
-        if (src >= 0) v = ldf<Tin>(x + (size_t)src * CIN + ci);
-      }
-      xs[r][ci] = v;
-    }
-    for (int e = threadIdx.x; e < kWChunk * COUT; e += kB) {
-      const int r = e / COUT, co = e % COUT, node = base + r;
-      gs[r][co] = node < end ? g[(size_t)node * COUT + co] : 0.f;
-    }
-    __syncthreads();
+  for (int tt = 0; tt < TPW; ++tt)
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      const int p = threadIdx.x + k * kB;
-      if (p < P) {
-        const int ci = p / COUT, co = p % COUT;
-        float s = acc[k];
-#pragma unroll 8
-        for (int r = 0; r < kWChunk; ++r) s = fmaf(xs[r][ci], gs[r][co], s);
-        acc[k] = s;
+    for (int i = 0; i < CIT; ++i)
+#pragma unroll
+      for (int j = 0; j < COT; ++j) acc[tt][i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  // Every load is unconditional (indices clamped into range, the value selected
+  // away afterwards), so a step's loads issue together, and the table entries of
+  // the next step are fetched while the current step's rows are in flight.
+  int nxt[TPW];
+  auto table_row = [&](int base, int* out) {
+    const int node = min(base + kq, end - 1);
+    if constexpr (NTAP > 1) {
+      const int* row = tab + (size_t)node * NTAP + t0;  // multi-tap layers always have a table
+#pragma unroll
+      for (int tt = 0; tt < TPW; ++tt) out[tt] = row[tt];
+    } else {
+      out[0] = tab ? tab[node] : node;
+    }
+  };
+  if (beg < end) table_row(beg, nxt);
+#pragma unroll 1
+  for (int base = beg; base < end; base += 4) {
+    const int node = base + kq;
+    const bool ok = node < end;
+    const int nodec = min(node, end - 1);
+    int src[TPW];
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt) src[tt] = nxt[tt];
+    float b[COT];
+#pragma unroll
+    for (int j = 0; j < COT; ++j) {
+      const int co = 16 * j + col;
+      const float v = g[(size_t)nodec * COUT + min(co, COUT - 1)];
+      b[j] = (ok && co < COUT) ? v : 0.f;
+    }
+    float a[TPW][CIT];
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt)
+#pragma unroll
+      for (int i = 0; i < CIT; ++i) {
+        const float v = bf2f(x[(size_t)max(src[tt], 0) * CIN + 16 * i + col]);
+        a[tt][i] = (ok && src[tt] >= 0) ? v : 0.f;
       }
+    if (base + 4 < end) table_row(base + 4, nxt);
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt)
+#pragma unroll
+      for (int i = 0; i < CIT; ++i)
+#pragma unroll
+        for (int j = 0; j < COT; ++j) acc[tt][i][j] = mfma4(a[tt][i], b[j], acc[tt][i][j]);
+  }
+  // the four waves' sums, added in wave order
+  for (int w = 0; w < kWgradWaves; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int tt = 0; tt < TPW; ++tt)
+#pragma unroll
+        for (int i = 0; i < CIT; ++i)
+#pragma unroll
+          for (int j = 0; j < COT; ++j) {
+            f32x4_t& r = red[(tt * CIT + i) * COT + j][lane];
+            r = w == 0 ? acc[tt][i][j] : r + acc[tt][i][j];
+          }
     }
     __syncthreads();
   }
-  float* out = partial + ((size_t)blockIdx.x * NTAP + t) * P;
+  // lane l of a tile holds D[ci = 16 i + 4 (l / 16) + r][co = 16 j + l % 16], r = 0..3
+  for (int e = threadIdx.x; e < TILES * 64; e += kB) {
+    const int tile = e / 64, ln = e % 64;
+    const int tt = tile / (CIT * COT), i = (tile / COT) % CIT, j = tile % COT;
+    const int co = 16 * j + (ln & 15);
+    if (co >= COUT) continue;
+    float* out = partial + ((size_t)blockIdx.x * NTAP + t0 + tt) * CIN * COUT;
+    const f32x4_t v = red[tile][ln];
 #pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    const int p = threadIdx.x + k * kB;
-    if (p < P) out[p] = acc[k];
+    for (int r = 0; r < 4; ++r) out[(size_t)(16 * i + 4 * (ln >> 4) + r) * COUT + co] = v[r];
   }
 }
 
-// dst[e] += sum_{c < chunks} partial[c][e], c in increasing order
-__global__ void k_reduce_partials(size_t per, int chunks, const float* __restrict__ partial, float* __restrict__ dst) {
-  const size_t e = (size_t)blockIdx.x * kB + threadIdx.x;
-  if (e >= per) return;
-  float s = 0.f;
-  for (int c = 0; c < chunks; ++c) s += partial[(size_t)c * per + e];
-  dst[e] += s;
+// dst[e] += sum_{c < chunks} partial[c][e]: a block covers 64 elements with four
+// streams (chunks c = s, s + 4, ...), added in stream order (deterministic)
+__global__ __launch_bounds__(kB) void k_reduce_partials(size_t per, int chunks, const float* __restrict__ partial,
+                                                        float* __restrict__ dst) {
+  __shared__ float sh[4][64];
+  const int lane = threadIdx.x & 63, st = threadIdx.x >> 6;
+  const size_t e = (size_t)blockIdx.x * 64 + lane;
+  float sum = 0.f;
+  if (e < per)
+#pragma unroll 4
+    for (int c = st; c < chunks; c += 4) sum += partial[(size_t)c * per + e];
+  sh[st][lane] = sum;
+  __syncthreads();
+  if (st == 0 && e < per) dst[e] += ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
 }
+
+inline unsigned reduce_blocks(size_t per) { return (unsigned)((per + 63) / 64); }
 
 // Bias gradient db[co] += sum_i g[i][co]: per-block sums (grid-stride over a
 // fixed grid) into partial[block][co], then k_reduce_partials.
@@ -357,37 +427,43 @@ __global__ void k_embed(int n, const uint8_t* __restrict__ occ8, const float* __
   y[e] = f2bf(E[(size_t)occ8[i] * C + c]);
 }
 
-// Embedding gradient dE[o][c] += sum_{i : occ8[i] = o} g[i][c]: block o scans
-// every node in a fixed order and reduces its threads' sums in a fixed tree
-// (deterministic; each block reads the n occupancy bytes, an L2-resident stream).
-template <int C>
-__global__ __launch_bounds__(kB) void k_embed_grad(int n, const uint8_t* __restrict__ occ8, const float* __restrict__ g,
-                                                   float* __restrict__ dE) {
-  __shared__ float sh[kB / 64][C];
-  const int o = blockIdx.x;
-  float acc[C];
-#pragma unroll
-  for (int c = 0; c < C; ++c) acc[c] = 0.f;
-  for (int i = threadIdx.x; i < n; i += kB)
-    if (occ8[i] == o) {
-#pragma unroll
-      for (int c = 0; c < C; ++c) acc[c] += g[(size_t)i * C + c];
-    }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    float v = acc[c];
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) v += __shfl_down(v, d, 64);
-    if (lane == 0) sh[w][c] = v;
-  }
+// Embedding gradient dE[o][c] += sum of g[i][c] over the nodes i with occupancy o,
+// over the nodes sorted by occupancy (stable; built once at setup): block k sums
+// chunk k of that list (one occupancy value, at most kEmbedChunk nodes; thread t
+// takes channel t % C of every (kB / C)-th node, the kB / C streams are then
+// added in stream order) into partial[k][c], and k_embed_reduce adds the chunks
+// of each value in order (deterministic).
+constexpr int kEmbedChunk = 4096;
+
+struct EmbedChunk {
+  int value, start, count;
+};
+
+__global__ __launch_bounds__(kB) void k_embed_grad(const int* __restrict__ nodes, const EmbedChunk* __restrict__ chunks,
+                                                   int C, const float* __restrict__ g, float* __restrict__ partial) {
+  __shared__ float sh[kB];
+  const EmbedChunk ck = chunks[blockIdx.x];
+  const int S = kB / C, c = threadIdx.x % C, st = threadIdx.x / C;
+  float acc = 0.f;
+  if (st < S)
+    for (int k = st; k < ck.count; k += S) acc += g[(size_t)nodes[ck.start + k] * C + c];
+  sh[threadIdx.x] = acc;
   __syncthreads();
   if (threadIdx.x < C) {
-    float s = 0.f;
-#pragma unroll
-    for (int k = 0; k < kB / 64; ++k) s += sh[k][threadIdx.x];
-    dE[(size_t)o * C + threadIdx.x] += s;
+    float sum = 0.f;
+    for (int j = 0; j < S; ++j) sum += sh[j * C + threadIdx.x];
+    partial[(size_t)blockIdx.x * C + threadIdx.x] = sum;
   }
+}
+
+__global__ void k_embed_reduce(const int* __restrict__ first, int C, const float* __restrict__ partial,
+                               float* __restrict__ dE) {
+  const int e = blockIdx.x * kB + threadIdx.x;
+  if (e >= 256 * C) return;
+  const int v = e / C, c = e % C;
+  float sum = 0.f;
+  for (int k = first[v]; k < first[v + 1]; ++k) sum += partial[(size_t)k * C + c];
+  dE[e] += sum;
 }
 
 // tables ----------------------------------------------------------------------
@@ -523,10 +599,17 @@ static void gconv_dispatch(int cin, int cout, int ntap, int n, const int* tab, c
                            const float* b, const uint16_t* skip, float scale, void* y, hipStream_t s) {
   if (n <= 0) return;
   const unsigned g = nblk(n);
-#define GC(CI, CO, NT)                                                                                       \
-  if (cin == CI && cout == CO && ntap == NT) {                                                              \
-    hipLaunchKernelGGL((k_gconv<Tin, Tout, CI, CO, NT, FLAGS>), dim3(g), dim3(kB), 0, s, n, tab, (const Tin*)x, \
-                       W, b, skip, scale, (Tout*)y, 0);                                                      \
+  // below ~1000 blocks of nodes, a thread per 16 output channels
+  const bool split = g < 1024;
+#define GC(CI, CO, NT)                                                                                        \
+  if (cin == CI && cout == CO && ntap == NT) {                                                               \
+    constexpr int SP = CO % 16 == 0 ? CO / 16 : 1;                                                           \
+    if (split && SP > 1)                                                                                     \
+      hipLaunchKernelGGL((k_gconv<Tin, Tout, CI, CO, NT, FLAGS, SP>), dim3(g, SP), dim3(kB), 0, s, n, tab,    \
+                         (const Tin*)x, W, b, skip, scale, (Tout*)y);                                        \
+    else                                                                                                     \
+      hipLaunchKernelGGL((k_gconv<Tin, Tout, CI, CO, NT, FLAGS, 1>), dim3(g), dim3(kB), 0, s, n, tab,         \
+                         (const Tin*)x, W, b, skip, scale, (Tout*)y);                                        \
     GMT_LAUNCH_CHECK();                                                                                      \
     return;                                                                                                  \
   }
@@ -562,22 +645,33 @@ static void mfma_dispatch(int cin, int cout, int ntap, int n, const int* tab, co
   fail(GMT_E_INVAL, "MFMA gather conv (%d -> %d, %d taps) not instantiated", cin, cout, ntap);
 }
 
-template <typename Tin>
-static void wgrad_dispatch(int cin, int cout, int ntap, int n, const int* tab, const void* x, const float* g,
+// taps per wave: as many as keep at most 12 accumulator tiles (48 registers), so
+// that several waves per SIMD keep enough gathers in flight
+constexpr int wgrad_tpw(int cin, int cout, int ntap) {
+  const int tiles = (cin / 16) * ((cout + 15) / 16);
+  if (ntap == 1) return 1;
+  return tiles * 27 <= 12 ? 27 : tiles * 9 <= 12 ? 9 : tiles * 3 <= 12 ? 3 : 1;
+}
+
+static void wgrad_dispatch(int cin, int cout, int ntap, int n, const int* tab, const uint16_t* x, const float* g,
                            float* dW, float* partial, hipStream_t s) {
   if (n <= 0) return;
-  const int chunks = std::min(kMaxChunks, (n + 1023) / 1024);
-  const int per_block = (n + chunks - 1) / chunks;
-  const dim3 grid((unsigned)chunks, (unsigned)ntap);
-#define WG(CI, CO, NT)                                                                                     \
-  if (cin == CI && cout == CO && ntap == NT) {                                                            \
-    hipLaunchKernelGGL((k_wgrad<Tin, CI, CO, NT>), grid, dim3(kB), 0, s, n, tab, (const Tin*)x, g, partial, \
-                       per_block);                                                                         \
-    GMT_LAUNCH_CHECK();                                                                                    \
-    const size_t per = (size_t)NT * CI * CO;                                                               \
-    hipLaunchKernelGGL(k_reduce_partials, dim3(nblk(per)), dim3(kB), 0, s, per, chunks, partial, dW);      \
-    GMT_LAUNCH_CHECK();                                                                                    \
-    return;                                                                                                \
+  const size_t per = (size_t)ntap * cin * cout;
+#define WG(CI, CO, NT)                                                                                      \
+  if (cin == CI && cout == CO && ntap == NT) {                                                             \
+    constexpr int TPW = wgrad_tpw(CI, CO, NT), GROUPS = NT / TPW;                                          \
+    /* about kWgradTargetWaves waves of at least 64 nodes, within the partial buffer */                    \
+    int chunks = std::max(1, std::min((n + 63) / 64, kWgradTargetWaves / GROUPS));                         \
+    int blocks = (chunks + kWgradWaves - 1) / kWgradWaves;                                                 \
+    blocks = (int)std::max<size_t>(1, std::min<size_t>(blocks, kPartFloats / per));                        \
+    chunks = blocks * kWgradWaves;                                                                          \
+    const int npc = (n + chunks - 1) / chunks;                                                              \
+    hipLaunchKernelGGL((k_wgrad<CI, CO, NT, TPW>), dim3((unsigned)blocks, (unsigned)GROUPS), dim3(kB), 0, s, n, \
+                       tab, x, g, partial, npc);                                                            \
+    GMT_LAUNCH_CHECK();                                                                                     \
+    hipLaunchKernelGGL(k_reduce_partials, dim3(reduce_blocks(per)), dim3(kB), 0, s, per, blocks, partial, dW); \
+    GMT_LAUNCH_CHECK();                                                                                     \
+    return;                                                                                                 \
   }
   WG(16, 16, 27) WG(32, 32, 27) WG(64, 64, 27) WG(16, 32, 27) WG(32, 64, 27) WG(32, 16, 27) WG(64, 32, 27)
   WG(16, 32, 1) WG(32, 32, 1) WG(64, 32, 1) WG(32, 18, 1) WG(32, 3, 1) WG(16, 16, 1) WG(64, 64, 1)
@@ -594,7 +688,7 @@ static void bgrad_dispatch(int cout, int n, const float* g, float* db, float* pa
   if (cout == CO) {                                                                              \
     hipLaunchKernelGGL(k_bgrad<CO>, dim3(grid), dim3(kB), 0, s, n, g, partial);                  \
     GMT_LAUNCH_CHECK();                                                                          \
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kB), 0, s, (size_t)CO, (int)grid, partial, db); \
+    hipLaunchKernelGGL(k_reduce_partials, dim3(reduce_blocks(CO)), dim3(kB), 0, s, (size_t)CO, (int)grid, partial, db); \
     GMT_LAUNCH_CHECK();                                                                          \
     return;                                                                                      \
   }
@@ -693,6 +787,11 @@ struct NNState {
   std::vector<uint16_t*> q, k, v, o16, sb;
   std::vector<float*> o32, lse;
   float* g3 = nullptr;
+  // level-1 nodes sorted by occupancy and the chunk table of the embedding gradient
+  int* emb_nodes = nullptr;
+  EmbedChunk* emb_chunks = nullptr;
+  int* emb_first = nullptr;  // [257]: first chunk of every occupancy value
+  int n_emb_chunks = 0;
   // the tensor that leaves level l's encoder: s_l with attention, a_l without
   const uint16_t* out(int l) const { return nl.att ? sb[l] : a[l]; }
 };
@@ -829,7 +928,7 @@ void nn_setup(Hier& h, const gmt_nn_config& cfg, hipStream_t s) {
   S->g1 = h.alloc<float>(maxnc);
   S->g2 = h.alloc<float>(maxnc);
   if (S->nl.att) S->g3 = h.alloc<float>(maxnc);
-  S->part = h.alloc<float>(std::max((size_t)kMaxChunks * 27 * 64 * 64, (size_t)kBgradBlocks * 64));
+  S->part = h.alloc<float>(std::max(kPartFloats, (size_t)kBgradBlocks * 64));
   GMT_HIP(hipStreamSynchronize(s));
 }
 
@@ -953,7 +1052,7 @@ static void attention_block_backward(Hier& h, NNState& S, int l, float* grad, hi
   const size_t tc = (size_t)n * C;
   float* gs = S.ga[l];
   // Wo: rows are nodes, the input o is gathered through inv
-  wgrad_dispatch<uint16_t>(C, C, 1, n, S.inv[l], S.o16[l], gs, grad + N.Wo[l], S.part, s);
+  wgrad_dispatch(C, C, 1, n, S.inv[l], S.o16[l], gs, grad + N.Wo[l], S.part, s);
   transpose_taps(S, W + N.Wo[l], 1, C, C, false, s);
   dgrad(S, C, C, 1, n, S.order[l], gs, S.g0, s);  // dL/do in serialization order
   attention_backward(n, attention_window(l), C, h.lv[l].N, S.ser_lin[l], S.q[l], S.k[l], S.v[l], S.o32[l],
@@ -962,11 +1061,42 @@ static void attention_block_backward(Hier& h, NNState& S, int l, float* grad, hi
   float* gx[3] = {S.g1, S.g2, S.g3};
   for (int j = 0; j < 3; ++j) {
     // rows in serialization order, the input a gathered through order; dL/da += gathered back through inv
-    wgrad_dispatch<uint16_t>(C, C, 1, n, S.order[l], S.a[l], gx[j], grad + Wx[j], S.part, s);
+    wgrad_dispatch(C, C, 1, n, S.order[l], S.a[l], gx[j], grad + Wx[j], S.part, s);
     transpose_taps(S, W + Wx[j], 1, C, C, false, s);
     dgrad(S, C, C, 1, n, S.inv[l], gx[j], S.g0, s);
     addv(gs, S.g0, tc, s);
   }
+}
+
+// The embedding gradient's node order (level-1 nodes grouped by occupancy, stable)
+// and its chunk table, built on the first backward (inference never needs it).
+static void embed_order(Hier& h, NNState& S, hipStream_t s) {
+  if (S.emb_nodes) return;
+  const int n0 = h.lv[0].n_n;
+  std::vector<uint8_t> occ((size_t)n0);
+  GMT_HIP(hipMemcpyAsync(occ.data(), h.lv[0].occ8, (size_t)n0, hipMemcpyDeviceToHost, s));
+  GMT_HIP(hipStreamSynchronize(s));
+  std::vector<int> cnt(257, 0), nodes((size_t)n0);
+  for (int i = 0; i < n0; ++i) ++cnt[occ[i] + 1];
+  for (int v = 0; v < 256; ++v) cnt[v + 1] += cnt[v];
+  std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+  for (int i = 0; i < n0; ++i) nodes[pos[occ[i]]++] = i;
+  std::vector<EmbedChunk> ch;
+  std::vector<int> first(257, 0);
+  for (int v = 0; v < 256; ++v) {
+    first[v] = (int)ch.size();
+    for (int b = cnt[v]; b < cnt[v + 1]; b += kEmbedChunk) ch.push_back({v, b, std::min(kEmbedChunk, cnt[v + 1] - b)});
+  }
+  first[256] = (int)ch.size();
+  S.n_emb_chunks = (int)ch.size();
+  S.emb_nodes = h.alloc<int>(std::max(n0, 1));
+  S.emb_chunks = h.alloc<EmbedChunk>(std::max<size_t>(ch.size(), 1));
+  S.emb_first = h.alloc<int>(257);
+  GMT_HIP(hipMemcpyAsync(S.emb_nodes, nodes.data(), (size_t)n0 * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!ch.empty())
+    GMT_HIP(hipMemcpyAsync(S.emb_chunks, ch.data(), ch.size() * sizeof(EmbedChunk), hipMemcpyHostToDevice, s));
+  GMT_HIP(hipMemcpyAsync(S.emb_first, first.data(), 257 * sizeof(int), hipMemcpyHostToDevice, s));
+  GMT_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
 }
 
 // grad += d/dparams sum_l <gout[l], out[l]> (activations of the last forward)
@@ -984,17 +1114,17 @@ void nn_backward(Hier& h, const float* const* gout, float* grad, hipStream_t s) 
     hipLaunchKernelGGL(k_scale_copy, dim3(nblk(tq)), dim3(kB), 0, s, tq, gout[l], (float)h.N, S.g2);
     GMT_LAUNCH_CHECK();
     center_rows(S, S.g2, n, q, s);
-    wgrad_dispatch<uint16_t>(H, q, 1, n, nullptr, S.z2[l], S.g2, grad + N.W3[l], S.part, s);
+    wgrad_dispatch(H, q, 1, n, nullptr, S.z2[l], S.g2, grad + N.W3[l], S.part, s);
     bgrad_dispatch(q, n, S.g2, grad + N.b3[l], S.part, s);
     transpose_taps(S, W + N.W3[l], 1, H, q, false, s);
     dgrad(S, q, H, 1, n, nullptr, S.g2, S.g0, s);
     act_grad(S.g0, S.z2[l], (size_t)n * H, s);
-    wgrad_dispatch<uint16_t>(H, H, 1, n, nullptr, S.z1[l], S.g0, grad + N.W2[l], S.part, s);
+    wgrad_dispatch(H, H, 1, n, nullptr, S.z1[l], S.g0, grad + N.W2[l], S.part, s);
     bgrad_dispatch(H, n, S.g0, grad + N.b2[l], S.part, s);
     transpose_taps(S, W + N.W2[l], 1, H, H, false, s);
     dgrad(S, H, H, 1, n, nullptr, S.g0, S.g1, s);
     act_grad(S.g1, S.z1[l], (size_t)n * H, s);
-    wgrad_dispatch<uint16_t>(C, H, 1, n, nullptr, S.d[l], S.g1, grad + N.W1[l], S.part, s);
+    wgrad_dispatch(C, H, 1, n, nullptr, S.d[l], S.g1, grad + N.W1[l], S.part, s);
     bgrad_dispatch(H, n, S.g1, grad + N.b1[l], S.part, s);
     transpose_taps(S, W + N.W1[l], 1, C, H, false, s);
     dgrad(S, H, C, 1, n, nullptr, S.g1, S.g2, s);
@@ -1006,7 +1136,7 @@ void nn_backward(Hier& h, const float* const* gout, float* grad, hipStream_t s) 
     const size_t tc = (size_t)n * C;
     GMT_HIP(hipMemcpyAsync(S.g0, S.gd[l], tc * sizeof(float), hipMemcpyDeviceToDevice, s));
     act_grad(S.g0, S.d[l], tc, s);
-    wgrad_dispatch<uint16_t>(C, C, 27, n, S.conv[l], S.t[l], S.g0, grad + N.Wd[l], S.part, s);
+    wgrad_dispatch(C, C, 27, n, S.conv[l], S.t[l], S.g0, grad + N.Wd[l], S.part, s);
     bgrad_dispatch(C, n, S.g0, grad + N.bd[l], S.part, s);
     transpose_taps(S, W + N.Wd[l], 27, C, C, true, s);
     dgrad(S, C, C, 27, n, S.conv[l], S.g0, S.g1, s);
@@ -1015,7 +1145,7 @@ void nn_backward(Hier& h, const float* const* gout, float* grad, hipStream_t s) 
     GMT_HIP(hipMemcpyAsync(S.ga[l], S.g1, tc * sizeof(float), hipMemcpyDeviceToDevice, s));
     bgrad_dispatch(C, n, S.g1, grad + N.bu[l], S.part, s);
     const uint16_t* dn = l + 1 == L - 1 ? S.out(L - 1) : S.d[l + 1];
-    wgrad_dispatch<uint16_t>(Cn, C, 27, n, S.unpool[l], dn, S.g1, grad + N.Wu[l], S.part, s);
+    wgrad_dispatch(Cn, C, 27, n, S.unpool[l], dn, S.g1, grad + N.Wu[l], S.part, s);
     transpose_taps(S, W + N.Wu[l], 27, Cn, C, false, s);
     dgrad(S, C, Cn, 27, nn, S.pool[l], S.g1, S.g2, s);
     addv(S.gd[l + 1], S.g2, (size_t)nn * Cn, s);
@@ -1031,24 +1161,28 @@ void nn_backward(Hier& h, const float* const* gout, float* grad, hipStream_t s) 
     if (N.att) attention_block_backward(h, S, l, grad, s);  // ga[l]: dL/ds_l -> dL/da_l
     GMT_HIP(hipMemcpyAsync(S.g0, S.ga[l], tc * sizeof(float), hipMemcpyDeviceToDevice, s));
     act_grad(S.g0, S.a[l], tc, s);
-    wgrad_dispatch<uint16_t>(C, C, 27, n, S.conv[l], S.h[l], S.g0, grad + N.We[l], S.part, s);
+    wgrad_dispatch(C, C, 27, n, S.conv[l], S.h[l], S.g0, grad + N.We[l], S.part, s);
     bgrad_dispatch(C, n, S.g0, grad + N.be[l], S.part, s);
     transpose_taps(S, W + N.We[l], 27, C, C, true, s);
     dgrad(S, C, C, 27, n, S.conv[l], S.g0, S.g1, s);
     if (l > 0) {
       const int Cp = N.C[l - 1], np = h.lv[l - 1].n_n;
       act_grad(S.g1, S.h[l], tc, s);
-      wgrad_dispatch<uint16_t>(Cp, C, 27, n, S.pool[l - 1], S.out(l - 1), S.g1, grad + N.Wp[l - 1], S.part, s);
+      wgrad_dispatch(Cp, C, 27, n, S.pool[l - 1], S.out(l - 1), S.g1, grad + N.Wp[l - 1], S.part, s);
       bgrad_dispatch(C, n, S.g1, grad + N.bp[l - 1], S.part, s);
       transpose_taps(S, W + N.Wp[l - 1], 27, Cp, C, false, s);
       dgrad(S, C, Cp, 27, np, S.unpool[l - 1], S.g1, S.g2, s);
       addv(S.ga[l - 1], S.g2, (size_t)np * Cp, s);
     } else {
-      const int n0 = h.lv[0].n_n;
-      if (C == 16) hipLaunchKernelGGL(k_embed_grad<16>, dim3(256), dim3(kB), 0, s, n0, h.lv[0].occ8, S.g1, grad + N.E);
-      else if (C == 32) hipLaunchKernelGGL(k_embed_grad<32>, dim3(256), dim3(kB), 0, s, n0, h.lv[0].occ8, S.g1, grad + N.E);
-      else fail(GMT_E_INVAL, "embedding width %d not instantiated", C);
-      GMT_LAUNCH_CHECK();
+      embed_order(h, S, s);
+      if (S.n_emb_chunks > 0) {
+        hipLaunchKernelGGL(k_embed_grad, dim3(S.n_emb_chunks), dim3(kB), 0, s, S.emb_nodes, S.emb_chunks, C, S.g1,
+                           S.part);
+        GMT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_embed_reduce, dim3(nblk((size_t)256 * C)), dim3(kB), 0, s, S.emb_first, C, S.part,
+                           grad + N.E);
+        GMT_LAUNCH_CHECK();
+      }
     }
   }
 }

@@ -48,15 +48,16 @@ def make_cells(N, seeds, procs=16):
     procs = max(1, min(procs, os.cpu_count() or 1))
     pool = mp.get_context("fork").Pool(procs)
     try:
-        return pool.map(_gen, [(s, N) for s in seeds], chunksize=4)
+        seeds = list(seeds)
+        return pool.map(_gen, [(s, N) for s in seeds], chunksize=max(1, min(4, len(seeds) // procs)))
     finally:
         pool.close()
         pool.join()
 
 
-def build(vox, levels, physics="elastic", attention=False):
+def build(vox, levels, physics="elastic", attention=False, net_levels=0):
     H = B.Hierarchy(vox, levels, physics)
-    H.nn_setup(channels_for(levels), attention=attention)
+    H.nn_setup(channels_for(net_levels or levels), attention=attention)
     return H
 
 
@@ -86,6 +87,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--levels", type=int, default=0)
+    ap.add_argument("--net-levels", type=int, default=0,
+                    help="network on the finest levels only (default: every level of the hierarchy)")
     ap.add_argument("--cells", type=int, default=1024)
     ap.add_argument("--held-out", type=int, default=16)
     ap.add_argument("--steps", type=int, default=20000, help="length of the cosine schedule")
@@ -96,6 +99,7 @@ def main(argv=None):
     ap.add_argument("--test-seed0", type=int, default=900000)
     ap.add_argument("--init", default="", help="start from these exported (BF16) weights")
     ap.add_argument("--warmup-steps", type=int, default=300)
+    ap.add_argument("--ema", type=float, default=0.999, help="decay of the weights' moving average")
     ap.add_argument("--attention", action="store_true", help="an attention block per level (Sec. 4.2-4.3)")
     ap.add_argument("--ckpt", default="unet.pt")
     ap.add_argument("--resume", action="store_true")
@@ -104,8 +108,11 @@ def main(argv=None):
     ap.add_argument("--time-budget", type=float, default=0.0, help="stop after this many seconds of training")
     ap.add_argument("--cache-gb", type=float, default=120.0, help="GPU memory for cached hierarchies")
     ap.add_argument("--eval-every", type=int, default=1000)
+    ap.add_argument("--steps-per-cell", type=int, default=1,
+                    help="consecutive steps on one drawn cell (amortises the build of large uncached cells)")
     args = ap.parse_args(argv)
     levels = args.levels or B.default_levels(args.N)
+    nl = args.net_levels or levels
     t0 = time.time()
     # all cells are generated (forked workers) before the first GPU call
     cells = make_cells(args.N, range(args.seed0, args.seed0 + args.cells))
@@ -114,8 +121,8 @@ def main(argv=None):
     print(f"# {len(cells)} train + {len(test)} held-out cells at {args.N}^3 in {time.time() - t0:.1f} s, "
           f"levels {levels}", flush=True)
     att = args.attention
-    n_params = B.nn_param_count(levels, channels_for(levels), attention=att)
-    tr = Trainer(n_params, levels, lr=args.lr, lam=args.lam, warmup=args.warmup_steps, attention=att)
+    n_params = B.nn_param_count(nl, channels_for(nl), attention=att)
+    tr = Trainer(n_params, nl, lr=args.lr, lam=args.lam, warmup=args.warmup_steps, attention=att, ema=args.ema)
     if args.init:
         from .learned import load_weights
         w, winfo = load_weights(args.init)
@@ -127,7 +134,7 @@ def main(argv=None):
     if args.resume and os.path.exists(args.ckpt):
         tr.load(args.ckpt)
         print(f"# resumed {args.ckpt} at step {tr.step}", flush=True)
-    hs_test = [build(voxels(c, args.N), levels, attention=att) for c in test]
+    hs_test = [build(voxels(c, args.N), levels, attention=att, net_levels=nl) for c in test]
     base0 = evaluate(tr.ema, hs_test)
     zero = evaluate_zero(hs_test)
     print(f"# params {n_params}; held-out post-V-cycle residual: zero init median {np.median(zero):.3e}, "
@@ -139,17 +146,19 @@ def main(argv=None):
     t_last = t_start
     rng = np.random.default_rng(tr.step)
     k = 0
+    H, idx, fresh = None, -1, False
     while tr.step < args.steps:
-        idx = int(rng.integers(len(cells)))
-        H = cache.get(idx)
-        fresh = H is None
-        if fresh:
-            H = build(voxels(cells[idx], args.N), levels, attention=att)
-            if torch.cuda.memory_allocated() < budget:
-                cache[idx] = H
+        if k % args.steps_per_cell == 0:
+            if fresh and idx not in cache:
+                H.close()
+            idx = int(rng.integers(len(cells)))
+            H = cache.get(idx)
+            fresh = H is None
+            if fresh:
+                H = build(voxels(cells[idx], args.N), levels, attention=att, net_levels=nl)
+                if torch.cuda.memory_allocated() < budget:
+                    cache[idx] = H
         loss, rn, rel = tr.train_cell(H, args.steps)
-        if fresh and idx not in cache:
-            H.close()
         if not math.isfinite(loss):
             raise RuntimeError(f"non-finite loss at step {tr.step}")
         log.append({"step": tr.step, "loss": loss, "rel": rel, "family": cells[idx][1]})
@@ -170,6 +179,8 @@ def main(argv=None):
         if args.time_budget and now - t_start > args.time_budget:
             print(f"# time budget reached at step {tr.step}", flush=True)
             break
+    if fresh and idx not in cache:
+        H.close()
     tr.save(args.ckpt)
     ev = evaluate(tr.ema, hs_test)
     ev_noinj = evaluate(tr.ema, hs_test, inject=False)
@@ -179,8 +190,12 @@ def main(argv=None):
                "step": tr.step, "seconds": time.time() - t_start, "ms_per_step": (time.time() - t_start) / max(k, 1) * 1e3}
     print("# " + json.dumps(summary), flush=True)
     if args.export:
-        save_weights(args.export, tr.ema, levels, args.N, "elastic", meta={"step": tr.step, **summary},
-                     attention=att)
+        meta = {"step": tr.step, "train_cells": args.cells, "train_seed0": args.seed0,
+                "held_out_seed0": args.test_seed0, "steps_per_cell": args.steps_per_cell, "lr": args.lr,
+                "ema": args.ema, **summary}
+        if args.init:
+            meta["init"] = os.path.basename(args.init)
+        save_weights(args.export, tr.ema, nl, args.N, "elastic", meta=meta, attention=att)
         print(f"# exported EMA weights to {args.export}", flush=True)
     if args.log:
         with open(args.log, "w") as fh:

@@ -126,3 +126,30 @@ def test_network_beats_zero_init_on_held_out_cells():
     med = float(np.median(ratios))
     print(f"[gain] median ratio network / zero init after one V-cycle: {med:.3f}", flush=True)
     assert med <= 0.85
+
+
+def test_512_network_beats_zero_init_on_a_held_out_cell():
+    """The 512^3 network (fine-tuned at 512^3 from the 128^3 one, on the 6 finest of 8 levels)
+    against a zero start on a held-out 512^3 workload cell: one V-cycle each."""
+    from paper_2604_26518_amd import binding, learned
+    params, info = learned.load_weights(os.path.join(ROOT, "paper_2604_26518_amd", "weights", "unet512_elastic.npz"))
+    assert info["N"] == 512
+    seed = info["held_out_seed0"]
+    fam, vf, vox = workload_cell(512, seed)
+    print(f"[gain512] seed {seed} {fam} VF {vf:.2f}: cell generated", flush=True)
+    H = binding.Hierarchy(vox, binding.default_levels(512), "elastic")
+    H.nn_setup(info["channels"])
+    f64 = H.load_vector()
+    f32 = f64.to(torch.float32)
+    rel = lambda u: float(np.max(H.relative_residual(f64, u.to(torch.float64))))  # noqa: E731
+    u0 = torch.zeros_like(f32)
+    H.vcycle(f32, u0)
+    r0 = rel(u0)
+    del u0
+    preds = H.nn_forward(params)
+    u1 = preds[0].clone()
+    H.vcycle(f32, u1, e_init=learned.injection(H, preds))
+    r1 = rel(u1)
+    H.close()
+    print(f"[gain512] zero init {r0:.3f}, network {r1:.3f}, ratio {r1 / r0:.3f}", flush=True)
+    assert r1 <= 0.85 * r0
