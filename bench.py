@@ -388,6 +388,8 @@ def cell512(args):
             "CH_learned_vs_plain": float(np.linalg.norm(rl["CH"] - rp["CH"]) / np.linalg.norm(rp["CH"]))}}
         del sv
         print("# spinodal done", file=sys.stderr, flush=True)
+        out["extras"]["attention512"] = attention_extra(B, vox, levels, net_levels)
+        print("# attention done", file=sys.stderr, flush=True)
         out["extras"]["mixed_vs_fp64_128"] = mixed_vs_fp64(B, res["c2"], B.default_levels(128), args.tol,
                                                            args.max_iter, args.workers)
         print("# mixed vs FP64 batch done", file=sys.stderr, flush=True)
@@ -483,6 +485,51 @@ def cells128(args):
            "dof_solves_per_s": round(dofs / wall, 1), "iterations_mean": float(np.mean(its_all)),
            "iterations_max": int(np.max(its_all)), "roofline": roof}
     print(json.dumps(out), flush=True)
+
+
+# algorithmic FP32 operations per attention score in the forward: the 8-term q.k dot
+# and the 8-term p v update (2 x 16), the exponential, the offset subtraction and the
+# sum of the probabilities
+ATTN_FLOP_PER_SCORE = 35
+FP32_PEAK_TFLOPS = 157.3
+
+
+def attention_extra(B, vox, levels, net_levels, reps=5):
+    """The network with an attention block per level on the headline cell (seeded random
+    weights: timing only): forward time against the convolutional network's, and every
+    level's window-attention kernel timed with HIP events on its launch stream."""
+    import torch
+
+    from paper_2604_26518_amd.learned import channels_for, init_params
+    H = B.Hierarchy(vox, levels, "elastic")
+    chs = channels_for(net_levels)
+    H.nn_setup(chs, attention=True)
+    params = init_params(H.n_params, net_levels, attention=True, seed=1)
+    H.nn_forward(params)
+    _sync()
+    t = time.perf_counter()
+    for _ in range(reps):
+        H.nn_forward(params)
+    _sync()
+    fwd_ms = (time.perf_counter() - t) / reps * 1e3
+    per_level = []
+    for l in range(net_levels):
+        n, W, heads = H.n_n(l + 1), min(256 << l, 1024), chs[l] // 8
+        scores = heads * ((n // W) * W * W + (n % W) ** 2)
+        ms = H.nn_time_attention(l + 1, reps)
+        tf = scores * ATTN_FLOP_PER_SCORE / (ms * 1e-3) / 1e12
+        per_level.append({"level": l + 1, "tokens": n, "window": W, "heads": heads, "scores": scores,
+                          "kernel_ms": round(ms, 3), "tflops": round(tf, 2)})
+    H.close()
+    top = per_level[0]
+    return {"workload": "headline cell, network with one serialized window-attention block (Ra-RoPE) per level "
+                        "on levels 1..%d, seeded random weights" % net_levels,
+            "forward_ms": round(fwd_ms, 2), "levels": per_level,
+            "attention_ms_total": round(sum(x["kernel_ms"] for x in per_level), 2),
+            "roofline": {"kernel": "k_attn_fwd, level 1", "bound": "alu", "achieved": top["tflops"],
+                         "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(top["tflops"] / FP32_PEAK_TFLOPS, 4),
+                         "flop_per_score": ATTN_FLOP_PER_SCORE}}
 
 
 def run_uneven(B, cells, tol, max_iter, workers, graph, mem_gb):

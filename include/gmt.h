@@ -429,6 +429,13 @@ gmt_status gmt_vcycle_loss(gmt_hier_t h, const float* const* d_pred, const gmt_c
 gmt_status gmt_time_sweep(gmt_hier_t h, int32_t level, int32_t reps, int32_t dtype, double* h_ms,
                           void* stream);
 
+/* Instrumentation: after a gmt_nn_forward of a network with attention blocks,
+ * times `reps` launches of level l's window-attention forward kernel on the
+ * stored q, k, v (rewriting the same outputs) with HIP events on the given
+ * stream; h_ms receives the mean duration of one launch.  GMT_E_STATE without
+ * attention blocks.  Synchronizes the stream. */
+gmt_status gmt_nn_time_attention(gmt_hier_t h, int32_t level, int32_t reps, double* h_ms, void* stream);
+
 const char* gmt_last_error(void);
 
 #ifdef __cplusplus

@@ -123,6 +123,7 @@ SIGNATURES = {
     "gmt_nn_backward": (_P, _P, _P, _P),
     "gmt_nn_activation": (_P, _I, _I, _P, ct.POINTER(ct.c_int32), _P),
     "gmt_nn_serialization": (_P, _I, _P, _P),
+    "gmt_nn_time_attention": (_P, _I, _I, ct.POINTER(ct.c_double), _P),
     "gmt_nn_adamw": (_P, _P, _P, _P, ct.c_size_t, ct.c_double, ct.c_double, ct.c_double, ct.c_double,
                      ct.c_double, _I, ct.c_double, _P),
     "gmt_nn_norm2": (_P, ct.c_size_t, ct.POINTER(ct.c_double), _P),
@@ -501,6 +502,13 @@ class Hierarchy:
         out = torch.empty(self.n_n(level), dtype=torch.int32, device=self._vox.device)
         _check(lib().gmt_nn_serialization(self._h, level, _ptr(out), _stream()))
         return out
+
+    def nn_time_attention(self, level: int, reps: int = 10) -> float:
+        """Mean ms of one launch of level `level`'s attention forward kernel (after a forward)."""
+        self._level(level)
+        out = ct.c_double()
+        _check(lib().gmt_nn_time_attention(self._h, level, reps, ct.byref(out), _stream()))
+        return out.value
 
     def vcycle_loss(self, preds, lam=0.0, want_grad=True, want_u1=False, nu1=2, nu2=2, smoother="chebyshev",
                     omega=None, lo=None, hi=None):

@@ -407,6 +407,7 @@ double nn_norm2_noalloc(const float* x, size_t n, hipStream_t s);
 size_t nn_norm2_noalloc_max();
 int nn_activation(Hier& h, int l, int which, float* out, hipStream_t s);
 void nn_serialization(Hier& h, int l, int* out, hipStream_t s);
+double nn_time_attention(Hier& h, int l, int reps, hipStream_t s);
 void nn_ema(float* e, const float* x, size_t n, double decay, hipStream_t s);
 
 // attention block of the learned initializer (attention.hip): Morton serialization

@@ -102,7 +102,7 @@ void Hier::release_all() {
   owned_hip.clear();
 }
 
-// GMT_FORCE_L1_VARIANT=<cb> pins the level-1 sweep variant (0..3, 5..7, see the
+// GMT_FORCE_L1_VARIANT=<cb> pins the level-1 sweep variant (0..3, 5..8, see the
 // autotuner) for tests that compare every variant with the oracle.
 static int forced_l1_variant() {
   const char* e = std::getenv("GMT_FORCE_L1_VARIANT");
@@ -2518,6 +2518,15 @@ gmt_status gmt_nn_serialization(gmt_hier_t H, int32_t level, int32_t* d_order, v
     check_level(H, level);
     if (!d_order) fail(GMT_E_INVAL, "null pointer");
     nn_serialization(H->h, level - 1, d_order, S(stream));
+  });
+}
+
+gmt_status gmt_nn_time_attention(gmt_hier_t H, int32_t level, int32_t reps, double* h_ms, void* stream) {
+  return guarded([&] {
+    check_level(H, level);
+    if (!h_ms) fail(GMT_E_INVAL, "h_ms is NULL");
+    if (reps < 1 || reps > 100000) fail(GMT_E_INVAL, "reps out of range");
+    *h_ms = nn_time_attention(H->h, level - 1, reps, S(stream));
   });
 }
 

@@ -1192,6 +1192,30 @@ __global__ void k_widen(size_t total, const uint16_t* __restrict__ a, float* __r
   if (i < total) b[i] = bf2f(a[i]);
 }
 
+double nn_time_attention(Hier& h, int l, int reps, hipStream_t s) {
+  NNState& S = nn_state(h);
+  if (!S.nl.att) fail(GMT_E_STATE, "the network was set up without attention blocks");
+  if (l >= S.nl.L) fail(GMT_E_INVAL, "level %d is below the network's %d levels", l + 1, S.nl.L);
+  const int n = h.lv[l].n_n, C = S.nl.C[l];
+  auto run = [&] {
+    attention_forward(n, attention_window(l), C, h.lv[l].N, S.ser_lin[l], S.q[l], S.k[l], S.v[l], S.o32[l],
+                      S.o16[l], S.lse[l], s);
+  };
+  run();  // warm
+  hipEvent_t e0, e1;
+  GMT_HIP(hipEventCreate(&e0));
+  GMT_HIP(hipEventCreate(&e1));
+  GMT_HIP(hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r) run();
+  GMT_HIP(hipEventRecord(e1, s));
+  GMT_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  GMT_HIP(hipEventElapsedTime(&ms, e0, e1));
+  GMT_HIP(hipEventDestroy(e0));
+  GMT_HIP(hipEventDestroy(e1));
+  return (double)ms / reps;
+}
+
 void nn_serialization(Hier& h, int l, int* out, hipStream_t s) {
   NNState& S = nn_state(h);
   if (!S.nl.att) fail(GMT_E_STATE, "the network was set up without attention blocks");

@@ -126,10 +126,16 @@ def main(argv=None):
     if args.init:
         from .learned import load_weights
         w, winfo = load_weights(args.init)
-        if w.numel() != n_params:
+        n_conv = B.nn_param_count(nl, channels_for(nl))
+        if w.numel() == n_params:
+            tr.params.copy_(w)
+        elif att and w.numel() == n_conv:
+            # a convolutional network: the attention projections follow its parameters and keep
+            # their initialisation (small output projections: every block starts near the identity)
+            tr.params[:n_conv].copy_(w)
+        else:
             raise ValueError(f"{args.init} holds {w.numel()} parameters, the network has {n_params}")
-        tr.params.copy_(w)
-        tr.ema.copy_(w)
+        tr.ema.copy_(tr.params)
         print(f"# initialised from {args.init} ({winfo.get('step')} steps)", flush=True)
     if args.resume and os.path.exists(args.ckpt):
         tr.load(args.ckpt)

@@ -268,3 +268,19 @@ def test_attention_deterministic():
     assert torch.equal(g1, g2)
     assert float(g1.abs().sum()) > 0
     H.close()
+
+
+def test_attention_timing_keeps_the_outputs():
+    """gmt_nn_time_attention relaunches a level's attention kernel on the stored q, k, v: it
+    reports a positive duration and leaves the stored attention output bit for bit as it was."""
+    vox, H, net, g, flat = _make(16, 3, [16, 32, 64])
+    H.nn_forward(_t(flat))
+    before = [H.nn_activation(l + 1, 10).clone() for l in range(3)]
+    for l in range(3):
+        assert H.nn_time_attention(l + 1, 3) > 0
+    for l in range(3):
+        assert torch.equal(H.nn_activation(l + 1, 10), before[l])
+    H.nn_setup([16, 32, 64])
+    with pytest.raises(_gmt().GmtError):
+        H.nn_time_attention(1, 3)
+    H.close()
