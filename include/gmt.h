@@ -381,6 +381,16 @@ gmt_status gmt_nn_backward(gmt_hier_t h, const float* const* d_gout, float* d_gr
 gmt_status gmt_nn_activation(gmt_hier_t h, int32_t level, int32_t which, float* d_out, int32_t* h_width,
                              void* stream);
 
+/* Supervised term of training on solved cells (the plain solver's solution as
+ * the target of u_hat^1; used with the label-free loss of gmt_vcycle_loss):
+ * with t_c the target d_target [n_1][c][d] (FP32) centred per column like the
+ * predictions, h_loss = alpha |d_pred - t_c|^2 / |t_c|^2 (FP64 sums in a fixed
+ * order), and, if d_grad is not NULL, d_grad += its gradient with respect to
+ * d_pred (the gradient to pass, with the V-cycle loss's, to gmt_nn_backward).
+ * GMT_E_INVAL for a target that is zero after centring.  Synchronizes. */
+gmt_status gmt_nn_supervised_loss(gmt_hier_t h, const float* d_pred, const float* d_target, double alpha,
+                                  float* d_grad, double* h_loss, void* stream);
+
 /* Serialization of level l (1..cfg.levels) of a network set up with attention:
  * d_order[r] (n_l int32, device) receives the node id of rank r in the level's
  * Morton order (view (l-1) mod 3).  GMT_E_STATE without attention blocks. */

@@ -124,6 +124,7 @@ SIGNATURES = {
     "gmt_nn_activation": (_P, _I, _I, _P, ct.POINTER(ct.c_int32), _P),
     "gmt_nn_serialization": (_P, _I, _P, _P),
     "gmt_nn_time_attention": (_P, _I, _I, ct.POINTER(ct.c_double), _P),
+    "gmt_nn_supervised_loss": (_P, _P, _P, ct.c_double, _P, ct.POINTER(ct.c_double), _P),
     "gmt_nn_adamw": (_P, _P, _P, _P, ct.c_size_t, ct.c_double, ct.c_double, ct.c_double, ct.c_double,
                      ct.c_double, _I, ct.c_double, _P),
     "gmt_nn_norm2": (_P, ct.c_size_t, ct.POINTER(ct.c_double), _P),
@@ -502,6 +503,17 @@ class Hierarchy:
         out = torch.empty(self.n_n(level), dtype=torch.int32, device=self._vox.device)
         _check(lib().gmt_nn_serialization(self._h, level, _ptr(out), _stream()))
         return out
+
+    def nn_supervised_loss(self, pred, target, alpha=1.0, grad=None) -> float:
+        """alpha |pred - target_c|^2 / |target_c|^2 (target centred per column); grad += its gradient."""
+        self._v(pred, 1, torch.float32, "pred")
+        self._v(target, 1, torch.float32, "target")
+        if grad is not None:
+            self._v(grad, 1, torch.float32, "grad")
+        out = ct.c_double()
+        _check(lib().gmt_nn_supervised_loss(self._h, _ptr(pred), _ptr(target), float(alpha),
+                                            _ptr(grad) if grad is not None else None, ct.byref(out), _stream()))
+        return out.value
 
     def nn_time_attention(self, level: int, reps: int = 10) -> float:
         """Mean ms of one launch of level `level`'s attention forward kernel (after a forward)."""

@@ -181,6 +181,10 @@ void launch_copy(const T* a, T* b, size_t n, hipStream_t s);
 template <typename T>
 void launch_dot(const T* a, const T* b, int n, int C, int D, double* partial, double* out,
                 hipStream_t s);
+// the same with b's column means (sums[c*D + d] / n, rounded to T) removed from b on the fly
+template <typename T>
+void launch_dot_centered(const T* a, const T* b, const double* sums, double inv_n, int n, int C, int D, double* partial,
+                         double* out, hipStream_t s);
 // Gram matrix out[c1*C + c2] = sum_{i,d} a[i][c1][d] b[i][c2][d] in FP64
 template <typename Ta, typename Tb>
 void launch_gram(const Ta* a, const Tb* b, int n, int C, int D, double* partial, double* out,
@@ -189,9 +193,10 @@ void launch_gram(const Ta* a, const Tb* b, int n, int C, int D, double* partial,
 template <typename T>
 void launch_pcg_update(T* u, T* r, const T* p, const T* q, const double* alpha, int n, int Q, int D,
                        hipStream_t s);
-// p = z + beta[c] p
+// p = z + beta[c] p (with sums: z with its column means sums / n removed on the fly)
 template <typename T>
-void launch_pcg_direction(T* p, const T* z, const double* beta, int n, int Q, int D, hipStream_t s);
+void launch_pcg_direction(T* p, const T* z, const double* beta, int n, int Q, int D, hipStream_t s,
+                          const double* sums = nullptr, double inv_n = 0.0);
 // layout changes between the ABI's [n][C][D] and the solver's [C][n][D] (with type conversion)
 template <typename Tin, typename Tout>
 void launch_aos_to_soa(const Tin* a, Tout* b, int n, int C, int D, hipStream_t s);
@@ -408,6 +413,7 @@ size_t nn_norm2_noalloc_max();
 int nn_activation(Hier& h, int l, int which, float* out, hipStream_t s);
 void nn_serialization(Hier& h, int l, int* out, hipStream_t s);
 double nn_time_attention(Hier& h, int l, int reps, hipStream_t s);
+double nn_supervised(Hier& h, const float* p, const float* t, double alpha, float* grad, hipStream_t s);
 void nn_ema(float* e, const float* x, size_t n, double decay, hipStream_t s);
 
 // attention block of the learned initializer (attention.hip): Morton serialization

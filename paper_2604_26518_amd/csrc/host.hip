@@ -773,7 +773,7 @@ static void cycle_visit(Hier& h, int l, bool zero_start, int sched, CycleState<T
 // sub-cycle of the coarser levels, used by the adjoint of the learned path).
 template <typename T>
 static void vcycle(Hier& h, const T* f0, T* u0, bool u0_zero, const T* const* e_init, const CycleCfg& cfg,
-                   hipStream_t s, int l0 = 0) {
+                   hipStream_t s, int l0 = 0, const T** result = nullptr) {
   h.ensure_work<T>();
   Work<T>& W = h.work<T>();
   const int L = h.L;
@@ -787,7 +787,13 @@ static void vcycle(Hier& h, const T* f0, T* u0, bool u0_zero, const T* const* e_
   st.alt[l0] = W.ualt[l0];
   st.f[l0] = f0;
   cycle_visit<T>(h, l0, u0_zero, cfg.schedule, st, cfg, s);
-  if (st.cur[l0] != u0) launch_copy<T>(st.cur[l0], u0, (size_t)h.lv[l0].n_n * h.Q, s);
+  // the smoothers ping-pong between u0 and a work buffer; a caller that passes
+  // `result` takes the iterate where it ended (the same buffer for the same
+  // cycle configuration) instead of a copy back into u0
+  if (result)
+    *result = st.cur[l0];
+  else if (st.cur[l0] != u0)
+    launch_copy<T>(st.cur[l0], u0, (size_t)h.lv[l0].n_n * h.Q, s);
 }
 
 // ------------------------------------------------------------ launch-shape autotuner
@@ -967,29 +973,44 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
   double* sc = h.red_out;
   double *rz = sc, *pq = sc + 8, *alpha = sc + 16, *beta = sc + 24, *rzn = sc + 32, *rr = sc + 40;
   double* sums = sc + 200;
+  double* sums_z = sc + 224;  // column sums of the preconditioned residual
+  const double inv_n = n > 0 ? 1.0 / n : 0.0;
   double bn2[8], rr_h[8];
   launch_fill<T>(x, tot, T(0), s);
   launch_copy<T>(b, W.pr, tot, s);
   launch_project<T>(W.pr, n, Q, D, h.red_partial, sums, s);
   launch_dot<T>(W.pr, W.pr, n, C, D, h.red_partial, rr, s);
   host_dot(h, rr, C, bn2, s);
-  // z = Pi V(r): the V-cycle in T, or (MIXED) in FP32 on the rounded residual
+  // z = Pi V(r): the V-cycle in T, or (MIXED) in FP32 on the rounded residual; z is
+  // left where the cycle ends (W.pz or the level's work buffer, fixed for the cycle
+  // configuration) and its projection Pi is applied on the fly by the consumers:
+  // the column sums, then the dot r.z and the direction update read z minus its
+  // means (bit for bit what projecting z in place gives)
+  const T* z = W.pz;
   auto vc = [&](hipStream_t st) {
     if constexpr (MIXED) {
       launch_convert<double, float>(W.pr, W32.pr, tot, st);
-      vcycle<float>(h, W32.pr, W32.pz, true, nullptr, cfg, st);
-      launch_convert<float, double>(W32.pz, W.pz, tot, st);
+      const float* z32 = W32.pz;
+      vcycle<float>(h, W32.pr, W32.pz, true, nullptr, cfg, st, 0, &z32);
+      launch_convert<float, double>(z32, W.pz, tot, st);
+      z = W.pz;
     } else {
-      vcycle<T>(h, W.pr, W.pz, true, nullptr, cfg, st);
+      vcycle<T>(h, W.pr, W.pz, true, nullptr, cfg, st, 0, &z);
     }
   };
-  auto precond = [&]() {
-    vc(s);
-    launch_project<T>(W.pz, n, Q, D, h.red_partial, sums, s);
+  // rzn = r . Pi z and p = Pi z + beta p
+  auto finish_direction = [&](hipStream_t st, const double* fl) {
+    launch_colsum<T>(z, n, Q, D, h.red_partial, sums_z, st);
+    launch_dot_centered<T>(W.pr, z, sums_z, inv_n, n, C, D, h.red_partial, rzn, st);
+    launch_pcg_beta(rzn, rz, beta, C, st, fl);
+    launch_pcg_direction<T>(W.pp, z, beta, n, Q, D, st, sums_z, inv_n);
   };
-  precond();
-  launch_copy<T>(W.pz, W.pp, tot, s);
-  launch_dot<T>(W.pr, W.pz, n, C, D, h.red_partial, rz, s);
+  vc(s);
+  launch_colsum<T>(z, n, Q, D, h.red_partial, sums_z, s);
+  launch_dot_centered<T>(W.pr, z, sums_z, inv_n, n, C, D, h.red_partial, rz, s);
+  launch_fill<T>(W.pp, tot, T(0), s);
+  launch_fill<double>(beta, C, 0.0, s);
+  launch_pcg_direction<T>(W.pp, z, beta, n, Q, D, s, sums_z, inv_n);  // p = Pi z
   int it = 0;
   double best = INFINITY;
   int since_best = 0;
@@ -1036,10 +1057,7 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
       launch_pcg_update<T>(x, W.pr, W.pp, W.pq, alpha, n, Q, D, st);
       launch_project<T>(W.pr, n, Q, D, h.red_partial, sums, st);
       vc(st);
-      launch_project<T>(W.pz, n, Q, D, h.red_partial, sums, st);
-      launch_dot<T>(W.pr, W.pz, n, C, D, h.red_partial, rzn, st);
-      launch_pcg_beta(rzn, rz, beta, C, st, fl);
-      launch_pcg_direction<T>(W.pp, W.pz, beta, n, Q, D, st);
+      finish_direction(st, fl);
       launch_dot<T>(W.pr, W.pr, n, C, D, h.red_partial, rr, st);
       launch_pcg_check(rr, C, fl, st);
     };
@@ -1157,10 +1175,8 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
         break;  // stagnation: hand back to the FP64 refinement loop
       }
     }
-    precond();
-    launch_dot<T>(W.pr, W.pz, n, C, D, h.red_partial, rzn, s);
-    launch_pcg_beta(rzn, rz, beta, C, s);
-    launch_pcg_direction<T>(W.pp, W.pz, beta, n, Q, D, s);
+    vc(s);
+    finish_direction(s, nullptr);
   }
   return it;
 }
@@ -2518,6 +2534,16 @@ gmt_status gmt_nn_serialization(gmt_hier_t H, int32_t level, int32_t* d_order, v
     check_level(H, level);
     if (!d_order) fail(GMT_E_INVAL, "null pointer");
     nn_serialization(H->h, level - 1, d_order, S(stream));
+  });
+}
+
+gmt_status gmt_nn_supervised_loss(gmt_hier_t H, const float* d_pred, const float* d_target, double alpha,
+                                  float* d_grad, double* h_loss, void* stream) {
+  return guarded([&] {
+    check_level(H, 1);
+    if (!d_pred || !d_target || !h_loss) fail(GMT_E_INVAL, "null pointer");
+    if (!(alpha >= 0.0)) fail(GMT_E_INVAL, "alpha must be >= 0");
+    *h_loss = nn_supervised(H->h, d_pred, d_target, alpha, d_grad, S(stream));
   });
 }
 

@@ -1092,19 +1092,29 @@ __device__ void block_reduce_store(double (&v)[NV], double* __restrict__ partial
   }
 }
 
-template <typename T, int C, int D>
+// CB: b enters with its column means removed, b - (T)(sums[col] inv_n), rounded
+// as k_sub_mean rounds it (the dot of a projected vector without writing it)
+template <typename T, int C, int D, bool CB = false>
 __global__ __launch_bounds__(kBlock) void k_dot(const T* __restrict__ a, const T* __restrict__ b, int n,
-                                                double* __restrict__ partial) {
+                                                double* __restrict__ partial, const double* __restrict__ sums = nullptr,
+                                                double inv_n = 0.0) {
   double v[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) v[c] = 0.0;
+  T m[CB ? C * D : 1];
+  if constexpr (CB) {
+#pragma unroll
+    for (int k = 0; k < C * D; ++k) m[k] = (T)(sums[k] * inv_n);
+  }
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
 #pragma unroll
     for (int c = 0; c < C; ++c)
 #pragma unroll
       for (int q = 0; q < D; ++q) {
         const size_t idx = vix(c, n, i, D, q);
-        v[c] += (double)a[idx] * (double)b[idx];
+        T bv = b[idx];
+        if constexpr (CB) bv -= m[c * D + q];
+        v[c] += (double)a[idx] * (double)bv;
       }
   }
   block_reduce_store<C>(v, partial);
@@ -1212,15 +1222,19 @@ __global__ void k_pcg_update(T* __restrict__ u, T* __restrict__ r, const T* __re
   r[i] = fma(-a, q[i], r[i]);
 }
 
+// p = z + beta p; with sums, z enters with its column means removed (as k_sub_mean
+// would have written it)
 template <typename T>
 __global__ void k_pcg_direction(T* __restrict__ p, const T* __restrict__ z, const double* __restrict__ beta, int n,
-                                int D) {
+                                int D, const double* __restrict__ sums, double inv_n) {
   // grid row = case
   const int j = blockIdx.x * kBlock + threadIdx.x;
   if (j >= n * D) return;
   const size_t i = (size_t)blockIdx.y * n * D + j;
   const T b = (T)beta[blockIdx.y];
-  p[i] = fma(b, p[i], z[i]);
+  T zv = z[i];
+  if (sums) zv -= (T)(sums[blockIdx.y * D + j % D] * inv_n);
+  p[i] = fma(b, p[i], zv);
 }
 
 // stop (nullable): the device-side convergence flag of captured PCG blocks; once
@@ -2069,6 +2083,21 @@ void launch_dot(const T* a, const T* b, int n, int C, int D, double* partial, do
   GMT_LAUNCH_CHECK();
 }
 
+template <typename T>
+void launch_dot_centered(const T* a, const T* b, const double* sums, double inv_n, int n, int C, int D, double* partial,
+                         double* out, hipStream_t s) {
+  const unsigned g = red_grid(n);
+  if (C == 6 && D == 3)
+    hipLaunchKernelGGL((k_dot<T, 6, 3, true>), dim3(g), dim3(kBlock), 0, s, a, b, n, partial, sums, inv_n);
+  else if (C == 3 && D == 1)
+    hipLaunchKernelGGL((k_dot<T, 3, 1, true>), dim3(g), dim3(kBlock), 0, s, a, b, n, partial, sums, inv_n);
+  else
+    fail(GMT_E_INVAL, "unsupported (c, d)");
+  GMT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_reduce_final, dim3(C), dim3(kBlock), 0, s, partial, (int)g, C, out);
+  GMT_LAUNCH_CHECK();
+}
+
 template <typename Ta, typename Tb>
 void launch_gram(const Ta* a, const Tb* b, int n, int C, int D, double* partial, double* out, hipStream_t s) {
   const unsigned g = red_grid(n);
@@ -2142,10 +2171,12 @@ void launch_pcg_update(T* u, T* r, const T* p, const T* q, const double* alpha, 
 }
 
 template <typename T>
-void launch_pcg_direction(T* p, const T* z, const double* beta, int n, int Q, int D, hipStream_t s) {
+void launch_pcg_direction(T* p, const T* z, const double* beta, int n, int Q, int D, hipStream_t s,
+                          const double* sums, double inv_n) {
   const size_t tot = (size_t)n * Q;
   if (!tot) return;
-  hipLaunchKernelGGL(k_pcg_direction<T>, dim3(blocks_for((size_t)n * D), Q / D), dim3(kBlock), 0, s, p, z, beta, n, D);
+  hipLaunchKernelGGL(k_pcg_direction<T>, dim3(blocks_for((size_t)n * D), Q / D), dim3(kBlock), 0, s, p, z, beta, n, D,
+                     sums, inv_n);
   GMT_LAUNCH_CHECK();
 }
 
@@ -2422,7 +2453,10 @@ void launch_random(double* x, size_t n, uint64_t seed, hipStream_t s) {
   template void launch_dot<T>(const T*, const T*, int, int, int, double*, double*, hipStream_t);             \
   template void launch_normalize<T>(const T*, size_t, const double*, T*, hipStream_t);                     \
   template void launch_pcg_update<T>(T*, T*, const T*, const T*, const double*, int, int, int, hipStream_t);  \
-  template void launch_pcg_direction<T>(T*, const T*, const double*, int, int, int, hipStream_t);            \
+  template void launch_pcg_direction<T>(T*, const T*, const double*, int, int, int, hipStream_t, const double*, \
+                                        double);                                                               \
+  template void launch_dot_centered<T>(const T*, const T*, const double*, double, int, int, int, double*, double*, \
+                                       hipStream_t);                                                           \
   template void launch_aos_to_soa<T, T>(const T*, T*, int, int, int, hipStream_t);                           \
   template void launch_soa_to_aos<T, T>(const T*, T*, int, int, int, hipStream_t);                           \
   template void launch_gauge_shift<T>(T*, int, int, int, T*, hipStream_t);                                   \

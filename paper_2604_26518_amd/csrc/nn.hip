@@ -570,6 +570,45 @@ __global__ __launch_bounds__(kB) void k_colsum_rows(int n, const float* __restri
   }
 }
 
+// supervised term: with t the centred target (t - column mean), per block the FP64
+// sums of t^2 and (p - t)^2 (fixed grid, added on the host in block order)
+template <int Q>
+__global__ __launch_bounds__(kB) void k_sup_sums(int n, const float* __restrict__ p, const float* __restrict__ t,
+                                                 const double* __restrict__ mean, double* __restrict__ partial) {
+  __shared__ double sh[2][kB / 64];
+  double st = 0.0, se = 0.0;
+  for (size_t e = (size_t)blockIdx.x * kB + threadIdx.x; e < (size_t)n * Q; e += (size_t)gridDim.x * kB) {
+    const double tc = (double)t[e] - mean[e % Q];
+    const double d = (double)p[e] - tc;
+    st += tc * tc;
+    se += d * d;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    st += __shfl_down(st, o, 64);
+    se += __shfl_down(se, o, 64);
+  }
+  if (lane == 0) {
+    sh[0][w] = st;
+    sh[1][w] = se;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double v = 0.0;
+    for (int k = 0; k < kB / 64; ++k) v += sh[threadIdx.x][k];
+    partial[(size_t)blockIdx.x * 2 + threadIdx.x] = v;
+  }
+}
+
+// g += scale (p - (t - mean))
+__global__ void k_sup_grad(size_t total, int Q, const float* __restrict__ p, const float* __restrict__ t,
+                           const double* __restrict__ mean, float scale, float* __restrict__ g) {
+  const size_t e = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (e >= total) return;
+  g[e] += scale * (float)((double)p[e] - ((double)t[e] - mean[e % Q]));
+}
+
 __global__ void k_colmean_final(const double* __restrict__ partial, int nblk, int Q, int n, double* __restrict__ mean) {
   const int q = threadIdx.x;
   if (q >= Q) return;
@@ -1190,6 +1229,45 @@ void nn_backward(Hier& h, const float* const* gout, float* grad, hipStream_t s) 
 __global__ void k_widen(size_t total, const uint16_t* __restrict__ a, float* __restrict__ b) {
   const size_t i = (size_t)blockIdx.x * kB + threadIdx.x;
   if (i < total) b[i] = bf2f(a[i]);
+}
+
+// Supervised term on the level-1 prediction p [n][Q] against a solution target t
+// (centred here, as p is): loss = alpha |p - t_c|^2 / |t_c|^2, grad += its gradient.
+double nn_supervised(Hier& h, const float* p, const float* t, double alpha, float* grad, hipStream_t s) {
+  NNState& S = nn_state(h);
+  const int n = h.lv[0].n_n, Q = S.nl.q;
+  if (n <= 0) return 0.0;
+  double* partial = S.colred;
+  double* mean = S.colred + (size_t)kColBlocks * 32;
+  if (Q == 18)
+    hipLaunchKernelGGL(k_colsum_rows<18>, dim3(kColBlocks), dim3(kB), 0, s, n, t, partial);
+  else
+    hipLaunchKernelGGL(k_colsum_rows<3>, dim3(kColBlocks), dim3(kB), 0, s, n, t, partial);
+  GMT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_colmean_final, dim3(1), dim3(64), 0, s, partial, kColBlocks, Q, n, mean);
+  GMT_LAUNCH_CHECK();
+  // the sums reuse the front of the partial buffer (the column sums are consumed)
+  if (Q == 18)
+    hipLaunchKernelGGL(k_sup_sums<18>, dim3(kColBlocks), dim3(kB), 0, s, n, p, t, mean, partial);
+  else
+    hipLaunchKernelGGL(k_sup_sums<3>, dim3(kColBlocks), dim3(kB), 0, s, n, p, t, mean, partial);
+  GMT_LAUNCH_CHECK();
+  std::vector<double> hp((size_t)kColBlocks * 2);
+  GMT_HIP(hipMemcpyAsync(hp.data(), partial, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  GMT_HIP(hipStreamSynchronize(s));
+  double st = 0.0, se = 0.0;
+  for (int b = 0; b < kColBlocks; ++b) {
+    st += hp[(size_t)2 * b];
+    se += hp[(size_t)2 * b + 1];
+  }
+  if (!(st > 0.0)) fail(GMT_E_INVAL, "the supervised target is zero after centring");
+  if (grad) {
+    const size_t tot = (size_t)n * Q;
+    hipLaunchKernelGGL(k_sup_grad, dim3(nblk(tot)), dim3(kB), 0, s, tot, Q, p, t, mean, (float)(2.0 * alpha / st),
+                       grad);
+    GMT_LAUNCH_CHECK();
+  }
+  return alpha * se / st;
 }
 
 double nn_time_attention(Hier& h, int l, int reps, hipStream_t s) {

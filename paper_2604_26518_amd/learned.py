@@ -91,8 +91,10 @@ class Trainer:
         w = min(1.0, (k + 1) / warmup) if warmup > 0 else 1.0
         return self.lr * w * 0.5 * (1 + math.cos(math.pi * min(k, total) / max(total, 1)))
 
-    def train_cell(self, H: B.Hierarchy, total_steps: int, inject: bool = True):
-        """One optimisation step on one cell; returns (loss, ||r||, max relative residual)."""
+    def train_cell(self, H: B.Hierarchy, total_steps: int, inject: bool = True, target=None, alpha=0.0):
+        """One optimisation step on one cell; returns (loss, ||r||, max relative residual).
+        With a target (the plain solver's FP32 solution) and alpha > 0 the loss adds the
+        supervised term alpha |u_hat^1 - target_c|^2 / |target_c|^2."""
         preds = H.nn_forward(self.params)
         if not inject:
             preds = preds[:1]
@@ -100,6 +102,8 @@ class Trainer:
         # gauge penalty lambda (sum_i u_i)^2 with lambda = lam / n^2: lam times the squared
         # per-component mean of u^1 (the residual does not see rigid translations)
         loss, rn, rel, _, grads = H.vcycle_loss(preds, lam=self.lam / float(H.n_n(1)) ** 2)
+        if target is not None and alpha > 0:
+            loss += H.nn_supervised_loss(preds[0], target, alpha, grad=grads[0])
         self.grad.zero_()  # memory fill
         H.nn_backward(grads, self.grad)
         gn = math.sqrt(B.norm2(self.grad))

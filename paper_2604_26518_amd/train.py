@@ -100,6 +100,9 @@ def main(argv=None):
     ap.add_argument("--init", default="", help="start from these exported (BF16) weights")
     ap.add_argument("--warmup-steps", type=int, default=300)
     ap.add_argument("--ema", type=float, default=0.999, help="decay of the weights' moving average")
+    ap.add_argument("--supervised", type=float, default=0.0,
+                    help="weight of the supervised term on u_hat^1 against each cell's plain-solver solution")
+    ap.add_argument("--target-tol", type=float, default=1e-6, help="tolerance of the target solves")
     ap.add_argument("--attention", action="store_true", help="an attention block per level (Sec. 4.2-4.3)")
     ap.add_argument("--ckpt", default="unet.pt")
     ap.add_argument("--resume", action="store_true")
@@ -152,7 +155,8 @@ def main(argv=None):
     t_last = t_start
     rng = np.random.default_rng(tr.step)
     k = 0
-    H, idx, fresh = None, -1, False
+    H, idx, fresh, target = None, -1, False, None
+    targets = {}
     while tr.step < args.steps:
         if k % args.steps_per_cell == 0:
             if fresh and idx not in cache:
@@ -162,9 +166,19 @@ def main(argv=None):
             fresh = H is None
             if fresh:
                 H = build(voxels(cells[idx], args.N), levels, attention=att, net_levels=nl)
+                target = None
+                if args.supervised > 0:
+                    # the plain solver's solution of this cell (mixed precision, FP32 copy)
+                    u64, _ = H.solve(H.load_vector(), tol=args.target_tol, precision="f32", max_iter=3000,
+                                     raise_on_noconv=False)
+                    target = u64.to(torch.float32)
+                    del u64
                 if torch.cuda.memory_allocated() < budget:
                     cache[idx] = H
-        loss, rn, rel = tr.train_cell(H, args.steps)
+                    targets[idx] = target
+            else:
+                target = targets.get(idx)
+        loss, rn, rel = tr.train_cell(H, args.steps, target=target, alpha=args.supervised)
         if not math.isfinite(loss):
             raise RuntimeError(f"non-finite loss at step {tr.step}")
         log.append({"step": tr.step, "loss": loss, "rel": rel, "family": cells[idx][1]})
@@ -198,7 +212,7 @@ def main(argv=None):
     if args.export:
         meta = {"step": tr.step, "train_cells": args.cells, "train_seed0": args.seed0,
                 "held_out_seed0": args.test_seed0, "steps_per_cell": args.steps_per_cell, "lr": args.lr,
-                "ema": args.ema, **summary}
+                "ema": args.ema, "supervised": args.supervised, **summary}
         if args.init:
             meta["init"] = os.path.basename(args.init)
         save_weights(args.export, tr.ema, nl, args.N, "elastic", meta=meta, attention=att)

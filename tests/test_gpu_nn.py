@@ -253,6 +253,28 @@ def test_vcycle_loss_matches_oracle_and_gradient(setup):
         assert abs(an - fd) <= 2e-3 * abs(fd) + 1e-9, (which, an, fd)
 
 
+def test_supervised_loss_and_gradient(setup):
+    """gmt_nn_supervised_loss against its definition in FP64: the target centred per column,
+    loss = alpha |p - t_c|^2 / |t_c|^2, and the gradient added to what the buffer held."""
+    vox, H, net, g, flat = setup
+    p = H.nn_forward(_t(flat))[0]
+    n = H.n_n(1)
+    rng = np.random.default_rng(5)
+    t = _t(rng.standard_normal(tuple(p.shape)) + 3.0)
+    grad = torch.full_like(p, 0.5)
+    alpha = 0.7
+    loss = H.nn_supervised_loss(p, t, alpha, grad=grad)
+    P, T = _np(p).reshape(n, -1), _np(t).reshape(n, -1)
+    Tc = T - T.mean(axis=0)
+    ref = alpha * ((P - Tc) ** 2).sum() / (Tc ** 2).sum()
+    gref = 0.5 + 2 * alpha * (P - Tc) / (Tc ** 2).sum()
+    assert abs(loss - ref) <= 1e-12 * ref
+    assert np.abs(_np(grad).reshape(n, -1) - gref).max() <= 2.0 ** -22 * np.abs(gref).max()
+    assert H.nn_supervised_loss(p, t, alpha) == loss  # without a gradient buffer
+    with pytest.raises(_gmt().GmtError):  # a target that is constant per column centres to zero
+        H.nn_supervised_loss(p, torch.ones_like(p), alpha)
+
+
 def test_adamw_step():
     B = _gmt()
     rng = np.random.default_rng(0)
