@@ -189,10 +189,19 @@ void launch_dot_centered(const T* a, const T* b, const double* sums, double inv_
 template <typename Ta, typename Tb>
 void launch_gram(const Ta* a, const Tb* b, int n, int C, int D, double* partial, double* out,
                  hipStream_t s);
-// u += alpha[c] p ; r -= alpha[c] q  (vectors [C][n][D])
+// u += alpha[c] p ; r -= alpha[c] q  (vectors [C][n][D]); with qsums, q minus its column
+// means qsums / n
 template <typename T>
 void launch_pcg_update(T* u, T* r, const T* p, const T* q, const double* alpha, int n, int Q, int D,
+                       hipStream_t s, const double* qsums = nullptr, double inv_n = 0.0);
+// dots[c] = a.b per case and sums[c*D + d] = column sums of b, in one pass
+template <typename T>
+void launch_dot_colsum(const T* a, const T* b, int n, int C, int D, double* partial, double* dots, double* sums,
                        hipStream_t s);
+// rz[c] = r.(z - column means sums / n) and rr[c] = r.r, in one pass
+template <typename T>
+void launch_dot2_centered(const T* r, const T* z, const double* sums, double inv_n, int n, int C, int D,
+                          double* partial, double* rz, double* rr, hipStream_t s);
 // p = z + beta[c] p (with sums: z with its column means sums / n removed on the fly)
 template <typename T>
 void launch_pcg_direction(T* p, const T* z, const double* beta, int n, int Q, int D, hipStream_t s,

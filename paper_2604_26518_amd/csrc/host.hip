@@ -974,6 +974,7 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
   double *rz = sc, *pq = sc + 8, *alpha = sc + 16, *beta = sc + 24, *rzn = sc + 32, *rr = sc + 40;
   double* sums = sc + 200;
   double* sums_z = sc + 224;  // column sums of the preconditioned residual
+  double* sums_q = sc + 100;  // column sums of K p
   const double inv_n = n > 0 ? 1.0 / n : 0.0;
   double bn2[8], rr_h[8];
   launch_fill<T>(x, tot, T(0), s);
@@ -1050,15 +1051,20 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
     }
     // one iteration after the initial preconditioning, as in the launch-by-launch
     // loop below, ending with the residual norms and the convergence check
+    // The residual is kept free of rigid translations by removing the column
+    // means of q = K p in the update (K p has none in exact arithmetic; the sums
+    // come with p.q in one pass), instead of projecting r after it; r.z and r.r
+    // share one pass over r.
     auto step = [&](hipStream_t st) {
       apply<T>(h, 0, EPI_KU, W.pp, nullptr, W.pq, C, st);
-      launch_dot<T>(W.pp, W.pq, n, C, D, h.red_partial, pq, st);
+      launch_dot_colsum<T>(W.pp, W.pq, n, C, D, h.red_partial, pq, sums_q, st);
       launch_pcg_alpha(rz, pq, alpha, C, st, fl);
-      launch_pcg_update<T>(x, W.pr, W.pp, W.pq, alpha, n, Q, D, st);
-      launch_project<T>(W.pr, n, Q, D, h.red_partial, sums, st);
+      launch_pcg_update<T>(x, W.pr, W.pp, W.pq, alpha, n, Q, D, st, sums_q, inv_n);
       vc(st);
-      finish_direction(st, fl);
-      launch_dot<T>(W.pr, W.pr, n, C, D, h.red_partial, rr, st);
+      launch_colsum<T>(z, n, Q, D, h.red_partial, sums_z, st);
+      launch_dot2_centered<T>(W.pr, z, sums_z, inv_n, n, C, D, h.red_partial, rzn, rr, st);
+      launch_pcg_beta(rzn, rz, beta, C, st, fl);
+      launch_pcg_direction<T>(W.pp, z, beta, n, Q, D, st, sums_z, inv_n);
       launch_pcg_check(rr, C, fl, st);
     };
     Hier::PcgGraphs& G = MIXED ? h.gmx : graphs_of<T>(h);
@@ -1157,10 +1163,9 @@ static int pcg(Hier& h, const T* b, T* x, const double* tol, int maxit, int chec
   while (it < maxit) {
     ++it;
     apply<T>(h, 0, EPI_KU, W.pp, nullptr, W.pq, C, s);
-    launch_dot<T>(W.pp, W.pq, n, C, D, h.red_partial, pq, s);
+    launch_dot_colsum<T>(W.pp, W.pq, n, C, D, h.red_partial, pq, sums_q, s);
     launch_pcg_alpha(rz, pq, alpha, C, s);
-    launch_pcg_update<T>(x, W.pr, W.pp, W.pq, alpha, n, Q, D, s);
-    launch_project<T>(W.pr, n, Q, D, h.red_partial, sums, s);
+    launch_pcg_update<T>(x, W.pr, W.pp, W.pq, alpha, n, Q, D, s, sums_q, inv_n);
     if (it % check_every == 0 || it == maxit) {
       launch_dot<T>(W.pr, W.pr, n, C, D, h.red_partial, rr, s);
       host_dot(h, rr, C, rr_h, s);

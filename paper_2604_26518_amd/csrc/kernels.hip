@@ -1120,6 +1120,53 @@ __global__ __launch_bounds__(kBlock) void k_dot(const T* __restrict__ a, const T
   block_reduce_store<C>(v, partial);
 }
 
+// p.q per case and the column sums of q, in one pass over p and q
+template <typename T, int C, int D>
+__global__ __launch_bounds__(kBlock) void k_dot_colsum(const T* __restrict__ a, const T* __restrict__ b, int n,
+                                                       double* __restrict__ partial) {
+  double v[C + C * D];
+#pragma unroll
+  for (int k = 0; k < C + C * D; ++k) v[k] = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        const size_t idx = vix(c, n, i, D, q);
+        const double bv = (double)b[idx];
+        v[c] += (double)a[idx] * bv;
+        v[C + c * D + q] += bv;
+      }
+  }
+  block_reduce_store<C + C * D>(v, partial);
+}
+
+// r.(z - its column means) and r.r per case, in one pass over r and z
+template <typename T, int C, int D>
+__global__ __launch_bounds__(kBlock) void k_dot2_centered(const T* __restrict__ r, const T* __restrict__ z, int n,
+                                                          const double* __restrict__ sums, double inv_n,
+                                                          double* __restrict__ partial) {
+  double v[2 * C];
+#pragma unroll
+  for (int k = 0; k < 2 * C; ++k) v[k] = 0.0;
+  T m[C * D];
+#pragma unroll
+  for (int k = 0; k < C * D; ++k) m[k] = (T)(sums[k] * inv_n);
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        const size_t idx = vix(c, n, i, D, q);
+        const double rv = (double)r[idx];
+        const T zv = z[idx] - m[c * D + q];
+        v[c] += rv * (double)zv;
+        v[C + c] += rv * rv;
+      }
+  }
+  block_reduce_store<2 * C>(v, partial);
+}
+
 template <typename Ta, typename Tb, int C, int D>
 __global__ __launch_bounds__(kBlock) void k_gram(const Ta* __restrict__ a, const Tb* __restrict__ b, int n,
                                                  double* __restrict__ partial) {
@@ -1192,6 +1239,27 @@ __global__ void k_mul_nodewise(T* __restrict__ v, const T* __restrict__ w, int n
   v[i] = divide ? v[i] / ww : v[i] * ww;
 }
 
+// Second stage with the values split over two outputs: k < n1 -> out1[k], else out2[k - n1].
+__global__ void k_reduce_split(const double* __restrict__ partial, int nblocks, int nv, int n1, double* __restrict__ out1,
+                               double* __restrict__ out2) {
+  __shared__ double sh[kBlock];
+  const int k = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) s += partial[(size_t)b * nv + k];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (k < n1)
+      out1[k] = sh[0];
+    else
+      out2[k - n1] = sh[0];
+  }
+}
+
 // Second stage: out[k] = sum over blocks of partial[b][k], fixed order.
 // One workgroup per reduced value k (grid = nv).
 __global__ void k_reduce_final(const double* __restrict__ partial, int nblocks, int nv, double* __restrict__ out) {
@@ -1210,16 +1278,21 @@ __global__ void k_reduce_final(const double* __restrict__ partial, int nblocks, 
   }
 }
 
+// u += alpha p, r -= alpha q; with qsums, q enters with its column means removed,
+// so a residual with zero column means keeps them zero
 template <typename T>
 __global__ void k_pcg_update(T* __restrict__ u, T* __restrict__ r, const T* __restrict__ p,
-                             const T* __restrict__ q, const double* __restrict__ alpha, int n, int D) {
+                             const T* __restrict__ q, const double* __restrict__ alpha, int n, int D,
+                             const double* __restrict__ qsums, double inv_n) {
   // grid row = case
   const int j = blockIdx.x * kBlock + threadIdx.x;
   if (j >= n * D) return;
   const size_t i = (size_t)blockIdx.y * n * D + j;
   const T a = (T)alpha[blockIdx.y];
   u[i] = fma(a, p[i], u[i]);
-  r[i] = fma(-a, q[i], r[i]);
+  T qv = q[i];
+  if (qsums) qv -= (T)(qsums[blockIdx.y * D + j % D] * inv_n);
+  r[i] = fma(-a, qv, r[i]);
 }
 
 // p = z + beta p; with sums, z enters with its column means removed (as k_sub_mean
@@ -2162,11 +2235,38 @@ void launch_project(T* v, int n, int Q, int D, double* partial, double* sums, hi
 
 template <typename T>
 void launch_pcg_update(T* u, T* r, const T* p, const T* q, const double* alpha, int n, int Q, int D,
-                       hipStream_t s) {
+                       hipStream_t s, const double* qsums, double inv_n) {
   const size_t tot = (size_t)n * Q;
   if (!tot) return;
   hipLaunchKernelGGL(k_pcg_update<T>, dim3(blocks_for((size_t)n * D), Q / D), dim3(kBlock), 0, s, u, r, p, q, alpha, n,
-                     D);
+                     D, qsums, inv_n);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_dot_colsum(const T* a, const T* b, int n, int C, int D, double* partial, double* dots, double* sums,
+                       hipStream_t s) {
+  const unsigned g = red_grid(n);
+  if (C == 6 && D == 3) hipLaunchKernelGGL((k_dot_colsum<T, 6, 3>), dim3(g), dim3(kBlock), 0, s, a, b, n, partial);
+  else if (C == 3 && D == 1) hipLaunchKernelGGL((k_dot_colsum<T, 3, 1>), dim3(g), dim3(kBlock), 0, s, a, b, n, partial);
+  else fail(GMT_E_INVAL, "unsupported (c, d)");
+  GMT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_reduce_split, dim3(C + C * D), dim3(kBlock), 0, s, partial, (int)g, C + C * D, C, dots, sums);
+  GMT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_dot2_centered(const T* r, const T* z, const double* sums, double inv_n, int n, int C, int D,
+                          double* partial, double* rz, double* rr, hipStream_t s) {
+  const unsigned g = red_grid(n);
+  if (C == 6 && D == 3)
+    hipLaunchKernelGGL((k_dot2_centered<T, 6, 3>), dim3(g), dim3(kBlock), 0, s, r, z, n, sums, inv_n, partial);
+  else if (C == 3 && D == 1)
+    hipLaunchKernelGGL((k_dot2_centered<T, 3, 1>), dim3(g), dim3(kBlock), 0, s, r, z, n, sums, inv_n, partial);
+  else
+    fail(GMT_E_INVAL, "unsupported (c, d)");
+  GMT_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_reduce_split, dim3(2 * C), dim3(kBlock), 0, s, partial, (int)g, 2 * C, C, rz, rr);
   GMT_LAUNCH_CHECK();
 }
 
@@ -2452,7 +2552,11 @@ void launch_random(double* x, size_t n, uint64_t seed, hipStream_t s) {
   template void launch_inv<T>(const T*, T*, size_t, hipStream_t);                                            \
   template void launch_dot<T>(const T*, const T*, int, int, int, double*, double*, hipStream_t);             \
   template void launch_normalize<T>(const T*, size_t, const double*, T*, hipStream_t);                     \
-  template void launch_pcg_update<T>(T*, T*, const T*, const T*, const double*, int, int, int, hipStream_t);  \
+  template void launch_pcg_update<T>(T*, T*, const T*, const T*, const double*, int, int, int, hipStream_t,     \
+                                     const double*, double);                                                   \
+  template void launch_dot_colsum<T>(const T*, const T*, int, int, int, double*, double*, double*, hipStream_t); \
+  template void launch_dot2_centered<T>(const T*, const T*, const double*, double, int, int, int, double*, double*, \
+                                        double*, hipStream_t);                                                 \
   template void launch_pcg_direction<T>(T*, const T*, const double*, int, int, int, hipStream_t, const double*, \
                                         double);                                                               \
   template void launch_dot_centered<T>(const T*, const T*, const double*, double, int, int, int, double*, double*, \
