@@ -84,6 +84,11 @@ typedef struct {
   void* (*alloc)(size_t bytes, void* ctx);
   void (*release)(void* ptr, void* ctx);
   void* alloc_ctx;
+  /* gauge of the solutions gmt_solve reports (the cell problem fixes u only up to
+   * a rigid translation per case): 0 (default) node 0 pinned, u(node 0) = 0;
+   * 1 zero mean of every component over the fine nodes (the gauge of Sec. 4.5).
+   * C_H does not depend on it. */
+  int32_t gauge;
 } gmt_params;
 
 typedef struct {

@@ -37,7 +37,7 @@ class GmtParams(ct.Structure):
     _fields_ = [("physics", ct.c_int32), ("E", ct.c_double), ("nu", ct.c_double),
                 ("kappa", ct.c_double), ("levels", ct.c_int32), ("power_iters", ct.c_int32),
                 ("seed", ct.c_uint64), ("alloc", ALLOC_FN), ("release", RELEASE_FN),
-                ("alloc_ctx", ct.c_void_p)]
+                ("alloc_ctx", ct.c_void_p), ("gauge", ct.c_int32)]
 
 
 class GmtSimpParams(ct.Structure):
@@ -207,9 +207,11 @@ class Hierarchy:
     def __init__(self, voxels, levels: int, physics: str = "elastic", E: float = 1.0,
                  nu: float = 0.3, kappa: float = 1.0, power_iters: int = 20, seed: int = 0,
                  device="cuda", torch_memory: bool = True, density=None, p: float = 3.0,
-                 rho_min: float = 1e-3, prune: float = 0.0):
+                 rho_min: float = 1e-3, prune: float = 0.0, gauge: str = "pin"):
         """voxels: binary N^3 cell; or voxels=None and density = an N^3 field rho for the
-        SIMP cell problem (App. F.3) with penalization p, floor rho_min and pruning threshold."""
+        SIMP cell problem (App. F.3) with penalization p, floor rho_min and pruning threshold.
+        gauge: 'pin' (node 0 fixed, the default) or 'mean' (zero mean per component) for the
+        solutions that solve() reports."""
         if physics not in ("elastic", "thermal"):
             raise ValueError(physics)
         self.density = None
@@ -234,6 +236,9 @@ class Hierarchy:
         p.levels = levels
         p.power_iters = power_iters
         p.seed = seed
+        if gauge not in ("pin", "mean"):
+            raise ValueError("gauge is 'pin' (node 0 fixed) or 'mean' (zero mean per component)")
+        p.gauge = 1 if gauge == "mean" else 0
         self._arena = None
         if torch_memory:
             self._arena = _TorchArena(self._vox.device)

@@ -1734,7 +1734,10 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
       last_f32 = false;
     }
   }
-  launch_gauge_shift<double>(u, h.lv[0].n_n, h.Q, h.D, h.gauge_tmp64, s);
+  if (h.p.gauge == 1)
+    launch_project<double>(u, h.lv[0].n_n, h.Q, h.D, h.red_partial, h.red_out + 200, s);
+  else
+    launch_gauge_shift<double>(u, h.lv[0].n_n, h.Q, h.D, h.gauge_tmp64, s);
   GMT_HIP(hipStreamSynchronize(s));
   R.iterations = its;
   if (rep) *rep = R;
@@ -1829,6 +1832,7 @@ static gmt_hier* new_hierarchy(int32_t N, const gmt_params* params) {
   if (params->physics != GMT_ELASTIC && params->physics != GMT_THERMAL) fail(GMT_E_INVAL, "bad physics");
   if ((params->alloc == nullptr) != (params->release == nullptr))
     fail(GMT_E_INVAL, "alloc and release must be given together");
+  if (params->gauge != 0 && params->gauge != 1) fail(GMT_E_INVAL, "gauge must be 0 (node 0 pinned) or 1 (zero mean)");
   gmt_hier* H = new gmt_hier();
   Hier& h = H->h;
   h.p = *params;

@@ -160,6 +160,8 @@ def _gpu_cache(H, net, g, flat):
              "t": [act(l, 2) for l in range(L - 1)] + [None],
              "z1": [act(l, 4) for l in range(L - 1)], "z2": [act(l, 5) for l in range(L - 1)]}
     cache["d"] = [act(l, 3) for l in range(L - 1)] + [cache["s"][L - 1]]
+    if not H.nn_attention:
+        return cache
     att = []
     for l in range(L):
         order = H.nn_serialization(l + 1).cpu().numpy()
@@ -284,3 +286,51 @@ def test_attention_timing_keeps_the_outputs():
     with pytest.raises(_gmt().GmtError):
         H.nn_time_attention(1, 3)
     H.close()
+
+
+@pytest.mark.parametrize("attention", [False, True])
+def test_thermal_network_on_gpu_activations(attention):
+    """The network of the thermal problem (3 outputs per node: the 3 load cases x 1 DOF),
+    with and without attention blocks: the predictions against the oracle's head on the GPU's
+    own last hidden layer (FP32 sum of H + 1 terms scaled by N, then centred), and every
+    parameter gradient against the oracle's backward on the GPU's activations (each entry
+    within 1e-3 of its tensor's largest entry, as for the elastic network)."""
+    chs = [16, 32, 64]
+    vox = gyroid_sheet(16, 7, 0.4)
+    H = _gmt().Hierarchy(vox, 3, "thermal")
+    H.nn_setup(chs, attention=attention)
+    net = onn.UNet(chs, 32, 3, attention=attention)
+    g = onn.Graph(ohier.build(vox, 3))
+    assert H.n_params == net.n_params()
+    flat = net.init(11) + 0.02 * np.random.default_rng(12).standard_normal(net.n_params())
+    outs = H.nn_forward(_t(flat))
+    cache = _gpu_cache(H, net, g, flat)
+    W = cache["W"]
+    for l, o in enumerate(outs):
+        z2 = cache["z2"][l]
+        raw = g.N * (z2 @ W[f"W3_{l}"] + W[f"b3_{l}"])
+        ref = onn.center(raw)
+        S3 = g.N * (np.abs(z2) @ np.abs(W[f"W3_{l}"]) + np.abs(W[f"b3_{l}"]))
+        delta = (32 + 3) * U32 * S3
+        bound = 2 * delta.max(axis=0, keepdims=True) + delta + 2 * U32 * np.abs(ref)
+        err = np.abs(_np(o).reshape(ref.shape) - ref)
+        print(f"[thermal att={attention}] out{l}: max err / bound {(err / bound).max():.3f}", flush=True)
+        assert np.all(err <= bound), l
+    rng = np.random.default_rng(23)
+    gouts = [rng.standard_normal((o.shape[0], 3)) for o in outs]
+    grad = torch.zeros(net.n_params(), dtype=torch.float32, device=DEV)
+    H.nn_backward([_t(x.reshape(o.shape)) for x, o in zip(gouts, outs)], grad)
+    H.close()
+    gref = onn.backward(net, g, cache, gouts)
+    Gg, Gr = net.unflatten(_np(grad)), net.unflatten(gref)
+    total = np.abs(gref).max()
+    worst = {}
+    for name, _ in net.shapes():
+        err = np.abs(Gg[name] - Gr[name]).max()
+        if name.startswith("b3_"):
+            assert err <= 1e-3 * total, name
+            continue
+        worst[name] = err / np.abs(Gr[name]).max()
+    print(f"[thermal att={attention}] grads: " + " ".join(f"{k}:{v:.1e}" for k, v in worst.items()), flush=True)
+    bad = {k: v for k, v in worst.items() if v > 1e-3}
+    assert not bad, bad

@@ -284,6 +284,25 @@ def test_solve_fp64(solved):
     assert np.allclose(rel, osolve.relative_residual(P, un), rtol=1e-6, atol=1e-13)
 
 
+def test_solve_zero_mean_gauge(solved):
+    """gauge='mean' reports the solution with every component's mean over the nodes removed
+    (the gauge of Sec. 4.5): the oracle's pinned solution minus its means, the same C_H."""
+    name, vox, P, H, u_ref, CH_ref = solved
+    Hm = _gmt().Hierarchy(vox, P.L, "elastic" if P.c == 6 else "thermal", gauge="mean")
+    f = Hm.load_vector()
+    u, rep = Hm.solve(f, tol=1e-10, precision="f64")
+    assert rep["converged"]
+    un = _np(u)
+    ref = u_ref - u_ref.mean(axis=0, keepdims=True)
+    assert np.abs(un.mean(axis=0)).max() <= 1e-13 * np.abs(ref).max()
+    assert np.abs(un - ref).max() <= 1e-7 * np.abs(ref).max()
+    CH = Hm.homogenize(u)
+    assert np.linalg.norm(CH - CH_ref) <= 1e-8 * np.linalg.norm(CH_ref)
+    Hm.close()
+    with pytest.raises(ValueError):
+        _gmt().Hierarchy(vox, P.L, gauge="node7")
+
+
 def test_solve_mixed(solved):
     name, vox, P, H, u_ref, CH_ref = solved
     f = H.load_vector()
