@@ -1280,34 +1280,41 @@ __global__ void k_reduce_final(const double* __restrict__ partial, int nblocks, 
 
 // u += alpha p, r -= alpha q; with qsums, q enters with its column means removed,
 // so a residual with zero column means keeps them zero
-template <typename T>
+// the D column means of case row c of a [C][n][D] vector, rounded to T (zero without sums)
+template <typename T, int D>
+__device__ __forceinline__ void case_means(const double* __restrict__ sums, double inv_n, int c, T (&m)[D]) {
+#pragma unroll
+  for (int d = 0; d < D; ++d) m[d] = sums ? (T)(sums[c * D + d] * inv_n) : T(0);
+}
+
+template <typename T, int D>
 __global__ void k_pcg_update(T* __restrict__ u, T* __restrict__ r, const T* __restrict__ p,
-                             const T* __restrict__ q, const double* __restrict__ alpha, int n, int D,
+                             const T* __restrict__ q, const double* __restrict__ alpha, int n,
                              const double* __restrict__ qsums, double inv_n) {
   // grid row = case
   const int j = blockIdx.x * kBlock + threadIdx.x;
   if (j >= n * D) return;
   const size_t i = (size_t)blockIdx.y * n * D + j;
   const T a = (T)alpha[blockIdx.y];
+  T m[D];
+  case_means<T, D>(qsums, inv_n, blockIdx.y, m);
   u[i] = fma(a, p[i], u[i]);
-  T qv = q[i];
-  if (qsums) qv -= (T)(qsums[blockIdx.y * D + j % D] * inv_n);
-  r[i] = fma(-a, qv, r[i]);
+  r[i] = fma(-a, q[i] - m[j % D], r[i]);
 }
 
 // p = z + beta p; with sums, z enters with its column means removed (as k_sub_mean
 // would have written it)
-template <typename T>
+template <typename T, int D>
 __global__ void k_pcg_direction(T* __restrict__ p, const T* __restrict__ z, const double* __restrict__ beta, int n,
-                                int D, const double* __restrict__ sums, double inv_n) {
+                                const double* __restrict__ sums, double inv_n) {
   // grid row = case
   const int j = blockIdx.x * kBlock + threadIdx.x;
   if (j >= n * D) return;
   const size_t i = (size_t)blockIdx.y * n * D + j;
   const T b = (T)beta[blockIdx.y];
-  T zv = z[i];
-  if (sums) zv -= (T)(sums[blockIdx.y * D + j % D] * inv_n);
-  p[i] = fma(b, p[i], zv);
+  T m[D];
+  case_means<T, D>(sums, inv_n, blockIdx.y, m);
+  p[i] = fma(b, p[i], z[i] - m[j % D]);
 }
 
 // stop (nullable): the device-side convergence flag of captured PCG blocks; once
@@ -2238,8 +2245,13 @@ void launch_pcg_update(T* u, T* r, const T* p, const T* q, const double* alpha, 
                        hipStream_t s, const double* qsums, double inv_n) {
   const size_t tot = (size_t)n * Q;
   if (!tot) return;
-  hipLaunchKernelGGL(k_pcg_update<T>, dim3(blocks_for((size_t)n * D), Q / D), dim3(kBlock), 0, s, u, r, p, q, alpha, n,
-                     D, qsums, inv_n);
+  const dim3 g(blocks_for((size_t)n * D), Q / D);
+  if (D == 3)
+    hipLaunchKernelGGL((k_pcg_update<T, 3>), g, dim3(kBlock), 0, s, u, r, p, q, alpha, n, qsums, inv_n);
+  else if (D == 1)
+    hipLaunchKernelGGL((k_pcg_update<T, 1>), g, dim3(kBlock), 0, s, u, r, p, q, alpha, n, qsums, inv_n);
+  else
+    fail(GMT_E_INVAL, "unsupported d = %d", D);
   GMT_LAUNCH_CHECK();
 }
 
@@ -2275,8 +2287,13 @@ void launch_pcg_direction(T* p, const T* z, const double* beta, int n, int Q, in
                           const double* sums, double inv_n) {
   const size_t tot = (size_t)n * Q;
   if (!tot) return;
-  hipLaunchKernelGGL(k_pcg_direction<T>, dim3(blocks_for((size_t)n * D), Q / D), dim3(kBlock), 0, s, p, z, beta, n, D,
-                     sums, inv_n);
+  const dim3 g(blocks_for((size_t)n * D), Q / D);
+  if (D == 3)
+    hipLaunchKernelGGL((k_pcg_direction<T, 3>), g, dim3(kBlock), 0, s, p, z, beta, n, sums, inv_n);
+  else if (D == 1)
+    hipLaunchKernelGGL((k_pcg_direction<T, 1>), g, dim3(kBlock), 0, s, p, z, beta, n, sums, inv_n);
+  else
+    fail(GMT_E_INVAL, "unsupported d = %d", D);
   GMT_LAUNCH_CHECK();
 }
 
