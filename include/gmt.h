@@ -139,6 +139,9 @@ typedef struct {
   int32_t graph;      /* 1: inner PCG iterations run as replays of captured hipGraph
                          blocks of 1 or 4 iterations (host check between blocks);
                          0: kernel-by-kernel launches, check every check_every */
+  int32_t zero_start; /* 1: start from u = 0 whatever d_u holds on entry (the first
+                         residual is then f itself: no operator sweep, no layout pass
+                         over d_u); 0: start from d_u */
 } gmt_solve_opts;
 
 typedef struct {

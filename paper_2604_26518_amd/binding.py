@@ -59,7 +59,7 @@ class GmtCycleOpts(ct.Structure):
 class GmtSolveOpts(ct.Structure):
     _fields_ = [("tol", ct.c_double), ("max_iter", ct.c_int32), ("precision", ct.c_int32),
                 ("max_outer", ct.c_int32), ("check_every", ct.c_int32), ("cycle", GmtCycleOpts),
-                ("graph", ct.c_int32)]
+                ("graph", ct.c_int32), ("zero_start", ct.c_int32)]
 
 
 class GmtSolveReport(ct.Structure):
@@ -439,11 +439,13 @@ class Hierarchy:
               nu1=2, nu2=2, smoother="chebyshev", omega=None, lo=None, hi=None, raise_on_noconv=True,
               graph=True, schedule="V"):
         self._v(f, 1, torch.float64, "f")
-        if u is None:
-            u = torch.zeros_like(f)
+        zero = u is None
+        if zero:
+            u = torch.empty_like(f)  # output only: the solve starts from zero
         self._v(u, 1, torch.float64, "u")
         o, keep = self.solve_opts(tol, max_iter, precision, max_outer, check_every, nu1, nu2, smoother, omega, lo,
                                   hi, graph, schedule)
+        o.zero_start = 1 if zero else 0
         rep = GmtSolveReport()
         st = lib().gmt_solve(self._h, _ptr(f), _ptr(u), ct.byref(o), ct.byref(rep), _stream())
         report = _report(rep, self.c, st)
@@ -592,8 +594,9 @@ def solve_batch(hs, fs, us=None, n_workers=4, raise_on_noconv=True, **opts):
     n = len(hs)
     if len(fs) != n or (us is not None and len(us) != n):
         raise ValueError("hs, fs and us must have the same length")
-    if us is None:
-        us = [torch.zeros_like(f) for f in fs]
+    zero = us is None
+    if zero:
+        us = [torch.empty_like(f) for f in fs]  # outputs only: every cell starts from zero
     for H, f, u in zip(hs, fs, us):
         H._v(f, 1, torch.float64, "f")
         H._v(u, 1, torch.float64, "u")
@@ -601,6 +604,7 @@ def solve_batch(hs, fs, us=None, n_workers=4, raise_on_noconv=True, **opts):
         if opts.get(k) is not None:
             raise ValueError(f"{k} is per cell; the batch uses each cell's defaults")
     o, keep = hs[0].solve_opts(**opts) if n else (GmtSolveOpts(), [])
+    o.zero_start = 1 if zero else 0
     harr = (ct.c_void_p * max(n, 1))(*[H._h for H in hs])
     farr = (ct.c_void_p * max(n, 1))(*[f.data_ptr() for f in fs])
     uarr = (ct.c_void_p * max(n, 1))(*[u.data_ptr() for u in us])

@@ -1196,9 +1196,12 @@ static bool zero_load(const Hier& h, const double* fnorm) {
 }
 
 static void rel_residual64(Hier& h, const double* f, const double* u, double* r, double* rel,
-                           double* fnorm_out, hipStream_t s) {
+                           double* fnorm_out, hipStream_t s, bool u_zero = false) {
   const int n = h.lv[0].n_n, C = h.C, D = h.D;
-  apply<double>(h, 0, EPI_RESID, u, f, r, C, s);
+  if (u_zero)  // r = f - K 0
+    launch_copy<double>(f, r, (size_t)n * h.Q, s);
+  else
+    apply<double>(h, 0, EPI_RESID, u, f, r, C, s);
   double* rr = h.red_out + 48;
   double* ff = h.red_out + 56;
   launch_dot<double>(r, r, n, C, D, h.red_partial, rr, s);
@@ -1613,7 +1616,7 @@ constexpr int kMaxInner32 = 120;
 constexpr int kInnerMixed = 100;
 
 static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, gmt_solve_report* rep,
-                  hipStream_t s, gmt_status* st) {
+                  hipStream_t s, gmt_status* st, bool u_zero = false) {
   const double tol = o && o->tol > 0 ? o->tol : 1e-5;
   const int max_iter = o && o->max_iter > 0 ? o->max_iter : 500;
   const int max_outer = o && o->max_outer > 0 ? o->max_outer : 8;  // (+ one FP64 fallback switch)
@@ -1646,7 +1649,7 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
   bool stalled32 = false;         // an FP32 inner solve stopped on stagnation
   double prev_worst = INFINITY;
   for (int outer = 0;; ++outer) {
-    rel_residual64(h, f, u, r64, rel, den, s);
+    rel_residual64(h, f, u, r64, rel, den, s, outer == 0 && u_zero);
     if (outer == 0 && zero_load(h, den)) {
       // zero load: the solution in the pinned gauge is u = 0
       launch_fill<double>(u, tot, 0.0, s);
@@ -2194,9 +2197,13 @@ gmt_status gmt_solve(gmt_hier_t H, const void* d_f, void* d_u, const gmt_solve_o
     if (opts && opts->cycle.smoother == GMT_SMOOTH_GS) ensure_colours(h, s);
     double* f = scratch64(h, &h.s_f64s);
     double* u = scratch64(h, &h.s_u64s);
+    const bool zero = opts && opts->zero_start;
     launch_aos_to_soa<double, double>((const double*)d_f, f, n, h.C, h.D, s);
-    launch_aos_to_soa<double, double>((const double*)d_u, u, n, h.C, h.D, s);
-    solve(h, f, u, opts, report, s, &st);
+    if (zero)
+      launch_fill<double>(u, (size_t)n * h.Q, 0.0, s);
+    else
+      launch_aos_to_soa<double, double>((const double*)d_u, u, n, h.C, h.D, s);
+    solve(h, f, u, opts, report, s, &st, zero);
     launch_soa_to_aos<double, double>(u, (double*)d_u, n, h.C, h.D, s);
     GMT_HIP(hipStreamSynchronize(s));
   });
@@ -2289,9 +2296,13 @@ gmt_status gmt_solve_batch(gmt_hier_t const* hs, int32_t n, const void* const* d
           const int nn = h.lv[0].n_n;
           double* f = h.s_f64s;
           double* u = h.s_u64s;
+          const bool zero = opts && opts->zero_start;
           launch_aos_to_soa<double, double>((const double*)d_f[i], f, nn, h.C, h.D, ws);
-          launch_aos_to_soa<double, double>((const double*)d_u[i], u, nn, h.C, h.D, ws);
-          solve(h, f, u, opts, &rep, ws, &cell);
+          if (zero)
+            launch_fill<double>(u, (size_t)nn * h.Q, 0.0, ws);
+          else
+            launch_aos_to_soa<double, double>((const double*)d_u[i], u, nn, h.C, h.D, ws);
+          solve(h, f, u, opts, &rep, ws, &cell, zero);
           launch_soa_to_aos<double, double>(u, (double*)d_u[i], nn, h.C, h.D, ws);
           GMT_HIP(hipStreamSynchronize(ws));
         });

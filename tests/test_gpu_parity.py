@@ -303,6 +303,23 @@ def test_solve_zero_mean_gauge(solved):
         _gmt().Hierarchy(vox, P.L, gauge="node7")
 
 
+def test_solve_zero_start_ignores_the_guess(solved):
+    """gmt_solve_opts.zero_start = 1 starts from u = 0 whatever the output buffer holds on entry
+    (here NaN): the same iterations and the same solution bit for bit as a start from zeros."""
+    import ctypes as ct
+    B = _gmt()
+    name, vox, P, H, u_ref, CH_ref = solved
+    f = H.load_vector()
+    u0, rep0 = H.solve(f, tol=1e-6, precision="f32", u=torch.zeros_like(f))
+    u1 = torch.full_like(f, float("nan"))
+    o, keep = H.solve_opts(tol=1e-6, precision="f32")
+    o.zero_start = 1
+    r = B.GmtSolveReport()
+    B._check(B.lib().gmt_solve(H._h, B._ptr(f), B._ptr(u1), ct.byref(o), ct.byref(r), B._stream()))
+    assert r.iterations == rep0["iterations"]
+    assert torch.equal(u0, u1)
+
+
 def test_solve_mixed(solved):
     name, vox, P, H, u_ref, CH_ref = solved
     f = H.load_vector()
