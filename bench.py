@@ -61,6 +61,7 @@ SWEEP_KERNELS = {
     6: "k_apply_interior_nc + k_apply_boundary_cls",
     7: "k_apply_interior<PRE=1> + k_apply_boundary_cls<PRE=1>",
     8: "k_apply_interior<PRE=1> + k_apply_boundary_all",
+    9: "k_apply_interior_stage + k_apply_interior<PRE=1> (unstaged rest) + k_apply_boundary_cls<PRE=1>",
 }
 # one network per resolution (the 512^3 one fine-tuned at 512^3 from the 128^3 one)
 WEIGHTS_BY_N = {N: os.path.join(ROOT, "paper_2604_26518_amd", "weights", f"unet{N}_elastic.npz") for N in (128, 512)}

@@ -102,7 +102,7 @@ void Hier::release_all() {
   owned_hip.clear();
 }
 
-// GMT_FORCE_L1_VARIANT=<cb> pins the level-1 sweep variant (0..3, 5..8, see the
+// GMT_FORCE_L1_VARIANT=<cb> pins the level-1 sweep variant (0..3, 5..9, see the
 // autotuner) for tests that compare every variant with the oracle.
 static int forced_l1_variant() {
   const char* e = std::getenv("GMT_FORCE_L1_VARIANT");
@@ -134,6 +134,13 @@ LevelView<T> Hier::view(int l) const {
   v.n_runs = d.n_runs;
   v.runs = d.runs;
   v.bnd_nbrs = d.bnd_nbrs;
+  v.st_blk = d.st_blk;
+  v.n_st_blk = d.n_st_blk;
+  v.st_off = d.st_off;
+  v.st_ids = d.st_ids;
+  v.st_slot = d.st_slot;
+  v.st_rest = d.st_rest;
+  v.n_st_rest = d.n_st_rest;
   if constexpr (std::is_same<T, double>::value)
     v.oscale = d.oscale64;
   else
@@ -161,9 +168,10 @@ LevelView<T> Hier::view(int l) const {
   }
   if (l == 0) {
     const int f = forced_l1_variant();
-    if (f >= 0 && f <= 8 && f != 4) v.cb = f;
+    if (f >= 0 && f <= 9 && f != 4) v.cb = f;
     // a density hierarchy has only the scaled class-assembled boundary sweeps
     if (density && v.cb != 5 && v.cb != 7 && v.cb != 8) v.cb = 7;
+    if (v.cb == 9 && v.n_st_blk == 0 && v.n_st_rest == 0) v.cb = 7;  // no staged tables
   }
   return v;
 }
@@ -805,8 +813,9 @@ static void vcycle(Hier& h, const T* f0, T* u0, bool u0_zero, const T* const* e_
 // per case (cb 1, or cb 3 with interior nodes in runs along x), or takes the
 // boundary nodes as a masked stencil assembled in registers from the symmetry
 // classes of K_e, with the interior one case per pass (cb 5; cb 7 with all 27
-// neighbours of a case loaded before the arithmetic) or all cases per
-// neighbour load (cb 6).
+// neighbours of a case loaded before the arithmetic; cb 9 with the distinct
+// neighbours of each workgroup of 256 interior nodes staged in LDS) or all
+// cases per neighbour load (cb 6).
 // Before the first solve of a hierarchy, every
 // candidate is timed on every level (K.u on the work vectors: 2 warm-up and 3
 // timed launches between HIP events) and the fastest is kept.  Choices are
@@ -864,6 +873,7 @@ static void autotune(Hier& h, hipStream_t s) {
       cand = {{256, 7, 1}, {256, 7, 0}, {256, 5, 1}, {256, 8, 1}, {256, 8, 0}};
     } else if (l == 0) {
       cand = {{256, 8, 1}, {256, 8, 0}, {256, 7, 1}, {256, 7, 0}, {256, 5, 1}, {256, 6, 1}, {256, 6, 0}};
+      if (d.n_st_blk > 0) cand.insert(cand.end(), {{256, 9, 1}, {256, 9, 0}});
       if (h.C > 1) cand.insert(cand.end(), {{256, 1, 1}, {256, 1, 0}});
     }
     if (l > 0) {
@@ -1375,6 +1385,53 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s, const double* rho 
       if (reinterpret_cast<uintptr_t>(d.bnd_nbrs) % 16 != 0)  // the sweeps read its rows as int4
         fail(GMT_E_STATE, "boundary neighbour table is not 16-byte aligned");
       launch_boundary_nbrs(d.boundary, d.n_bnd, d.node_lin, d.node_map, d.N, d.bnd_nbrs, s);
+    }
+    // tables of the staged interior sweep: distinct neighbour ids per workgroup
+    // of 256 interior nodes (counted first); the workgroups with at most
+    // kStageIds of them are staged, the others' nodes listed for the plain kernel
+    if (d.n_int > 0) {
+      const int nblk = (d.n_int + 255) / 256;
+      int* cnt = h.alloc<int>(nblk);
+      launch_stage_tables(d.interior, d.n_int, d.node_lin, d.node_map, d.N, 0, nullptr, 0, cnt, nullptr, nullptr,
+                          nullptr, s);
+      std::vector<int> hc(nblk);
+      GMT_HIP(hipMemcpyAsync(hc.data(), cnt, nblk * sizeof(int), hipMemcpyDeviceToHost, s));
+      GMT_HIP(hipStreamSynchronize(s));
+      auto nodes_of = [&](int b) { return std::min(256, d.n_int - 256 * b); };
+      std::vector<int> good, rest;
+      std::vector<long long> ho(1, 0);
+      for (int b = 0; b < nblk; ++b) {
+        if (hc[b] <= kStageIds) {
+          good.push_back(b);
+          ho.push_back(ho.back() + hc[b]);
+        } else {
+          rest.push_back(b);
+        }
+      }
+      d.n_st_blk = (int)good.size();
+      if (!good.empty()) {
+        d.st_blk = h.alloc<int>(good.size());
+        d.st_off = h.alloc<long long>(ho.size());
+        d.st_ids = h.alloc<int>((size_t)std::max(ho.back(), 1LL));
+        d.st_slot = h.alloc<uint16_t>((size_t)d.n_int * kSlotStride);
+        GMT_HIP(hipMemcpyAsync(d.st_blk, good.data(), good.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        GMT_HIP(hipMemcpyAsync(d.st_off, ho.data(), ho.size() * sizeof(long long), hipMemcpyHostToDevice, s));
+        launch_stage_tables(d.interior, d.n_int, d.node_lin, d.node_map, d.N, 1, d.st_blk, d.n_st_blk, cnt,
+                            d.st_off, d.st_ids, d.st_slot, s);
+      }
+      if (!rest.empty()) {
+        long long nr = 0;
+        for (int b : rest) nr += nodes_of(b);
+        int* rb = h.alloc<int>(rest.size());
+        GMT_HIP(hipMemcpyAsync(rb, rest.data(), rest.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        d.st_rest = h.alloc<int>((size_t)rest.size() * 256);
+        d.n_st_rest = (int)nr;
+        launch_gather_blocks(d.interior, d.n_int, rb, (int)rest.size(), d.st_rest, s);
+        GMT_HIP(hipStreamSynchronize(s));
+        h.release(rb);
+      }
+      GMT_HIP(hipStreamSynchronize(s));
+      h.release(cnt);
     }
     GMT_HIP(hipStreamSynchronize(s));
     h.release(tmpmap);

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <type_traits>
 
@@ -89,7 +90,8 @@ constexpr bool needs_dinv() {
 // round trip.  The arithmetic is that of epilogue_d.
 template <typename T, int EPI, int CC, int D>
 __device__ __forceinline__ void epilogue_node(const EpiArgs<T>& e, const T* __restrict__ u, size_t n, size_t i, int c0,
-                                              const T* acc, const T* uself, const T* dv) {
+                                              const T* acc, const T* uself, const T* dv, const T* fpre = nullptr,
+                                              const T* dpre = nullptr) {
   T fv[CC][D], dd[CC][D], us[CC][D], di[D];
 #pragma unroll
   for (int q = 0; q < D; ++q) di[q] = needs_dinv<EPI>() ? (dv ? dv[q] : e.dinv[i * D + q]) : T(0);
@@ -98,8 +100,8 @@ __device__ __forceinline__ void epilogue_node(const EpiArgs<T>& e, const T* __re
 #pragma unroll
     for (int q = 0; q < D; ++q) {
       const size_t idx = vix(c0 + c, n, i, D, q);
-      fv[c][q] = EPI != EPI_KU ? e.f[idx] : T(0);
-      dd[c][q] = EPI == EPI_CHEB ? e.dvec[idx] : T(0);
+      fv[c][q] = EPI != EPI_KU ? (fpre ? fpre[c * D + q] : e.f[idx]) : T(0);
+      dd[c][q] = EPI == EPI_CHEB ? (dpre ? dpre[c * D + q] : e.dvec[idx]) : T(0);
       us[c][q] = needs_dinv<EPI>() ? (uself ? uself[c * D + q] : u[idx]) : T(0);
     }
   // results first, then each output array's D values of a case as one run of
@@ -237,6 +239,137 @@ __global__ __launch_bounds__(kBlock) void k_apply_interior(LevelView<T> L, int C
       }
     }
     epilogue_node<T, EPI, 1, D>(e, u, n, i, c, acc, uself, dv);
+  }
+}
+
+constexpr int kStageK = kStageIds / kBlock;
+
+// Level 1, interior nodes, neighbourhoods staged in LDS.  Workgroup g takes
+// the interior nodes b*256 .. b*256 + 255 of b = st_blk[g] and, per case, first copies the
+// distinct vector entries that their 27-point stencils read (one gather per
+// distinct node, about 4 per interior node on a lattice cell instead of 27)
+// into LDS, then applies the stencil from there through the node's 27 slots.
+// The plain kernel's per-node gathers keep the vector memory data path busy
+// (each wide gather occupies it for ~30 cycles); here most reads go to LDS.
+// A workgroup stages at most kStageK * 256 distinct nodes (kStageK per
+// thread); the workgroups with more are left to the plain kernel (st_rest).
+template <typename T, int D, int EPI>
+__global__ __launch_bounds__(kBlock) void k_apply_interior_stage(LevelView<T> L, int C, const T* __restrict__ u,
+                                                                 EpiArgs<T> e) {
+  // an FP32 node's 3 values at a 16-byte stride: one 128-bit LDS read each
+  constexpr int DP = (D == 3 && sizeof(T) == 4) ? 4 : D;
+  __shared__ __align__(16) T stg[kStageK * kBlock * DP];
+  const int g = block_index(L.xcd);
+  const int t = L.st_blk[g] * kBlock + (int)threadIdx.x;
+  const bool valid = t < L.n_int;
+  const size_t n = (size_t)L.n_n;
+  const long long o0 = L.st_off[g];
+  const int U = (int)(L.st_off[g + 1] - o0);
+  int sid[kStageK];
+#pragma unroll
+  for (int k = 0; k < kStageK; ++k) {
+    const int p = (int)threadIdx.x + k * kBlock;
+    sid[k] = p < U ? L.st_ids[o0 + p] : -1;
+  }
+  // the node's 27 slots, two per 32-bit word
+  unsigned sw[kSlotStride / 2];
+  const int i = valid ? L.interior[t] : 0;
+  if (valid) {
+    const uint2* row = reinterpret_cast<const uint2*>(L.st_slot + (size_t)t * kSlotStride);
+#pragma unroll
+    for (int k = 0; k < kSlotStride / 4; ++k) {
+      const uint2 v = row[k];
+      sw[2 * k] = v.x;
+      sw[2 * k + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kSlotStride / 2; ++k) sw[k] = 0;
+  }
+  T dv[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) dv[q] = needs_dinv<EPI>() && valid ? e.dinv[(size_t)i * D + q] : T(0);
+  const StencilClasses<T, D> S(L.scls);
+  // One case ahead: the staged values, f and the Chebyshev direction of case
+  // c + 1 are loaded while case c is computed from LDS, so that each case
+  // waits for one round trip to memory at most.
+  T w[kStageK][D], fn[D], dn[D];
+  auto load_case = [&](int c) {
+    // chunks past the workgroup's count are skipped as a whole (U is uniform);
+    // inside the last chunk, lanes past it load node 0's values unconditionally,
+    // so that the D loads of a node merge into one
+#pragma unroll
+    for (int k = 0; k < kStageK; ++k)
+      if (k * kBlock < U) {
+        const size_t id = sid[k] >= 0 ? (size_t)sid[k] : 0;
+#pragma unroll
+        for (int q = 0; q < D; ++q) w[k][q] = u[vix(c, n, id, D, q)];
+      }
+#pragma unroll
+    for (int q = 0; q < D; ++q) {  // (threads without a node read node 0's: i = 0)
+      const size_t idx = vix(c, n, i, D, q);
+      fn[q] = EPI != EPI_KU ? e.f[idx] : T(0);
+      dn[q] = EPI == EPI_CHEB ? e.dvec[idx] : T(0);
+    }
+  };
+  auto store_stage = [&]() {
+#pragma unroll
+    for (int k = 0; k < kStageK; ++k)
+      if (k * kBlock < U && sid[k] >= 0) {
+        T* dst = stg + ((int)threadIdx.x + k * kBlock) * DP;
+        if constexpr (DP == 4) {
+          *reinterpret_cast<float4*>(dst) = make_float4(w[k][0], w[k][1], w[k][2], 0.0f);
+        } else {
+#pragma unroll
+          for (int q = 0; q < D; ++q) dst[q] = w[k][q];
+        }
+      }
+  };
+  load_case(0);
+  store_stage();
+  __syncthreads();
+#pragma unroll 1
+  for (int c = 0; c < C; ++c) {
+    T fc[D], dc[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      fc[q] = fn[q];
+      dc[q] = dn[q];
+    }
+    if (c + 1 < C) load_case(c + 1);
+    if (valid) {
+      T acc[D], uself[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q) acc[q] = T(0);
+#pragma unroll
+      for (int j = 0; j < 27; ++j) {
+        const int slot = (int)((sw[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+        T vv[D];
+        if constexpr (DP == 4) {
+          const float4 f4 = *reinterpret_cast<const float4*>(stg + slot * 4);
+          vv[0] = f4.x;
+          vv[1] = f4.y;
+          vv[2] = f4.z;
+        } else {
+#pragma unroll
+          for (int q2 = 0; q2 < D; ++q2) vv[q2] = stg[slot * D + q2];
+        }
+#pragma unroll
+        for (int q2 = 0; q2 < D; ++q2) {
+          const T v = vv[q2];
+          if (j == 13) uself[q2] = v;
+#pragma unroll
+          for (int q = 0; q < D; ++q)
+            if (stencil_nonzero<D>(j, q, q2)) acc[q] = fma(S(j, q, q2), v, acc[q]);
+        }
+      }
+      epilogue_node<T, EPI, 1, D>(e, u, n, i, c, acc, uself, dv, fc, dc);
+    }
+    if (c + 1 < C) {
+      __syncthreads();  // every read of case c's stage is done
+      store_stage();
+      __syncthreads();
+    }
   }
 }
 
@@ -1472,6 +1605,88 @@ __global__ void k_scan_top(int* __restrict__ bsum, int nb, int* __restrict__ d_t
   if (threadIdx.x == 0) *d_total = carry;
 }
 
+// Tables of the staged interior sweep, one workgroup per 256 interior nodes:
+// the 27 x 256 neighbour ids are sorted in LDS (bitonic), the distinct ones
+// counted (pass 0, every workgroup b: cnt[b]) or, for the workgroups
+// b = blk[g] the staged sweep takes, written out ascending at off[g] together
+// with each node's 27 positions among them (pass 1: binary search).
+constexpr int kStageSort = 8192;  // >= 27 * kBlock, a power of two
+constexpr int kStageItems = kStageSort / kBlock;
+__global__ __launch_bounds__(kBlock) void k_stage_tables(const int* __restrict__ interior, int n_int,
+                                                         const int* __restrict__ node_lin,
+                                                         const int* __restrict__ node_map, int N, int pass,
+                                                         const int* __restrict__ blk, int* __restrict__ cnt,
+                                                         const long long* __restrict__ off, int* __restrict__ ids,
+                                                         uint16_t* __restrict__ slot) {
+  __shared__ int s[kStageSort];
+  const int g = blockIdx.x;
+  const int b = pass == 0 ? g : blk[g];
+  const int t = b * kBlock + (int)threadIdx.x;
+  const bool valid = t < n_int;
+  int nb[27];
+  if (valid) {
+    const int lin = node_lin[interior[t]];
+    neighbour_ids<true>(node_map, N, lin % N, (lin / N) % N, lin / (N * N), nb);
+  }
+#pragma unroll
+  for (int j = 0; j < 27; ++j) s[(int)threadIdx.x * 27 + j] = valid ? nb[j] : INT_MAX;
+  for (int k = 27 * kBlock + (int)threadIdx.x; k < kStageSort; k += kBlock) s[k] = INT_MAX;
+  __syncthreads();
+  for (int size = 2; size <= kStageSort; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int p = (int)threadIdx.x; p < kStageSort / 2; p += kBlock) {
+        const int lo = 2 * p - (p & (stride - 1));  // the partner index lo + stride has that bit set
+        const int hi = lo + stride;
+        const int a = s[lo], c = s[hi];
+        if ((a > c) == ((lo & size) == 0)) {
+          s[lo] = c;
+          s[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // distinct values: thread k owns the sorted entries k * kStageItems ..
+  int v[kStageItems];
+  int m = 0;
+  const int base = (int)threadIdx.x * kStageItems;
+#pragma unroll
+  for (int k = 0; k < kStageItems; ++k) {
+    v[k] = s[base + k];
+    const int prev = base + k > 0 ? s[base + k - 1] : INT_MIN;
+    if (v[k] == INT_MAX || v[k] == prev) v[k] = -1;  // not the first of its value
+    m += v[k] >= 0;
+  }
+  int total;
+  int pos = block_exclusive_scan(m, &total);  // contains a barrier after every read of s above
+  if (pass == 0) {
+    if (threadIdx.x == 0) cnt[b] = total;
+    return;
+  }
+  const long long o0 = off[g];
+#pragma unroll
+  for (int k = 0; k < kStageItems; ++k)
+    if (v[k] >= 0) {
+      s[pos] = v[k];
+      ids[o0 + pos] = v[k];
+      ++pos;
+    }
+  __syncthreads();
+  if (!valid) return;
+  uint16_t* row = slot + (size_t)t * kSlotStride;
+#pragma unroll
+  for (int j = 0; j < 27; ++j) {
+    int lo = 0, hi = total;  // first position with s[pos] >= nb[j]
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (s[mid] < nb[j]) lo = mid + 1;
+      else hi = mid;
+    }
+    row[j] = (uint16_t)lo;
+  }
+  row[27] = 0;
+}
+
 // per block: ids of the flagged items in linear order; map (id or -1), lin (id -> index)
 __global__ void k_scan_compact(const int* __restrict__ flags, size_t n, const int* __restrict__ boff,
                                int* __restrict__ map, int* __restrict__ lin) {
@@ -1961,12 +2176,29 @@ static void launch_coarse(const LevelView<T>& L, int kind, int rows, const T* u,
   }
 }
 
+// staged interior sweep (variant 9): the staged workgroups, then the plain
+// kernel (all 27 neighbours of a case loaded up front) over the rest
+template <typename T, int D, int EPI>
+static void launch_interior_stage(const LevelView<T>& L, int C, const T* u, const EpiArgs<T>& e, hipStream_t s) {
+  if (L.n_st_blk > 0)
+    hipLaunchKernelGGL((k_apply_interior_stage<T, D, EPI>), dim3((unsigned)L.n_st_blk), dim3(kBlock), 0, s, L, C, u,
+                       e);
+  if (L.n_st_rest > 0) {
+    LevelView<T> R = L;
+    R.interior = L.st_rest;
+    R.n_int = L.n_st_rest;
+    hipLaunchKernelGGL((k_apply_interior<T, D, EPI, 1>), dim3(blocks_for(R.n_int)), dim3(kBlock), 0, s, R, C, u, e);
+  }
+}
+
 template <typename T, int D, int C, int EPI>
 static void apply_dispatch_kind(const LevelView<T>& L, int kind, const T* u, const EpiArgs<T>& e, hipStream_t s) {
   if (kind == KIND_SHARED) {
-    if (L.cb >= 5 && L.cb <= 8) {  // boundary as a register-assembled masked stencil
+    if (L.cb >= 5 && L.cb <= 9) {  // boundary as a register-assembled masked stencil
       if (L.n_int > 0) {
-        if (L.cb == 5)
+        if (L.cb == 9)
+          launch_interior_stage<T, D, EPI>(L, C, u, e, s);
+        else if (L.cb == 5)
           hipLaunchKernelGGL((k_apply_interior<T, D, EPI>), dim3(blocks_for(L.n_int)), dim3(kBlock), 0, s, L, C, u, e);
         else if (L.cb == 7 || L.cb == 8)
           hipLaunchKernelGGL((k_apply_interior<T, D, EPI, 1>), dim3(blocks_for(L.n_int)), dim3(kBlock), 0, s, L, C, u, e);
@@ -1982,7 +2214,7 @@ static void apply_dispatch_kind(const LevelView<T>& L, int kind, const T* u, con
         if (L.cb == 8)  // all cases per thread: one assembly per node
           hipLaunchKernelGGL((k_apply_boundary_all<T, D, C, EPI>), dim3(blocks_for(L.n_bnd)), dim3(kBlock), 0, s, L,
                              u, e);
-        else if (L.cb == 7)
+        else if (L.cb == 7 || L.cb == 9)
           hipLaunchKernelGGL((k_apply_boundary_cls<T, D, 1, EPI, 1>), g, dim3(kBlock), 0, s, L, u, e);
         else
           hipLaunchKernelGGL((k_apply_boundary_cls<T, D, 1, EPI>), g, dim3(kBlock), 0, s, L, u, e);
@@ -2398,6 +2630,31 @@ void launch_boundary_nbrs(const int* boundary, int n_bnd, const int* node_lin, c
 void launch_run_flags(const int* interior, int n_int, const int* node_lin, int N, int* flags, hipStream_t s) {
   if (!n_int) return;
   hipLaunchKernelGGL(k_run_flags, dim3(blocks_for(n_int)), dim3(kBlock), 0, s, interior, n_int, node_lin, N, flags);
+  GMT_LAUNCH_CHECK();
+}
+
+void launch_stage_tables(const int* interior, int n_int, const int* node_lin, const int* node_map, int N, int pass,
+                         const int* blk, int n_blk, int* cnt, const long long* off, int* ids, uint16_t* slot,
+                         hipStream_t s) {
+  static_assert(27 * kBlock <= kStageSort, "sort buffer too small");
+  const unsigned grid = pass == 0 ? blocks_for(n_int) : (unsigned)n_blk;
+  if (!n_int || !grid) return;
+  hipLaunchKernelGGL(k_stage_tables, dim3(grid), dim3(kBlock), 0, s, interior, n_int, node_lin, node_map, N, pass, blk,
+                     cnt, off, ids, slot);
+  GMT_LAUNCH_CHECK();
+}
+
+// out = the interior ids of the workgroups blk[0 .. n_blk) (256 positions each,
+// the last workgroup of the list possibly partial), in that order
+__global__ void k_gather_blocks(const int* __restrict__ interior, int n_int, const int* __restrict__ blk,
+                                int* __restrict__ out) {
+  const int t = blk[blockIdx.x] * kBlock + (int)threadIdx.x;
+  if (t < n_int) out[(size_t)blockIdx.x * kBlock + threadIdx.x] = interior[t];
+}
+
+void launch_gather_blocks(const int* interior, int n_int, const int* blk, int n_blk, int* out, hipStream_t s) {
+  if (!n_blk) return;
+  hipLaunchKernelGGL(k_gather_blocks, dim3(n_blk), dim3(kBlock), 0, s, interior, n_int, blk, out);
   GMT_LAUNCH_CHECK();
 }
 

@@ -170,13 +170,13 @@ def test_smoother(pair, smoother):
     assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 5, 6, 7, 8])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 5, 6, 7, 8, 9])
 def test_level1_sweep_variants(pair, variant, monkeypatch):
     """Every level-1 kernel variant the autotuner may pick (all cases per neighbour load with
     the boundary as a masked stencil or element by element; one case per pass, with the
     interior in x-runs or node by node; the boundary as a stencil assembled from the symmetry
-    classes of K_e, with or without all neighbours loaded up front): K.u, residual and both
-    fused smoothers."""
+    classes of K_e, with or without all neighbours loaded up front; the interior staged in LDS
+    per workgroup): K.u, residual and both fused smoothers."""
     name, vox, P, H = pair
     monkeypatch.setenv("GMT_FORCE_L1_VARIANT", str(variant))
     lam = _bounds(P, H)
