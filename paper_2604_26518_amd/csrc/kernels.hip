@@ -1035,9 +1035,14 @@ __global__ void k_smooth_zero(int n, int D, int C, const T* __restrict__ f, cons
 
 // Restriction in gather form: coarse node X collects the fine nodes 2X + delta,
 // delta in {-1,0,1}^3, with weight prod_d (1 - |delta_d|/2): exactly R = P^T.
+// The 27 fine ids are looked up first; then, case by case, the 27 fine values
+// are all loaded before the first FMA (27 gathers in flight instead of one
+// dependent lookup-and-load per neighbour).  The sum runs over the neighbours
+// in the same order either way; absent neighbours are skipped, not added as 0.
 template <typename T, int Q, int D>
 __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> F, LevelView<T> Cv, const T* __restrict__ rf,
                                                      T* __restrict__ fc) {
+  constexpr int C = Q / D;
   const int J = xcd_block() * kBlock + threadIdx.x;
   if (J >= Cv.n_n) return;
   const int Nc = Cv.N, Nf = F.N;
@@ -1047,26 +1052,35 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> F, LevelView<T
   const int t = lin / Nc;
   const int Y = t % Nc;
   const int Z = t / Nc;
-  T acc[Q];
+  int ids[27];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) acc[q] = T(0);
-#pragma unroll 1
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int fz = wrapm(2 * Z + dz, Nf);
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int fy = wrapm(2 * Y + dy, Nf);
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int fx = wrapm(2 * X + dx, Nf);
-        const int id = F.node_map[fx + Nf * (fy + Nf * fz)];
-        if (id < 0) continue;
-        const T w = T((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
-#pragma unroll
-        for (int q = 0; q < Q; ++q) acc[q] = fma(w, rf[vix(q / D, nf, id, D, q % D)], acc[q]);
-      }
-    }
+  for (int k = 0; k < 27; ++k) {
+    const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+    ids[k] = F.node_map[wrapm(2 * X + dx, Nf) + Nf * (wrapm(2 * Y + dy, Nf) + Nf * wrapm(2 * Z + dz, Nf))];
   }
+#pragma unroll 1
+  for (int c = 0; c < C; ++c) {
+    T v[27][D];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) fc[vix(q / D, nc, J, D, q % D)] = acc[q];
+    for (int k = 0; k < 27; ++k) {
+      const size_t id = ids[k] >= 0 ? (size_t)ids[k] : 0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) v[k][d] = rf[vix(c, nf, id, D, d)];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the FMA chain
+    T acc[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) acc[d] = T(0);
+#pragma unroll
+    for (int k = 0; k < 27; ++k) {
+      const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+      const T w = T((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
+#pragma unroll
+      for (int d = 0; d < D; ++d) acc[d] = ids[k] >= 0 ? fma(w, v[k][d], acc[d]) : acc[d];
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) fc[vix(c, nc, J, D, d)] = acc[d];
+  }
 }
 
 // Prolongation + correction: u_f(i) += sum_k W_ik u_c(I_ik) (App. E.1 weights).
