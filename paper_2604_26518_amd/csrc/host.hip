@@ -1587,11 +1587,12 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s, const double* rho 
     double* part = h.alloc<double>((size_t)h.L * kRedBlocks);
     pw[0] = X32, pw[1] = Y32, pw[2] = T32, pw[3] = X64, pw[4] = Y64, pw[5] = T64, pw[6] = part;
     double* o = h.red_out + 64;  // [4 + 2l, 5 + 2l]: quotient of level l; [40 + l]: its norm
-    // One vector: on level 1 the class-assembled boundary sweep (cb 7) costs
-    // in proportion to the number of cases, the masked-stencil one (cb 0, the
-    // default before the autotuner runs) does not.
+    // One vector: on level 1 the class-assembled boundary sweep (cb 7, or 9
+    // with the staged interior) costs in proportion to the number of cases,
+    // the masked-stencil one (cb 0, the default before the autotuner runs)
+    // does not.
     const int cb_keep = h.lv[0].cb32, cb_keep64 = h.lv[0].cb64;
-    if (h.lv[0].kind == KIND_SHARED) h.lv[0].cb32 = h.lv[0].cb64 = 7;
+    if (h.lv[0].kind == KIND_SHARED) h.lv[0].cb32 = h.lv[0].cb64 = h.lv[0].n_st_blk > 0 ? 9 : 7;
     hipEvent_t fork = evs.make();
     GMT_HIP(hipEventRecord(fork, s));
     for (int l = 0; l < h.L; ++l) {

@@ -1084,9 +1084,14 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> F, LevelView<T
 }
 
 // Prolongation + correction: u_f(i) += sum_k W_ik u_c(I_ik) (App. E.1 weights).
+// Per axis an even fine coordinate has one parent (weight 1), an odd one two
+// (1/2 each).  The up to 8 parent ids are looked up first; then, case by case,
+// the parents' values are loaded before the first FMA.  The sum runs over the
+// parents in the same order as a loop over (z, y, x) offsets would.
 template <typename T, int Q, int D>
 __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView<T> F, LevelView<T> Cv, const T* __restrict__ uc,
                                                         T* __restrict__ uf) {
+  constexpr int C = Q / D;
   const int i = xcd_block() * kBlock + threadIdx.x;
   if (i >= F.n_n) return;
   const int Nc = Cv.N, Nf = F.N;
@@ -1096,25 +1101,37 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView<T> F, LevelVie
   const int t = lin / Nf;
   const int y = t % Nf;
   const int z = t / Nf;
-  // per axis: even coordinate -> one parent (weight 1); odd -> two (1/2 each)
   const int cx0 = x >> 1, cy0 = y >> 1, cz0 = z >> 1;
   const int nx = (x & 1) ? 2 : 1, ny = (y & 1) ? 2 : 1, nz = (z & 1) ? 2 : 1;
-  T acc[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) acc[q] = uf[vix(q / D, nf, i, D, q % D)];
   const T w = T(1.0 / (nx * ny * nz));
-#pragma unroll 1
-  for (int oz = 0; oz < nz; ++oz)
-    for (int oy = 0; oy < ny; ++oy)
-      for (int ox = 0; ox < nx; ++ox) {
-        const int X = wrapm(cx0 + ox, Nc), Y = wrapm(cy0 + oy, Nc), Z = wrapm(cz0 + oz, Nc);
-        const int id = Cv.node_map[X + Nc * (Y + Nc * Z)];
-        if (id < 0) continue;  // cannot happen for a consistent hierarchy
+  int pid[8];  // parent (ox, oy, oz) = (k & 1, (k >> 1) & 1, k >> 2); -1 where absent
 #pragma unroll
-        for (int q = 0; q < Q; ++q) acc[q] = fma(w, uc[vix(q / D, nc, id, D, q % D)], acc[q]);
+  for (int k = 0; k < 8; ++k) {
+    const int ox = k & 1, oy = (k >> 1) & 1, oz = k >> 2;
+    pid[k] = -1;
+    if (ox < nx && oy < ny && oz < nz)  // (a consistent hierarchy has every such parent)
+      pid[k] = Cv.node_map[wrapm(cx0 + ox, Nc) + Nc * (wrapm(cy0 + oy, Nc) + Nc * wrapm(cz0 + oz, Nc))];
+  }
+#pragma unroll 1
+  for (int c = 0; c < C; ++c) {
+    T acc[D], v[8][D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) acc[d] = uf[vix(c, nf, i, D, d)];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (pid[k] >= 0) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) v[k][d] = uc[vix(c, nc, pid[k], D, d)];
       }
 #pragma unroll
-  for (int q = 0; q < Q; ++q) uf[vix(q / D, nf, i, D, q % D)] = acc[q];
+    for (int k = 0; k < 8; ++k)
+      if (pid[k] >= 0) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) acc[d] = fma(w, v[k][d], acc[d]);
+      }
+#pragma unroll
+    for (int d = 0; d < D; ++d) uf[vix(c, nf, i, D, d)] = acc[d];
+  }
 }
 
 // ---------------------------------------------------------------- coarsest solve
