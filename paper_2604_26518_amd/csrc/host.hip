@@ -1673,6 +1673,18 @@ constexpr int kMaxInner32 = 120;
 // V-cycle (pcg<double, true>)
 constexpr int kInnerMixed = 100;
 
+// Mixed precision runs only a few level-1 FP64 residual sweeps: rather than
+// timing the FP64 candidates for them, they borrow the launch shape the FP32
+// autotuner chose for level 1 (every variant exists in both precisions).  A
+// later FP64 autotune (FP64 inner solves) still times its own.
+static void borrow_f32_shape(Hier& h) {
+  LevelData& d = h.lv[0];
+  if (d.tuned64 || !d.tuned32) return;
+  d.bs64 = d.bs32;
+  d.cb64 = d.cb32;
+  d.xcd64 = d.xcd32;
+}
+
 static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, gmt_solve_report* rep,
                   hipStream_t s, gmt_status* st, bool u_zero = false) {
   const double tol = o && o->tol > 0 ? o->tol : 1e-5;
@@ -1691,11 +1703,12 @@ static void solve(Hier& h, const double* f, double* u, const gmt_solve_opts* o, 
   if (cfg.schedule == GMT_CYCLE_F)
     fail(GMT_E_INVAL, "the F-cycle is not symmetric: it cannot precondition conjugate gradients");
   double* r64 = scratch64(h, &h.s_r64);
-  // (in mixed precision the few FP64 residual sweeps keep the default shape)
-  if (prec == GMT_F32)
+  if (prec == GMT_F32) {
     autotune<float>(h, s);
-  else
+    borrow_f32_shape(h);
+  } else {
     autotune<double>(h, s);
+  }
   const int C = h.C;
   const size_t tot = (size_t)h.lv[0].n_n * h.Q;
   gmt_solve_report R{};
@@ -2209,6 +2222,7 @@ gmt_status gmt_coarse_solve(gmt_hier_t H, const void* d_f, void* d_u, int32_t dt
 template <typename T>
 static void vcycle_abi(Hier& h, const void* d_f, void* d_u, const void* const* d_e_init, const CycleCfg& cfg,
                        hipStream_t s) {
+  autotune<T>(h, s);  // the launch shapes the solver uses (cached per shape class)
   h.ensure_io<T>(0);
   Work<T>& W = h.work<T>();
   const T* f = stage_in<T>(h, 0, d_f, W.io1[0], s);
@@ -2282,6 +2296,7 @@ static void prepare_solve(Hier& h, int prec, const gmt_solve_opts* o, hipStream_
     if (!h.s_x32) h.s_x32 = h.alloc<float>(tot);
     scratch64(h, &h.s_usave);
     autotune<float>(h, s);
+    borrow_f32_shape(h);
   } else {
     scratch64(h, &h.s_x64);
     autotune<double>(h, s);
@@ -2677,6 +2692,7 @@ static void vcycle_loss(Hier& h, const float* const* d_pred, const gmt_cycle_opt
   const CycleCfg cfg = make_cycle(h, opts);
   if (cfg.smoother == GMT_SMOOTH_GS || cfg.schedule != GMT_CYCLE_V)
     fail(GMT_E_INVAL, "the loss adjoint covers the V-cycle with Chebyshev or Jacobi smoothing");
+  autotune<float>(h, s);  // the launch shapes the solver uses (cached per shape class)
   h.ensure_work<float>();
   h.ensure_io<float>(0);
   Work<float>& W = h.work<float>();
