@@ -91,9 +91,13 @@ __host__ __device__ constexpr bool scls_negative(int j, int d, int d2) {
 constexpr int kBndStride = 28;
 // uint16 neighbour slots per interior node in the staged sweep's table (27 used)
 constexpr int kSlotStride = 28;
-// most distinct neighbour ids one workgroup of the staged sweep copies to LDS
-// (8 per thread of 256)
-constexpr int kStageIds = 2048;
+// the staged interior sweep takes the interior nodes in groups of nb = 256 or
+// 512 (one workgroup each; 512 on levels with at least kStageBigFrom interior
+// nodes, where the larger groups share more of their neighbourhoods) and
+// copies at most stage_k(nb, fp64) distinct neighbours per thread to LDS
+// (FP32: 8 per thread, 32 / 64 KB; FP64: 8 / 5 per thread, 48 / 60 KB)
+constexpr int kStageBigFrom = 1 << 21;
+__host__ __device__ constexpr int stage_k(int nb, bool f64) { return nb == 512 && f64 ? 5 : 8; }
 
 template <typename T>
 struct LevelView {
@@ -117,13 +121,14 @@ struct LevelView {
   const int* runs;
   // level 1: the 27 neighbour ids of boundary node t at bnd_nbrs[t * kBndStride ..]
   const int* bnd_nbrs;
-  // level 1, staged interior sweep: its workgroup g takes the interior nodes
-  // b*256 .. b*256 + 255 of b = st_blk[g] and reads the distinct node ids
-  // st_ids[st_off[g] .. st_off[g + 1]) (ascending) of their neighbourhoods, at
-  // most kStageIds of them; st_slot[t * kSlotStride + j] is the position of
-  // neighbour j of interior node t among them.  The nodes of the other
-  // workgroups (st_rest, n_st_rest ids) go through the plain interior kernel.
-  // Both counts 0: no tables.
+  // level 1, staged interior sweep: its workgroup g takes the group of
+  // interior nodes b*st_nodes .. of b = st_blk[g] and reads the distinct
+  // node ids st_ids[st_off[b] .. st_off[b + 1]) (ascending) of their
+  // neighbourhoods, at most the precision's cap; st_slot[t * kSlotStride + j]
+  // is the position of neighbour j of interior node t among them.  The nodes
+  // of the other groups (st_rest, n_st_rest ids) go through the plain interior
+  // kernel.  Both counts 0: no tables.
+  int st_nodes;  // nodes per group (256 or 512)
   const int* st_blk;
   int n_st_blk;
   const long long* st_off;
@@ -259,14 +264,14 @@ void launch_occ8(const int* node_lin, int n_n, const int* elem_map, int N, uint8
 void launch_occ_flags(const uint8_t* occ8, int n, int want_full, int* flags, hipStream_t s);
 void launch_run_flags(const int* interior, int n_int, const int* node_lin, int N, int* flags, hipStream_t s);
 // Tables of the staged interior sweep of level 1 (see LevelView::st_*): pass 0
-// writes the distinct-id count of every workgroup of 256 interior nodes to
-// cnt, pass 1 (for the n_blk workgroups blk[], with their offsets) the ids and
-// the slot table.
-void launch_stage_tables(const int* interior, int n_int, const int* node_lin, const int* node_map, int N, int pass,
-                         const int* blk, int n_blk, int* cnt, const long long* off, int* ids, uint16_t* slot,
+// writes the distinct-id count of every group of nb interior nodes to
+// cnt, pass 1 (for the n_blk groups blk[], offsets per group) the ids and the
+// slot table.
+void launch_stage_tables(const int* interior, int n_int, const int* node_lin, const int* node_map, int N, int nb,
+                         int pass, const int* blk, int n_blk, int* cnt, const long long* off, int* ids, uint16_t* slot,
                          hipStream_t s);
-// out = the interior ids of the workgroups (256 positions each) blk[0 .. n_blk)
-void launch_gather_blocks(const int* interior, int n_int, const int* blk, int n_blk, int* out, hipStream_t s);
+// out = the interior ids of the groups (nb positions each) blk[0 .. n_blk)
+void launch_gather_blocks(const int* interior, int n_int, int nb, const int* blk, int n_blk, int* out, hipStream_t s);
 void launch_boundary_nbrs(const int* boundary, int n_bnd, const int* node_lin, const int* node_map, int N, int* table,
                           hipStream_t s);
 void launch_gather_cmask(const int* elem_lin, int n_e, const uint8_t* dense_cmask, uint8_t* cmask,
@@ -324,13 +329,18 @@ struct LevelData {
   int* runs = nullptr;        // level 1: chunk starts of `interior` (+ sentinel)
   int n_runs = 0;
   int* bnd_nbrs = nullptr;    // level 1: neighbour ids of the boundary nodes (kBndStride per node)
-  int* st_blk = nullptr;       // level 1: tables of the staged interior sweep (LevelView)
-  int n_st_blk = 0;
-  long long* st_off = nullptr;
-  int* st_ids = nullptr;
+  int st_nodes = 0;
+  long long* st_off = nullptr; // level 1: tables of the staged interior sweep (LevelView),
+  int* st_ids = nullptr;       // the staged groups and the left-over nodes per precision
   uint16_t* st_slot = nullptr;
-  int* st_rest = nullptr;
-  int n_st_rest = 0;
+  int* st_blk32 = nullptr;
+  int n_st_blk32 = 0;
+  int* st_rest32 = nullptr;
+  int n_st_rest32 = 0;
+  int* st_blk64 = nullptr;
+  int n_st_blk64 = 0;
+  int* st_rest64 = nullptr;
+  int n_st_rest64 = 0;
   double* oscale64 = nullptr; // level 1 of a density hierarchy: [n_n][8] octant scales
   float* oscale32 = nullptr;
   double* erho = nullptr;     // level 1 of a density hierarchy: rho and scale per element

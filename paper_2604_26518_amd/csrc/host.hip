@@ -134,13 +134,21 @@ LevelView<T> Hier::view(int l) const {
   v.n_runs = d.n_runs;
   v.runs = d.runs;
   v.bnd_nbrs = d.bnd_nbrs;
-  v.st_blk = d.st_blk;
-  v.n_st_blk = d.n_st_blk;
+  v.st_nodes = d.st_nodes;
   v.st_off = d.st_off;
   v.st_ids = d.st_ids;
   v.st_slot = d.st_slot;
-  v.st_rest = d.st_rest;
-  v.n_st_rest = d.n_st_rest;
+  if constexpr (std::is_same<T, double>::value) {
+    v.st_blk = d.st_blk64;
+    v.n_st_blk = d.n_st_blk64;
+    v.st_rest = d.st_rest64;
+    v.n_st_rest = d.n_st_rest64;
+  } else {
+    v.st_blk = d.st_blk32;
+    v.n_st_blk = d.n_st_blk32;
+    v.st_rest = d.st_rest32;
+    v.n_st_rest = d.n_st_rest32;
+  }
   if constexpr (std::is_same<T, double>::value)
     v.oscale = d.oscale64;
   else
@@ -873,7 +881,7 @@ static void autotune(Hier& h, hipStream_t s) {
       cand = {{256, 7, 1}, {256, 7, 0}, {256, 5, 1}, {256, 8, 1}, {256, 8, 0}};
     } else if (l == 0) {
       cand = {{256, 8, 1}, {256, 8, 0}, {256, 7, 1}, {256, 7, 0}, {256, 5, 1}, {256, 6, 1}, {256, 6, 0}};
-      if (d.n_st_blk > 0) cand.insert(cand.end(), {{256, 9, 1}, {256, 9, 0}});
+      if ((f32 ? d.n_st_blk32 : d.n_st_blk64) > 0) cand.insert(cand.end(), {{256, 9, 1}, {256, 9, 0}});
       if (h.C > 1) cand.insert(cand.end(), {{256, 1, 1}, {256, 1, 0}});
     }
     if (l > 0) {
@@ -1386,49 +1394,60 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s, const double* rho 
         fail(GMT_E_STATE, "boundary neighbour table is not 16-byte aligned");
       launch_boundary_nbrs(d.boundary, d.n_bnd, d.node_lin, d.node_map, d.N, d.bnd_nbrs, s);
     }
-    // tables of the staged interior sweep: distinct neighbour ids per workgroup
-    // of 256 interior nodes (counted first); the workgroups with at most
-    // kStageIds of them are staged, the others' nodes listed for the plain kernel
+    // tables of the staged interior sweep: distinct neighbour ids per group of
+    // nb interior nodes (counted first; written for the groups within the FP32
+    // cap); per precision, the groups within its cap are staged, the others'
+    // nodes listed for the plain kernel
     if (d.n_int > 0) {
-      const int nblk = (d.n_int + 255) / 256;
+      // GMT_STAGE_NODES=256|512 pins the group size (tests of both on small cells)
+      const char* env_nb = std::getenv("GMT_STAGE_NODES");
+      const int nb = env_nb && *env_nb ? (std::atoi(env_nb) == 512 ? 512 : 256) : (d.n_int >= kStageBigFrom ? 512 : 256);
+      const int cap32 = nb * stage_k(nb, false), cap64 = nb * stage_k(nb, true);
+      d.st_nodes = nb;
+      const int nblk = (d.n_int + nb - 1) / nb;
       int* cnt = h.alloc<int>(nblk);
-      launch_stage_tables(d.interior, d.n_int, d.node_lin, d.node_map, d.N, 0, nullptr, 0, cnt, nullptr, nullptr,
+      launch_stage_tables(d.interior, d.n_int, d.node_lin, d.node_map, d.N, nb, 0, nullptr, 0, cnt, nullptr, nullptr,
                           nullptr, s);
       std::vector<int> hc(nblk);
       GMT_HIP(hipMemcpyAsync(hc.data(), cnt, nblk * sizeof(int), hipMemcpyDeviceToHost, s));
       GMT_HIP(hipStreamSynchronize(s));
-      auto nodes_of = [&](int b) { return std::min(256, d.n_int - 256 * b); };
-      std::vector<int> good, rest;
-      std::vector<long long> ho(1, 0);
+      auto nodes_of = [&](int b) { return std::min(nb, d.n_int - nb * b); };
+      std::vector<long long> ho(nblk + 1, 0);
+      std::vector<int> good[2], rest[2];
       for (int b = 0; b < nblk; ++b) {
-        if (hc[b] <= kStageIds) {
-          good.push_back(b);
-          ho.push_back(ho.back() + hc[b]);
-        } else {
-          rest.push_back(b);
-        }
+        ho[b + 1] = ho[b] + (hc[b] <= cap32 ? hc[b] : 0);
+        (hc[b] <= cap32 ? good[0] : rest[0]).push_back(b);
+        (hc[b] <= cap64 ? good[1] : rest[1]).push_back(b);
       }
-      d.n_st_blk = (int)good.size();
-      if (!good.empty()) {
-        d.st_blk = h.alloc<int>(good.size());
+      if (!good[0].empty()) {
+        int* g32 = h.alloc<int>(good[0].size());
         d.st_off = h.alloc<long long>(ho.size());
         d.st_ids = h.alloc<int>((size_t)std::max(ho.back(), 1LL));
         d.st_slot = h.alloc<uint16_t>((size_t)d.n_int * kSlotStride);
-        GMT_HIP(hipMemcpyAsync(d.st_blk, good.data(), good.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        GMT_HIP(hipMemcpyAsync(g32, good[0].data(), good[0].size() * sizeof(int), hipMemcpyHostToDevice, s));
         GMT_HIP(hipMemcpyAsync(d.st_off, ho.data(), ho.size() * sizeof(long long), hipMemcpyHostToDevice, s));
-        launch_stage_tables(d.interior, d.n_int, d.node_lin, d.node_map, d.N, 1, d.st_blk, d.n_st_blk, cnt,
+        launch_stage_tables(d.interior, d.n_int, d.node_lin, d.node_map, d.N, nb, 1, g32, (int)good[0].size(), cnt,
                             d.st_off, d.st_ids, d.st_slot, s);
+        d.st_blk32 = g32;
+        d.n_st_blk32 = (int)good[0].size();
+        if (!good[1].empty()) {
+          d.st_blk64 = h.alloc<int>(good[1].size());
+          GMT_HIP(hipMemcpyAsync(d.st_blk64, good[1].data(), good[1].size() * sizeof(int), hipMemcpyHostToDevice, s));
+          d.n_st_blk64 = (int)good[1].size();
+        }
       }
-      if (!rest.empty()) {
+      for (int p = 0; p < 2; ++p) {
+        if (rest[p].empty()) continue;
         long long nr = 0;
-        for (int b : rest) nr += nodes_of(b);
-        int* rb = h.alloc<int>(rest.size());
-        GMT_HIP(hipMemcpyAsync(rb, rest.data(), rest.size() * sizeof(int), hipMemcpyHostToDevice, s));
-        d.st_rest = h.alloc<int>((size_t)rest.size() * 256);
-        d.n_st_rest = (int)nr;
-        launch_gather_blocks(d.interior, d.n_int, rb, (int)rest.size(), d.st_rest, s);
+        for (int b : rest[p]) nr += nodes_of(b);
+        int* rb = h.alloc<int>(rest[p].size());
+        GMT_HIP(hipMemcpyAsync(rb, rest[p].data(), rest[p].size() * sizeof(int), hipMemcpyHostToDevice, s));
+        int* list = h.alloc<int>((size_t)rest[p].size() * nb);
+        launch_gather_blocks(d.interior, d.n_int, nb, rb, (int)rest[p].size(), list, s);
         GMT_HIP(hipStreamSynchronize(s));
         h.release(rb);
+        (p == 0 ? d.st_rest32 : d.st_rest64) = list;
+        (p == 0 ? d.n_st_rest32 : d.n_st_rest64) = (int)nr;
       }
       GMT_HIP(hipStreamSynchronize(s));
       h.release(cnt);
@@ -1592,7 +1611,7 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s, const double* rho 
     // the masked-stencil one (cb 0, the default before the autotuner runs)
     // does not.
     const int cb_keep = h.lv[0].cb32, cb_keep64 = h.lv[0].cb64;
-    if (h.lv[0].kind == KIND_SHARED) h.lv[0].cb32 = h.lv[0].cb64 = h.lv[0].n_st_blk > 0 ? 9 : 7;
+    if (h.lv[0].kind == KIND_SHARED) h.lv[0].cb32 = h.lv[0].cb64 = h.lv[0].n_st_blk32 > 0 ? 9 : 7;
     hipEvent_t fork = evs.make();
     GMT_HIP(hipEventRecord(fork, s));
     for (int l = 0; l < h.L; ++l) {

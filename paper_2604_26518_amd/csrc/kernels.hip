@@ -242,33 +242,35 @@ __global__ __launch_bounds__(kBlock) void k_apply_interior(LevelView<T> L, int C
   }
 }
 
-constexpr int kStageK = kStageIds / kBlock;
 
 // Level 1, interior nodes, neighbourhoods staged in LDS.  Workgroup g takes
-// the interior nodes b*256 .. b*256 + 255 of b = st_blk[g] and, per case, first copies the
+// the NB interior nodes of group b = st_blk[g] and, per case, first copies the
 // distinct vector entries that their 27-point stencils read (one gather per
 // distinct node, about 4 per interior node on a lattice cell instead of 27)
 // into LDS, then applies the stencil from there through the node's 27 slots.
 // The plain kernel's per-node gathers keep the vector memory data path busy
 // (each wide gather occupies it for ~30 cycles); here most reads go to LDS.
-// A workgroup stages at most kStageK * 256 distinct nodes (kStageK per
-// thread); the workgroups with more are left to the plain kernel (st_rest).
-template <typename T, int D, int EPI>
-__global__ __launch_bounds__(kBlock) void k_apply_interior_stage(LevelView<T> L, int C, const T* __restrict__ u,
-                                                                 EpiArgs<T> e) {
+// A workgroup stages at most kStageK distinct nodes per thread; the groups
+// with more are left to the plain kernel (st_rest).
+template <typename T, int D, int EPI, int NB>
+__global__ __launch_bounds__(NB) void k_apply_interior_stage(LevelView<T> L, int C, const T* __restrict__ u,
+                                                             EpiArgs<T> e) {
+  constexpr int kStageNodes = NB;
+  constexpr int kStageK = stage_k(NB, sizeof(T) == 8);
   // an FP32 node's 3 values at a 16-byte stride: one 128-bit LDS read each
   constexpr int DP = (D == 3 && sizeof(T) == 4) ? 4 : D;
-  __shared__ __align__(16) T stg[kStageK * kBlock * DP];
+  __shared__ __align__(16) T stg[kStageK * kStageNodes * DP];
   const int g = block_index(L.xcd);
-  const int t = L.st_blk[g] * kBlock + (int)threadIdx.x;
+  const int b = L.st_blk[g];
+  const int t = b * kStageNodes + (int)threadIdx.x;
   const bool valid = t < L.n_int;
   const size_t n = (size_t)L.n_n;
-  const long long o0 = L.st_off[g];
-  const int U = (int)(L.st_off[g + 1] - o0);
+  const long long o0 = L.st_off[b];
+  const int U = (int)(L.st_off[b + 1] - o0);
   int sid[kStageK];
 #pragma unroll
   for (int k = 0; k < kStageK; ++k) {
-    const int p = (int)threadIdx.x + k * kBlock;
+    const int p = (int)threadIdx.x + k * kStageNodes;
     sid[k] = p < U ? L.st_ids[o0 + p] : -1;
   }
   // the node's 27 slots, two per 32-bit word
@@ -300,7 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_interior_stage(LevelView<T> L,
     // so that the D loads of a node merge into one
 #pragma unroll
     for (int k = 0; k < kStageK; ++k)
-      if (k * kBlock < U) {
+      if (k * kStageNodes < U) {
         const size_t id = sid[k] >= 0 ? (size_t)sid[k] : 0;
 #pragma unroll
         for (int q = 0; q < D; ++q) w[k][q] = u[vix(c, n, id, D, q)];
@@ -315,8 +317,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_interior_stage(LevelView<T> L,
   auto store_stage = [&]() {
 #pragma unroll
     for (int k = 0; k < kStageK; ++k)
-      if (k * kBlock < U && sid[k] >= 0) {
-        T* dst = stg + ((int)threadIdx.x + k * kBlock) * DP;
+      if (k * kStageNodes < U && sid[k] >= 0) {
+        T* dst = stg + ((int)threadIdx.x + k * kStageNodes) * DP;
         if constexpr (DP == 4) {
           *reinterpret_cast<float4*>(dst) = make_float4(w[k][0], w[k][1], w[k][2], 0.0f);
         } else {
@@ -1582,6 +1584,30 @@ __global__ void k_coarsen(const int* __restrict__ femap, int Nf, int* __restrict
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;
 
+// The same for NT threads, with the NT / 64 wave sums in the caller's LDS
+// (free at the call; it is free again when the function returns).
+template <int NT>
+__device__ int block_exclusive_scan_n(int v, int* total, int* wsum) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int tt = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += tt;
+  }
+  if (lane == 63) wsum[wid] = incl;
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    if (w < wid) off += wsum[w];
+    tot += wsum[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + incl - v;
+}
+
 __device__ int block_exclusive_scan(int v, int* total) {
   __shared__ int wsum[kBlock / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -1641,18 +1667,21 @@ __global__ void k_scan_top(int* __restrict__ bsum, int nb, int* __restrict__ d_t
 // counted (pass 0, every workgroup b: cnt[b]) or, for the workgroups
 // b = blk[g] the staged sweep takes, written out ascending at off[g] together
 // with each node's 27 positions among them (pass 1: binary search).
-constexpr int kStageSort = 8192;  // >= 27 * kBlock, a power of two
-constexpr int kStageItems = kStageSort / kBlock;
-__global__ __launch_bounds__(kBlock) void k_stage_tables(const int* __restrict__ interior, int n_int,
+template <int NB>
+__global__ __launch_bounds__(NB) void k_stage_tables(const int* __restrict__ interior, int n_int,
                                                          const int* __restrict__ node_lin,
                                                          const int* __restrict__ node_map, int N, int pass,
                                                          const int* __restrict__ blk, int* __restrict__ cnt,
                                                          const long long* __restrict__ off, int* __restrict__ ids,
                                                          uint16_t* __restrict__ slot) {
+  constexpr int kStageNodes = NB;
+  constexpr int kStageSort = NB == 256 ? 8192 : 16384;  // >= 27 * NB, a power of two
+  constexpr int kStageItems = kStageSort / NB;
+  static_assert(27 * NB <= kStageSort, "sort buffer too small");
   __shared__ int s[kStageSort];
   const int g = blockIdx.x;
   const int b = pass == 0 ? g : blk[g];
-  const int t = b * kBlock + (int)threadIdx.x;
+  const int t = b * kStageNodes + (int)threadIdx.x;
   const bool valid = t < n_int;
   int nb[27];
   if (valid) {
@@ -1661,11 +1690,11 @@ __global__ __launch_bounds__(kBlock) void k_stage_tables(const int* __restrict__
   }
 #pragma unroll
   for (int j = 0; j < 27; ++j) s[(int)threadIdx.x * 27 + j] = valid ? nb[j] : INT_MAX;
-  for (int k = 27 * kBlock + (int)threadIdx.x; k < kStageSort; k += kBlock) s[k] = INT_MAX;
+  for (int k = 27 * kStageNodes + (int)threadIdx.x; k < kStageSort; k += kStageNodes) s[k] = INT_MAX;
   __syncthreads();
   for (int size = 2; size <= kStageSort; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int p = (int)threadIdx.x; p < kStageSort / 2; p += kBlock) {
+      for (int p = (int)threadIdx.x; p < kStageSort / 2; p += kStageNodes) {
         const int lo = 2 * p - (p & (stride - 1));  // the partner index lo + stride has that bit set
         const int hi = lo + stride;
         const int a = s[lo], c = s[hi];
@@ -1689,12 +1718,13 @@ __global__ __launch_bounds__(kBlock) void k_stage_tables(const int* __restrict__
     m += v[k] >= 0;
   }
   int total;
-  int pos = block_exclusive_scan(m, &total);  // contains a barrier after every read of s above
+  __syncthreads();  // every read of s above is done: its first words hold the wave sums
+  int pos = block_exclusive_scan_n<kStageNodes>(m, &total, s);
   if (pass == 0) {
     if (threadIdx.x == 0) cnt[b] = total;
     return;
   }
-  const long long o0 = off[g];
+  const long long o0 = off[b];
 #pragma unroll
   for (int k = 0; k < kStageItems; ++k)
     if (v[k] >= 0) {
@@ -2211,9 +2241,14 @@ static void launch_coarse(const LevelView<T>& L, int kind, int rows, const T* u,
 // kernel (all 27 neighbours of a case loaded up front) over the rest
 template <typename T, int D, int EPI>
 static void launch_interior_stage(const LevelView<T>& L, int C, const T* u, const EpiArgs<T>& e, hipStream_t s) {
-  if (L.n_st_blk > 0)
-    hipLaunchKernelGGL((k_apply_interior_stage<T, D, EPI>), dim3((unsigned)L.n_st_blk), dim3(kBlock), 0, s, L, C, u,
-                       e);
+  if (L.n_st_blk > 0) {
+    if (L.st_nodes == 512)
+      hipLaunchKernelGGL((k_apply_interior_stage<T, D, EPI, 512>), dim3((unsigned)L.n_st_blk), dim3(512), 0, s, L, C,
+                         u, e);
+    else
+      hipLaunchKernelGGL((k_apply_interior_stage<T, D, EPI, 256>), dim3((unsigned)L.n_st_blk), dim3(256), 0, s, L, C,
+                         u, e);
+  }
   if (L.n_st_rest > 0) {
     LevelView<T> R = L;
     R.interior = L.st_rest;
@@ -2664,28 +2699,31 @@ void launch_run_flags(const int* interior, int n_int, const int* node_lin, int N
   GMT_LAUNCH_CHECK();
 }
 
-void launch_stage_tables(const int* interior, int n_int, const int* node_lin, const int* node_map, int N, int pass,
-                         const int* blk, int n_blk, int* cnt, const long long* off, int* ids, uint16_t* slot,
+void launch_stage_tables(const int* interior, int n_int, const int* node_lin, const int* node_map, int N, int nb,
+                         int pass, const int* blk, int n_blk, int* cnt, const long long* off, int* ids, uint16_t* slot,
                          hipStream_t s) {
-  static_assert(27 * kBlock <= kStageSort, "sort buffer too small");
-  const unsigned grid = pass == 0 ? blocks_for(n_int) : (unsigned)n_blk;
+  const unsigned grid = pass == 0 ? (unsigned)((n_int + nb - 1) / nb) : (unsigned)n_blk;
   if (!n_int || !grid) return;
-  hipLaunchKernelGGL(k_stage_tables, dim3(grid), dim3(kBlock), 0, s, interior, n_int, node_lin, node_map, N, pass, blk,
-                     cnt, off, ids, slot);
+  if (nb == 512)
+    hipLaunchKernelGGL(k_stage_tables<512>, dim3(grid), dim3(512), 0, s, interior, n_int, node_lin, node_map, N, pass,
+                       blk, cnt, off, ids, slot);
+  else
+    hipLaunchKernelGGL(k_stage_tables<256>, dim3(grid), dim3(256), 0, s, interior, n_int, node_lin, node_map, N, pass,
+                       blk, cnt, off, ids, slot);
   GMT_LAUNCH_CHECK();
 }
 
-// out = the interior ids of the workgroups blk[0 .. n_blk) (256 positions each,
-// the last workgroup of the list possibly partial), in that order
+// out = the interior ids of the groups blk[0 .. n_blk) (blockDim.x positions
+// each, the last group of the list possibly partial), in that order
 __global__ void k_gather_blocks(const int* __restrict__ interior, int n_int, const int* __restrict__ blk,
                                 int* __restrict__ out) {
-  const int t = blk[blockIdx.x] * kBlock + (int)threadIdx.x;
-  if (t < n_int) out[(size_t)blockIdx.x * kBlock + threadIdx.x] = interior[t];
+  const int t = blk[blockIdx.x] * (int)blockDim.x + (int)threadIdx.x;
+  if (t < n_int) out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = interior[t];
 }
 
-void launch_gather_blocks(const int* interior, int n_int, const int* blk, int n_blk, int* out, hipStream_t s) {
+void launch_gather_blocks(const int* interior, int n_int, int nb, const int* blk, int n_blk, int* out, hipStream_t s) {
   if (!n_blk) return;
-  hipLaunchKernelGGL(k_gather_blocks, dim3(n_blk), dim3(kBlock), 0, s, interior, n_int, blk, out);
+  hipLaunchKernelGGL(k_gather_blocks, dim3(n_blk), dim3(nb), 0, s, interior, n_int, blk, out);
   GMT_LAUNCH_CHECK();
 }
 

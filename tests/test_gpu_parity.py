@@ -195,6 +195,32 @@ def test_level1_sweep_variants(pair, variant, monkeypatch):
     assert np.abs(out - osolve.chebyshev(P, 0, u0, P.f, 3, lo, hi)).max() <= 1e-12 * np.abs(out).max()
 
 
+@pytest.mark.parametrize("nodes", [256, 512])
+def test_staged_sweep_group_sizes(pair, nodes, monkeypatch):
+    """The staged interior sweep with both group sizes (256 nodes per workgroup on smaller
+    levels, 512 on large ones), pinned on these cells: K.u and residual within the forward-error
+    bound, and the Chebyshev sweep against the oracle, in both precisions."""
+    name, vox, P, H0 = pair
+    monkeypatch.setenv("GMT_STAGE_NODES", str(nodes))
+    monkeypatch.setenv("GMT_FORCE_L1_VARIANT", "9")
+    H = _gmt().Hierarchy(vox, P.L, "elastic" if P.c == 6 else "thermal")
+    try:
+        n = P.levels[0].n_n
+        u0 = random_vectors(n, P.c * P.d, 37).reshape(n, P.c, P.d)
+        ref = oops.apply_K(P.levels[0], P.mats[0], u0)
+        for dtype in (torch.float64, torch.float32):
+            y = _np(H.apply_K(_t(u0, dtype), 1)).astype(np.float64)
+            _within(y, ref, _fwd_bound(P, 0, u0, dtype), f"{name} staged {nodes} K.u {dtype}")
+            r = _np(H.residual(_t(P.f, dtype), _t(u0, dtype), 1)).astype(np.float64)
+            _within(r, P.f - ref, _fwd_bound(P, 0, u0, dtype, P.f), f"{name} staged {nodes} residual {dtype}")
+        lam = H.level_info(1)["lambda_max"]
+        lo, hi = lam / 30, 1.1 * lam
+        out = _np(H.smooth(_t(P.f), _t(u0), 3, "chebyshev", lo, hi))
+        assert np.abs(out - osolve.chebyshev(P, 0, u0, P.f, 3, lo, hi)).max() <= 1e-12 * np.abs(out).max()
+    finally:
+        H.close()
+
+
 @pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_coarse_sweep_variants(pair, variant, monkeypatch):
     """Every sweep variant of levels >= 2 (all cases or one case per thread; element-major,
