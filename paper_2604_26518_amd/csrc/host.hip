@@ -1402,7 +1402,10 @@ static void build(Hier& h, const uint8_t* vox, hipStream_t s, const double* rho 
       // GMT_STAGE_NODES=256|512 pins the group size (tests of both on small cells)
       const char* env_nb = std::getenv("GMT_STAGE_NODES");
       const int nb = env_nb && *env_nb ? (std::atoi(env_nb) == 512 ? 512 : 256) : (d.n_int >= kStageBigFrom ? 512 : 256);
-      const int cap32 = nb * stage_k(nb, false), cap64 = nb * stage_k(nb, true);
+      int cap32 = nb * stage_k(nb, false), cap64 = nb * stage_k(nb, true);
+      // GMT_STAGE_CAP=<k> lowers both caps (tests of the unstaged remainder)
+      if (const char* ec = std::getenv("GMT_STAGE_CAP"))
+        if (*ec && std::atoi(ec) > 0) cap32 = std::min(cap32, std::atoi(ec)), cap64 = std::min(cap64, std::atoi(ec));
       d.st_nodes = nb;
       const int nblk = (d.n_int + nb - 1) / nb;
       int* cnt = h.alloc<int>(nblk);

@@ -195,13 +195,16 @@ def test_level1_sweep_variants(pair, variant, monkeypatch):
     assert np.abs(out - osolve.chebyshev(P, 0, u0, P.f, 3, lo, hi)).max() <= 1e-12 * np.abs(out).max()
 
 
-@pytest.mark.parametrize("nodes", [256, 512])
-def test_staged_sweep_group_sizes(pair, nodes, monkeypatch):
+@pytest.mark.parametrize("nodes,cap", [(256, 0), (512, 0), (256, 700), (512, 1500)])
+def test_staged_sweep_group_sizes(pair, nodes, cap, monkeypatch):
     """The staged interior sweep with both group sizes (256 nodes per workgroup on smaller
-    levels, 512 on large ones), pinned on these cells: K.u and residual within the forward-error
-    bound, and the Chebyshev sweep against the oracle, in both precisions."""
+    levels, 512 on large ones), pinned on these cells, and with caps low enough that some or all
+    groups are left to the unstaged kernel: K.u and residual within the forward-error bound, and
+    the Chebyshev sweep against the oracle, in both precisions."""
     name, vox, P, H0 = pair
     monkeypatch.setenv("GMT_STAGE_NODES", str(nodes))
+    if cap:
+        monkeypatch.setenv("GMT_STAGE_CAP", str(cap))
     monkeypatch.setenv("GMT_FORCE_L1_VARIANT", "9")
     H = _gmt().Hierarchy(vox, P.L, "elastic" if P.c == 6 else "thermal")
     try:
