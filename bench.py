@@ -50,7 +50,7 @@ COPY_BYTES = 512 << 20
 # kernel reports null until it is profiled again.
 SWEEP_TRAFFIC_BYTES = {
     # profiles/level1_chebyshev_sweep_gyroid512_hbm_traffic.txt
-    ("gyroid512_seed30001", 9, "198f25e4b30630be"): (24_033_608 + 5_186_519) * 1024,
+    ("gyroid512_seed30001", 9, "25f950ffada205a3"): (22_911_206 + 5_186_459) * 1024,
 }
 SWEEP_KERNELS = {
     0: "k_apply_interior_nc + k_apply_boundary_st",

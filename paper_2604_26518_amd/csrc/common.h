@@ -171,7 +171,8 @@ template <typename T>
 struct EpiArgs {
   const T* f;
   const T* dinv;  // [n_n][d]
-  T* dvec;        // Chebyshev direction, updated in place
+  T* dvec;        // Chebyshev direction, written
+  const T* dvec_in;  // the direction read (dvec, or the iterate when the last step started from zero)
   T* out;
   T omega;        // Jacobi weight
   T rho1, rho2;   // Chebyshev: d = rho1 d + rho2 D^-1 (f - K u)

@@ -539,11 +539,13 @@ static const T* dinv_of(const Hier& h, int l) {
 
 template <typename T>
 static void apply(Hier& h, int l, int epi, const T* u, const T* f, T* out, int C, hipStream_t s,
-                  T omega = 0, T rho1 = 0, T rho2 = 0, T* dvec = nullptr, const LevelView<T>* view = nullptr) {
+                  T omega = 0, T rho1 = 0, T rho2 = 0, T* dvec = nullptr, const LevelView<T>* view = nullptr,
+                  const T* dvec_in = nullptr) {
   EpiArgs<T> e{};
   e.f = f;
   e.dinv = dinv_of<T>(h, l);
   e.dvec = dvec;
+  e.dvec_in = dvec_in ? dvec_in : dvec;
   e.out = out;
   e.omega = omega;
   e.rho1 = rho1;
@@ -710,15 +712,23 @@ static void smooth(Hier& h, int l, const T* f, T*& u, T*& ualt, T* dvec, int nu,
   const double lo = p1, hi = p2;
   const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
   double rho = 1.0 / sigma;
+  // A first step from zero leaves the direction equal to the iterate
+  // (d = u = D^-1 f / theta): it writes u only, and the next step reads the
+  // direction from u (one pass over a vector saved).  With a single step the
+  // direction is written too, for whoever reads it after the smoother.
+  bool d_in_u = false;
   if (zero_start) {
-    launch_smooth_zero<T>(n, h.D, h.C, f, dinv, (T)(1.0 / theta), u, dvec, s);
+    d_in_u = nu > 1;
+    launch_smooth_zero<T>(n, h.D, h.C, f, dinv, (T)(1.0 / theta), u, d_in_u ? nullptr : dvec, s);
   } else {
     apply<T>(h, l, EPI_CHEB0, u, f, ualt, h.C, s, T(0), T(0), (T)(1.0 / theta), dvec);
     std::swap(u, ualt);
   }
   for (int k = 1; k < nu; ++k) {
     const double rn = 1.0 / (2.0 * sigma - rho);
-    apply<T>(h, l, EPI_CHEB, u, f, ualt, h.C, s, T(0), (T)(rn * rho), (T)(2.0 * rn / delta), dvec);
+    apply<T>(h, l, EPI_CHEB, u, f, ualt, h.C, s, T(0), (T)(rn * rho), (T)(2.0 * rn / delta), dvec, nullptr,
+             d_in_u ? u : nullptr);
+    d_in_u = false;
     std::swap(u, ualt);
     rho = rn;
   }

@@ -66,7 +66,7 @@ __device__ __forceinline__ void epilogue_d(const EpiArgs<T>& e, size_t idx, T ac
   } else if constexpr (EPI == EPI_JACOBI) {
     e.out[idx] = uself + e.omega * dinv * (e.f[idx] - acc);
   } else if constexpr (EPI == EPI_CHEB) {
-    const T dn = e.rho1 * e.dvec[idx] + e.rho2 * dinv * (e.f[idx] - acc);
+    const T dn = e.rho1 * e.dvec_in[idx] + e.rho2 * dinv * (e.f[idx] - acc);
     e.dvec[idx] = dn;
     e.out[idx] = uself + dn;
   } else {  // EPI_CHEB0
@@ -101,7 +101,7 @@ __device__ __forceinline__ void epilogue_node(const EpiArgs<T>& e, const T* __re
     for (int q = 0; q < D; ++q) {
       const size_t idx = vix(c0 + c, n, i, D, q);
       fv[c][q] = EPI != EPI_KU ? (fpre ? fpre[c * D + q] : e.f[idx]) : T(0);
-      dd[c][q] = EPI == EPI_CHEB ? (dpre ? dpre[c * D + q] : e.dvec[idx]) : T(0);
+      dd[c][q] = EPI == EPI_CHEB ? (dpre ? dpre[c * D + q] : e.dvec_in[idx]) : T(0);
       us[c][q] = needs_dinv<EPI>() ? (uself ? uself[c * D + q] : u[idx]) : T(0);
     }
   // results first, then each output array's D values of a case as one run of
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(NB) void k_apply_interior_stage(LevelView<T> L, int
     for (int q = 0; q < D; ++q) {  // (threads without a node read node 0's: i = 0)
       const size_t idx = vix(c, n, i, D, q);
       fn[q] = EPI != EPI_KU ? e.f[idx] : T(0);
-      dn[q] = EPI == EPI_CHEB ? e.dvec[idx] : T(0);
+      dn[q] = EPI == EPI_CHEB ? e.dvec_in[idx] : T(0);
     }
   };
   auto store_stage = [&]() {
