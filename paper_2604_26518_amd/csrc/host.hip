@@ -832,7 +832,7 @@ static void vcycle(Hier& h, const T* f0, T* u0, bool u0_zero, const T* const* e_
 // boundary nodes as a masked stencil assembled in registers from the symmetry
 // classes of K_e, with the interior one case per pass (cb 5; cb 7 with all 27
 // neighbours of a case loaded before the arithmetic; cb 9 with the distinct
-// neighbours of each workgroup of 256 interior nodes staged in LDS) or all
+// neighbours of each group of 256 or 512 interior nodes staged in LDS) or all
 // cases per neighbour load (cb 6).
 // Before the first solve of a hierarchy, every
 // candidate is timed on every level (K.u on the work vectors: 2 warm-up and 3
