@@ -655,10 +655,15 @@ __global__ __launch_bounds__(kBlock) void k_apply_boundary_st(LevelView<T> L, co
 // neighbour loads are issued from a clamped index and the values of an
 // inactive neighbour (whose block is zero) are selected away, so no load sits
 // in a branch.
+// The grid is 1-D, rows workgroups per block of kBlock nodes, one per group
+// of C cases, adjacent in the launch order: the rows of a node block run
+// together and share its neighbour-id rows and occupancy in L2.
 template <typename T, int D, int C, int EPI, int PRE = 0>
-__global__ __launch_bounds__(kBlock) void k_apply_boundary_cls(LevelView<T> L, const T* __restrict__ u, EpiArgs<T> e) {
-  const int t = block_index(L.xcd) * kBlock + threadIdx.x;
-  const int c0 = (int)blockIdx.y * C;  // this grid row's first case
+__global__ __launch_bounds__(kBlock) void k_apply_boundary_cls(LevelView<T> L, const T* __restrict__ u, EpiArgs<T> e,
+                                                               int rows) {
+  const int bi = block_index(L.xcd);
+  const int t = (bi / rows) * kBlock + threadIdx.x;
+  const int c0 = (bi % rows) * C;  // this workgroup's first case
   if (t >= L.n_bnd) return;
   const int i = L.boundary[t];
   const size_t n = (size_t)L.n_n;
@@ -2273,17 +2278,17 @@ static void apply_dispatch_kind(const LevelView<T>& L, int kind, const T* u, con
                              e);
       }
       if (L.n_bnd > 0) {
-        // one case per thread (C grid rows): the assembly is repeated per case,
+        // one case per thread (C workgroups per node block): the assembly is repeated per case,
         // but the live set stays small (with several cases per thread the
         // compiler hoists every neighbour's loads and spills)
-        const dim3 g(blocks_for(L.n_bnd), C);
+        const dim3 g(blocks_for(L.n_bnd) * C);
         if (L.cb == 8)  // all cases per thread: one assembly per node
           hipLaunchKernelGGL((k_apply_boundary_all<T, D, C, EPI>), dim3(blocks_for(L.n_bnd)), dim3(kBlock), 0, s, L,
                              u, e);
         else if (L.cb == 7 || L.cb == 9)
-          hipLaunchKernelGGL((k_apply_boundary_cls<T, D, 1, EPI, 1>), g, dim3(kBlock), 0, s, L, u, e);
+          hipLaunchKernelGGL((k_apply_boundary_cls<T, D, 1, EPI, 1>), g, dim3(kBlock), 0, s, L, u, e, C);
         else
-          hipLaunchKernelGGL((k_apply_boundary_cls<T, D, 1, EPI>), g, dim3(kBlock), 0, s, L, u, e);
+          hipLaunchKernelGGL((k_apply_boundary_cls<T, D, 1, EPI>), g, dim3(kBlock), 0, s, L, u, e, C);
       }
     } else if (L.cb == 0 || L.cb == 2) {  // all cases per neighbour load
       if (L.n_int > 0)
