@@ -50,7 +50,7 @@ COPY_BYTES = 512 << 20
 # kernel reports null until it is profiled again.
 SWEEP_TRAFFIC_BYTES = {
     # profiles/level1_chebyshev_sweep_gyroid512_hbm_traffic.txt
-    ("gyroid512_seed30001", 9, "25f950ffada205a3"): (22_911_206 + 5_186_459) * 1024,
+    ("gyroid512_seed30001", 9, "64c7445f942b8902"): (22_693_601 + 5_186_849) * 1024,
 }
 SWEEP_KERNELS = {
     0: "k_apply_interior_nc + k_apply_boundary_st",
